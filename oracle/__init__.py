@@ -1,0 +1,332 @@
+"""CPU oracle for the homomorphic SZp path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package.  The product (the HIP library and its
+binding) never imports it, and it never imports the product: the two share
+no code.  Everything computed here is done by ``hsz_oracle.c`` (plain C,
+binary64, no fused multiply-add); this module only marshals numpy arrays
+through ctypes.
+
+Functions and the passages of the paper they follow:
+  quantize           Sec. IV quantization paragraph, Alg. 1 quantize loop
+  quant_params       error bound -> quantum (value-range relative bound,
+                     Sec. VI-B; safety margin: a reading, see the C file)
+  encode_q           Alg. 1 partition/metadata/decorrelate/encode (SZp)
+  compress           Alg. 1 end to end
+  decompress         Alg. 2 (stages: 1 metadata, 2 decorrelated,
+                     3 quantized, 4 floats)
+  mean, var          Sec. III-B Eq. (var) on the decompressed field
+  derivative,        Sec. III-B Eq. (derivatives), unit spacing, one-sided
+  gradmag            at the ends of an axis
+  int_sums           sum q and sum q^2 of the quantized field (exact)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hsz_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+OK, ERR_ARG, ERR_STREAM, ERR_UNSUPPORTED, ERR_RANGE, ERR_EB, ERR_NONFINITE, ERR_CAPACITY = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+F32, F64 = 1, 2
+META, DELTA, QUANT, FLOAT = 1, 2, 3, 4
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: oracle error {code}")
+        self.code = code
+
+
+def build(force: bool = True) -> str:
+    """Compile hsz_oracle.c into liboracle.so with gcc (no FMA contraction)."""
+    import subprocess
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+            "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    u64, u32, i32, dbl = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_double
+    lib.or_compress_bound.restype = u64
+    lib.or_compress_bound.argtypes = [u64, u32]
+    lib.or_ulp.restype = dbl
+    lib.or_ulp.argtypes = [dbl, i32]
+    lib.or_quant_params.restype = i32
+    lib.or_quant_params.argtypes = [dbl, dbl, dbl, i32, i32, P, P]
+    lib.or_quantize.restype = u64
+    lib.or_quantize.argtypes = [P, u64, dbl, P]
+    lib.or_encode_q.restype = i32
+    lib.or_encode_q.argtypes = [P, u32, P, u32, dbl, dbl, u32, P, u64, P]
+    lib.or_compress.restype = i32
+    lib.or_compress.argtypes = [P, u32, u32, P, dbl, i32, u32, P, u64, P]
+    lib.or_read_header.restype = i32
+    lib.or_read_header.argtypes = [P, u64, P]
+    lib.or_stage_bytes.restype = u64
+    lib.or_stage_bytes.argtypes = [P, u64, i32]
+    lib.or_decompress.restype = i32
+    lib.or_decompress.argtypes = [P, u64, i32, P]
+    lib.or_dequantize64.restype = None
+    lib.or_dequantize64.argtypes = [P, u64, dbl, P]
+    for name in ("or_mean", "or_var"):
+        getattr(lib, name).restype = i32
+        getattr(lib, name).argtypes = [P, P, P, P, P]
+    lib.or_derivative.restype = i32
+    lib.or_derivative.argtypes = [P, P, i32, P, P, P]
+    lib.or_gradmag.restype = i32
+    lib.or_gradmag.argtypes = [P, P, P, P, P]
+    lib.or_int_sums.restype = i32
+    lib.or_int_sums.argtypes = [P, P, P, P, P, P, P, P]
+    _lib = lib
+    return lib
+
+
+class _Hdr(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_uint32), ("ndim", ctypes.c_uint32),
+        ("dims", ctypes.c_uint64 * 3), ("n", ctypes.c_uint64),
+        ("block", ctypes.c_uint32), ("chunk_blocks", ctypes.c_uint32),
+        ("eb_abs", ctypes.c_double), ("quantum", ctypes.c_double),
+        ("inv_quantum", ctypes.c_double), ("vmin", ctypes.c_double),
+        ("vmax", ctypes.c_double), ("max_abs_q", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32), ("nb", ctypes.c_uint64),
+        ("nchunks", ctypes.c_uint64), ("off_chunk", ctypes.c_uint64),
+        ("off_q0", ctypes.c_uint64), ("off_width", ctypes.c_uint64),
+        ("off_payload", ctypes.c_uint64), ("payload_words", ctypes.c_uint64),
+        ("total_bytes", ctypes.c_uint64),
+    ]
+
+
+@dataclass
+class Header:
+    dtype: int
+    ndim: int
+    dims: tuple  # the field's own shape (ndim entries), slow -> fast
+    dims3: tuple  # 3D view with leading ones
+    n: int
+    block: int
+    eb_abs: float
+    quantum: float
+    inv_quantum: float
+    vmin: float
+    vmax: float
+    max_abs_q: int
+    nb: int
+    nchunks: int
+    off_chunk: int
+    off_q0: int
+    off_width: int
+    off_payload: int
+    payload_words: int
+    total_bytes: int
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise OracleError(rc, what)
+
+
+def _dims3(shape) -> np.ndarray:
+    shape = tuple(int(s) for s in shape)
+    if not 1 <= len(shape) <= 3:
+        raise ValueError("fields are 1D, 2D or 3D")
+    return np.array((1,) * (3 - len(shape)) + shape, dtype=np.uint64)
+
+
+def _box3(shape, box):
+    """box = None or (lo, hi) sequences in the field's own axes -> 3D arrays."""
+    nd = len(shape)
+    if box is None:
+        return None, None
+    lo, hi = box
+    lo3 = np.array((0,) * (3 - nd) + tuple(int(v) for v in lo), dtype=np.int64)
+    hi3 = np.array((1,) * (3 - nd) + tuple(int(v) for v in hi), dtype=np.int64)
+    return lo3, hi3
+
+
+def compress_bound(n: int, block: int) -> int:
+    return int(_load().or_compress_bound(n, block))
+
+
+def ulp(v: float, dtype: int) -> float:
+    return float(_load().or_ulp(v, dtype))
+
+
+def quant_params(vmin: float, vmax: float, eb: float, rel: bool, dtype: int):
+    """-> (eps_abs, quantum)."""
+    lib = _load()
+    e = ctypes.c_double()
+    d = ctypes.c_double()
+    _check(lib.or_quant_params(vmin, vmax, eb, int(rel), dtype, ctypes.byref(e), ctypes.byref(d)),
+           "quant_params")
+    return e.value, d.value
+
+
+def quantize(x, quantum: float) -> np.ndarray:
+    """q = floor(x * (1/quantum) + 0.5) in binary64; out-of-range values clamp."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).ravel())
+    q = np.empty(x.size, dtype=np.int32)
+    _load().or_quantize(_ptr(x), x.size, quantum, _ptr(q))
+    return q
+
+
+def encode_q(q, shape, quantum: float, block: int, dtype: int = F32, eb_abs: float = 0.0) -> np.ndarray:
+    q = np.ascontiguousarray(np.asarray(q, dtype=np.int32).ravel())
+    dims = np.array([int(s) for s in shape], dtype=np.uint64)
+    cap = compress_bound(q.size, block)
+    out = np.zeros(cap, dtype=np.uint8)
+    size = ctypes.c_uint64()
+    _check(_load().or_encode_q(_ptr(q), len(shape), _ptr(dims), dtype, eb_abs, quantum, block,
+                               _ptr(out), cap, ctypes.byref(size)), "encode_q")
+    return out[: size.value].copy()
+
+
+def compress(x: np.ndarray, eb: float, rel: bool = True, block: int = 32) -> np.ndarray:
+    x = np.ascontiguousarray(x)
+    if x.dtype == np.float32:
+        dt = F32
+    elif x.dtype == np.float64:
+        dt = F64
+    else:
+        raise TypeError("field must be float32 or float64")
+    dims = np.array(x.shape, dtype=np.uint64)
+    cap = compress_bound(x.size, block)
+    out = np.empty(cap, dtype=np.uint8)
+    size = ctypes.c_uint64()
+    _check(_load().or_compress(_ptr(x), dt, x.ndim, _ptr(dims), eb, int(rel), block, _ptr(out),
+                               cap, ctypes.byref(size)), "compress")
+    return out[: size.value].copy()
+
+
+def read_header(buf: np.ndarray) -> Header:
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    h = _Hdr()
+    _check(_load().or_read_header(_ptr(buf), buf.size, ctypes.byref(h)), "read_header")
+    dims3 = tuple(int(v) for v in h.dims)
+    return Header(
+        dtype=h.dtype, ndim=h.ndim, dims=dims3[3 - h.ndim:], dims3=dims3, n=h.n, block=h.block,
+        eb_abs=h.eb_abs, quantum=h.quantum, inv_quantum=h.inv_quantum, vmin=h.vmin, vmax=h.vmax,
+        max_abs_q=h.max_abs_q, nb=h.nb, nchunks=h.nchunks, off_chunk=h.off_chunk,
+        off_q0=h.off_q0, off_width=h.off_width, off_payload=h.off_payload,
+        payload_words=h.payload_words, total_bytes=h.total_bytes)
+
+
+def decompress(buf: np.ndarray, stage: int):
+    """Alg. 2 to the given stage.
+
+    stage 1 -> q0 (int32[nb]); stage 2 -> (p int32[n] shaped like the field,
+    q0 int32[nb]); stage 3 -> q int32 shaped like the field; stage 4 -> the
+    decompressed field in its own dtype.
+    """
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    h = read_header(buf)
+    lib = _load()
+    nbytes = int(lib.or_stage_bytes(_ptr(buf), buf.size, stage))
+    if nbytes == 0:
+        raise OracleError(ERR_ARG, "decompress: bad stage")
+    raw = np.empty(nbytes, dtype=np.uint8)
+    _check(lib.or_decompress(_ptr(buf), buf.size, stage, _ptr(raw)), "decompress")
+    if stage == META:
+        return raw.view(np.int32).copy()
+    if stage == DELTA:
+        v = raw.view(np.int32)
+        return v[: h.n].reshape(h.dims).copy(), v[h.n:].copy()
+    if stage == QUANT:
+        return raw.view(np.int32).reshape(h.dims).copy()
+    return raw.view(np.float32 if h.dtype == F32 else np.float64).reshape(h.dims).copy()
+
+
+def dequantize64(q: np.ndarray, quantum: float) -> np.ndarray:
+    """d' = q * quantum in binary64, shaped like q."""
+    qq = np.ascontiguousarray(q, dtype=np.int32)
+    out = np.empty(qq.shape, dtype=np.float64)
+    _load().or_dequantize64(_ptr(qq), qq.size, quantum, _ptr(out))
+    return out
+
+
+def _field(x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return x, _dims3(x.shape)
+
+
+def mean(x, box=None) -> float:
+    x, d = _field(x)
+    lo, hi = _box3(x.shape, box)
+    r = ctypes.c_double()
+    _check(_load().or_mean(_ptr(x), _ptr(d), None if lo is None else _ptr(lo),
+                           None if hi is None else _ptr(hi), ctypes.byref(r)), "mean")
+    return r.value
+
+
+def var(x, box=None) -> float:
+    x, d = _field(x)
+    lo, hi = _box3(x.shape, box)
+    r = ctypes.c_double()
+    _check(_load().or_var(_ptr(x), _ptr(d), None if lo is None else _ptr(lo),
+                          None if hi is None else _ptr(hi), ctypes.byref(r)), "var")
+    return r.value
+
+
+def _box_shape(shape, box):
+    if box is None:
+        return tuple(shape)
+    lo, hi = box
+    return tuple(int(h) - int(l) for l, h in zip(lo, hi))
+
+
+def derivative(x, axis: int, box=None) -> np.ndarray:
+    """Derivative along the field's own axis (0 = slowest), restricted to box."""
+    x, d = _field(x)
+    nd = x.ndim
+    if not 0 <= axis < nd:
+        raise ValueError("axis out of range")
+    lo, hi = _box3(x.shape, box)
+    out = np.empty(_box_shape(x.shape, box), dtype=np.float64)
+    _check(_load().or_derivative(_ptr(x), _ptr(d), axis + 3 - nd, None if lo is None else _ptr(lo),
+                                 None if hi is None else _ptr(hi), _ptr(out)), "derivative")
+    return out
+
+
+def gradmag(x, box=None) -> np.ndarray:
+    x, d = _field(x)
+    lo, hi = _box3(x.shape, box)
+    out = np.empty(_box_shape(x.shape, box), dtype=np.float64)
+    _check(_load().or_gradmag(_ptr(x), _ptr(d), None if lo is None else _ptr(lo),
+                              None if hi is None else _ptr(hi), _ptr(out)), "gradmag")
+    return out
+
+
+def int_sums(q, box=None):
+    """-> (N, sum q, sum q^2) as Python ints, over the box."""
+    q = np.ascontiguousarray(q, dtype=np.int32)
+    d = _dims3(q.shape)
+    lo, hi = _box3(q.shape, box)
+    n, s1, s2lo, s2hi = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint64(), ctypes.c_int64()
+    _check(_load().or_int_sums(_ptr(q), _ptr(d), None if lo is None else _ptr(lo),
+                               None if hi is None else _ptr(hi), ctypes.byref(n), ctypes.byref(s1),
+                               ctypes.byref(s2lo), ctypes.byref(s2hi)), "int_sums")
+    return n.value, s1.value, (s2hi.value << 64) + s2lo.value

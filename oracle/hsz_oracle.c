@@ -1,0 +1,635 @@
+/*
+ * hsz_oracle.c -- plain, slow, obviously correct CPU reference for the
+ * homomorphic SZp path (error-bounded compression, multi-stage
+ * decompression, and analytical operations on the decompressed field).
+ *
+ * THIS IS TEST INFRASTRUCTURE, NOT THE PRODUCT.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or helper with the GPU library: it is a
+ * second, independent implementation of the same arithmetic and the same
+ * byte format, written for a reader who checks it against the paper by eye.
+ *
+ * What it follows (paper: "Enabling Homomorphic Analytical Operations on
+ * Compressed Scientific Data with Multi-stage Decompression"):
+ *   - Sec. IV, quantization paragraph and Alg. 1 (quantize loop):
+ *       q_i = round(d_i / (2 eps)),  d'_i = 2 q_i eps,  |d_i - d'_i| <= eps.
+ *   - Sec. IV, data partition / metadata / decorrelation paragraphs and
+ *     Alg. 1 (block loop), SZp flavour: blocks of S consecutive elements of
+ *     the field read as a flat array, metadata = first q of the block,
+ *     p_i = q_i - q_{i-1} inside the block.
+ *   - Sec. IV, encoding paragraph and Alg. 1 (encode): per block the sign
+ *     bits are stored together, then each |p| with the block's bit width
+ *     (enough bits for the largest |p|).
+ *   - Alg. 2: partial decompression to decorrelated data, quantized data, or
+ *     floats (decode, recorrelate, dequantize).
+ *   - Sec. III-B, Eq. (var) and Eq. (derivatives): mean, standard deviation
+ *     (N-1), central differences.  The operations here are computed plainly
+ *     on the fully decompressed field, never with homomorphic shortcuts.
+ *
+ * Readings where the paper is silent (each is listed with its reason in the
+ * design notes of the repository):
+ *   R1 round() is round-half-up: q = floor(t + 0.5).  The worked example of
+ *      Sec. IV (HSZx-nd paragraph) reproduces only under this rule.
+ *   R2 t = x * (1/Delta) in IEEE binary64 with no fused multiply-add.
+ *   R3 the quantum is Delta = 2*eps_q with eps_q = eps - m*ulp(max|x| + eps),
+ *      m = 1 for binary32 fields and m = 8 for binary64 fields, so that the
+ *      bound |x - x'| <= eps of Sec. III-A holds after floating-point
+ *      rounding.  A relative bound is eps = rel * (max - min) (value-range
+ *      relative, Sec. VI-B); a constant field uses rel * |max|, and an
+ *      all-zero field uses rel.
+ *   R4 slot 0 of every block holds p = 0 (its q is the metadata q0).
+ *   R5 width w = bit length of max |p| over the block (0 if all zero); a
+ *      block with w = 0 stores nothing.  A block with w > 0 stores
+ *      ceil(S/32) sign words then ceil(S*w/32) magnitude words; element i
+ *      owns stream bits [i*w, i*w + w), bit k of the stream is bit k%32 of
+ *      word k/32 (little-endian, least significant bit first).
+ *   R6 |q| <= 2^29 - 1, else the compressor reports a range error.
+ *   R7 derivatives use unit spacing; interior points use central
+ *      differences, the two ends of an axis use one-sided differences
+ *      (the rule of numpy.gradient with edge_order=1); an axis of length 1
+ *      has derivative 0.  Gradient magnitude = sqrt(sum_k g_k^2).
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- error codes (the same numbers the library reports) ---------------- */
+#define OR_OK 0
+#define OR_ERR_ARG (-1)
+#define OR_ERR_STREAM (-2)
+#define OR_ERR_UNSUPPORTED (-3)
+#define OR_ERR_RANGE (-4)
+#define OR_ERR_EB (-5)
+#define OR_ERR_NONFINITE (-6)
+#define OR_ERR_CAPACITY (-7)
+
+/* ---- byte format constants --------------------------------------------- */
+#define OR_HEADER_BYTES 256u
+#define OR_SECTION_ALIGN 256u
+#define OR_CHUNK_BLOCKS 64u
+#define OR_QMAX 536870911 /* 2^29 - 1 */
+
+typedef struct {
+  uint32_t dtype;   /* 1 = binary32, 2 = binary64 */
+  uint32_t ndim;    /* 1..3 */
+  uint64_t dims[3]; /* slow -> fast, unused = 1 (leading) */
+  uint64_t n;
+  uint32_t block;   /* S */
+  uint32_t chunk_blocks;
+  double eb_abs;    /* user bound eps (absolute) */
+  double quantum;   /* Delta = 2 eps_q */
+  double inv_quantum;
+  double vmin, vmax;
+  uint32_t max_abs_q;
+  uint32_t flags;
+  uint64_t nb, nchunks;
+  uint64_t off_chunk, off_q0, off_width, off_payload;
+  uint64_t payload_words;
+  uint64_t total_bytes;
+} or_header;
+
+/* little-endian field writers/readers, byte by byte */
+static void put_u16(uint8_t *p, uint16_t v) { p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8); }
+static void put_u32(uint8_t *p, uint32_t v) { for (int k = 0; k < 4; k++) p[k] = (uint8_t)(v >> (8 * k)); }
+static void put_u64(uint8_t *p, uint64_t v) { for (int k = 0; k < 8; k++) p[k] = (uint8_t)(v >> (8 * k)); }
+static void put_f64(uint8_t *p, double d) { uint64_t v; memcpy(&v, &d, 8); put_u64(p, v); }
+static uint16_t get_u16(const uint8_t *p) { return (uint16_t)(p[0] | (p[1] << 8)); }
+static uint32_t get_u32(const uint8_t *p) { uint32_t v = 0; for (int k = 3; k >= 0; k--) v = (v << 8) | p[k]; return v; }
+static uint64_t get_u64(const uint8_t *p) { uint64_t v = 0; for (int k = 7; k >= 0; k--) v = (v << 8) | p[k]; return v; }
+static double get_f64(const uint8_t *p) { uint64_t v = get_u64(p); double d; memcpy(&d, &v, 8); return d; }
+
+static uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+static uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+/* Section placement: header, chunk offsets, q0, widths, payload. */
+static void layout(or_header *h) {
+  h->nb = ceil_div(h->n, h->block);
+  h->nchunks = ceil_div(h->nb, h->chunk_blocks);
+  h->off_chunk = OR_HEADER_BYTES;
+  h->off_q0 = round_up(h->off_chunk + 8 * (h->nchunks + 1), OR_SECTION_ALIGN);
+  h->off_width = round_up(h->off_q0 + 4 * h->nb, OR_SECTION_ALIGN);
+  h->off_payload = round_up(h->off_width + h->nb, OR_SECTION_ALIGN);
+}
+
+/* words one block occupies in the payload (rule R5) */
+static uint64_t block_words(uint32_t S, uint32_t w) {
+  if (w == 0) return 0;
+  return ceil_div(S, 32) + ceil_div((uint64_t)S * w, 32);
+}
+
+static void write_header(uint8_t *out, const or_header *h) {
+  memset(out, 0, OR_HEADER_BYTES);
+  memcpy(out + 0, "HSZ1", 4);
+  put_u16(out + 4, 1);
+  out[6] = (uint8_t)h->dtype;
+  out[7] = (uint8_t)h->ndim;
+  put_u64(out + 8, h->dims[0]);
+  put_u64(out + 16, h->dims[1]);
+  put_u64(out + 24, h->dims[2]);
+  put_u64(out + 32, h->n);
+  put_u32(out + 40, h->block);
+  put_u32(out + 44, h->chunk_blocks);
+  put_f64(out + 48, h->eb_abs);
+  put_f64(out + 56, h->quantum);
+  put_f64(out + 64, h->inv_quantum);
+  put_f64(out + 72, h->vmin);
+  put_f64(out + 80, h->vmax);
+  put_u32(out + 88, h->max_abs_q);
+  put_u32(out + 92, h->flags);
+  put_u64(out + 96, h->nb);
+  put_u64(out + 104, h->nchunks);
+  put_u64(out + 112, h->off_chunk);
+  put_u64(out + 120, h->off_q0);
+  put_u64(out + 128, h->off_width);
+  put_u64(out + 136, h->off_payload);
+  put_u64(out + 144, h->payload_words);
+  put_u64(out + 152, h->total_bytes);
+}
+
+/* Parse and validate a header.  Returns OR_OK or OR_ERR_STREAM. */
+int or_read_header(const uint8_t *buf, uint64_t len, or_header *h) {
+  if (!buf || !h) return OR_ERR_ARG;
+  if (len < OR_HEADER_BYTES) return OR_ERR_STREAM;
+  if (memcmp(buf, "HSZ1", 4) != 0 || get_u16(buf + 4) != 1) return OR_ERR_STREAM;
+  memset(h, 0, sizeof *h);
+  h->dtype = buf[6];
+  h->ndim = buf[7];
+  h->dims[0] = get_u64(buf + 8);
+  h->dims[1] = get_u64(buf + 16);
+  h->dims[2] = get_u64(buf + 24);
+  h->n = get_u64(buf + 32);
+  h->block = get_u32(buf + 40);
+  h->chunk_blocks = get_u32(buf + 44);
+  h->eb_abs = get_f64(buf + 48);
+  h->quantum = get_f64(buf + 56);
+  h->inv_quantum = get_f64(buf + 64);
+  h->vmin = get_f64(buf + 72);
+  h->vmax = get_f64(buf + 80);
+  h->max_abs_q = get_u32(buf + 88);
+  h->flags = get_u32(buf + 92);
+  h->nb = get_u64(buf + 96);
+  h->nchunks = get_u64(buf + 104);
+  h->off_chunk = get_u64(buf + 112);
+  h->off_q0 = get_u64(buf + 120);
+  h->off_width = get_u64(buf + 128);
+  h->off_payload = get_u64(buf + 136);
+  h->payload_words = get_u64(buf + 144);
+  h->total_bytes = get_u64(buf + 152);
+  if (h->dtype != 1 && h->dtype != 2) return OR_ERR_STREAM;
+  if (h->ndim < 1 || h->ndim > 3) return OR_ERR_STREAM;
+  if (h->block < 1 || h->block > 64 || h->chunk_blocks != OR_CHUNK_BLOCKS) return OR_ERR_STREAM;
+  uint64_t prod = 1;
+  for (int k = 0; k < 3; k++) {
+    if (h->dims[k] == 0) return OR_ERR_STREAM;
+    if (k < 3 - (int)h->ndim && h->dims[k] != 1) return OR_ERR_STREAM;
+    prod *= h->dims[k];
+  }
+  if (prod != h->n || h->n == 0) return OR_ERR_STREAM;
+  if (!(h->quantum > 0.0) || h->inv_quantum != 1.0 / h->quantum) return OR_ERR_STREAM;
+  or_header ref = *h;
+  layout(&ref);
+  if (ref.nb != h->nb || ref.nchunks != h->nchunks || ref.off_chunk != h->off_chunk ||
+      ref.off_q0 != h->off_q0 || ref.off_width != h->off_width || ref.off_payload != h->off_payload)
+    return OR_ERR_STREAM;
+  if (h->total_bytes != h->off_payload + 4 * h->payload_words) return OR_ERR_STREAM;
+  if (h->total_bytes > len) return OR_ERR_STREAM;
+  return OR_OK;
+}
+
+uint64_t or_compress_bound(uint64_t n, uint32_t S) {
+  if (n == 0 || S < 1 || S > 64) return 0;
+  or_header h;
+  memset(&h, 0, sizeof h);
+  h.n = n;
+  h.block = S;
+  h.chunk_blocks = OR_CHUNK_BLOCKS;
+  layout(&h);
+  return h.off_payload + 4 * h.nb * block_words(S, 31);
+}
+
+/* ---- quantizer parameters (rule R3) ------------------------------------ */
+
+/* spacing of the field's floating-point numbers in the binade holding v>0 */
+double or_ulp(double v, int dtype) {
+  int e;
+  frexp(v, &e); /* v = m * 2^e, 0.5 <= m < 1, so v lies in [2^(e-1), 2^e) */
+  return ldexp(1.0, e - 1 - (dtype == 1 ? 23 : 52));
+}
+
+/* From the field's extremes and the user's bound, compute eps (absolute)
+ * and the quantum Delta.  Returns OR_ERR_EB when no positive quantum is
+ * left after the safety margin. */
+int or_quant_params(double vmin, double vmax, double eb, int eb_is_rel, int dtype,
+                    double *eb_abs, double *quantum) {
+  if (!(eb > 0.0) || !isfinite(eb)) return OR_ERR_EB;
+  double eps;
+  if (eb_is_rel) {
+    double range = vmax - vmin;
+    if (range > 0.0) eps = eb * range;
+    else if (fabs(vmax) > 0.0) eps = eb * fabs(vmax);
+    else eps = eb;
+  } else {
+    eps = eb;
+  }
+  double maxabs = fabs(vmin) > fabs(vmax) ? fabs(vmin) : fabs(vmax);
+  double margin = (dtype == 1 ? 1.0 : 8.0) * or_ulp(maxabs + eps, dtype);
+  double eps_q = eps - margin;
+  if (!(eps_q > 0.0)) return OR_ERR_EB;
+  *eb_abs = eps;
+  *quantum = 2.0 * eps_q;
+  return OR_OK;
+}
+
+/* ---- Alg. 1, quantize loop --------------------------------------------- */
+
+/* q_i = round(x_i / Delta), round-half-up, the division done as a multiply
+ * by the stored reciprocal (rules R1, R2).  Returns the number of elements
+ * whose |q| exceeds 2^29 - 1 (their q is clamped). */
+uint64_t or_quantize(const double *x, uint64_t n, double quantum, int32_t *q) {
+  double inv = 1.0 / quantum;
+  uint64_t bad = 0;
+  for (uint64_t i = 0; i < n; i++) {
+    double t = x[i] * inv;
+    double r = floor(t + 0.5);
+    if (r > OR_QMAX) { r = OR_QMAX; bad++; }
+    if (r < -OR_QMAX) { r = -OR_QMAX; bad++; }
+    q[i] = (int32_t)r;
+  }
+  return bad;
+}
+
+/* ---- Alg. 1, partition + metadata + decorrelate + encode --------------- */
+
+static uint32_t bit_length(uint32_t v) {
+  uint32_t w = 0;
+  while (v) { w++; v >>= 1; }
+  return w;
+}
+
+static void stream_set_bits(uint32_t *words, uint64_t bitpos, uint32_t value, uint32_t nbits) {
+  for (uint32_t k = 0; k < nbits; k++)
+    if ((value >> k) & 1u) words[(bitpos + k) / 32] |= 1u << ((bitpos + k) % 32);
+}
+
+static uint32_t stream_get_bits(const uint32_t *words, uint64_t bitpos, uint32_t nbits) {
+  uint32_t v = 0;
+  for (uint32_t k = 0; k < nbits; k++)
+    if ((words[(bitpos + k) / 32] >> ((bitpos + k) % 32)) & 1u) v |= 1u << k;
+  return v;
+}
+
+/* Encode already-quantized integers q[n] (the field read as a flat array)
+ * into the byte format.  'h' carries dtype, dims, eps, Delta, extremes; the
+ * layout fields are filled here.  The output must be zero-filled by this
+ * function's caller or it is cleared here up to the bound. */
+static int encode_q(const int32_t *q, or_header *h, uint8_t *out, uint64_t cap, uint64_t *out_size) {
+  const uint32_t S = h->block;
+  h->chunk_blocks = OR_CHUNK_BLOCKS;
+  layout(h);
+  uint64_t bound = h->off_payload + 4 * h->nb * block_words(S, 31);
+  if (cap < h->off_payload) { if (out_size) *out_size = bound; return OR_ERR_CAPACITY; }
+
+  /* metadata (first q of each block) and decorrelated data p, block by block */
+  int32_t *p = (int32_t *)calloc(h->nb * S, sizeof(int32_t));
+  uint32_t *width = (uint32_t *)calloc(h->nb, sizeof(uint32_t));
+  int32_t *q0 = (int32_t *)calloc(h->nb, sizeof(int32_t));
+  if (!p || !width || !q0) { free(p); free(width); free(q0); return OR_ERR_ARG; }
+  uint32_t max_abs_q = 0;
+  uint64_t words = 0;
+  for (uint64_t b = 0; b < h->nb; b++) {
+    uint64_t first = b * S;
+    uint64_t len = (h->n - first < S) ? h->n - first : S;
+    q0[b] = q[first];
+    uint32_t maxp = 0;
+    for (uint64_t i = 0; i < len; i++) {
+      int32_t qi = q[first + i];
+      uint32_t aq = (uint32_t)(qi < 0 ? -(int64_t)qi : qi);
+      if (aq > max_abs_q) max_abs_q = aq;
+      int32_t pi = (i == 0) ? 0 : qi - q[first + i - 1];
+      p[first + i] = pi;
+      uint32_t ap = (uint32_t)(pi < 0 ? -(int64_t)pi : pi);
+      if (ap > maxp) maxp = ap;
+    }
+    width[b] = bit_length(maxp);
+    words += block_words(S, width[b]);
+  }
+  h->max_abs_q = max_abs_q;
+  h->payload_words = words;
+  h->total_bytes = h->off_payload + 4 * words;
+  if (out_size) *out_size = h->total_bytes;
+  if (cap < h->total_bytes) { free(p); free(width); free(q0); return OR_ERR_CAPACITY; }
+
+  memset(out, 0, h->total_bytes);
+  write_header(out, h);
+  uint32_t *payload = (uint32_t *)calloc(words ? words : 1, sizeof(uint32_t));
+  if (!payload) { free(p); free(width); free(q0); return OR_ERR_ARG; }
+  uint64_t pos = 0;
+  for (uint64_t b = 0; b < h->nb; b++) {
+    if (b % OR_CHUNK_BLOCKS == 0) put_u64(out + h->off_chunk + 8 * (b / OR_CHUNK_BLOCKS), pos);
+    put_u32(out + h->off_q0 + 4 * b, (uint32_t)q0[b]);
+    out[h->off_width + b] = (uint8_t)width[b];
+    uint32_t w = width[b];
+    if (w == 0) continue;
+    uint32_t *sign = payload + pos;
+    uint32_t *mag = sign + ceil_div(S, 32);
+    for (uint32_t i = 0; i < S; i++) {
+      uint64_t e = b * S + i;
+      int32_t pi = (e < h->n) ? p[e] : 0;
+      if (pi < 0) sign[i / 32] |= 1u << (i % 32);
+      uint32_t ap = (uint32_t)(pi < 0 ? -(int64_t)pi : pi);
+      stream_set_bits(mag, (uint64_t)i * w, ap, w);
+    }
+    pos += block_words(S, w);
+  }
+  put_u64(out + h->off_chunk + 8 * h->nchunks, pos);
+  for (uint64_t k = 0; k < words; k++) put_u32(out + h->off_payload + 4 * k, payload[k]);
+  free(payload); free(p); free(width); free(q0);
+  return OR_OK;
+}
+
+/* Encode given quantization integers (used to pin the decorrelation and the
+ * encoding on the paper's worked example, where the quantum is fixed). */
+int or_encode_q(const int32_t *q, uint32_t ndim, const uint64_t *dims, uint32_t dtype,
+                double eb_abs, double quantum, uint32_t S, uint8_t *out, uint64_t cap,
+                uint64_t *out_size) {
+  if (!q || !dims || ndim < 1 || ndim > 3 || S < 1 || S > 64 || (dtype != 1 && dtype != 2))
+    return OR_ERR_ARG;
+  or_header h;
+  memset(&h, 0, sizeof h);
+  h.dtype = dtype;
+  h.ndim = ndim;
+  for (int k = 0; k < 3; k++) h.dims[k] = 1;
+  h.n = 1;
+  for (uint32_t k = 0; k < ndim; k++) { h.dims[3 - ndim + k] = dims[k]; h.n *= dims[k]; }
+  if (h.n == 0) return OR_ERR_ARG;
+  h.block = S;
+  h.eb_abs = eb_abs;
+  h.quantum = quantum;
+  h.inv_quantum = 1.0 / quantum;
+  h.vmin = 0.0;
+  h.vmax = 0.0;
+  return encode_q(q, &h, out, cap, out_size);
+}
+
+/* Full compressor C(d, eps): extremes -> parameters -> quantize -> encode. */
+int or_compress(const void *x, uint32_t dtype, uint32_t ndim, const uint64_t *dims, double eb,
+                int eb_is_rel, uint32_t S, uint8_t *out, uint64_t cap, uint64_t *out_size) {
+  if (!x || !dims || ndim < 1 || ndim > 3 || S < 1 || S > 64 || (dtype != 1 && dtype != 2))
+    return OR_ERR_ARG;
+  or_header h;
+  memset(&h, 0, sizeof h);
+  h.dtype = dtype;
+  h.ndim = ndim;
+  for (int k = 0; k < 3; k++) h.dims[k] = 1;
+  h.n = 1;
+  for (uint32_t k = 0; k < ndim; k++) { h.dims[3 - ndim + k] = dims[k]; h.n *= dims[k]; }
+  if (h.n == 0) return OR_ERR_ARG;
+  h.block = S;
+
+  double *xd = (double *)malloc(h.n * sizeof(double));
+  if (!xd) return OR_ERR_ARG;
+  for (uint64_t i = 0; i < h.n; i++)
+    xd[i] = (dtype == 1) ? (double)((const float *)x)[i] : ((const double *)x)[i];
+  double vmin = xd[0], vmax = xd[0];
+  for (uint64_t i = 0; i < h.n; i++) {
+    if (!isfinite(xd[i])) { free(xd); return OR_ERR_NONFINITE; }
+    if (xd[i] < vmin) vmin = xd[i];
+    if (xd[i] > vmax) vmax = xd[i];
+  }
+  h.vmin = vmin;
+  h.vmax = vmax;
+  int rc = or_quant_params(vmin, vmax, eb, eb_is_rel, (int)dtype, &h.eb_abs, &h.quantum);
+  if (rc != OR_OK) { free(xd); return rc; }
+  h.inv_quantum = 1.0 / h.quantum;
+
+  int32_t *q = (int32_t *)malloc(h.n * sizeof(int32_t));
+  if (!q) { free(xd); return OR_ERR_ARG; }
+  uint64_t bad = or_quantize(xd, h.n, h.quantum, q);
+  free(xd);
+  if (bad) { free(q); return OR_ERR_RANGE; }
+  rc = encode_q(q, &h, out, cap, out_size);
+  free(q);
+  return rc;
+}
+
+/* ---- Alg. 2: partial decompression ------------------------------------- */
+
+/* stage: 1 = metadata (q0[nb]); 2 = decorrelated data (p[n] then q0[nb]);
+ * 3 = quantized data (q[n]); 4 = decompressed floats (field dtype, n).
+ * 'out' must hold or_stage_bytes(...) bytes. */
+uint64_t or_stage_bytes(const uint8_t *buf, uint64_t len, int stage) {
+  or_header h;
+  if (or_read_header(buf, len, &h) != OR_OK) return 0;
+  switch (stage) {
+    case 1: return 4 * h.nb;
+    case 2: return 4 * h.n + 4 * h.nb;
+    case 3: return 4 * h.n;
+    case 4: return (h.dtype == 1 ? 4 : 8) * h.n;
+    default: return 0;
+  }
+}
+
+int or_decompress(const uint8_t *buf, uint64_t len, int stage, void *out) {
+  or_header h;
+  int rc = or_read_header(buf, len, &h);
+  if (rc != OR_OK) return rc;
+  if (!out || stage < 1 || stage > 4) return OR_ERR_ARG;
+  const uint32_t S = h.block;
+  int32_t *q0 = (int32_t *)malloc(h.nb * sizeof(int32_t));
+  if (!q0) return OR_ERR_ARG;
+  for (uint64_t b = 0; b < h.nb; b++) q0[b] = (int32_t)get_u32(buf + h.off_q0 + 4 * b);
+  if (stage == 1) { memcpy(out, q0, h.nb * sizeof(int32_t)); free(q0); return OR_OK; }
+
+  /* decode: signs and magnitudes -> p */
+  int32_t *p = (int32_t *)calloc(h.n, sizeof(int32_t));
+  if (!p) { free(q0); return OR_ERR_ARG; }
+  uint64_t pos = 0;
+  for (uint64_t b = 0; b < h.nb; b++) {
+    if (b % OR_CHUNK_BLOCKS == 0 && get_u64(buf + h.off_chunk + 8 * (b / OR_CHUNK_BLOCKS)) != pos) {
+      free(p); free(q0); return OR_ERR_STREAM;
+    }
+    uint32_t w = buf[h.off_width + b];
+    if (w > 30) { free(p); free(q0); return OR_ERR_STREAM; }
+    if (w == 0) continue;
+    uint64_t nw = block_words(S, w);
+    if (pos + nw > h.payload_words) { free(p); free(q0); return OR_ERR_STREAM; }
+    uint32_t *blk = (uint32_t *)malloc(nw * sizeof(uint32_t));
+    if (!blk) { free(p); free(q0); return OR_ERR_ARG; }
+    for (uint64_t k = 0; k < nw; k++) blk[k] = get_u32(buf + h.off_payload + 4 * (pos + k));
+    const uint32_t *mag = blk + ceil_div(S, 32);
+    for (uint32_t i = 0; i < S; i++) {
+      uint64_t e = b * S + i;
+      if (e >= h.n) break;
+      uint32_t a = stream_get_bits(mag, (uint64_t)i * w, w);
+      int neg = (blk[i / 32] >> (i % 32)) & 1u;
+      p[e] = neg ? -(int32_t)a : (int32_t)a;
+    }
+    free(blk);
+    pos += nw;
+  }
+  if (pos != h.payload_words) { free(p); free(q0); return OR_ERR_STREAM; }
+  if (stage == 2) {
+    memcpy(out, p, h.n * sizeof(int32_t));
+    memcpy((int32_t *)out + h.n, q0, h.nb * sizeof(int32_t));
+    free(p); free(q0);
+    return OR_OK;
+  }
+
+  /* recorrelate: q_i = q_{i-1} + p_i inside a block, starting from q0 */
+  int32_t *q = (int32_t *)malloc(h.n * sizeof(int32_t));
+  if (!q) { free(p); free(q0); return OR_ERR_ARG; }
+  for (uint64_t e = 0; e < h.n; e++) {
+    uint64_t b = e / S;
+    q[e] = (e % S == 0) ? q0[b] : q[e - 1] + p[e];
+  }
+  free(p); free(q0);
+  if (stage == 3) { memcpy(out, q, h.n * sizeof(int32_t)); free(q); return OR_OK; }
+
+  /* dequantize: d' = q * Delta (Delta = 2 eps_q) */
+  for (uint64_t e = 0; e < h.n; e++) {
+    double v = (double)q[e] * h.quantum;
+    if (h.dtype == 1) ((float *)out)[e] = (float)v;
+    else ((double *)out)[e] = v;
+  }
+  free(q);
+  return OR_OK;
+}
+
+/* d' = q * Delta in binary64 (the decompressed value before it is stored in
+ * the field's own type). */
+void or_dequantize64(const int32_t *q, uint64_t n, double quantum, double *out) {
+  for (uint64_t i = 0; i < n; i++) out[i] = (double)q[i] * quantum;
+}
+
+/* ---- operations on the decompressed field (Sec. III-B) ----------------- */
+
+/* dims3: slow -> fast, box lo/hi half-open, all 3D (leading axes of length
+ * 1 for 1D and 2D fields).  NULL box = whole field. */
+typedef struct { int64_t lo[3], hi[3]; } or_box;
+
+static int box_ok(const uint64_t *d, const int64_t *lo, const int64_t *hi, or_box *b) {
+  for (int k = 0; k < 3; k++) {
+    b->lo[k] = lo ? lo[k] : 0;
+    b->hi[k] = hi ? hi[k] : (int64_t)d[k];
+    if (b->lo[k] < 0 || b->hi[k] > (int64_t)d[k] || b->lo[k] >= b->hi[k]) return 0;
+  }
+  return 1;
+}
+
+/* Neumaier-compensated running sum */
+typedef struct { double s, c; } ksum;
+static void ksum_add(ksum *k, double v) {
+  double t = k->s + v;
+  if (fabs(k->s) >= fabs(v)) k->c += (k->s - t) + v;
+  else k->c += (v - t) + k->s;
+  k->s = t;
+}
+static double ksum_get(const ksum *k) { return k->s + k->c; }
+
+/* mean = (sum of d_i) / N over the box */
+int or_mean(const double *x, const uint64_t *d, const int64_t *lo, const int64_t *hi, double *mean) {
+  or_box b;
+  if (!box_ok(d, lo, hi, &b)) return OR_ERR_ARG;
+  ksum k = {0, 0};
+  int64_t cnt = 0;
+  for (int64_t z = b.lo[0]; z < b.hi[0]; z++)
+    for (int64_t y = b.lo[1]; y < b.hi[1]; y++)
+      for (int64_t xx = b.lo[2]; xx < b.hi[2]; xx++) {
+        ksum_add(&k, x[((uint64_t)z * d[1] + (uint64_t)y) * d[2] + (uint64_t)xx]);
+        cnt++;
+      }
+  *mean = ksum_get(&k) / (double)cnt;
+  return OR_OK;
+}
+
+/* sample variance sum (d_i - mu)^2 / (N - 1), two passes */
+int or_var(const double *x, const uint64_t *d, const int64_t *lo, const int64_t *hi, double *var) {
+  or_box b;
+  if (!box_ok(d, lo, hi, &b)) return OR_ERR_ARG;
+  double mu;
+  or_mean(x, d, lo, hi, &mu);
+  ksum k = {0, 0};
+  int64_t cnt = 0;
+  for (int64_t z = b.lo[0]; z < b.hi[0]; z++)
+    for (int64_t y = b.lo[1]; y < b.hi[1]; y++)
+      for (int64_t xx = b.lo[2]; xx < b.hi[2]; xx++) {
+        double e = x[((uint64_t)z * d[1] + (uint64_t)y) * d[2] + (uint64_t)xx] - mu;
+        ksum_add(&k, e * e);
+        cnt++;
+      }
+  *var = (cnt > 1) ? ksum_get(&k) / (double)(cnt - 1) : NAN;
+  return OR_OK;
+}
+
+/* derivative of the field along axis a (0 = slowest of the 3D view) at one
+ * point, unit spacing, rule R7 */
+static double deriv_at(const double *x, const uint64_t *d, int a, int64_t z, int64_t y, int64_t xx) {
+  int64_t idx[3] = {z, y, xx};
+  int64_t len = (int64_t)d[a];
+  if (len < 2) return 0.0;
+  int64_t im = idx[a] - 1, ip = idx[a] + 1;
+  double denom = 2.0;
+  if (idx[a] == 0) { im = 0; denom = 1.0; }
+  if (idx[a] == len - 1) { ip = len - 1; denom = 1.0; }
+  int64_t jm[3] = {z, y, xx}, jp[3] = {z, y, xx};
+  jm[a] = im;
+  jp[a] = ip;
+  double vm = x[((uint64_t)jm[0] * d[1] + (uint64_t)jm[1]) * d[2] + (uint64_t)jm[2]];
+  double vp = x[((uint64_t)jp[0] * d[1] + (uint64_t)jp[1]) * d[2] + (uint64_t)jp[2]];
+  return (vp - vm) / denom;
+}
+
+/* out[box volume] = derivative along axis a (3D view axis) */
+int or_derivative(const double *x, const uint64_t *d, int a, const int64_t *lo, const int64_t *hi, double *out) {
+  or_box b;
+  if (a < 0 || a > 2 || !box_ok(d, lo, hi, &b)) return OR_ERR_ARG;
+  uint64_t o = 0;
+  for (int64_t z = b.lo[0]; z < b.hi[0]; z++)
+    for (int64_t y = b.lo[1]; y < b.hi[1]; y++)
+      for (int64_t xx = b.lo[2]; xx < b.hi[2]; xx++) out[o++] = deriv_at(x, d, a, z, y, xx);
+  return OR_OK;
+}
+
+/* out[box volume] = sqrt(sum over axes of derivative^2) */
+int or_gradmag(const double *x, const uint64_t *d, const int64_t *lo, const int64_t *hi, double *out) {
+  or_box b;
+  if (!box_ok(d, lo, hi, &b)) return OR_ERR_ARG;
+  uint64_t o = 0;
+  for (int64_t z = b.lo[0]; z < b.hi[0]; z++)
+    for (int64_t y = b.lo[1]; y < b.hi[1]; y++)
+      for (int64_t xx = b.lo[2]; xx < b.hi[2]; xx++) {
+        double s = 0.0;
+        for (int a = 0; a < 3; a++) {
+          double g = deriv_at(x, d, a, z, y, xx);
+          s += g * g;
+        }
+        out[o++] = sqrt(s);
+      }
+  return OR_OK;
+}
+
+/* Exact integer sums over the box of the quantized field: N, sum q, sum q^2
+ * (the last as a 128-bit two's-complement value split into lo/hi words). */
+int or_int_sums(const int32_t *q, const uint64_t *d, const int64_t *lo, const int64_t *hi,
+                int64_t *n, int64_t *s1, uint64_t *s2_lo, int64_t *s2_hi) {
+  or_box b;
+  if (!box_ok(d, lo, hi, &b)) return OR_ERR_ARG;
+  int64_t cnt = 0, a1 = 0;
+  __int128 a2 = 0;
+  for (int64_t z = b.lo[0]; z < b.hi[0]; z++)
+    for (int64_t y = b.lo[1]; y < b.hi[1]; y++)
+      for (int64_t xx = b.lo[2]; xx < b.hi[2]; xx++) {
+        int64_t v = q[((uint64_t)z * d[1] + (uint64_t)y) * d[2] + (uint64_t)xx];
+        cnt++;
+        a1 += v;
+        a2 += (__int128)(v * v);
+      }
+  *n = cnt;
+  *s1 = a1;
+  *s2_lo = (uint64_t)a2;
+  *s2_hi = (int64_t)(a2 >> 64);
+  return OR_OK;
+}
