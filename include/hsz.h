@@ -1,0 +1,204 @@
+/*
+ * hsz.h -- C ABI of libhsz: error-bounded SZp-style compression, multi-stage
+ * decompression and homomorphic analytical operations on MI355X (gfx950).
+ *
+ * The operations follow the problem statement of Sec. III-A of "Enabling
+ * Homomorphic Analytical Operations on Compressed Scientific Data with
+ * Multi-stage Decompression": a compressor c = C(d, eps), a decompressor
+ * split into stages D = D_m o ... o D_1 with intermediate representations
+ * d^(i), and operations Q_i evaluated directly on d^(i).  Stage numbers are
+ * those of Table I: 1 metadata (D_m), 2 decorrelated data (D_p),
+ * 3 quantized data (D_q), 4 fully decompressed floats (D_f).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named d_* are DEVICE pointers (HIP global memory of the
+ *     current device); pointers named h_* are HOST pointers.  The caller owns
+ *     every buffer; the library never allocates, frees or retains caller
+ *     memory.  Device buffers must be 16-byte aligned.
+ *   - 'stream' is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call that takes a stream only enqueues work on it and returns;
+ *     results are valid after the stream is synchronised.
+ *   - Every entry point returns HSZ_OK (0) or a negative HSZ_ERR_* code and
+ *     never throws.  Argument errors are detected on the host before any
+ *     work is enqueued.  Errors that depend on data (non-finite input, an
+ *     out-of-range quantization integer, a corrupt block width) are
+ *     detected by the kernels and recorded in a status word at the start of
+ *     the call's workspace; read it with hsz_read_status().
+ *   - Fields are C-order (row-major) arrays of 1, 2 or 3 dimensions, dims
+ *     listed slow -> fast.  Boxes are half-open [lo, hi) per axis in the
+ *     field's own axes; a NULL box means the whole field.
+ *   - The library is reentrant: calls that use distinct workspaces may run
+ *     concurrently on different streams.
+ */
+#ifndef HSZ_H
+#define HSZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- codes ---------------------------------------------------------------- */
+enum {
+  HSZ_OK = 0,
+  HSZ_ERR_INVALID_ARG = -1, /* bad pointer, size, shape, alignment, enum    */
+  HSZ_ERR_BAD_STREAM = -2,  /* corrupt or truncated compressed stream       */
+  HSZ_ERR_UNSUPPORTED = -3, /* op not defined at that stage, or block size  */
+  HSZ_ERR_RANGE = -4,       /* |q| would exceed 2^29 - 1                    */
+  HSZ_ERR_EB = -5,          /* error bound <= 0 or below the dtype spacing   */
+  HSZ_ERR_NONFINITE = -6,   /* NaN or Inf in the input field                */
+  HSZ_ERR_CAPACITY = -7,    /* output or workspace buffer too small         */
+  HSZ_ERR_HIP = -8          /* a HIP runtime call failed (hsz_last_hip_error) */
+};
+
+enum { HSZ_F32 = 1, HSZ_F64 = 2 };                                  /* field dtype */
+enum { HSZ_META = 1, HSZ_DELTA = 2, HSZ_QUANT = 3, HSZ_FLOAT = 4 }; /* Table I     */
+enum { HSZ_MEAN = 1, HSZ_VAR = 2, HSZ_DERIV = 3, HSZ_GRADMAG = 4 }; /* operations  */
+
+/* Size of the fixed header at the start of every compressed stream. */
+#define HSZ_HEADER_BYTES 256
+
+/* Parsed header of a compressed stream (host-side copy). */
+typedef struct hsz_header {
+  int32_t dtype;          /* HSZ_F32 / HSZ_F64                               */
+  int32_t ndim;           /* 1..3                                            */
+  int64_t dims[3];        /* the field's own dims, slow -> fast (ndim used)  */
+  int64_t n;              /* element count                                   */
+  int32_t block;          /* S: elements per block (32 or 64 on the GPU)     */
+  int32_t chunk_blocks;   /* blocks per chunk-offset entry (64)              */
+  double eb_abs;          /* eps: absolute error bound the stream honours    */
+  double quantum;         /* Delta = 2*eps_q, d' = q * Delta                 */
+  double inv_quantum;     /* 1 / Delta, the quantizer's multiplier           */
+  double vmin, vmax;      /* extremes of the input field                     */
+  uint32_t max_abs_q;     /* max |q| over the field                          */
+  uint32_t flags;         /* reserved, 0                                     */
+  int64_t nb;             /* number of blocks = ceil(n / S)                  */
+  int64_t nchunks;        /* ceil(nb / 64)                                   */
+  uint64_t off_chunk;     /* byte offsets of the sections in the stream      */
+  uint64_t off_q0;
+  uint64_t off_width;
+  uint64_t off_payload;
+  uint64_t payload_words; /* 32-bit words in the payload section             */
+  uint64_t total_bytes;   /* stream length                                   */
+} hsz_header;
+
+/* Half-open box [lo, hi) in the field's own axes (first ndim entries used). */
+typedef struct hsz_box {
+  int64_t lo[3];
+  int64_t hi[3];
+} hsz_box;
+
+/* Result of HSZ_MEAN / HSZ_VAR (48 bytes, written to device memory).
+ * On stages 2 and 3 (and the fused path via 2 or 3), s1 = sum q and
+ * s2 = sum q^2 over the box are exact (s2 is a two's-complement 128-bit
+ * integer s2_hi:s2_lo); mean = s1*Delta/n and var = (n*s2 - s1^2) /
+ * (n*(n-1)) * Delta^2 are rounded once from the exact integers.  HSZ_MEAN
+ * leaves s2 = 0 and var = NaN.  On stage 4 the sums are 0 and mean/var are
+ * computed from the floats in binary64. */
+typedef struct hsz_stats {
+  int64_t n;
+  int64_t s1;
+  uint64_t s2_lo;
+  int64_t s2_hi;
+  double mean;
+  double var;
+} hsz_stats;
+
+/* ---- housekeeping ----------------------------------------------------------- */
+
+/* Static string for a code; never NULL. */
+const char *hsz_strerror(int code);
+
+/* Library version: major*10000 + minor*100 + patch. */
+int hsz_version(void);
+
+/* Last HIP error code seen by the library on this thread (hipError_t). */
+int hsz_last_hip_error(void);
+
+/* Read the status word at the start of a workspace after the stream that
+ * used it has completed: synchronises 'stream', then stores HSZ_OK or the
+ * first data-dependent error any kernel of the call recorded. */
+int hsz_read_status(const void *d_workspace, void *stream, int *h_status);
+
+/* ---- compression: c = C(d, eps), Sec. IV, Alg. 1 -------------------------------
+ * Quantize q = floor(x/Delta + 0.5) (binary64, the division done as a
+ * multiply by 1/Delta), partition the flat array into blocks of S, keep the
+ * first q of each block (q0), decorrelate p_i = q_i - q_{i-1} inside the
+ * block, and encode each block as its sign bits followed by |p| at the
+ * block's bit width.  eps is absolute (eb_is_rel = 0) or relative to the
+ * value range max - min (eb_is_rel = 1).  The quantum is
+ * Delta = 2*(eps - m*ulp(max|x| + eps)) with m = 1 (binary32) or 8
+ * (binary64), so |x - x'| <= eps holds for every element after rounding. */
+
+/* Worst-case stream size for a field (bytes). */
+int hsz_compress_bound(int dtype, int ndim, const int64_t *h_dims, int block, uint64_t *h_bytes);
+
+/* Workspace hsz_compress needs (bytes). */
+int hsz_compress_workspace(int ndim, const int64_t *h_dims, int block, uint64_t *h_bytes);
+
+/* Compress d_x (dtype, dims) into d_out (capacity 'cap' bytes, at least
+ * hsz_compress_bound()).  The stream's length is header.total_bytes; after
+ * the stream completes, read the header back (HSZ_HEADER_BYTES from d_out)
+ * and check hsz_read_status(d_workspace).  block must be 32 or 64. */
+int hsz_compress(const void *d_x, int dtype, int ndim, const int64_t *h_dims, double eb,
+                 int eb_is_rel, int block, void *d_out, uint64_t cap, void *d_workspace,
+                 uint64_t workspace_bytes, void *stream);
+
+/* Parse and validate a header held in HOST memory.  'len' is the number of
+ * stream bytes the caller holds (at least HSZ_HEADER_BYTES); the stream's
+ * own length must not exceed 'len_stream' (pass the device buffer size). */
+int hsz_read_header(const void *h_bytes, uint64_t len, uint64_t len_stream, hsz_header *h_out);
+
+/* ---- multi-stage decompression: d^(i) = D_i(...D_1(c)), Alg. 2 ---------------
+ * Stage buffer layouts (bytes from hsz_stage_bytes):
+ *   HSZ_META  : q0 int32[nb]                   (first q of each block)
+ *   HSZ_DELTA : p int32[n], then q0 int32[nb]  (p = 0 at each block's slot 0)
+ *   HSZ_QUANT : q int32[n]
+ *   HSZ_FLOAT : d' = (dtype)(q * Delta), dtype[n] */
+int hsz_stage_bytes(const hsz_header *h, int stage, uint64_t *h_bytes);
+
+/* Decode the stream d_c (device) to 'stage' into d_out (capacity 'cap').
+ * d_workspace (at least 256 bytes) receives the status word: a block whose
+ * width or payload disagrees with the chunk table is reported as
+ * HSZ_ERR_BAD_STREAM and decoded as constant q0 (never read out of bounds). */
+int hsz_decompress_to_stage(const void *d_c, const hsz_header *h, int stage, void *d_out,
+                            uint64_t cap, void *d_workspace, uint64_t workspace_bytes,
+                            void *stream);
+
+/* ---- operations Q_i(d^(i)), Sec. V ------------------------------------------
+ * op = HSZ_MEAN, HSZ_VAR : result = one hsz_stats (Eq. (var), sample
+ *      variance with N - 1; the standard deviation is sqrt(var)).
+ * op = HSZ_DERIV (axis)  : result = derivative along 'axis' (0 = slowest)
+ *      at every point of the box, field dtype, box-shaped C order.
+ * op = HSZ_GRADMAG       : result = sqrt(sum over axes of derivative^2).
+ * Derivatives follow Eq. (derivatives): central differences (q_{+1} -
+ * q_{-1}) * Delta/2 inside the field and one-sided (q_1 - q_0) * Delta at
+ * its ends, unit spacing, neighbours taken from the whole field even when
+ * they lie outside the box; an axis of length 1 contributes 0.
+ * Stage support: MEAN/VAR on stages 2, 3, 4; DERIV/GRADMAG on 2, 3, 4;
+ * stage 1 supports none (HSZ_ERR_UNSUPPORTED), as Table II lists for SZp. */
+
+/* Workspace an operation needs (bytes; at least 256). */
+int hsz_op_workspace(const hsz_header *h, int op, uint64_t *h_bytes);
+
+/* Operation on a materialised stage buffer produced by
+ * hsz_decompress_to_stage (d_stage, 'stage'). */
+int hsz_op_on_stage(const void *d_stage, const hsz_header *h, int stage, int op, int axis,
+                    const hsz_box *h_box, void *d_result, uint64_t cap, void *d_workspace,
+                    uint64_t workspace_bytes, void *stream);
+
+/* The same operation computed directly from the compressed stream d_c in one
+ * pass, the intermediate stage 'via' (2, 3 or 4) existing only in registers
+ * and on-chip memory (the blockwise pipeline of Alg. 3).  Results equal
+ * hsz_op_on_stage on the same stage bit for bit for integer sums, within
+ * rounding for floating-point results. */
+int hsz_op_fused(const void *d_c, const hsz_header *h, int via, int op, int axis,
+                 const hsz_box *h_box, void *d_result, uint64_t cap, void *d_workspace,
+                 uint64_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSZ_H */

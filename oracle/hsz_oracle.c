@@ -207,7 +207,8 @@ uint64_t or_compress_bound(uint64_t n, uint32_t S) {
   h.block = S;
   h.chunk_blocks = OR_CHUNK_BLOCKS;
   layout(&h);
-  return h.off_payload + 4 * h.nb * block_words(S, 31);
+  /* |q| <= 2^29 - 1 (R6) bounds |p| below 2^30, so no block is wider than 30 bits */
+  return h.off_payload + 4 * h.nb * block_words(S, 30);
 }
 
 /* ---- quantizer parameters (rule R3) ------------------------------------ */
@@ -289,7 +290,7 @@ static int encode_q(const int32_t *q, or_header *h, uint8_t *out, uint64_t cap, 
   const uint32_t S = h->block;
   h->chunk_blocks = OR_CHUNK_BLOCKS;
   layout(h);
-  uint64_t bound = h->off_payload + 4 * h->nb * block_words(S, 31);
+  uint64_t bound = h->off_payload + 4 * h->nb * block_words(S, 30);
   if (cap < h->off_payload) { if (out_size) *out_size = bound; return OR_ERR_CAPACITY; }
 
   /* metadata (first q of each block) and decorrelated data p, block by block */
@@ -399,6 +400,10 @@ int or_compress(const void *x, uint32_t dtype, uint32_t ndim, const uint64_t *di
     if (xd[i] < vmin) vmin = xd[i];
     if (xd[i] > vmax) vmax = xd[i];
   }
+  /* + 0.0 turns a -0.0 extreme into +0.0, so the stored extremes have one
+     byte pattern whichever of two equal zeros came first */
+  vmin = vmin + 0.0;
+  vmax = vmax + 0.0;
   h.vmin = vmin;
   h.vmax = vmax;
   int rc = or_quant_params(vmin, vmax, eb, eb_is_rel, (int)dtype, &h.eb_abs, &h.quantum);

@@ -1,0 +1,356 @@
+// api.cpp -- the C ABI of libhsz (declared in include/hsz.h): argument and
+// stream validation on the host, then stream-ordered kernel launches.
+#include "../../include/hsz.h"
+
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include "hsz_device.hpp"
+#include "hsz_launch.hpp"
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return HSZ_ERR_HIP;
+}
+
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+uint16_t rd16(const uint8_t* p) { return (uint16_t)(p[0] | (p[1] << 8)); }
+uint32_t rd32(const uint8_t* p) {
+  uint32_t v = 0;
+  for (int k = 3; k >= 0; --k) v = (v << 8) | p[k];
+  return v;
+}
+uint64_t rd64(const uint8_t* p) {
+  uint64_t v = 0;
+  for (int k = 7; k >= 0; --k) v = (v << 8) | p[k];
+  return v;
+}
+double rdf64(const uint8_t* p) {
+  uint64_t v = rd64(p);
+  double d;
+  memcpy(&d, &v, 8);
+  return d;
+}
+
+// dims of the field's own axes -> 3D view with leading ones
+bool dims3_of(int ndim, const int64_t* dims, int64_t out[3], int64_t* n) {
+  if (ndim < 1 || ndim > 3 || !dims) return false;
+  out[0] = out[1] = out[2] = 1;
+  int64_t prod = 1;
+  for (int k = 0; k < ndim; ++k) {
+    if (dims[k] < 1) return false;
+    out[3 - ndim + k] = dims[k];
+    if (prod > (int64_t(1) << 40) / dims[k]) return false;
+    prod *= dims[k];
+  }
+  *n = prod;
+  return true;
+}
+
+bool valid_block(int block) { return block == 32 || block == 64; }
+
+hsz::StreamView view_of(const void* d_c, const hsz_header* h) {
+  hsz::StreamView v;
+  const uint8_t* base = (const uint8_t*)d_c;
+  v.base = base;
+  v.chunk_off = (const uint64_t*)(base + h->off_chunk);
+  v.q0 = (const int32_t*)(base + h->off_q0);
+  v.width = base + h->off_width;
+  v.payload = (const uint32_t*)(base + h->off_payload);
+  v.payload_words = h->payload_words;
+  v.n = h->n;
+  v.nb = h->nb;
+  v.nchunks = h->nchunks;
+  v.block = h->block;
+  v.dtype = h->dtype;
+  v.quantum = h->quantum;
+  v.max_abs_q = h->max_abs_q;
+  return v;
+}
+
+// Re-check a header the caller hands back (it may have been edited).
+int check_header(const hsz_header* h) {
+  if (!h) return HSZ_ERR_INVALID_ARG;
+  if (h->dtype != HSZ_F32 && h->dtype != HSZ_F64) return HSZ_ERR_BAD_STREAM;
+  int64_t d3[3], n;
+  if (!dims3_of(h->ndim, h->dims, d3, &n) || n != h->n) return HSZ_ERR_BAD_STREAM;
+  if (!valid_block(h->block)) return HSZ_ERR_UNSUPPORTED;
+  hsz::Layout L = hsz::make_layout(h->n, h->block);
+  if (L.nb != h->nb || L.nchunks != h->nchunks || L.off_chunk != h->off_chunk || L.off_q0 != h->off_q0 ||
+      L.off_width != h->off_width || L.off_payload != h->off_payload)
+    return HSZ_ERR_BAD_STREAM;
+  if (h->total_bytes != h->off_payload + 4 * h->payload_words) return HSZ_ERR_BAD_STREAM;
+  if (!(h->quantum > 0.0) || h->max_abs_q > (uint32_t)hsz::kQMax) return HSZ_ERR_BAD_STREAM;
+  return HSZ_OK;
+}
+
+__global__ void k_reset_status(int* status) {
+  if (threadIdx.x == 0) *status = 0;
+}
+
+int reset_status(void* ws, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, (int*)ws);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? HSZ_OK : hip_fail(e);
+}
+
+// box in the field's axes -> 3D box; NULL = whole field
+bool box3_of(const hsz_header* h, const hsz_box* b, hsz::Box3* o) {
+  int64_t d3[3], n;
+  dims3_of(h->ndim, h->dims, d3, &n);
+  int64_t lo[3] = {0, 0, 0}, hi[3] = {d3[0], d3[1], d3[2]};
+  if (b) {
+    for (int k = 0; k < h->ndim; ++k) {
+      const int a = 3 - h->ndim + k;
+      lo[a] = b->lo[k];
+      hi[a] = b->hi[k];
+      if (lo[a] < 0 || hi[a] > d3[a] || lo[a] >= hi[a]) return false;
+    }
+  }
+  *o = hsz::Box3{lo[0], hi[0], lo[1], hi[1], lo[2], hi[2]};
+  return true;
+}
+
+int op_common(const hsz_header* h, int op, int axis, const hsz_box* box, uint64_t cap, void* d_result,
+              void* d_ws, uint64_t ws_bytes, hsz::OpTarget* t, int* axis3) {
+  int rc = check_header(h);
+  if (rc) return rc;
+  if (op < HSZ_MEAN || op > HSZ_GRADMAG) return HSZ_ERR_INVALID_ARG;
+  if (!d_result || !d_ws || !aligned16(d_ws)) return HSZ_ERR_INVALID_ARG;
+  if (ws_bytes < hsz::op_workspace_bytes()) return HSZ_ERR_CAPACITY;
+  int64_t d3[3], n;
+  dims3_of(h->ndim, h->dims, d3, &n);
+  t->d = hsz::Dims3{d3[0], d3[1], d3[2]};
+  if (!box3_of(h, box, &t->box)) return HSZ_ERR_INVALID_ARG;
+  if (op == HSZ_DERIV) {
+    if (axis < 0 || axis >= h->ndim) return HSZ_ERR_INVALID_ARG;
+    *axis3 = axis + 3 - h->ndim;
+  } else {
+    *axis3 = 0;
+  }
+  const uint64_t esz = h->dtype == HSZ_F32 ? 4 : 8;
+  const uint64_t need = (op <= HSZ_VAR) ? sizeof(hsz_stats) : esz * (uint64_t)t->box.volume();
+  if (cap < need) return HSZ_ERR_CAPACITY;
+  if (op >= HSZ_DERIV && !aligned16(d_result)) return HSZ_ERR_INVALID_ARG;
+  return HSZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hsz_strerror(int code) {
+  switch (code) {
+    case HSZ_OK: return "ok";
+    case HSZ_ERR_INVALID_ARG: return "invalid argument";
+    case HSZ_ERR_BAD_STREAM: return "corrupt or truncated compressed stream";
+    case HSZ_ERR_UNSUPPORTED: return "operation or block size not supported at this stage";
+    case HSZ_ERR_RANGE: return "quantization integer out of range (|q| > 2^29 - 1)";
+    case HSZ_ERR_EB: return "error bound not positive or below the field's floating-point spacing";
+    case HSZ_ERR_NONFINITE: return "non-finite value in the input field";
+    case HSZ_ERR_CAPACITY: return "buffer too small";
+    case HSZ_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown error";
+}
+
+int hsz_version(void) { return 100; }
+
+int hsz_last_hip_error(void) { return g_last_hip; }
+
+int hsz_read_status(const void* d_workspace, void* stream, int* h_status) {
+  if (!d_workspace || !h_status) return HSZ_ERR_INVALID_ARG;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e);
+  int st = 0;
+  e = hipMemcpy(&st, d_workspace, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e);
+  *h_status = st;
+  return HSZ_OK;
+}
+
+int hsz_compress_bound(int dtype, int ndim, const int64_t* h_dims, int block, uint64_t* h_bytes) {
+  int64_t d3[3], n;
+  if (!h_bytes || (dtype != HSZ_F32 && dtype != HSZ_F64) || !dims3_of(ndim, h_dims, d3, &n))
+    return HSZ_ERR_INVALID_ARG;
+  if (!valid_block(block)) return HSZ_ERR_UNSUPPORTED;
+  hsz::Layout L = hsz::make_layout(n, block);
+  *h_bytes = L.off_payload + 4 * (uint64_t)L.nb * (uint64_t)((block / 32) * (1 + hsz::kMaxWidth));
+  return HSZ_OK;
+}
+
+int hsz_compress_workspace(int ndim, const int64_t* h_dims, int block, uint64_t* h_bytes) {
+  int64_t d3[3], n;
+  if (!h_bytes || !dims3_of(ndim, h_dims, d3, &n)) return HSZ_ERR_INVALID_ARG;
+  if (!valid_block(block)) return HSZ_ERR_UNSUPPORTED;
+  *h_bytes = hsz::compress_workspace_bytes(hsz::make_layout(n, block));
+  return HSZ_OK;
+}
+
+int hsz_compress(const void* d_x, int dtype, int ndim, const int64_t* h_dims, double eb, int eb_is_rel, int block,
+                 void* d_out, uint64_t cap, void* d_workspace, uint64_t workspace_bytes, void* stream) {
+  int64_t d3[3], n;
+  if (!d_x || !d_out || !d_workspace || (dtype != HSZ_F32 && dtype != HSZ_F64) || !dims3_of(ndim, h_dims, d3, &n))
+    return HSZ_ERR_INVALID_ARG;
+  if (!aligned16(d_x) || !aligned16(d_out) || !aligned16(d_workspace)) return HSZ_ERR_INVALID_ARG;
+  if (!valid_block(block)) return HSZ_ERR_UNSUPPORTED;
+  if (!(eb > 0.0) || eb != eb || eb > 1e300) return HSZ_ERR_EB;
+  hsz::Layout L = hsz::make_layout(n, block);
+  if (workspace_bytes < hsz::compress_workspace_bytes(L)) return HSZ_ERR_CAPACITY;
+  if (cap < L.off_payload) return HSZ_ERR_CAPACITY;
+  hsz::CompressArgs a;
+  a.x = d_x;
+  a.dtype = dtype;
+  a.ndim = ndim;
+  a.dims[0] = d3[0];
+  a.dims[1] = d3[1];
+  a.dims[2] = d3[2];
+  a.eb = eb;
+  a.eb_is_rel = eb_is_rel ? 1 : 0;
+  a.lay = L;
+  a.out = (uint8_t*)d_out;
+  a.cap = cap;
+  a.ws = (uint8_t*)d_workspace;
+  a.ws_bytes = workspace_bytes;
+  hipError_t e = hsz::launch_compress(a, (hipStream_t)stream);
+  return e == hipSuccess ? HSZ_OK : hip_fail(e);
+}
+
+int hsz_read_header(const void* h_bytes, uint64_t len, uint64_t len_stream, hsz_header* o) {
+  if (!h_bytes || !o) return HSZ_ERR_INVALID_ARG;
+  if (len < HSZ_HEADER_BYTES) return HSZ_ERR_BAD_STREAM;
+  const uint8_t* p = (const uint8_t*)h_bytes;
+  if (memcmp(p, "HSZ1", 4) != 0 || rd16(p + 4) != 1) return HSZ_ERR_BAD_STREAM;
+  hsz_header h;
+  memset(&h, 0, sizeof h);
+  h.dtype = p[6];
+  h.ndim = p[7];
+  if (h.dtype != HSZ_F32 && h.dtype != HSZ_F64) return HSZ_ERR_BAD_STREAM;
+  if (h.ndim < 1 || h.ndim > 3) return HSZ_ERR_BAD_STREAM;
+  uint64_t d3[3] = {rd64(p + 8), rd64(p + 16), rd64(p + 24)};
+  for (int k = 0; k < 3 - h.ndim; ++k)
+    if (d3[k] != 1) return HSZ_ERR_BAD_STREAM;
+  for (int k = 0; k < h.ndim; ++k) {
+    if (d3[3 - h.ndim + k] > (uint64_t(1) << 40)) return HSZ_ERR_BAD_STREAM;
+    h.dims[k] = (int64_t)d3[3 - h.ndim + k];
+  }
+  h.n = (int64_t)rd64(p + 32);
+  h.block = (int32_t)rd32(p + 40);
+  h.chunk_blocks = (int32_t)rd32(p + 44);
+  h.eb_abs = rdf64(p + 48);
+  h.quantum = rdf64(p + 56);
+  h.inv_quantum = rdf64(p + 64);
+  h.vmin = rdf64(p + 72);
+  h.vmax = rdf64(p + 80);
+  h.max_abs_q = rd32(p + 88);
+  h.flags = rd32(p + 92);
+  h.nb = (int64_t)rd64(p + 96);
+  h.nchunks = (int64_t)rd64(p + 104);
+  h.off_chunk = rd64(p + 112);
+  h.off_q0 = rd64(p + 120);
+  h.off_width = rd64(p + 128);
+  h.off_payload = rd64(p + 136);
+  h.payload_words = rd64(p + 144);
+  h.total_bytes = rd64(p + 152);
+  if (h.chunk_blocks != hsz::kChunkBlocks || h.block < 1 || h.block > 64) return HSZ_ERR_BAD_STREAM;
+  if (h.inv_quantum != 1.0 / h.quantum) return HSZ_ERR_BAD_STREAM;
+  int64_t dd[3], n;
+  if (!dims3_of(h.ndim, h.dims, dd, &n) || n != h.n) return HSZ_ERR_BAD_STREAM;
+  if (!(h.quantum > 0.0) || h.max_abs_q > (uint32_t)hsz::kQMax) return HSZ_ERR_BAD_STREAM;
+  // layout depends only on n and S
+  const int64_t nb = (h.n + h.block - 1) / h.block;
+  const int64_t nch = (nb + 63) / 64;
+  const uint64_t oc = HSZ_HEADER_BYTES;
+  const uint64_t oq = (oc + 8 * (uint64_t)(nch + 1) + 255) / 256 * 256;
+  const uint64_t ow = (oq + 4 * (uint64_t)nb + 255) / 256 * 256;
+  const uint64_t op = (ow + (uint64_t)nb + 255) / 256 * 256;
+  if (h.nb != nb || h.nchunks != nch || h.off_chunk != oc || h.off_q0 != oq || h.off_width != ow ||
+      h.off_payload != op)
+    return HSZ_ERR_BAD_STREAM;
+  if (h.payload_words > (uint64_t)nb * 64 || h.total_bytes != op + 4 * h.payload_words) return HSZ_ERR_BAD_STREAM;
+  if (h.total_bytes > len_stream) return HSZ_ERR_BAD_STREAM;
+  *o = h;
+  return HSZ_OK;
+}
+
+int hsz_stage_bytes(const hsz_header* h, int stage, uint64_t* h_bytes) {
+  if (!h || !h_bytes) return HSZ_ERR_INVALID_ARG;
+  const uint64_t n = (uint64_t)h->n, nb = (uint64_t)h->nb;
+  switch (stage) {
+    case HSZ_META: *h_bytes = 4 * nb; return HSZ_OK;
+    case HSZ_DELTA: *h_bytes = 4 * n + 4 * nb; return HSZ_OK;
+    case HSZ_QUANT: *h_bytes = 4 * n; return HSZ_OK;
+    case HSZ_FLOAT: *h_bytes = (h->dtype == HSZ_F32 ? 4 : 8) * n; return HSZ_OK;
+  }
+  return HSZ_ERR_INVALID_ARG;
+}
+
+int hsz_decompress_to_stage(const void* d_c, const hsz_header* h, int stage, void* d_out, uint64_t cap,
+                            void* d_workspace, uint64_t workspace_bytes, void* stream) {
+  int rc = check_header(h);
+  if (rc) return rc;
+  if (!d_c || !d_out || !d_workspace || !aligned16(d_c) || !aligned16(d_out) || !aligned16(d_workspace))
+    return HSZ_ERR_INVALID_ARG;
+  if (workspace_bytes < 256) return HSZ_ERR_CAPACITY;
+  uint64_t need = 0;
+  if (hsz_stage_bytes(h, stage, &need)) return HSZ_ERR_INVALID_ARG;
+  if (cap < need) return HSZ_ERR_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = reset_status(d_workspace, s))) return rc;
+  hipError_t e = hsz::launch_decode(view_of(d_c, h), stage, d_out, (int*)d_workspace, s);
+  return e == hipSuccess ? HSZ_OK : hip_fail(e);
+}
+
+int hsz_op_workspace(const hsz_header* h, int op, uint64_t* h_bytes) {
+  if (!h || !h_bytes || op < HSZ_MEAN || op > HSZ_GRADMAG) return HSZ_ERR_INVALID_ARG;
+  *h_bytes = hsz::op_workspace_bytes();
+  return HSZ_OK;
+}
+
+int hsz_op_on_stage(const void* d_stage, const hsz_header* h, int stage, int op, int axis, const hsz_box* h_box,
+                    void* d_result, uint64_t cap, void* d_workspace, uint64_t workspace_bytes, void* stream) {
+  hsz::OpTarget t;
+  int axis3 = 0;
+  int rc = op_common(h, op, axis, h_box, cap, d_result, d_workspace, workspace_bytes, &t, &axis3);
+  if (rc) return rc;
+  if (!d_stage || !aligned16(d_stage)) return HSZ_ERR_INVALID_ARG;
+  if (stage == HSZ_META) return HSZ_ERR_UNSUPPORTED;
+  if (stage < HSZ_DELTA || stage > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
+  if (op >= HSZ_DERIV && stage == HSZ_DELTA) return HSZ_ERR_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = reset_status(d_workspace, s))) return rc;
+  const hsz::StreamView v = view_of(nullptr, h);
+  hipError_t e = (op <= HSZ_VAR)
+                     ? hsz::launch_stats_stage(d_stage, stage, v, op, t, d_result, (uint8_t*)d_workspace, s)
+                     : hsz::launch_grad_stage(d_stage, stage, v, op, axis3, t, d_result, (uint8_t*)d_workspace, s);
+  return e == hipSuccess ? HSZ_OK : hip_fail(e);
+}
+
+int hsz_op_fused(const void* d_c, const hsz_header* h, int via, int op, int axis, const hsz_box* h_box,
+                 void* d_result, uint64_t cap, void* d_workspace, uint64_t workspace_bytes, void* stream) {
+  hsz::OpTarget t;
+  int axis3 = 0;
+  int rc = op_common(h, op, axis, h_box, cap, d_result, d_workspace, workspace_bytes, &t, &axis3);
+  if (rc) return rc;
+  if (!d_c || !aligned16(d_c)) return HSZ_ERR_INVALID_ARG;
+  if (via == HSZ_META) return HSZ_ERR_UNSUPPORTED;
+  if (via < HSZ_DELTA || via > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const hsz::StreamView v = view_of(d_c, h);
+  if (op >= HSZ_DERIV) {
+    if ((rc = reset_status(d_workspace, s))) return rc;
+    hipError_t e = hsz::launch_grad_fused(v, via, op, axis3, t, d_result, (uint8_t*)d_workspace, s);
+    if (e == hipErrorNotSupported) return HSZ_ERR_UNSUPPORTED;
+    return e == hipSuccess ? HSZ_OK : hip_fail(e);
+  }
+  if ((rc = reset_status(d_workspace, s))) return rc;
+  hipError_t e = hsz::launch_stats_fused(v, via, op, t, d_result, (uint8_t*)d_workspace, s);
+  return e == hipSuccess ? HSZ_OK : hip_fail(e);
+}
+
+}  // extern "C"

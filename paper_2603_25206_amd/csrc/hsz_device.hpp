@@ -1,0 +1,200 @@
+// hsz_device.hpp -- device-side building blocks shared by the HIP kernels:
+// the byte-format constants, wave64 primitives (DPP scans, reductions), the
+// status word, and the block decoder used by every stage and operation.
+//
+// Work layout used throughout: one wavefront owns a chunk of 64 consecutive
+// blocks and each lane owns ONE block (lane l <-> block 64*c + l).  A lane
+// walks the S slots of its block serially, so recorrelation (the prefix sum
+// q_i = q_{i-1} + p_i of Alg. 2) is a single add per element, and all
+// per-block metadata (width, q0, payload offset) lives in the lane's own
+// registers.  The chunk's payload words are staged in LDS transposed,
+// word k of lane l at tile[k*64 + l], so that when every lane reads "its"
+// word k (k differs per lane) the 64 addresses fall in 64 distinct banks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hsz {
+
+constexpr int kHeaderBytes = 256;
+constexpr int kSectionAlign = 256;
+constexpr int kChunkBlocks = 64;
+constexpr int kMaxWidth = 30;  // |p| < 2^30 because |q| <= 2^29 - 1
+constexpr int32_t kQMax = 536870911;
+constexpr int kWave = 64;
+
+// Status codes recorded by kernels (same values as the C ABI).
+constexpr int kErrBadStream = -2;
+constexpr int kErrRange = -4;
+constexpr int kErrEb = -5;
+constexpr int kErrNonFinite = -6;
+constexpr int kErrCapacity = -7;
+
+// First error wins; later ones are dropped.  A vector atomic on global
+// memory (never a scalar-cache store).
+__device__ __forceinline__ void record_status(int* status, int code) {
+  if (status) atomicCAS(status, 0, code);
+}
+
+// Payload words of a block of S slots with bit width w: S/32 sign words and
+// S*w/32 magnitude words, nothing when w = 0.
+template <int S>
+__device__ __forceinline__ int block_words(int w) {
+  return w ? (S / 32) * (1 + w) : 0;
+}
+
+// ---- wave64 primitives -------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// DPP controls (GFX9 encoding): row_shr:n = 0x110 + n, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143.  Lanes whose source is outside the row read 'old' = 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dpp(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, 0xf, false);
+}
+
+// Inclusive prefix sum over the 64 lanes of the wave.
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  x += dpp<0x111>(x);
+  x += dpp<0x112>(x);
+  x += dpp<0x114>(x);
+  x += dpp<0x118>(x);
+  x += dpp<0x142, 0xa>(x);  // lane 15 -> row 1, lane 47 -> row 3
+  x += dpp<0x143, 0xc>(x);  // lane 31 -> rows 2 and 3
+  return x;
+}
+
+__device__ __forceinline__ int wave_max(int x) {
+  for (int m = 32; m >= 1; m >>= 1) x = max(x, __shfl_xor(x, m));
+  return x;
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t x) {
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+  return x;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double x) {
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+  return x;
+}
+
+// ---- 128-bit unsigned accumulator (sum of q^2 can pass 2^64) ----------------
+struct U128 {
+  uint64_t lo, hi;
+};
+__device__ __forceinline__ void add_u64(U128& a, uint64_t v) {
+  uint64_t t = a.lo + v;
+  a.hi += (t < v);
+  a.lo = t;
+}
+__device__ __forceinline__ void add_u128(U128& a, U128 b) {
+  uint64_t t = a.lo + b.lo;
+  a.hi += b.hi + (t < b.lo);
+  a.lo = t;
+}
+
+// ---- chunk staging -----------------------------------------------------------
+// Per-lane metadata of one block of a chunk.
+struct LaneBlock {
+  int w;        // bit width (0..30), 0 for lanes past the last block
+  int q0;       // first quantization integer of the block
+  int len;      // valid slots (S for all but the field's last block, 0 if none)
+  int64_t b;    // block index
+};
+
+// Stage chunk c: lane l loads the width and q0 of block 64c+l, the wave
+// scans the payload word counts, checks them against the chunk table, and
+// copies every lane's payload words into its column of the LDS tile
+// (tile rows = kmax+1, row k at tile + k*64).  Returns false (and records a
+// status) when the chunk is inconsistent; the lane's block is then treated
+// as all-zero.
+template <int S>
+__device__ __forceinline__ bool stage_chunk(const uint8_t* __restrict__ width,
+                                           const int32_t* __restrict__ q0s,
+                                           const uint64_t* __restrict__ chunk_off,
+                                           const uint32_t* __restrict__ payload,
+                                           uint64_t payload_words, int64_t n, int64_t nb,
+                                           int64_t c, uint32_t* tile, int kmax, LaneBlock& lb,
+                                           int* status) {
+  const int l = lane_id();
+  lb.b = c * kChunkBlocks + l;
+  const bool valid = lb.b < nb;
+  int w = valid ? (int)width[lb.b] : 0;
+  lb.q0 = valid ? q0s[lb.b] : 0;
+  int64_t first = lb.b * S;
+  lb.len = valid ? (int)((n - first) < S ? (n - first) : S) : 0;
+  int nw = block_words<S>(w);
+  bool bad = (w > kMaxWidth) || (nw > kmax);
+  int incl = wave_incl_scan(bad ? 0 : nw);
+  int woff = incl - (bad ? 0 : nw);
+  int total = __shfl(incl, kWave - 1);
+  uint64_t base = chunk_off[c];
+  uint64_t next = chunk_off[c + 1];
+  int any_bad = __any(bad);
+  if (any_bad || next - base != (uint64_t)total || next > payload_words) {
+    if (l == 0) record_status(status, kErrBadStream);
+    lb.w = 0;
+    return false;
+  }
+  lb.w = w;
+  // copy: each lane its own words, eight at a time so the loads overlap
+  const uint32_t* src = payload + base + woff;
+  int maxnw = wave_max(nw);
+  for (int k0 = 0; k0 < maxnw; k0 += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (k0 + u < nw) ? src[k0 + u] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < nw) tile[(k0 + u) * kWave + l] = v[u];
+  }
+  return true;
+}
+
+// Decode the lane's block from its LDS column.  For every slot j in order
+// it calls sink(j, p_j, q_j) with p the decorrelated integer (stage 2) and
+// q the recorrelated quantization integer (stage 3).  Slot 0 has p = 0 and
+// q = q0.  col = tile + lane (column base); rows hold sign word(s) first,
+// then magnitude words.
+template <int S, class Sink>
+__device__ __forceinline__ void decode_lane_block(const uint32_t* col, int w, int q0, Sink&& sink) {
+  const uint32_t sg0 = w ? col[0] : 0u;
+  const uint32_t sg1 = (S == 64 && w) ? col[kWave] : 0u;
+  const uint32_t* mag = col + (S / 32) * kWave;
+  int q = q0;
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    const uint32_t pos = (uint32_t)j * (uint32_t)w;
+    const uint32_t k = pos >> 5;
+    const uint32_t lo = mag[k * kWave];
+    const uint32_t hi = mag[(k + 1) * kWave];
+    const uint32_t a = __builtin_amdgcn_alignbit(hi, lo, pos & 31u);
+    const uint32_t m = __builtin_amdgcn_ubfe(a, 0u, (uint32_t)w);
+    const int s = (j < 32) ? __builtin_amdgcn_sbfe((int)sg0, (uint32_t)j, 1u)
+                           : __builtin_amdgcn_sbfe((int)sg1, (uint32_t)(j - 32), 1u);
+    const int p = (int)(m ^ (uint32_t)s) - s;
+    q += p;
+    sink(j, p, q);
+  }
+}
+
+// Rows of the staging tile needed for blocks of width <= wmax: sign words,
+// magnitude words, and one spare row read (never used) past the last word.
+template <int S>
+__host__ __device__ constexpr int tile_rows(int wmax) {
+  return (S / 32) * (1 + wmax) + 1;
+}
+
+// Exact (float)(q * quantum) and q * quantum: the dequantization of Alg. 2,
+// always through binary64 so every platform rounds the same way.
+__device__ __forceinline__ double dequant64(int q, double quantum) { return (double)q * quantum; }
+
+}  // namespace hsz

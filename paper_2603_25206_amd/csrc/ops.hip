@@ -1,0 +1,503 @@
+// ops.hip -- analytical operations Q_i on the stages (Sec. V): mean and
+// sample variance (Eq. (var), Sec. V-A), derivatives and gradient magnitude
+// (Eq. (derivatives), Sec. V-B), on materialised stage buffers and fused
+// with decoding straight from the compressed stream.
+//
+// Integer routes (stages 2 and 3) accumulate exact sums of q and q^2
+// (int64 and 128-bit) and scale by the quantum once, in the finalize kernel.
+// The stage-2 mean uses the block-sum identity of Sec. V-A for SZp
+// (sum_i q_i = S_b*q0 + sum_{i>=1} (S_b - i) p_i, generalised to a slot
+// range [a, z] of the block) and never forms q.  The stage-4 routes work on
+// floats in binary64, shifted by the box's first value.
+#include "hsz_device.hpp"
+#include "hsz_launch.hpp"
+
+namespace hsz {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWavesPerGroup = kThreads / kWave;
+constexpr uint64_t kPartialOff = 256;
+
+// Per-workgroup partial: integer sums or binary64 sums.
+struct Partial {
+  int64_t s1;
+  uint64_t s2lo, s2hi;
+  int64_t cnt;
+  double f1, f2;
+  double pad0, pad1;
+};
+
+// A set of contiguous flat ranges ("rows"): row r = iz*nry + iy starts at
+// base + iz*sz + iy*sy and has len elements.
+struct Rows {
+  int64_t nrz, nry, len, base, sz, sy;
+  __host__ __device__ int64_t count() const { return nrz * nry; }
+  __device__ int64_t start(int64_t r) const { return base + (r / nry) * sz + (r % nry) * sy; }
+};
+
+Rows make_rows(const Dims3& d, const Box3& b) {
+  Rows r;
+  const int64_t plane = d.y * d.x;
+  if (b.x0 == 0 && b.x1 == d.x && b.y0 == 0 && b.y1 == d.y) {
+    r.nrz = 1; r.nry = 1; r.len = (b.z1 - b.z0) * plane; r.base = b.z0 * plane; r.sz = 0; r.sy = 0;
+  } else if (b.x0 == 0 && b.x1 == d.x) {
+    r.nrz = b.z1 - b.z0; r.nry = 1; r.len = (b.y1 - b.y0) * d.x; r.base = b.z0 * plane + b.y0 * d.x;
+    r.sz = plane; r.sy = 0;
+  } else {
+    r.nrz = b.z1 - b.z0; r.nry = b.y1 - b.y0; r.len = b.x1 - b.x0;
+    r.base = b.z0 * plane + b.y0 * d.x + b.x0; r.sz = plane; r.sy = d.x;
+  }
+  return r;
+}
+
+// ---- accumulation helpers ------------------------------------------------------
+struct IntAcc {
+  int64_t s1 = 0;
+  U128 s2 = {0, 0};
+  int64_t cnt = 0;
+  __device__ void add(int q, bool want_sq) {
+    s1 += q;
+    if (want_sq) add_u64(s2, (uint64_t)((int64_t)q * (int64_t)q));
+    cnt += 1;
+  }
+};
+
+// Reduce a lane's integer accumulators over the workgroup and store one
+// partial per workgroup.
+__device__ void store_int_partial(IntAcc a, Partial* parts) {
+  __shared__ int64_t ss1[kWavesPerGroup], scnt[kWavesPerGroup];
+  __shared__ uint64_t slo[kWavesPerGroup], shi[kWavesPerGroup];
+  // 128-bit sum across lanes: add the low words as 64-bit with carries
+  // counted through the high words (lane values of s2.lo are < 2^64).
+  int64_t s1 = wave_sum64(a.s1);
+  int64_t cnt = wave_sum64(a.cnt);
+  U128 s2 = a.s2;
+  for (int m = 32; m >= 1; m >>= 1) {
+    U128 o;
+    o.lo = __shfl_xor(s2.lo, m);
+    o.hi = __shfl_xor(s2.hi, m);
+    add_u128(s2, o);
+  }
+  const int wv = threadIdx.x / kWave;
+  if (lane_id() == 0) { ss1[wv] = s1; scnt[wv] = cnt; slo[wv] = s2.lo; shi[wv] = s2.hi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kWavesPerGroup; ++k) {
+      s1 += ss1[k];
+      cnt += scnt[k];
+      add_u128(s2, U128{slo[k], shi[k]});
+    }
+    Partial p{};
+    p.s1 = s1; p.s2lo = s2.lo; p.s2hi = s2.hi; p.cnt = cnt;
+    parts[blockIdx.x] = p;
+  }
+}
+
+__device__ void store_f64_partial(double f1, double f2, int64_t cnt, double K, Partial* parts) {
+  __shared__ double sf1[kWavesPerGroup], sf2[kWavesPerGroup];
+  __shared__ int64_t scnt[kWavesPerGroup];
+  f1 = wave_sum_f64(f1);
+  f2 = wave_sum_f64(f2);
+  cnt = wave_sum64(cnt);
+  const int wv = threadIdx.x / kWave;
+  if (lane_id() == 0) { sf1[wv] = f1; sf2[wv] = f2; scnt[wv] = cnt; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kWavesPerGroup; ++k) { f1 += sf1[k]; f2 += sf2[k]; cnt += scnt[k]; }
+    Partial p{};
+    p.f1 = f1; p.f2 = f2; p.cnt = cnt; p.pad0 = K;
+    parts[blockIdx.x] = p;
+  }
+}
+
+// ---- stats on a stage-3 buffer (q) or stage-4 buffer (floats) -------------------
+constexpr int64_t kSeg = 4096;
+
+template <int OP>
+__global__ void __launch_bounds__(kThreads) k_stats_q(const int32_t* __restrict__ q, Rows rows, Partial* parts) {
+  IntAcc acc;
+  const int64_t segs = (rows.len + kSeg - 1) / kSeg;
+  const int64_t items = rows.count() * segs;
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t r = it / segs, sg = it % segs;
+    const int64_t lo = sg * kSeg, hi = min(rows.len, lo + kSeg);
+    const int32_t* src = q + rows.start(r);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) acc.add(src[i], OP == 2);
+  }
+  store_int_partial(acc, parts);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_stats_f(const T* __restrict__ x, Rows rows, Partial* parts) {
+  const double K = (double)x[rows.base];
+  double f1 = 0.0, f2 = 0.0;
+  int64_t cnt = 0;
+  const int64_t segs = (rows.len + kSeg - 1) / kSeg;
+  const int64_t items = rows.count() * segs;
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t r = it / segs, sg = it % segs;
+    const int64_t lo = sg * kSeg, hi = min(rows.len, lo + kSeg);
+    const T* src = x + rows.start(r);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
+      const double e = (double)src[i] - K;
+      f1 += e;
+      f2 += e * e;
+      cnt += 1;
+    }
+  }
+  store_f64_partial(f1, f2, cnt, K, parts);
+}
+
+// ---- block segments: the part of one block that lies inside one row -------------
+// Items are (row, k-th block touched by the row).  For a row [f, f+len) the
+// blocks are f/S .. (f+len-1)/S; inside block b the row covers slots a..z.
+template <int S>
+struct Segs {
+  Rows rows;
+  int64_t per_row;  // upper bound of blocks touched by one row
+  __host__ __device__ int64_t count() const { return rows.count() * per_row; }
+  // returns false if item k lies past the row's last block
+  __device__ bool get(int64_t item, int64_t& b, int& a, int& z) const {
+    const int64_t r = item / per_row, k = item % per_row;
+    const int64_t f = rows.start(r), e = f + rows.len;  // [f, e)
+    b = f / S + k;
+    if (b > (e - 1) / S) return false;
+    const int64_t bs = b * S;
+    a = (int)(f > bs ? f - bs : 0);
+    z = (int)((e < bs + S ? e : bs + S) - 1 - bs);
+    return true;
+  }
+};
+template <int S>
+Segs<S> make_segs(const Rows& r) {
+  Segs<S> s;
+  s.rows = r;
+  s.per_row = (r.len + S - 2) / S + 1;
+  return s;
+}
+
+// Stage-2 statistics from a p buffer (p[n], q0[nb]).
+template <int S, int OP>
+__global__ void __launch_bounds__(kThreads) k_stats_delta(const int32_t* __restrict__ p,
+                                                         const int32_t* __restrict__ q0s, Segs<S> segs,
+                                                         Partial* parts) {
+  IntAcc acc;
+  const int64_t items = segs.count();
+  for (int64_t it = blockIdx.x * (int64_t)kThreads + threadIdx.x; it < items;
+       it += (int64_t)gridDim.x * kThreads) {
+    int64_t b;
+    int a, z;
+    if (!segs.get(it, b, a, z)) continue;
+    const int32_t* pb = p + b * S;
+    const int q0 = q0s[b];
+    if constexpr (OP == 1) {
+      // sum_{i=a}^{z} q_i = (z-a+1) q0 + sum_{t=1}^{z} (z - max(a,t) + 1) p_t
+      int64_t s = (int64_t)(z - a + 1) * q0;
+      for (int t = 1; t <= z; ++t) s += (int64_t)(z - (a > t ? a : t) + 1) * pb[t];
+      acc.s1 += s;
+      acc.cnt += z - a + 1;
+    } else {
+      int q = q0;
+      for (int t = 0; t <= z; ++t) {
+        if (t > 0) q += pb[t];
+        if (t >= a) acc.add(q, true);
+      }
+    }
+  }
+  store_int_partial(acc, parts);
+}
+
+// ---- fused statistics straight from the compressed stream ------------------------
+// Word offset (within the payload) of block b: the chunk table entry plus the
+// words of the blocks before b in its 64-block chunk, read as 16 words of
+// packed widths.
+template <int S>
+__device__ __forceinline__ uint64_t block_offset(const StreamView& v, int64_t b) {
+  const int64_t c = b / kChunkBlocks;
+  const int cnt = (int)(b - c * kChunkBlocks);
+  const uint32_t* wq = (const uint32_t*)(v.width + c * kChunkBlocks);
+  const int64_t avail = v.nb - c * kChunkBlocks;  // bytes of this chunk inside the section
+  uint32_t sumw = 0, nz = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (4 * k < cnt) {
+      // the width section is padded to 256 bytes, so whole words are readable
+      uint32_t d = (4 * k < avail) ? wq[k] : 0u;
+      const int keep = cnt - 4 * k;
+      if (keep < 4) d &= (1u << (8 * keep)) - 1u;
+      sumw += __builtin_amdgcn_sad_u8(d, 0u, 0u);
+      const uint32_t t = ((d & 0x7f7f7f7fu) + 0x7f7f7f7fu) | d;
+      nz += __builtin_popcount(t & 0x80808080u);
+    }
+  }
+  return v.chunk_off[c] + (uint64_t)(S / 32) * (sumw + nz);
+}
+
+// Stage the lane's own block b into its LDS column (random-access variant of
+// stage_chunk).  Returns the width (0 when the block is invalid or corrupt).
+template <int S>
+__device__ __forceinline__ int stage_lane(const StreamView& v, int64_t b, uint32_t* col, int kmax, int& q0,
+                                          int* status) {
+  int w = (int)v.width[b];
+  q0 = v.q0[b];
+  const int nw = block_words<S>(w);
+  const uint64_t off = block_offset<S>(v, b);
+  if (w > kMaxWidth || nw > kmax || off + (uint64_t)nw > v.payload_words) {
+    record_status(status, kErrBadStream);
+    return 0;
+  }
+  const uint32_t* src = v.payload + off;
+  for (int k0 = 0; k0 < nw; k0 += 8) {
+    uint32_t t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = (k0 + u < nw) ? src[k0 + u] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < nw) col[(k0 + u) * kWave] = t[u];
+  }
+  return w;
+}
+
+// VIA: 2 (decorrelated), 3 (quantized), 4 (floats).  WHOLE: the items are
+// every block in order (chunk-aligned waves use the chunk scan).
+template <int S, int VIA, int OP, typename T, bool WHOLE>
+__global__ void __launch_bounds__(kThreads) k_stats_fused(StreamView v, Segs<S> segs, int kmax, const double* Kp,
+                                                         Partial* parts, int* status) {
+  extern __shared__ uint32_t smem[];
+  const int wv = threadIdx.x / kWave;
+  uint32_t* tile = smem + wv * (kmax + 1) * kWave;
+  const int l = lane_id();
+  IntAcc acc;
+  double f1 = 0.0, f2 = 0.0;
+  int64_t fcnt = 0;
+  const double quantum = v.quantum;
+  const double K = (VIA == 4) ? *Kp : 0.0;
+  const int64_t waves = (int64_t)gridDim.x * kWavesPerGroup;
+  const int64_t items = WHOLE ? v.nchunks * kChunkBlocks : segs.count();
+  for (int64_t base = (blockIdx.x * (int64_t)kWavesPerGroup + wv) * kWave; base < items; base += waves * kWave) {
+    int w, q0, a, z;
+    int64_t b;
+    if constexpr (WHOLE) {
+      LaneBlock lb;
+      stage_chunk<S>(v.width, v.q0, v.chunk_off, v.payload, v.payload_words, v.n, v.nb, base / kWave, tile,
+                     kmax, lb, status);
+      w = lb.w; q0 = lb.q0; a = 0; z = lb.len - 1; b = lb.b;
+    } else {
+      const int64_t it = base + l;
+      bool ok = it < items && segs.get(it, b, a, z);
+      w = 0; q0 = 0;
+      if (ok) w = stage_lane<S>(v, b, tile + l, kmax, q0, status);
+      else z = -1;
+    }
+    if (z < 0) continue;
+    if constexpr (VIA == 2 && OP == 1) {
+      // weighted block sum, no recorrelation
+      int64_t s = (int64_t)(z - a + 1) * q0;
+      decode_lane_block<S>(tile + l, w, q0, [&](int j, int p, int) {
+        if (j >= 1 && j <= z) s += (int64_t)(z - (a > j ? a : j) + 1) * p;
+      });
+      acc.s1 += s;
+      acc.cnt += z - a + 1;
+    } else if constexpr (VIA == 4) {
+      decode_lane_block<S>(tile + l, w, q0, [&](int j, int, int q) {
+        if (j >= a && j <= z) {
+          const double e = (double)(T)dequant64(q, quantum) - K;
+          f1 += e;
+          f2 += e * e;
+          fcnt += 1;
+        }
+      });
+    } else {
+      decode_lane_block<S>(tile + l, w, q0, [&](int j, int, int q) {
+        if (j >= a && j <= z) acc.add(q, OP == 2);
+      });
+    }
+  }
+  if constexpr (VIA == 4) store_f64_partial(f1, f2, fcnt, K, parts);
+  else store_int_partial(acc, parts);
+}
+
+// ---- finalize: partials -> hsz_stats ------------------------------------------------
+struct StatsOut {
+  int64_t n, s1;
+  uint64_t s2lo;
+  int64_t s2hi;
+  double mean, var;
+};
+
+__device__ double u128_to_f64(unsigned __int128 v) {
+  return (double)(uint64_t)(v >> 64) * 18446744073709551616.0 + (double)(uint64_t)v;
+}
+
+__global__ void k_finalize(const Partial* parts, int groups, int op, int fl, double quantum, StatsOut* out) {
+  if (threadIdx.x != 0) return;
+  StatsOut r{};
+  if (!fl) {
+    int64_t s1 = 0, cnt = 0;
+    unsigned __int128 s2 = 0;
+    for (int g = 0; g < groups; ++g) {
+      s1 += parts[g].s1;
+      cnt += parts[g].cnt;
+      s2 += ((unsigned __int128)parts[g].s2hi << 64) | parts[g].s2lo;
+    }
+    r.n = cnt;
+    r.s1 = s1;
+    r.mean = (double)s1 * quantum / (double)cnt;
+    if (op == 2) {
+      r.s2lo = (uint64_t)s2;
+      r.s2hi = (int64_t)(uint64_t)(s2 >> 64);
+      // n*s2 - s1^2 >= 0, exact in 128 bits for n < 2^34 and |q| < 2^29
+      const unsigned __int128 a = (unsigned __int128)(uint64_t)cnt * s2;
+      const uint64_t m = (uint64_t)(s1 < 0 ? -s1 : s1);
+      const unsigned __int128 b = (unsigned __int128)m * m;
+      const double num = u128_to_f64(a - b);
+      r.var = cnt > 1 ? num / ((double)cnt * (double)(cnt - 1)) * (quantum * quantum) : __builtin_nan("");
+    } else {
+      r.var = __builtin_nan("");
+    }
+  } else {
+    double f1 = 0.0, f2 = 0.0;
+    int64_t cnt = 0;
+    for (int g = 0; g < groups; ++g) {
+      f1 += parts[g].f1;
+      f2 += parts[g].f2;
+      cnt += parts[g].cnt;
+    }
+    const double K = parts[0].pad0;
+    r.n = cnt;
+    r.mean = K + f1 / (double)cnt;
+    r.var = (op == 2 && cnt > 1) ? (f2 - f1 * f1 / (double)cnt) / (double)(cnt - 1) : __builtin_nan("");
+  }
+  *out = r;
+}
+
+int grid_for(int64_t work_items, int per_group) {
+  int64_t g = (work_items + per_group - 1) / per_group;
+  if (g < 1) g = 1;
+  return (int)(g < kOpWorkgroups ? g : kOpWorkgroups);
+}
+
+int kmax_for(const StreamView& v) {
+  int wmax = 32 - __builtin_clz(2u * v.max_abs_q | 1u);
+  wmax = wmax < 1 ? 1 : (wmax > kMaxWidth ? kMaxWidth : wmax);
+  return (v.block / 32) * (1 + wmax);
+}
+
+// One wave: decode the value at flat index f (the shift of the binary64
+// float-route sums) into *K.
+template <int S, typename T>
+__global__ void k_first_value(StreamView v, int64_t f, int kmax, double* K, int* status) {
+  extern __shared__ uint32_t smem[];
+  const int64_t b = f / S;
+  const int slot = (int)(f - b * S);
+  int q0 = 0;
+  const int w = lane_id() == 0 ? stage_lane<S>(v, b, smem, kmax, q0, status) : 0;
+  if (lane_id() != 0) return;
+  int qv = 0;
+  decode_lane_block<S>(smem, w, q0, [&](int j, int, int q) {
+    if (j == slot) qv = q;
+  });
+  *K = (double)(T)dequant64(qv, v.quantum);
+}
+
+template <int S, int VIA, int OP, typename T>
+hipError_t run_fused_stats(const StreamView& v, const Rows& rows, bool whole, double* K, Partial* parts, int& grid,
+                           int* status, hipStream_t s) {
+  const int kmax = kmax_for(v);
+  const size_t lds = (size_t)kWavesPerGroup * (kmax + 1) * kWave * sizeof(uint32_t);
+  Segs<S> segs = make_segs<S>(rows);
+  if (VIA == 4)
+    hipLaunchKernelGGL((k_first_value<S, T>), dim3(1), dim3(kWave), (kmax + 1) * kWave * sizeof(uint32_t), s, v,
+                       rows.base, kmax, K, status);
+  const int64_t items = whole ? v.nchunks * kChunkBlocks : segs.count();
+  grid = grid_for(items, kThreads);
+  if (whole)
+    hipLaunchKernelGGL((k_stats_fused<S, VIA, OP, T, true>), dim3(grid), dim3(kThreads), lds, s, v, segs, kmax, K,
+                       parts, status);
+  else
+    hipLaunchKernelGGL((k_stats_fused<S, VIA, OP, T, false>), dim3(grid), dim3(kThreads), lds, s, v, segs, kmax,
+                       K, parts, status);
+  return hipGetLastError();
+}
+
+template <int S, int OP>
+hipError_t fused_by_via(const StreamView& v, int via, const Rows& rows, bool whole, double* K, Partial* parts,
+                        int& grid, int* status, hipStream_t s) {
+  switch (via) {
+    case 2: return run_fused_stats<S, 2, OP, float>(v, rows, whole, K, parts, grid, status, s);
+    case 3: return run_fused_stats<S, 3, OP, float>(v, rows, whole, K, parts, grid, status, s);
+    case 4:
+      return v.dtype == 1 ? run_fused_stats<S, 4, OP, float>(v, rows, whole, K, parts, grid, status, s)
+                          : run_fused_stats<S, 4, OP, double>(v, rows, whole, K, parts, grid, status, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+uint64_t op_workspace_bytes() { return kPartialOff + sizeof(Partial) * (uint64_t)kOpWorkgroups; }
+
+hipError_t launch_stats_stage(const void* buf, int stage, const StreamView& v, int op, const OpTarget& t,
+                              void* result, uint8_t* ws, hipStream_t s) {
+  Partial* parts = (Partial*)(ws + kPartialOff);
+  const Rows rows = make_rows(t.d, t.box);
+  int grid = 1;
+  if (stage == 3) {
+    grid = grid_for(rows.count() * ((rows.len + kSeg - 1) / kSeg), 1);
+    if (op == 1) hipLaunchKernelGGL(k_stats_q<1>, dim3(grid), dim3(kThreads), 0, s, (const int32_t*)buf, rows, parts);
+    else hipLaunchKernelGGL(k_stats_q<2>, dim3(grid), dim3(kThreads), 0, s, (const int32_t*)buf, rows, parts);
+  } else if (stage == 4) {
+    grid = grid_for(rows.count() * ((rows.len + kSeg - 1) / kSeg), 1);
+    if (v.dtype == 1)
+      hipLaunchKernelGGL(k_stats_f<float>, dim3(grid), dim3(kThreads), 0, s, (const float*)buf, rows, parts);
+    else
+      hipLaunchKernelGGL(k_stats_f<double>, dim3(grid), dim3(kThreads), 0, s, (const double*)buf, rows, parts);
+  } else if (stage == 2) {
+    const int32_t* p = (const int32_t*)buf;
+    const int32_t* q0 = p + v.n;
+    if (v.block == 32) {
+      Segs<32> sg = make_segs<32>(rows);
+      grid = grid_for(sg.count(), kThreads);
+      if (op == 1) hipLaunchKernelGGL((k_stats_delta<32, 1>), dim3(grid), dim3(kThreads), 0, s, p, q0, sg, parts);
+      else hipLaunchKernelGGL((k_stats_delta<32, 2>), dim3(grid), dim3(kThreads), 0, s, p, q0, sg, parts);
+    } else {
+      Segs<64> sg = make_segs<64>(rows);
+      grid = grid_for(sg.count(), kThreads);
+      if (op == 1) hipLaunchKernelGGL((k_stats_delta<64, 1>), dim3(grid), dim3(kThreads), 0, s, p, q0, sg, parts);
+      else hipLaunchKernelGGL((k_stats_delta<64, 2>), dim3(grid), dim3(kThreads), 0, s, p, q0, sg, parts);
+    }
+  } else {
+    return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // stage 4 sums are shifted by the box's first value; every partial carries it
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, parts, grid, op, stage == 4 ? 1 : 0, v.quantum,
+                     (StatsOut*)result);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_fused(const StreamView& v, int via, int op, const OpTarget& t, void* result, uint8_t* ws,
+                              hipStream_t s) {
+  Partial* parts = (Partial*)(ws + kPartialOff);
+  int* status = (int*)ws;
+  const Rows rows = make_rows(t.d, t.box);
+  const bool whole = rows.count() == 1 && rows.base == 0 && rows.len == v.n;
+  double* K = (double*)(ws + 8);
+  int grid = 1;
+  hipError_t e;
+  if (v.block == 32)
+    e = op == 1 ? fused_by_via<32, 1>(v, via, rows, whole, K, parts, grid, status, s)
+                : fused_by_via<32, 2>(v, via, rows, whole, K, parts, grid, status, s);
+  else
+    e = op == 1 ? fused_by_via<64, 1>(v, via, rows, whole, K, parts, grid, status, s)
+                : fused_by_via<64, 2>(v, via, rows, whole, K, parts, grid, status, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, parts, grid, op, via == 4 ? 1 : 0, v.quantum,
+                     (StatsOut*)result);
+  return hipGetLastError();
+}
+
+}  // namespace hsz

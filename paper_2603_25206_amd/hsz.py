@@ -1,0 +1,371 @@
+"""Python binding of libhsz (include/hsz.h) -- argument marshalling only.
+
+Every step of compression, decompression and the operations runs in the HIP
+kernels of libhsz.so; this module allocates device buffers with torch,
+passes raw pointers and the current torch stream through ctypes, and turns
+results back into tensors.  There is no fallback: if the library is not
+built, or no GPU is visible, the calls raise.
+
+Names follow the C ABI: compress, read_header, decompress_to_stage,
+op_on_stage, op_fused (plus helpers).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import struct
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhsz.so")
+
+OK = 0
+ERR_INVALID_ARG, ERR_BAD_STREAM, ERR_UNSUPPORTED, ERR_RANGE, ERR_EB, ERR_NONFINITE, ERR_CAPACITY, ERR_HIP = (
+    -1, -2, -3, -4, -5, -6, -7, -8)
+F32, F64 = 1, 2
+META, DELTA, QUANT, FLOAT = 1, 2, 3, 4
+MEAN, VAR, DERIV, GRADMAG = 1, 2, 3, 4
+HEADER_BYTES = 256
+
+_OPS = {"mean": MEAN, "var": VAR, "deriv": DERIV, "gradmag": GRADMAG}
+_STAGES = {"meta": META, "delta": DELTA, "quant": QUANT, "float": FLOAT}
+
+
+class HszError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        msg = f"{what}: {code}"
+        if _lib is not None:
+            msg += f" ({_lib.hsz_strerror(code).decode()})"
+        if detail:
+            msg += f" {detail}"
+        super().__init__(msg)
+        self.code = code
+
+
+class Header(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int32), ("ndim", ctypes.c_int32), ("dims", ctypes.c_int64 * 3),
+        ("n", ctypes.c_int64), ("block", ctypes.c_int32), ("chunk_blocks", ctypes.c_int32),
+        ("eb_abs", ctypes.c_double), ("quantum", ctypes.c_double), ("inv_quantum", ctypes.c_double),
+        ("vmin", ctypes.c_double), ("vmax", ctypes.c_double), ("max_abs_q", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32), ("nb", ctypes.c_int64), ("nchunks", ctypes.c_int64),
+        ("off_chunk", ctypes.c_uint64), ("off_q0", ctypes.c_uint64), ("off_width", ctypes.c_uint64),
+        ("off_payload", ctypes.c_uint64), ("payload_words", ctypes.c_uint64),
+        ("total_bytes", ctypes.c_uint64),
+    ]
+
+    @property
+    def shape(self):
+        return tuple(int(self.dims[k]) for k in range(self.ndim))
+
+    @property
+    def torch_dtype(self):
+        return torch.float32 if self.dtype == F32 else torch.float64
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int64 * 3), ("hi", ctypes.c_int64 * 3)]
+
+
+EXPORTS = (
+    "hsz_strerror", "hsz_version", "hsz_last_hip_error", "hsz_read_status", "hsz_compress_bound",
+    "hsz_compress_workspace", "hsz_compress", "hsz_read_header", "hsz_stage_bytes",
+    "hsz_decompress_to_stage", "hsz_op_workspace", "hsz_op_on_stage", "hsz_op_fused",
+)
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libhsz.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libhsz.so is not built ({path}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P, i32, u64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_double
+    pi64, pu64 = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64)
+    sig = {
+        "hsz_strerror": (ctypes.c_char_p, [i32]),
+        "hsz_version": (i32, []),
+        "hsz_last_hip_error": (i32, []),
+        "hsz_read_status": (i32, [P, P, ctypes.POINTER(ctypes.c_int)]),
+        "hsz_compress_bound": (i32, [i32, i32, pi64, i32, pu64]),
+        "hsz_compress_workspace": (i32, [i32, pi64, i32, pu64]),
+        "hsz_compress": (i32, [P, i32, i32, pi64, dbl, i32, i32, P, u64, P, u64, P]),
+        "hsz_read_header": (i32, [P, u64, u64, ctypes.POINTER(Header)]),
+        "hsz_stage_bytes": (i32, [ctypes.POINTER(Header), i32, pu64]),
+        "hsz_decompress_to_stage": (i32, [P, ctypes.POINTER(Header), i32, P, u64, P, u64, P]),
+        "hsz_op_workspace": (i32, [ctypes.POINTER(Header), i32, pu64]),
+        "hsz_op_on_stage": (i32, [P, ctypes.POINTER(Header), i32, i32, i32, ctypes.POINTER(Box), P, u64, P,
+                                  u64, P]),
+        "hsz_op_fused": (i32, [P, ctypes.POINTER(Header), i32, i32, i32, ctypes.POINTER(Box), P, u64, P, u64,
+                               P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        detail = ""
+        if rc == ERR_HIP:
+            detail = f"hipError {_lib.hsz_last_hip_error()}"
+        raise HszError(rc, what, detail)
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dims(shape):
+    arr = (ctypes.c_int64 * 3)(*([int(v) for v in shape] + [1] * (3 - len(shape))))
+    return arr
+
+
+def _box(box, ndim):
+    if box is None:
+        return None
+    lo, hi = box
+    b = Box()
+    for k in range(ndim):
+        b.lo[k] = int(lo[k])
+        b.hi[k] = int(hi[k])
+    return ctypes.byref(b)
+
+
+def _empty_bytes(nbytes: int, device) -> torch.Tensor:
+    # rounded up to 16 bytes so every buffer is 16-byte aligned and whole
+    return torch.empty(((int(nbytes) + 15) // 16) * 16, dtype=torch.uint8, device=device)
+
+
+_ws_cache: dict = {}
+
+
+def workspace(nbytes: int, device=None, key: str = "op") -> torch.Tensor:
+    """A cached device workspace of at least nbytes (per device and key)."""
+    dev = torch.device(device if device is not None else "cuda")
+    k = (str(dev), key)
+    t = _ws_cache.get(k)
+    if t is None or t.numel() < nbytes:
+        t = _empty_bytes(max(int(nbytes), 256), dev)
+        _ws_cache[k] = t
+    return t
+
+
+def read_status(ws: torch.Tensor, stream=None) -> int:
+    lib = load()
+    st = ctypes.c_int(0)
+    _check(lib.hsz_read_status(ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(_stream(stream)),
+                               ctypes.byref(st)), "read_status")
+    return st.value
+
+
+@dataclass
+class Compressed:
+    """A compressed stream resident in device memory, with its parsed header."""
+    data: torch.Tensor  # uint8, at least header.total_bytes long
+    header: Header
+
+    @property
+    def nbytes(self) -> int:
+        return int(self.header.total_bytes)
+
+    @property
+    def ratio(self) -> float:
+        esz = 4 if self.header.dtype == F32 else 8
+        return self.header.n * esz / self.nbytes
+
+    def to_bytes(self):
+        return self.data[: self.nbytes].cpu().numpy()
+
+
+def read_header(buf, len_stream: int | None = None) -> Header:
+    """Parse a header from host bytes (numpy/bytes) or a device uint8 tensor."""
+    lib = load()
+    if isinstance(buf, torch.Tensor):
+        if len_stream is None:
+            len_stream = buf.numel()
+        host = buf[:HEADER_BYTES].cpu().numpy().tobytes()
+    else:
+        host = bytes(memoryview(buf)[:HEADER_BYTES])
+        if len_stream is None:
+            len_stream = len(memoryview(buf))
+    h = Header()
+    cbuf = ctypes.create_string_buffer(host, len(host))
+    _check(lib.hsz_read_header(cbuf, len(host), int(len_stream), ctypes.byref(h)), "read_header")
+    return h
+
+
+def compress_bound(shape, dtype: int, block: int) -> int:
+    lib = load()
+    out = ctypes.c_uint64()
+    _check(lib.hsz_compress_bound(dtype, len(shape), _dims(shape), block, ctypes.byref(out)), "compress_bound")
+    return out.value
+
+
+def compress(x: torch.Tensor, eb: float, rel: bool = True, block: int = 32, stream=None,
+             out: torch.Tensor | None = None, check: bool = True) -> Compressed:
+    """c = C(x, eb) on the GPU.  x: contiguous float32/float64 CUDA tensor."""
+    lib = load()
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous GPU tensor")
+    dt = F32 if x.dtype == torch.float32 else F64 if x.dtype == torch.float64 else None
+    if dt is None:
+        raise TypeError("x must be float32 or float64")
+    shape = tuple(x.shape)
+    dims = _dims(shape)
+    cap = compress_bound(shape, dt, block)
+    if out is None:
+        out = _empty_bytes(cap, x.device)
+    wsb = ctypes.c_uint64()
+    _check(lib.hsz_compress_workspace(len(shape), dims, block, ctypes.byref(wsb)), "compress_workspace")
+    ws = workspace(wsb.value, x.device, key="compress")
+    s = _stream(stream)
+    _check(lib.hsz_compress(ctypes.c_void_p(x.data_ptr()), dt, len(shape), dims, float(eb), int(rel), block,
+                            ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.c_void_p(ws.data_ptr()),
+                            ws.numel(), ctypes.c_void_p(s)), "compress")
+    if not check:
+        return Compressed(out, Header())
+    st = read_status(ws, stream)
+    if st != OK:
+        raise HszError(st, "compress")
+    return Compressed(out, read_header(out))
+
+
+def stage_bytes(h: Header, stage: int) -> int:
+    lib = load()
+    out = ctypes.c_uint64()
+    _check(lib.hsz_stage_bytes(ctypes.byref(h), stage, ctypes.byref(out)), "stage_bytes")
+    return out.value
+
+
+def decompress_to_stage(c: Compressed, stage, stream=None, out: torch.Tensor | None = None,
+                        check: bool = False):
+    """Alg. 2 to stage 1..4.  Returns (for stage 2) (p, q0), else one tensor
+    shaped like the field (stage 1: q0 of shape [nb])."""
+    lib = load()
+    stage = _STAGES.get(stage, stage)
+    h = c.header
+    nbytes = stage_bytes(h, stage)
+    if out is None:
+        out = _empty_bytes(nbytes, c.data.device)
+    ws = workspace(256, c.data.device, key="decode")
+    _check(lib.hsz_decompress_to_stage(ctypes.c_void_p(c.data.data_ptr()), ctypes.byref(h), stage,
+                                       ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                       ctypes.c_void_p(_stream(stream))), "decompress_to_stage")
+    if check:
+        st = read_status(ws, stream)
+        if st != OK:
+            raise HszError(st, "decompress_to_stage")
+    return stage_view(out, h, stage)
+
+
+def stage_view(buf: torch.Tensor, h: Header, stage: int):
+    n, nb = int(h.n), int(h.nb)
+    if stage == META:
+        return buf[: 4 * nb].view(torch.int32)
+    if stage == DELTA:
+        v = buf[: 4 * (n + nb)].view(torch.int32)
+        return v[:n].view(h.shape), v[n:]
+    if stage == QUANT:
+        return buf[: 4 * n].view(torch.int32).view(h.shape)
+    esz = 4 if h.dtype == F32 else 8
+    return buf[: esz * n].view(h.torch_dtype).view(h.shape)
+
+
+def _stats_from_raw(raw: bytes) -> dict:
+    n, s1, s2lo, s2hi, mean, var = struct.unpack("<qqQqdd", raw)
+    return {"n": n, "s1": s1, "s2": (s2hi << 64) + s2lo, "mean": mean, "var": var}
+
+
+def _result_buffer(h: Header, op: int, box, device):
+    if op in (MEAN, VAR):
+        return _empty_bytes(48, device), None
+    if box is None:
+        shape = h.shape
+    else:
+        shape = tuple(int(hi) - int(lo) for lo, hi in zip(*box))
+    esz = 4 if h.dtype == F32 else 8
+    vol = 1
+    for s in shape:
+        vol *= s
+    return _empty_bytes(esz * vol, device), shape
+
+
+def _finish(buf, shape, h, op, ws, stream, check):
+    if check:
+        st = read_status(ws, stream)
+        if st != OK:
+            raise HszError(st, "operation")
+    if op in (MEAN, VAR):
+        return _stats_from_raw(buf[:48].cpu().numpy().tobytes())
+    vol = 1
+    for s in shape:
+        vol *= s
+    esz = 4 if h.dtype == F32 else 8
+    return buf[: esz * vol].view(h.torch_dtype).view(shape)
+
+
+def op_on_stage(stage_buf, h: Header, stage, op, axis: int = 0, box=None, stream=None, check: bool = True,
+                out: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+    """Operation on a materialised stage buffer (the tensor(s) returned by
+    decompress_to_stage).  Stats return a dict; derivatives a tensor."""
+    lib = load()
+    stage = _STAGES.get(stage, stage)
+    op = _OPS.get(op, op)
+    base = stage_buf[0] if isinstance(stage_buf, tuple) else stage_buf
+    dev = base.device
+    buf, shape = _result_buffer(h, op, box, dev) if out is None else (out, None)
+    if shape is None and op not in (MEAN, VAR):
+        shape = h.shape if box is None else tuple(int(hi) - int(lo) for lo, hi in zip(*box))
+    if ws is None:
+        wsb = ctypes.c_uint64()
+        _check(lib.hsz_op_workspace(ctypes.byref(h), op, ctypes.byref(wsb)), "op_workspace")
+        ws = workspace(wsb.value, dev)
+    _check(lib.hsz_op_on_stage(ctypes.c_void_p(base.data_ptr()), ctypes.byref(h), stage, op, axis,
+                               _box(box, h.ndim), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream(stream))),
+           "op_on_stage")
+    return _finish(buf, shape, h, op, ws, stream, check)
+
+
+def op_fused(c: Compressed, via, op, axis: int = 0, box=None, stream=None, check: bool = True,
+             out: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+    """Operation computed straight from the compressed stream through stage via."""
+    lib = load()
+    via = _STAGES.get(via, via)
+    op = _OPS.get(op, op)
+    h = c.header
+    dev = c.data.device
+    buf, shape = _result_buffer(h, op, box, dev) if out is None else (out, None)
+    if shape is None and op not in (MEAN, VAR):
+        shape = h.shape if box is None else tuple(int(hi) - int(lo) for lo, hi in zip(*box))
+    if ws is None:
+        wsb = ctypes.c_uint64()
+        _check(lib.hsz_op_workspace(ctypes.byref(h), op, ctypes.byref(wsb)), "op_workspace")
+        ws = workspace(wsb.value, dev)
+    _check(lib.hsz_op_fused(ctypes.c_void_p(c.data.data_ptr()), ctypes.byref(h), via, op, axis,
+                            _box(box, h.ndim), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream(stream))),
+           "op_fused")
+    return _finish(buf, shape, h, op, ws, stream, check)
+
+
+def from_bytes(data, device="cuda") -> Compressed:
+    """Upload a compressed stream held in host memory."""
+    import numpy as np
+    arr = np.frombuffer(bytes(memoryview(data)), dtype=np.uint8)
+    h = read_header(arr)
+    t = _empty_bytes(arr.size, device)
+    t[: arr.size].copy_(torch.from_numpy(arr.copy()))
+    return Compressed(t, h)

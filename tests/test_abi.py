@@ -1,0 +1,122 @@
+"""The C ABI library loads, exports every entry point include/hsz.h declares,
+and its host-only logic (header parsing, sizes, argument validation) agrees
+with the oracle.  No GPU: nothing here launches a kernel."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hsz.h")
+
+torch = pytest.importorskip("torch")
+from paper_2603_25206_amd import hsz  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return hsz.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hsz_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(hsz.EXPORTS) == names
+
+
+def test_strerror_and_version(lib):
+    assert lib.hsz_version() >= 100
+    for code in range(0, -9, -1):
+        assert lib.hsz_strerror(code)
+    assert lib.hsz_strerror(-99) == b"unknown error"
+
+
+@pytest.mark.parametrize("shape,dtype,rel,block", [
+    ((10, 20, 30), np.float32, 1e-3, 32),
+    ((7, 1001), np.float64, 1e-6, 64),
+    ((100003,), np.float32, 1e-2, 32),
+])
+def test_read_header_matches_oracle(shape, dtype, rel, block):
+    x = np.random.default_rng(2).normal(size=shape).astype(dtype)
+    buf = oracle.compress(x, rel, rel=True, block=block)
+    oh = oracle.read_header(buf)
+    h = hsz.read_header(buf)
+    assert h.shape == oh.dims and h.n == oh.n and h.block == oh.block
+    assert (h.eb_abs, h.quantum, h.inv_quantum, h.vmin, h.vmax) == (
+        oh.eb_abs, oh.quantum, oh.inv_quantum, oh.vmin, oh.vmax)
+    assert (h.nb, h.nchunks, h.off_chunk, h.off_q0, h.off_width, h.off_payload) == (
+        oh.nb, oh.nchunks, oh.off_chunk, oh.off_q0, oh.off_width, oh.off_payload)
+    assert (h.payload_words, h.total_bytes, h.max_abs_q) == (oh.payload_words, oh.total_bytes, oh.max_abs_q)
+    assert hsz.compress_bound(shape, 1 if dtype == np.float32 else 2, block) == oracle.compress_bound(x.size, block)
+    for stage, nbytes in ((1, 4 * h.nb), (2, 4 * (h.n + h.nb)), (3, 4 * h.n), (4, x.itemsize * h.n)):
+        assert hsz.stage_bytes(h, stage) == nbytes
+
+
+def test_read_header_rejects_corruption():
+    x = np.linspace(0, 1, 5000).astype(np.float32)
+    buf = oracle.compress(x, 1e-3)
+    for pos, val in ((0, ord("X")), (4, 9), (6, 7), (7, 5), (40, 16), (113, 0), (91, 0x7f)):
+        bad = buf.copy()
+        bad[pos] = val
+        with pytest.raises(hsz.HszError) as e:
+            hsz.read_header(bad)
+        assert e.value.code == hsz.ERR_BAD_STREAM
+    with pytest.raises(hsz.HszError):
+        hsz.read_header(buf, len_stream=buf.size - 1)  # truncated stream
+    with pytest.raises(hsz.HszError):
+        hsz.read_header(buf[:100])
+
+
+def test_argument_validation_before_any_launch(lib):
+    """Paths that must return on the host, before any device pointer is
+    touched (fake aligned addresses are never dereferenced here)."""
+    dims = (ctypes.c_int64 * 3)(64, 64, 64)
+    fake = ctypes.c_void_p(0x10000)
+    assert lib.hsz_compress(None, 1, 3, dims, 1e-3, 1, 32, fake, 1 << 30, fake, 1 << 20, None) == hsz.ERR_INVALID_ARG
+    assert lib.hsz_compress(fake, 1, 3, dims, 1e-3, 1, 16, fake, 1 << 30, fake, 1 << 20, None) == hsz.ERR_UNSUPPORTED
+    assert lib.hsz_compress(fake, 1, 3, dims, 0.0, 1, 32, fake, 1 << 30, fake, 1 << 20, None) == hsz.ERR_EB
+    assert lib.hsz_compress(fake, 1, 3, dims, 1e-3, 1, 32, fake, 1 << 30, fake, 16, None) == hsz.ERR_CAPACITY
+    assert lib.hsz_compress(fake, 1, 3, dims, 1e-3, 1, 32, fake, 64, fake, 1 << 20, None) == hsz.ERR_CAPACITY
+    assert lib.hsz_compress(ctypes.c_void_p(0x10004), 1, 3, dims, 1e-3, 1, 32, fake, 1 << 30, fake, 1 << 20,
+                            None) == hsz.ERR_INVALID_ARG  # misaligned
+    x = np.linspace(0, 1, 5000).astype(np.float32)
+    h = hsz.read_header(oracle.compress(x, 1e-3))
+    ws = ctypes.c_uint64()
+    assert lib.hsz_op_workspace(ctypes.byref(h), hsz.MEAN, ctypes.byref(ws)) == 0 and ws.value >= 256
+    args = (ctypes.byref(h),)
+    # stage 1 supports no operation (Table II lists stages 2-4 for SZp)
+    assert lib.hsz_op_on_stage(fake, *args, hsz.META, hsz.MEAN, 0, None, fake, 48, fake, ws.value, None) == \
+        hsz.ERR_UNSUPPORTED
+    assert lib.hsz_op_fused(fake, *args, hsz.META, hsz.VAR, 0, None, fake, 48, fake, ws.value, None) == \
+        hsz.ERR_UNSUPPORTED
+    # derivatives are not defined on the 1D compressor's decorrelated stage
+    assert lib.hsz_op_on_stage(fake, *args, hsz.DELTA, hsz.GRADMAG, 0, None, fake, 4 * 5000, fake, ws.value,
+                               None) == hsz.ERR_UNSUPPORTED
+    assert lib.hsz_op_on_stage(fake, *args, hsz.QUANT, hsz.DERIV, 1, None, fake, 4 * 5000, fake, ws.value,
+                               None) == hsz.ERR_INVALID_ARG  # axis out of range for a 1D field
+    assert lib.hsz_op_on_stage(fake, *args, hsz.QUANT, hsz.GRADMAG, 0, None, fake, 16, fake, ws.value,
+                               None) == hsz.ERR_CAPACITY
+    assert lib.hsz_op_on_stage(fake, *args, hsz.QUANT, 9, 0, None, fake, 48, fake, ws.value, None) == \
+        hsz.ERR_INVALID_ARG
+    box = hsz.Box()
+    box.lo[0], box.hi[0] = 10, 10  # empty
+    assert lib.hsz_op_on_stage(fake, *args, hsz.QUANT, hsz.MEAN, 0, ctypes.byref(box), fake, 48, fake, ws.value,
+                               None) == hsz.ERR_INVALID_ARG
+    assert lib.hsz_op_on_stage(fake, *args, hsz.QUANT, hsz.MEAN, 0, None, fake, 48, fake, 8, None) == \
+        hsz.ERR_CAPACITY
+    assert lib.hsz_decompress_to_stage(fake, *args, 5, fake, 1 << 20, fake, 256, None) == hsz.ERR_INVALID_ARG
+    assert lib.hsz_decompress_to_stage(fake, *args, hsz.QUANT, fake, 16, fake, 256, None) == hsz.ERR_CAPACITY
