@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""Benchmark: homomorphic analytics on a compressed 512^3 binary32 field on one
+MI355X, against full decompression + the same operations on the same GPU.
+
+Workload (the large-field configuration): a 512^3 binary32 field (64
+Gaussian bumps, sigma 8..64 cells, times a log-normal(0, 0.1) texture,
+seed 0), compressed on the GPU with a value-range relative bound (default
+1e-4) and blocks of S = 32.  A timed STEP is one pass of the analytics over
+one compressed copy of the field, straight from the compressed bytes:
+  mean      fused decode + block sums through the decorrelated stage (D_p)
+  variance  fused decode + exact sum q, sum q^2 through D_q
+  gradient  magnitude of the central-difference gradient, through D_q
+The reported value is GB/s of ORIGINAL data (n * 4 bytes per step / step
+time).  Inputs are resident in HBM before timing; the step rotates over
+several distinct copies of the compressed stream (together well above the
+256 MB last-level cache) so repeated steps cannot be served from cache.
+
+Also measured on the same GPU and reported beside it: the full-decompress
+baseline (decode to floats, then the same three operations on the floats),
+every stage of partial decompression, every operation on every
+materialised stage, compression, and the CPU checker (oracle) timed on a
+bounded slab of the same field.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--eb", type=float, default=1e-4)
+    ap.add_argument("--block", type=int, default=32)
+    ap.add_argument("--shape", type=str, default="512,512,512")
+    ap.add_argument("--copies", type=int, default=4)
+    ap.add_argument("--cpu-planes", type=int, default=96, help="slab of the field the CPU checker is timed on")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the per-stage table")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 512 MiB device copy (counter calibration under rocprofv3)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2603_25206_amd import hsz, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    shape = tuple(int(v) for v in a.shape.split(","))
+    spec = synth.large_field_spec(seed=0, shape=shape)
+    t0 = time.time()
+    x = synth.make_field(spec)
+    log(f"[bench] field {shape} generated in {time.time() - t0:.1f}s")
+    n = x.size
+    orig_bytes = x.nbytes
+    xg = torch.from_numpy(x).to(dev)
+    c0 = hsz.compress(xg, a.eb, rel=True, block=a.block)
+    h = c0.header
+    log(f"[bench] compressed: {c0.nbytes / 2**20:.1f} MiB, ratio {c0.ratio:.2f}, max|q| {h.max_abs_q}")
+    copies = [c0] + [hsz.Compressed(c0.data.clone(), h) for _ in range(a.copies - 1)]
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    S48 = [torch.empty(64, dtype=torch.uint8, device=dev) for _ in range(3)]
+    gbuf = torch.empty(n * 4, dtype=torch.uint8, device=dev)
+    qbuf = torch.empty(n * 4, dtype=torch.uint8, device=dev)
+    fbuf = torch.empty(n * 4 + 64, dtype=torch.uint8, device=dev)
+    dbuf = torch.empty(4 * (n + h.nb) + 64, dtype=torch.uint8, device=dev)
+    ws = [hsz.workspace(1 << 20, dev, key=f"bench{k}") for k in range(3)]
+
+    def timed(name, fns, steps, warmup):
+        """Run the list of (label, fn(copy)) per step; per-label HIP event times."""
+        for i in range(warmup):
+            for _, fn in fns:
+                fn(copies[i % len(copies)])
+        torch.cuda.synchronize()
+        evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in fns]
+               for _ in range(steps)]
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for i in range(steps):
+            c = copies[i % len(copies)]
+            for j, (_, fn) in enumerate(fns):
+                evs[i][j][0].record(stream)
+                fn(c)
+                evs[i][j][1].record(stream)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        total_ms = start.elapsed_time(stop)
+        per = {lab: float(np.mean([evs[i][j][0].elapsed_time(evs[i][j][1]) for i in range(steps)]))
+               for j, (lab, _) in enumerate(fns)}
+        return total_ms / steps, per
+
+    # ---- the step: homomorphic analytics from compressed bytes ----------------------
+    def f_mean(c):
+        hsz.op_fused(c, hsz.DELTA, hsz.MEAN, out=S48[0], ws=ws[0], check=False, raw=True)
+
+    def f_var(c):
+        hsz.op_fused(c, hsz.QUANT, hsz.VAR, out=S48[1], ws=ws[1], check=False, raw=True)
+
+    def f_grad(c):
+        try:
+            hsz.op_fused(c, hsz.QUANT, hsz.GRADMAG, out=gbuf, ws=ws[2], check=False, raw=True)
+        except hsz.HszError as e:
+            if e.code != hsz.ERR_UNSUPPORTED:
+                raise
+            hsz.decompress_to_stage(c, hsz.QUANT, out=qbuf)
+            hsz.op_on_stage(hsz.stage_view(qbuf, h, hsz.QUANT), h, hsz.QUANT, hsz.GRADMAG, out=gbuf, ws=ws[2],
+                            check=False, raw=True)
+
+    step_fns = [("mean_fused_delta", f_mean), ("var_fused_quant", f_var), ("gradmag_quant", f_grad)]
+    ms_step, per_step = timed("step", step_fns, a.steps, a.warmup)
+    # correctness spot check of the timed outputs against the other routes (cheap)
+    st_v = hsz.stats_of(S48[1])
+    st_m = hsz.stats_of(S48[0])
+
+    # ---- baseline: full decompression + the same ops on floats ------------------------
+    def b_dec(c):
+        hsz.decompress_to_stage(c, hsz.FLOAT, out=fbuf)
+
+    fview = hsz.stage_view(fbuf, h, hsz.FLOAT)
+
+    def b_mean(c):
+        hsz.op_on_stage(fview, h, hsz.FLOAT, hsz.MEAN, out=S48[0], ws=ws[0], check=False, raw=True)
+
+    def b_var(c):
+        hsz.op_on_stage(fview, h, hsz.FLOAT, hsz.VAR, out=S48[1], ws=ws[1], check=False, raw=True)
+
+    def b_grad(c):
+        hsz.op_on_stage(fview, h, hsz.FLOAT, hsz.GRADMAG, out=gbuf, ws=ws[2], check=False, raw=True)
+
+    base_fns = [("decompress_float", b_dec), ("mean_float", b_mean), ("var_float", b_var), ("gradmag_float", b_grad)]
+    ms_base, per_base = timed("baseline", base_fns, max(5, a.steps // 2), 2)
+    st_bv = hsz.stats_of(S48[1])
+
+    # ---- per-stage table ------------------------------------------------------------
+    extra = {}
+    if not a.no_extra:
+        def dec(stage, out):
+            return lambda c: hsz.decompress_to_stage(c, stage, out=out)
+        rows = [("decompress_delta", dec(hsz.DELTA, dbuf)), ("decompress_quant", dec(hsz.QUANT, qbuf)),
+                ("decompress_float", dec(hsz.FLOAT, fbuf))]
+        _, per = timed("decode", rows, 6, 2)
+        extra.update(per)
+        dview = hsz.stage_view(dbuf, h, hsz.DELTA)
+        qview = hsz.stage_view(qbuf, h, hsz.QUANT)
+        rows = []
+        for stn, st, view in (("delta", hsz.DELTA, dview), ("quant", hsz.QUANT, qview), ("float", hsz.FLOAT, fview)):
+            for opn, op in (("mean", hsz.MEAN), ("var", hsz.VAR)):
+                rows.append((f"{opn}_on_{stn}", (lambda v, s_, o: lambda c: hsz.op_on_stage(
+                    v, h, s_, o, out=S48[2], ws=ws[2], check=False, raw=True))(view, st, op)))
+                rows.append((f"{opn}_fused_{stn}", (lambda s_, o: lambda c: hsz.op_fused(
+                    c, s_, o, out=S48[2], ws=ws[2], check=False, raw=True))(st, op)))
+        for stn, st, view in (("quant", hsz.QUANT, qview), ("float", hsz.FLOAT, fview)):
+            rows.append((f"gradmag_on_{stn}", (lambda v, s_: lambda c: hsz.op_on_stage(
+                v, h, s_, hsz.GRADMAG, out=gbuf, ws=ws[2], check=False, raw=True))(view, st)))
+        _, per = timed("ops", rows, 6, 2)
+        extra.update(per)
+        # compression (input resident in HBM)
+        cbuf = torch.empty_like(c0.data)
+
+        def comp(c):
+            hsz.compress(xg, a.eb, rel=True, block=a.block, out=cbuf, check=False)
+        _, per = timed("compress", [("compress", comp)], 4, 1)
+        extra.update(per)
+    if a.calibrate_copy:
+        src = torch.empty(512 * 2**20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    # ---- roofline of the dominant kernel of the step -------------------------------------
+    cbytes = c0.nbytes
+    alg = {  # algorithmic bytes per launch (compressed input + outputs; never the avoided floats)
+        "mean_fused_delta": cbytes,
+        "var_fused_quant": cbytes,
+        "gradmag_quant": cbytes + 4 * n + 4 * n + 4 * n,  # decode to q (read c, write q) + stencil (read q, write g)
+        "decompress_quant": cbytes + 4 * n,
+        "decompress_float": cbytes + 4 * n,
+        "decompress_delta": cbytes + 4 * n + 4 * h.nb,
+        "gradmag_on_quant": 8 * n,
+        "gradmag_float": 8 * n,
+    }
+    dom = max(per_step, key=per_step.get)
+    achieved = alg[dom] / (per_step[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "alg_bytes_per_launch": int(alg[dom])}
+
+    value = orig_bytes / (ms_step * 1e-3) / 1e9
+    base_value = orig_bytes / (ms_base * 1e-3) / 1e9
+    out = {
+        "metric": "GB/s (orig. data) homomorphic op vs full-decompress+op at eb; p50/p99 query ms",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{'x'.join(map(str, shape))} f32 gaussian-mixture x lognormal texture, "
+                               f"rel eb {a.eb:g}, S={a.block}; step = mean(D_p) + var(D_q) + gradmag(D_q)",
+                   "global_batch": 1, "field_bytes": orig_bytes, "compressed_bytes": cbytes,
+                   "ratio": round(c0.ratio, 3), "parallelism": "single-gpu"},
+        "step_ms": {k: round(v, 4) for k, v in per_step.items()},
+        "full_decompress_baseline": {"value": round(base_value, 1), "unit": "GB/s", "ms_per_step": round(ms_base, 4),
+                                     "per_op_ms": {k: round(v, 4) for k, v in per_base.items()},
+                                     "speedup_homomorphic": round(ms_base / ms_step, 3)},
+        "stage_table_ms": {k: round(v, 4) for k, v in extra.items()},
+        "roofline": roofline,
+        "check": {"var_int_route": st_v["var"], "var_float_route": st_bv["var"], "mean": st_m["mean"]},
+    }
+
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(spec, x, a)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(spec, x, a):
+    """The oracle as it stands (single thread, plain C) on a slab of the same
+    field: decompress to floats, then mean, variance and gradient magnitude
+    on the floats -- the same analytics as one step.  GB/s of original data."""
+    import oracle
+    planes = min(a.cpu_planes, x.shape[0])
+    slab = np.ascontiguousarray(x[:planes])
+    buf = oracle.compress(slab, a.eb, rel=True, block=a.block)
+    t0 = time.perf_counter()
+    xf = oracle.decompress(buf, oracle.FLOAT)
+    oracle.mean(xf)
+    oracle.var(xf)
+    oracle.gradmag(xf)
+    dt = time.perf_counter() - t0
+    return {"value": round(slab.nbytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{planes}x{x.shape[1]}x{x.shape[2]} slab of the same field ({slab.nbytes / 2**20:.0f} MiB), "
+                      f"decompress to floats + mean + var + gradmag, {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -321,7 +321,9 @@ int hsz_op_on_stage(const void* d_stage, const hsz_header* h, int stage, int op,
   if (!d_stage || !aligned16(d_stage)) return HSZ_ERR_INVALID_ARG;
   if (stage == HSZ_META) return HSZ_ERR_UNSUPPORTED;
   if (stage < HSZ_DELTA || stage > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
-  if (op >= HSZ_DERIV && stage == HSZ_DELTA) return HSZ_ERR_UNSUPPORTED;
+  // on the decorrelated stage only the derivative along the fast axis is
+  // defined (the 1D partition keeps no other neighbour relation)
+  if (op >= HSZ_DERIV && stage == HSZ_DELTA && !(op == HSZ_DERIV && axis3 == 2)) return HSZ_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   if ((rc = reset_status(d_workspace, s))) return rc;
   const hsz::StreamView v = view_of(nullptr, h);
@@ -343,6 +345,7 @@ int hsz_op_fused(const void* d_c, const hsz_header* h, int via, int op, int axis
   hipStream_t s = (hipStream_t)stream;
   const hsz::StreamView v = view_of(d_c, h);
   if (op >= HSZ_DERIV) {
+    if (via == HSZ_DELTA && !(op == HSZ_DERIV && axis3 == 2)) return HSZ_ERR_UNSUPPORTED;
     if ((rc = reset_status(d_workspace, s))) return rc;
     hipError_t e = hsz::launch_grad_fused(v, via, op, axis3, t, d_result, (uint8_t*)d_workspace, s);
     if (e == hipErrorNotSupported) return HSZ_ERR_UNSUPPORTED;

@@ -74,17 +74,35 @@ __device__ double ulp_of(double v, int dtype) {
   return ldexp(1.0, e - 1 - (dtype == 1 ? 23 : 52));
 }
 
-__global__ void k_params(const double* partial, int groups, double eb, int eb_is_rel, int dtype,
-                         CompressWs* ws) {
-  if (threadIdx.x != 0) return;
-  ws->status = 0;
+// One workgroup: reduce the min/max partials (256 threads, then a tree),
+// then thread 0 derives eps, eps_q, Delta and 1/Delta.
+__global__ void __launch_bounds__(kThreads) k_params(const double* partial, int groups, double eb, int eb_is_rel,
+                                                     int dtype, CompressWs* ws) {
+  __shared__ double slo[kThreads], shi[kThreads];
+  __shared__ int sbad[kThreads];
+  const int t = threadIdx.x;
   double lo = INFINITY, hi = -INFINITY;
   int bad = 0;
-  for (int g = 0; g < groups; ++g) {
+  for (int g = t; g < groups; g += kThreads) {
     lo = fmin(lo, partial[3 * g + 0]);
     hi = fmax(hi, partial[3 * g + 1]);
     bad |= partial[3 * g + 2] != 0.0;
   }
+  slo[t] = lo; shi[t] = hi; sbad[t] = bad;
+  __syncthreads();
+  for (int half = kThreads / 2; half >= 1; half >>= 1) {
+    if (t < half) {
+      slo[t] = fmin(slo[t], slo[t + half]);
+      shi[t] = fmax(shi[t], shi[t + half]);
+      sbad[t] |= sbad[t + half];
+    }
+    __syncthreads();
+  }
+  if (t != 0) return;
+  ws->status = 0;
+  lo = slo[0];
+  hi = shi[0];
+  bad = sbad[0];
   // + 0.0 turns a -0.0 extreme into +0.0 so the stored bytes are canonical
   lo = lo + 0.0;
   hi = hi + 0.0;
@@ -324,7 +342,7 @@ hipError_t run(const CompressArgs& a, hipStream_t s) {
   int g = (int)((L.n + kThreads * 8 - 1) / (kThreads * 8));
   g = g < 1 ? 1 : (g > kMinmaxGroups ? kMinmaxGroups : g);
   hipLaunchKernelGGL(k_minmax<T>, dim3(g), dim3(kThreads), 0, s, x, L.n, partial);
-  hipLaunchKernelGGL(k_params, dim3(1), dim3(64), 0, s, partial, g, a.eb, a.eb_is_rel, a.dtype, ws);
+  hipLaunchKernelGGL(k_params, dim3(1), dim3(kThreads), 0, s, partial, g, a.eb, a.eb_is_rel, a.dtype, ws);
   const int64_t cg = (L.nchunks + 3) / 4;
   const int grid = (int)(cg < 4096 ? cg : 4096);
   hipLaunchKernelGGL((k_quant_meta<T, S>), dim3(grid), dim3(kThreads), 0, s, x, L.n, L.nb, L.nchunks, ws,

@@ -1,12 +1,20 @@
 // grad.hip -- derivatives and gradient magnitude (Eq. (derivatives),
-// Sec. V-B) on materialised stage buffers.
+// Sec. V-B) on materialised stage buffers and fused with decoding.
 //
-// Stage 3 (D_q): integer numerators n = q_{+1} - q_{-1} inside the field and
-// n = 2 (q_1 - q_0) at its ends (the one-sided difference, expressed over the
-// same denominator), scaled once by Delta/2:  g = n * Delta/2.
-// Stage 4 (D_f): the same stencil on the decompressed floats in the field's
-// own precision: (x_{+1} - x_{-1}) / 2 inside, x_1 - x_0 at the ends.
-// Gradient magnitude = sqrt(sum_k g_k^2); an axis of length 1 adds 0.
+// Integer route (D_q): numerators n = q_{+1} - q_{-1} inside the field and
+// n = 2 (q_1 - q_0) at its ends (the one-sided difference over the same
+// denominator), scaled once by Delta/2: g = n * Delta/2.
+// Float route (D_f): the same stencil on the decompressed values in the
+// field's own precision: (x_{+1} - x_{-1}) * 0.5 inside, x_1 - x_0 at the ends.
+// Gradient magnitude = sqrt(g_z^2 + g_y^2 + g_x^2); an axis of length 1 adds 0.
+//
+// Both kernels march along z (the slowest axis) and keep the z-neighbours of
+// every (x, y) column in registers, so each value is read from memory once
+// per pass; in-plane neighbours come from the cache (buffer kernel) or from
+// one LDS plane (fused kernel).  The fused kernel is the blockwise sliding
+// window of Alg. 3 mapped to the GPU: it decodes each plane of its tile
+// (plus a one-cell halo) from the compressed bytes into LDS, one lane per
+// block, and never writes the stage to memory.
 #include "hsz_device.hpp"
 #include "hsz_launch.hpp"
 
@@ -14,92 +22,409 @@ namespace hsz {
 
 namespace {
 
-constexpr int kThreads = 256;
-
-// integer numerator along one axis at coordinate i of length L, stride st
-__device__ __forceinline__ int qnum(const int32_t* __restrict__ q, int64_t e, int64_t i, int64_t L, int64_t st) {
+// ---- numerators -------------------------------------------------------------------
+// v(-1), v(0), v(+1) along one axis at coordinate i of length L.
+__device__ __forceinline__ int inum(int vm, int v0, int vp, int64_t i, int64_t L) {
   if (L < 2) return 0;
-  if (i == 0) return 2 * (q[e + st] - q[e]);
-  if (i == L - 1) return 2 * (q[e] - q[e - st]);
-  return q[e + st] - q[e - st];
+  if (i == 0) return 2 * (vp - v0);
+  if (i == L - 1) return 2 * (v0 - vm);
+  return vp - vm;
 }
 
 template <typename T>
-__device__ __forceinline__ T fdiff(const T* __restrict__ x, int64_t e, int64_t i, int64_t L, int64_t st) {
+__device__ __forceinline__ T fnum(T vm, T v0, T vp, int64_t i, int64_t L) {
   if (L < 2) return T(0);
-  if (i == 0) return x[e + st] - x[e];
-  if (i == L - 1) return x[e] - x[e - st];
-  return (x[e + st] - x[e - st]) * T(0.5);
+  if (i == 0) return vp - v0;
+  if (i == L - 1) return v0 - vm;
+  return (vp - vm) * T(0.5);
 }
 
-// SRC 3: int32 q in; SRC 4: T floats in.  OP 3: derivative along axis, 4: magnitude.
-template <int SRC, int OP, typename T>
-__global__ void __launch_bounds__(kThreads) k_grad_buf(const void* __restrict__ in, Dims3 d, Box3 b, int axis,
-                                                      double halfq, T* __restrict__ out) {
-  const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0, bz = b.z1 - b.z0;
-  const int64_t tiles = (bx + kThreads - 1) / kThreads;
-  const int64_t items = bz * by * tiles;
-  const T h = (T)halfq;
-  const int64_t sy = d.x, sz = d.x * d.y;
-  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
-    const int64_t tile = it % tiles, row = it / tiles;
-    const int64_t ox = tile * kThreads + threadIdx.x;
-    if (ox >= bx) continue;
-    const int64_t iy = row % by, iz = row / by;
-    const int64_t x = b.x0 + ox, y = b.y0 + iy, z = b.z0 + iz;
-    const int64_t e = (z * d.y + y) * d.x + x;
-    T r;
-    if constexpr (SRC == 3) {
-      const int32_t* q = (const int32_t*)in;
-      if constexpr (OP == 3) {
-        int n = axis == 0 ? qnum(q, e, z, d.z, sz) : axis == 1 ? qnum(q, e, y, d.y, sy) : qnum(q, e, x, d.x, 1);
-        r = (T)n * h;
-      } else {
-        const T gz = (T)qnum(q, e, z, d.z, sz), gy = (T)qnum(q, e, y, d.y, sy), gx = (T)qnum(q, e, x, d.x, 1);
-        r = sqrt(gz * gz + gy * gy + gx * gx) * h;
-      }
-    } else {
-      const T* f = (const T*)in;
-      if constexpr (OP == 3) {
-        r = axis == 0 ? fdiff(f, e, z, d.z, sz) : axis == 1 ? fdiff(f, e, y, d.y, sy) : fdiff(f, e, x, d.x, (int64_t)1);
-      } else {
-        const T gz = fdiff(f, e, z, d.z, sz), gy = fdiff(f, e, y, d.y, sy), gx = fdiff(f, e, x, d.x, (int64_t)1);
-        r = sqrt(gz * gz + gy * gy + gx * gx);
-      }
-    }
-    out[(iz * by + iy) * bx + ox] = r;
+// value of a z/y/x-numerator triple -> output
+template <int OP, bool INT, typename T, typename N>
+__device__ __forceinline__ T finish(N nz, N ny, N nx, int axis, T h) {
+  if constexpr (INT) {
+    if constexpr (OP == 3) return (T)(axis == 0 ? nz : axis == 1 ? ny : nx) * h;
+    const T gz = (T)nz, gy = (T)ny, gx = (T)nx;
+    return sqrt(gz * gz + gy * gy + gx * gx) * h;
+  } else {
+    if constexpr (OP == 3) return axis == 0 ? nz : axis == 1 ? ny : nx;
+    return sqrt(nz * nz + ny * ny + nx * nx);
   }
 }
 
+// ---- stage buffers: 2.5D z-march, one thread per (x, y) column -------------------
+constexpr int kBx = 64, kBy = 4, kBufThreads = kBx * kBy;
+
+// SRC 3: int32 q; SRC 4: T floats.  OP 3: derivative along axis, 4: magnitude.
+template <int SRC, int OP, typename T>
+__global__ void __launch_bounds__(kBufThreads) k_grad_buf(const void* __restrict__ in, Dims3 d, Box3 b, int axis,
+                                                          int tz, double halfq, T* __restrict__ out) {
+  using V = typename std::conditional<SRC == 3, int, T>::type;
+  constexpr bool INT = SRC == 3;
+  const V* src = (const V*)in;
+  const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0, bz = b.z1 - b.z0;
+  const int64_t ntx = (bx + kBx - 1) / kBx, nty = (by + kBy - 1) / kBy;
+  int64_t blk = blockIdx.x;
+  const int64_t tx = blk % ntx;
+  blk /= ntx;
+  const int64_t ty = blk % nty;
+  const int64_t tzi = blk / nty;
+  const int64_t x = b.x0 + tx * kBx + (threadIdx.x % kBx);
+  const int64_t y = b.y0 + ty * kBy + (threadIdx.x / kBx);
+  if (x >= b.x1 || y >= b.y1) return;
+  const int64_t z0 = b.z0 + tzi * tz;
+  const int64_t z1 = min(b.z1, z0 + tz);
+  const int64_t sy = d.x, sz = d.x * d.y;
+  const T h = (T)halfq;
+  const bool need_z = OP == 4 || axis == 0, need_y = OP == 4 || axis == 1, need_x = OP == 4 || axis == 2;
+  const V* col = src + y * sy + x;
+  V qm = z0 > 0 ? col[(z0 - 1) * sz] : V(0);
+  V qc = col[z0 * sz];
+  for (int64_t z = z0; z < z1; ++z) {
+    const V qp = (z + 1 < d.z) ? col[(z + 1) * sz] : V(0);
+    const V* e = col + z * sz;
+    using N = typename std::conditional<INT, int, T>::type;
+    N nz = 0, ny = 0, nx = 0;
+    if constexpr (INT) {
+      if (need_z) nz = inum(qm, qc, qp, z, d.z);
+      if (need_y) ny = inum(y > 0 ? e[-sy] : 0, qc, y + 1 < d.y ? e[sy] : 0, y, d.y);
+      if (need_x) nx = inum(x > 0 ? e[-1] : 0, qc, x + 1 < d.x ? e[1] : 0, x, d.x);
+    } else {
+      if (need_z) nz = fnum<T>(qm, qc, qp, z, d.z);
+      if (need_y) ny = fnum<T>(y > 0 ? e[-sy] : T(0), qc, y + 1 < d.y ? e[sy] : T(0), y, d.y);
+      if (need_x) nx = fnum<T>(x > 0 ? e[-1] : T(0), qc, x + 1 < d.x ? e[1] : T(0), x, d.x);
+    }
+    out[((z - b.z0) * by + (y - b.y0)) * bx + (x - b.x0)] = finish<OP, INT, T>(nz, ny, nx, axis, h);
+    qm = qc;
+    qc = qp;
+  }
+}
+
+// ---- fused: decode tiles from the compressed stream --------------------------------
+constexpr int kTx = 256, kTy = 16, kRows = kTy + 2, kCols = kTx + 2;
+constexpr int kPitch = kCols + (kCols >> 5) + 1;  // one pad word per 32: conflict-free block writes
+constexpr int kFusedThreads = kTx;
+
+__device__ __forceinline__ int pidx(int r, int c) { return r * kPitch + c + (c >> 5); }
+
+template <int S, int VIA, int OP, typename T>
+__global__ void __launch_bounds__(kFusedThreads) k_grad_fused(StreamView v, Dims3 d, Box3 b, int axis, int tz,
+                                                              int kmax, double halfq, T* __restrict__ out,
+                                                              int* status) {
+  using V = typename std::conditional<VIA == 3, int, T>::type;
+  constexpr bool INT = VIA == 3;
+  using N = typename std::conditional<INT, int, T>::type;
+  extern __shared__ uint32_t smem[];
+  V* plane = (V*)smem;
+  uint32_t* stage = smem + (kRows * kPitch * sizeof(V) + 3) / 4;
+  const int t = threadIdx.x;
+
+  const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0, bz = b.z1 - b.z0;
+  const int64_t ntx = (bx + kTx - 1) / kTx, nty = (by + kTy - 1) / kTy;
+  int64_t blk = blockIdx.x;
+  const int64_t tx = blk % ntx;
+  blk /= ntx;
+  const int64_t ty = blk % nty;
+  const int64_t tzi = blk / nty;
+  const int64_t x0 = b.x0 + tx * kTx, y0 = b.y0 + ty * kTy, z0 = b.z0 + tzi * tz;
+  const int xs = (int)min((int64_t)kTx, b.x1 - x0), ys = (int)min((int64_t)kTy, b.y1 - y0);
+  const int64_t zs = min((int64_t)tz, b.z1 - z0);
+  // decoded window: columns [cA, cB), rows [rA, rB) of the field, planes [za, zb)
+  const int64_t cA = max((int64_t)0, x0 - 1), cB = min(d.x, x0 + xs + 1);
+  const int64_t rA = max((int64_t)0, y0 - 1), rB = min(d.y, y0 + ys + 1);
+  const int64_t za = max((int64_t)0, z0 - 1), zb = min(d.z, z0 + zs + 1);
+  const int64_t per_row = (cB - cA + S - 2) / S + 1;
+  const int64_t items = (rB - rA) * per_row;
+  const double quantum = v.quantum;
+  const T h = (T)halfq;
+  const bool need_z = OP == 4 || axis == 0, need_y = OP == 4 || axis == 1, need_x = OP == 4 || axis == 2;
+
+  const int c = t + 1;  // this thread's LDS column; x = x0 + t
+  const int64_t x = x0 + t;
+  const bool active = t < xs;
+  V qm2[kTy], qm1[kTy];
+  N gx1[kTy], gy1[kTy];
+#pragma unroll
+  for (int i = 0; i < kTy; ++i) { qm2[i] = V(0); qm1[i] = V(0); gx1[i] = N(0); gy1[i] = N(0); }
+
+  auto emit = [&](int64_t o, int i, N nz) {
+    const int64_t y = y0 + i;
+    out[((o - b.z0) * by + (y - b.y0)) * bx + (x - b.x0)] = finish<OP, INT, T>(nz, gy1[i], gx1[i], axis, h);
+  };
+
+  for (int64_t p = za; p < zb; ++p) {
+    __syncthreads();  // the previous plane's stencil reads are done
+    for (int64_t it = t; it < items; it += kFusedThreads) {
+      const int64_t r = it / per_row, k = it % per_row;
+      const int64_t y = rA + r;
+      const int64_t f = (p * d.y + y) * d.x;
+      const int64_t blk_id = (f + cA) / S + k;
+      if (blk_id > (f + cB - 1) / S) continue;
+      int q0 = 0;
+      const int w = stage_block<S, kFusedThreads>(v.width, v.q0, v.chunk_off, v.payload, v.payload_words, v.nb,
+                                                   blk_id, stage + t, kmax, q0, status);
+      const int lr = (int)(y - (y0 - 1));
+      const int64_t e0 = blk_id * S - f;  // column of slot 0
+      decode_lane_block<S, kFusedThreads>(stage + t, w, q0, [&](int j, int, int q) {
+        const int64_t xx = e0 + j;
+        if (xx >= cA && xx < cB) {
+          const int cc = (int)(xx - (x0 - 1));
+          if constexpr (INT) plane[pidx(lr, cc)] = q;
+          else plane[pidx(lr, cc)] = (T)dequant64(q, quantum);
+        }
+      });
+    }
+    __syncthreads();
+    if (active) {
+      const int64_t o = p - 1;
+      const bool out_prev = o >= z0 && o < z0 + zs;
+#pragma unroll
+      for (int i = 0; i < kTy; ++i) {
+        if (i < ys) {
+          const int r = i + 1;
+          const int64_t y = y0 + i;
+          const V qc = plane[pidx(r, c)];
+          N nx = 0, ny = 0;
+          if constexpr (INT) {
+            if (need_x) nx = inum(x > 0 ? plane[pidx(r, c - 1)] : 0, qc, x + 1 < d.x ? plane[pidx(r, c + 1)] : 0, x, d.x);
+            if (need_y) ny = inum(y > 0 ? plane[pidx(r - 1, c)] : 0, qc, y + 1 < d.y ? plane[pidx(r + 1, c)] : 0, y, d.y);
+          } else {
+            if (need_x)
+              nx = fnum<T>(x > 0 ? plane[pidx(r, c - 1)] : T(0), qc, x + 1 < d.x ? plane[pidx(r, c + 1)] : T(0), x, d.x);
+            if (need_y)
+              ny = fnum<T>(y > 0 ? plane[pidx(r - 1, c)] : T(0), qc, y + 1 < d.y ? plane[pidx(r + 1, c)] : T(0), y, d.y);
+          }
+          if (out_prev) {
+            N nz = 0;
+            if (need_z) {
+              if constexpr (INT) nz = inum(qm2[i], qm1[i], qc, o, d.z);
+              else nz = fnum<T>(qm2[i], qm1[i], qc, o, d.z);
+            }
+            emit(o, i, nz);
+          }
+          qm2[i] = qm1[i];
+          qm1[i] = qc;
+          gx1[i] = nx;
+          gy1[i] = ny;
+        }
+      }
+    }
+  }
+  // the field's last plane has no plane after it: one-sided (or 0 if nz = 1)
+  if (active && z0 + zs == zb) {
+    const int64_t o = zb - 1;
+#pragma unroll
+    for (int i = 0; i < kTy; ++i) {
+      if (i < ys) {
+        N nz = 0;
+        if (need_z && d.z >= 2) {
+          if constexpr (INT) nz = 2 * (qm1[i] - qm2[i]);
+          else nz = qm1[i] - qm2[i];
+        }
+        emit(o, i, nz);
+      }
+    }
+  }
+}
+
+// ---- stage 2 (D_p): derivative along the fast axis, no recorrelation -----------
+// Inside a block the central difference is q_{j+1} - q_{j-1} = p_j + p_{j+1}
+// (p_j = q_j - q_{j-1}).  At a block edge the missing neighbour comes from
+// the metadata: the next block's q0, or the previous block's last value
+// q0 + (sum of its deltas).  One lane per (box row, block) segment; the
+// previous block's last value is taken from the neighbouring lane when that
+// lane holds it, else summed from its deltas.
+template <int S, bool FROM_STREAM, typename T>
+__global__ void __launch_bounds__(256) k_deriv_fast_delta(const int32_t* __restrict__ pbuf,
+                                                          const int32_t* __restrict__ q0buf, StreamView v,
+                                                          Segs<S> segs, Dims3 d, Box3 b, int kmax, double halfq,
+                                                          T* __restrict__ out, int* status) {
+  extern __shared__ uint32_t smem[];
+  const int t = threadIdx.x;
+  const int64_t items = segs.count();
+  const T h = (T)halfq;
+  const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0;
+  const int32_t* q0s = FROM_STREAM ? v.q0 : q0buf;
+  uint32_t* col = smem + t;
+  // p of block k, the block's first q, and its last q = q0 + sum of deltas
+  auto load_block = [&](int64_t k, int (&pv)[S], int& q0) {
+    if constexpr (FROM_STREAM) {
+      const int w = stage_block<S, 256>(v.width, v.q0, v.chunk_off, v.payload, v.payload_words, v.nb, k, col,
+                                        kmax, q0, status);
+      decode_lane_block<S, 256>(col, w, q0, [&](int j, int p, int) { pv[j] = p; });
+    } else {
+      q0 = q0buf[k];
+#pragma unroll
+      for (int j = 0; j < S; ++j) pv[j] = (k * S + j < v.n) ? pbuf[k * S + j] : 0;
+    }
+    int sum = 0;
+#pragma unroll
+    for (int j = 1; j < S; ++j) sum += pv[j];
+    return q0 + sum;
+  };
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < items; base += (int64_t)gridDim.x * 256) {
+    const int64_t it = base + t;
+    int64_t blk = -1;
+    int a = 0, z = -1;
+    const bool ok = it < items && segs.get(it, blk, a, z);
+    int pv[S];
+    int q0 = 0, qlast = 0;
+    if (ok) qlast = load_block(blk, pv, q0);
+    const int64_t prev_blk = __shfl_up(blk, 1);
+    const int prev_last = __shfl_up(qlast, 1);
+    const int prev_ok = __shfl_up((int)ok, 1);
+    if (!ok) continue;
+    const int64_t r = it / segs.per_row;
+    const int64_t f = segs.rows.start(r);  // flat index of the box row's first element
+    const int64_t e0 = blk * S;
+    const int64_t x_of0 = b.x0 + (e0 - f);  // x of slot 0 (may lie left of the box)
+    int qprev = 0;
+    if (a == 0 && x_of0 > 0) {
+      if (lane_id() > 0 && prev_ok && prev_blk == blk - 1) {
+        qprev = prev_last;
+      } else {
+        int pp[S];
+        int q0p;
+        qprev = load_block(blk - 1, pp, q0p);  // pv stays in registers
+      }
+    }
+    const int q0next = (z == S - 1 && x_of0 + S - 1 < d.x - 1) ? q0s[blk + 1] : 0;
+    const int64_t iz = r / segs.rows.nry, iy = r % segs.rows.nry;
+    const int64_t orow = (iz * by + iy) * bx - b.x0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      if (j >= a && j <= z) {
+        const int64_t x = x_of0 + j;
+        int nn;
+        if (d.x < 2) nn = 0;
+        else if (x == 0) nn = 2 * (j + 1 <= S - 1 ? pv[j + 1 < S ? j + 1 : S - 1] : q0next - qlast);
+        else if (x == d.x - 1) nn = 2 * (j >= 1 ? pv[j] : q0 - qprev);
+        else if (j == 0) nn = q0 + pv[1] - qprev;
+        else if (j == S - 1) nn = q0next - (qlast - pv[S - 1]);
+        else nn = pv[j] + pv[j + 1 < S ? j + 1 : S - 1];
+        out[orow + x] = (T)nn * h;
+      }
+    }
+  }
+}
+
+int kmax_for(const StreamView& v) {
+  int wmax = 32 - __builtin_clz(2u * v.max_abs_q | 1u);
+  wmax = wmax < 1 ? 1 : (wmax > kMaxWidth ? kMaxWidth : wmax);
+  return (v.block / 32) * (1 + wmax);
+}
+
 template <int SRC, typename T>
-hipError_t run(const void* buf, int op, int axis, const OpTarget& t, double halfq, void* out, hipStream_t s) {
+hipError_t run_buf(const void* buf, int op, int axis, const OpTarget& t, double halfq, void* out, hipStream_t s) {
   const Box3& b = t.box;
-  const int64_t tiles = (b.x1 - b.x0 + kThreads - 1) / kThreads;
-  const int64_t items = (b.z1 - b.z0) * (b.y1 - b.y0) * tiles;
-  const int grid = (int)(items < 65536 ? items : 65536);
+  const int64_t ntx = (b.x1 - b.x0 + kBx - 1) / kBx, nty = (b.y1 - b.y0 + kBy - 1) / kBy;
+  const int64_t bz = b.z1 - b.z0;
+  // enough workgroups to fill the chip, long enough z runs to reuse the column registers
+  int64_t tz = bz;
+  while (tz > 16 && ntx * nty * ((bz + tz - 1) / tz) < 4096) tz = (tz + 1) / 2;
+  const int64_t grid = ntx * nty * ((bz + tz - 1) / tz);
   if (op == 3)
-    hipLaunchKernelGGL((k_grad_buf<SRC, 3, T>), dim3(grid), dim3(kThreads), 0, s, buf, t.d, b, axis, halfq, (T*)out);
+    hipLaunchKernelGGL((k_grad_buf<SRC, 3, T>), dim3((unsigned)grid), dim3(kBufThreads), 0, s, buf, t.d, b, axis,
+                       (int)tz, halfq, (T*)out);
   else
-    hipLaunchKernelGGL((k_grad_buf<SRC, 4, T>), dim3(grid), dim3(kThreads), 0, s, buf, t.d, b, axis, halfq, (T*)out);
+    hipLaunchKernelGGL((k_grad_buf<SRC, 4, T>), dim3((unsigned)grid), dim3(kBufThreads), 0, s, buf, t.d, b, axis,
+                       (int)tz, halfq, (T*)out);
   return hipGetLastError();
+}
+
+template <int S, int VIA, typename T>
+hipError_t run_fused(const StreamView& v, int op, int axis, const OpTarget& t, void* out, int* status,
+                     hipStream_t s) {
+  using V = typename std::conditional<VIA == 3, int, T>::type;
+  const Box3& b = t.box;
+  const int kmax = kmax_for(v);
+  const size_t plane_bytes = ((kRows * kPitch * sizeof(V) + 3) / 4) * 4;
+  const size_t lds = plane_bytes + (size_t)(kmax + 1) * kFusedThreads * sizeof(uint32_t);
+  const int64_t ntx = (b.x1 - b.x0 + kTx - 1) / kTx, nty = (b.y1 - b.y0 + kTy - 1) / kTy;
+  const int64_t bz = b.z1 - b.z0;
+  int64_t tz = bz;
+  while (tz > 8 && ntx * nty * ((bz + tz - 1) / tz) < 1024) tz = (tz + 1) / 2;
+  const int64_t grid = ntx * nty * ((bz + tz - 1) / tz);
+  const double halfq = 0.5 * v.quantum;
+  if (op == 3)
+    hipLaunchKernelGGL((k_grad_fused<S, VIA, 3, T>), dim3((unsigned)grid), dim3(kFusedThreads), lds, s, v, t.d, b,
+                       axis, (int)tz, kmax, halfq, (T*)out, status);
+  else
+    hipLaunchKernelGGL((k_grad_fused<S, VIA, 4, T>), dim3((unsigned)grid), dim3(kFusedThreads), lds, s, v, t.d, b,
+                       axis, (int)tz, kmax, halfq, (T*)out, status);
+  return hipGetLastError();
+}
+
+template <int S>
+hipError_t fused_by_via(const StreamView& v, int via, int op, int axis, const OpTarget& t, void* out, int* status,
+                        hipStream_t s) {
+  if (via == 3)
+    return v.dtype == 1 ? run_fused<S, 3, float>(v, op, axis, t, out, status, s)
+                        : run_fused<S, 3, double>(v, op, axis, t, out, status, s);
+  if (via == 4)
+    return v.dtype == 1 ? run_fused<S, 4, float>(v, op, axis, t, out, status, s)
+                        : run_fused<S, 4, double>(v, op, axis, t, out, status, s);
+  return hipErrorNotSupported;
+}
+
+template <int S, bool FROM_STREAM, typename T>
+hipError_t run_fast_delta(const int32_t* p, const StreamView& v, const OpTarget& t, void* out, int* status,
+                          hipStream_t s) {
+  const Box3& b = t.box;
+  Rows rows;
+  rows.nrz = b.z1 - b.z0;
+  rows.nry = b.y1 - b.y0;
+  rows.len = b.x1 - b.x0;
+  rows.base = (b.z0 * t.d.y + b.y0) * t.d.x + b.x0;
+  rows.sz = t.d.x * t.d.y;
+  rows.sy = t.d.x;
+  const Segs<S> segs = make_segs<S>(rows);
+  const int kmax = kmax_for(v);
+  const size_t lds = FROM_STREAM ? (size_t)(kmax + 1) * 256 * sizeof(uint32_t) : 0;
+  const int64_t g = (segs.count() + 255) / 256;
+  const unsigned grid = (unsigned)(g < 8192 ? g : 8192);
+  hipLaunchKernelGGL((k_deriv_fast_delta<S, FROM_STREAM, T>), dim3(grid), dim3(256), lds, s, p,
+                     p ? p + v.n : nullptr, v, segs, t.d, b, kmax, 0.5 * v.quantum, (T*)out, status);
+  return hipGetLastError();
+}
+
+template <bool FROM_STREAM>
+hipError_t fast_delta(const int32_t* p, const StreamView& v, const OpTarget& t, void* out, int* status,
+                      hipStream_t s) {
+  if (v.block == 32)
+    return v.dtype == 1 ? run_fast_delta<32, FROM_STREAM, float>(p, v, t, out, status, s)
+                        : run_fast_delta<32, FROM_STREAM, double>(p, v, t, out, status, s);
+  return v.dtype == 1 ? run_fast_delta<64, FROM_STREAM, float>(p, v, t, out, status, s)
+                      : run_fast_delta<64, FROM_STREAM, double>(p, v, t, out, status, s);
 }
 
 }  // namespace
 
 hipError_t launch_grad_stage(const void* buf, int stage, const StreamView& v, int op, int axis3, const OpTarget& t,
-                             void* result, uint8_t*, hipStream_t s) {
+                             void* result, uint8_t* ws, hipStream_t s) {
   const double halfq = 0.5 * v.quantum;
+  if (stage == 2) {
+    if (op != 3 || axis3 != 2) return hipErrorNotSupported;
+    return fast_delta<false>((const int32_t*)buf, v, t, result, (int*)ws, s);
+  }
   if (stage == 3)
-    return v.dtype == 1 ? run<3, float>(buf, op, axis3, t, halfq, result, s)
-                        : run<3, double>(buf, op, axis3, t, halfq, result, s);
+    return v.dtype == 1 ? run_buf<3, float>(buf, op, axis3, t, halfq, result, s)
+                        : run_buf<3, double>(buf, op, axis3, t, halfq, result, s);
   if (stage == 4)
-    return v.dtype == 1 ? run<4, float>(buf, op, axis3, t, halfq, result, s)
-                        : run<4, double>(buf, op, axis3, t, halfq, result, s);
+    return v.dtype == 1 ? run_buf<4, float>(buf, op, axis3, t, halfq, result, s)
+                        : run_buf<4, double>(buf, op, axis3, t, halfq, result, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_grad_fused(const StreamView&, int, int, int, const OpTarget&, void*, uint8_t*, hipStream_t) {
-  return hipErrorNotSupported;
+hipError_t launch_grad_fused(const StreamView& v, int via, int op, int axis3, const OpTarget& t, void* result,
+                             uint8_t* ws, hipStream_t s) {
+  int* status = (int*)ws;
+  if (via == 2) {
+    if (op != 3 || axis3 != 2) return hipErrorNotSupported;
+    return fast_delta<true>(nullptr, v, t, result, status, s);
+  }
+  return v.block == 32 ? fused_by_via<32>(v, via, op, axis3, t, result, status, s)
+                       : fused_by_via<64>(v, via, op, axis3, t, result, status, s);
 }
 
 }  // namespace hsz

@@ -15,6 +15,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
+#include "hsz_launch.hpp"
+
 namespace hsz {
 
 constexpr int kHeaderBytes = 256;
@@ -84,6 +88,58 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
 __device__ __forceinline__ double wave_sum_f64(double x) {
   for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
   return x;
+}
+
+// ---- row sets and block segments (boxes) -------------------------------------
+// A set of contiguous flat ranges ("rows"): row r = iz*nry + iy starts at
+// base + iz*sz + iy*sy and has len elements.
+struct Rows {
+  int64_t nrz, nry, len, base, sz, sy;
+  __host__ __device__ int64_t count() const { return nrz * nry; }
+  __device__ int64_t start(int64_t r) const { return base + (r / nry) * sz + (r % nry) * sy; }
+};
+
+inline Rows make_rows(const Dims3& d, const Box3& b) {
+  Rows r;
+  const int64_t plane = d.y * d.x;
+  if (b.x0 == 0 && b.x1 == d.x && b.y0 == 0 && b.y1 == d.y) {
+    r.nrz = 1; r.nry = 1; r.len = (b.z1 - b.z0) * plane; r.base = b.z0 * plane; r.sz = 0; r.sy = 0;
+  } else if (b.x0 == 0 && b.x1 == d.x) {
+    r.nrz = b.z1 - b.z0; r.nry = 1; r.len = (b.y1 - b.y0) * d.x; r.base = b.z0 * plane + b.y0 * d.x;
+    r.sz = plane; r.sy = 0;
+  } else {
+    r.nrz = b.z1 - b.z0; r.nry = b.y1 - b.y0; r.len = b.x1 - b.x0;
+    r.base = b.z0 * plane + b.y0 * d.x + b.x0; r.sz = plane; r.sy = d.x;
+  }
+  return r;
+}
+
+// ---- block segments: the part of one block that lies inside one row -------------
+// Items are (row, k-th block touched by the row).  For a row [f, f+len) the
+// blocks are f/S .. (f+len-1)/S; inside block b the row covers slots a..z.
+template <int S>
+struct Segs {
+  Rows rows;
+  int64_t per_row;  // upper bound of blocks touched by one row
+  __host__ __device__ int64_t count() const { return rows.count() * per_row; }
+  // returns false if item k lies past the row's last block
+  __device__ bool get(int64_t item, int64_t& b, int& a, int& z) const {
+    const int64_t r = item / per_row, k = item % per_row;
+    const int64_t f = rows.start(r), e = f + rows.len;  // [f, e)
+    b = f / S + k;
+    if (b > (e - 1) / S) return false;
+    const int64_t bs = b * S;
+    a = (int)(f > bs ? f - bs : 0);
+    z = (int)((e < bs + S ? e : bs + S) - 1 - bs);
+    return true;
+  }
+};
+template <int S>
+inline Segs<S> make_segs(const Rows& r) {
+  Segs<S> s;
+  s.rows = r;
+  s.per_row = (r.len + S - 2) / S + 1;
+  return s;
 }
 
 // ---- 128-bit unsigned accumulator (sum of q^2 can pass 2^64) ----------------
@@ -159,23 +215,80 @@ __device__ __forceinline__ bool stage_chunk(const uint8_t* __restrict__ width,
   return true;
 }
 
+// ---- random access to one block ----------------------------------------------
+// Word offset (within the payload) of block b: the chunk table entry plus the
+// words of the blocks before b in its 64-block chunk, read as up to 16 words
+// of packed widths (byte sums with v_sad_u8, non-zero bytes by bit tricks).
+template <int S>
+__device__ __forceinline__ uint64_t block_offset(const uint8_t* __restrict__ width,
+                                                 const uint64_t* __restrict__ chunk_off, int64_t nb,
+                                                 int64_t b) {
+  const int64_t c = b / kChunkBlocks;
+  const int cnt = (int)(b - c * kChunkBlocks);
+  const uint32_t* wq = (const uint32_t*)(width + c * kChunkBlocks);
+  const int64_t avail = nb - c * kChunkBlocks;  // bytes of this chunk inside the section
+  uint32_t sumw = 0, nz = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (4 * k < cnt) {
+      // the width section is padded to 256 bytes, so whole words are readable
+      uint32_t dw = (4 * k < avail) ? wq[k] : 0u;
+      const int keep = cnt - 4 * k;
+      if (keep < 4) dw &= (1u << (8 * keep)) - 1u;
+      sumw += __builtin_amdgcn_sad_u8(dw, 0u, 0u);
+      const uint32_t t = ((dw & 0x7f7f7f7fu) + 0x7f7f7f7fu) | dw;
+      nz += __builtin_popcount(t & 0x80808080u);
+    }
+  }
+  return chunk_off[c] + (uint64_t)(S / 32) * (sumw + nz);
+}
+
+// Stage block b into one LDS column (rows STRIDE words apart).  Returns the
+// width, 0 when the block is corrupt (status recorded) -- it then decodes as
+// the constant q0.
+template <int S, int STRIDE>
+__device__ __forceinline__ int stage_block(const uint8_t* __restrict__ width, const int32_t* __restrict__ q0s,
+                                           const uint64_t* __restrict__ chunk_off,
+                                           const uint32_t* __restrict__ payload, uint64_t payload_words,
+                                           int64_t nb, int64_t b, uint32_t* col, int kmax, int& q0,
+                                           int* status) {
+  const int w = (int)width[b];
+  q0 = q0s[b];
+  const int nw = block_words<S>(w);
+  const uint64_t off = block_offset<S>(width, chunk_off, nb, b);
+  if (w > kMaxWidth || nw > kmax || off + (uint64_t)nw > payload_words) {
+    record_status(status, kErrBadStream);
+    return 0;
+  }
+  const uint32_t* src = payload + off;
+  for (int k0 = 0; k0 < nw; k0 += 8) {
+    uint32_t t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = (k0 + u < nw) ? src[k0 + u] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < nw) col[(k0 + u) * STRIDE] = t[u];
+  }
+  return w;
+}
+
 // Decode the lane's block from its LDS column.  For every slot j in order
 // it calls sink(j, p_j, q_j) with p the decorrelated integer (stage 2) and
 // q the recorrelated quantization integer (stage 3).  Slot 0 has p = 0 and
 // q = q0.  col = tile + lane (column base); rows hold sign word(s) first,
 // then magnitude words.
-template <int S, class Sink>
+template <int S, int STRIDE = kWave, class Sink>
 __device__ __forceinline__ void decode_lane_block(const uint32_t* col, int w, int q0, Sink&& sink) {
   const uint32_t sg0 = w ? col[0] : 0u;
-  const uint32_t sg1 = (S == 64 && w) ? col[kWave] : 0u;
-  const uint32_t* mag = col + (S / 32) * kWave;
+  const uint32_t sg1 = (S == 64 && w) ? col[STRIDE] : 0u;
+  const uint32_t* mag = col + (S / 32) * STRIDE;
   int q = q0;
 #pragma unroll
   for (int j = 0; j < S; ++j) {
     const uint32_t pos = (uint32_t)j * (uint32_t)w;
     const uint32_t k = pos >> 5;
-    const uint32_t lo = mag[k * kWave];
-    const uint32_t hi = mag[(k + 1) * kWave];
+    const uint32_t lo = mag[k * STRIDE];
+    const uint32_t hi = mag[(k + 1) * STRIDE];
     const uint32_t a = __builtin_amdgcn_alignbit(hi, lo, pos & 31u);
     const uint32_t m = __builtin_amdgcn_ubfe(a, 0u, (uint32_t)w);
     const int s = (j < 32) ? __builtin_amdgcn_sbfe((int)sg0, (uint32_t)j, 1u)

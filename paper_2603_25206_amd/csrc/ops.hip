@@ -29,29 +29,6 @@ struct Partial {
   double pad0, pad1;
 };
 
-// A set of contiguous flat ranges ("rows"): row r = iz*nry + iy starts at
-// base + iz*sz + iy*sy and has len elements.
-struct Rows {
-  int64_t nrz, nry, len, base, sz, sy;
-  __host__ __device__ int64_t count() const { return nrz * nry; }
-  __device__ int64_t start(int64_t r) const { return base + (r / nry) * sz + (r % nry) * sy; }
-};
-
-Rows make_rows(const Dims3& d, const Box3& b) {
-  Rows r;
-  const int64_t plane = d.y * d.x;
-  if (b.x0 == 0 && b.x1 == d.x && b.y0 == 0 && b.y1 == d.y) {
-    r.nrz = 1; r.nry = 1; r.len = (b.z1 - b.z0) * plane; r.base = b.z0 * plane; r.sz = 0; r.sy = 0;
-  } else if (b.x0 == 0 && b.x1 == d.x) {
-    r.nrz = b.z1 - b.z0; r.nry = 1; r.len = (b.y1 - b.y0) * d.x; r.base = b.z0 * plane + b.y0 * d.x;
-    r.sz = plane; r.sy = 0;
-  } else {
-    r.nrz = b.z1 - b.z0; r.nry = b.y1 - b.y0; r.len = b.x1 - b.x0;
-    r.base = b.z0 * plane + b.y0 * d.x + b.x0; r.sz = plane; r.sy = d.x;
-  }
-  return r;
-}
-
 // ---- accumulation helpers ------------------------------------------------------
 struct IntAcc {
   int64_t s1 = 0;
@@ -150,34 +127,6 @@ __global__ void __launch_bounds__(kThreads) k_stats_f(const T* __restrict__ x, R
   store_f64_partial(f1, f2, cnt, K, parts);
 }
 
-// ---- block segments: the part of one block that lies inside one row -------------
-// Items are (row, k-th block touched by the row).  For a row [f, f+len) the
-// blocks are f/S .. (f+len-1)/S; inside block b the row covers slots a..z.
-template <int S>
-struct Segs {
-  Rows rows;
-  int64_t per_row;  // upper bound of blocks touched by one row
-  __host__ __device__ int64_t count() const { return rows.count() * per_row; }
-  // returns false if item k lies past the row's last block
-  __device__ bool get(int64_t item, int64_t& b, int& a, int& z) const {
-    const int64_t r = item / per_row, k = item % per_row;
-    const int64_t f = rows.start(r), e = f + rows.len;  // [f, e)
-    b = f / S + k;
-    if (b > (e - 1) / S) return false;
-    const int64_t bs = b * S;
-    a = (int)(f > bs ? f - bs : 0);
-    z = (int)((e < bs + S ? e : bs + S) - 1 - bs);
-    return true;
-  }
-};
-template <int S>
-Segs<S> make_segs(const Rows& r) {
-  Segs<S> s;
-  s.rows = r;
-  s.per_row = (r.len + S - 2) / S + 1;
-  return s;
-}
-
 // Stage-2 statistics from a p buffer (p[n], q0[nb]).
 template <int S, int OP>
 __global__ void __launch_bounds__(kThreads) k_stats_delta(const int32_t* __restrict__ p,
@@ -210,56 +159,6 @@ __global__ void __launch_bounds__(kThreads) k_stats_delta(const int32_t* __restr
 }
 
 // ---- fused statistics straight from the compressed stream ------------------------
-// Word offset (within the payload) of block b: the chunk table entry plus the
-// words of the blocks before b in its 64-block chunk, read as 16 words of
-// packed widths.
-template <int S>
-__device__ __forceinline__ uint64_t block_offset(const StreamView& v, int64_t b) {
-  const int64_t c = b / kChunkBlocks;
-  const int cnt = (int)(b - c * kChunkBlocks);
-  const uint32_t* wq = (const uint32_t*)(v.width + c * kChunkBlocks);
-  const int64_t avail = v.nb - c * kChunkBlocks;  // bytes of this chunk inside the section
-  uint32_t sumw = 0, nz = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    if (4 * k < cnt) {
-      // the width section is padded to 256 bytes, so whole words are readable
-      uint32_t d = (4 * k < avail) ? wq[k] : 0u;
-      const int keep = cnt - 4 * k;
-      if (keep < 4) d &= (1u << (8 * keep)) - 1u;
-      sumw += __builtin_amdgcn_sad_u8(d, 0u, 0u);
-      const uint32_t t = ((d & 0x7f7f7f7fu) + 0x7f7f7f7fu) | d;
-      nz += __builtin_popcount(t & 0x80808080u);
-    }
-  }
-  return v.chunk_off[c] + (uint64_t)(S / 32) * (sumw + nz);
-}
-
-// Stage the lane's own block b into its LDS column (random-access variant of
-// stage_chunk).  Returns the width (0 when the block is invalid or corrupt).
-template <int S>
-__device__ __forceinline__ int stage_lane(const StreamView& v, int64_t b, uint32_t* col, int kmax, int& q0,
-                                          int* status) {
-  int w = (int)v.width[b];
-  q0 = v.q0[b];
-  const int nw = block_words<S>(w);
-  const uint64_t off = block_offset<S>(v, b);
-  if (w > kMaxWidth || nw > kmax || off + (uint64_t)nw > v.payload_words) {
-    record_status(status, kErrBadStream);
-    return 0;
-  }
-  const uint32_t* src = v.payload + off;
-  for (int k0 = 0; k0 < nw; k0 += 8) {
-    uint32_t t[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = (k0 + u < nw) ? src[k0 + u] : 0u;
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (k0 + u < nw) col[(k0 + u) * kWave] = t[u];
-  }
-  return w;
-}
-
 // VIA: 2 (decorrelated), 3 (quantized), 4 (floats).  WHOLE: the items are
 // every block in order (chunk-aligned waves use the chunk scan).
 template <int S, int VIA, int OP, typename T, bool WHOLE>
@@ -288,7 +187,7 @@ __global__ void __launch_bounds__(kThreads) k_stats_fused(StreamView v, Segs<S> 
       const int64_t it = base + l;
       bool ok = it < items && segs.get(it, b, a, z);
       w = 0; q0 = 0;
-      if (ok) w = stage_lane<S>(v, b, tile + l, kmax, q0, status);
+      if (ok) w = stage_block<S, kWave>(v.width, v.q0, v.chunk_off, v.payload, v.payload_words, v.nb, b, tile + l, kmax, q0, status);
       else z = -1;
     }
     if (z < 0) continue;
@@ -331,44 +230,68 @@ __device__ double u128_to_f64(unsigned __int128 v) {
   return (double)(uint64_t)(v >> 64) * 18446744073709551616.0 + (double)(uint64_t)v;
 }
 
-__global__ void k_finalize(const Partial* parts, int groups, int op, int fl, double quantum, StatsOut* out) {
-  if (threadIdx.x != 0) return;
-  StatsOut r{};
-  if (!fl) {
-    int64_t s1 = 0, cnt = 0;
-    unsigned __int128 s2 = 0;
-    for (int g = 0; g < groups; ++g) {
-      s1 += parts[g].s1;
-      cnt += parts[g].cnt;
-      s2 += ((unsigned __int128)parts[g].s2hi << 64) | parts[g].s2lo;
+// One workgroup of 256 threads: thread t sums partials t, t+256, ... in
+// order, then a fixed-shape tree combines the 256 sums, so the result does
+// not depend on timing.
+constexpr int kFinThreads = 256;
+
+__global__ void __launch_bounds__(kFinThreads) k_finalize(const Partial* parts, int groups, int op, int fl,
+                                                          double quantum, StatsOut* out) {
+  __shared__ int64_t s1s[kFinThreads], cnts[kFinThreads];
+  __shared__ uint64_t los[kFinThreads], his[kFinThreads];
+  __shared__ double f1s[kFinThreads], f2s[kFinThreads];
+  const int t = threadIdx.x;
+  int64_t s1 = 0, cnt = 0;
+  U128 s2 = {0, 0};
+  double f1 = 0.0, f2 = 0.0;
+  for (int g = t; g < groups; g += kFinThreads) {
+    const Partial p = parts[g];
+    s1 += p.s1;
+    cnt += p.cnt;
+    add_u128(s2, U128{p.s2lo, p.s2hi});
+    f1 += p.f1;
+    f2 += p.f2;
+  }
+  s1s[t] = s1; cnts[t] = cnt; los[t] = s2.lo; his[t] = s2.hi; f1s[t] = f1; f2s[t] = f2;
+  __syncthreads();
+  for (int half = kFinThreads / 2; half >= 1; half >>= 1) {
+    if (t < half) {
+      s1s[t] += s1s[t + half];
+      cnts[t] += cnts[t + half];
+      U128 a{los[t], his[t]};
+      add_u128(a, U128{los[t + half], his[t + half]});
+      los[t] = a.lo;
+      his[t] = a.hi;
+      f1s[t] += f1s[t + half];
+      f2s[t] += f2s[t + half];
     }
-    r.n = cnt;
-    r.s1 = s1;
-    r.mean = (double)s1 * quantum / (double)cnt;
+    __syncthreads();
+  }
+  if (t != 0) return;
+  StatsOut r{};
+  r.n = cnts[0];
+  const int64_t n = cnts[0];
+  if (!fl) {
+    const int64_t S1 = s1s[0];
+    const unsigned __int128 S2 = ((unsigned __int128)his[0] << 64) | los[0];
+    r.s1 = S1;
+    r.mean = (double)S1 * quantum / (double)n;
     if (op == 2) {
-      r.s2lo = (uint64_t)s2;
-      r.s2hi = (int64_t)(uint64_t)(s2 >> 64);
+      r.s2lo = (uint64_t)S2;
+      r.s2hi = (int64_t)(uint64_t)(S2 >> 64);
       // n*s2 - s1^2 >= 0, exact in 128 bits for n < 2^34 and |q| < 2^29
-      const unsigned __int128 a = (unsigned __int128)(uint64_t)cnt * s2;
-      const uint64_t m = (uint64_t)(s1 < 0 ? -s1 : s1);
+      const unsigned __int128 a = (unsigned __int128)(uint64_t)n * S2;
+      const uint64_t m = (uint64_t)(S1 < 0 ? -S1 : S1);
       const unsigned __int128 b = (unsigned __int128)m * m;
       const double num = u128_to_f64(a - b);
-      r.var = cnt > 1 ? num / ((double)cnt * (double)(cnt - 1)) * (quantum * quantum) : __builtin_nan("");
+      r.var = n > 1 ? num / ((double)n * (double)(n - 1)) * (quantum * quantum) : __builtin_nan("");
     } else {
       r.var = __builtin_nan("");
     }
   } else {
-    double f1 = 0.0, f2 = 0.0;
-    int64_t cnt = 0;
-    for (int g = 0; g < groups; ++g) {
-      f1 += parts[g].f1;
-      f2 += parts[g].f2;
-      cnt += parts[g].cnt;
-    }
     const double K = parts[0].pad0;
-    r.n = cnt;
-    r.mean = K + f1 / (double)cnt;
-    r.var = (op == 2 && cnt > 1) ? (f2 - f1 * f1 / (double)cnt) / (double)(cnt - 1) : __builtin_nan("");
+    r.mean = K + f1s[0] / (double)n;
+    r.var = (op == 2 && n > 1) ? (f2s[0] - f1s[0] * f1s[0] / (double)n) / (double)(n - 1) : __builtin_nan("");
   }
   *out = r;
 }
@@ -393,7 +316,7 @@ __global__ void k_first_value(StreamView v, int64_t f, int kmax, double* K, int*
   const int64_t b = f / S;
   const int slot = (int)(f - b * S);
   int q0 = 0;
-  const int w = lane_id() == 0 ? stage_lane<S>(v, b, smem, kmax, q0, status) : 0;
+  const int w = lane_id() == 0 ? stage_block<S, kWave>(v.width, v.q0, v.chunk_off, v.payload, v.payload_words, v.nb, b, smem, kmax, q0, status) : 0;
   if (lane_id() != 0) return;
   int qv = 0;
   decode_lane_block<S>(smem, w, q0, [&](int j, int, int q) {
@@ -474,7 +397,7 @@ hipError_t launch_stats_stage(const void* buf, int stage, const StreamView& v, i
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // stage 4 sums are shifted by the box's first value; every partial carries it
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, parts, grid, op, stage == 4 ? 1 : 0, v.quantum,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, parts, grid, op, stage == 4 ? 1 : 0, v.quantum,
                      (StatsOut*)result);
   return hipGetLastError();
 }
@@ -495,7 +418,7 @@ hipError_t launch_stats_fused(const StreamView& v, int via, int op, const OpTarg
     e = op == 1 ? fused_by_via<64, 1>(v, via, rows, whole, K, parts, grid, status, s)
                 : fused_by_via<64, 2>(v, via, rows, whole, K, parts, grid, status, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, parts, grid, op, via == 4 ? 1 : 0, v.quantum,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, parts, grid, op, via == 4 ? 1 : 0, v.quantum,
                      (StatsOut*)result);
   return hipGetLastError();
 }

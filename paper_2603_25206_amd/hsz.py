@@ -302,7 +302,14 @@ def _result_buffer(h: Header, op: int, box, device):
     return _empty_bytes(esz * vol, device), shape
 
 
-def _finish(buf, shape, h, op, ws, stream, check):
+def stats_of(buf: torch.Tensor) -> dict:
+    """Decode a 48-byte hsz_stats result buffer (synchronises)."""
+    return _stats_from_raw(buf[:48].cpu().numpy().tobytes())
+
+
+def _finish(buf, shape, h, op, ws, stream, check, raw=False):
+    if raw:
+        return buf
     if check:
         st = read_status(ws, stream)
         if st != OK:
@@ -317,7 +324,7 @@ def _finish(buf, shape, h, op, ws, stream, check):
 
 
 def op_on_stage(stage_buf, h: Header, stage, op, axis: int = 0, box=None, stream=None, check: bool = True,
-                out: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+                out: torch.Tensor | None = None, ws: torch.Tensor | None = None, raw: bool = False):
     """Operation on a materialised stage buffer (the tensor(s) returned by
     decompress_to_stage).  Stats return a dict; derivatives a tensor."""
     lib = load()
@@ -336,11 +343,11 @@ def op_on_stage(stage_buf, h: Header, stage, op, axis: int = 0, box=None, stream
                                _box(box, h.ndim), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream(stream))),
            "op_on_stage")
-    return _finish(buf, shape, h, op, ws, stream, check)
+    return _finish(buf, shape, h, op, ws, stream, check, raw)
 
 
 def op_fused(c: Compressed, via, op, axis: int = 0, box=None, stream=None, check: bool = True,
-             out: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+             out: torch.Tensor | None = None, ws: torch.Tensor | None = None, raw: bool = False):
     """Operation computed straight from the compressed stream through stage via."""
     lib = load()
     via = _STAGES.get(via, via)
@@ -358,7 +365,7 @@ def op_fused(c: Compressed, via, op, axis: int = 0, box=None, stream=None, check
                             _box(box, h.ndim), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream(stream))),
            "op_fused")
-    return _finish(buf, shape, h, op, ws, stream, check)
+    return _finish(buf, shape, h, op, ws, stream, check, raw)
 
 
 def from_bytes(data, device="cuda") -> Compressed:

@@ -194,6 +194,53 @@ def test_gradient_stage_routes(case, op):
                 assert np.all(got[want == 0] == 0)
 
 
+@pytest.mark.parametrize("op", ["deriv", "gradmag"])
+def test_gradient_fused_routes(case, op):
+    """Gradient straight from the compressed stream: via D_q (integers) and via
+    D_f (floats) against the oracle, as for the stage buffers."""
+    c = case["c"]
+    nd = len(case["shape"])
+    axes = range(nd) if op == "deriv" else [0]
+    for box in boxes_for(case["shape"], seed=nd * 17 + case["S"], count=3):
+        for ax in axes:
+            for route, via, base in (("int", hsz.QUANT, case["xh64"]), ("float", hsz.FLOAT, case["x_stored"])):
+                want = oracle.derivative(base, ax, box) if op == "deriv" else oracle.gradmag(base, box)
+                got = hsz.op_fused(c, via, op, axis=ax, box=box).cpu().numpy().astype(np.float64)
+                assert got.shape == want.shape
+                err = np.abs(got - want)
+                bad = err > _grad_tol(case, want, route)
+                assert not bad.any(), (route, ax, box, int(bad.sum()), float(err.max()))
+                assert np.all(got[want == 0] == 0)
+
+
+def test_fast_axis_derivative_on_deltas(case):
+    """Stage 2 (D_p): the derivative along the fast axis from p_j + p_{j+1}
+    and the block metadata, as a stage buffer and straight from the stream;
+    the other axes and the magnitude are not defined there."""
+    c = case["c"]
+    nd = len(case["shape"])
+    fast = nd - 1
+    dbuf = hsz.decompress_to_stage(c, hsz.DELTA)
+    for box in boxes_for(case["shape"], seed=nd * 19 + case["S"], count=4):
+        want = oracle.derivative(case["xh64"], fast, box)
+        for got in (hsz.op_on_stage(dbuf, c.header, hsz.DELTA, "deriv", axis=fast, box=box),
+                    hsz.op_fused(c, hsz.DELTA, "deriv", axis=fast, box=box)):
+            got = got.cpu().numpy().astype(np.float64)
+            err = np.abs(got - want)
+            bad = err > _grad_tol(case, want, "int")
+            assert not bad.any(), (box, int(bad.sum()), float(err.max()))
+            assert np.all(got[want == 0] == 0)
+        # identical to the integer route on D_q, bit for bit
+        qroute = hsz.op_fused(c, hsz.QUANT, "deriv", axis=fast, box=box).cpu().numpy()
+        assert np.array_equal(hsz.op_fused(c, hsz.DELTA, "deriv", axis=fast, box=box).cpu().numpy(), qroute)
+    for op, ax in (("gradmag", 0), ("deriv", 0)):
+        if op == "deriv" and nd == 1:
+            continue
+        with pytest.raises(hsz.HszError) as e:
+            hsz.op_fused(c, hsz.DELTA, op, axis=ax)
+        assert e.value.code == hsz.ERR_UNSUPPORTED
+
+
 def test_repeat_runs_identical(case):
     c = case["c"]
     a = hsz.op_fused(c, hsz.QUANT, "var")
