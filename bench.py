@@ -89,7 +89,8 @@ def main():
     qbuf = torch.empty(n * 4, dtype=torch.uint8, device=dev)
     fbuf = torch.empty(n * 4 + 64, dtype=torch.uint8, device=dev)
     dbuf = torch.empty(4 * (n + h.nb) + 64, dtype=torch.uint8, device=dev)
-    ws = [hsz.workspace(1 << 20, dev, key=f"bench{k}") for k in range(3)]
+    ws_bytes = max(hsz.op_workspace_bytes(h, op) for op in (hsz.MEAN, hsz.VAR, hsz.GRADMAG))
+    ws = [hsz.workspace(ws_bytes, dev, key=f"bench{k}") for k in range(3)]
 
     def timed(name, fns, steps, warmup):
         """Run the list of (label, fn(copy)) per step; per-label HIP event times."""

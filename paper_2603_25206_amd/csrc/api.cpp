@@ -133,6 +133,7 @@ int op_common(const hsz_header* h, int op, int axis, const hsz_box* box, uint64_
   } else {
     *axis3 = 0;
   }
+  if (op >= HSZ_DERIV && ws_bytes < hsz::grad_workspace_bytes(h->nb)) return HSZ_ERR_CAPACITY;
   const uint64_t esz = h->dtype == HSZ_F32 ? 4 : 8;
   const uint64_t need = (op <= HSZ_VAR) ? sizeof(hsz_stats) : esz * (uint64_t)t->box.volume();
   if (cap < need) return HSZ_ERR_CAPACITY;
@@ -308,7 +309,8 @@ int hsz_decompress_to_stage(const void* d_c, const hsz_header* h, int stage, voi
 
 int hsz_op_workspace(const hsz_header* h, int op, uint64_t* h_bytes) {
   if (!h || !h_bytes || op < HSZ_MEAN || op > HSZ_GRADMAG) return HSZ_ERR_INVALID_ARG;
-  *h_bytes = hsz::op_workspace_bytes();
+  uint64_t a = hsz::op_workspace_bytes(), b = hsz::grad_workspace_bytes(h->nb);
+  *h_bytes = (op >= HSZ_DERIV && b > a) ? b : a;
   return HSZ_OK;
 }
 

@@ -37,28 +37,78 @@ __device__ __forceinline__ void store_block(T* dst, const T (&v)[S], int len) {
 }
 
 // STAGE: 2, 3 or 4.  T: output element type (int32 for 2/3, float/double for 4).
+// 4-byte outputs leave through an LDS transpose: lane l writes its block's S
+// values to row l of a (64 x (S+1))-word tile (the +1 keeps the writes
+// conflict-free), then every lane reads four consecutive outputs of the
+// chunk and the wave stores 1 KB of contiguous memory per instruction.
 template <int S, int STAGE, typename T>
-__global__ void __launch_bounds__(kThreads) k_decode(StreamView v, int kmax, T* __restrict__ out,
+__global__ void __launch_bounds__(kThreads) k_decode(StreamView v, int kmax, int wave_words, T* __restrict__ out,
                                                     int32_t* __restrict__ out_q0, int* status) {
   extern __shared__ uint32_t smem[];
   const int wv = threadIdx.x / kWave;
-  uint32_t* tile = smem + wv * (kmax + 1) * kWave;
+  uint32_t* tile = smem + wv * wave_words;
   const int l = lane_id();
   const int64_t waves = (int64_t)gridDim.x * kWavesPerGroup;
   const double quantum = v.quantum;
+  constexpr bool kTranspose = sizeof(T) == 4;
   for (int64_t c = blockIdx.x * (int64_t)kWavesPerGroup + wv; c < v.nchunks; c += waves) {
     LaneBlock lb;
     stage_chunk<S>(v.width, v.q0, v.chunk_off, v.payload, v.payload_words, v.n, v.nb, c, tile, kmax, lb,
                    status);
-    if (lb.len == 0) continue;
     T vals[S];
     decode_lane_block<S>(tile + l, lb.w, lb.q0, [&](int j, int p, int q) {
       if constexpr (STAGE == 2) vals[j] = p;
       else if constexpr (STAGE == 3) vals[j] = q;
       else vals[j] = (T)dequant64(q, quantum);
     });
-    store_block<T, S>(out + lb.b * S, vals, lb.len);
-    if constexpr (STAGE == 2) out_q0[lb.b] = lb.q0;
+    if constexpr (STAGE == 2) {
+      if (lb.len > 0) out_q0[lb.b] = lb.q0;
+    }
+    if constexpr (kTranspose) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int j = 0; j < S; ++j) tile[l * (S + 1) + j] = __builtin_bit_cast(uint32_t, vals[j]);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const int64_t base = c * kChunkBlocks * S;
+      const bool full = base + (int64_t)kChunkBlocks * S <= v.n;
+#pragma unroll
+      for (int m = 0; m < S / 4; ++m) {
+        const int e = m * 4 * kWave + 4 * l;
+        const int a = (e / S) * (S + 1) + (e % S);
+        uint32_t w4[4] = {tile[a], tile[a + 1], tile[a + 2], tile[a + 3]};
+        if (full) {
+          typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+          *(u4*)((uint32_t*)out + base + e) = u4{w4[0], w4[1], w4[2], w4[3]};
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (base + e + u < v.n) ((uint32_t*)out)[base + e + u] = w4[u];
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    } else {
+      if (lb.len > 0) store_block<T, S>(out + lb.b * S, vals, lb.len);
+    }
+  }
+}
+
+// Per-block payload offsets relative to the block's chunk (16 bits: a chunk
+// holds at most 64 * 62 words), so that any block's words can be located
+// with two independent loads: chunk_off[b / 64] + rel[b].  One wave per chunk.
+template <int S>
+__global__ void __launch_bounds__(kThreads) k_block_index(StreamView v, uint16_t* __restrict__ rel) {
+  const int wv = threadIdx.x / kWave;
+  const int l = lane_id();
+  const int64_t waves = (int64_t)gridDim.x * kWavesPerGroup;
+  for (int64_t c = blockIdx.x * (int64_t)kWavesPerGroup + wv; c < v.nchunks; c += waves) {
+    const int64_t b = c * kChunkBlocks + l;
+    const int w = b < v.nb ? (int)v.width[b] : 0;
+    const int nw = block_words<S>(w < kMaxWidth ? w : kMaxWidth);
+    const int incl = wave_incl_scan(nw);
+    if (b < v.nb) rel[b] = (uint16_t)(incl - nw);
   }
 }
 
@@ -71,12 +121,14 @@ template <int S, int STAGE, typename T>
 hipError_t run(const StreamView& v, void* out, int* status, hipStream_t s) {
   const int wmax = max(1, 32 - __builtin_clz(2u * v.max_abs_q | 1u));
   const int kmax = tile_rows<S>(wmax > kMaxWidth ? kMaxWidth : wmax) - 1;
-  const size_t lds = (size_t)kWavesPerGroup * (kmax + 1) * kWave * sizeof(uint32_t);
+  int wave_words = (kmax + 1) * kWave;
+  if (sizeof(T) == 4 && wave_words < kWave * (S + 1)) wave_words = kWave * (S + 1);
+  const size_t lds = (size_t)kWavesPerGroup * wave_words * sizeof(uint32_t);
   const int64_t groups = (v.nchunks + kWavesPerGroup - 1) / kWavesPerGroup;
   const int grid = (int)(groups < 8192 ? groups : 8192);
   int32_t* q0out = (STAGE == 2) ? (int32_t*)out + v.n : nullptr;
-  hipLaunchKernelGGL((k_decode<S, STAGE, T>), dim3(grid), dim3(kThreads), lds, s, v, kmax, (T*)out, q0out,
-                     status);
+  hipLaunchKernelGGL((k_decode<S, STAGE, T>), dim3(grid), dim3(kThreads), lds, s, v, kmax, wave_words, (T*)out,
+                     q0out, status);
   return hipGetLastError();
 }
 
@@ -92,6 +144,14 @@ hipError_t dispatch(const StreamView& v, int stage, void* out, int* status, hipS
 }
 
 }  // namespace
+
+hipError_t launch_block_index(const StreamView& v, uint16_t* rel, hipStream_t s) {
+  const int64_t groups = (v.nchunks + kWavesPerGroup - 1) / kWavesPerGroup;
+  const unsigned grid = (unsigned)(groups < 8192 ? groups : 8192);
+  if (v.block == 32) hipLaunchKernelGGL(k_block_index<32>, dim3(grid), dim3(kThreads), 0, s, v, rel);
+  else hipLaunchKernelGGL(k_block_index<64>, dim3(grid), dim3(kThreads), 0, s, v, rel);
+  return hipGetLastError();
+}
 
 hipError_t launch_decode(const StreamView& v, int stage, void* out, int* status, hipStream_t s) {
   if (stage == 1) {

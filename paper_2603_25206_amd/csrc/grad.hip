@@ -39,16 +39,29 @@ __device__ __forceinline__ T fnum(T vm, T v0, T vp, int64_t i, int64_t L) {
   return (vp - vm) * T(0.5);
 }
 
-// value of a z/y/x-numerator triple -> output
+// square root: v_sqrt_f32 (within 1 ulp) for binary32, the IEEE one for binary64
+__device__ __forceinline__ float vsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+__device__ __forceinline__ double vsqrt(double a) { return sqrt(a); }
+
+// in-plane part of the squared magnitude, gy^2 + gx^2
+template <bool INT, typename T, typename N>
+__device__ __forceinline__ T sq_xy(N ny, N nx) {
+  const T gy = (T)ny, gx = (T)nx;
+  return gy * gy + gx * gx;
+}
+
+// a z/y/x-numerator triple -> output; the magnitude is sqrt(gz^2 + (gy^2 + gx^2))
 template <int OP, bool INT, typename T, typename N>
 __device__ __forceinline__ T finish(N nz, N ny, N nx, int axis, T h) {
-  if constexpr (INT) {
-    if constexpr (OP == 3) return (T)(axis == 0 ? nz : axis == 1 ? ny : nx) * h;
-    const T gz = (T)nz, gy = (T)ny, gx = (T)nx;
-    return sqrt(gz * gz + gy * gy + gx * gx) * h;
+  if constexpr (OP == 3) {
+    const N n = axis == 0 ? nz : axis == 1 ? ny : nx;
+    if constexpr (INT) return (T)n * h;
+    else return n;
   } else {
-    if constexpr (OP == 3) return axis == 0 ? nz : axis == 1 ? ny : nx;
-    return sqrt(nz * nz + ny * ny + nx * nx);
+    const T gz = (T)nz;
+    const T m = vsqrt(gz * gz + sq_xy<INT, T, N>(ny, nx));
+    if constexpr (INT) return m * h;
+    else return m;
   }
 }
 
@@ -78,25 +91,42 @@ __global__ void __launch_bounds__(kBufThreads) k_grad_buf(const void* __restrict
   const T h = (T)halfq;
   const bool need_z = OP == 4 || axis == 0, need_y = OP == 4 || axis == 1, need_x = OP == 4 || axis == 2;
   const V* col = src + y * sy + x;
+  using N = typename std::conditional<INT, int, T>::type;
+  constexpr int U = 4;  // planes per iteration: their loads are issued together
   V qm = z0 > 0 ? col[(z0 - 1) * sz] : V(0);
   V qc = col[z0 * sz];
-  for (int64_t z = z0; z < z1; ++z) {
-    const V qp = (z + 1 < d.z) ? col[(z + 1) * sz] : V(0);
-    const V* e = col + z * sz;
-    using N = typename std::conditional<INT, int, T>::type;
-    N nz = 0, ny = 0, nx = 0;
-    if constexpr (INT) {
-      if (need_z) nz = inum(qm, qc, qp, z, d.z);
-      if (need_y) ny = inum(y > 0 ? e[-sy] : 0, qc, y + 1 < d.y ? e[sy] : 0, y, d.y);
-      if (need_x) nx = inum(x > 0 ? e[-1] : 0, qc, x + 1 < d.x ? e[1] : 0, x, d.x);
-    } else {
-      if (need_z) nz = fnum<T>(qm, qc, qp, z, d.z);
-      if (need_y) ny = fnum<T>(y > 0 ? e[-sy] : T(0), qc, y + 1 < d.y ? e[sy] : T(0), y, d.y);
-      if (need_x) nx = fnum<T>(x > 0 ? e[-1] : T(0), qc, x + 1 < d.x ? e[1] : T(0), x, d.x);
+  for (int64_t zb = z0; zb < z1; zb += U) {
+    V qn[U], ym[U], yp[U], xm[U], xp[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t z = zb + u;
+      const bool in = z < z1;
+      qn[u] = (in && z + 1 < d.z) ? col[(z + 1) * sz] : V(0);
+      const V* e = col + z * sz;
+      ym[u] = (in && need_y && y > 0) ? e[-sy] : V(0);
+      yp[u] = (in && need_y && y + 1 < d.y) ? e[sy] : V(0);
+      xm[u] = (in && need_x && x > 0) ? e[-1] : V(0);
+      xp[u] = (in && need_x && x + 1 < d.x) ? e[1] : V(0);
     }
-    out[((z - b.z0) * by + (y - b.y0)) * bx + (x - b.x0)] = finish<OP, INT, T>(nz, ny, nx, axis, h);
-    qm = qc;
-    qc = qp;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t z = zb + u;
+      if (z < z1) {
+        N nz = 0, ny = 0, nx = 0;
+        if constexpr (INT) {
+          if (need_z) nz = inum(qm, qc, qn[u], z, d.z);
+          if (need_y) ny = inum(ym[u], qc, yp[u], y, d.y);
+          if (need_x) nx = inum(xm[u], qc, xp[u], x, d.x);
+        } else {
+          if (need_z) nz = fnum<T>(qm, qc, qn[u], z, d.z);
+          if (need_y) ny = fnum<T>(ym[u], qc, yp[u], y, d.y);
+          if (need_x) nx = fnum<T>(xm[u], qc, xp[u], x, d.x);
+        }
+        out[((z - b.z0) * by + (y - b.y0)) * bx + (x - b.x0)] = finish<OP, INT, T>(nz, ny, nx, axis, h);
+        qm = qc;
+        qc = qn[u];
+      }
+    }
   }
 }
 
@@ -107,19 +137,40 @@ constexpr int kFusedThreads = kTx;
 
 __device__ __forceinline__ int pidx(int r, int c) { return r * kPitch + c + (c >> 5); }
 
+// One workgroup: a tile of kTx columns x kTy rows, marching over tz planes.
+// Every decoded row's covering blocks get one thread each (decode items);
+// every tile column gets one thread (stencil).  Per plane p:
+//   A  each decode thread decodes its staged block of plane p into the LDS
+//      plane tile (its staging column is private, so no barrier is needed)
+//   -- barrier --
+//   B  it issues the payload loads of its block of plane p+1 into registers
+//      and the metadata loads (width, q0, offset) of plane p+2
+//   C  every stencil thread processes its column for all rows of plane p
+//      while those loads are in flight
+//   D  the prefetched words go to the staging column
+//   -- barrier --
+// so the global-memory latency of the next planes overlaps the stencil.
+// Block offsets come from the chunk table plus the per-block index 'rel'.
+// z-neighbours and the in-plane part of the previous plane stay in registers.
 template <int S, int VIA, int OP, typename T>
-__global__ void __launch_bounds__(kFusedThreads) k_grad_fused(StreamView v, Dims3 d, Box3 b, int axis, int tz,
-                                                              int kmax, double halfq, T* __restrict__ out,
-                                                              int* status) {
+__global__ void __launch_bounds__(kFusedThreads) k_grad_fused(StreamView v, const uint16_t* __restrict__ rel,
+                                                              Dims3 d, Box3 b, int axis, int tz, int kmax,
+                                                              double halfq, T* __restrict__ out, int* status) {
   using V = typename std::conditional<VIA == 3, int, T>::type;
   constexpr bool INT = VIA == 3;
   using N = typename std::conditional<INT, int, T>::type;
+  // per-row state from the previous plane: one in-plane numerator (a single
+  // derivative) or gy^2 + gx^2 (the magnitude)
+  using G = typename std::conditional<OP == 3, N, T>::type;
+  constexpr int NBR = (kCols + S - 2) / S + 1;  // max blocks covering one decoded row
+  constexpr int PF = 16 * (S / 32);             // payload words prefetched per thread
+  static_assert(kRows * NBR <= kFusedThreads, "one decode item per thread");
   extern __shared__ uint32_t smem[];
   V* plane = (V*)smem;
   uint32_t* stage = smem + (kRows * kPitch * sizeof(V) + 3) / 4;
   const int t = threadIdx.x;
 
-  const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0, bz = b.z1 - b.z0;
+  const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0;
   const int64_t ntx = (bx + kTx - 1) / kTx, nty = (by + kTy - 1) / kTy;
   int64_t blk = blockIdx.x;
   const int64_t tx = blk % ntx;
@@ -129,52 +180,116 @@ __global__ void __launch_bounds__(kFusedThreads) k_grad_fused(StreamView v, Dims
   const int64_t x0 = b.x0 + tx * kTx, y0 = b.y0 + ty * kTy, z0 = b.z0 + tzi * tz;
   const int xs = (int)min((int64_t)kTx, b.x1 - x0), ys = (int)min((int64_t)kTy, b.y1 - y0);
   const int64_t zs = min((int64_t)tz, b.z1 - z0);
-  // decoded window: columns [cA, cB), rows [rA, rB) of the field, planes [za, zb)
   const int64_t cA = max((int64_t)0, x0 - 1), cB = min(d.x, x0 + xs + 1);
   const int64_t rA = max((int64_t)0, y0 - 1), rB = min(d.y, y0 + ys + 1);
   const int64_t za = max((int64_t)0, z0 - 1), zb = min(d.z, z0 + zs + 1);
-  const int64_t per_row = (cB - cA + S - 2) / S + 1;
-  const int64_t items = (rB - rA) * per_row;
+  const int nrows = (int)(rB - rA);
   const double quantum = v.quantum;
   const T h = (T)halfq;
   const bool need_z = OP == 4 || axis == 0, need_y = OP == 4 || axis == 1, need_x = OP == 4 || axis == 2;
 
-  const int c = t + 1;  // this thread's LDS column; x = x0 + t
-  const int64_t x = x0 + t;
-  const bool active = t < xs;
-  V qm2[kTy], qm1[kTy];
-  N gx1[kTy], gy1[kTy];
-#pragma unroll
-  for (int i = 0; i < kTy; ++i) { qm2[i] = V(0); qm1[i] = V(0); gx1[i] = N(0); gy1[i] = N(0); }
+  // decode item of this thread: decoded row dr, dk-th block of the row
+  const int dr = t / NBR, dk = t % NBR;
+  const int64_t dy = rA + dr;
+  const bool decoder = dr < nrows;
+  V* prow = plane + (int)(dy - (y0 - 1)) * kPitch;
+  uint32_t* col = stage + t;
 
-  auto emit = [&](int64_t o, int i, N nz) {
-    const int64_t y = y0 + i;
-    out[((o - b.z0) * by + (y - b.y0)) * bx + (x - b.x0)] = finish<OP, INT, T>(nz, gy1[i], gx1[i], axis, h);
+  struct Meta {
+    int w, q0, words, e0;
+    uint64_t off;
+    bool valid;
+  };
+  // metadata of this thread's block in plane p (loads only; checked in use)
+  auto meta_of = [&](int64_t p) {
+    Meta m{0, 0, 0, 0, 0, false};
+    if (decoder && p < zb) {
+      const int64_t f = (p * d.y + dy) * d.x;
+      const int64_t bA = (f + cA) / S, bB = (f + cB - 1) / S, bk = bA + dk;
+      if (bk <= bB) {
+        m.valid = true;
+        m.w = (int)v.width[bk];
+        m.q0 = v.q0[bk];
+        m.off = v.chunk_off[bk / kChunkBlocks] + rel[bk];
+        m.e0 = (int)(bk * S - f);
+      }
+    }
+    return m;
+  };
+  auto check = [&](Meta& m) {
+    if (!m.valid) return;
+    m.words = block_words<S>(m.w);
+    if (m.w > kMaxWidth || m.words > kmax || m.off + (uint64_t)m.words > v.payload_words) {
+      record_status(status, kErrBadStream);
+      m.w = 0;
+      m.words = 0;
+    }
+  };
+  auto stage_rest = [&](const Meta& m, int from) {  // words [from, m.words) straight to LDS
+    const uint32_t* src = v.payload + m.off;
+    for (int k = from; k < m.words; ++k) col[k * kFusedThreads] = src[k];
+  };
+  auto decode = [&](const Meta& m) {
+    if (!m.valid) return;
+    const int cb = m.e0 - (int)(x0 - 1);  // LDS column of slot 0
+    const int ja = max(0, (int)(cA - m.e0)), jb = min(S, (int)(cB - m.e0));
+    decode_lane_block<S, kFusedThreads>(col, m.w, m.q0, [&](int j, int, int q) {
+      if (j >= ja && j < jb) {
+        const int cc = cb + j;
+        if constexpr (INT) prow[cc + (cc >> 5)] = q;
+        else prow[cc + (cc >> 5)] = (T)dequant64(q, quantum);
+      }
+    });
   };
 
-  for (int64_t p = za; p < zb; ++p) {
-    __syncthreads();  // the previous plane's stencil reads are done
-    for (int64_t it = t; it < items; it += kFusedThreads) {
-      const int64_t r = it / per_row, k = it % per_row;
-      const int64_t y = rA + r;
-      const int64_t f = (p * d.y + y) * d.x;
-      const int64_t blk_id = (f + cA) / S + k;
-      if (blk_id > (f + cB - 1) / S) continue;
-      int q0 = 0;
-      const int w = stage_block<S, kFusedThreads>(v.width, v.q0, v.chunk_off, v.payload, v.payload_words, v.nb,
-                                                   blk_id, stage + t, kmax, q0, status);
-      const int lr = (int)(y - (y0 - 1));
-      const int64_t e0 = blk_id * S - f;  // column of slot 0
-      decode_lane_block<S, kFusedThreads>(stage + t, w, q0, [&](int j, int, int q) {
-        const int64_t xx = e0 + j;
-        if (xx >= cA && xx < cB) {
-          const int cc = (int)(xx - (x0 - 1));
-          if constexpr (INT) plane[pidx(lr, cc)] = q;
-          else plane[pidx(lr, cc)] = (T)dequant64(q, quantum);
-        }
-      });
+  // stencil column of this thread
+  const int c = t + 1;
+  const int64_t x = x0 + t;
+  const bool active = t < xs;
+  const int ac = c + (c >> 5);              // LDS address of column c in row 0
+  const int am = (c - 1) + ((c - 1) >> 5);  // column c-1
+  const int ap = (c + 1) + ((c + 1) >> 5);  // column c+1
+  const bool xlo = x == 0, xhi = x == d.x - 1, xone = d.x < 2;
+  const int64_t obase = x - b.x0;
+
+  V qm2[kTy], qm1[kTy];
+  G g1[kTy];
+#pragma unroll
+  for (int i = 0; i < kTy; ++i) { qm2[i] = V(0); qm1[i] = V(0); g1[i] = G(0); }
+
+  auto emit = [&](int64_t o, int i, N nz) {
+    const int64_t row = ((o - b.z0) * by + (y0 + i - b.y0)) * bx;
+    T r;
+    if constexpr (OP == 3) {
+      if (axis == 0) r = INT ? (T)nz * h : (T)nz;
+      else r = INT ? (T)g1[i] * h : (T)g1[i];
+    } else {
+      const T gz = (T)nz;
+      const T m = vsqrt(gz * gz + g1[i]);
+      r = INT ? m * h : m;
     }
+    out[row + obase] = r;
+  };
+
+  // prologue: plane za staged, metadata of za+1 in flight
+  Meta cur = meta_of(za);
+  check(cur);
+  stage_rest(cur, 0);
+  Meta nxt = meta_of(za + 1);
+
+  for (int64_t p = za; p < zb; ++p) {
+    decode(cur);  // A
     __syncthreads();
+    // B: prefetch plane p+1's payload, request plane p+2's metadata
+    check(nxt);
+    uint32_t pw[PF];
+    {
+      const uint32_t* src = v.payload + nxt.off;
+#pragma unroll
+      for (int k = 0; k < PF; ++k) pw[k] = (k < nxt.words) ? src[k] : 0u;
+    }
+    const Meta nn = meta_of(p + 2);
+    // C: stencil on this thread's column
     if (active) {
       const int64_t o = p - 1;
       const bool out_prev = o >= z0 && o < z0 + zs;
@@ -183,16 +298,20 @@ __global__ void __launch_bounds__(kFusedThreads) k_grad_fused(StreamView v, Dims
         if (i < ys) {
           const int r = i + 1;
           const int64_t y = y0 + i;
-          const V qc = plane[pidx(r, c)];
+          const V qc = plane[r * kPitch + ac];
           N nx = 0, ny = 0;
-          if constexpr (INT) {
-            if (need_x) nx = inum(x > 0 ? plane[pidx(r, c - 1)] : 0, qc, x + 1 < d.x ? plane[pidx(r, c + 1)] : 0, x, d.x);
-            if (need_y) ny = inum(y > 0 ? plane[pidx(r - 1, c)] : 0, qc, y + 1 < d.y ? plane[pidx(r + 1, c)] : 0, y, d.y);
-          } else {
-            if (need_x)
-              nx = fnum<T>(x > 0 ? plane[pidx(r, c - 1)] : T(0), qc, x + 1 < d.x ? plane[pidx(r, c + 1)] : T(0), x, d.x);
-            if (need_y)
-              ny = fnum<T>(y > 0 ? plane[pidx(r - 1, c)] : T(0), qc, y + 1 < d.y ? plane[pidx(r + 1, c)] : T(0), y, d.y);
+          if (need_x) {
+            const V vm = plane[r * kPitch + am], vp = plane[r * kPitch + ap];
+            const V lo = xlo ? qc : vm, hi = xhi ? qc : vp;
+            if constexpr (INT) nx = xone ? 0 : (hi - lo) * ((xlo || xhi) ? 2 : 1);
+            else nx = xone ? T(0) : (xlo || xhi) ? hi - lo : (hi - lo) * T(0.5);
+          }
+          if (need_y) {
+            const bool ylo = y == 0, yhi = y == d.y - 1;
+            const V lo = ylo ? qc : plane[(r - 1) * kPitch + ac];
+            const V hi = yhi ? qc : plane[(r + 1) * kPitch + ac];
+            if constexpr (INT) ny = d.y < 2 ? 0 : (hi - lo) * ((ylo || yhi) ? 2 : 1);
+            else ny = d.y < 2 ? T(0) : (ylo || yhi) ? hi - lo : (hi - lo) * T(0.5);
           }
           if (out_prev) {
             N nz = 0;
@@ -204,11 +323,19 @@ __global__ void __launch_bounds__(kFusedThreads) k_grad_fused(StreamView v, Dims
           }
           qm2[i] = qm1[i];
           qm1[i] = qc;
-          gx1[i] = nx;
-          gy1[i] = ny;
+          if constexpr (OP == 3) g1[i] = axis == 1 ? ny : nx;
+          else g1[i] = sq_xy<INT, T, N>(ny, nx);
         }
       }
     }
+    // D: plane p+1's words into this thread's staging column
+#pragma unroll
+    for (int k = 0; k < PF; ++k)
+      if (k < nxt.words) col[k * kFusedThreads] = pw[k];
+    stage_rest(nxt, PF);
+    cur = nxt;
+    nxt = nn;
+    __syncthreads();
   }
   // the field's last plane has no plane after it: one-sided (or 0 if nz = 1)
   if (active && z0 + zs == zb) {
@@ -321,7 +448,7 @@ hipError_t run_buf(const void* buf, int op, int axis, const OpTarget& t, double 
   const int64_t bz = b.z1 - b.z0;
   // enough workgroups to fill the chip, long enough z runs to reuse the column registers
   int64_t tz = bz;
-  while (tz > 16 && ntx * nty * ((bz + tz - 1) / tz) < 4096) tz = (tz + 1) / 2;
+  while (tz > 16 && ntx * nty * ((bz + tz - 1) / tz) < 16384) tz = (tz + 1) / 2;
   const int64_t grid = ntx * nty * ((bz + tz - 1) / tz);
   if (op == 3)
     hipLaunchKernelGGL((k_grad_buf<SRC, 3, T>), dim3((unsigned)grid), dim3(kBufThreads), 0, s, buf, t.d, b, axis,
@@ -333,9 +460,13 @@ hipError_t run_buf(const void* buf, int op, int axis, const OpTarget& t, double 
 }
 
 template <int S, int VIA, typename T>
-hipError_t run_fused(const StreamView& v, int op, int axis, const OpTarget& t, void* out, int* status,
+hipError_t run_fused(const StreamView& v, int op, int axis, const OpTarget& t, void* out, uint8_t* ws,
                      hipStream_t s) {
   using V = typename std::conditional<VIA == 3, int, T>::type;
+  int* status = (int*)ws;
+  uint16_t* rel = (uint16_t*)(ws + kGradIndexOff);
+  hipError_t e = launch_block_index(v, rel, s);
+  if (e != hipSuccess) return e;
   const Box3& b = t.box;
   const int kmax = kmax_for(v);
   const size_t plane_bytes = ((kRows * kPitch * sizeof(V) + 3) / 4) * 4;
@@ -347,23 +478,23 @@ hipError_t run_fused(const StreamView& v, int op, int axis, const OpTarget& t, v
   const int64_t grid = ntx * nty * ((bz + tz - 1) / tz);
   const double halfq = 0.5 * v.quantum;
   if (op == 3)
-    hipLaunchKernelGGL((k_grad_fused<S, VIA, 3, T>), dim3((unsigned)grid), dim3(kFusedThreads), lds, s, v, t.d, b,
-                       axis, (int)tz, kmax, halfq, (T*)out, status);
+    hipLaunchKernelGGL((k_grad_fused<S, VIA, 3, T>), dim3((unsigned)grid), dim3(kFusedThreads), lds, s, v, rel, t.d,
+                       b, axis, (int)tz, kmax, halfq, (T*)out, status);
   else
-    hipLaunchKernelGGL((k_grad_fused<S, VIA, 4, T>), dim3((unsigned)grid), dim3(kFusedThreads), lds, s, v, t.d, b,
-                       axis, (int)tz, kmax, halfq, (T*)out, status);
+    hipLaunchKernelGGL((k_grad_fused<S, VIA, 4, T>), dim3((unsigned)grid), dim3(kFusedThreads), lds, s, v, rel, t.d,
+                       b, axis, (int)tz, kmax, halfq, (T*)out, status);
   return hipGetLastError();
 }
 
 template <int S>
-hipError_t fused_by_via(const StreamView& v, int via, int op, int axis, const OpTarget& t, void* out, int* status,
+hipError_t fused_by_via(const StreamView& v, int via, int op, int axis, const OpTarget& t, void* out, uint8_t* ws,
                         hipStream_t s) {
   if (via == 3)
-    return v.dtype == 1 ? run_fused<S, 3, float>(v, op, axis, t, out, status, s)
-                        : run_fused<S, 3, double>(v, op, axis, t, out, status, s);
+    return v.dtype == 1 ? run_fused<S, 3, float>(v, op, axis, t, out, ws, s)
+                        : run_fused<S, 3, double>(v, op, axis, t, out, ws, s);
   if (via == 4)
-    return v.dtype == 1 ? run_fused<S, 4, float>(v, op, axis, t, out, status, s)
-                        : run_fused<S, 4, double>(v, op, axis, t, out, status, s);
+    return v.dtype == 1 ? run_fused<S, 4, float>(v, op, axis, t, out, ws, s)
+                        : run_fused<S, 4, double>(v, op, axis, t, out, ws, s);
   return hipErrorNotSupported;
 }
 
@@ -400,6 +531,8 @@ hipError_t fast_delta(const int32_t* p, const StreamView& v, const OpTarget& t, 
 
 }  // namespace
 
+uint64_t grad_workspace_bytes(int64_t nb) { return kGradIndexOff + ((2 * (uint64_t)nb + 255) / 256) * 256; }
+
 hipError_t launch_grad_stage(const void* buf, int stage, const StreamView& v, int op, int axis3, const OpTarget& t,
                              void* result, uint8_t* ws, hipStream_t s) {
   const double halfq = 0.5 * v.quantum;
@@ -423,8 +556,8 @@ hipError_t launch_grad_fused(const StreamView& v, int via, int op, int axis3, co
     if (op != 3 || axis3 != 2) return hipErrorNotSupported;
     return fast_delta<true>(nullptr, v, t, result, status, s);
   }
-  return v.block == 32 ? fused_by_via<32>(v, via, op, axis3, t, result, status, s)
-                       : fused_by_via<64>(v, via, op, axis3, t, result, status, s);
+  return v.block == 32 ? fused_by_via<32>(v, via, op, axis3, t, result, ws, s)
+                       : fused_by_via<64>(v, via, op, axis3, t, result, ws, s);
 }
 
 }  // namespace hsz

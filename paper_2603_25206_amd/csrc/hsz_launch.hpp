@@ -60,11 +60,16 @@ hipError_t launch_compress(const CompressArgs& a, hipStream_t s);
 
 // ---- decompression -----------------------------------------------------------
 hipError_t launch_decode(const StreamView& v, int stage, void* out, int* status, hipStream_t s);
+// per-block payload offsets within their chunk (uint16[nb])
+hipError_t launch_block_index(const StreamView& v, uint16_t* rel, hipStream_t s);
 
 // ---- operations ----------------------------------------------------------------
 // Workspace: [0,256) status + scratch words, then per-workgroup partials.
 constexpr int kOpWorkgroups = 2048;  // max workgroups of a reduction launch
 uint64_t op_workspace_bytes();
+// gradient operations also keep a per-block offset index in the workspace
+uint64_t grad_workspace_bytes(int64_t nb);
+constexpr uint64_t kGradIndexOff = 256;
 
 struct OpTarget {
   Dims3 d;

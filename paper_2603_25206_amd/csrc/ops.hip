@@ -127,6 +127,134 @@ __global__ void __launch_bounds__(kThreads) k_stats_f(const T* __restrict__ x, R
   store_f64_partial(f1, f2, cnt, K, parts);
 }
 
+// ---- whole contiguous ranges: 16-byte loads, four in flight per thread ----------
+// Used when the box is one contiguous, 4-element-aligned flat range (the whole
+// field, or whole planes).  Elements [0, len) of 'src'.
+constexpr int kUnroll = 4;
+
+template <int OP>
+__global__ void __launch_bounds__(kThreads) k_stats_q_flat(const int32_t* __restrict__ q, int64_t len,
+                                                          Partial* parts) {
+  IntAcc acc;
+  typedef int32_t i4 __attribute__((ext_vector_type(4)));
+  const i4* v4 = (const i4*)q;
+  const int64_t nv = len / 4;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  for (; i + (kUnroll - 1) * stride < nv; i += kUnroll * stride) {
+    i4 t[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) t[u] = v4[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      acc.add(t[u].x, OP == 2); acc.add(t[u].y, OP == 2); acc.add(t[u].z, OP == 2); acc.add(t[u].w, OP == 2);
+    }
+  }
+  for (; i < nv; i += stride) {
+    const i4 t = v4[i];
+    acc.add(t.x, OP == 2); acc.add(t.y, OP == 2); acc.add(t.z, OP == 2); acc.add(t.w, OP == 2);
+  }
+  if (blockIdx.x == 0 && threadIdx.x < (len & 3)) acc.add(q[nv * 4 + threadIdx.x], OP == 2);
+  store_int_partial(acc, parts);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_stats_f_flat(const T* __restrict__ x, int64_t len, Partial* parts) {
+  constexpr int kPer = 16 / sizeof(T);
+  typedef T vt __attribute__((ext_vector_type(kPer)));
+  const double K = (double)x[0];
+  double f1 = 0.0, f2 = 0.0;
+  int64_t cnt = 0;
+  const vt* v = (const vt*)x;
+  const int64_t nv = len / kPer;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  auto add = [&](T val) {
+    const double e = (double)val - K;
+    f1 += e;
+    f2 += e * e;
+  };
+  int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  for (; i + (kUnroll - 1) * stride < nv; i += kUnroll * stride) {
+    vt t[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) t[u] = v[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) add(t[u][k]);
+    cnt += kUnroll * kPer;
+  }
+  for (; i < nv; i += stride) {
+    const vt t = v[i];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) add(t[k]);
+    cnt += kPer;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < (len % kPer)) {
+    add(x[nv * kPer + threadIdx.x]);
+    cnt += 1;
+  }
+  store_f64_partial(f1, f2, cnt, K, parts);
+}
+
+// Stage 2 over the whole field: thread i holds p[4i .. 4i+3] (one block is
+// S/4 consecutive threads).  Mean: sum_j (S_b - j) p_j per block plus
+// S_b q0_b (the q0 term is added by the thread holding slot 0).  Variance:
+// in-thread prefix, then an exclusive scan over the block's S/4 threads.
+template <int S, int OP>
+__global__ void __launch_bounds__(kThreads) k_stats_delta_flat(const int32_t* __restrict__ p,
+                                                              const int32_t* __restrict__ q0s, int64_t n,
+                                                              int64_t nb, Partial* parts) {
+  constexpr int G = S / 4;  // threads per block
+  IntAcc acc;
+  typedef int32_t i4 __attribute__((ext_vector_type(4)));
+  const i4* v4 = (const i4*)p;
+  const int64_t nvec = nb * G;  // vectors covering whole blocks (the tail is read element-wise)
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t base = blockIdx.x * (int64_t)kThreads; base < nvec; base += stride) {
+    const int64_t i = base + threadIdx.x;
+    const bool ok = i < nvec;
+    const int64_t b = i / G;
+    const int j0 = (int)(i % G) * 4;
+    const int64_t e0 = i * 4;
+    int t4[4] = {0, 0, 0, 0};
+    if (ok) {
+      if (e0 + 4 <= n) {
+        const i4 t = v4[i];
+        t4[0] = t.x; t4[1] = t.y; t4[2] = t.z; t4[3] = t.w;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t4[u] = (e0 + u < n) ? p[e0 + u] : 0;
+      }
+    }
+    const int sb = ok ? (int)min((int64_t)S, n - b * S) : 0;  // the block's valid length
+    const int q0 = (ok && j0 == 0) || OP == 2 ? (ok ? q0s[b] : 0) : 0;
+    if constexpr (OP == 1) {
+      int64_t s = (j0 == 0) ? (int64_t)sb * q0 : 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (j0 + u < sb) s += (int64_t)(sb - (j0 + u)) * t4[u];
+      acc.s1 += s;
+      acc.cnt += max(0, min(4, sb - j0));
+    } else {
+      int run = t4[0] + t4[1] + t4[2] + t4[3];
+      int incl = run;
+#pragma unroll
+      for (int d = 1; d < G; d <<= 1) {
+        const int o = __shfl_up(incl, d, G);
+        if ((int)(i % G) >= d) incl += o;
+      }
+      int q = q0 + incl - run;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        q += t4[u];
+        if (ok && j0 + u < sb) acc.add(q, true);
+      }
+    }
+  }
+  store_int_partial(acc, parts);
+}
+
 // Stage-2 statistics from a p buffer (p[n], q0[nb]).
 template <int S, int OP>
 __global__ void __launch_bounds__(kThreads) k_stats_delta(const int32_t* __restrict__ p,
@@ -366,11 +494,27 @@ hipError_t launch_stats_stage(const void* buf, int stage, const StreamView& v, i
                               void* result, uint8_t* ws, hipStream_t s) {
   Partial* parts = (Partial*)(ws + kPartialOff);
   const Rows rows = make_rows(t.d, t.box);
+  const bool contiguous = rows.count() == 1 && rows.base % 4 == 0;
+  const bool whole = contiguous && rows.base == 0 && rows.len == v.n;
   int grid = 1;
-  if (stage == 3) {
+  if (stage == 3 && contiguous) {
+    const int32_t* q = (const int32_t*)buf + rows.base;
+    grid = grid_for(rows.len / 4, kThreads * kUnroll);
+    if (op == 1) hipLaunchKernelGGL(k_stats_q_flat<1>, dim3(grid), dim3(kThreads), 0, s, q, rows.len, parts);
+    else hipLaunchKernelGGL(k_stats_q_flat<2>, dim3(grid), dim3(kThreads), 0, s, q, rows.len, parts);
+  } else if (stage == 3) {
     grid = grid_for(rows.count() * ((rows.len + kSeg - 1) / kSeg), 1);
     if (op == 1) hipLaunchKernelGGL(k_stats_q<1>, dim3(grid), dim3(kThreads), 0, s, (const int32_t*)buf, rows, parts);
     else hipLaunchKernelGGL(k_stats_q<2>, dim3(grid), dim3(kThreads), 0, s, (const int32_t*)buf, rows, parts);
+  } else if (stage == 4 && contiguous) {
+    const int per = v.dtype == 1 ? 4 : 2;
+    grid = grid_for(rows.len / per, kThreads * kUnroll);
+    if (v.dtype == 1)
+      hipLaunchKernelGGL(k_stats_f_flat<float>, dim3(grid), dim3(kThreads), 0, s, (const float*)buf + rows.base,
+                         rows.len, parts);
+    else
+      hipLaunchKernelGGL(k_stats_f_flat<double>, dim3(grid), dim3(kThreads), 0, s,
+                         (const double*)buf + rows.base, rows.len, parts);
   } else if (stage == 4) {
     grid = grid_for(rows.count() * ((rows.len + kSeg - 1) / kSeg), 1);
     if (v.dtype == 1)
@@ -380,7 +524,17 @@ hipError_t launch_stats_stage(const void* buf, int stage, const StreamView& v, i
   } else if (stage == 2) {
     const int32_t* p = (const int32_t*)buf;
     const int32_t* q0 = p + v.n;
-    if (v.block == 32) {
+    if (whole) {
+      const int G = v.block / 4;
+      grid = grid_for(v.nb * G, kThreads * 2);
+      if (v.block == 32) {
+        if (op == 1) hipLaunchKernelGGL((k_stats_delta_flat<32, 1>), dim3(grid), dim3(kThreads), 0, s, p, q0, v.n, v.nb, parts);
+        else hipLaunchKernelGGL((k_stats_delta_flat<32, 2>), dim3(grid), dim3(kThreads), 0, s, p, q0, v.n, v.nb, parts);
+      } else {
+        if (op == 1) hipLaunchKernelGGL((k_stats_delta_flat<64, 1>), dim3(grid), dim3(kThreads), 0, s, p, q0, v.n, v.nb, parts);
+        else hipLaunchKernelGGL((k_stats_delta_flat<64, 2>), dim3(grid), dim3(kThreads), 0, s, p, q0, v.n, v.nb, parts);
+      }
+    } else if (v.block == 32) {
       Segs<32> sg = make_segs<32>(rows);
       grid = grid_for(sg.count(), kThreads);
       if (op == 1) hipLaunchKernelGGL((k_stats_delta<32, 1>), dim3(grid), dim3(kThreads), 0, s, p, q0, sg, parts);

@@ -241,6 +241,14 @@ def compress(x: torch.Tensor, eb: float, rel: bool = True, block: int = 32, stre
     return Compressed(out, read_header(out))
 
 
+def op_workspace_bytes(h: Header, op) -> int:
+    lib = load()
+    op = _OPS.get(op, op)
+    wsb = ctypes.c_uint64()
+    _check(lib.hsz_op_workspace(ctypes.byref(h), op, ctypes.byref(wsb)), "op_workspace")
+    return wsb.value
+
+
 def stage_bytes(h: Header, stage: int) -> int:
     lib = load()
     out = ctypes.c_uint64()
@@ -336,9 +344,7 @@ def op_on_stage(stage_buf, h: Header, stage, op, axis: int = 0, box=None, stream
     if shape is None and op not in (MEAN, VAR):
         shape = h.shape if box is None else tuple(int(hi) - int(lo) for lo, hi in zip(*box))
     if ws is None:
-        wsb = ctypes.c_uint64()
-        _check(lib.hsz_op_workspace(ctypes.byref(h), op, ctypes.byref(wsb)), "op_workspace")
-        ws = workspace(wsb.value, dev)
+        ws = workspace(op_workspace_bytes(h, op), dev)
     _check(lib.hsz_op_on_stage(ctypes.c_void_p(base.data_ptr()), ctypes.byref(h), stage, op, axis,
                                _box(box, h.ndim), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream(stream))),
@@ -358,9 +364,7 @@ def op_fused(c: Compressed, via, op, axis: int = 0, box=None, stream=None, check
     if shape is None and op not in (MEAN, VAR):
         shape = h.shape if box is None else tuple(int(hi) - int(lo) for lo, hi in zip(*box))
     if ws is None:
-        wsb = ctypes.c_uint64()
-        _check(lib.hsz_op_workspace(ctypes.byref(h), op, ctypes.byref(wsb)), "op_workspace")
-        ws = workspace(wsb.value, dev)
+        ws = workspace(op_workspace_bytes(h, op), dev)
     _check(lib.hsz_op_fused(ctypes.c_void_p(c.data.data_ptr()), ctypes.byref(h), via, op, axis,
                             _box(box, h.ndim), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream(stream))),
