@@ -198,6 +198,55 @@ int hsz_op_fused(const void *d_c, const hsz_header *h, int via, int op, int axis
                  const hsz_box *h_box, void *d_result, uint64_t cap, void *d_workspace,
                  uint64_t workspace_bytes, void *stream);
 
+/* ---- batches: many fields, boxes and operations in one pass ------------------
+ * One persistent launch per kernel family works through a device table of
+ * (job, unit) pairs: statistics units are 64-block chunks (whole fields) or
+ * groups of 64 block segments (boxes); gradient units are tiles.  Statistics
+ * are accumulated as exact integers with 64-bit atomics, so every job's
+ * result is bit-identical to hsz_op_fused on the same stream, box and stage,
+ * whatever else is in the batch.  Supported: HSZ_MEAN / HSZ_VAR via
+ * HSZ_DELTA or HSZ_QUANT; HSZ_DERIV / HSZ_GRADMAG via HSZ_QUANT or
+ * HSZ_FLOAT.  Other combinations return HSZ_ERR_UNSUPPORTED. */
+typedef struct hsz_work {
+  const void *d_c;      /* compressed stream (device, 16-byte aligned)          */
+  const hsz_header *h;  /* its parsed header (host)                             */
+  int32_t op;           /* HSZ_MEAN, HSZ_VAR, HSZ_DERIV, HSZ_GRADMAG            */
+  int32_t via;          /* the stage held on chip (see above)                   */
+  int32_t axis;         /* HSZ_DERIV: axis in the field's own order             */
+  int32_t use_box;      /* 0: the whole field; 1: 'box'                         */
+  hsz_box box;
+  void *d_result;       /* hsz_stats, or the box-shaped result (16-byte aligned) */
+  uint64_t result_bytes;
+} hsz_work;
+
+/* Launch shape of a batch; zeros select the defaults. */
+typedef struct hsz_tuning {
+  int32_t stats_waves_per_cu;  /* statistics launch: waves per compute unit (8)   */
+  int32_t grad_groups_per_cu;  /* gradient launch: workgroups per compute unit (4) */
+  int32_t grad_tz;             /* planes per gradient tile (32)                    */
+  int32_t reserved;
+} hsz_tuning;
+
+/* Workspace a batch needs (bytes). */
+int hsz_batch_workspace(const hsz_work *h_items, int n, uint64_t *h_bytes);
+
+/* Validate, copy the work table into d_workspace and enqueue the pass. */
+int hsz_batch_run(const hsz_work *h_items, int n, const hsz_tuning *h_tune, void *d_workspace,
+                  uint64_t workspace_bytes, void *stream);
+
+/* A batch captured once as a HIP graph (table copy + kernels) and replayed.
+ * 'stream' must be a created (non-null) stream.  hsz_plan_update rewrites the
+ * table for a batch of the same structure (same jobs per kernel variant, no
+ * larger index or staging needs) -- new streams, boxes, axes and result
+ * buffers; it waits for the previous replay to have read the old table.
+ * The workspace belongs to the plan until hsz_plan_destroy. */
+typedef struct hsz_plan hsz_plan;
+int hsz_plan_create(const hsz_work *h_items, int n, const hsz_tuning *h_tune, void *d_workspace,
+                    uint64_t workspace_bytes, void *stream, hsz_plan **out);
+int hsz_plan_update(hsz_plan *plan, const hsz_work *h_items, int n);
+int hsz_plan_launch(hsz_plan *plan, void *stream);
+void hsz_plan_destroy(hsz_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

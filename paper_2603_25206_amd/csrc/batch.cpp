@@ -1,0 +1,430 @@
+// batch.cpp -- many jobs (fields, boxes, operations) in one pass of
+// persistent kernels, and replayable HIP-graph plans of such a pass.
+//
+// The host lays out a device work table in the caller's workspace:
+//   counts      int64 pairs (jobs, units) per kernel, read by the kernels
+//   stats jobs  per block size (32, 64): StatsJob[] + first unit of each job
+//   grad jobs   per kernel variant (S, via, op, dtype): GradJob[] + first tile
+//   index jobs  every gradient job again + its first chunk (offset index)
+//   acc         BatchAcc per statistics job (exact sums)
+//   rel         one 16-bit offset index per gradient job
+// then enqueues: reset -> offset index -> statistics -> gradients -> finalize.
+// Because job and unit counts are read from device memory, a captured graph
+// can be replayed after the table is rewritten for a batch of the same
+// structure (hsz_plan_update).
+#include <algorithm>
+#include <vector>
+
+#include "abi_util.hpp"
+
+namespace {
+
+using namespace hsz_abi;
+
+constexpr int kVariants = 16;  // S(2) x via(2) x op(2) x dtype(2)
+constexpr uint64_t kAlign = 256;
+
+uint64_t up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int variant_of(int S, int via, int op, int dtype) {
+  return ((S == 64) << 3) | ((via == HSZ_FLOAT) << 2) | ((op == HSZ_GRADMAG) << 1) | (dtype == HSZ_F64);
+}
+
+struct Layout {
+  uint64_t counts = 0;                   // int64[2 * (2 + kVariants + 1)]
+  uint64_t stats_jobs[2] = {0, 0}, stats_start[2] = {0, 0};
+  uint64_t grad_jobs[kVariants] = {}, grad_start[kVariants] = {};
+  uint64_t index_jobs = 0, index_start = 0;
+  uint64_t acc[2] = {0, 0};
+  uint64_t table_end = 0;                // [counts, table_end) is copied from the host
+  std::vector<uint64_t> rel;             // per gradient job (in input order)
+  uint64_t total = 0;
+};
+
+struct Item {
+  int kind;  // 0 stats, 1 gradient
+  int S, via, op, dtype, axis3;
+  hsz::StreamView v;
+  hsz::OpTarget t;
+  void* out;
+};
+
+// counts slots
+int cslot_stats(int si) { return si; }             // si: 0 (S=32), 1 (S=64)
+int cslot_grad(int var) { return 2 + var; }
+int cslot_index() { return 2 + kVariants; }
+constexpr int kCountSlots = 2 + kVariants + 1;
+
+// Validate one work item and classify it.
+int classify(const hsz_work& w, Item* it) {
+  const hsz_header* h = w.h;
+  int rc = check_header(h);
+  if (rc) return rc;
+  if (!w.d_c || ((uintptr_t)w.d_c & 15u) || !w.d_result) return HSZ_ERR_INVALID_ARG;
+  int64_t d3[3], n;
+  dims3_of(h->ndim, h->dims, d3, &n);
+  it->t.d = hsz::Dims3{d3[0], d3[1], d3[2]};
+  if (!box3_of(h, w.use_box ? &w.box : nullptr, &it->t.box)) return HSZ_ERR_INVALID_ARG;
+  it->S = h->block;
+  it->via = w.via;
+  it->op = w.op;
+  it->dtype = h->dtype;
+  it->v = view_of(w.d_c, h);
+  it->out = w.d_result;
+  if (w.op == HSZ_MEAN || w.op == HSZ_VAR) {
+    if (w.via != HSZ_DELTA && w.via != HSZ_QUANT) return HSZ_ERR_UNSUPPORTED;  // exact integer routes only
+    if (w.result_bytes < sizeof(hsz_stats)) return HSZ_ERR_CAPACITY;
+    it->kind = 0;
+    it->axis3 = 0;
+    return HSZ_OK;
+  }
+  if (w.op == HSZ_DERIV || w.op == HSZ_GRADMAG) {
+    if (w.via != HSZ_QUANT && w.via != HSZ_FLOAT) return HSZ_ERR_UNSUPPORTED;
+    if (w.op == HSZ_DERIV && (w.axis < 0 || w.axis >= h->ndim)) return HSZ_ERR_INVALID_ARG;
+    if ((uintptr_t)w.d_result & 15u) return HSZ_ERR_INVALID_ARG;
+    const uint64_t esz = h->dtype == HSZ_F32 ? 4 : 8;
+    if (w.result_bytes < esz * (uint64_t)it->t.box.volume()) return HSZ_ERR_CAPACITY;
+    it->kind = 1;
+    it->axis3 = w.op == HSZ_DERIV ? w.axis + 3 - h->ndim : 0;
+    return HSZ_OK;
+  }
+  return HSZ_ERR_INVALID_ARG;
+}
+
+struct Built {
+  Layout L;
+  std::vector<uint8_t> table;  // bytes [L.counts, L.table_end)
+  int stats_kmax[2] = {0, 0};
+  int grad_kmax[kVariants] = {};
+  int n_stats[2] = {0, 0};
+  int n_grad[kVariants] = {};
+  int n_index = 0;
+  int64_t stats_units[2] = {0, 0};
+  int64_t grad_tile_total[kVariants] = {};
+  int64_t index_chunks = 0;
+};
+
+int tz_for(const hsz::Box3& b, int want) {
+  const int64_t bz = b.z1 - b.z0;
+  int64_t tz = want > 0 ? want : 32;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tz, bz));
+}
+
+// Lay out and fill the table for 'items' in the workspace at d_ws.
+int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws, Built* B) {
+  Layout& L = B->L;
+  std::vector<int> order_stats[2], order_grad[kVariants];
+  std::vector<int> grads;
+  for (int i = 0; i < (int)items.size(); ++i) {
+    const Item& it = items[i];
+    if (it.kind == 0) order_stats[it.S == 64].push_back(i);
+    else {
+      order_grad[variant_of(it.S, it.via, it.op, it.dtype)].push_back(i);
+      grads.push_back(i);
+    }
+  }
+  uint64_t off = kAlign;  // [0, 256): status
+  L.counts = off;
+  off = up(off + sizeof(int64_t) * 2 * kCountSlots);
+  for (int si = 0; si < 2; ++si) {
+    L.stats_jobs[si] = off;
+    off = up(off + sizeof(hsz::StatsJob) * order_stats[si].size());
+    L.stats_start[si] = off;
+    off = up(off + sizeof(int64_t) * order_stats[si].size());
+  }
+  for (int g = 0; g < kVariants; ++g) {
+    L.grad_jobs[g] = off;
+    off = up(off + sizeof(hsz::GradJob) * order_grad[g].size());
+    L.grad_start[g] = off;
+    off = up(off + sizeof(int64_t) * order_grad[g].size());
+  }
+  L.index_jobs = off;
+  off = up(off + sizeof(hsz::GradJob) * grads.size());
+  L.index_start = off;
+  off = up(off + sizeof(int64_t) * grads.size());
+  L.table_end = off;
+  for (int si = 0; si < 2; ++si) {
+    L.acc[si] = off;
+    off = up(off + sizeof(hsz::BatchAcc) * order_stats[si].size());
+  }
+  L.rel.assign(items.size(), 0);
+  for (int i : grads) {
+    L.rel[i] = off;
+    off = up(off + 2 * (uint64_t)items[i].v.nb);
+  }
+  L.total = off;
+
+  B->table.assign(L.table_end - L.counts, 0);
+  auto at = [&](uint64_t o) { return B->table.data() + (o - L.counts); };
+  int64_t* counts = (int64_t*)at(L.counts);
+  for (int si = 0; si < 2; ++si) {
+    int64_t u = 0;
+    int km = 0;
+    for (size_t k = 0; k < order_stats[si].size(); ++k) {
+      const Item& it = items[order_stats[si][k]];
+      hsz::StatsJob J{};
+      J.v = it.v;
+      J.rows = hsz::make_rows(it.t.d, it.t.box);
+      J.whole = J.rows.count() == 1 && J.rows.base == 0 && J.rows.len == it.v.n;
+      J.per_row = (J.rows.len + it.S - 2) / it.S + 1;
+      J.op = it.op;
+      J.via = it.via;
+      J.out = it.out;
+      ((hsz::StatsJob*)at(L.stats_jobs[si]))[k] = J;
+      ((int64_t*)at(L.stats_start[si]))[k] = u;
+      u += J.whole ? it.v.nchunks : (J.rows.count() * J.per_row + hsz::kWave - 1) / hsz::kWave;
+      km = std::max(km, hsz::stats_kmax(it.v));
+    }
+    counts[2 * cslot_stats(si)] = (int64_t)order_stats[si].size();
+    counts[2 * cslot_stats(si) + 1] = u;
+    B->n_stats[si] = (int)order_stats[si].size();
+    B->stats_units[si] = u;
+    B->stats_kmax[si] = km;
+  }
+  std::vector<hsz::GradJob> gj(items.size());
+  for (int i : grads) {
+    const Item& it = items[i];
+    hsz::GradJob J{};
+    J.v = it.v;
+    J.rel = (const uint16_t*)(d_ws + L.rel[i]);
+    J.d = it.t.d;
+    J.b = it.t.box;
+    J.axis = it.axis3;
+    J.tz = tz_for(it.t.box, tune.grad_tz);
+    J.kmax = hsz::grad_kmax(it.v);
+    J.halfq = 0.5 * it.v.quantum;
+    J.out = it.out;
+    gj[i] = J;
+  }
+  for (int g = 0; g < kVariants; ++g) {
+    int64_t tiles = 0;
+    int km = 0;
+    for (size_t k = 0; k < order_grad[g].size(); ++k) {
+      const hsz::GradJob& J = gj[order_grad[g][k]];
+      ((hsz::GradJob*)at(L.grad_jobs[g]))[k] = J;
+      ((int64_t*)at(L.grad_start[g]))[k] = tiles;
+      tiles += hsz::grad_tiles(J.b, J.tz);
+      km = std::max(km, J.kmax);
+    }
+    counts[2 * cslot_grad(g)] = (int64_t)order_grad[g].size();
+    counts[2 * cslot_grad(g) + 1] = tiles;
+    B->n_grad[g] = (int)order_grad[g].size();
+    B->grad_tile_total[g] = tiles;
+    B->grad_kmax[g] = km;
+  }
+  int64_t chunks = 0;
+  for (size_t k = 0; k < grads.size(); ++k) {
+    ((hsz::GradJob*)at(L.index_jobs))[k] = gj[grads[k]];
+    ((int64_t*)at(L.index_start))[k] = chunks;
+    chunks += items[grads[k]].v.nchunks;
+  }
+  counts[2 * cslot_index()] = (int64_t)grads.size();
+  counts[2 * cslot_index() + 1] = chunks;
+  B->n_index = (int)grads.size();
+  B->index_chunks = chunks;
+  return HSZ_OK;
+}
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+  return cus;
+}
+
+// Enqueue the kernels of a built batch ('kmax' values fix the LDS sizes).
+int enqueue(const Built& B, uint8_t* d_ws, const hsz_tuning& tune, hipStream_t s) {
+  const Layout& L = B.L;
+  const int64_t* counts = (const int64_t*)(d_ws + L.counts);
+  int* status = (int*)d_ws;
+  const int cus = device_cus();
+  const int stats_grid = std::max(1, cus * (tune.stats_waves_per_cu > 0 ? tune.stats_waves_per_cu : 8) / 4);
+  const int grad_grid = std::max(1, cus * (tune.grad_groups_per_cu > 0 ? tune.grad_groups_per_cu : 4));
+  hipError_t e;
+  for (int si = 0; si < 2; ++si) {
+    // every batch resets its accumulators (a small kernel: no memset nodes in graphs)
+    if ((e = hsz::launch_batch_reset((hsz::BatchAcc*)(d_ws + L.acc[si]), B.n_stats[si], status, s)) != hipSuccess)
+      return hip_fail(e);
+  }
+  if (B.n_index > 0) {
+    if ((e = hsz::launch_batch_block_index((const hsz::GradJob*)(d_ws + L.index_jobs),
+                                           (const int64_t*)(d_ws + L.index_start), counts + 2 * cslot_index(),
+                                           std::max(1, cus * 8), s)) != hipSuccess)
+      return hip_fail(e);
+  }
+  for (int si = 0; si < 2; ++si) {
+    if (B.n_stats[si] == 0) continue;
+    if ((e = hsz::launch_batch_stats(si ? 64 : 32, (const hsz::StatsJob*)(d_ws + L.stats_jobs[si]),
+                                     (const int64_t*)(d_ws + L.stats_start[si]), counts + 2 * cslot_stats(si),
+                                     B.stats_kmax[si], (hsz::BatchAcc*)(d_ws + L.acc[si]), status, stats_grid, s)) !=
+        hipSuccess)
+      return hip_fail(e);
+  }
+  for (int g = 0; g < kVariants; ++g) {
+    if (B.n_grad[g] == 0) continue;
+    const int S = (g >> 3) ? 64 : 32, via = ((g >> 2) & 1) ? HSZ_FLOAT : HSZ_QUANT;
+    const int op = ((g >> 1) & 1) ? HSZ_GRADMAG : HSZ_DERIV, dtype = (g & 1) ? HSZ_F64 : HSZ_F32;
+    if ((e = hsz::launch_batch_grad(S, via, op, dtype, (const hsz::GradJob*)(d_ws + L.grad_jobs[g]),
+                                    (const int64_t*)(d_ws + L.grad_start[g]), counts + 2 * cslot_grad(g),
+                                    B.grad_kmax[g], grad_grid, status, s)) != hipSuccess)
+      return hip_fail(e);
+  }
+  for (int si = 0; si < 2; ++si) {
+    if (B.n_stats[si] == 0) continue;
+    if ((e = hsz::launch_batch_finalize((const hsz::StatsJob*)(d_ws + L.stats_jobs[si]), counts + 2 * cslot_stats(si),
+                                        (const hsz::BatchAcc*)(d_ws + L.acc[si]), B.n_stats[si], s)) != hipSuccess)
+      return hip_fail(e);
+  }
+  return HSZ_OK;
+}
+
+int collect(const hsz_work* items, int n, std::vector<Item>* out) {
+  if (!items || n <= 0) return HSZ_ERR_INVALID_ARG;
+  out->resize(n);
+  for (int i = 0; i < n; ++i) {
+    int rc = classify(items[i], &(*out)[i]);
+    if (rc) return rc;
+  }
+  return HSZ_OK;
+}
+
+}  // namespace
+
+struct hsz_plan {
+  Built built;
+  hsz_tuning tune;
+  uint8_t* d_ws = nullptr;
+  uint64_t ws_bytes = 0;
+  void* h_table = nullptr;  // pinned copy of the table, read by the graph's copy node
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  bool launched = false;
+};
+
+extern "C" {
+
+int hsz_batch_workspace(const hsz_work* items, int n, uint64_t* h_bytes) {
+  if (!h_bytes) return HSZ_ERR_INVALID_ARG;
+  std::vector<Item> its;
+  int rc = collect(items, n, &its);
+  if (rc) return rc;
+  Built B;
+  hsz_tuning t{};
+  build(its, t, nullptr, &B);
+  *h_bytes = B.L.total;
+  return HSZ_OK;
+}
+
+int hsz_batch_run(const hsz_work* items, int n, const hsz_tuning* tune, void* d_workspace, uint64_t workspace_bytes,
+                  void* stream) {
+  std::vector<Item> its;
+  int rc = collect(items, n, &its);
+  if (rc) return rc;
+  if (!d_workspace || ((uintptr_t)d_workspace & 15u)) return HSZ_ERR_INVALID_ARG;
+  hsz_tuning t = tune ? *tune : hsz_tuning{};
+  Built B;
+  build(its, t, (uint8_t*)d_workspace, &B);
+  if (workspace_bytes < B.L.total) return HSZ_ERR_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync((uint8_t*)d_workspace + B.L.counts, B.table.data(), B.table.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e);
+  return enqueue(B, (uint8_t*)d_workspace, t, s);
+}
+
+int hsz_plan_create(const hsz_work* items, int n, const hsz_tuning* tune, void* d_workspace, uint64_t workspace_bytes,
+                    void* stream, hsz_plan** out) {
+  if (!out || !stream) return HSZ_ERR_INVALID_ARG;  // capture needs a created stream
+  *out = nullptr;
+  std::vector<Item> its;
+  int rc = collect(items, n, &its);
+  if (rc) return rc;
+  if (!d_workspace || ((uintptr_t)d_workspace & 15u)) return HSZ_ERR_INVALID_ARG;
+  hsz_plan* p = new hsz_plan();
+  p->tune = tune ? *tune : hsz_tuning{};
+  p->d_ws = (uint8_t*)d_workspace;
+  p->ws_bytes = workspace_bytes;
+  build(its, p->tune, p->d_ws, &p->built);
+  if (workspace_bytes < p->built.L.total) {
+    delete p;
+    return HSZ_ERR_CAPACITY;
+  }
+  hipError_t e = hipHostMalloc(&p->h_table, p->built.table.size(), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e);
+  }
+  memcpy(p->h_table, p->built.table.data(), p->built.table.size());
+  hipStream_t s = (hipStream_t)stream;
+  if ((e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming)) != hipSuccess) {
+    hsz_plan_destroy(p);
+    return hip_fail(e);
+  }
+  if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+    hsz_plan_destroy(p);
+    return hip_fail(e);
+  }
+  e = hipMemcpyAsync(p->d_ws + p->built.L.counts, p->h_table, p->built.table.size(), hipMemcpyHostToDevice, s);
+  int erc = (e == hipSuccess) ? enqueue(p->built, p->d_ws, p->tune, s) : hip_fail(e);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(s, &g);
+  if (erc != HSZ_OK || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    hsz_plan_destroy(p);
+    return erc != HSZ_OK ? erc : hip_fail(e2);
+  }
+  p->graph = g;
+  if ((e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+    hsz_plan_destroy(p);
+    return hip_fail(e);
+  }
+  *out = p;
+  return HSZ_OK;
+}
+
+int hsz_plan_update(hsz_plan* p, const hsz_work* items, int n) {
+  if (!p) return HSZ_ERR_INVALID_ARG;
+  std::vector<Item> its;
+  int rc = collect(items, n, &its);
+  if (rc) return rc;
+  Built B;
+  build(its, p->tune, p->d_ws, &B);
+  // the captured launches fix the table layout, the kernel variants and the
+  // LDS sizes: a new batch must have the same structure and fit them
+  const Built& A = p->built;
+  bool same = B.L.total <= p->ws_bytes && B.table.size() == A.table.size() && B.n_index == A.n_index;
+  for (int si = 0; si < 2 && same; ++si)
+    same = B.n_stats[si] == A.n_stats[si] && B.stats_kmax[si] <= A.stats_kmax[si] && B.L.acc[si] == A.L.acc[si];
+  for (int g = 0; g < kVariants && same; ++g) same = B.n_grad[g] == A.n_grad[g] && B.grad_kmax[g] <= A.grad_kmax[g];
+  for (size_t i = 0; i < B.L.rel.size() && same; ++i) same = B.L.rel[i] == A.L.rel[i];
+  if (!same) return HSZ_ERR_UNSUPPORTED;
+  if (p->launched) {
+    hipError_t e = hipEventSynchronize(p->done);  // the last replay has read the table
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  memcpy(p->h_table, B.table.data(), B.table.size());
+  return HSZ_OK;
+}
+
+int hsz_plan_launch(hsz_plan* p, void* stream) {
+  if (!p || !p->exec) return HSZ_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipGraphLaunch(p->exec, s);
+  if (e != hipSuccess) return hip_fail(e);
+  if ((e = hipEventRecord(p->done, s)) != hipSuccess) return hip_fail(e);
+  p->launched = true;
+  return HSZ_OK;
+}
+
+void hsz_plan_destroy(hsz_plan* p) {
+  if (!p) return;
+  if (p->launched && p->done) (void)hipEventSynchronize(p->done);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->done) (void)hipEventDestroy(p->done);
+  if (p->h_table) (void)hipHostFree(p->h_table);
+  delete p;
+}
+
+}  // extern "C"

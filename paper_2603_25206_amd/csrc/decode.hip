@@ -112,6 +112,33 @@ __global__ void __launch_bounds__(kThreads) k_block_index(StreamView v, uint16_t
   }
 }
 
+// The same index for every gradient job of a batch: units are the chunks of
+// all jobs (counts[0] jobs, counts[1] chunks in total).
+__global__ void __launch_bounds__(kThreads) k_batch_block_index(const GradJob* __restrict__ jobs,
+                                                               const int64_t* __restrict__ chunk_start,
+                                                               const int64_t* __restrict__ counts) {
+  const int wv = threadIdx.x / kWave;
+  const int l = lane_id();
+  const int n = (int)counts[0];
+  const int64_t total = counts[1];
+  const int64_t waves = (int64_t)gridDim.x * kWavesPerGroup;
+  for (int64_t u = blockIdx.x * (int64_t)kWavesPerGroup + wv; u < total; u += waves) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (chunk_start[mid] <= u) lo = mid;
+      else hi = mid - 1;
+    }
+    const GradJob& J = jobs[lo];
+    const int64_t b = (u - chunk_start[lo]) * kChunkBlocks + l;
+    const int w = b < J.v.nb ? (int)J.v.width[b] : 0;
+    const int wc = w < kMaxWidth ? w : kMaxWidth;
+    const int nw = wc ? (J.v.block / 32) * (1 + wc) : 0;
+    const int incl = wave_incl_scan(nw);
+    if (b < J.v.nb) ((uint16_t*)J.rel)[b] = (uint16_t)(incl - nw);
+  }
+}
+
 __global__ void k_copy_q0(const int32_t* __restrict__ q0, int64_t nb, int32_t* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x)
     out[i] = q0[i];
@@ -150,6 +177,12 @@ hipError_t launch_block_index(const StreamView& v, uint16_t* rel, hipStream_t s)
   const unsigned grid = (unsigned)(groups < 8192 ? groups : 8192);
   if (v.block == 32) hipLaunchKernelGGL(k_block_index<32>, dim3(grid), dim3(kThreads), 0, s, v, rel);
   else hipLaunchKernelGGL(k_block_index<64>, dim3(grid), dim3(kThreads), 0, s, v, rel);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_block_index(const GradJob* jobs, const int64_t* chunk_start, const int64_t* counts, int grid,
+                                    hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_block_index, dim3(grid), dim3(kThreads), 0, s, jobs, chunk_start, counts);
   return hipGetLastError();
 }
 

@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(kBufThreads) k_grad_buf(const void* __restrict
   using V = typename std::conditional<SRC == 3, int, T>::type;
   constexpr bool INT = SRC == 3;
   const V* src = (const V*)in;
-  const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0, bz = b.z1 - b.z0;
+  const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0;
   const int64_t ntx = (bx + kBx - 1) / kBx, nty = (by + kBy - 1) / kBy;
   int64_t blk = blockIdx.x;
   const int64_t tx = blk % ntx;
@@ -153,9 +153,14 @@ __device__ __forceinline__ int pidx(int r, int c) { return r * kPitch + c + (c >
 // Block offsets come from the chunk table plus the per-block index 'rel'.
 // z-neighbours and the in-plane part of the previous plane stay in registers.
 template <int S, int VIA, int OP, typename T>
-__global__ void __launch_bounds__(kFusedThreads) k_grad_fused(StreamView v, const uint16_t* __restrict__ rel,
-                                                              Dims3 d, Box3 b, int axis, int tz, int kmax,
-                                                              double halfq, T* __restrict__ out, int* status) {
+__device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint32_t* smem, int* status) {
+  const StreamView& v = job.v;
+  const uint16_t* __restrict__ rel = job.rel;
+  const Dims3 d = job.d;
+  const Box3 b = job.b;
+  const int axis = job.axis, tz = job.tz, kmax = job.kmax;
+  const double halfq = job.halfq;
+  T* __restrict__ out = (T*)job.out;
   using V = typename std::conditional<VIA == 3, int, T>::type;
   constexpr bool INT = VIA == 3;
   using N = typename std::conditional<INT, int, T>::type;
@@ -165,14 +170,13 @@ __global__ void __launch_bounds__(kFusedThreads) k_grad_fused(StreamView v, cons
   constexpr int NBR = (kCols + S - 2) / S + 1;  // max blocks covering one decoded row
   constexpr int PF = 16 * (S / 32);             // payload words prefetched per thread
   static_assert(kRows * NBR <= kFusedThreads, "one decode item per thread");
-  extern __shared__ uint32_t smem[];
   V* plane = (V*)smem;
   uint32_t* stage = smem + (kRows * kPitch * sizeof(V) + 3) / 4;
   const int t = threadIdx.x;
 
   const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0;
   const int64_t ntx = (bx + kTx - 1) / kTx, nty = (by + kTy - 1) / kTy;
-  int64_t blk = blockIdx.x;
+  int64_t blk = tile;
   const int64_t tx = blk % ntx;
   blk /= ntx;
   const int64_t ty = blk % nty;
@@ -354,6 +358,33 @@ __global__ void __launch_bounds__(kFusedThreads) k_grad_fused(StreamView v, cons
   }
 }
 
+template <int S, int VIA, int OP, typename T>
+__global__ void __launch_bounds__(kFusedThreads) k_grad_fused(GradJob job, int* status) {
+  extern __shared__ uint32_t smem[];
+  grad_tile<S, VIA, OP, T>(job, blockIdx.x, smem, status);
+}
+
+// Persistent batch: the tiles of every job of one kernel variant, listed in
+// a device table (count and tile offsets read from device memory, so a
+// captured graph can be replayed with a new table).
+template <int S, int VIA, int OP, typename T>
+__global__ void __launch_bounds__(kFusedThreads) k_batch_grad(const GradJob* __restrict__ jobs,
+                                                              const int64_t* __restrict__ tile_start,
+                                                              const int64_t* __restrict__ counts, int* status) {
+  extern __shared__ uint32_t smem[];
+  const int n = (int)counts[0];
+  const int64_t total = counts[1];
+  for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    int lo = 0, hi = n - 1;  // last job whose first tile is <= tile
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (tile_start[mid] <= tile) lo = mid;
+      else hi = mid - 1;
+    }
+    grad_tile<S, VIA, OP, T>(jobs[lo], tile - tile_start[lo], smem, status);
+  }
+}
+
 // ---- stage 2 (D_p): derivative along the fast axis, no recorrelation -----------
 // Inside a block the central difference is q_{j+1} - q_{j-1} = p_j + p_{j+1}
 // (p_j = q_j - q_{j-1}).  At a block edge the missing neighbour comes from
@@ -476,13 +507,11 @@ hipError_t run_fused(const StreamView& v, int op, int axis, const OpTarget& t, v
   int64_t tz = bz;
   while (tz > 8 && ntx * nty * ((bz + tz - 1) / tz) < 1024) tz = (tz + 1) / 2;
   const int64_t grid = ntx * nty * ((bz + tz - 1) / tz);
-  const double halfq = 0.5 * v.quantum;
+  GradJob job{v, rel, t.d, b, axis, (int)tz, kmax, 0.5 * v.quantum, out};
   if (op == 3)
-    hipLaunchKernelGGL((k_grad_fused<S, VIA, 3, T>), dim3((unsigned)grid), dim3(kFusedThreads), lds, s, v, rel, t.d,
-                       b, axis, (int)tz, kmax, halfq, (T*)out, status);
+    hipLaunchKernelGGL((k_grad_fused<S, VIA, 3, T>), dim3((unsigned)grid), dim3(kFusedThreads), lds, s, job, status);
   else
-    hipLaunchKernelGGL((k_grad_fused<S, VIA, 4, T>), dim3((unsigned)grid), dim3(kFusedThreads), lds, s, v, rel, t.d,
-                       b, axis, (int)tz, kmax, halfq, (T*)out, status);
+    hipLaunchKernelGGL((k_grad_fused<S, VIA, 4, T>), dim3((unsigned)grid), dim3(kFusedThreads), lds, s, job, status);
   return hipGetLastError();
 }
 
@@ -529,9 +558,55 @@ hipError_t fast_delta(const int32_t* p, const StreamView& v, const OpTarget& t, 
                       : run_fast_delta<64, FROM_STREAM, double>(p, v, t, out, status, s);
 }
 
+size_t grad_lds_bytes(int dtype, int via, int kmax) {
+  const size_t vsz = (via == 4 && dtype == 2) ? 8 : 4;
+  return ((kRows * kPitch * vsz + 3) / 4) * 4 + (size_t)(kmax + 1) * kFusedThreads * sizeof(uint32_t);
+}
+
+template <int S, int VIA, int OP, typename T>
+hipError_t batch_grad_v(const GradJob* jobs, const int64_t* tile_start, const int64_t* counts, int kmax, int grid,
+                        int* status, hipStream_t s) {
+  const size_t lds = grad_lds_bytes(sizeof(T) == 4 ? 1 : 2, VIA, kmax);
+  hipLaunchKernelGGL((k_batch_grad<S, VIA, OP, T>), dim3(grid), dim3(kFusedThreads), lds, s, jobs, tile_start, counts,
+                     status);
+  return hipGetLastError();
+}
+
+template <int S, int VIA, int OP>
+hipError_t batch_grad_t(int dtype, const GradJob* jobs, const int64_t* tile_start, const int64_t* counts, int kmax,
+                        int grid, int* status, hipStream_t s) {
+  return dtype == 1 ? batch_grad_v<S, VIA, OP, float>(jobs, tile_start, counts, kmax, grid, status, s)
+                    : batch_grad_v<S, VIA, OP, double>(jobs, tile_start, counts, kmax, grid, status, s);
+}
+
+template <int S>
+hipError_t batch_grad_s(int via, int op, int dtype, const GradJob* jobs, const int64_t* tile_start,
+                        const int64_t* counts, int kmax, int grid, int* status, hipStream_t s) {
+  if (via == 3)
+    return op == 3 ? batch_grad_t<S, 3, 3>(dtype, jobs, tile_start, counts, kmax, grid, status, s)
+                   : batch_grad_t<S, 3, 4>(dtype, jobs, tile_start, counts, kmax, grid, status, s);
+  return op == 3 ? batch_grad_t<S, 4, 3>(dtype, jobs, tile_start, counts, kmax, grid, status, s)
+                 : batch_grad_t<S, 4, 4>(dtype, jobs, tile_start, counts, kmax, grid, status, s);
+}
+
 }  // namespace
 
 uint64_t grad_workspace_bytes(int64_t nb) { return kGradIndexOff + ((2 * (uint64_t)nb + 255) / 256) * 256; }
+
+size_t batch_grad_lds(int dtype, int via, int kmax) { return grad_lds_bytes(dtype, via, kmax); }
+
+hipError_t launch_batch_grad(int S, int via, int op, int dtype, const GradJob* jobs, const int64_t* tile_start,
+                             const int64_t* counts, int kmax, int grid, int* status, hipStream_t s) {
+  return S == 32 ? batch_grad_s<32>(via, op, dtype, jobs, tile_start, counts, kmax, grid, status, s)
+                 : batch_grad_s<64>(via, op, dtype, jobs, tile_start, counts, kmax, grid, status, s);
+}
+
+int grad_tiles(const Box3& b, int tz) {
+  const int64_t ntx = (b.x1 - b.x0 + kTx - 1) / kTx, nty = (b.y1 - b.y0 + kTy - 1) / kTy;
+  return (int)(ntx * nty * ((b.z1 - b.z0 + tz - 1) / tz));
+}
+
+int grad_kmax(const StreamView& v) { return kmax_for(v); }
 
 hipError_t launch_grad_stage(const void* buf, int stage, const StreamView& v, int op, int axis3, const OpTarget& t,
                              void* result, uint8_t* ws, hipStream_t s) {

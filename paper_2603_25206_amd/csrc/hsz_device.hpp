@@ -91,14 +91,6 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
 }
 
 // ---- row sets and block segments (boxes) -------------------------------------
-// A set of contiguous flat ranges ("rows"): row r = iz*nry + iy starts at
-// base + iz*sz + iy*sy and has len elements.
-struct Rows {
-  int64_t nrz, nry, len, base, sz, sy;
-  __host__ __device__ int64_t count() const { return nrz * nry; }
-  __device__ int64_t start(int64_t r) const { return base + (r / nry) * sz + (r % nry) * sy; }
-};
-
 inline Rows make_rows(const Dims3& d, const Box3& b) {
   Rows r;
   const int64_t plane = d.y * d.x;

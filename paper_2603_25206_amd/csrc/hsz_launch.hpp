@@ -76,11 +76,60 @@ struct OpTarget {
   Box3 box;
 };
 
+// ---- batches -----------------------------------------------------------------------
+// A set of contiguous flat ranges ("rows"): row r = iz*nry + iy starts at
+// base + iz*sz + iy*sy and has len elements.
+struct Rows {
+  int64_t nrz, nry, len, base, sz, sy;
+  __host__ __device__ int64_t count() const { return nrz * nry; }
+  __device__ int64_t start(int64_t r) const { return base + (r / nry) * sz + (r % nry) * sy; }
+};
+
+// One statistics job of a batch (integer routes only).
+struct StatsJob {
+  StreamView v;
+  Rows rows;        // the box as contiguous rows
+  int64_t per_row;  // blocks a row can touch
+  int32_t op, via, whole, pad;
+  void* out;        // hsz_stats (device)
+};
+// Exact per-job accumulator (sum q, count, sum q^2 as two 64-bit halves).
+struct BatchAcc {
+  int64_t s1, cnt;
+  uint64_t s2lo, s2hi;
+};
+hipError_t launch_batch_reset(BatchAcc* acc, int n, int* status, hipStream_t s);
+hipError_t launch_batch_stats(int S, const StatsJob* jobs, const int64_t* unit_start, const int64_t* counts,
+                              int kmax, BatchAcc* acc, int* status, int grid, hipStream_t s);
+hipError_t launch_batch_finalize(const StatsJob* jobs, const int64_t* counts, const BatchAcc* acc, int n,
+                                 hipStream_t s);
+
 // Statistics (op = 1 mean, 2 var) on a stage buffer or fused from a stream.
 hipError_t launch_stats_stage(const void* stage_buf, int stage, const StreamView& v, int op,
                               const OpTarget& t, void* result, uint8_t* ws, hipStream_t s);
 hipError_t launch_stats_fused(const StreamView& v, int via, int op, const OpTarget& t, void* result,
                               uint8_t* ws, hipStream_t s);
+
+// One fused-gradient job: a box of one stream, its block-offset index, the
+// z-extent of a tile (tz) and the staging rows needed (kmax).
+struct GradJob {
+  StreamView v;
+  const uint16_t* rel;
+  Dims3 d;
+  Box3 b;
+  int axis, tz, kmax;
+  double halfq;
+  void* out;
+};
+
+hipError_t launch_batch_block_index(const GradJob* jobs, const int64_t* chunk_start, const int64_t* counts, int grid,
+                                    hipStream_t s);
+hipError_t launch_batch_grad(int S, int via, int op, int dtype, const GradJob* jobs, const int64_t* tile_start,
+                             const int64_t* counts, int kmax, int grid, int* status, hipStream_t s);
+size_t batch_grad_lds(int dtype, int via, int kmax);
+int grad_tiles(const Box3& b, int tz);  // tiles of one fused-gradient job
+int grad_kmax(const StreamView& v);     // staging rows a stream needs
+int stats_kmax(const StreamView& v);
 
 // Derivative (op = 3, axis in the 3D view) or gradient magnitude (op = 4).
 hipError_t launch_grad_stage(const void* stage_buf, int stage, const StreamView& v, int op, int axis3,

@@ -358,6 +358,28 @@ __device__ double u128_to_f64(unsigned __int128 v) {
   return (double)(uint64_t)(v >> 64) * 18446744073709551616.0 + (double)(uint64_t)v;
 }
 
+// mean = s1 Delta / n; var = (n s2 - s1^2) / (n (n - 1)) Delta^2 with the
+// numerator exact in 128 bits (n < 2^34, |q| < 2^29), one rounding each
+__device__ StatsOut stats_from_sums(int64_t n, int64_t s1, uint64_t s2lo, uint64_t s2hi, int op, double quantum) {
+  StatsOut r{};
+  r.n = n;
+  r.s1 = s1;
+  r.mean = (double)s1 * quantum / (double)n;
+  if (op == 2) {
+    const unsigned __int128 S2 = ((unsigned __int128)s2hi << 64) | s2lo;
+    r.s2lo = s2lo;
+    r.s2hi = (int64_t)s2hi;
+    const unsigned __int128 a = (unsigned __int128)(uint64_t)n * S2;
+    const uint64_t m = (uint64_t)(s1 < 0 ? -s1 : s1);
+    const unsigned __int128 b = (unsigned __int128)m * m;
+    const double num = u128_to_f64(a - b);
+    r.var = n > 1 ? num / ((double)n * (double)(n - 1)) * (quantum * quantum) : __builtin_nan("");
+  } else {
+    r.var = __builtin_nan("");
+  }
+  return r;
+}
+
 // One workgroup of 256 threads: thread t sums partials t, t+256, ... in
 // order, then a fixed-shape tree combines the 256 sums, so the result does
 // not depend on timing.
@@ -400,28 +422,115 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(const Partial* parts, 
   r.n = cnts[0];
   const int64_t n = cnts[0];
   if (!fl) {
-    const int64_t S1 = s1s[0];
-    const unsigned __int128 S2 = ((unsigned __int128)his[0] << 64) | los[0];
-    r.s1 = S1;
-    r.mean = (double)S1 * quantum / (double)n;
-    if (op == 2) {
-      r.s2lo = (uint64_t)S2;
-      r.s2hi = (int64_t)(uint64_t)(S2 >> 64);
-      // n*s2 - s1^2 >= 0, exact in 128 bits for n < 2^34 and |q| < 2^29
-      const unsigned __int128 a = (unsigned __int128)(uint64_t)n * S2;
-      const uint64_t m = (uint64_t)(S1 < 0 ? -S1 : S1);
-      const unsigned __int128 b = (unsigned __int128)m * m;
-      const double num = u128_to_f64(a - b);
-      r.var = n > 1 ? num / ((double)n * (double)(n - 1)) * (quantum * quantum) : __builtin_nan("");
-    } else {
-      r.var = __builtin_nan("");
-    }
+    r = stats_from_sums(n, s1s[0], los[0], his[0], op, quantum);
   } else {
     const double K = parts[0].pad0;
     r.mean = K + f1s[0] / (double)n;
     r.var = (op == 2 && n > 1) ? (f2s[0] - f1s[0] * f1s[0] / (double)n) / (double)(n - 1) : __builtin_nan("");
   }
   *out = r;
+}
+
+// ---- batches: many jobs, one persistent launch --------------------------------------
+// Integer-route statistics of every job of one block size.  Units: a chunk
+// of a whole field, or 64 block segments of a box.  A wave walks the units
+// u = wave, wave + W, ...; it accumulates per job and adds its sums to the
+// job's accumulator with 64-bit atomics when the job changes (the 128-bit
+// sum of q^2 carries by hand).  Integer atomics make the totals exact and
+// independent of the schedule, so a job's result equals the one-op result.
+template <int S>
+__global__ void __launch_bounds__(kThreads) k_batch_stats(const StatsJob* __restrict__ jobs,
+                                                         const int64_t* __restrict__ unit_start,
+                                                         const int64_t* __restrict__ counts, int kmax,
+                                                         BatchAcc* __restrict__ acc, int* status) {
+  extern __shared__ uint32_t smem[];
+  const int wv = threadIdx.x / kWave;
+  uint32_t* tile = smem + wv * (kmax + 1) * kWave;
+  const int l = lane_id();
+  const int n = (int)counts[0];
+  const int64_t total = counts[1];
+  const int64_t waves = (int64_t)gridDim.x * kWavesPerGroup;
+  IntAcc a;
+  int cur = -1;
+  auto flush = [&](int j) {
+    const int64_t s1 = wave_sum64(a.s1);
+    const int64_t cnt = wave_sum64(a.cnt);
+    U128 s2 = a.s2;
+    for (int m = 32; m >= 1; m >>= 1) {
+      U128 o;
+      o.lo = __shfl_xor(s2.lo, m);
+      o.hi = __shfl_xor(s2.hi, m);
+      add_u128(s2, o);
+    }
+    if (l == 0) {
+      atomicAdd((unsigned long long*)&acc[j].s1, (unsigned long long)s1);
+      atomicAdd((unsigned long long*)&acc[j].cnt, (unsigned long long)cnt);
+      const unsigned long long old = atomicAdd((unsigned long long*)&acc[j].s2lo, (unsigned long long)s2.lo);
+      const uint64_t carry = (old + s2.lo < old) ? 1u : 0u;
+      if (s2.hi + carry) atomicAdd((unsigned long long*)&acc[j].s2hi, (unsigned long long)(s2.hi + carry));
+    }
+    a = IntAcc{};
+  };
+  for (int64_t u = blockIdx.x * (int64_t)kWavesPerGroup + wv; u < total; u += waves) {
+    int lo = 0, hi = n - 1;  // last job whose first unit is <= u
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (unit_start[mid] <= u) lo = mid;
+      else hi = mid - 1;
+    }
+    if (lo != cur) {
+      if (cur >= 0) flush(cur);
+      cur = lo;
+    }
+    const StatsJob& J = jobs[lo];
+    const int64_t lu = u - unit_start[lo];
+    int w = 0, q0 = 0, sa = 0, sz = -1;
+    if (J.whole) {
+      LaneBlock lb;
+      stage_chunk<S>(J.v.width, J.v.q0, J.v.chunk_off, J.v.payload, J.v.payload_words, J.v.n, J.v.nb, lu, tile,
+                     kmax, lb, status);
+      w = lb.w; q0 = lb.q0; sz = lb.len - 1;
+    } else {
+      Segs<S> segs;
+      segs.rows = J.rows;
+      segs.per_row = J.per_row;
+      int64_t b;
+      if (lu * kWave + l < segs.count() && segs.get(lu * kWave + l, b, sa, sz))
+        w = stage_block<S, kWave>(J.v.width, J.v.q0, J.v.chunk_off, J.v.payload, J.v.payload_words, J.v.nb, b,
+                                  tile + l, kmax, q0, status);
+      else
+        sz = -1;
+    }
+    if (sz < 0) continue;
+    if (J.via == 2 && J.op == 1) {
+      int64_t s = (int64_t)(sz - sa + 1) * q0;
+      decode_lane_block<S>(tile + l, w, q0, [&](int j, int p, int) {
+        if (j >= 1 && j <= sz) s += (int64_t)(sz - (sa > j ? sa : j) + 1) * p;
+      });
+      a.s1 += s;
+      a.cnt += sz - sa + 1;
+    } else {
+      const bool sq = J.op == 2;
+      decode_lane_block<S>(tile + l, w, q0, [&](int j, int, int q) {
+        if (j >= sa && j <= sz) a.add(q, sq);
+      });
+    }
+  }
+  if (cur >= 0) flush(cur);
+}
+
+__global__ void k_batch_reset(BatchAcc* acc, int n, int* status) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc[i] = BatchAcc{0, 0, 0, 0};
+  if (threadIdx.x == 0) *status = 0;
+}
+
+__global__ void k_batch_finalize(const StatsJob* __restrict__ jobs, const int64_t* __restrict__ counts,
+                                 const BatchAcc* __restrict__ acc) {
+  const int n = (int)counts[0];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const BatchAcc& a = acc[i];
+    *(StatsOut*)jobs[i].out = stats_from_sums(a.cnt, a.s1, a.s2lo, a.s2hi, jobs[i].op, jobs[i].v.quantum);
+  }
 }
 
 int grid_for(int64_t work_items, int per_group) {
@@ -487,6 +596,31 @@ hipError_t fused_by_via(const StreamView& v, int via, const Rows& rows, bool who
 }
 
 }  // namespace
+
+hipError_t launch_batch_reset(BatchAcc* acc, int n, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, acc, n, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_stats(int S, const StatsJob* jobs, const int64_t* unit_start, const int64_t* counts, int kmax,
+                              BatchAcc* acc, int* status, int grid, hipStream_t s) {
+  const size_t lds = (size_t)kWavesPerGroup * (kmax + 1) * kWave * sizeof(uint32_t);
+  if (S == 32)
+    hipLaunchKernelGGL(k_batch_stats<32>, dim3(grid), dim3(kThreads), lds, s, jobs, unit_start, counts, kmax, acc,
+                       status);
+  else
+    hipLaunchKernelGGL(k_batch_stats<64>, dim3(grid), dim3(kThreads), lds, s, jobs, unit_start, counts, kmax, acc,
+                       status);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const StatsJob* jobs, const int64_t* counts, const BatchAcc* acc, int n,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_finalize, dim3((n + 255) / 256), dim3(256), 0, s, jobs, counts, acc);
+  return hipGetLastError();
+}
+
+int stats_kmax(const StreamView& v) { return kmax_for(v); }
 
 uint64_t op_workspace_bytes() { return kPartialOff + sizeof(Partial) * (uint64_t)kOpWorkgroups; }
 

@@ -69,10 +69,23 @@ class Box(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_int64 * 3), ("hi", ctypes.c_int64 * 3)]
 
 
+class Work(ctypes.Structure):
+    _fields_ = [("d_c", ctypes.c_void_p), ("h", ctypes.POINTER(Header)), ("op", ctypes.c_int32),
+                ("via", ctypes.c_int32), ("axis", ctypes.c_int32), ("use_box", ctypes.c_int32), ("box", Box),
+                ("d_result", ctypes.c_void_p), ("result_bytes", ctypes.c_uint64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("stats_waves_per_cu", ctypes.c_int32), ("grad_groups_per_cu", ctypes.c_int32),
+                ("grad_tz", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 EXPORTS = (
     "hsz_strerror", "hsz_version", "hsz_last_hip_error", "hsz_read_status", "hsz_compress_bound",
     "hsz_compress_workspace", "hsz_compress", "hsz_read_header", "hsz_stage_bytes",
     "hsz_decompress_to_stage", "hsz_op_workspace", "hsz_op_on_stage", "hsz_op_fused",
+    "hsz_batch_workspace", "hsz_batch_run", "hsz_plan_create", "hsz_plan_update", "hsz_plan_launch",
+    "hsz_plan_destroy",
 )
 
 _lib = None
@@ -104,6 +117,13 @@ def load(path: str = LIB_PATH):
                                   u64, P]),
         "hsz_op_fused": (i32, [P, ctypes.POINTER(Header), i32, i32, i32, ctypes.POINTER(Box), P, u64, P, u64,
                                P]),
+        "hsz_batch_workspace": (i32, [ctypes.POINTER(Work), i32, pu64]),
+        "hsz_batch_run": (i32, [ctypes.POINTER(Work), i32, ctypes.POINTER(Tuning), P, u64, P]),
+        "hsz_plan_create": (i32, [ctypes.POINTER(Work), i32, ctypes.POINTER(Tuning), P, u64, P,
+                                  ctypes.POINTER(ctypes.c_void_p)]),
+        "hsz_plan_update": (i32, [P, ctypes.POINTER(Work), i32]),
+        "hsz_plan_launch": (i32, [P, P]),
+        "hsz_plan_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -380,3 +400,144 @@ def from_bytes(data, device="cuda") -> Compressed:
     t = _empty_bytes(arr.size, device)
     t[: arr.size].copy_(torch.from_numpy(arr.copy()))
     return Compressed(t, h)
+
+
+# ---- batches --------------------------------------------------------------------------
+
+@dataclass
+class Job:
+    """One operation of a batch: op on stream c through stage via (box optional)."""
+    c: Compressed
+    op: int
+    via: int
+    axis: int = 0
+    box: tuple | None = None
+
+
+def _result_for(job: Job, device):
+    h = job.c.header
+    op = _OPS.get(job.op, job.op)
+    buf, shape = _result_buffer(h, op, job.box, device)
+    return buf, shape
+
+
+class _Batch:
+    """Marshalled work items of a batch (keeps the ctypes objects alive)."""
+
+    def __init__(self, jobs, outs=None, device=None):
+        self.jobs = list(jobs)
+        dev = device if device is not None else self.jobs[0].c.data.device
+        self.results, self.shapes = [], []
+        for k, j in enumerate(self.jobs):
+            if outs is not None:
+                buf, shape = outs[k]
+            else:
+                buf, shape = _result_for(j, dev)
+            self.results.append(buf)
+            self.shapes.append(shape)
+        self.items = (Work * len(self.jobs))()
+        self._headers = []
+        for k, j in enumerate(self.jobs):
+            w = self.items[k]
+            hh = j.c.header
+            self._headers.append(hh)
+            w.d_c = j.c.data.data_ptr()
+            w.h = ctypes.pointer(hh)
+            w.op = _OPS.get(j.op, j.op)
+            w.via = _STAGES.get(j.via, j.via)
+            w.axis = j.axis
+            w.use_box = 0 if j.box is None else 1
+            if j.box is not None:
+                lo, hi = j.box
+                for a in range(hh.ndim):
+                    w.box.lo[a] = int(lo[a])
+                    w.box.hi[a] = int(hi[a])
+            w.d_result = self.results[k].data_ptr()
+            w.result_bytes = self.results[k].numel()
+
+    def workspace_bytes(self) -> int:
+        out = ctypes.c_uint64()
+        _check(load().hsz_batch_workspace(self.items, len(self.jobs), ctypes.byref(out)), "batch_workspace")
+        return out.value
+
+    def outputs(self):
+        """Results as dicts (statistics) or tensors (derivatives); synchronises."""
+        res = []
+        for j, buf, shape in zip(self.jobs, self.results, self.shapes):
+            op = _OPS.get(j.op, j.op)
+            res.append(_finish(buf, shape, j.c.header, op, None, None, False))
+        return res
+
+
+def _tuning(tune):
+    if tune is None:
+        return None
+    t = Tuning()
+    t.stats_waves_per_cu = int(tune.get("stats_waves_per_cu", 0))
+    t.grad_groups_per_cu = int(tune.get("grad_groups_per_cu", 0))
+    t.grad_tz = int(tune.get("grad_tz", 0))
+    return ctypes.byref(t)
+
+
+def batch_run(jobs, tune: dict | None = None, stream=None, ws: torch.Tensor | None = None, sync: bool = True):
+    """Run a batch of jobs in one pass; returns the results (or the _Batch when
+    sync is False: call .outputs() after the stream completes)."""
+    lib = load()
+    b = _Batch(jobs)
+    need = b.workspace_bytes()
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, b.results[0].device, key="batch")
+    _check(lib.hsz_batch_run(b.items, len(b.jobs), _tuning(tune), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                             ctypes.c_void_p(_stream(stream))), "batch_run")
+    if not sync:
+        b.ws = ws
+        return b
+    st = read_status(ws, stream)
+    if st != OK:
+        raise HszError(st, "batch_run")
+    return b.outputs()
+
+
+class Plan:
+    """A batch captured as a HIP graph; replay with launch(), retarget with update()."""
+
+    def __init__(self, jobs, tune: dict | None = None, stream=None):
+        lib = load()
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.batch = _Batch(jobs)
+        need = self.batch.workspace_bytes()
+        self.ws = _empty_bytes(need, self.batch.results[0].device)
+        handle = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _check(lib.hsz_plan_create(self.batch.items, len(self.batch.jobs), _tuning(tune),
+                                   ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)), "plan_create")
+        self.handle = handle
+
+    def update(self, jobs, outs=None):
+        """New jobs of the same structure (new streams, boxes, axes); results go
+        to 'outs' ((buffer, shape) per job) or to freshly allocated buffers."""
+        nb = _Batch(jobs, outs=outs)
+        _check(load().hsz_plan_update(self.handle, nb.items, len(nb.jobs)), "plan_update")
+        self.batch = nb
+
+    def launch(self):
+        _check(load().hsz_plan_launch(self.handle, ctypes.c_void_p(self.stream.cuda_stream)), "plan_launch")
+
+    def results(self):
+        self.stream.synchronize()
+        st = read_status(self.ws, self.stream)
+        if st != OK:
+            raise HszError(st, "plan")
+        return self.batch.outputs()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().hsz_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
