@@ -217,7 +217,16 @@ typedef struct hsz_work {
   hsz_box box;
   void *d_result;       /* hsz_stats, or the box-shaped result (16-byte aligned) */
   uint64_t result_bytes;
+  const void *d_index;  /* optional: the stream's block index (hsz_block_index);
+                           NULL builds one in the workspace for gradient jobs  */
 } hsz_work;
+
+/* Block index of a stream: for every block, the offset of its payload
+ * within its 64-block chunk (uint16[nb]).  With it any block is located by
+ * two independent loads (chunk table + index) instead of a prefix over the
+ * chunk's widths; streams that stay resident (serving) build it once. */
+int hsz_block_index_bytes(const hsz_header *h, uint64_t *h_bytes);
+int hsz_block_index(const void *d_c, const hsz_header *h, void *d_index, uint64_t cap, void *stream);
 
 /* Launch shape of a batch; zeros select the defaults. */
 typedef struct hsz_tuning {

@@ -214,6 +214,23 @@ int hsz_decompress_to_stage(const void* d_c, const hsz_header* h, int stage, voi
   return e == hipSuccess ? HSZ_OK : hip_fail(e);
 }
 
+int hsz_block_index_bytes(const hsz_header* h, uint64_t* h_bytes) {
+  if (!h || !h_bytes) return HSZ_ERR_INVALID_ARG;
+  int rc = check_header(h);
+  if (rc) return rc;
+  *h_bytes = 2 * (uint64_t)h->nb;
+  return HSZ_OK;
+}
+
+int hsz_block_index(const void* d_c, const hsz_header* h, void* d_index, uint64_t cap, void* stream) {
+  int rc = check_header(h);
+  if (rc) return rc;
+  if (!d_c || !d_index || !aligned16(d_c) || !aligned16(d_index)) return HSZ_ERR_INVALID_ARG;
+  if (cap < 2 * (uint64_t)h->nb) return HSZ_ERR_CAPACITY;
+  hipError_t e = hsz::launch_block_index(view_of(d_c, h), (uint16_t*)d_index, (hipStream_t)stream);
+  return e == hipSuccess ? HSZ_OK : hip_fail(e);
+}
+
 int hsz_op_workspace(const hsz_header* h, int op, uint64_t* h_bytes) {
   if (!h || !h_bytes || op < HSZ_MEAN || op > HSZ_GRADMAG) return HSZ_ERR_INVALID_ARG;
   uint64_t a = hsz::op_workspace_bytes(), b = hsz::grad_workspace_bytes(h->nb);

@@ -47,6 +47,7 @@ struct Item {
   hsz::StreamView v;
   hsz::OpTarget t;
   void* out;
+  const uint16_t* index;  // caller's block index, or null
 };
 
 // counts slots
@@ -71,6 +72,8 @@ int classify(const hsz_work& w, Item* it) {
   it->dtype = h->dtype;
   it->v = view_of(w.d_c, h);
   it->out = w.d_result;
+  it->index = (const uint16_t*)w.d_index;
+  if (w.d_index && ((uintptr_t)w.d_index & 1u)) return HSZ_ERR_INVALID_ARG;
   if (w.op == HSZ_MEAN || w.op == HSZ_VAR) {
     if (w.via != HSZ_DELTA && w.via != HSZ_QUANT) return HSZ_ERR_UNSUPPORTED;  // exact integer routes only
     if (w.result_bytes < sizeof(hsz_stats)) return HSZ_ERR_CAPACITY;
@@ -120,7 +123,7 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
     if (it.kind == 0) order_stats[it.S == 64].push_back(i);
     else {
       order_grad[variant_of(it.S, it.via, it.op, it.dtype)].push_back(i);
-      grads.push_back(i);
+      if (!it.index) grads.push_back(i);  // jobs that need an index built here
     }
   }
   uint64_t off = kAlign;  // [0, 256): status
@@ -170,6 +173,7 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
       J.op = it.op;
       J.via = it.via;
       J.out = it.out;
+      J.rel = it.index;
       ((hsz::StatsJob*)at(L.stats_jobs[si]))[k] = J;
       ((int64_t*)at(L.stats_start[si]))[k] = u;
       u += J.whole ? it.v.nchunks : (J.rows.count() * J.per_row + hsz::kWave - 1) / hsz::kWave;
@@ -182,11 +186,12 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
     B->stats_kmax[si] = km;
   }
   std::vector<hsz::GradJob> gj(items.size());
-  for (int i : grads) {
+  for (int i = 0; i < (int)items.size(); ++i) {
     const Item& it = items[i];
+    if (it.kind != 1) continue;
     hsz::GradJob J{};
     J.v = it.v;
-    J.rel = (const uint16_t*)(d_ws + L.rel[i]);
+    J.rel = it.index ? it.index : (const uint16_t*)(d_ws + L.rel[i]);
     J.d = it.t.d;
     J.b = it.t.box;
     J.axis = it.axis3;

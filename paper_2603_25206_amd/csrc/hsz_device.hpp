@@ -243,11 +243,11 @@ __device__ __forceinline__ int stage_block(const uint8_t* __restrict__ width, co
                                            const uint64_t* __restrict__ chunk_off,
                                            const uint32_t* __restrict__ payload, uint64_t payload_words,
                                            int64_t nb, int64_t b, uint32_t* col, int kmax, int& q0,
-                                           int* status) {
+                                           int* status, const uint16_t* __restrict__ rel = nullptr) {
   const int w = (int)width[b];
   q0 = q0s[b];
   const int nw = block_words<S>(w);
-  const uint64_t off = block_offset<S>(width, chunk_off, nb, b);
+  const uint64_t off = rel ? chunk_off[b / kChunkBlocks] + rel[b] : block_offset<S>(width, chunk_off, nb, b);
   if (w > kMaxWidth || nw > kmax || off + (uint64_t)nw > payload_words) {
     record_status(status, kErrBadStream);
     return 0;

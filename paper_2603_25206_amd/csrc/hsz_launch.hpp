@@ -91,7 +91,8 @@ struct StatsJob {
   Rows rows;        // the box as contiguous rows
   int64_t per_row;  // blocks a row can touch
   int32_t op, via, whole, pad;
-  void* out;        // hsz_stats (device)
+  void* out;            // hsz_stats (device)
+  const uint16_t* rel;  // block index, or null (offsets from the widths)
 };
 // Exact per-job accumulator (sum q, count, sum q^2 as two 64-bit halves).
 struct BatchAcc {

@@ -497,7 +497,7 @@ __global__ void __launch_bounds__(kThreads) k_batch_stats(const StatsJob* __rest
       int64_t b;
       if (lu * kWave + l < segs.count() && segs.get(lu * kWave + l, b, sa, sz))
         w = stage_block<S, kWave>(J.v.width, J.v.q0, J.v.chunk_off, J.v.payload, J.v.payload_words, J.v.nb, b,
-                                  tile + l, kmax, q0, status);
+                                  tile + l, kmax, q0, status, J.rel);
       else
         sz = -1;
     }

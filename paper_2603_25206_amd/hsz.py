@@ -72,7 +72,7 @@ class Box(ctypes.Structure):
 class Work(ctypes.Structure):
     _fields_ = [("d_c", ctypes.c_void_p), ("h", ctypes.POINTER(Header)), ("op", ctypes.c_int32),
                 ("via", ctypes.c_int32), ("axis", ctypes.c_int32), ("use_box", ctypes.c_int32), ("box", Box),
-                ("d_result", ctypes.c_void_p), ("result_bytes", ctypes.c_uint64)]
+                ("d_result", ctypes.c_void_p), ("result_bytes", ctypes.c_uint64), ("d_index", ctypes.c_void_p)]
 
 
 class Tuning(ctypes.Structure):
@@ -85,7 +85,7 @@ EXPORTS = (
     "hsz_compress_workspace", "hsz_compress", "hsz_read_header", "hsz_stage_bytes",
     "hsz_decompress_to_stage", "hsz_op_workspace", "hsz_op_on_stage", "hsz_op_fused",
     "hsz_batch_workspace", "hsz_batch_run", "hsz_plan_create", "hsz_plan_update", "hsz_plan_launch",
-    "hsz_plan_destroy",
+    "hsz_plan_destroy", "hsz_block_index_bytes", "hsz_block_index",
 )
 
 _lib = None
@@ -124,6 +124,8 @@ def load(path: str = LIB_PATH):
         "hsz_plan_update": (i32, [P, ctypes.POINTER(Work), i32]),
         "hsz_plan_launch": (i32, [P, P]),
         "hsz_plan_destroy": (None, [P]),
+        "hsz_block_index_bytes": (i32, [ctypes.POINTER(Header), pu64]),
+        "hsz_block_index": (i32, [P, ctypes.POINTER(Header), P, u64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -191,9 +193,24 @@ def read_status(ws: torch.Tensor, stream=None) -> int:
 
 @dataclass
 class Compressed:
-    """A compressed stream resident in device memory, with its parsed header."""
+    """A compressed stream resident in device memory, with its parsed header
+    (and, once built with build_index(), its block index)."""
     data: torch.Tensor  # uint8, at least header.total_bytes long
     header: Header
+    index: torch.Tensor | None = None
+
+    def build_index(self, stream=None) -> torch.Tensor:
+        """Build (once) the per-block payload offsets used by batches."""
+        if self.index is None:
+            lib = load()
+            nbytes = ctypes.c_uint64()
+            _check(lib.hsz_block_index_bytes(ctypes.byref(self.header), ctypes.byref(nbytes)), "block_index_bytes")
+            idx = _empty_bytes(nbytes.value, self.data.device)
+            _check(lib.hsz_block_index(ctypes.c_void_p(self.data.data_ptr()), ctypes.byref(self.header),
+                                       ctypes.c_void_p(idx.data_ptr()), idx.numel(),
+                                       ctypes.c_void_p(_stream(stream))), "block_index")
+            self.index = idx
+        return self.index
 
     @property
     def nbytes(self) -> int:
@@ -454,6 +471,7 @@ class _Batch:
                     w.box.hi[a] = int(hi[a])
             w.d_result = self.results[k].data_ptr()
             w.result_bytes = self.results[k].numel()
+            w.d_index = j.c.index.data_ptr() if j.c.index is not None else None
 
     def workspace_bytes(self) -> int:
         out = ctypes.c_uint64()

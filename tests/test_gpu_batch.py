@@ -153,3 +153,19 @@ def test_batch_rejects_float_route_statistics(streams):
     with pytest.raises(hsz.HszError) as e:
         hsz.batch_run([hsz.Job(streams[0][1], "mean", hsz.FLOAT)])
     assert e.value.code == hsz.ERR_UNSUPPORTED
+
+
+def test_batch_with_prebuilt_block_indexes(streams):
+    """Jobs that carry the stream's prebuilt block index (the serving path)
+    give the same results as jobs that let the batch build it."""
+    say("[case] prebuilt indexes")
+    jobs = make_jobs(streams, seed=5)
+    ref = hsz.batch_run(jobs)
+    idx_streams = [(x, hsz.Compressed(c.data, c.header)) for x, c in streams]
+    for _, c in idx_streams:
+        c.build_index()
+    jobs_i = [hsz.Job(idx_streams[[id(c) for _, c in streams].index(id(j.c))][1], j.op, j.via, j.axis, j.box)
+              for j in jobs]
+    got = hsz.batch_run(jobs_i)
+    for k, (a, b) in enumerate(zip(ref, got)):
+        assert same(a, b), k
