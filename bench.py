@@ -51,6 +51,11 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the per-stage table")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workloads")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--snapshots", type=int, default=64)
+    ap.add_argument("--queries", type=int, default=20000)
+    ap.add_argument("--rate", type=float, default=2000.0)
     return ap.parse_args()
 
 
@@ -200,7 +205,7 @@ def main():
     alg = {  # algorithmic bytes per launch (compressed input + outputs; never the avoided floats)
         "mean_fused_delta": cbytes,
         "var_fused_quant": cbytes,
-        "gradmag_quant": cbytes + 4 * n + 4 * n + 4 * n,  # decode to q (read c, write q) + stencil (read q, write g)
+        "gradmag_quant": cbytes + 4 * n,  # fused: read the compressed stream once, write the f32 magnitude
         "decompress_quant": cbytes + 4 * n,
         "decompress_float": cbytes + 4 * n,
         "decompress_delta": cbytes + 4 * n + 4 * h.nb,
@@ -241,9 +246,139 @@ def main():
         "check": {"var_int_route": st_v["var"], "var_float_route": st_bv["var"], "mean": st_m["mean"]},
     }
 
+    del copies, gbuf, qbuf, fbuf, dbuf
+    torch.cuda.empty_cache()
+    if not a.no_batch:
+        out["batching"] = bench_batches(a, log)
+        torch.cuda.empty_cache()
+    if not a.no_serve:
+        out["serving"] = bench_serving(a, log)
+        torch.cuda.empty_cache()
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, x, a)
     print(json.dumps(out), flush=True)
+
+
+def _events_ms(fn, reps, stream):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def bench_batches(a, log):
+    """Many fields of uneven shapes analysed in one pass: each field gets mean
+    (via D_p), variance (via D_q) and gradient magnitude (via D_q).  Timed as
+    a captured graph replay with the autotuned launch shape, against the same
+    jobs as separate single-field launches and against full decompression +
+    the operations on floats."""
+    import torch
+
+    from paper_2603_25206_amd import hsz, synth, tune
+
+    res = {}
+    workloads = {
+        "12 uneven f32 fields (4x 100x500x500, 4x 256x384x384, 4x 1800x3600), rel eb 1e-2/1e-3/1e-4, S=32":
+            synth.batch_specs(),
+        "8 f64 256^3 fields with tanh fronts, rel eb 1e-6, S=32":
+            [(synth.front_field_spec(i), 1e-6) for i in range(8)],
+    }
+    for name, specs in workloads.items():
+        comps, orig = [], 0
+        for sp, rel in specs:
+            f = synth.make_field_torch(sp, "cuda")
+            comps.append(hsz.compress(f, rel, rel=True, block=32))
+            orig += f.numel() * f.element_size()
+            del f
+        jobs = []
+        for c in comps:
+            jobs += [hsz.Job(c, "mean", hsz.DELTA), hsz.Job(c, "var", hsz.QUANT), hsz.Job(c, "gradmag", hsz.QUANT)]
+        best, timings = tune.tune(jobs, reps=3, cache_path=None)
+        plan = hsz.Plan(jobs, tune=best)
+        ms_plan = _events_ms(plan.launch, 5, plan.stream)
+        plan.close()
+        cur = torch.cuda.current_stream()
+        outs = [hsz._result_for(j, comps[0].data.device)[0] for j in jobs]
+        wsz = max(hsz.op_workspace_bytes(c.header, hsz.GRADMAG) for c in comps)
+        ws = hsz.workspace(wsz, comps[0].data.device, key="bench-single")
+
+        def singles():
+            for j, o in zip(jobs, outs):
+                hsz.op_fused(j.c, j.via, j.op, out=o, ws=ws, check=False, raw=True)
+        ms_single = _events_ms(singles, 3, cur)
+        fbufs = [torch.empty(c.header.n * (4 if c.header.dtype == 1 else 8) + 64, dtype=torch.uint8,
+                             device=c.data.device) for c in comps[:1]]
+
+        def baseline():
+            for c, j0 in zip(comps, range(len(comps))):
+                fb = fbufs[0]
+                if fb.numel() < c.header.n * (4 if c.header.dtype == 1 else 8):
+                    fb = fbufs[0] = torch.empty(c.header.n * 8 + 64, dtype=torch.uint8, device=c.data.device)
+                hsz.decompress_to_stage(c, hsz.FLOAT, out=fb)
+                fv = hsz.stage_view(fb, c.header, hsz.FLOAT)
+                for op, o in ((hsz.MEAN, outs[3 * j0]), (hsz.VAR, outs[3 * j0 + 1]), (hsz.GRADMAG, outs[3 * j0 + 2])):
+                    hsz.op_on_stage(fv, c.header, hsz.FLOAT, op, out=o, ws=ws, check=False, raw=True)
+        ms_base = _events_ms(baseline, 3, cur)
+        res[name] = {"fields": len(comps), "jobs": len(jobs), "orig_bytes": orig,
+                     "compressed_bytes": sum(c.nbytes for c in comps),
+                     "graph_ms": round(ms_plan, 4), "gbs_orig": round(orig / ms_plan / 1e6, 1),
+                     "single_launches_ms": round(ms_single, 4), "full_decompress_ms": round(ms_base, 4),
+                     "speedup_vs_single": round(ms_single / ms_plan, 3),
+                     "speedup_vs_full_decompress": round(ms_base / ms_plan, 3),
+                     "autotuned": best, "candidates_tried": len(timings)}
+        log(f"[bench] batch {name}: {res[name]}")
+        del comps, jobs, outs, fbufs
+        torch.cuda.empty_cache()
+    return res
+
+
+def bench_serving(a, log):
+    """Compressed snapshots resident in HBM (even: 512^3, odd: 100x500x500,
+    f32, rel eb 1e-3, S=32), a Poisson stream of queries (mean, variance or
+    gradient magnitude over a random box with sides 32..256), continuous
+    batching over 4 stream slots with a 4 GiB result budget."""
+    import torch
+
+    from paper_2603_25206_amd import hsz, synth
+    from paper_2603_25206_amd.serve import GpuExecutor, Server, make_queries, summary
+
+    snaps, shapes = [], []
+    t0 = time.time()
+    for k in range(a.snapshots):
+        sp = synth.snapshot_spec(k)
+        f = synth.make_field_torch(sp, "cuda")
+        snaps.append(hsz.compress(f, 1e-3, rel=True, block=32))
+        shapes.append(tuple(sp.shape))
+        del f
+    torch.cuda.synchronize()
+    log(f"[bench] serving: {a.snapshots} snapshots in {time.time() - t0:.1f}s, "
+        f"{sum(c.nbytes for c in snaps) / 2**30:.2f} GiB compressed")
+    ex = GpuExecutor(snaps, n_slots=4)
+    srv = Server(ex, mem_budget=4 << 30, max_batch=64)
+    warm = make_queries(shapes, 200, rate_hz=a.rate, seed=1)
+    srv.run(warm)
+    srv.done.clear()
+    srv.stats = type(srv.stats)()
+    qs = make_queries(shapes, a.queries, rate_hz=a.rate, seed=7)
+    t0 = time.perf_counter()
+    done = srv.run(qs)
+    wall = time.perf_counter() - t0
+    s = summary(done, wall, bytes_per_elem=4)
+    s.update({"snapshots": a.snapshots, "rate_hz": a.rate, "slots": ex.n_slots,
+              "batches": srv.stats.launched_batches,
+              "mean_batch": round(float(np.mean(srv.stats.batch_sizes)), 2),
+              "max_in_flight": srv.stats.max_in_flight})
+    s = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
+    log(f"[bench] serving: {s}")
+    return s
 
 
 def cpu_baseline(spec, x, a):

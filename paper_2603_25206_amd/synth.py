@@ -127,3 +127,54 @@ def snapshot_spec(k: int) -> FieldSpec:
     """Serving snapshot k: even k -> 512^3, odd k -> 100x500x500; large-field recipe."""
     shape = (512, 512, 512) if k % 2 == 0 else (100, 500, 500)
     return large_field_spec(seed=300 + k, shape=shape)
+
+
+def make_field_torch(spec: FieldSpec, device="cuda"):
+    """The same recipe generated on the GPU with torch's seeded generator (a
+    different random stream from make_field, so different values): used where
+    many large fields are needed quickly and no CPU reference consumes them
+    (the serving snapshots).  binary64 arithmetic, cast at the end."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(spec.seed))
+    f64 = torch.float64
+    shape = tuple(int(s) for s in spec.shape)
+    nd = len(shape)
+    k = spec.k
+    dims = torch.tensor(shape, dtype=f64, device=device)
+    centres = torch.rand(k, nd, generator=g, dtype=f64, device=device) * dims
+    sig = spec.sigma[0] + (spec.sigma[1] - spec.sigma[0]) * torch.rand(k, generator=g, dtype=f64, device=device)
+    amp = 0.5 + 1.5 * torch.rand(k, generator=g, dtype=f64, device=device)
+    z3, y3, x3 = _pad3(shape)
+    c3 = torch.zeros(k, 3, dtype=f64, device=device)
+    c3[:, 3 - nd:] = centres
+
+    def prof(n, c):
+        i = torch.arange(n, dtype=f64, device=device)
+        return torch.exp(-((i[None, :] - c[:, None]) ** 2) / (2.0 * sig[:, None] ** 2))
+
+    gz = prof(z3, c3[:, 0]) if z3 > 1 else torch.ones(k, 1, dtype=f64, device=device)
+    gy = prof(y3, c3[:, 1]) if y3 > 1 else torch.ones(k, 1, dtype=f64, device=device)
+    gx = prof(x3, c3[:, 2])
+    gzy = (amp[:, None, None] * gz[:, :, None] * gy[:, None, :]).reshape(k, z3 * y3)
+    f = (gzy.T @ gx).reshape(shape)
+    if spec.fronts:
+        zz = torch.arange(z3, dtype=f64, device=device)[:, None, None]
+        yy = torch.arange(y3, dtype=f64, device=device)[None, :, None]
+        xx = torch.arange(x3, dtype=f64, device=device)[None, None, :]
+        dims3 = torch.tensor([z3, y3, x3], dtype=f64, device=device)
+        acc = torch.zeros((z3, y3, x3), dtype=f64, device=device)
+        for _ in range(spec.fronts):
+            point = torch.rand(3, generator=g, dtype=f64, device=device) * dims3
+            nrm = torch.randn(3, generator=g, dtype=f64, device=device)
+            nrm = nrm / torch.linalg.norm(nrm)
+            b = 0.5 + 1.5 * torch.rand((), generator=g, dtype=f64, device=device)
+            s = (zz - point[0]) * nrm[0] + (yy - point[1]) * nrm[1] + (xx - point[2]) * nrm[2]
+            acc += b * torch.tanh(s / 2.0)
+        f = f + acc.reshape(shape)
+    if spec.noise:
+        f = f + spec.noise * torch.randn(shape, generator=g, dtype=f64, device=device)
+    if spec.texture:
+        f = f * torch.exp(spec.texture * torch.randn(shape, generator=g, dtype=f64, device=device))
+    return f.to(torch.float32 if spec.dtype == "f32" else torch.float64).contiguous()
