@@ -9,6 +9,9 @@
 //   acc         BatchAcc per statistics job (exact sums)
 //   rel         one 16-bit offset index per gradient job
 // then enqueues: reset -> offset index -> statistics -> gradients -> finalize.
+// A statistics job over the same stream and box as a gradient job through
+// the quantized stage is computed inside that job's tiles (one decode for
+// both); hsz_tuning.separate_stats turns this off.
 // Because job and unit counts are read from device memory, a captured graph
 // can be replayed after the table is rewritten for a batch of the same
 // structure (hsz_plan_update).
@@ -21,13 +24,13 @@ namespace {
 
 using namespace hsz_abi;
 
-constexpr int kVariants = 16;  // S(2) x via(2) x op(2) x dtype(2)
+constexpr int kVariants = 48;  // S(2) x via(2) x op(2) x dtype(2) x shared-statistics mode(3)
 constexpr uint64_t kAlign = 256;
 
 uint64_t up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-int variant_of(int S, int via, int op, int dtype) {
-  return ((S == 64) << 3) | ((via == HSZ_FLOAT) << 2) | ((op == HSZ_GRADMAG) << 1) | (dtype == HSZ_F64);
+int variant_of(int S, int via, int op, int dtype, int acc) {
+  return 16 * acc + (((S == 64) << 3) | ((via == HSZ_FLOAT) << 2) | ((op == HSZ_GRADMAG) << 1) | (dtype == HSZ_F64));
 }
 
 struct Layout {
@@ -107,6 +110,10 @@ struct Built {
   int64_t index_chunks = 0;
 };
 
+bool same_box(const hsz::Box3& a, const hsz::Box3& b) {
+  return a.z0 == b.z0 && a.z1 == b.z1 && a.y0 == b.y0 && a.y1 == b.y1 && a.x0 == b.x0 && a.x1 == b.x1;
+}
+
 int tz_for(const hsz::Box3& b, int want) {
   const int64_t bz = b.z1 - b.z0;
   int64_t tz = want > 0 ? want : 32;
@@ -116,13 +123,30 @@ int tz_for(const hsz::Box3& b, int want) {
 // Lay out and fill the table for 'items' in the workspace at d_ws.
 int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws, Built* B) {
   Layout& L = B->L;
+  // Statistics that share a gradient job's decode: same stream and box, the
+  // gradient through the quantized stage.  Such a job gets no units of its
+  // own; the gradient tiles add its sums (exact, so the result is the same).
+  std::vector<int> host(items.size(), -1), slot(items.size(), -1), acc_mode(items.size(), 0);
+  if (!tune.separate_stats) {
+    for (int i = 0; i < (int)items.size(); ++i) {
+      if (items[i].kind != 0) continue;
+      for (int g = 0; g < (int)items.size(); ++g) {
+        const Item& G = items[g];
+        if (G.kind == 1 && G.via == HSZ_QUANT && G.v.base == items[i].v.base && same_box(G.t.box, items[i].t.box)) {
+          host[i] = g;
+          acc_mode[g] = (G.v.max_abs_q < 65536u && tz_for(G.t.box, tune.grad_tz) <= 2048) ? 1 : 2;
+          break;
+        }
+      }
+    }
+  }
   std::vector<int> order_stats[2], order_grad[kVariants];
   std::vector<int> grads;
   for (int i = 0; i < (int)items.size(); ++i) {
     const Item& it = items[i];
     if (it.kind == 0) order_stats[it.S == 64].push_back(i);
     else {
-      order_grad[variant_of(it.S, it.via, it.op, it.dtype)].push_back(i);
+      order_grad[variant_of(it.S, it.via, it.op, it.dtype, acc_mode[i])].push_back(i);
       if (!it.index) grads.push_back(i);  // jobs that need an index built here
     }
   }
@@ -164,7 +188,8 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
     int64_t u = 0;
     int km = 0;
     for (size_t k = 0; k < order_stats[si].size(); ++k) {
-      const Item& it = items[order_stats[si][k]];
+      const int i = order_stats[si][k];
+      const Item& it = items[i];
       hsz::StatsJob J{};
       J.v = it.v;
       J.rows = hsz::make_rows(it.t.d, it.t.box);
@@ -172,11 +197,17 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
       J.per_row = (J.rows.len + it.S - 2) / it.S + 1;
       J.op = it.op;
       J.via = it.via;
+      J.acc = (int32_t)k;
       J.out = it.out;
       J.rel = it.index;
-      ((hsz::StatsJob*)at(L.stats_jobs[si]))[k] = J;
       ((int64_t*)at(L.stats_start[si]))[k] = u;
-      u += J.whole ? it.v.nchunks : (J.rows.count() * J.per_row + hsz::kWave - 1) / hsz::kWave;
+      if (host[i] >= 0) {
+        if (slot[host[i]] < 0) slot[host[i]] = (int)k;
+        J.acc = slot[host[i]];
+      } else {
+        u += J.whole ? it.v.nchunks : (J.rows.count() * J.per_row + hsz::kWave - 1) / hsz::kWave;
+      }
+      ((hsz::StatsJob*)at(L.stats_jobs[si]))[k] = J;
       km = std::max(km, hsz::stats_kmax(it.v));
     }
     counts[2 * cslot_stats(si)] = (int64_t)order_stats[si].size();
@@ -199,6 +230,10 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
     J.kmax = hsz::grad_kmax(it.v);
     J.halfq = 0.5 * it.v.quantum;
     J.out = it.out;
+    if (slot[i] >= 0) {
+      J.acc = d_ws + L.acc[it.S == 64] + sizeof(hsz::BatchAcc) * (uint64_t)slot[i];
+      J.acc_mode = acc_mode[i];
+    }
     gj[i] = J;
   }
   for (int g = 0; g < kVariants; ++g) {
@@ -267,9 +302,9 @@ int enqueue(const Built& B, uint8_t* d_ws, const hsz_tuning& tune, hipStream_t s
   }
   for (int g = 0; g < kVariants; ++g) {
     if (B.n_grad[g] == 0) continue;
-    const int S = (g >> 3) ? 64 : 32, via = ((g >> 2) & 1) ? HSZ_FLOAT : HSZ_QUANT;
-    const int op = ((g >> 1) & 1) ? HSZ_GRADMAG : HSZ_DERIV, dtype = (g & 1) ? HSZ_F64 : HSZ_F32;
-    if ((e = hsz::launch_batch_grad(S, via, op, dtype, (const hsz::GradJob*)(d_ws + L.grad_jobs[g]),
+    const int S = ((g >> 3) & 1) ? 64 : 32, via = ((g >> 2) & 1) ? HSZ_FLOAT : HSZ_QUANT;
+    const int op = ((g >> 1) & 1) ? HSZ_GRADMAG : HSZ_DERIV, dtype = (g & 1) ? HSZ_F64 : HSZ_F32, acc = g >> 4;
+    if ((e = hsz::launch_batch_grad(S, via, op, dtype, acc, (const hsz::GradJob*)(d_ws + L.grad_jobs[g]),
                                     (const int64_t*)(d_ws + L.grad_start[g]), counts + 2 * cslot_grad(g),
                                     B.grad_kmax[g], grad_grid, status, s)) != hipSuccess)
       return hip_fail(e);

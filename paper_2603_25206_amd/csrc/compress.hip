@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(kThreads) k_minmax(const T* __restrict__ x, in
   }
   __shared__ double slo[kThreads / kWave], shi[kThreads / kWave];
   __shared__ int sbad[kThreads / kWave];
-  const int wv = threadIdx.x / kWave;
+  const int wv = wave_in_group();
   if (lane_id() == 0) { slo[wv] = lo; shi[wv] = hi; sbad[wv] = bad; }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(kThreads) k_quant_meta(const T* __restrict__ x
   const int64_t waves = (int64_t)gridDim.x * (kThreads / kWave);
   uint32_t maxq = 0;
   bool over = false;
-  for (int64_t c = blockIdx.x * (int64_t)(kThreads / kWave) + threadIdx.x / kWave; c < nchunks; c += waves) {
+  for (int64_t c = blockIdx.x * (int64_t)(kThreads / kWave) + wave_in_group(); c < nchunks; c += waves) {
     const int64_t b = c * kChunkBlocks + l;
     int w = 0;
     if (b < nb) {
@@ -235,11 +235,11 @@ __global__ void __launch_bounds__(kThreads) k_pack(const T* __restrict__ x, int6
   if (ws->status != 0) return;
   constexpr int kRows = (S / 32) * (1 + kMaxWidth);
   __shared__ uint32_t lin_all[(kThreads / kWave) * kRows * kWave];
-  uint32_t* lin = lin_all + (threadIdx.x / kWave) * kRows * kWave;
+  uint32_t* lin = lin_all + (wave_in_group()) * kRows * kWave;
   const double inv = ws->inv_quantum;
   const int l = lane_id();
   const int64_t waves = (int64_t)gridDim.x * (kThreads / kWave);
-  for (int64_t c = blockIdx.x * (int64_t)(kThreads / kWave) + threadIdx.x / kWave; c < nchunks; c += waves) {
+  for (int64_t c = blockIdx.x * (int64_t)(kThreads / kWave) + wave_in_group(); c < nchunks; c += waves) {
     const int64_t b = c * kChunkBlocks + l;
     const int w = (b < nb) ? (int)widths[b] : 0;
     const int nw = block_words<S>(w);

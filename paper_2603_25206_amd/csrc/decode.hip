@@ -45,7 +45,7 @@ template <int S, int STAGE, typename T>
 __global__ void __launch_bounds__(kThreads) k_decode(StreamView v, int kmax, int wave_words, T* __restrict__ out,
                                                     int32_t* __restrict__ out_q0, int* status) {
   extern __shared__ uint32_t smem[];
-  const int wv = threadIdx.x / kWave;
+  const int wv = wave_in_group();
   uint32_t* tile = smem + wv * wave_words;
   const int l = lane_id();
   const int64_t waves = (int64_t)gridDim.x * kWavesPerGroup;
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(kThreads) k_decode(StreamView v, int kmax, int
 // with two independent loads: chunk_off[b / 64] + rel[b].  One wave per chunk.
 template <int S>
 __global__ void __launch_bounds__(kThreads) k_block_index(StreamView v, uint16_t* __restrict__ rel) {
-  const int wv = threadIdx.x / kWave;
+  const int wv = wave_in_group();
   const int l = lane_id();
   const int64_t waves = (int64_t)gridDim.x * kWavesPerGroup;
   for (int64_t c = blockIdx.x * (int64_t)kWavesPerGroup + wv; c < v.nchunks; c += waves) {
@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(kThreads) k_block_index(StreamView v, uint16_t
 __global__ void __launch_bounds__(kThreads) k_batch_block_index(const GradJob* __restrict__ jobs,
                                                                const int64_t* __restrict__ chunk_start,
                                                                const int64_t* __restrict__ counts) {
-  const int wv = threadIdx.x / kWave;
+  const int wv = wave_in_group();
   const int l = lane_id();
   const int n = (int)counts[0];
   const int64_t total = counts[1];
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(kThreads) k_batch_block_index(const GradJob* _
       if (chunk_start[mid] <= u) lo = mid;
       else hi = mid - 1;
     }
-    const GradJob& J = jobs[lo];
+    const GradJob J = load_job(jobs, lo);
     const int64_t b = (u - chunk_start[lo]) * kChunkBlocks + l;
     const int w = b < J.v.nb ? (int)J.v.width[b] : 0;
     const int wc = w < kMaxWidth ? w : kMaxWidth;

@@ -152,6 +152,10 @@ __device__ __forceinline__ int pidx(int r, int c) { return r * kPitch + c + (c >
 // so the global-memory latency of the next planes overlaps the stencil.
 // Block offsets come from the chunk table plus the per-block index 'rel'.
 // z-neighbours and the in-plane part of the previous plane stay in registers.
+// ACC (quantized route only): also sum q and q^2 over the tile's own
+// elements (each element of the box is emitted by exactly one tile) and add
+// the sums to job.acc -- statistics that share this decode.  ACC 1 needs
+// max|q| < 2^16 (squares fit 32 bits), ACC 2 takes any q.
 template <int S, int VIA, int OP, typename T>
 __device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint32_t* smem, int* status) {
   const StreamView& v = job.v;
@@ -260,7 +264,6 @@ __device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint
   G g1[kTy];
 #pragma unroll
   for (int i = 0; i < kTy; ++i) { qm2[i] = V(0); qm1[i] = V(0); g1[i] = G(0); }
-
   auto emit = [&](int64_t o, int i, N nz) {
     const int64_t row = ((o - b.z0) * by + (y0 + i - b.y0)) * bx;
     T r;
@@ -358,17 +361,349 @@ __device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint
   }
 }
 
+// ---- fused, quantized route (D_q) --------------------------------------------------
+// The same z-march and pipeline as above, laid out for the integer route:
+//  * A row of the LDS plane holds the tile's columns x0-1 .. x0+kTx plus S-1
+//    spare columns on each side, so every slot of every block covering the
+//    row has a place: the decoder writes whole blocks, with no range tests.
+//    Column e of a row sits at e + e/32 (one pad word per 32 columns, so the
+//    64 lanes of a wave, each writing slot j of its own block, hit distinct
+//    banks).  When rows start on a 32-column boundary (d.x and the box's x0
+//    multiples of 32) the pad positions are compile-time offsets.
+//  * Domain edges use ghost cells: q_{-1} = 2 q_0 - q_1 (and the mirror at
+//    the far end) makes the central numerator q_{+1} - q_{-1} equal the
+//    one-sided 2 (q_1 - q_0) exactly in integers, and a length-1 axis gets
+//    q itself (numerator 0).  Each thread writes the ghosts of its own
+//    column (y, and x at the two edge columns) after the decode barrier, so
+//    the stencil has no per-row edge tests; z edges are patched once per
+//    tile in registers.
+//  * The squared magnitude is summed exactly in integers when max|q| < 8192
+//    (|numerator| < 2^15, three squares < 2^32) for binary32 output, and in
+//    binary64 for binary64 output (exact while the sum is below 2^53, that is
+//    max|q| < 2^23); binary32 output with larger q sums in binary32.
+//  * ACC: exact sums of q and q^2 over the tile's own elements for
+//    statistics sharing this decode (ACC 1: max|q| < 2^16 and tz <= 2048, so
+//    a thread's sum of q fits 32 bits; ACC 2: any q).
+template <int S>
+struct QRow {
+  static constexpr int kOff = S - 1;  // extended column of tile column 0 (x = x0 - 1)
+  static constexpr int kExt = kCols + 2 * (S - 1);
+  static constexpr int kPitch = kExt + (kExt >> 5) + 1;
+  static __host__ __device__ constexpr int at(int e) { return e + (e >> 5); }
+};
+
+// Decode one staged block (column 'col', stride kFusedThreads) and write its
+// S values of q to dst[j + j/32 + pad_j], pad_j = ((j & 31) >= jx) (jx = 32:
+// none).  Reads are issued eight slots at a time, ahead of the writes.
+template <int S, bool ALIGNED>
+__device__ __forceinline__ void decode_block_q(const uint32_t* col, int w, int q0, int* dst, int jx) {
+  const uint32_t sg0 = col[0];
+  const uint32_t sg1 = S == 64 ? col[kFusedThreads] : 0u;
+  const uint32_t* mag = col + (S / 32) * kFusedThreads;
+  int* dst1 = dst + 1;
+  int q = q0;
+  int wg = w;
+#pragma unroll
+  for (int g = 0; g < S; g += 8) {
+    // an empty asm that "changes" wg keeps the compiler from computing the
+    // bit positions of all S slots up front (S live registers)
+    asm volatile("" : "+v"(wg));
+    uint32_t lo[8], hi[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t pos = (uint32_t)(g + u) * (uint32_t)wg;
+      const uint32_t* a = mag + (pos >> 5) * kFusedThreads;
+      lo[u] = a[0];
+      hi[u] = a[kFusedThreads];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = g + u;
+      const uint32_t pos = (uint32_t)j * (uint32_t)wg;
+      const uint32_t m = __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(hi[u], lo[u], pos), 0u, (uint32_t)wg);
+      const int sg = __builtin_amdgcn_sbfe((int)(j < 32 ? sg0 : sg1), (uint32_t)(j & 31), 1u);
+      q += (int)(m ^ (uint32_t)sg) - sg;
+      if constexpr (ALIGNED) {
+        dst[j + (j >> 5)] = q;
+      } else {
+        int* d = ((j & 31) >= jx) ? dst1 : dst;
+        d[j + (j >> 5)] = q;
+      }
+    }
+  }
+}
+
+template <int S, int OP, typename T, int ACC, bool SMALL>
+__device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, uint32_t* smem, int* status) {
+  static_assert(!SMALL || (OP == 4 && sizeof(T) == 4), "32-bit squared sums: binary32 magnitude only");
+  using R = QRow<S>;
+  constexpr int P = R::kPitch;
+  const StreamView& v = job.v;
+  const uint16_t* __restrict__ rel = job.rel;
+  const Dims3 d = job.d;
+  const Box3 b = job.b;
+  const int axis = job.axis, tz = job.tz, kmax = job.kmax;
+  const double halfq = job.halfq;
+  T* __restrict__ out = (T*)job.out;
+  constexpr int NBR = (kCols + S - 2) / S + 1;  // max blocks covering one decoded row
+  constexpr int PF = 16 * (S / 32);             // payload words prefetched per thread
+  static_assert(kRows * NBR <= kFusedThreads, "one decode item per thread");
+  int* const pl = (int*)smem;
+  uint32_t* stage = smem + kRows * P;
+  const int t = threadIdx.x;
+
+  const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0;
+  const int64_t ntx = (bx + kTx - 1) / kTx, nty = (by + kTy - 1) / kTy;
+  int64_t blk = tile;
+  const int64_t tx = blk % ntx;
+  blk /= ntx;
+  const int64_t ty = blk % nty;
+  const int64_t tzi = blk / nty;
+  const int64_t x0 = b.x0 + tx * kTx, y0 = b.y0 + ty * kTy, z0 = b.z0 + tzi * tz;
+  const int xs = (int)min((int64_t)kTx, b.x1 - x0), ys = (int)min((int64_t)kTy, b.y1 - y0);
+  const int64_t zs = min((int64_t)tz, b.z1 - z0);
+  const int64_t cA = max((int64_t)0, x0 - 1), cB = min(d.x, x0 + xs + 1);
+  const int64_t rA = max((int64_t)0, y0 - 1), rB = min(d.y, y0 + ys + 1);
+  const int64_t za = max((int64_t)0, z0 - 1), zb = min(d.z, z0 + zs + 1);
+  const int nrows = (int)(rB - rA);
+  const T h = (T)halfq;
+  const bool need_z = OP == 4 || axis == 0, need_y = OP == 4 || axis == 1, need_x = OP == 4 || axis == 2;
+  const bool aligned = (d.x & 31) == 0 && (x0 & 31) == 0;
+
+  // decode item of this thread: decoded row dr, dk-th block of the row
+  const int dr = t / NBR, dk = t % NBR;
+  const int64_t dy = rA + dr;
+  const bool decoder = dr < nrows;
+  int* const prow = pl + (int)(dy - (y0 - 1)) * P;
+  uint32_t* col = stage + t;
+
+  struct Meta {
+    int w, q0, words, e0;
+    uint64_t off;
+    bool valid;
+  };
+  auto meta_of = [&](int64_t p) {
+    Meta m{0, 0, 0, 0, 0, false};
+    if (decoder && p < zb) {
+      const int64_t f = (p * d.y + dy) * d.x;
+      const int64_t bA = (f + cA) / S, bB = (f + cB - 1) / S, bk = bA + dk;
+      if (bk <= bB) {
+        m.valid = true;
+        m.w = (int)v.width[bk];
+        m.q0 = v.q0[bk];
+        m.off = v.chunk_off[bk / kChunkBlocks] + rel[bk];
+        m.e0 = (int)(bk * S - f);
+      }
+    }
+    return m;
+  };
+  auto check = [&](Meta& m) {
+    if (!m.valid) return;
+    m.words = block_words<S>(m.w);
+    if (m.w > kMaxWidth || m.words > kmax || m.off + (uint64_t)m.words > v.payload_words) {
+      record_status(status, kErrBadStream);
+      m.w = 0;
+      m.words = 0;
+    }
+  };
+  auto stage_rest = [&](const Meta& m, int from) {
+    const uint32_t* src = v.payload + m.off;
+    for (int k = from; k < m.words; ++k) col[k * kFusedThreads] = src[k];
+  };
+  auto decode = [&](const Meta& m) {
+    if (!m.valid) return;
+    const int cb = m.e0 - (int)(x0 - 1) + R::kOff;  // extended column of slot 0 (>= 0)
+    int* dst = prow + R::at(cb);
+    if (aligned) decode_block_q<S, true>(col, m.w, m.q0, dst, 32);
+    else decode_block_q<S, false>(col, m.w, m.q0, dst, 32 - (cb & 31));
+  };
+
+  // stencil column of this thread and its neighbours (row-relative offsets)
+  const int ec = R::at(t + 1 + R::kOff), em = R::at(t + R::kOff), ep = R::at(t + 2 + R::kOff);
+  const int64_t x = x0 + t;
+  const bool active = t < xs;
+  const bool ylo = y0 == 0, yhi = y0 + ys == d.y, xlo = x == 0, xhi = x == d.x - 1;
+  const bool y2 = d.y >= 2, x2 = d.x >= 2;
+
+  // per row: q of the two previous planes; in-plane part of the previous
+  // plane (squared sum, or the one numerator of a single derivative)
+  using G = typename std::conditional<OP == 3, int, typename std::conditional<SMALL, uint32_t, T>::type>::type;
+  int qm2[kTy], qm1[kTy];
+  G g1[kTy];
+#pragma unroll
+  for (int i = 0; i < kTy; ++i) { qm2[i] = 0; qm1[i] = 0; g1[i] = G(0); }
+  using S1 = typename std::conditional<ACC == 1, int, int64_t>::type;
+  S1 as1 = 0;
+  uint64_t as2s = 0;
+  U128 as2 = {0, 0};
+
+  // one output value from the numerators (in-plane part already squared)
+  auto value = [&](int i, int nz) -> T {
+    if constexpr (OP == 3) {
+      const int n = axis == 0 ? nz : (int)g1[i];
+      return (T)n * h;
+    } else if constexpr (SMALL) {
+      const uint32_t s2 = g1[i] + (uint32_t)__mul24(nz, nz);
+      return vsqrt((float)s2) * h;
+    } else {
+      const T dz = (T)nz;
+      return vsqrt(g1[i] + dz * dz) * h;
+    }
+  };
+  auto accumulate = [&](int q) {
+    if constexpr (ACC == 1) {
+      as1 += q;
+      as2s += (uint32_t)__mul24(q, q);
+    } else if constexpr (ACC == 2) {
+      as1 += q;
+      add_u64(as2, (uint64_t)((int64_t)q * (int64_t)q));
+    }
+  };
+
+  // stencil over the rows of plane p (in LDS); emits plane o = p - 1
+  auto rows = [&](int64_t p) {
+    const int64_t o = p - 1;
+    const bool emit = o >= z0 && o < z0 + zs;
+    // ghosts of this thread's column
+    if (ylo) pl[ec] = y2 ? 2 * pl[P + ec] - pl[2 * P + ec] : pl[P + ec];
+    if (yhi) {
+      int* r = pl + ys * P + ec;
+      r[P] = y2 ? 2 * r[0] - r[-P] : r[0];
+    }
+    if (need_x && (xlo || xhi)) {
+#pragma unroll
+      for (int i = 0; i < kTy; ++i) {
+        int* r = pl + (i + 1) * P;
+        if (xlo) r[em] = x2 ? 2 * r[ec] - r[ep] : r[ec];
+        if (xhi) r[ep] = x2 ? 2 * r[ec] - r[em] : r[ec];
+      }
+    }
+    // the field's first plane: ghost plane q_{-1} = 2 q_0 - q_1 (or q_0)
+    if (o == 0 && need_z) {
+#pragma unroll
+      for (int i = 0; i < kTy; ++i) {
+        const int c1 = pl[(i + 1) * P + ec];
+        qm2[i] = d.z >= 2 ? 2 * qm1[i] - c1 : qm1[i];
+      }
+    }
+    T* orow = out + ((o - b.z0) * by + (y0 - b.y0)) * bx + (x0 - b.x0);
+#pragma unroll
+    for (int hh = 0; hh < kTy; hh += kTy / 4) {
+      constexpr int H = kTy / 4;
+      int cv[H + 2], xm[H], xp[H];
+#pragma unroll
+      for (int k = 0; k < H + 2; ++k) cv[k] = pl[(hh + k) * P + ec];
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        xm[k] = need_x ? pl[(hh + k + 1) * P + em] : 0;
+        xp[k] = need_x ? pl[(hh + k + 1) * P + ep] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        const int i = hh + k;
+        const int qc = cv[k + 1];
+        if (emit && i < ys) {
+          const int nz = need_z ? qc - qm2[i] : 0;
+          T* rowp = orow + (int64_t)i * bx;
+          rowp[(uint32_t)t] = value(i, nz);
+          accumulate(qm1[i]);
+        }
+        const int nx = xp[k] - xm[k], ny = need_y ? cv[k + 2] - cv[k] : 0;
+        qm2[i] = qm1[i];
+        qm1[i] = qc;
+        if constexpr (OP == 3) g1[i] = axis == 1 ? ny : nx;
+        else if constexpr (SMALL) g1[i] = (uint32_t)__mul24(nx, nx) + (uint32_t)__mul24(ny, ny);
+        else g1[i] = (T)nx * (T)nx + (T)ny * (T)ny;
+      }
+    }
+  };
+
+  // prologue: plane za staged, metadata of za+1 in flight
+  Meta cur = meta_of(za);
+  check(cur);
+  stage_rest(cur, 0);
+  Meta nxt = meta_of(za + 1);
+
+  for (int64_t p = za; p < zb; ++p) {
+    decode(cur);  // A
+    __syncthreads();
+    // B: prefetch plane p+1's payload, request plane p+2's metadata
+    check(nxt);
+    uint32_t pw[PF];
+    {
+      const uint32_t* src = v.payload + nxt.off;
+#pragma unroll
+      for (int k = 0; k < PF; ++k) pw[k] = (k < nxt.words) ? src[k] : 0u;
+    }
+    const Meta nn = meta_of(p + 2);
+    if (active) rows(p);  // C
+    // D: plane p+1's words into this thread's staging column
+#pragma unroll
+    for (int k = 0; k < PF; ++k)
+      if (k < nxt.words) col[k * kFusedThreads] = pw[k];
+    stage_rest(nxt, PF);
+    cur = nxt;
+    nxt = nn;
+    __syncthreads();
+  }
+  // the field's last plane has no plane after it: one-sided (or 0 if nz = 1)
+  if (active && z0 + zs == zb) {
+    const int64_t o = zb - 1;
+    T* orow = out + ((o - b.z0) * by + (y0 - b.y0)) * bx + (x0 - b.x0);
+#pragma unroll
+    for (int i = 0; i < kTy; ++i) {
+      if (i < ys) {
+        const int nz = (need_z && d.z >= 2) ? 2 * (qm1[i] - qm2[i]) : 0;
+        T* rowp = orow + (int64_t)i * bx;
+        rowp[(uint32_t)t] = value(i, nz);
+        accumulate(qm1[i]);
+      }
+    }
+  }
+  if constexpr (ACC != 0) {
+    const int64_t cnt = active ? (int64_t)ys * zs : 0;
+    if constexpr (ACC == 1) as2.lo = as2s;
+    acc_add_wave((BatchAcc*)job.acc, (int64_t)as1, cnt, as2);
+  }
+}
+
+// One tile of a job: the quantized route by the integer tile (32-bit squared
+// sums when the stream's max|q| allows), the float route by the float tile.
+template <int S, int VIA, int OP, typename T, int ACC>
+__device__ __forceinline__ void any_tile(const GradJob& job, int64_t tile, uint32_t* smem, int* status) {
+  if constexpr (VIA == 3) {
+    if constexpr (OP == 4 && sizeof(T) == 4) {
+      if (job.v.max_abs_q < 8192u) {
+        grad_tile_q<S, OP, T, ACC, true>(job, tile, smem, status);
+        return;
+      }
+    }
+    grad_tile_q<S, OP, T, ACC, false>(job, tile, smem, status);
+  } else {
+    static_assert(ACC == 0, "shared statistics need the quantized route");
+    grad_tile<S, VIA, OP, T>(job, tile, smem, status);
+  }
+}
+
+// Four waves per SIMD (128 registers) for the binary32 quantized route with
+// S = 32; the others (binary64 squared sums, twice the prefetch for S = 64)
+// take the registers they need.
+template <int S, int VIA, typename T>
+constexpr int kGradWaves = (S == 32 && VIA == 3 && sizeof(T) == 4) ? 4 : 1;
+
 template <int S, int VIA, int OP, typename T>
-__global__ void __launch_bounds__(kFusedThreads) k_grad_fused(GradJob job, int* status) {
+__global__ void __launch_bounds__(kFusedThreads, (kGradWaves<S, VIA, T>)) k_grad_fused(GradJob job, int* status) {
   extern __shared__ uint32_t smem[];
-  grad_tile<S, VIA, OP, T>(job, blockIdx.x, smem, status);
+  any_tile<S, VIA, OP, T, 0>(job, blockIdx.x, smem, status);
 }
 
 // Persistent batch: the tiles of every job of one kernel variant, listed in
 // a device table (count and tile offsets read from device memory, so a
-// captured graph can be replayed with a new table).
-template <int S, int VIA, int OP, typename T>
-__global__ void __launch_bounds__(kFusedThreads) k_batch_grad(const GradJob* __restrict__ jobs,
+// captured graph can be replayed with a new table).  ACC is the variant's
+// shared-statistics mode (one instantiation each, so a variant without
+// statistics keeps the plain kernel's registers and code size).
+template <int S, int VIA, int OP, typename T, int ACC>
+__global__ void __launch_bounds__(kFusedThreads, (kGradWaves<S, VIA, T>)) k_batch_grad(const GradJob* __restrict__ jobs,
                                                               const int64_t* __restrict__ tile_start,
                                                               const int64_t* __restrict__ counts, int* status) {
   extern __shared__ uint32_t smem[];
@@ -381,7 +716,8 @@ __global__ void __launch_bounds__(kFusedThreads) k_batch_grad(const GradJob* __r
       if (tile_start[mid] <= tile) lo = mid;
       else hi = mid - 1;
     }
-    grad_tile<S, VIA, OP, T>(jobs[lo], tile - tile_start[lo], smem, status);
+    const GradJob job = load_job(jobs, lo);
+    any_tile<S, VIA, OP, T, ACC>(job, tile - tile_start[lo], smem, status);
   }
 }
 
@@ -490,18 +826,18 @@ hipError_t run_buf(const void* buf, int op, int axis, const OpTarget& t, double 
   return hipGetLastError();
 }
 
+size_t grad_lds_bytes(int S, int dtype, int via, int kmax);
+
 template <int S, int VIA, typename T>
 hipError_t run_fused(const StreamView& v, int op, int axis, const OpTarget& t, void* out, uint8_t* ws,
                      hipStream_t s) {
-  using V = typename std::conditional<VIA == 3, int, T>::type;
   int* status = (int*)ws;
   uint16_t* rel = (uint16_t*)(ws + kGradIndexOff);
   hipError_t e = launch_block_index(v, rel, s);
   if (e != hipSuccess) return e;
   const Box3& b = t.box;
   const int kmax = kmax_for(v);
-  const size_t plane_bytes = ((kRows * kPitch * sizeof(V) + 3) / 4) * 4;
-  const size_t lds = plane_bytes + (size_t)(kmax + 1) * kFusedThreads * sizeof(uint32_t);
+  const size_t lds = grad_lds_bytes(S, v.dtype, VIA, kmax);
   const int64_t ntx = (b.x1 - b.x0 + kTx - 1) / kTx, nty = (b.y1 - b.y0 + kTy - 1) / kTy;
   const int64_t bz = b.z1 - b.z0;
   int64_t tz = bz;
@@ -558,47 +894,61 @@ hipError_t fast_delta(const int32_t* p, const StreamView& v, const OpTarget& t, 
                       : run_fast_delta<64, FROM_STREAM, double>(p, v, t, out, status, s);
 }
 
-size_t grad_lds_bytes(int dtype, int via, int kmax) {
-  const size_t vsz = (via == 4 && dtype == 2) ? 8 : 4;
-  return ((kRows * kPitch * vsz + 3) / 4) * 4 + (size_t)(kmax + 1) * kFusedThreads * sizeof(uint32_t);
+// LDS of one gradient tile: the plane (integer rows of QRow for the quantized
+// route, padded rows of T for the float route) and the staging columns.
+size_t grad_lds_bytes(int S, int dtype, int via, int kmax) {
+  const size_t stage = (size_t)(kmax + 1) * kFusedThreads * sizeof(uint32_t);
+  if (via == 3) return (size_t)kRows * (S == 32 ? QRow<32>::kPitch : QRow<64>::kPitch) * sizeof(int) + stage;
+  const size_t vsz = dtype == 2 ? 8 : 4;
+  return ((kRows * kPitch * vsz + 3) / 4) * 4 + stage;
 }
 
-template <int S, int VIA, int OP, typename T>
+template <int S, int VIA, int OP, typename T, int ACC>
 hipError_t batch_grad_v(const GradJob* jobs, const int64_t* tile_start, const int64_t* counts, int kmax, int grid,
                         int* status, hipStream_t s) {
-  const size_t lds = grad_lds_bytes(sizeof(T) == 4 ? 1 : 2, VIA, kmax);
-  hipLaunchKernelGGL((k_batch_grad<S, VIA, OP, T>), dim3(grid), dim3(kFusedThreads), lds, s, jobs, tile_start, counts,
-                     status);
+  const size_t lds = grad_lds_bytes(S, sizeof(T) == 4 ? 1 : 2, VIA, kmax);
+  hipLaunchKernelGGL((k_batch_grad<S, VIA, OP, T, ACC>), dim3(grid), dim3(kFusedThreads), lds, s, jobs, tile_start,
+                     counts, status);
   return hipGetLastError();
 }
 
-template <int S, int VIA, int OP>
+template <int S, int VIA, int OP, int ACC>
 hipError_t batch_grad_t(int dtype, const GradJob* jobs, const int64_t* tile_start, const int64_t* counts, int kmax,
                         int grid, int* status, hipStream_t s) {
-  return dtype == 1 ? batch_grad_v<S, VIA, OP, float>(jobs, tile_start, counts, kmax, grid, status, s)
-                    : batch_grad_v<S, VIA, OP, double>(jobs, tile_start, counts, kmax, grid, status, s);
+  return dtype == 1 ? batch_grad_v<S, VIA, OP, float, ACC>(jobs, tile_start, counts, kmax, grid, status, s)
+                    : batch_grad_v<S, VIA, OP, double, ACC>(jobs, tile_start, counts, kmax, grid, status, s);
+}
+
+template <int S, int OP>
+hipError_t batch_grad_acc(int acc, int dtype, const GradJob* jobs, const int64_t* tile_start, const int64_t* counts,
+                          int kmax, int grid, int* status, hipStream_t s) {
+  return acc == 1   ? batch_grad_t<S, 3, OP, 1>(dtype, jobs, tile_start, counts, kmax, grid, status, s)
+         : acc == 2 ? batch_grad_t<S, 3, OP, 2>(dtype, jobs, tile_start, counts, kmax, grid, status, s)
+                    : batch_grad_t<S, 3, OP, 0>(dtype, jobs, tile_start, counts, kmax, grid, status, s);
 }
 
 template <int S>
-hipError_t batch_grad_s(int via, int op, int dtype, const GradJob* jobs, const int64_t* tile_start,
+hipError_t batch_grad_s(int via, int op, int dtype, int acc, const GradJob* jobs, const int64_t* tile_start,
                         const int64_t* counts, int kmax, int grid, int* status, hipStream_t s) {
   if (via == 3)
-    return op == 3 ? batch_grad_t<S, 3, 3>(dtype, jobs, tile_start, counts, kmax, grid, status, s)
-                   : batch_grad_t<S, 3, 4>(dtype, jobs, tile_start, counts, kmax, grid, status, s);
-  return op == 3 ? batch_grad_t<S, 4, 3>(dtype, jobs, tile_start, counts, kmax, grid, status, s)
-                 : batch_grad_t<S, 4, 4>(dtype, jobs, tile_start, counts, kmax, grid, status, s);
+    return op == 3 ? batch_grad_acc<S, 3>(acc, dtype, jobs, tile_start, counts, kmax, grid, status, s)
+                   : batch_grad_acc<S, 4>(acc, dtype, jobs, tile_start, counts, kmax, grid, status, s);
+  if (acc) return hipErrorInvalidValue;
+  return op == 3 ? batch_grad_t<S, 4, 3, 0>(dtype, jobs, tile_start, counts, kmax, grid, status, s)
+                 : batch_grad_t<S, 4, 4, 0>(dtype, jobs, tile_start, counts, kmax, grid, status, s);
 }
 
 }  // namespace
 
 uint64_t grad_workspace_bytes(int64_t nb) { return kGradIndexOff + ((2 * (uint64_t)nb + 255) / 256) * 256; }
 
-size_t batch_grad_lds(int dtype, int via, int kmax) { return grad_lds_bytes(dtype, via, kmax); }
+size_t batch_grad_lds(int S, int dtype, int via, int kmax) { return grad_lds_bytes(S, dtype, via, kmax); }
 
-hipError_t launch_batch_grad(int S, int via, int op, int dtype, const GradJob* jobs, const int64_t* tile_start,
-                             const int64_t* counts, int kmax, int grid, int* status, hipStream_t s) {
-  return S == 32 ? batch_grad_s<32>(via, op, dtype, jobs, tile_start, counts, kmax, grid, status, s)
-                 : batch_grad_s<64>(via, op, dtype, jobs, tile_start, counts, kmax, grid, status, s);
+hipError_t launch_batch_grad(int S, int via, int op, int dtype, int acc, const GradJob* jobs,
+                             const int64_t* tile_start, const int64_t* counts, int kmax, int grid, int* status,
+                             hipStream_t s) {
+  return S == 32 ? batch_grad_s<32>(via, op, dtype, acc, jobs, tile_start, counts, kmax, grid, status, s)
+                 : batch_grad_s<64>(via, op, dtype, acc, jobs, tile_start, counts, kmax, grid, status, s);
 }
 
 int grad_tiles(const Box3& b, int tz) {

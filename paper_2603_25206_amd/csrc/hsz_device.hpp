@@ -13,6 +13,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include <type_traits>
@@ -148,6 +149,138 @@ __device__ __forceinline__ void add_u128(U128& a, U128 b) {
   a.hi += b.hi + (t < b.lo);
   a.lo = t;
 }
+
+// ---- job tables in device memory ------------------------------------------------
+// A pointer loaded from a device-side job table has an unknown address space
+// to the compiler, which then emits flat loads and stores.  Flat accesses
+// count against the LDS wait counter too, so every LDS wait also waits for
+// outstanding memory traffic and prefetching stops overlapping.  The mirror
+// structs below have the same layout as the host-built ones with the
+// pointers typed as global; a kernel reads its table entry through them and
+// converts, and every access derived from that entry is emitted as global.
+#define HSZ_GLOBAL __attribute__((address_space(1)))
+
+struct StreamViewG {
+  const HSZ_GLOBAL uint8_t* base;
+  const HSZ_GLOBAL uint64_t* chunk_off;
+  const HSZ_GLOBAL int32_t* q0;
+  const HSZ_GLOBAL uint8_t* width;
+  const HSZ_GLOBAL uint32_t* payload;
+  uint64_t payload_words;
+  int64_t n, nb, nchunks;
+  int block;
+  int dtype;
+  double quantum;
+  uint32_t max_abs_q;
+};
+static_assert(sizeof(StreamViewG) == sizeof(StreamView), "mirror layout");
+static_assert(offsetof(StreamViewG, payload_words) == offsetof(StreamView, payload_words), "mirror layout");
+static_assert(offsetof(StreamViewG, max_abs_q) == offsetof(StreamView, max_abs_q), "mirror layout");
+
+struct GradJobG {
+  StreamViewG v;
+  const HSZ_GLOBAL uint16_t* rel;
+  Dims3 d;
+  Box3 b;
+  int axis, tz, kmax;
+  double halfq;
+  HSZ_GLOBAL void* out;
+  HSZ_GLOBAL void* acc;
+  int acc_mode;
+};
+static_assert(sizeof(GradJobG) == sizeof(GradJob), "mirror layout");
+static_assert(offsetof(GradJobG, acc_mode) == offsetof(GradJob, acc_mode), "mirror layout");
+static_assert(offsetof(GradJobG, rel) == offsetof(GradJob, rel), "mirror layout");
+static_assert(offsetof(GradJobG, halfq) == offsetof(GradJob, halfq), "mirror layout");
+static_assert(offsetof(GradJobG, out) == offsetof(GradJob, out), "mirror layout");
+
+struct StatsJobG {
+  StreamViewG v;
+  Rows rows;
+  int64_t per_row;
+  int32_t op, via, whole, acc;
+  HSZ_GLOBAL void* out;
+  const HSZ_GLOBAL uint16_t* rel;
+};
+static_assert(sizeof(StatsJobG) == sizeof(StatsJob), "mirror layout");
+static_assert(offsetof(StatsJobG, per_row) == offsetof(StatsJob, per_row), "mirror layout");
+static_assert(offsetof(StatsJobG, out) == offsetof(StatsJob, out), "mirror layout");
+static_assert(offsetof(StatsJobG, rel) == offsetof(StatsJob, rel), "mirror layout");
+
+__device__ __forceinline__ StreamView view_of(const StreamViewG& g) {
+  StreamView v;
+  v.base = (const uint8_t*)g.base;
+  v.chunk_off = (const uint64_t*)g.chunk_off;
+  v.q0 = (const int32_t*)g.q0;
+  v.width = (const uint8_t*)g.width;
+  v.payload = (const uint32_t*)g.payload;
+  v.payload_words = g.payload_words;
+  v.n = g.n;
+  v.nb = g.nb;
+  v.nchunks = g.nchunks;
+  v.block = g.block;
+  v.dtype = g.dtype;
+  v.quantum = g.quantum;
+  v.max_abs_q = g.max_abs_q;
+  return v;
+}
+
+// Table entry k, read as uniform (scalar) loads with global pointers.
+__device__ __forceinline__ GradJob load_job(const GradJob* jobs, int k) {
+  const GradJobG g = ((const GradJobG*)jobs)[k];
+  GradJob j;
+  j.v = view_of(g.v);
+  j.rel = (const uint16_t*)g.rel;
+  j.d = g.d;
+  j.b = g.b;
+  j.axis = g.axis;
+  j.tz = g.tz;
+  j.kmax = g.kmax;
+  j.halfq = g.halfq;
+  j.out = (void*)g.out;
+  j.acc = (void*)g.acc;
+  j.acc_mode = g.acc_mode;
+  return j;
+}
+
+__device__ __forceinline__ StatsJob load_job(const StatsJob* jobs, int k) {
+  const StatsJobG g = ((const StatsJobG*)jobs)[k];
+  StatsJob j;
+  j.v = view_of(g.v);
+  j.rows = g.rows;
+  j.per_row = g.per_row;
+  j.op = g.op;
+  j.via = g.via;
+  j.whole = g.whole;
+  j.acc = g.acc;
+  j.out = (void*)g.out;
+  j.rel = (const uint16_t*)g.rel;
+  return j;
+}
+
+// Add a wave's exact sums (s1, count, s2 as 128 bits) to a batch
+// accumulator: reduce over the wave, then lane 0 adds with 64-bit atomics,
+// carrying the low half of s2 into the high half by hand.
+__device__ __forceinline__ void acc_add_wave(BatchAcc* acc, int64_t s1, int64_t cnt, U128 s2) {
+  s1 = wave_sum64(s1);
+  cnt = wave_sum64(cnt);
+  for (int m = 32; m >= 1; m >>= 1) {
+    U128 o;
+    o.lo = __shfl_xor(s2.lo, m);
+    o.hi = __shfl_xor(s2.hi, m);
+    add_u128(s2, o);
+  }
+  if (lane_id() == 0) {
+    atomicAdd((unsigned long long*)&acc->s1, (unsigned long long)s1);
+    atomicAdd((unsigned long long*)&acc->cnt, (unsigned long long)cnt);
+    const unsigned long long old = atomicAdd((unsigned long long*)&acc->s2lo, (unsigned long long)s2.lo);
+    const uint64_t carry = (old + s2.lo < old) ? 1u : 0u;
+    if (s2.hi + carry) atomicAdd((unsigned long long*)&acc->s2hi, (unsigned long long)(s2.hi + carry));
+  }
+}
+
+// Index of the calling wave within its workgroup, as a wave-uniform value.
+__device__ __forceinline__ int wave_in_group() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
 
 // ---- chunk staging -----------------------------------------------------------
 // Per-lane metadata of one block of a chunk.

@@ -90,7 +90,8 @@ struct StatsJob {
   StreamView v;
   Rows rows;        // the box as contiguous rows
   int64_t per_row;  // blocks a row can touch
-  int32_t op, via, whole, pad;
+  int32_t op, via, whole;
+  int32_t acc;          // accumulator slot (its own index, or the slot it shares)
   void* out;            // hsz_stats (device)
   const uint16_t* rel;  // block index, or null (offsets from the widths)
 };
@@ -121,13 +122,20 @@ struct GradJob {
   int axis, tz, kmax;
   double halfq;
   void* out;
+  // Statistics sharing this job's decode (batches only): the exact sums of
+  // q over the box go to *acc.  acc_mode 0: none; 1: max|q| < 2^16 (32-bit
+  // squares); 2: any q.
+  void* acc;
+  int acc_mode;
 };
 
 hipError_t launch_batch_block_index(const GradJob* jobs, const int64_t* chunk_start, const int64_t* counts, int grid,
                                     hipStream_t s);
-hipError_t launch_batch_grad(int S, int via, int op, int dtype, const GradJob* jobs, const int64_t* tile_start,
-                             const int64_t* counts, int kmax, int grid, int* status, hipStream_t s);
-size_t batch_grad_lds(int dtype, int via, int kmax);
+// acc: the variant's shared-statistics mode (GradJob::acc_mode of all its jobs)
+hipError_t launch_batch_grad(int S, int via, int op, int dtype, int acc, const GradJob* jobs,
+                             const int64_t* tile_start, const int64_t* counts, int kmax, int grid, int* status,
+                             hipStream_t s);
+size_t batch_grad_lds(int S, int dtype, int via, int kmax);
 int grad_tiles(const Box3& b, int tz);  // tiles of one fused-gradient job
 int grad_kmax(const StreamView& v);     // staging rows a stream needs
 int stats_kmax(const StreamView& v);

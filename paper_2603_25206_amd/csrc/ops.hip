@@ -57,7 +57,7 @@ __device__ void store_int_partial(IntAcc a, Partial* parts) {
     o.hi = __shfl_xor(s2.hi, m);
     add_u128(s2, o);
   }
-  const int wv = threadIdx.x / kWave;
+  const int wv = wave_in_group();
   if (lane_id() == 0) { ss1[wv] = s1; scnt[wv] = cnt; slo[wv] = s2.lo; shi[wv] = s2.hi; }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -78,7 +78,7 @@ __device__ void store_f64_partial(double f1, double f2, int64_t cnt, double K, P
   f1 = wave_sum_f64(f1);
   f2 = wave_sum_f64(f2);
   cnt = wave_sum64(cnt);
-  const int wv = threadIdx.x / kWave;
+  const int wv = wave_in_group();
   if (lane_id() == 0) { sf1[wv] = f1; sf2[wv] = f2; scnt[wv] = cnt; }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -293,7 +293,7 @@ template <int S, int VIA, int OP, typename T, bool WHOLE>
 __global__ void __launch_bounds__(kThreads) k_stats_fused(StreamView v, Segs<S> segs, int kmax, const double* Kp,
                                                          Partial* parts, int* status) {
   extern __shared__ uint32_t smem[];
-  const int wv = threadIdx.x / kWave;
+  const int wv = wave_in_group();
   uint32_t* tile = smem + wv * (kmax + 1) * kWave;
   const int l = lane_id();
   IntAcc acc;
@@ -438,85 +438,97 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(const Partial* parts, 
 // job's accumulator with 64-bit atomics when the job changes (the 128-bit
 // sum of q^2 carries by hand).  Integer atomics make the totals exact and
 // independent of the schedule, so a job's result equals the one-op result.
+// One unit of a statistics job: MODE 0 = weighted delta sum (mean through
+// D_p), 1 = sum of q, 2 = sums of q and q^2.
+template <int S, int MODE, bool WHOLE>
+__device__ __forceinline__ void stats_unit(const StatsJob& J, int64_t lu, uint32_t* tile, int kmax, IntAcc& a,
+                                           int* status) {
+  const int l = lane_id();
+  int w = 0, q0 = 0, sa = 0, sz = -1;
+  if constexpr (WHOLE) {
+    LaneBlock lb;
+    stage_chunk<S>(J.v.width, J.v.q0, J.v.chunk_off, J.v.payload, J.v.payload_words, J.v.n, J.v.nb, lu, tile, kmax,
+                   lb, status);
+    w = lb.w; q0 = lb.q0; sz = lb.len - 1;
+  } else {
+    Segs<S> segs;
+    segs.rows = J.rows;
+    segs.per_row = J.per_row;
+    int64_t b;
+    if (lu * kWave + l < segs.count() && segs.get(lu * kWave + l, b, sa, sz))
+      w = stage_block<S, kWave>(J.v.width, J.v.q0, J.v.chunk_off, J.v.payload, J.v.payload_words, J.v.nb, b,
+                                tile + l, kmax, q0, status, J.rel);
+    else
+      sz = -1;
+  }
+  if (sz < 0) return;
+  if constexpr (MODE == 0) {
+    int64_t s = (int64_t)(sz - sa + 1) * q0;
+    decode_lane_block<S>(tile + l, w, q0, [&](int j, int p, int) {
+      if (j >= 1 && j <= sz) s += (int64_t)(sz - (sa > j ? sa : j) + 1) * p;
+    });
+    a.s1 += s;
+    a.cnt += sz - sa + 1;
+  } else {
+    decode_lane_block<S>(tile + l, w, q0, [&](int j, int, int q) {
+      if (j >= sa && j <= sz) a.add(q, MODE == 2);
+    });
+  }
+}
+
+// ---- batches: many jobs, one persistent launch --------------------------------------
+// Integer-route statistics of every job of one block size.  Units: a chunk
+// of a whole field, or 64 block segments of a box.  A wave walks the units
+// u = wave, wave + W, ... (increasing, so the job index only moves forward);
+// it accumulates per job and adds its sums to the job's accumulator with
+// 64-bit atomics when the job changes (the 128-bit sum of q^2 carries by
+// hand).  Integer atomics make the totals exact and independent of the
+// schedule, so a job's result equals the one-op result.  The job entry and
+// the unit index are wave-uniform, so the table is read with scalar loads.
 template <int S>
 __global__ void __launch_bounds__(kThreads) k_batch_stats(const StatsJob* __restrict__ jobs,
                                                          const int64_t* __restrict__ unit_start,
                                                          const int64_t* __restrict__ counts, int kmax,
                                                          BatchAcc* __restrict__ acc, int* status) {
   extern __shared__ uint32_t smem[];
-  const int wv = threadIdx.x / kWave;
+  const int wv = wave_in_group();
   uint32_t* tile = smem + wv * (kmax + 1) * kWave;
-  const int l = lane_id();
   const int n = (int)counts[0];
   const int64_t total = counts[1];
   const int64_t waves = (int64_t)gridDim.x * kWavesPerGroup;
   IntAcc a;
-  int cur = -1;
-  auto flush = [&](int j) {
-    const int64_t s1 = wave_sum64(a.s1);
-    const int64_t cnt = wave_sum64(a.cnt);
-    U128 s2 = a.s2;
-    for (int m = 32; m >= 1; m >>= 1) {
-      U128 o;
-      o.lo = __shfl_xor(s2.lo, m);
-      o.hi = __shfl_xor(s2.hi, m);
-      add_u128(s2, o);
-    }
-    if (l == 0) {
-      atomicAdd((unsigned long long*)&acc[j].s1, (unsigned long long)s1);
-      atomicAdd((unsigned long long*)&acc[j].cnt, (unsigned long long)cnt);
-      const unsigned long long old = atomicAdd((unsigned long long*)&acc[j].s2lo, (unsigned long long)s2.lo);
-      const uint64_t carry = (old + s2.lo < old) ? 1u : 0u;
-      if (s2.hi + carry) atomicAdd((unsigned long long*)&acc[j].s2hi, (unsigned long long)(s2.hi + carry));
-    }
+  auto flush = [&](int slot) {
+    acc_add_wave(acc + slot, a.s1, a.cnt, a.s2);
     a = IntAcc{};
   };
-  for (int64_t u = blockIdx.x * (int64_t)kWavesPerGroup + wv; u < total; u += waves) {
-    int lo = 0, hi = n - 1;  // last job whose first unit is <= u
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) / 2;
-      if (unit_start[mid] <= u) lo = mid;
-      else hi = mid - 1;
+  int64_t u = blockIdx.x * (int64_t)kWavesPerGroup + wv;
+  if (u >= total) return;
+  int cur = 0;  // last job whose first unit is <= u
+  while (cur + 1 < n && unit_start[cur + 1] <= u) ++cur;
+  StatsJob J = load_job(jobs, cur);
+  int64_t first = unit_start[cur], next = cur + 1 < n ? unit_start[cur + 1] : total;
+  int mode = J.via == 2 && J.op == 1 ? 0 : J.op == 2 ? 2 : 1;
+  for (; u < total; u += waves) {
+    if (u >= next) {
+      flush(J.acc);
+      while (cur + 1 < n && unit_start[cur + 1] <= u) ++cur;
+      J = load_job(jobs, cur);
+      first = unit_start[cur];
+      next = cur + 1 < n ? unit_start[cur + 1] : total;
+      mode = J.via == 2 && J.op == 1 ? 0 : J.op == 2 ? 2 : 1;
     }
-    if (lo != cur) {
-      if (cur >= 0) flush(cur);
-      cur = lo;
-    }
-    const StatsJob& J = jobs[lo];
-    const int64_t lu = u - unit_start[lo];
-    int w = 0, q0 = 0, sa = 0, sz = -1;
+    const int64_t lu = u - first;
     if (J.whole) {
-      LaneBlock lb;
-      stage_chunk<S>(J.v.width, J.v.q0, J.v.chunk_off, J.v.payload, J.v.payload_words, J.v.n, J.v.nb, lu, tile,
-                     kmax, lb, status);
-      w = lb.w; q0 = lb.q0; sz = lb.len - 1;
+      if (mode == 0) stats_unit<S, 0, true>(J, lu, tile, kmax, a, status);
+      else if (mode == 1) stats_unit<S, 1, true>(J, lu, tile, kmax, a, status);
+      else stats_unit<S, 2, true>(J, lu, tile, kmax, a, status);
     } else {
-      Segs<S> segs;
-      segs.rows = J.rows;
-      segs.per_row = J.per_row;
-      int64_t b;
-      if (lu * kWave + l < segs.count() && segs.get(lu * kWave + l, b, sa, sz))
-        w = stage_block<S, kWave>(J.v.width, J.v.q0, J.v.chunk_off, J.v.payload, J.v.payload_words, J.v.nb, b,
-                                  tile + l, kmax, q0, status, J.rel);
-      else
-        sz = -1;
-    }
-    if (sz < 0) continue;
-    if (J.via == 2 && J.op == 1) {
-      int64_t s = (int64_t)(sz - sa + 1) * q0;
-      decode_lane_block<S>(tile + l, w, q0, [&](int j, int p, int) {
-        if (j >= 1 && j <= sz) s += (int64_t)(sz - (sa > j ? sa : j) + 1) * p;
-      });
-      a.s1 += s;
-      a.cnt += sz - sa + 1;
-    } else {
-      const bool sq = J.op == 2;
-      decode_lane_block<S>(tile + l, w, q0, [&](int j, int, int q) {
-        if (j >= sa && j <= sz) a.add(q, sq);
-      });
+      if (mode == 0) stats_unit<S, 0, false>(J, lu, tile, kmax, a, status);
+      else if (mode == 1) stats_unit<S, 1, false>(J, lu, tile, kmax, a, status);
+      else stats_unit<S, 2, false>(J, lu, tile, kmax, a, status);
     }
   }
-  if (cur >= 0) flush(cur);
+  flush(J.acc);
 }
 
 __global__ void k_batch_reset(BatchAcc* acc, int n, int* status) {
@@ -528,7 +540,7 @@ __global__ void k_batch_finalize(const StatsJob* __restrict__ jobs, const int64_
                                  const BatchAcc* __restrict__ acc) {
   const int n = (int)counts[0];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const BatchAcc& a = acc[i];
+    const BatchAcc& a = acc[jobs[i].acc];
     *(StatsOut*)jobs[i].out = stats_from_sums(a.cnt, a.s1, a.s2lo, a.s2hi, jobs[i].op, jobs[i].v.quantum);
   }
 }

@@ -114,6 +114,7 @@ def test_batch_against_oracle(streams):
     {"stats_waves_per_cu": 4, "grad_groups_per_cu": 2, "grad_tz": 8},
     {"stats_waves_per_cu": 16, "grad_groups_per_cu": 6, "grad_tz": 64},
     {"stats_waves_per_cu": 1, "grad_groups_per_cu": 1, "grad_tz": 3},
+    {"stats_waves_per_cu": 8, "grad_groups_per_cu": 4, "grad_tz": 32, "separate_stats": 1},
 ])
 def test_results_independent_of_launch_shape(streams, tune):
     say(f"[case] tuning {tune}")
@@ -144,6 +145,40 @@ def test_plan_replays_and_updates(streams):
         plan.launch()
         got = plan.results()
         for k, (a, b) in enumerate(zip(got, want2)):
+            assert same(a, b), (rep, k)
+        torch.cuda.synchronize()
+    plan.close()
+
+
+def test_shared_decode_statistics(streams):
+    """Mean and variance over the same stream and box as a gradient job
+    through D_q are summed inside the gradient tiles; the results equal the
+    separate statistics pass and the single operations bit for bit (small
+    and large max|q|, whole fields and boxes)."""
+    say("[case] shared decode")
+    rng = np.random.default_rng(11)
+    jobs = []
+    for x, c in streams:
+        box = rand_box(x.shape, rng)
+        for b in (None, box):
+            jobs += [
+                hsz.Job(c, "gradmag", hsz.QUANT, box=b),
+                hsz.Job(c, "mean", hsz.DELTA, box=b),
+                hsz.Job(c, "var", hsz.QUANT, box=b),
+                hsz.Job(c, "mean", hsz.QUANT, box=b),
+                hsz.Job(c, "deriv", hsz.QUANT, axis=x.ndim - 1, box=b),
+            ]
+    assert any(c.header.max_abs_q >= 65536 for _, c in streams)
+    assert any(c.header.max_abs_q < 65536 for _, c in streams)
+    shared = hsz.batch_run(jobs)
+    separate = hsz.batch_run(jobs, tune={"separate_stats": 1})
+    for k, (j, a, b) in enumerate(zip(jobs, shared, separate)):
+        assert same(a, b), (k, j.op, j.via, j.box)
+        assert same(a, alone(j)), (k, j.op, j.via, j.box)
+    plan = hsz.Plan(jobs, tune={"grad_tz": 8})
+    for rep in range(3):
+        plan.launch()
+        for k, (a, b) in enumerate(zip(plan.results(), separate)):
             assert same(a, b), (rep, k)
         torch.cuda.synchronize()
     plan.close()
