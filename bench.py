@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the per-stage table")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain 512 MiB device copy (counter calibration under rocprofv3)")
+                    help="also run a plain streaming kernel of known traffic (512 MiB in, 512 MiB out) "
+                         "to scale memory counters under rocprofv3")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workloads")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--snapshots", type=int, default=64)
@@ -230,10 +231,12 @@ def main():
         _, per = timed("compress", [("compress", comp)], 4, 1)
         extra.update(per)
     if a.calibrate_copy:
-        src = torch.empty(512 * 2**20, dtype=torch.uint8, device=dev)
+        # a plain streaming kernel of known traffic for scaling memory counters:
+        # bitwise NOT of 2^27 int32 reads 512 MiB and writes 512 MiB
+        src = torch.zeros(2**27, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.bitwise_not(src, out=dst)
         torch.cuda.synchronize()
 
     # ---- roofline of the dominant kernel of the step -------------------------------------

@@ -6,7 +6,7 @@
 //   stats jobs  per block size (32, 64): StatsJob[] + first unit of each job
 //   grad jobs   per kernel variant (S, via, op, dtype): GradJob[] + first tile
 //   index jobs  every gradient job again + its first chunk (offset index)
-//   acc         BatchAcc per statistics job (exact sums)
+//   acc         kAccStripes BatchAcc per statistics job (exact sums)
 //   rel         one 16-bit offset index per gradient job
 // then enqueues: reset -> offset index -> statistics -> gradients -> finalize.
 // A statistics job over the same stream and box as a gradient job through
@@ -172,7 +172,7 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
   L.table_end = off;
   for (int si = 0; si < 2; ++si) {
     L.acc[si] = off;
-    off = up(off + sizeof(hsz::BatchAcc) * order_stats[si].size());
+    off = up(off + sizeof(hsz::BatchAcc) * hsz::kAccStripes * order_stats[si].size());
   }
   L.rel.assign(items.size(), 0);
   for (int i : grads) {
@@ -231,7 +231,7 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
     J.halfq = 0.5 * it.v.quantum;
     J.out = it.out;
     if (slot[i] >= 0) {
-      J.acc = d_ws + L.acc[it.S == 64] + sizeof(hsz::BatchAcc) * (uint64_t)slot[i];
+      J.acc = d_ws + L.acc[it.S == 64] + sizeof(hsz::BatchAcc) * hsz::kAccStripes * (uint64_t)slot[i];
       J.acc_mode = acc_mode[i];
     }
     gj[i] = J;

@@ -586,6 +586,9 @@ __device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, ui
         qm2[i] = d.z >= 2 ? 2 * qm1[i] - c1 : qm1[i];
       }
     }
+    // rows to store this plane (kTy, ys, or none): it depends on the plane,
+    // so the compiler keeps no per-row masks across the march
+    const int nr = emit ? ys : 0;
     T* orow = out + ((o - b.z0) * by + (y0 - b.y0)) * bx + (x0 - b.x0);
 #pragma unroll
     for (int hh = 0; hh < kTy; hh += kTy / 4) {
@@ -602,7 +605,7 @@ __device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, ui
       for (int k = 0; k < H; ++k) {
         const int i = hh + k;
         const int qc = cv[k + 1];
-        if (emit && i < ys) {
+        if (i < nr) {
           const int nz = need_z ? qc - qm2[i] : 0;
           T* rowp = orow + (int64_t)i * bx;
           rowp[(uint32_t)t] = value(i, nz);

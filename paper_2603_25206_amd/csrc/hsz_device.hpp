@@ -258,10 +258,10 @@ __device__ __forceinline__ StatsJob load_job(const StatsJob* jobs, int k) {
   return j;
 }
 
-// Add a wave's exact sums (s1, count, s2 as 128 bits) to a batch
-// accumulator: reduce over the wave, then lane 0 adds with 64-bit atomics,
-// carrying the low half of s2 into the high half by hand.
-__device__ __forceinline__ void acc_add_wave(BatchAcc* acc, int64_t s1, int64_t cnt, U128 s2) {
+// Add a wave's exact sums (s1, count, s2 < 2^96) to a batch accumulator
+// slot: reduce over the wave, then lane 0 adds to the slot's stripe for this
+// wave with no-return 64-bit atomics (s2 split as hi * 2^32 + lo).
+__device__ __forceinline__ void acc_add_wave(BatchAcc* slot, int64_t s1, int64_t cnt, U128 s2) {
   s1 = wave_sum64(s1);
   cnt = wave_sum64(cnt);
   for (int m = 32; m >= 1; m >>= 1) {
@@ -271,11 +271,12 @@ __device__ __forceinline__ void acc_add_wave(BatchAcc* acc, int64_t s1, int64_t 
     add_u128(s2, o);
   }
   if (lane_id() == 0) {
-    atomicAdd((unsigned long long*)&acc->s1, (unsigned long long)s1);
-    atomicAdd((unsigned long long*)&acc->cnt, (unsigned long long)cnt);
-    const unsigned long long old = atomicAdd((unsigned long long*)&acc->s2lo, (unsigned long long)s2.lo);
-    const uint64_t carry = (old + s2.lo < old) ? 1u : 0u;
-    if (s2.hi + carry) atomicAdd((unsigned long long*)&acc->s2hi, (unsigned long long)(s2.hi + carry));
+    const unsigned stripe = (blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) % kAccStripes;
+    BatchAcc* a = slot + stripe;
+    atomicAdd((unsigned long long*)&a->s1, (unsigned long long)s1);
+    atomicAdd((unsigned long long*)&a->cnt, (unsigned long long)cnt);
+    atomicAdd((unsigned long long*)&a->s2lo, (unsigned long long)(s2.lo & 0xffffffffull));
+    atomicAdd((unsigned long long*)&a->s2hi, (unsigned long long)((s2.lo >> 32) | (s2.hi << 32)));
   }
 }
 

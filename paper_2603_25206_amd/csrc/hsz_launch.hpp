@@ -95,12 +95,17 @@ struct StatsJob {
   void* out;            // hsz_stats (device)
   const uint16_t* rel;  // block index, or null (offsets from the widths)
 };
-// Exact per-job accumulator (sum q, count, sum q^2 as two 64-bit halves).
+// Exact accumulator of one statistics slot: sum q, count, and sum q^2 as
+// s2hi * 2^32 + s2lo, so that every wave adds with plain (no-return) 64-bit
+// atomics: its low 32 bits to s2lo, the rest to s2hi.  A slot is
+// kAccStripes consecutive accumulators; a wave adds to one chosen by its
+// index, which keeps simultaneous atomics on one address few.
 struct BatchAcc {
   int64_t s1, cnt;
   uint64_t s2lo, s2hi;
 };
-hipError_t launch_batch_reset(BatchAcc* acc, int n, int* status, hipStream_t s);
+constexpr int kAccStripes = 64;
+hipError_t launch_batch_reset(BatchAcc* acc, int slots, int* status, hipStream_t s);
 hipError_t launch_batch_stats(int S, const StatsJob* jobs, const int64_t* unit_start, const int64_t* counts,
                               int kmax, BatchAcc* acc, int* status, int grid, hipStream_t s);
 hipError_t launch_batch_finalize(const StatsJob* jobs, const int64_t* counts, const BatchAcc* acc, int n,

@@ -498,7 +498,7 @@ __global__ void __launch_bounds__(kThreads) k_batch_stats(const StatsJob* __rest
   const int64_t waves = (int64_t)gridDim.x * kWavesPerGroup;
   IntAcc a;
   auto flush = [&](int slot) {
-    acc_add_wave(acc + slot, a.s1, a.cnt, a.s2);
+    acc_add_wave(acc + (int64_t)slot * kAccStripes, a.s1, a.cnt, a.s2);
     a = IntAcc{};
   };
   int64_t u = blockIdx.x * (int64_t)kWavesPerGroup + wv;
@@ -531,17 +531,28 @@ __global__ void __launch_bounds__(kThreads) k_batch_stats(const StatsJob* __rest
   flush(J.acc);
 }
 
-__global__ void k_batch_reset(BatchAcc* acc, int n, int* status) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) acc[i] = BatchAcc{0, 0, 0, 0};
+__global__ void k_batch_reset(BatchAcc* acc, int slots, int* status) {
+  for (int i = threadIdx.x; i < slots * kAccStripes; i += blockDim.x) acc[i] = BatchAcc{0, 0, 0, 0};
   if (threadIdx.x == 0) *status = 0;
 }
 
+// Sum the stripes of each job's slot (exact: integers, any order) and finish.
 __global__ void k_batch_finalize(const StatsJob* __restrict__ jobs, const int64_t* __restrict__ counts,
                                  const BatchAcc* __restrict__ acc) {
   const int n = (int)counts[0];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const BatchAcc& a = acc[jobs[i].acc];
-    *(StatsOut*)jobs[i].out = stats_from_sums(a.cnt, a.s1, a.s2lo, a.s2hi, jobs[i].op, jobs[i].v.quantum);
+    const BatchAcc* a = acc + (int64_t)jobs[i].acc * kAccStripes;
+    int64_t s1 = 0, cnt = 0;
+    unsigned __int128 lo = 0, hi = 0;
+    for (int k = 0; k < kAccStripes; ++k) {
+      s1 += a[k].s1;
+      cnt += a[k].cnt;
+      lo += a[k].s2lo;
+      hi += a[k].s2hi;
+    }
+    const unsigned __int128 s2 = (hi << 32) + lo;
+    *(StatsOut*)jobs[i].out =
+        stats_from_sums(cnt, s1, (uint64_t)s2, (uint64_t)(s2 >> 64), jobs[i].op, jobs[i].v.quantum);
   }
 }
 
@@ -609,8 +620,8 @@ hipError_t fused_by_via(const StreamView& v, int via, const Rows& rows, bool who
 
 }  // namespace
 
-hipError_t launch_batch_reset(BatchAcc* acc, int n, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, acc, n, status);
+hipError_t launch_batch_reset(BatchAcc* acc, int slots, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, acc, slots, status);
   return hipGetLastError();
 }
 
