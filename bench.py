@@ -68,6 +68,37 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "k_batch_grad_gradmag_512cube_counters.txt")
+KERNEL_SOURCES = ("grad.hip", "hsz_device.hpp", "hsz_launch.hpp")
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2603_25206_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic():
+    """HBM bytes per launch of the step's gradient kernel from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the same
+    counter reads for a streaming kernel of known size), or None when there is
+    no summary or the kernel sources changed since it was taken."""
+    try:
+        with open(COUNTERS) as f:
+            lines = f.read().splitlines()
+    except OSError:
+        return None
+    for line in lines:
+        if line.startswith("TRAFFIC_JSON:"):
+            rec = json.loads(line.split(":", 1)[1])
+            if rec.get("source_sha") == kernel_source_sha():
+                return int(rec["bytes_per_launch"])
+    return None
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -260,7 +291,8 @@ def main():
     achieved = alg_step / (ms_replay * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "k_batch_grad<32,3,4,float,1> (mean+var+gradmag, one decode)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": a.traffic,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": a.traffic if a.traffic is not None else counter_traffic(),
                 "alg_bytes_per_launch": int(alg_step), "launch_ms": round(ms_replay, 4)}
     dom = "gradmag_quant"
     ach_sep = alg[dom] / (per_sep[dom] * 1e-3) / 1e9

@@ -246,12 +246,15 @@ int hsz_batch_workspace(const hsz_work *h_items, int n, uint64_t *h_bytes);
 int hsz_batch_run(const hsz_work *h_items, int n, const hsz_tuning *h_tune, void *d_workspace,
                   uint64_t workspace_bytes, void *stream);
 
-/* A batch captured once as a HIP graph (table copy + kernels) and replayed.
- * 'stream' must be a created (non-null) stream.  hsz_plan_update rewrites the
- * table for a batch of the same structure (same jobs per kernel variant, no
- * larger index or staging needs) -- new streams, boxes, axes and result
- * buffers; it waits for the previous replay to have read the old table.
- * The workspace belongs to the plan until hsz_plan_destroy. */
+/* A batch captured once as a HIP graph of its kernels and replayed.  The
+ * work table is uploaded (synchronously) by hsz_plan_create and by
+ * hsz_plan_update, never by a replay.  'stream' must be a created
+ * (non-null) stream.  hsz_plan_update rewrites the table for a batch of the
+ * same structure (same jobs per kernel variant, the same classes with
+ * separately summed statistics, no larger index or staging needs) -- new
+ * streams, boxes, axes and result buffers; it first waits for the previous
+ * replay to finish.  The workspace belongs to the plan until
+ * hsz_plan_destroy. */
 typedef struct hsz_plan hsz_plan;
 int hsz_plan_create(const hsz_work *h_items, int n, const hsz_tuning *h_tune, void *d_workspace,
                     uint64_t workspace_bytes, void *stream, hsz_plan **out);

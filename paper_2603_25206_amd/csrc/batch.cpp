@@ -281,11 +281,11 @@ int enqueue(const Built& B, uint8_t* d_ws, const hsz_tuning& tune, hipStream_t s
   const int stats_grid = std::max(1, cus * (tune.stats_waves_per_cu > 0 ? tune.stats_waves_per_cu : 8) / 4);
   const int grad_grid = std::max(1, cus * (tune.grad_groups_per_cu > 0 ? tune.grad_groups_per_cu : 4));
   hipError_t e;
-  for (int si = 0; si < 2; ++si) {
-    // every batch resets its accumulators (a small kernel: no memset nodes in graphs)
-    if ((e = hsz::launch_batch_reset((hsz::BatchAcc*)(d_ws + L.acc[si]), B.n_stats[si], status, s)) != hipSuccess)
-      return hip_fail(e);
-  }
+  // every pass first zeroes the status word and the accumulators of both
+  // classes (adjacent in the workspace), in one small kernel: no memset nodes
+  if ((e = hsz::launch_batch_reset((hsz::BatchAcc*)(d_ws + L.acc[0]), B.n_stats[0] + B.n_stats[1], status, s)) !=
+      hipSuccess)
+    return hip_fail(e);
   if (B.n_index > 0) {
     if ((e = hsz::launch_batch_block_index((const hsz::GradJob*)(d_ws + L.index_jobs),
                                            (const int64_t*)(d_ws + L.index_start), counts + 2 * cslot_index(),
@@ -293,7 +293,7 @@ int enqueue(const Built& B, uint8_t* d_ws, const hsz_tuning& tune, hipStream_t s
       return hip_fail(e);
   }
   for (int si = 0; si < 2; ++si) {
-    if (B.n_stats[si] == 0) continue;
+    if (B.stats_units[si] == 0) continue;  // none, or all summed inside gradient tiles
     if ((e = hsz::launch_batch_stats(si ? 64 : 32, (const hsz::StatsJob*)(d_ws + L.stats_jobs[si]),
                                      (const int64_t*)(d_ws + L.stats_start[si]), counts + 2 * cslot_stats(si),
                                      B.stats_kmax[si], (hsz::BatchAcc*)(d_ws + L.acc[si]), status, stats_grid, s)) !=
@@ -309,12 +309,11 @@ int enqueue(const Built& B, uint8_t* d_ws, const hsz_tuning& tune, hipStream_t s
                                     B.grad_kmax[g], grad_grid, status, s)) != hipSuccess)
       return hip_fail(e);
   }
-  for (int si = 0; si < 2; ++si) {
-    if (B.n_stats[si] == 0) continue;
-    if ((e = hsz::launch_batch_finalize((const hsz::StatsJob*)(d_ws + L.stats_jobs[si]), counts + 2 * cslot_stats(si),
-                                        (const hsz::BatchAcc*)(d_ws + L.acc[si]), B.n_stats[si], s)) != hipSuccess)
-      return hip_fail(e);
-  }
+  const hsz::StatsJob* fj[2] = {(const hsz::StatsJob*)(d_ws + L.stats_jobs[0]),
+                                (const hsz::StatsJob*)(d_ws + L.stats_jobs[1])};
+  const int64_t* fc[2] = {counts + 2 * cslot_stats(0), counts + 2 * cslot_stats(1)};
+  const hsz::BatchAcc* fa[2] = {(const hsz::BatchAcc*)(d_ws + L.acc[0]), (const hsz::BatchAcc*)(d_ws + L.acc[1])};
+  if ((e = hsz::launch_batch_finalize(fj, fc, fa, B.n_stats, s)) != hipSuccess) return hip_fail(e);
   return HSZ_OK;
 }
 
@@ -335,7 +334,6 @@ struct hsz_plan {
   hsz_tuning tune;
   uint8_t* d_ws = nullptr;
   uint64_t ws_bytes = 0;
-  void* h_table = nullptr;  // pinned copy of the table, read by the graph's copy node
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t done = nullptr;
@@ -390,12 +388,14 @@ int hsz_plan_create(const hsz_work* items, int n, const hsz_tuning* tune, void* 
     delete p;
     return HSZ_ERR_CAPACITY;
   }
-  hipError_t e = hipHostMalloc(&p->h_table, p->built.table.size(), hipHostMallocDefault);
+  // the table is uploaded here and by hsz_plan_update, not by the graph: a
+  // replay runs kernels only
+  hipError_t e = hipMemcpy(p->d_ws + p->built.L.counts, p->built.table.data(), p->built.table.size(),
+                           hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     delete p;
     return hip_fail(e);
   }
-  memcpy(p->h_table, p->built.table.data(), p->built.table.size());
   hipStream_t s = (hipStream_t)stream;
   if ((e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming)) != hipSuccess) {
     hsz_plan_destroy(p);
@@ -405,8 +405,7 @@ int hsz_plan_create(const hsz_work* items, int n, const hsz_tuning* tune, void* 
     hsz_plan_destroy(p);
     return hip_fail(e);
   }
-  e = hipMemcpyAsync(p->d_ws + p->built.L.counts, p->h_table, p->built.table.size(), hipMemcpyHostToDevice, s);
-  int erc = (e == hipSuccess) ? enqueue(p->built, p->d_ws, p->tune, s) : hip_fail(e);
+  int erc = enqueue(p->built, p->d_ws, p->tune, s);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(s, &g);
   if (erc != HSZ_OK || e2 != hipSuccess) {
@@ -435,7 +434,8 @@ int hsz_plan_update(hsz_plan* p, const hsz_work* items, int n) {
   const Built& A = p->built;
   bool same = B.L.total <= p->ws_bytes && B.table.size() == A.table.size() && B.n_index == A.n_index;
   for (int si = 0; si < 2 && same; ++si)
-    same = B.n_stats[si] == A.n_stats[si] && B.stats_kmax[si] <= A.stats_kmax[si] && B.L.acc[si] == A.L.acc[si];
+    same = B.n_stats[si] == A.n_stats[si] && B.stats_kmax[si] <= A.stats_kmax[si] && B.L.acc[si] == A.L.acc[si] &&
+           (B.stats_units[si] > 0) == (A.stats_units[si] > 0);
   for (int g = 0; g < kVariants && same; ++g) same = B.n_grad[g] == A.n_grad[g] && B.grad_kmax[g] <= A.grad_kmax[g];
   for (size_t i = 0; i < B.L.rel.size() && same; ++i) same = B.L.rel[i] == A.L.rel[i];
   if (!same) return HSZ_ERR_UNSUPPORTED;
@@ -443,7 +443,8 @@ int hsz_plan_update(hsz_plan* p, const hsz_work* items, int n) {
     hipError_t e = hipEventSynchronize(p->done);  // the last replay has read the table
     if (e != hipSuccess) return hip_fail(e);
   }
-  memcpy(p->h_table, B.table.data(), B.table.size());
+  hipError_t e = hipMemcpy(p->d_ws + B.L.counts, B.table.data(), B.table.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e);
   return HSZ_OK;
 }
 
@@ -463,7 +464,6 @@ void hsz_plan_destroy(hsz_plan* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->done) (void)hipEventDestroy(p->done);
-  if (p->h_table) (void)hipHostFree(p->h_table);
   delete p;
 }
 

@@ -105,11 +105,14 @@ struct BatchAcc {
   uint64_t s2lo, s2hi;
 };
 constexpr int kAccStripes = 64;
+// Zero 'slots' accumulator slots at acc and the status word.
 hipError_t launch_batch_reset(BatchAcc* acc, int slots, int* status, hipStream_t s);
 hipError_t launch_batch_stats(int S, const StatsJob* jobs, const int64_t* unit_start, const int64_t* counts,
                               int kmax, BatchAcc* acc, int* status, int grid, hipStream_t s);
-hipError_t launch_batch_finalize(const StatsJob* jobs, const int64_t* counts, const BatchAcc* acc, int n,
-                                 hipStream_t s);
+// Finish the statistics jobs of both block-size classes (n[c] jobs each, one
+// wave per job summing its slot's stripes).
+hipError_t launch_batch_finalize(const StatsJob* const jobs[2], const int64_t* const counts[2],
+                                 const BatchAcc* const acc[2], const int n[2], hipStream_t s);
 
 // Statistics (op = 1 mean, 2 var) on a stage buffer or fused from a stream.
 hipError_t launch_stats_stage(const void* stage_buf, int stage, const StreamView& v, int op,

@@ -9,6 +9,8 @@
 // (sum_i q_i = S_b*q0 + sum_{i>=1} (S_b - i) p_i, generalised to a slot
 // range [a, z] of the block) and never forms q.  The stage-4 routes work on
 // floats in binary64, shifted by the box's first value.
+#include <algorithm>
+
 #include "hsz_device.hpp"
 #include "hsz_launch.hpp"
 
@@ -532,27 +534,43 @@ __global__ void __launch_bounds__(kThreads) k_batch_stats(const StatsJob* __rest
 }
 
 __global__ void k_batch_reset(BatchAcc* acc, int slots, int* status) {
-  for (int i = threadIdx.x; i < slots * kAccStripes; i += blockDim.x) acc[i] = BatchAcc{0, 0, 0, 0};
-  if (threadIdx.x == 0) *status = 0;
+  const int n = slots * kAccStripes;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) acc[i] = BatchAcc{0, 0, 0, 0};
+  if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0;
 }
 
-// Sum the stripes of each job's slot (exact: integers, any order) and finish.
-__global__ void k_batch_finalize(const StatsJob* __restrict__ jobs, const int64_t* __restrict__ counts,
-                                 const BatchAcc* __restrict__ acc) {
-  const int n = (int)counts[0];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const BatchAcc* a = acc + (int64_t)jobs[i].acc * kAccStripes;
-    int64_t s1 = 0, cnt = 0;
-    unsigned __int128 lo = 0, hi = 0;
-    for (int k = 0; k < kAccStripes; ++k) {
-      s1 += a[k].s1;
-      cnt += a[k].cnt;
-      lo += a[k].s2lo;
-      hi += a[k].s2hi;
-    }
-    const unsigned __int128 s2 = (hi << 32) + lo;
-    *(StatsOut*)jobs[i].out =
-        stats_from_sums(cnt, s1, (uint64_t)s2, (uint64_t)(s2 >> 64), jobs[i].op, jobs[i].v.quantum);
+struct FinalizeArgs {
+  const StatsJob* jobs[2];
+  const int64_t* counts[2];
+  const BatchAcc* acc[2];
+  int n0;
+};
+
+// One wave per job of either class: lane k loads stripe k of the job's slot,
+// the wave adds them exactly (sum q^2 = hi * 2^32 + lo in 128 bits), lane 0
+// finishes the job.
+__global__ void __launch_bounds__(256) k_batch_finalize(FinalizeArgs fa) {
+  const int w = blockIdx.x * (blockDim.x / kWave) + wave_in_group();
+  const int c = w < fa.n0 ? 0 : 1;
+  const int i = c ? w - fa.n0 : w;
+  if (i >= (int)fa.counts[c][0]) return;
+  const StatsJob J = load_job(fa.jobs[c], i);
+  const BatchAcc a = fa.acc[c][(int64_t)J.acc * kAccStripes + lane_id()];
+  const int64_t s1 = wave_sum64(a.s1), cnt = wave_sum64(a.cnt);
+  U128 lo = {a.s2lo, 0}, hi = {a.s2hi, 0};
+  for (int m = 32; m >= 1; m >>= 1) {
+    U128 o;
+    o.lo = __shfl_xor(lo.lo, m);
+    o.hi = __shfl_xor(lo.hi, m);
+    add_u128(lo, o);
+    o.lo = __shfl_xor(hi.lo, m);
+    o.hi = __shfl_xor(hi.hi, m);
+    add_u128(hi, o);
+  }
+  if (lane_id() == 0) {
+    const unsigned __int128 s2 = ((((unsigned __int128)hi.hi << 64) | hi.lo) << 32) +
+                                 (((unsigned __int128)lo.hi << 64) | lo.lo);
+    *(StatsOut*)J.out = stats_from_sums(cnt, s1, (uint64_t)s2, (uint64_t)(s2 >> 64), J.op, J.v.quantum);
   }
 }
 
@@ -621,7 +639,9 @@ hipError_t fused_by_via(const StreamView& v, int via, const Rows& rows, bool who
 }  // namespace
 
 hipError_t launch_batch_reset(BatchAcc* acc, int slots, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, acc, slots, status);
+  const int n = slots * kAccStripes;
+  const unsigned grid = (unsigned)std::min(64, std::max(1, (n + 255) / 256));
+  hipLaunchKernelGGL(k_batch_reset, dim3(grid), dim3(256), 0, s, acc, slots, status);
   return hipGetLastError();
 }
 
@@ -637,9 +657,19 @@ hipError_t launch_batch_stats(int S, const StatsJob* jobs, const int64_t* unit_s
   return hipGetLastError();
 }
 
-hipError_t launch_batch_finalize(const StatsJob* jobs, const int64_t* counts, const BatchAcc* acc, int n,
-                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_finalize, dim3((n + 255) / 256), dim3(256), 0, s, jobs, counts, acc);
+hipError_t launch_batch_finalize(const StatsJob* const jobs[2], const int64_t* const counts[2],
+                                 const BatchAcc* const acc[2], const int n[2], hipStream_t s) {
+  FinalizeArgs fa;
+  for (int c = 0; c < 2; ++c) {
+    fa.jobs[c] = jobs[c];
+    fa.counts[c] = counts[c];
+    fa.acc[c] = acc[c];
+  }
+  fa.n0 = n[0];
+  const int waves = n[0] + n[1];
+  if (waves == 0) return hipSuccess;
+  const int per = 256 / kWave;
+  hipLaunchKernelGGL(k_batch_finalize, dim3((waves + per - 1) / per), dim3(256), 0, s, fa);
   return hipGetLastError();
 }
 
