@@ -1,14 +1,23 @@
 // compress.hip -- c = C(d, eps) on the GPU (Sec. IV, Alg. 1).
 //
-//   k_minmax      one read of the field: extremes and a non-finite flag
-//   k_params      eps -> eps_q -> Delta, 1/Delta (one thread, binary64)
-//   k_quant_meta  one lane per block: quantize, decorrelate, block width,
-//                 q0, payload words per 64-block chunk, max |q|
-//   k_scan_chunks exclusive scan of the chunk word counts -> chunk table
-//   k_pack        one lane per block: re-quantize and bit-pack the block
-//                 into an LDS copy of the chunk's payload, then copy it out
-//                 with coalesced stores
+//   k_minmax      one read of the field (16-byte loads): extremes and a
+//                 non-finite flag
+//   k_params      eps -> eps_q -> Delta, 1/Delta (binary64)
+//   k_quant_meta  quantize and decorrelate; block widths, q0, payload words
+//                 per 64-block chunk, max |q|
+//   k_scan_sums,  exclusive scan of the chunk word counts -> chunk table
+//   k_scan_write
+//   k_pack        quantize again and bit-pack each chunk in LDS, then copy it
+//                 out with coalesced stores
 //   k_header      the 256-byte header and the zero padding between sections
+//
+// Work layout of k_quant_meta and k_pack: a wavefront owns a 64-block chunk
+// and walks it 64 consecutive elements at a time, lane l <-> element l of
+// the step, so every load is coalesced.  With S = 32 a step holds two blocks
+// (lanes 0-31 and 32-63), with S = 64 one.  q_{i-1} comes from the lane
+// below (a shuffle); slot 0 of a block has p = 0; a block's width is the bit
+// length of the OR of |p| over its lanes; its sign word is a ballot; each
+// magnitude is OR-ed into its (at most two) words of the LDS chunk image.
 //
 // Quantization is q = floor(x * (1/Delta) + 0.5) in binary64 with no fused
 // multiply-add (compiled with contraction off); the same expression and
@@ -35,34 +44,76 @@ constexpr uint64_t kWsPartials = 256;  // byte offset of the min/max partials
 
 __host__ __device__ inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
+// 16-byte vector of the field type
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int k = 4;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int k = 2;
+};
+
+template <typename T>
+__device__ __forceinline__ void mm_add(T v, T& lo, T& hi, int& bad) {
+  bad |= !(v - v == T(0));  // NaN or infinity
+  lo = v < lo ? v : lo;
+  hi = v > hi ? v : hi;
+}
+
+// Extremes in the field's own type (exact), four 16-byte loads in flight
+// per thread; the scalar tail (n not a multiple of the vector) by one group.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_minmax(const T* __restrict__ x, int64_t n, double* partial) {
-  double lo = INFINITY, hi = -INFINITY;
+  using V = typename Vec16<T>::type;
+  constexpr int K = Vec16<T>::k;
+  constexpr int U = 4;
+  T lo = (T)INFINITY, hi = (T)-INFINITY;
   int bad = 0;
-  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-    double v = (double)x[i];
-    bad |= !isfinite(v);
-    lo = fmin(lo, v);
-    hi = fmax(hi, v);
+  const V* xv = (const V*)x;
+  const int64_t nv = n / K;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t i0 = blockIdx.x * (int64_t)kThreads + threadIdx.x; i0 < nv; i0 += stride * U) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < nv) v[u] = xv[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i0 + u * stride < nv) {
+        const T* e = (const T*)&v[u];
+#pragma unroll
+        for (int k = 0; k < K; ++k) mm_add(e[k], lo, hi, bad);
+      }
+    }
   }
+  if (blockIdx.x == 0)
+    for (int64_t i = nv * K + threadIdx.x; i < n; i += kThreads) mm_add(x[i], lo, hi, bad);
+  double dlo = (double)lo, dhi = (double)hi;
   for (int m = 32; m >= 1; m >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, m));
-    hi = fmax(hi, __shfl_xor(hi, m));
+    dlo = fmin(dlo, __shfl_xor(dlo, m));
+    dhi = fmax(dhi, __shfl_xor(dhi, m));
     bad |= __shfl_xor(bad, m);
   }
   __shared__ double slo[kThreads / kWave], shi[kThreads / kWave];
   __shared__ int sbad[kThreads / kWave];
   const int wv = wave_in_group();
-  if (lane_id() == 0) { slo[wv] = lo; shi[wv] = hi; sbad[wv] = bad; }
+  if (lane_id() == 0) { slo[wv] = dlo; shi[wv] = dhi; sbad[wv] = bad; }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int k = 1; k < kThreads / kWave; ++k) {
-      lo = fmin(lo, slo[k]);
-      hi = fmax(hi, shi[k]);
+      dlo = fmin(dlo, slo[k]);
+      dhi = fmax(dhi, shi[k]);
       bad |= sbad[k];
     }
-    partial[3 * blockIdx.x + 0] = lo;
-    partial[3 * blockIdx.x + 1] = hi;
+    partial[3 * blockIdx.x + 0] = dlo;
+    partial[3 * blockIdx.x + 1] = dhi;
     partial[3 * blockIdx.x + 2] = bad ? 1.0 : 0.0;
   }
 }
@@ -151,75 +202,199 @@ __device__ __forceinline__ int quantize(double x, double inv, bool& over) {
 
 __device__ __forceinline__ int bitlen(uint32_t v) { return 32 - __clz((int)v); }
 
+// Inclusive prefix-OR within each block's lanes by DPP: rows of 16 first,
+// then row 0 -> 1 and 2 -> 3; with S = 64 also the first half into the
+// second.  The block's OR ends up in its last lane (31, 63).
+template <int S>
+__device__ __forceinline__ int block_or_scan(int v) {
+  v |= dpp<0x111>(v);
+  v |= dpp<0x112>(v);
+  v |= dpp<0x114>(v);
+  v |= dpp<0x118>(v);
+  v |= dpp<0x142, 0xa>(v);
+  if (S == 64) v |= dpp<0x143, 0xc>(v);
+  return v;
+}
+
+// the value of the lane below (wave shift right by one; lane 0 gets 0).  The
+// empty asm keeps the shifted value in a register of its own: folded into
+// the subtraction that follows (as a v_subrev with a DPP operand) it gave
+// q_{i-1} - q_i instead of q_i - q_{i-1} for S = 64.
+__device__ __forceinline__ int from_lane_below(int v) {
+  int r = dpp<0x138>(v);
+  asm volatile("" : "+v"(r));
+  return r;
+}
+
+// Steps of 64 elements per chunk, and how many are loaded ahead.
+template <int S>
+constexpr int kSteps = kChunkBlocks * S / kWave;
+constexpr int kAhead = 16;
+
+// max|q| is reduced per workgroup into group_max[] (k_header takes the max
+// of those): one atomic per wave on a single word serialized the end of the
+// kernel.
+constexpr int kMetaGroups = 4096;
+
 template <typename T, int S>
 __global__ void __launch_bounds__(kThreads) k_quant_meta(const T* __restrict__ x, int64_t n, int64_t nb,
                                                         int64_t nchunks, CompressWs* ws, int32_t* q0s,
-                                                        uint8_t* widths, uint32_t* chunk_words) {
-  if (ws->status != 0) return;
+                                                        uint8_t* widths, uint32_t* chunk_words,
+                                                        uint32_t* group_max) {
+  if (ws->status != 0) {
+    if (threadIdx.x == 0) group_max[blockIdx.x] = 0;
+    return;
+  }
+  // per wave: the q0 and width of each block of its current chunk, written
+  // by the block's first / last lane as the steps go, read back by lane l
+  // (block 64c + l) for coalesced stores
+  __shared__ int meta_all[(kThreads / kWave) * 2 * kChunkBlocks];
+  int* mq0 = meta_all + wave_in_group() * 2 * kChunkBlocks;
+  int* mw = mq0 + kChunkBlocks;
   const double inv = ws->inv_quantum;
   const int l = lane_id();
+  const int slot = l % S;
   const int64_t waves = (int64_t)gridDim.x * (kThreads / kWave);
   uint32_t maxq = 0;
   bool over = false;
-  for (int64_t c = blockIdx.x * (int64_t)(kThreads / kWave) + wave_in_group(); c < nchunks; c += waves) {
-    const int64_t b = c * kChunkBlocks + l;
-    int w = 0;
-    if (b < nb) {
-      const T* xb = x + b * S;
-      const int len = (int)((n - b * S) < S ? (n - b * S) : S);
-      int qprev = 0;
-      uint32_t orp = 0;
-      int q0 = 0;
-#pragma unroll 8
-      for (int j = 0; j < S; ++j) {
-        if (j < len) {
-          int q = quantize((double)xb[j], inv, over);
-          uint32_t aq = (uint32_t)(q < 0 ? -q : q);
-          maxq = aq > maxq ? aq : maxq;
-          if (j == 0) q0 = q;
-          int p = (j == 0) ? 0 : q - qprev;
-          orp |= (uint32_t)(p < 0 ? -p : p);
-          qprev = q;
-        }
+  // a chunk: FULL when all its elements exist (no bounds tests, so the
+  // kAhead loads are issued back to back)
+  auto chunk = [&](int64_t c, auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    const int64_t e0 = c * (int64_t)(kChunkBlocks * S);
+    for (int st = 0; st < kSteps<S>; st += kAhead) {
+      T v[kAhead];
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const int64_t e = e0 + (int64_t)(st + u) * kWave + l;
+        v[u] = (FULL || e < n) ? x[e] : T(0);
       }
-      w = bitlen(orp);
-      q0s[b] = q0;
-      widths[b] = (uint8_t)w;
+      // quantize and decorrelate the kAhead steps, then run their block
+      // prefix-OR scans stage by stage: the independent DPP chains interleave
+      // instead of stalling on each other's results
+      int ab[kAhead];
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const bool valid = FULL || e0 + (int64_t)(st + u) * kWave + l < n;
+        const int q = valid ? quantize((double)v[u], inv, over) : 0;
+        const uint32_t aq = (uint32_t)(q < 0 ? -q : q);
+        maxq = aq > maxq ? aq : maxq;
+        const int qp = from_lane_below(q);
+        const int p = (slot == 0 || !valid) ? 0 : q - qp;
+        ab[u] = p < 0 ? -p : p;
+        if (slot == 0) mq0[(st + u) * (kWave / S) + l / S] = q;
+      }
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) ab[u] |= dpp<0x111>(ab[u]);
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) ab[u] |= dpp<0x112>(ab[u]);
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) ab[u] |= dpp<0x114>(ab[u]);
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) ab[u] |= dpp<0x118>(ab[u]);
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) ab[u] |= dpp<0x142, 0xa>(ab[u]);
+      if (S == 64) {
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) ab[u] |= dpp<0x143, 0xc>(ab[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u)  // the block's OR is in its last lane
+        if (slot == S - 1) mw[(st + u) * (kWave / S) + l / S] = bitlen((uint32_t)ab[u]);
     }
-    int words = block_words<S>(w);
-    int tot = wave_incl_scan(words);
-    if (l == kWave - 1) chunk_words[c] = (uint32_t)tot;
+    __builtin_amdgcn_wave_barrier();
+    const int64_t b = c * kChunkBlocks + l;
+    const bool exists = FULL || b < nb;
+    const int my_w = mw[l], my_q0 = mq0[l];
+    if (exists) {
+      q0s[b] = my_q0;
+      widths[b] = (uint8_t)my_w;
+    }
+    const int words = wave_incl_scan(exists ? block_words<S>(my_w) : 0);
+    if (l == kWave - 1) chunk_words[c] = (uint32_t)words;
+    __builtin_amdgcn_wave_barrier();
+  };
+  for (int64_t c = blockIdx.x * (int64_t)(kThreads / kWave) + wave_in_group(); c < nchunks; c += waves) {
+    if ((c + 1) * (int64_t)(kChunkBlocks * S) <= n) chunk(c, std::true_type{});
+    else chunk(c, std::false_type{});
   }
   maxq = (uint32_t)wave_max((int)maxq);
-  if (l == 0) atomicMax(&ws->max_abs_q, maxq);
+  __shared__ uint32_t wmax[kThreads / kWave];
+  if (l == 0) wmax[wave_in_group()] = maxq;
   if (__any(over) && l == 0) record_status(&ws->status, kErrRange);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = 0;
+    for (int k = 0; k < kThreads / kWave; ++k) m = wmax[k] > m ? wmax[k] : m;
+    group_max[blockIdx.x] = m;
+  }
 }
 
-// One workgroup: exclusive scan of chunk_words into the stream's chunk table.
-__global__ void __launch_bounds__(1024) k_scan_chunks(const uint32_t* chunk_words, int64_t nchunks,
-                                                      uint64_t* chunk_off, CompressWs* ws,
-                                                      uint64_t off_payload, uint64_t cap) {
-  __shared__ uint64_t part[1024];
-  const int t = threadIdx.x;
-  const int64_t per = (nchunks + 1023) / 1024;
-  const int64_t lo = t * per, hi = (lo + per < nchunks) ? lo + per : nchunks;
-  uint64_t s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += chunk_words[i];
-  part[t] = s;
+// Exclusive scan of the chunk word counts into the chunk table, in ranges of
+// kScanRange chunks (one workgroup each, 4 per thread): k_scan_sums adds each
+// range, k_scan_write starts every range at the sum of the ranges before it
+// and scans inside it.  A range's total is below 2^31 (a chunk holds at most
+// 64 * 62 words).
+constexpr int kScanThreads = 1024, kScanPer = 4, kScanRange = kScanThreads * kScanPer;
+
+// sum of 'v' over the workgroup (every thread gets it)
+__device__ __forceinline__ uint64_t group_sum(uint64_t v, uint64_t* red) {
+  v = wave_sum_u64(v);
+  const int wv = wave_in_group();
+  if (lane_id() == 0) red[wv] = v;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint64_t v = (t >= off) ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  uint64_t t = 0;
+  for (int k = 0; k < kScanThreads / kWave; ++k) t += red[k];
+  __syncthreads();
+  return t;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(const uint32_t* __restrict__ chunk_words,
+                                                            int64_t nchunks, uint64_t* range_sums) {
+  __shared__ uint64_t red[kScanThreads / kWave];
+  const int64_t i0 = blockIdx.x * (int64_t)kScanRange + threadIdx.x * (int64_t)kScanPer;
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) s += i0 + k < nchunks ? chunk_words[i0 + k] : 0u;
+  s = group_sum(s, red);
+  if (threadIdx.x == 0) range_sums[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_write(const uint32_t* __restrict__ chunk_words,
+                                                             int64_t nchunks, const uint64_t* __restrict__ range_sums,
+                                                             uint64_t* chunk_off, CompressWs* ws,
+                                                             uint64_t off_payload, uint64_t cap) {
+  __shared__ uint64_t red[kScanThreads / kWave];
+  __shared__ int wtot[kScanThreads / kWave];
+  const int t = threadIdx.x, l = lane_id(), wv = wave_in_group();
+  uint64_t before = 0;
+  for (int64_t g = t; g < blockIdx.x; g += kScanThreads) before += range_sums[g];
+  before = group_sum(before, red);
+  const int64_t i0 = blockIdx.x * (int64_t)kScanRange + t * (int64_t)kScanPer;
+  uint32_t v[kScanPer];
+  int sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = i0 + k < nchunks ? chunk_words[i0 + k] : 0u;
+    sum += (int)v[k];
   }
-  uint64_t run = part[t] - s;  // exclusive prefix of this thread's segment
-  for (int64_t i = lo; i < hi; ++i) {
-    chunk_off[i] = run;
-    run += chunk_words[i];
+  const int incl = wave_incl_scan(sum);
+  if (l == kWave - 1) wtot[wv] = incl;
+  __syncthreads();
+  int prior = 0, range = 0;
+  for (int k = 0; k < kScanThreads / kWave; ++k) {
+    const int wt = wtot[k];
+    prior += k < wv ? wt : 0;
+    range += wt;
   }
-  if (t == 1023) {
-    const uint64_t total = part[1023];
+  uint64_t run = before + (uint64_t)(prior + incl - sum);
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (i0 + k < nchunks) chunk_off[i0 + k] = run;
+    run += v[k];
+  }
+  if (t == 0 && (int64_t)(blockIdx.x + 1) * kScanRange >= nchunks) {  // the last range
+    const uint64_t total = before + (uint64_t)range;
     chunk_off[nchunks] = total;
     ws->total_words = total;
     if (off_payload + 4 * total > cap) record_status(&ws->status, kErrCapacity);
@@ -233,50 +408,75 @@ __global__ void __launch_bounds__(kThreads) k_pack(const T* __restrict__ x, int6
                                                   const uint64_t* __restrict__ chunk_off,
                                                   uint32_t* payload) {
   if (ws->status != 0) return;
-  constexpr int kRows = (S / 32) * (1 + kMaxWidth);
+  constexpr int kRows = (S / 32) * (1 + kMaxWidth);  // words of the widest block
   __shared__ uint32_t lin_all[(kThreads / kWave) * kRows * kWave];
-  uint32_t* lin = lin_all + (wave_in_group()) * kRows * kWave;
+  uint32_t* lin = lin_all + wave_in_group() * kRows * kWave;
   const double inv = ws->inv_quantum;
   const int l = lane_id();
+  const int slot = l % S;
   const int64_t waves = (int64_t)gridDim.x * (kThreads / kWave);
   for (int64_t c = blockIdx.x * (int64_t)(kThreads / kWave) + wave_in_group(); c < nchunks; c += waves) {
-    const int64_t b = c * kChunkBlocks + l;
-    const int w = (b < nb) ? (int)widths[b] : 0;
-    const int nw = block_words<S>(w);
-    const int incl = wave_incl_scan(nw);
-    const int woff = incl - nw;
+    // word offsets of the chunk's blocks (lane l <-> block 64c + l)
+    const int64_t bl = c * kChunkBlocks + l;
+    const int wl = bl < nb ? (int)widths[bl] : 0;
+    const int nwl = block_words<S>(wl);
+    const int incl = wave_incl_scan(nwl);
+    const int offl = incl - nwl;
     const int total = __shfl(incl, kWave - 1);
     if (total < 0 || total > kRows * kWave) continue;  // widths are <= 30, so never taken
-    for (int k = 0; k < nw; ++k) lin[woff + k] = 0u;
-    if (w > 0) {
-      const T* xb = x + b * S;
-      const int len = (int)((n - b * S) < S ? (n - b * S) : S);
-      uint32_t sg0 = 0, sg1 = 0;
-      uint32_t* mag = lin + woff + S / 32;
-      int qprev = 0;
-      bool over = false;
-      for (int j = 0; j < len; ++j) {
-        int q = quantize((double)xb[j], inv, over);
-        int p = (j == 0) ? 0 : q - qprev;
-        qprev = q;
-        if (p < 0) {
-          if (j < 32) sg0 |= 1u << j;
-          else sg1 |= 1u << (j - 32);
-        }
-        uint32_t m = (uint32_t)(p < 0 ? -p : p);
-        uint32_t pos = (uint32_t)j * (uint32_t)w;
-        uint32_t k = pos >> 5, sh = pos & 31u;
-        mag[k] |= m << sh;
-        if (sh + (uint32_t)w > 32u) mag[k + 1] |= m >> (32u - sh);
+    for (int k = l; k < total; k += kWave) lin[k] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    const int64_t e0 = c * (int64_t)(kChunkBlocks * S);
+    auto steps = [&](auto full_tag) {  // FULL: every element of the chunk exists
+      constexpr bool FULL = decltype(full_tag)::value;
+    for (int st = 0; st < kSteps<S>; st += kAhead) {
+      T v[kAhead];
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const int64_t e = e0 + (int64_t)(st + u) * kWave + l;
+        v[u] = (FULL || e < n) ? x[e] : T(0);
       }
-      lin[woff] = sg0;
-      if (S == 64) lin[woff + 1] = sg1;
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const int64_t base = e0 + (int64_t)(st + u) * kWave;
+        const bool valid = FULL || base + l < n;
+        bool ov = false;
+        const int q = valid ? quantize((double)v[u], inv, ov) : 0;
+        const int qp = from_lane_below(q);
+        const int p = (slot == 0 || !valid) ? 0 : q - qp;
+        const int blk = (st + u) * (kWave / S);  // first block of the step within the chunk
+        int w = __builtin_amdgcn_readlane(wl, blk), off = __builtin_amdgcn_readlane(offl, blk);
+        if (S == 32 && l >= 32) {
+          w = __builtin_amdgcn_readlane(wl, blk + 1);
+          off = __builtin_amdgcn_readlane(offl, blk + 1);
+        }
+        const uint64_t neg = __ballot(p < 0);
+        if (w > 0) {
+          if (S == 32) {
+            if (slot == 0) lin[off] = (uint32_t)(l < 32 ? neg : neg >> 32);
+          } else {
+            if (l == 0) lin[off] = (uint32_t)neg;
+            if (l == 32) lin[off + 1] = (uint32_t)(neg >> 32);
+          }
+          const uint32_t m = (uint32_t)(p < 0 ? -p : p);
+          if (m) {
+            const uint32_t pos = (uint32_t)slot * (uint32_t)w;
+            const uint32_t k = pos >> 5, sh = pos & 31u;
+            uint32_t* mag = lin + off + S / 32;
+            atomicOr(&mag[k], m << sh);
+            if (sh + (uint32_t)w > 32u) atomicOr(&mag[k + 1], m >> (32u - sh));
+          }
+        }
+      }
     }
+    };
+    if (e0 + (int64_t)(kChunkBlocks * S) <= n) steps(std::true_type{});
+    else steps(std::false_type{});
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     uint32_t* dst = payload + chunk_off[c];
-    for (int t = l; t < total; t += kWave) dst[t] = lin[t];
+    for (int k = l; k < total; k += kWave) dst[k] = lin[k];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -289,12 +489,23 @@ __device__ void put_bytes(uint8_t* h, int off, const void* v, int nbytes) {
 }
 
 // Header and zero padding.  One workgroup.
-__global__ void k_header(uint8_t* out, const CompressWs* ws, int dtype, int ndim, int64_t d0, int64_t d1,
-                         int64_t d2, int64_t n, int block, int64_t nb, int64_t nchunks, uint64_t off_chunk,
-                         uint64_t off_q0, uint64_t off_width, uint64_t off_payload) {
+__global__ void k_header(uint8_t* out, CompressWs* ws, const uint32_t* __restrict__ group_max, int groups,
+                         int dtype, int ndim, int64_t d0, int64_t d1, int64_t d2, int64_t n, int block, int64_t nb,
+                         int64_t nchunks, uint64_t off_chunk, uint64_t off_q0, uint64_t off_width,
+                         uint64_t off_payload) {
   __shared__ uint8_t h[kHeaderBytes];
+  __shared__ uint32_t smax[kHeaderBytes];
   const int t = threadIdx.x;
   if (t < kHeaderBytes) h[t] = 0;
+  uint32_t m = 0;
+  for (int g = t; g < groups; g += blockDim.x) m = group_max[g] > m ? group_max[g] : m;
+  smax[t] = m;
+  __syncthreads();
+  for (int half = kHeaderBytes / 2; half >= 1; half >>= 1) {
+    if (t < half && smax[t + half] > smax[t]) smax[t] = smax[t + half];
+    __syncthreads();
+  }
+  if (t == 0) ws->max_abs_q = smax[0];
   __syncthreads();
   if (t == 0) {
     h[0] = 'H'; h[1] = 'S'; h[2] = 'Z'; h[3] = '1';
@@ -331,6 +542,15 @@ __global__ void k_header(uint8_t* out, const CompressWs* ws, int dtype, int ndim
     if (ends[s] + t < next[s]) out[ends[s] + t] = 0;
 }
 
+// workspace: CompressWs | min/max partials | chunk word counts | range sums | group max|q|
+uint64_t ws_range_sums_off(const Layout& L) {
+  return kWsPartials + 24 * (uint64_t)kMinmaxGroups + align_up(4 * (uint64_t)L.nchunks, 256);
+}
+uint64_t ws_group_max_off(const Layout& L) {
+  const uint64_t ranges = (L.nchunks + kScanRange - 1) / kScanRange;
+  return align_up(ws_range_sums_off(L) + 8 * ranges, 256);
+}
+
 template <typename T, int S>
 hipError_t run(const CompressArgs& a, hipStream_t s) {
   const Layout& L = a.lay;
@@ -339,22 +559,26 @@ hipError_t run(const CompressArgs& a, hipStream_t s) {
   uint32_t* chunk_words = (uint32_t*)(a.ws + kWsPartials + 24 * kMinmaxGroups);
   uint8_t* out = a.out;
   const T* x = (const T*)a.x;
-  int g = (int)((L.n + kThreads * 8 - 1) / (kThreads * 8));
+  int g = (int)((L.n + kThreads * 16 - 1) / (kThreads * 16));
   g = g < 1 ? 1 : (g > kMinmaxGroups ? kMinmaxGroups : g);
   hipLaunchKernelGGL(k_minmax<T>, dim3(g), dim3(kThreads), 0, s, x, L.n, partial);
   hipLaunchKernelGGL(k_params, dim3(1), dim3(kThreads), 0, s, partial, g, a.eb, a.eb_is_rel, a.dtype, ws);
   const int64_t cg = (L.nchunks + 3) / 4;
-  const int grid = (int)(cg < 4096 ? cg : 4096);
+  const int grid = (int)(cg < kMetaGroups ? cg : kMetaGroups);
+  uint32_t* group_max = (uint32_t*)(a.ws + ws_group_max_off(L));
   hipLaunchKernelGGL((k_quant_meta<T, S>), dim3(grid), dim3(kThreads), 0, s, x, L.n, L.nb, L.nchunks, ws,
-                     (int32_t*)(out + L.off_q0), out + L.off_width, chunk_words);
-  hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, chunk_words, L.nchunks,
+                     (int32_t*)(out + L.off_q0), out + L.off_width, chunk_words, group_max);
+  const unsigned ranges = (unsigned)((L.nchunks + kScanRange - 1) / kScanRange);
+  uint64_t* range_sums = (uint64_t*)(a.ws + ws_range_sums_off(L));
+  hipLaunchKernelGGL(k_scan_sums, dim3(ranges), dim3(kScanThreads), 0, s, chunk_words, L.nchunks, range_sums);
+  hipLaunchKernelGGL(k_scan_write, dim3(ranges), dim3(kScanThreads), 0, s, chunk_words, L.nchunks, range_sums,
                      (uint64_t*)(out + L.off_chunk), ws, L.off_payload, a.cap);
   hipLaunchKernelGGL((k_pack<T, S>), dim3(grid), dim3(kThreads), 0, s, x, L.n, L.nb, L.nchunks, ws,
                      (const uint8_t*)(out + L.off_width), (const uint64_t*)(out + L.off_chunk),
                      (uint32_t*)(out + L.off_payload));
-  hipLaunchKernelGGL(k_header, dim3(1), dim3(kHeaderBytes), 0, s, out, ws, a.dtype, a.ndim, a.dims[0],
-                     a.dims[1], a.dims[2], L.n, L.block, L.nb, L.nchunks, L.off_chunk, L.off_q0,
-                     L.off_width, L.off_payload);
+  hipLaunchKernelGGL(k_header, dim3(1), dim3(kHeaderBytes), 0, s, out, ws, (const uint32_t*)group_max, grid,
+                     a.dtype, a.ndim, a.dims[0], a.dims[1], a.dims[2], L.n, L.block, L.nb, L.nchunks, L.off_chunk,
+                     L.off_q0, L.off_width, L.off_payload);
   return hipGetLastError();
 }
 
@@ -373,9 +597,7 @@ Layout make_layout(int64_t n, int block) {
   return L;
 }
 
-uint64_t compress_workspace_bytes(const Layout& lay) {
-  return kWsPartials + 24 * (uint64_t)kMinmaxGroups + 4 * (uint64_t)lay.nchunks + 256;
-}
+uint64_t compress_workspace_bytes(const Layout& lay) { return ws_group_max_off(lay) + 4 * (uint64_t)kMetaGroups; }
 
 hipError_t launch_compress(const CompressArgs& a, hipStream_t s) {
   if (a.dtype == 1)
