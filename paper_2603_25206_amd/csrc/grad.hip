@@ -132,10 +132,22 @@ __global__ void __launch_bounds__(kBufThreads) k_grad_buf(const void* __restrict
 
 // ---- fused: decode tiles from the compressed stream --------------------------------
 constexpr int kTx = 256, kTy = 16, kRows = kTy + 2, kCols = kTx + 2;
-constexpr int kPitch = kCols + (kCols >> 5) + 1;  // one pad word per 32: conflict-free block writes
 constexpr int kFusedThreads = kTx;
 
-__device__ __forceinline__ int pidx(int r, int c) { return r * kPitch + c + (c >> 5); }
+// LDS row pitch of a decoded plane.  Rows hold one pad word per 32 columns,
+// so consecutive blocks of a row start (S + S/32) words apart; decode lane i
+// owns block i % NBR of row i / NBR.  A pitch congruent to NBR (S + S/32)
+// modulo 64 places lane i's slot j at i (S + S/32) + const (mod 64): for
+// S = 32 (an odd block span) the 64 lanes of a wave write 64 distinct banks.
+constexpr int conflict_free_pitch(int min_pitch, int nbr, int span) {
+  int p = min_pitch;
+  while (p % 64 != (nbr * span) % 64) ++p;
+  return p;
+}
+template <int S>
+constexpr int kNbr = (kCols + S - 2) / S + 1;  // max blocks covering one decoded row
+template <int S>
+constexpr int kPitch = conflict_free_pitch(kCols + (kCols >> 5), kNbr<S>, S + S / 32);
 
 // One workgroup: a tile of kTx columns x kTy rows, marching over tz planes.
 // Every decoded row's covering blocks get one thread each (decode items);
@@ -171,11 +183,12 @@ __device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint
   // per-row state from the previous plane: one in-plane numerator (a single
   // derivative) or gy^2 + gx^2 (the magnitude)
   using G = typename std::conditional<OP == 3, N, T>::type;
-  constexpr int NBR = (kCols + S - 2) / S + 1;  // max blocks covering one decoded row
-  constexpr int PF = 16 * (S / 32);             // payload words prefetched per thread
+  constexpr int NBR = kNbr<S>;
+  constexpr int PF = 16 * (S / 32);  // payload words prefetched per thread
+  constexpr int kP = kPitch<S>;
   static_assert(kRows * NBR <= kFusedThreads, "one decode item per thread");
   V* plane = (V*)smem;
-  uint32_t* stage = smem + (kRows * kPitch * sizeof(V) + 3) / 4;
+  uint32_t* stage = smem + (kRows * kP * sizeof(V) + 3) / 4;
   const int t = threadIdx.x;
 
   const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0;
@@ -200,7 +213,7 @@ __device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint
   const int dr = t / NBR, dk = t % NBR;
   const int64_t dy = rA + dr;
   const bool decoder = dr < nrows;
-  V* prow = plane + (int)(dy - (y0 - 1)) * kPitch;
+  V* prow = plane + (int)(dy - (y0 - 1)) * kP;
   uint32_t* col = stage + t;
 
   struct Meta {
@@ -305,18 +318,18 @@ __device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint
         if (i < ys) {
           const int r = i + 1;
           const int64_t y = y0 + i;
-          const V qc = plane[r * kPitch + ac];
+          const V qc = plane[r * kP + ac];
           N nx = 0, ny = 0;
           if (need_x) {
-            const V vm = plane[r * kPitch + am], vp = plane[r * kPitch + ap];
+            const V vm = plane[r * kP + am], vp = plane[r * kP + ap];
             const V lo = xlo ? qc : vm, hi = xhi ? qc : vp;
             if constexpr (INT) nx = xone ? 0 : (hi - lo) * ((xlo || xhi) ? 2 : 1);
             else nx = xone ? T(0) : (xlo || xhi) ? hi - lo : (hi - lo) * T(0.5);
           }
           if (need_y) {
             const bool ylo = y == 0, yhi = y == d.y - 1;
-            const V lo = ylo ? qc : plane[(r - 1) * kPitch + ac];
-            const V hi = yhi ? qc : plane[(r + 1) * kPitch + ac];
+            const V lo = ylo ? qc : plane[(r - 1) * kP + ac];
+            const V hi = yhi ? qc : plane[(r + 1) * kP + ac];
             if constexpr (INT) ny = d.y < 2 ? 0 : (hi - lo) * ((ylo || yhi) ? 2 : 1);
             else ny = d.y < 2 ? T(0) : (ylo || yhi) ? hi - lo : (hi - lo) * T(0.5);
           }
@@ -388,8 +401,11 @@ template <int S>
 struct QRow {
   static constexpr int kOff = S - 1;  // extended column of tile column 0 (x = x0 - 1)
   static constexpr int kExt = kCols + 2 * (S - 1);
-  static constexpr int kPitch = kExt + (kExt >> 5) + 1;
+  static constexpr int kPitch = conflict_free_pitch(kExt + (kExt >> 5), kNbr<S>, S + S / 32);
   static __host__ __device__ constexpr int at(int e) { return e + (e >> 5); }
+  // staging columns start on a 256-byte boundary, so the constant part of
+  // every staging address fits the offset field of a strided LDS read
+  static constexpr int kStageOff = (kRows * kPitch + 63) / 64 * 64;
 };
 
 // Decode one staged block (column 'col', stride kFusedThreads) and write its
@@ -402,27 +418,28 @@ __device__ __forceinline__ void decode_block_q(const uint32_t* col, int w, int q
   const uint32_t* mag = col + (S / 32) * kFusedThreads;
   int* dst1 = dst + 1;
   int q = q0;
-  int wg = w;
+  uint32_t uw = (uint32_t)w;
 #pragma unroll
   for (int g = 0; g < S; g += 8) {
-    // an empty asm that "changes" wg keeps the compiler from computing the
+    // an empty asm that "changes" uw keeps the compiler from computing the
     // bit positions of all S slots up front (S live registers)
-    asm volatile("" : "+v"(wg));
-    uint32_t lo[8], hi[8];
+    asm volatile("" : "+v"(uw));
+    uint32_t lo[8], hi[8], pos[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const uint32_t pos = (uint32_t)(g + u) * (uint32_t)wg;
-      const uint32_t* a = mag + (pos >> 5) * kFusedThreads;
+      pos[u] = __umul24((uint32_t)(g + u), uw);  // full-rate 24-bit multiply
+      uint32_t k = pos[u] >> 5;
+      asm("" : "+v"(k));  // one shift-add per address (see decode_lane_block)
+      const uint32_t* a = mag + k * kFusedThreads;
       lo[u] = a[0];
       hi[u] = a[kFusedThreads];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int j = g + u;
-      const uint32_t pos = (uint32_t)j * (uint32_t)wg;
-      const uint32_t m = __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(hi[u], lo[u], pos), 0u, (uint32_t)wg);
+      const uint32_t m = __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(hi[u], lo[u], pos[u]), 0u, uw);
       const int sg = __builtin_amdgcn_sbfe((int)(j < 32 ? sg0 : sg1), (uint32_t)(j & 31), 1u);
-      q += (int)(m ^ (uint32_t)sg) - sg;
+      q = (int)((m ^ (uint32_t)sg) + (uint32_t)q) - sg;  // q += (m ^ sg) - sg
       if constexpr (ALIGNED) {
         dst[j + (j >> 5)] = q;
       } else {
@@ -430,6 +447,31 @@ __device__ __forceinline__ void decode_block_q(const uint32_t* col, int w, int q
         d[j + (j >> 5)] = q;
       }
     }
+  }
+}
+
+// Words [0, min(words, N)) of a block at payload word 'off' into w[] (the
+// rest 0).  A block's words are contiguous and the blocks of a decoded row
+// follow each other in the payload, so each lane reads its words four at a
+// time: one 16-byte load per four words (dword aligned) instead of four
+// scattered dword loads.  Four-word groups may run into the next block's
+// words (ignored); near the end of the payload the lane reads word by word.
+template <int N>
+__device__ __forceinline__ void prefetch_words(const uint32_t* __restrict__ payload, uint64_t payload_words,
+                                               uint64_t off, int words, uint32_t (&w)[N]) {
+  static_assert(N % 4 == 0, "four-word groups");
+  typedef uint32_t u4 __attribute__((ext_vector_type(4), aligned(4)));
+  const uint32_t* src = payload + off;
+  if (off + N <= payload_words) {
+#pragma unroll
+    for (int k = 0; k < N; k += 4) {
+      u4 t = {0u, 0u, 0u, 0u};
+      if (k < words) t = *(const u4*)(src + k);
+      w[k] = t.x; w[k + 1] = t.y; w[k + 2] = t.z; w[k + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) w[k] = (k < words) ? src[k] : 0u;
   }
 }
 
@@ -445,11 +487,11 @@ __device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, ui
   const int axis = job.axis, tz = job.tz, kmax = job.kmax;
   const double halfq = job.halfq;
   T* __restrict__ out = (T*)job.out;
-  constexpr int NBR = (kCols + S - 2) / S + 1;  // max blocks covering one decoded row
-  constexpr int PF = 16 * (S / 32);             // payload words prefetched per thread
+  constexpr int NBR = kNbr<S>;
+  constexpr int PF = 16 * (S / 32);  // payload words prefetched per thread
   static_assert(kRows * NBR <= kFusedThreads, "one decode item per thread");
   int* const pl = (int*)smem;
-  uint32_t* stage = smem + kRows * P;
+  uint32_t* stage = smem + R::kStageOff;
   const int t = threadIdx.x;
 
   const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0;
@@ -633,11 +675,7 @@ __device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, ui
     // B: prefetch plane p+1's payload, request plane p+2's metadata
     check(nxt);
     uint32_t pw[PF];
-    {
-      const uint32_t* src = v.payload + nxt.off;
-#pragma unroll
-      for (int k = 0; k < PF; ++k) pw[k] = (k < nxt.words) ? src[k] : 0u;
-    }
+    prefetch_words<PF>(v.payload, v.payload_words, nxt.off, nxt.words, pw);
     const Meta nn = meta_of(p + 2);
     if (active) rows(p);  // C
     // D: plane p+1's words into this thread's staging column
@@ -901,9 +939,9 @@ hipError_t fast_delta(const int32_t* p, const StreamView& v, const OpTarget& t, 
 // route, padded rows of T for the float route) and the staging columns.
 size_t grad_lds_bytes(int S, int dtype, int via, int kmax) {
   const size_t stage = (size_t)(kmax + 1) * kFusedThreads * sizeof(uint32_t);
-  if (via == 3) return (size_t)kRows * (S == 32 ? QRow<32>::kPitch : QRow<64>::kPitch) * sizeof(int) + stage;
+  if (via == 3) return (size_t)(S == 32 ? QRow<32>::kStageOff : QRow<64>::kStageOff) * sizeof(int) + stage;
   const size_t vsz = dtype == 2 ? 8 : 4;
-  return ((kRows * kPitch * vsz + 3) / 4) * 4 + stage;
+  return ((kRows * (S == 32 ? kPitch<32> : kPitch<64>) * vsz + 3) / 4) * 4 + stage;
 }
 
 template <int S, int VIA, int OP, typename T, int ACC>

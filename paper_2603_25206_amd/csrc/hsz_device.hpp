@@ -327,13 +327,27 @@ __device__ __forceinline__ bool stage_chunk(const uint8_t* __restrict__ width,
     return false;
   }
   lb.w = w;
-  // copy: each lane its own words, eight at a time so the loads overlap
+  // copy: each lane its own words, eight at a time so the loads overlap;
+  // 16-byte loads (dword aligned) where the four-word group stays inside
+  // the payload (a group may run into the next block's words: ignored)
   const uint32_t* src = payload + base + woff;
+  const uint64_t avail = payload_words - (base + woff);
+  typedef uint32_t u4 __attribute__((ext_vector_type(4), aligned(4)));
   int maxnw = wave_max(nw);
   for (int k0 = 0; k0 < maxnw; k0 += 8) {
     uint32_t v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = (k0 + u < nw) ? src[k0 + u] : 0u;
+    for (int h = 0; h < 8; h += 4) {
+      const int k = k0 + h;
+      if ((uint64_t)(k + 4) <= avail) {
+        u4 t = {0u, 0u, 0u, 0u};
+        if (k < nw) t = *(const u4*)(src + k);
+        v[h] = t.x; v[h + 1] = t.y; v[h + 2] = t.z; v[h + 3] = t.w;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[h + u] = (k + u < nw) ? src[k + u] : 0u;
+      }
+    }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
       if (k0 + u < nw) tile[(k0 + u) * kWave + l] = v[u];
@@ -409,19 +423,38 @@ __device__ __forceinline__ void decode_lane_block(const uint32_t* col, int w, in
   const uint32_t sg1 = (S == 64 && w) ? col[STRIDE] : 0u;
   const uint32_t* mag = col + (S / 32) * STRIDE;
   int q = q0;
+  uint32_t uw = (uint32_t)w;
 #pragma unroll
-  for (int j = 0; j < S; ++j) {
-    const uint32_t pos = (uint32_t)j * (uint32_t)w;
-    const uint32_t k = pos >> 5;
-    const uint32_t lo = mag[k * STRIDE];
-    const uint32_t hi = mag[(k + 1) * STRIDE];
-    const uint32_t a = __builtin_amdgcn_alignbit(hi, lo, pos & 31u);
-    const uint32_t m = __builtin_amdgcn_ubfe(a, 0u, (uint32_t)w);
-    const int s = (j < 32) ? __builtin_amdgcn_sbfe((int)sg0, (uint32_t)j, 1u)
-                           : __builtin_amdgcn_sbfe((int)sg1, (uint32_t)(j - 32), 1u);
-    const int p = (int)(m ^ (uint32_t)s) - s;
-    q += p;
-    sink(j, p, q);
+  for (int g = 0; g < S; g += 8) {
+    // an empty asm that "changes" uw keeps the compiler from computing the
+    // bit positions of all S slots up front (S live registers)
+    asm volatile("" : "+v"(uw));
+    uint32_t lo[8], hi[8], pos[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      // bit position j*w (24-bit multiply, full rate); word pos/32 and the next
+      pos[u] = __umul24((uint32_t)(g + u), uw);
+      // the word index, opaque to the optimiser: otherwise it folds j*w into
+      // each address (multiply, mask, add) and recomputes j*w for the bit
+      // offset, sometimes with the quarter-rate 32-bit multiply
+      uint32_t k = pos[u] >> 5;
+      asm("" : "+v"(k));
+      const uint32_t* a = mag + k * STRIDE;
+      lo[u] = a[0];
+      hi[u] = a[STRIDE];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = g + u;
+      const uint32_t m = __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(hi[u], lo[u], pos[u]), 0u, uw);
+      const int sg = __builtin_amdgcn_sbfe((int)(j < 32 ? sg0 : sg1), (uint32_t)(j & 31), 1u);
+      // p = (m ^ sg) - sg applies the sign (sg = 0 or -1); q is formed as
+      // ((m ^ sg) + q) - sg so that a sink using only q costs one xor-add
+      const uint32_t x = m ^ (uint32_t)sg;
+      const int p = (int)x - sg;
+      q = (int)(x + (uint32_t)q) - sg;
+      sink(j, p, q);
+    }
   }
 }
 
