@@ -52,6 +52,7 @@ CASES = [
     ((37, 41, 29), np.float32, 1e-4, 32),  # ragged: n % 32 != 0, nb % 64 != 0
     ((37, 41, 29), np.float32, 1e-2, 64),
     ((5, 300, 211), np.float32, 1e-4, 64),
+    ((6, 37, 264), np.float32, 1e-3, 32),  # whole 256 x 16 gradient tiles beside partial ones in x and y
     ((181, 367), np.float64, 1e-6, 32),
     ((20, 33, 70), np.float64, 1e-6, 64),
     ((100003,), np.float32, 1e-3, 32),
