@@ -292,21 +292,32 @@ struct LaneBlock {
   int64_t b;    // block index
 };
 
-// Stage chunk c: lane l loads the width and q0 of block 64c+l, the wave
-// scans the payload word counts, checks them against the chunk table, and
-// copies every lane's payload words into its column of the LDS tile
-// (tile rows = kmax+1, row k at tile + k*64).  Returns false (and records a
-// status) when the chunk is inconsistent; the lane's block is then treated
-// as all-zero.
-template <int S>
-__device__ __forceinline__ bool stage_chunk(const uint8_t* __restrict__ width,
-                                           const int32_t* __restrict__ q0s,
-                                           const uint64_t* __restrict__ chunk_off,
-                                           const uint32_t* __restrict__ payload,
-                                           uint64_t payload_words, int64_t n, int64_t nb,
-                                           int64_t c, uint32_t* tile, int kmax, LaneBlock& lb,
-                                           int* status) {
+// Staging of chunk c in two halves, so that a wave can load chunk c+1 while
+// it decodes chunk c.  chunk_begin: lane l loads the width and q0 of block
+// 64c+l, the wave scans the payload word counts and checks them against the
+// chunk table, and the lane loads the first PF words of its block into
+// registers (16-byte loads, dword aligned, where the four-word group stays
+// inside the payload; a group may run into the next block's words, which
+// are ignored).  chunk_end: the words go to the lane's column of the LDS
+// tile (tile rows = kmax+1, row k at tile + k*64); words past PF are copied
+// there directly.  An inconsistent chunk records a status and its lanes
+// decode as all-zero blocks.
+template <int PF>
+struct ChunkStage {
+  LaneBlock lb;
+  int nw;                  // payload words of the lane's block
+  const uint32_t* src;     // the block's first payload word
+  uint32_t pw[PF];         // words [0, PF) of the block
+};
+
+template <int S, int PF>
+__device__ __forceinline__ void chunk_begin(const uint8_t* __restrict__ width, const int32_t* __restrict__ q0s,
+                                            const uint64_t* __restrict__ chunk_off,
+                                            const uint32_t* __restrict__ payload, uint64_t payload_words, int64_t n,
+                                            int64_t nb, int64_t c, int kmax, ChunkStage<PF>& cs, int* status) {
+  static_assert(PF % 4 == 0, "four-word groups");
   const int l = lane_id();
+  LaneBlock& lb = cs.lb;
   lb.b = c * kChunkBlocks + l;
   const bool valid = lb.b < nb;
   int w = valid ? (int)width[lb.b] : 0;
@@ -323,36 +334,49 @@ __device__ __forceinline__ bool stage_chunk(const uint8_t* __restrict__ width,
   int any_bad = __any(bad);
   if (any_bad || next - base != (uint64_t)total || next > payload_words) {
     if (l == 0) record_status(status, kErrBadStream);
-    lb.w = 0;
-    return false;
+    w = 0;
+    nw = 0;
   }
   lb.w = w;
-  // copy: each lane its own words, eight at a time so the loads overlap;
-  // 16-byte loads (dword aligned) where the four-word group stays inside
-  // the payload (a group may run into the next block's words: ignored)
-  const uint32_t* src = payload + base + woff;
+  cs.nw = nw;
+  cs.src = payload + base + woff;
   const uint64_t avail = payload_words - (base + woff);
   typedef uint32_t u4 __attribute__((ext_vector_type(4), aligned(4)));
-  int maxnw = wave_max(nw);
-  for (int k0 = 0; k0 < maxnw; k0 += 8) {
-    uint32_t v[8];
 #pragma unroll
-    for (int h = 0; h < 8; h += 4) {
-      const int k = k0 + h;
-      if ((uint64_t)(k + 4) <= avail) {
-        u4 t = {0u, 0u, 0u, 0u};
-        if (k < nw) t = *(const u4*)(src + k);
-        v[h] = t.x; v[h + 1] = t.y; v[h + 2] = t.z; v[h + 3] = t.w;
-      } else {
+  for (int k = 0; k < PF; k += 4) {
+    if ((uint64_t)(k + 4) <= avail) {
+      u4 t = {0u, 0u, 0u, 0u};
+      if (k < nw) t = *(const u4*)(cs.src + k);
+      cs.pw[k] = t.x; cs.pw[k + 1] = t.y; cs.pw[k + 2] = t.z; cs.pw[k + 3] = t.w;
+    } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[h + u] = (k + u < nw) ? src[k + u] : 0u;
-      }
+      for (int u = 0; u < 4; ++u) cs.pw[k + u] = (k + u < nw) ? cs.src[k + u] : 0u;
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (k0 + u < nw) tile[(k0 + u) * kWave + l] = v[u];
   }
-  return true;
+}
+
+template <int PF>
+__device__ __forceinline__ void chunk_end(const ChunkStage<PF>& cs, uint32_t* tile) {
+  const int l = lane_id();
+#pragma unroll
+  for (int k = 0; k < PF; ++k)
+    if (k < cs.nw) tile[k * kWave + l] = cs.pw[k];
+  for (int k = PF; k < cs.nw; ++k) tile[k * kWave + l] = cs.src[k];
+}
+
+// Both halves at once.
+template <int S>
+__device__ __forceinline__ void stage_chunk(const uint8_t* __restrict__ width,
+                                           const int32_t* __restrict__ q0s,
+                                           const uint64_t* __restrict__ chunk_off,
+                                           const uint32_t* __restrict__ payload,
+                                           uint64_t payload_words, int64_t n, int64_t nb,
+                                           int64_t c, uint32_t* tile, int kmax, LaneBlock& lb,
+                                           int* status) {
+  ChunkStage<8> cs;
+  chunk_begin<S, 8>(width, q0s, chunk_off, payload, payload_words, n, nb, c, kmax, cs, status);
+  chunk_end<8>(cs, tile);
+  lb = cs.lb;
 }
 
 // ---- random access to one block ----------------------------------------------

@@ -288,6 +288,38 @@ __global__ void __launch_bounds__(kThreads) k_stats_delta(const int32_t* __restr
   store_int_partial(acc, parts);
 }
 
+// ---- whole blocks of streams with small integers -----------------------------------
+// Exact sums over one whole block (slots 0 .. S-1 all counted) when the
+// stream's max|q| is below small_q_limit<MODE>(): the block's terms are
+// summed in 32 bits with 24-bit multiply-adds and widened once per block.
+//   MODE 0, the stage-2 block sum S q0 + sum_{j>=1} (S - j) p_j: |p| < 2^23
+//     fits the 24-bit operands, terms are below 2^29 and every partial sum
+//     is bounded by 2 S max|q| < 2^29 (summation by parts);
+//   MODE 1, sum q: below S 2^22;
+//   MODE 2, sum q and sum q^2: q^2 < 2^26 and S q^2 < 2^32 (unsigned).
+template <int MODE>
+__host__ __device__ constexpr uint32_t small_q_limit() { return MODE == 2 ? 8192u : (1u << 22); }
+
+template <int S, int MODE>
+__device__ __forceinline__ void whole_block_sums(const uint32_t* col, int w, int q0, IntAcc& a) {
+  int s1 = 0;
+  uint32_t s2 = 0;
+  if constexpr (MODE == 0) {
+    decode_lane_block<S>(col, w, q0, [&](int j, int p, int) {
+      if (j >= 1) s1 = __mul24(S - j, p) + s1;
+    });
+    a.s1 += (int64_t)S * q0 + s1;
+  } else {
+    decode_lane_block<S>(col, w, q0, [&](int, int, int q) {
+      s1 += q;
+      if constexpr (MODE == 2) s2 = (uint32_t)__mul24(q, q) + s2;
+    });
+    a.s1 += s1;
+    if constexpr (MODE == 2) add_u64(a.s2, (uint64_t)s2);
+  }
+  a.cnt += S;
+}
+
 // ---- fused statistics straight from the compressed stream ------------------------
 // VIA: 2 (decorrelated), 3 (quantized), 4 (floats).  WHOLE: the items are
 // every block in order (chunk-aligned waves use the chunk scan).
@@ -305,22 +337,16 @@ __global__ void __launch_bounds__(kThreads) k_stats_fused(StreamView v, Segs<S> 
   const double K = (VIA == 4) ? *Kp : 0.0;
   const int64_t waves = (int64_t)gridDim.x * kWavesPerGroup;
   const int64_t items = WHOLE ? v.nchunks * kChunkBlocks : segs.count();
-  for (int64_t base = (blockIdx.x * (int64_t)kWavesPerGroup + wv) * kWave; base < items; base += waves * kWave) {
-    int w, q0, a, z;
-    int64_t b;
-    if constexpr (WHOLE) {
-      LaneBlock lb;
-      stage_chunk<S>(v.width, v.q0, v.chunk_off, v.payload, v.payload_words, v.n, v.nb, base / kWave, tile,
-                     kmax, lb, status);
-      w = lb.w; q0 = lb.q0; a = 0; z = lb.len - 1; b = lb.b;
-    } else {
-      const int64_t it = base + l;
-      bool ok = it < items && segs.get(it, b, a, z);
-      w = 0; q0 = 0;
-      if (ok) w = stage_block<S, kWave>(v.width, v.q0, v.chunk_off, v.payload, v.payload_words, v.nb, b, tile + l, kmax, q0, status);
-      else z = -1;
+  constexpr int kMode = (VIA == 2 && OP == 1) ? 0 : OP;
+  const bool small = v.max_abs_q < small_q_limit<kMode>();
+  // one block of the lane: slots a..z counted
+  auto process = [&](int w, int q0, int a, int z) {
+    if constexpr (VIA != 4) {
+      if (small && a == 0 && z == S - 1) {
+        whole_block_sums<S, kMode>(tile + l, w, q0, acc);
+        return;
+      }
     }
-    if (z < 0) continue;
     if constexpr (VIA == 2 && OP == 1) {
       // weighted block sum, no recorrelation
       int64_t s = (int64_t)(z - a + 1) * q0;
@@ -342,6 +368,35 @@ __global__ void __launch_bounds__(kThreads) k_stats_fused(StreamView v, Segs<S> 
       decode_lane_block<S>(tile + l, w, q0, [&](int j, int, int q) {
         if (j >= a && j <= z) acc.add(q, OP == 2);
       });
+    }
+  };
+  if constexpr (WHOLE) {
+    // chunks c, c + W, ... (W = waves of the grid); the next chunk's
+    // metadata and first words load while this one decodes
+    constexpr int PF = 16;
+    int64_t c = blockIdx.x * (int64_t)kWavesPerGroup + wv;
+    ChunkStage<PF> cs;
+    if (c < v.nchunks)
+      chunk_begin<S, PF>(v.width, v.q0, v.chunk_off, v.payload, v.payload_words, v.n, v.nb, c, kmax, cs, status);
+    for (; c < v.nchunks; c += waves) {
+      chunk_end<PF>(cs, tile);
+      const LaneBlock lb = cs.lb;
+      if (c + waves < v.nchunks)
+        chunk_begin<S, PF>(v.width, v.q0, v.chunk_off, v.payload, v.payload_words, v.n, v.nb, c + waves, kmax, cs,
+                           status);
+      if (lb.len > 0) process(lb.w, lb.q0, 0, lb.len - 1);
+    }
+  } else {
+    for (int64_t base = (blockIdx.x * (int64_t)kWavesPerGroup + wv) * kWave; base < items; base += waves * kWave) {
+      const int64_t it = base + l;
+      int64_t b;
+      int a = 0, z = -1, q0 = 0, w = 0;
+      if (it < items && segs.get(it, b, a, z))
+        w = stage_block<S, kWave>(v.width, v.q0, v.chunk_off, v.payload, v.payload_words, v.nb, b, tile + l, kmax,
+                                  q0, status);
+      else
+        z = -1;
+      if (z >= 0) process(w, q0, a, z);
     }
   }
   if constexpr (VIA == 4) store_f64_partial(f1, f2, fcnt, K, parts);
@@ -464,6 +519,10 @@ __device__ __forceinline__ void stats_unit(const StatsJob& J, int64_t lu, uint32
       sz = -1;
   }
   if (sz < 0) return;
+  if (J.v.max_abs_q < small_q_limit<MODE>() && sa == 0 && sz == S - 1) {
+    whole_block_sums<S, MODE>(tile + l, w, q0, a);
+    return;
+  }
   if constexpr (MODE == 0) {
     int64_t s = (int64_t)(sz - sa + 1) * q0;
     decode_lane_block<S>(tile + l, w, q0, [&](int j, int p, int) {
