@@ -18,6 +18,11 @@ Functions and the passages of the paper they follow:
   mean, var          Sec. III-B Eq. (var) on the decompressed field
   derivative,        Sec. III-B Eq. (derivatives), unit spacing, one-sided
   gradmag            at the ends of an axis
+  laplacian          Sec. III-B Eq. (laplacian) over every axis, the end
+                     value standing in for the missing neighbour
+  divergence, curl   Sec. III-B Eq. (divergence) and Eq. (curl), component
+                     k paired with axis k; 3D curl is the vector whose last
+                     component is the printed 2D formula
   int_sums           sum q and sum q^2 of the quantized field (exact)
 """
 from __future__ import annotations
@@ -95,6 +100,11 @@ def _load():
     lib.or_derivative.argtypes = [P, P, i32, P, P, P]
     lib.or_gradmag.restype = i32
     lib.or_gradmag.argtypes = [P, P, P, P, P]
+    lib.or_laplacian.restype = i32
+    lib.or_laplacian.argtypes = [P, P, P, P, P]
+    for name in ("or_divergence", "or_curl"):
+        getattr(lib, name).restype = i32
+        getattr(lib, name).argtypes = [P, i32, P, P, P, P]
     lib.or_int_sums.restype = i32
     lib.or_int_sums.argtypes = [P, P, P, P, P, P, P, P]
     _lib = lib
@@ -317,6 +327,55 @@ def gradmag(x, box=None) -> np.ndarray:
     out = np.empty(_box_shape(x.shape, box), dtype=np.float64)
     _check(_load().or_gradmag(_ptr(x), _ptr(d), None if lo is None else _ptr(lo),
                               None if hi is None else _ptr(hi), _ptr(out)), "gradmag")
+    return out
+
+
+def laplacian(x, box=None) -> np.ndarray:
+    """Laplacian (Eq. (laplacian) summed over the field's axes, mirrored ends),
+    restricted to box."""
+    x, d = _field(x)
+    lo, hi = _box3(x.shape, box)
+    out = np.empty(_box_shape(x.shape, box), dtype=np.float64)
+    _check(_load().or_laplacian(_ptr(x), _ptr(d), None if lo is None else _ptr(lo),
+                                None if hi is None else _ptr(hi), _ptr(out)), "laplacian")
+    return out
+
+
+def _components(comps):
+    cs = [np.ascontiguousarray(c, dtype=np.float64) for c in comps]
+    shape = cs[0].shape
+    if len(cs) != len(shape) or any(c.shape != shape for c in cs):
+        raise ValueError("one component per axis, all of the field's shape")
+    arr = (ctypes.c_void_p * len(cs))(*[c.ctypes.data for c in cs])
+    return cs, shape, arr
+
+
+def divergence(comps, box=None) -> np.ndarray:
+    """sum_k d F_k / d x_k (Eq. (divergence)); comps[k] pairs with axis k."""
+    cs, shape, arr = _components(comps)
+    d = _dims3(shape)
+    lo, hi = _box3(shape, box)
+    out = np.empty(_box_shape(shape, box), dtype=np.float64)
+    _check(_load().or_divergence(ctypes.cast(arr, ctypes.c_void_p), len(cs), _ptr(d),
+                                 None if lo is None else _ptr(lo), None if hi is None else _ptr(hi),
+                                 _ptr(out)), "divergence")
+    return out
+
+
+def curl(comps, box=None) -> np.ndarray:
+    """Eq. (curl): 2D fields -> delta_1 F_0 - delta_0 F_1 (box-shaped);
+    3D fields -> array (3, *box) of the components
+    (delta_2 F_1 - delta_1 F_2, delta_0 F_2 - delta_2 F_0, delta_1 F_0 - delta_0 F_1)."""
+    cs, shape, arr = _components(comps)
+    if len(shape) not in (2, 3):
+        raise ValueError("curl needs a 2D or 3D field")
+    d = _dims3(shape)
+    lo, hi = _box3(shape, box)
+    bs = _box_shape(shape, box)
+    out = np.empty(bs if len(shape) == 2 else (3,) + bs, dtype=np.float64)
+    _check(_load().or_curl(ctypes.cast(arr, ctypes.c_void_p), len(cs), _ptr(d),
+                           None if lo is None else _ptr(lo), None if hi is None else _ptr(hi),
+                           _ptr(out)), "curl")
     return out
 
 

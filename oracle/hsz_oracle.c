@@ -22,9 +22,12 @@
  *     (enough bits for the largest |p|).
  *   - Alg. 2: partial decompression to decorrelated data, quantized data, or
  *     floats (decode, recorrelate, dequantize).
- *   - Sec. III-B, Eq. (var) and Eq. (derivatives): mean, standard deviation
- *     (N-1), central differences.  The operations here are computed plainly
- *     on the fully decompressed field, never with homomorphic shortcuts.
+ *   - Sec. III-B, Eq. (var), Eq. (derivatives), Eq. (laplacian),
+ *     Eq. (divergence) and Eq. (curl): mean, standard deviation (N-1),
+ *     central differences, the five-point (2D) / seven-point (3D) Laplacian,
+ *     divergence and curl of vector fields.  The operations here are
+ *     computed plainly on the fully decompressed field, never with
+ *     homomorphic shortcuts.
  *
  * Readings where the paper is silent (each is listed with its reason in the
  * design notes of the repository):
@@ -48,6 +51,18 @@
  *      differences, the two ends of an axis use one-sided differences
  *      (the rule of numpy.gradient with edge_order=1); an axis of length 1
  *      has derivative 0.  Gradient magnitude = sqrt(sum_k g_k^2).
+ *   R8 the Laplacian of Eq. (laplacian) on n axes is the sum over the axes
+ *      of d_{-1} + d_{+1} - 2 d (unit spacing); at the two ends of an axis
+ *      the missing neighbour is the end value itself (the field mirrored
+ *      about its last sample), so an axis of length 1 adds 0.
+ *   R9 divergence and curl, Eq. (divergence) and Eq. (curl), use the
+ *      derivative of R7 with component k of the vector field paired with
+ *      the field's own axis k (delta_x = axis 0).  Divergence =
+ *      sum_k delta_k F_k.  Curl of a 2D field = delta_1 F_0 - delta_0 F_1
+ *      (Eq. (curl) as printed); of a 3D field, the vector
+ *      (delta_2 F_1 - delta_1 F_2, delta_0 F_2 - delta_2 F_0,
+ *       delta_1 F_0 - delta_0 F_1), whose last component is the 2D
+ *      formula.
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC
  */
@@ -612,6 +627,79 @@ int or_gradmag(const double *x, const uint64_t *d, const int64_t *lo, const int6
           s += g * g;
         }
         out[o++] = sqrt(s);
+      }
+  return OR_OK;
+}
+
+/* second difference of the field along axis a at one point, rule R8 */
+static double second_diff_at(const double *x, const uint64_t *d, int a, int64_t z, int64_t y, int64_t xx) {
+  int64_t idx[3] = {z, y, xx};
+  int64_t len = (int64_t)d[a];
+  int64_t im = idx[a] > 0 ? idx[a] - 1 : idx[a];
+  int64_t ip = idx[a] < len - 1 ? idx[a] + 1 : idx[a];
+  int64_t jm[3] = {z, y, xx}, jp[3] = {z, y, xx};
+  jm[a] = im;
+  jp[a] = ip;
+  double v0 = x[((uint64_t)z * d[1] + (uint64_t)y) * d[2] + (uint64_t)xx];
+  double vm = x[((uint64_t)jm[0] * d[1] + (uint64_t)jm[1]) * d[2] + (uint64_t)jm[2]];
+  double vp = x[((uint64_t)jp[0] * d[1] + (uint64_t)jp[1]) * d[2] + (uint64_t)jp[2]];
+  return vm + vp - 2.0 * v0;
+}
+
+/* out[box volume] = Laplacian (Eq. (laplacian), rule R8) */
+int or_laplacian(const double *x, const uint64_t *d, const int64_t *lo, const int64_t *hi, double *out) {
+  or_box b;
+  if (!box_ok(d, lo, hi, &b)) return OR_ERR_ARG;
+  uint64_t o = 0;
+  for (int64_t z = b.lo[0]; z < b.hi[0]; z++)
+    for (int64_t y = b.lo[1]; y < b.hi[1]; y++)
+      for (int64_t xx = b.lo[2]; xx < b.hi[2]; xx++) {
+        double s = 0.0;
+        for (int a = 0; a < 3; a++) s += second_diff_at(x, d, a, z, y, xx);
+        out[o++] = s;
+      }
+  return OR_OK;
+}
+
+/* Divergence (Eq. (divergence), rule R9) of a vector field with one
+ * component per axis of the field: comp[k] is component k (field axis k =
+ * 3D-view axis k + 3 - ndim).  out[box volume]. */
+int or_divergence(const double *const *comp, int ndim, const uint64_t *d, const int64_t *lo, const int64_t *hi,
+                  double *out) {
+  or_box b;
+  if (ndim < 1 || ndim > 3 || !box_ok(d, lo, hi, &b)) return OR_ERR_ARG;
+  uint64_t o = 0;
+  for (int64_t z = b.lo[0]; z < b.hi[0]; z++)
+    for (int64_t y = b.lo[1]; y < b.hi[1]; y++)
+      for (int64_t xx = b.lo[2]; xx < b.hi[2]; xx++) {
+        double s = 0.0;
+        for (int k = 0; k < ndim; k++) s += deriv_at(comp[k], d, k + 3 - ndim, z, y, xx);
+        out[o++] = s;
+      }
+  return OR_OK;
+}
+
+/* Curl (Eq. (curl), rule R9).  ndim 2: out[box volume] = delta_1 F_0 -
+ * delta_0 F_1.  ndim 3: out holds the three components one after the
+ * other, each of box volume. */
+int or_curl(const double *const *comp, int ndim, const uint64_t *d, const int64_t *lo, const int64_t *hi,
+            double *out) {
+  or_box b;
+  if ((ndim != 2 && ndim != 3) || !box_ok(d, lo, hi, &b)) return OR_ERR_ARG;
+  const uint64_t vol = (uint64_t)(b.hi[0] - b.lo[0]) * (uint64_t)(b.hi[1] - b.lo[1]) * (uint64_t)(b.hi[2] - b.lo[2]);
+  const int base = 3 - ndim; /* 3D-view axis of field axis 0 */
+  uint64_t o = 0;
+  for (int64_t z = b.lo[0]; z < b.hi[0]; z++)
+    for (int64_t y = b.lo[1]; y < b.hi[1]; y++)
+      for (int64_t xx = b.lo[2]; xx < b.hi[2]; xx++) {
+        if (ndim == 2) {
+          out[o] = deriv_at(comp[0], d, base + 1, z, y, xx) - deriv_at(comp[1], d, base + 0, z, y, xx);
+        } else {
+          out[o] = deriv_at(comp[1], d, 2, z, y, xx) - deriv_at(comp[2], d, 1, z, y, xx);
+          out[vol + o] = deriv_at(comp[2], d, 0, z, y, xx) - deriv_at(comp[0], d, 2, z, y, xx);
+          out[2 * vol + o] = deriv_at(comp[0], d, 1, z, y, xx) - deriv_at(comp[1], d, 0, z, y, xx);
+        }
+        o++;
       }
   return OR_OK;
 }
