@@ -252,6 +252,10 @@ def main():
         for stn, st, view in (("quant", hsz.QUANT, qview), ("float", hsz.FLOAT, fview)):
             rows.append((f"gradmag_on_{stn}", (lambda v, s_: lambda c: hsz.op_on_stage(
                 v, h, s_, hsz.GRADMAG, out=gbuf, ws=ws[2], check=False, raw=True))(view, st)))
+            rows.append((f"laplacian_on_{stn}", (lambda v, s_: lambda c: hsz.op_on_stage(
+                v, h, s_, hsz.LAPLACIAN, out=gbuf, ws=ws[2], check=False, raw=True))(view, st)))
+            rows.append((f"laplacian_fused_{stn}", (lambda s_: lambda c: hsz.op_fused(
+                c, s_, hsz.LAPLACIAN, out=gbuf, ws=ws[2], check=False, raw=True))(st)))
         _, per = timed("ops", rows, 6, 2)
         extra.update(per)
         # compression (input resident in HBM)

@@ -55,7 +55,7 @@ enum {
 
 enum { HSZ_F32 = 1, HSZ_F64 = 2 };                                  /* field dtype */
 enum { HSZ_META = 1, HSZ_DELTA = 2, HSZ_QUANT = 3, HSZ_FLOAT = 4 }; /* Table I     */
-enum { HSZ_MEAN = 1, HSZ_VAR = 2, HSZ_DERIV = 3, HSZ_GRADMAG = 4 }; /* operations  */
+enum { HSZ_MEAN = 1, HSZ_VAR = 2, HSZ_DERIV = 3, HSZ_GRADMAG = 4, HSZ_LAPLACIAN = 5 }; /* operations */
 
 /* Size of the fixed header at the start of every compressed stream. */
 #define HSZ_HEADER_BYTES 256
@@ -173,12 +173,22 @@ int hsz_decompress_to_stage(const void *d_c, const hsz_header *h, int stage, voi
  * op = HSZ_DERIV (axis)  : result = derivative along 'axis' (0 = slowest)
  *      at every point of the box, field dtype, box-shaped C order.
  * op = HSZ_GRADMAG       : result = sqrt(sum over axes of derivative^2).
+ * op = HSZ_LAPLACIAN     : result = Laplacian, Eq. (laplacian) summed over
+ *      the field's axes: sum_k (d_{-1} + d_{+1} - 2 d) along axis k, unit
+ *      spacing, the end value standing in for the missing neighbour at the
+ *      two ends of an axis (an axis of length 1 adds 0).  On stage 3 (and
+ *      the fused path via 3) the integer numerator sum_k (q_{-1} + q_{+1} -
+ *      2 q) is exact and scaled once by Delta (Eq. (laplacian_Dq)); this
+ *      needs max|q| < 2^27 (else HSZ_ERR_UNSUPPORTED; stage 4 has no limit).
+ *      Stage 2 and batches: HSZ_ERR_UNSUPPORTED (a 1D partition keeps no
+ *      multidimensional neighbours, Sec. V-B).
  * Derivatives follow Eq. (derivatives): central differences (q_{+1} -
  * q_{-1}) * Delta/2 inside the field and one-sided (q_1 - q_0) * Delta at
  * its ends, unit spacing, neighbours taken from the whole field even when
  * they lie outside the box; an axis of length 1 contributes 0.
  * Stage support: MEAN/VAR on stages 2, 3, 4; DERIV/GRADMAG on 2, 3, 4;
- * stage 1 supports none (HSZ_ERR_UNSUPPORTED), as Table II lists for SZp. */
+ * LAPLACIAN on 3, 4; stage 1 supports none (HSZ_ERR_UNSUPPORTED), as
+ * Table II lists for SZp. */
 
 /* Workspace an operation needs (bytes; at least 256). */
 int hsz_op_workspace(const hsz_header *h, int op, uint64_t *h_bytes);

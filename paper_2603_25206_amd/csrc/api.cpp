@@ -17,6 +17,9 @@ __global__ void k_reset_status(int* status) {
   if (threadIdx.x == 0) *status = 0;
 }
 
+// The integer Laplacian numerator is a sum of 12 terms of |q| in 32 bits.
+constexpr uint32_t kLapMaxQ = 1u << 27;
+
 int reset_status(void* ws, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, (int*)ws);
   hipError_t e = hipGetLastError();
@@ -27,7 +30,7 @@ int op_common(const hsz_header* h, int op, int axis, const hsz_box* box, uint64_
               void* d_ws, uint64_t ws_bytes, hsz::OpTarget* t, int* axis3) {
   int rc = check_header(h);
   if (rc) return rc;
-  if (op < HSZ_MEAN || op > HSZ_GRADMAG) return HSZ_ERR_INVALID_ARG;
+  if (op < HSZ_MEAN || op > HSZ_LAPLACIAN) return HSZ_ERR_INVALID_ARG;
   if (!d_result || !d_ws || !aligned16(d_ws)) return HSZ_ERR_INVALID_ARG;
   if (ws_bytes < hsz::op_workspace_bytes()) return HSZ_ERR_CAPACITY;
   int64_t d3[3], n;
@@ -232,7 +235,7 @@ int hsz_block_index(const void* d_c, const hsz_header* h, void* d_index, uint64_
 }
 
 int hsz_op_workspace(const hsz_header* h, int op, uint64_t* h_bytes) {
-  if (!h || !h_bytes || op < HSZ_MEAN || op > HSZ_GRADMAG) return HSZ_ERR_INVALID_ARG;
+  if (!h || !h_bytes || op < HSZ_MEAN || op > HSZ_LAPLACIAN) return HSZ_ERR_INVALID_ARG;
   uint64_t a = hsz::op_workspace_bytes(), b = hsz::grad_workspace_bytes(h->nb);
   *h_bytes = (op >= HSZ_DERIV && b > a) ? b : a;
   return HSZ_OK;
@@ -250,6 +253,7 @@ int hsz_op_on_stage(const void* d_stage, const hsz_header* h, int stage, int op,
   // on the decorrelated stage only the derivative along the fast axis is
   // defined (the 1D partition keeps no other neighbour relation)
   if (op >= HSZ_DERIV && stage == HSZ_DELTA && !(op == HSZ_DERIV && axis3 == 2)) return HSZ_ERR_UNSUPPORTED;
+  if (op == HSZ_LAPLACIAN && stage == HSZ_QUANT && h->max_abs_q >= kLapMaxQ) return HSZ_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   if ((rc = reset_status(d_workspace, s))) return rc;
   const hsz::StreamView v = view_of(nullptr, h);
@@ -272,6 +276,7 @@ int hsz_op_fused(const void* d_c, const hsz_header* h, int via, int op, int axis
   const hsz::StreamView v = view_of(d_c, h);
   if (op >= HSZ_DERIV) {
     if (via == HSZ_DELTA && !(op == HSZ_DERIV && axis3 == 2)) return HSZ_ERR_UNSUPPORTED;
+    if (op == HSZ_LAPLACIAN && via == HSZ_QUANT && h->max_abs_q >= kLapMaxQ) return HSZ_ERR_UNSUPPORTED;
     if ((rc = reset_status(d_workspace, s))) return rc;
     hipError_t e = hsz::launch_grad_fused(v, via, op, axis3, t, d_result, (uint8_t*)d_workspace, s);
     if (e == hipErrorNotSupported) return HSZ_ERR_UNSUPPORTED;

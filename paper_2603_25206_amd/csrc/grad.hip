@@ -7,6 +7,9 @@
 // Float route (D_f): the same stencil on the decompressed values in the
 // field's own precision: (x_{+1} - x_{-1}) * 0.5 inside, x_1 - x_0 at the ends.
 // Gradient magnitude = sqrt(g_z^2 + g_y^2 + g_x^2); an axis of length 1 adds 0.
+// Laplacian (Eq. (laplacian), op 5): the sum over the axes of the second
+// difference v_{-1} + v_{+1} - 2 v, the end value standing in for a missing
+// neighbour; the integer route scales the exact numerator once by Delta.
 //
 // Both kernels march along z (the slowest axis) and keep the z-neighbours of
 // every (x, y) column in registers, so each value is read from memory once
@@ -37,6 +40,20 @@ __device__ __forceinline__ T fnum(T vm, T v0, T vp, int64_t i, int64_t L) {
   if (i == 0) return vp - v0;
   if (i == L - 1) return v0 - vm;
   return (vp - vm) * T(0.5);
+}
+
+// second difference along one axis at coordinate i of length L, the end
+// value standing in for a missing neighbour (0 on an axis of length 1)
+template <typename N>
+__device__ __forceinline__ N lap1(N vm, N v0, N vp, int64_t i, int64_t L) {
+  const N a = i > 0 ? vm : v0, b = i + 1 < L ? vp : v0;
+  return (a + b) - (v0 + v0);
+}
+
+// an exact integer Laplacian numerator n -> n * Delta, rounded once
+template <typename T>
+__device__ __forceinline__ T lap_value(int n, double quantum) {
+  return (T)((double)n * quantum);
 }
 
 // square root: v_sqrt_f32 (within 1 ulp) for binary32, the IEEE one for binary64
@@ -89,7 +106,7 @@ __global__ void __launch_bounds__(kBufThreads) k_grad_buf(const void* __restrict
   const int64_t z1 = min(b.z1, z0 + tz);
   const int64_t sy = d.x, sz = d.x * d.y;
   const T h = (T)halfq;
-  const bool need_z = OP == 4 || axis == 0, need_y = OP == 4 || axis == 1, need_x = OP == 4 || axis == 2;
+  const bool need_z = OP >= 4 || axis == 0, need_y = OP >= 4 || axis == 1, need_x = OP >= 4 || axis == 2;
   const V* col = src + y * sy + x;
   using N = typename std::conditional<INT, int, T>::type;
   constexpr int U = 4;  // planes per iteration: their loads are issued together
@@ -111,7 +128,16 @@ __global__ void __launch_bounds__(kBufThreads) k_grad_buf(const void* __restrict
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t z = zb + u;
-      if (z < z1) {
+      if (z < z1 && OP == 5) {
+        const N lz = lap1<N>(qm, qc, qn[u], z, d.z), ly = lap1<N>(ym[u], qc, yp[u], y, d.y);
+        const N l = lz + ly + lap1<N>(xm[u], qc, xp[u], x, d.x);
+        T r;
+        if constexpr (INT) r = lap_value<T>(l, 2.0 * halfq);
+        else r = l;
+        out[((z - b.z0) * by + (y - b.y0)) * bx + (x - b.x0)] = r;
+        qm = qc;
+        qc = qn[u];
+      } else if (z < z1) {
         N nz = 0, ny = 0, nx = 0;
         if constexpr (INT) {
           if (need_z) nz = inum(qm, qc, qn[u], z, d.z);
@@ -207,7 +233,7 @@ __device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint
   const int nrows = (int)(rB - rA);
   const double quantum = v.quantum;
   const T h = (T)halfq;
-  const bool need_z = OP == 4 || axis == 0, need_y = OP == 4 || axis == 1, need_x = OP == 4 || axis == 2;
+  const bool need_z = OP >= 4 || axis == 0, need_y = OP >= 4 || axis == 1, need_x = OP >= 4 || axis == 2;
 
   // decode item of this thread: decoded row dr, dk-th block of the row
   const int dr = t / NBR, dk = t % NBR;
@@ -280,7 +306,9 @@ __device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint
   auto emit = [&](int64_t o, int i, N nz) {
     const int64_t row = ((o - b.z0) * by + (y0 + i - b.y0)) * bx;
     T r;
-    if constexpr (OP == 3) {
+    if constexpr (OP == 5) {
+      r = (T)g1[i] + (T)nz;  // the float route only (INT is false here)
+    } else if constexpr (OP == 3) {
       if (axis == 0) r = INT ? (T)nz * h : (T)nz;
       else r = INT ? (T)g1[i] * h : (T)g1[i];
     } else {
@@ -320,13 +348,16 @@ __device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint
           const int64_t y = y0 + i;
           const V qc = plane[r * kP + ac];
           N nx = 0, ny = 0;
-          if (need_x) {
+          if (OP == 5) {
+            nx = lap1<N>(plane[r * kP + am], qc, plane[r * kP + ap], x, d.x);
+            ny = lap1<N>(plane[(r - 1) * kP + ac], qc, plane[(r + 1) * kP + ac], y, d.y);
+          } else if (need_x) {
             const V vm = plane[r * kP + am], vp = plane[r * kP + ap];
             const V lo = xlo ? qc : vm, hi = xhi ? qc : vp;
             if constexpr (INT) nx = xone ? 0 : (hi - lo) * ((xlo || xhi) ? 2 : 1);
             else nx = xone ? T(0) : (xlo || xhi) ? hi - lo : (hi - lo) * T(0.5);
           }
-          if (need_y) {
+          if (need_y && OP != 5) {
             const bool ylo = y == 0, yhi = y == d.y - 1;
             const V lo = ylo ? qc : plane[(r - 1) * kP + ac];
             const V hi = yhi ? qc : plane[(r + 1) * kP + ac];
@@ -335,7 +366,9 @@ __device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint
           }
           if (out_prev) {
             N nz = 0;
-            if (need_z) {
+            if constexpr (OP == 5) {
+              nz = lap1<N>(qm2[i], qm1[i], qc, o, d.z);
+            } else if (need_z) {
               if constexpr (INT) nz = inum(qm2[i], qm1[i], qc, o, d.z);
               else nz = fnum<T>(qm2[i], qm1[i], qc, o, d.z);
             }
@@ -344,6 +377,7 @@ __device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint
           qm2[i] = qm1[i];
           qm1[i] = qc;
           if constexpr (OP == 3) g1[i] = axis == 1 ? ny : nx;
+          else if constexpr (OP == 5) g1[i] = nx + ny;
           else g1[i] = sq_xy<INT, T, N>(ny, nx);
         }
       }
@@ -364,7 +398,9 @@ __device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint
     for (int i = 0; i < kTy; ++i) {
       if (i < ys) {
         N nz = 0;
-        if (need_z && d.z >= 2) {
+        if constexpr (OP == 5) {
+          nz = d.z >= 2 ? qm2[i] - qm1[i] : N(0);  // the missing z+1 neighbour is the end value
+        } else if (need_z && d.z >= 2) {
           if constexpr (INT) nz = 2 * (qm1[i] - qm2[i]);
           else nz = qm1[i] - qm2[i];
         }
@@ -509,7 +545,8 @@ __device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, ui
   const int64_t za = max((int64_t)0, z0 - 1), zb = min(d.z, z0 + zs + 1);
   const int nrows = (int)(rB - rA);
   const T h = (T)halfq;
-  const bool need_z = OP == 4 || axis == 0, need_y = OP == 4 || axis == 1, need_x = OP == 4 || axis == 2;
+  const double quantum = v.quantum;
+  const bool need_z = OP >= 4 || axis == 0, need_y = OP >= 4 || axis == 1, need_x = OP >= 4 || axis == 2;
   const bool aligned = (d.x & 31) == 0 && (x0 & 31) == 0;
 
   // decode item of this thread: decoded row dr, dk-th block of the row
@@ -568,8 +605,10 @@ __device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, ui
   const bool y2 = d.y >= 2, x2 = d.x >= 2;
 
   // per row: q of the two previous planes; in-plane part of the previous
-  // plane (squared sum, or the one numerator of a single derivative)
-  using G = typename std::conditional<OP == 3, int, typename std::conditional<SMALL, uint32_t, T>::type>::type;
+  // plane (squared sum, the one numerator of a single derivative, or the
+  // in-plane second differences of the Laplacian)
+  using G = typename std::conditional<OP == 3 || OP == 5, int,
+                                      typename std::conditional<SMALL, uint32_t, T>::type>::type;
   int qm2[kTy], qm1[kTy];
   G g1[kTy];
 #pragma unroll
@@ -606,18 +645,20 @@ __device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, ui
   auto rows = [&](int64_t p) {
     const int64_t o = p - 1;
     const bool emit = o >= z0 && o < z0 + zs;
-    // ghosts of this thread's column
-    if (ylo) pl[ec] = y2 ? 2 * pl[P + ec] - pl[2 * P + ec] : pl[P + ec];
+    // ghosts of this thread's column: 2 q_0 - q_1 for differences (the
+    // one-sided numerator), q_0 itself for the Laplacian (mirrored end)
+    constexpr bool kMirror = OP == 5;
+    if (ylo) pl[ec] = (y2 && !kMirror) ? 2 * pl[P + ec] - pl[2 * P + ec] : pl[P + ec];
     if (yhi) {
       int* r = pl + ys * P + ec;
-      r[P] = y2 ? 2 * r[0] - r[-P] : r[0];
+      r[P] = (y2 && !kMirror) ? 2 * r[0] - r[-P] : r[0];
     }
     if (need_x && (xlo || xhi)) {
 #pragma unroll
       for (int i = 0; i < kTy; ++i) {
         int* r = pl + (i + 1) * P;
-        if (xlo) r[em] = x2 ? 2 * r[ec] - r[ep] : r[ec];
-        if (xhi) r[ep] = x2 ? 2 * r[ec] - r[em] : r[ec];
+        if (xlo) r[em] = (x2 && !kMirror) ? 2 * r[ec] - r[ep] : r[ec];
+        if (xhi) r[ep] = (x2 && !kMirror) ? 2 * r[ec] - r[em] : r[ec];
       }
     }
     // the field's first plane: ghost plane q_{-1} = 2 q_0 - q_1 (or q_0)
@@ -625,7 +666,7 @@ __device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, ui
 #pragma unroll
       for (int i = 0; i < kTy; ++i) {
         const int c1 = pl[(i + 1) * P + ec];
-        qm2[i] = d.z >= 2 ? 2 * qm1[i] - c1 : qm1[i];
+        qm2[i] = (d.z >= 2 && !kMirror) ? 2 * qm1[i] - c1 : qm1[i];
       }
     }
     // rows to store this plane (kTy, ys, or none): it depends on the plane,
@@ -648,15 +689,20 @@ __device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, ui
         const int i = hh + k;
         const int qc = cv[k + 1];
         if (i < nr) {
-          const int nz = need_z ? qc - qm2[i] : 0;
           T* rowp = orow + (int64_t)i * bx;
-          rowp[(uint32_t)t] = value(i, nz);
+          if constexpr (OP == 5) {
+            rowp[(uint32_t)t] = lap_value<T>(g1[i] + (qc + qm2[i]) - (qm1[i] + qm1[i]), quantum);
+          } else {
+            const int nz = need_z ? qc - qm2[i] : 0;
+            rowp[(uint32_t)t] = value(i, nz);
+          }
           accumulate(qm1[i]);
         }
         const int nx = xp[k] - xm[k], ny = need_y ? cv[k + 2] - cv[k] : 0;
         qm2[i] = qm1[i];
         qm1[i] = qc;
         if constexpr (OP == 3) g1[i] = axis == 1 ? ny : nx;
+        else if constexpr (OP == 5) g1[i] = ((xp[k] + xm[k]) - (qc + qc)) + ((cv[k + 2] + cv[k]) - (qc + qc));
         else if constexpr (SMALL) g1[i] = (uint32_t)__mul24(nx, nx) + (uint32_t)__mul24(ny, ny);
         else g1[i] = (T)nx * (T)nx + (T)ny * (T)ny;
       }
@@ -694,9 +740,15 @@ __device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, ui
 #pragma unroll
     for (int i = 0; i < kTy; ++i) {
       if (i < ys) {
-        const int nz = (need_z && d.z >= 2) ? 2 * (qm1[i] - qm2[i]) : 0;
         T* rowp = orow + (int64_t)i * bx;
-        rowp[(uint32_t)t] = value(i, nz);
+        if constexpr (OP == 5) {
+          // the missing z+1 neighbour is the end value qm1 itself; a field of
+          // one plane has no z term (qm2 never held a plane there)
+          rowp[(uint32_t)t] = lap_value<T>(g1[i] + (d.z >= 2 ? qm2[i] - qm1[i] : 0), quantum);
+        } else {
+          const int nz = (need_z && d.z >= 2) ? 2 * (qm1[i] - qm2[i]) : 0;
+          rowp[(uint32_t)t] = value(i, nz);
+        }
         accumulate(qm1[i]);
       }
     }
@@ -861,6 +913,9 @@ hipError_t run_buf(const void* buf, int op, int axis, const OpTarget& t, double 
   if (op == 3)
     hipLaunchKernelGGL((k_grad_buf<SRC, 3, T>), dim3((unsigned)grid), dim3(kBufThreads), 0, s, buf, t.d, b, axis,
                        (int)tz, halfq, (T*)out);
+  else if (op == 5)
+    hipLaunchKernelGGL((k_grad_buf<SRC, 5, T>), dim3((unsigned)grid), dim3(kBufThreads), 0, s, buf, t.d, b, axis,
+                       (int)tz, halfq, (T*)out);
   else
     hipLaunchKernelGGL((k_grad_buf<SRC, 4, T>), dim3((unsigned)grid), dim3(kBufThreads), 0, s, buf, t.d, b, axis,
                        (int)tz, halfq, (T*)out);
@@ -887,6 +942,8 @@ hipError_t run_fused(const StreamView& v, int op, int axis, const OpTarget& t, v
   GradJob job{v, rel, t.d, b, axis, (int)tz, kmax, 0.5 * v.quantum, out};
   if (op == 3)
     hipLaunchKernelGGL((k_grad_fused<S, VIA, 3, T>), dim3((unsigned)grid), dim3(kFusedThreads), lds, s, job, status);
+  else if (op == 5)
+    hipLaunchKernelGGL((k_grad_fused<S, VIA, 5, T>), dim3((unsigned)grid), dim3(kFusedThreads), lds, s, job, status);
   else
     hipLaunchKernelGGL((k_grad_fused<S, VIA, 4, T>), dim3((unsigned)grid), dim3(kFusedThreads), lds, s, job, status);
   return hipGetLastError();

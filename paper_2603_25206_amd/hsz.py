@@ -26,10 +26,10 @@ ERR_INVALID_ARG, ERR_BAD_STREAM, ERR_UNSUPPORTED, ERR_RANGE, ERR_EB, ERR_NONFINI
     -1, -2, -3, -4, -5, -6, -7, -8)
 F32, F64 = 1, 2
 META, DELTA, QUANT, FLOAT = 1, 2, 3, 4
-MEAN, VAR, DERIV, GRADMAG = 1, 2, 3, 4
+MEAN, VAR, DERIV, GRADMAG, LAPLACIAN = 1, 2, 3, 4, 5
 HEADER_BYTES = 256
 
-_OPS = {"mean": MEAN, "var": VAR, "deriv": DERIV, "gradmag": GRADMAG}
+_OPS = {"mean": MEAN, "var": VAR, "deriv": DERIV, "gradmag": GRADMAG, "laplacian": LAPLACIAN}
 _STAGES = {"meta": META, "delta": DELTA, "quant": QUANT, "float": FLOAT}
 
 

@@ -242,6 +242,71 @@ def test_fast_axis_derivative_on_deltas(case):
         assert e.value.code == hsz.ERR_UNSUPPORTED
 
 
+def _lap_tol(case, want, route):
+    """Integer route: the exact numerator rounded once to the field dtype,
+    against the oracle's binary64 sums of d' = q*Delta (their own rounding:
+    16 * 2^-53 * max|d'|).  Float route: the stencil in the field's own
+    precision (a few roundings of values up to max|d'|)."""
+    base = case["xh64"] if route == "int" else case["x_stored"]
+    m = float(np.max(np.abs(base)))
+    f32 = case["x"].dtype == np.float32
+    rel = 1e-6 if f32 else 1e-12
+    if route == "int":
+        return rel * np.abs(want) + 16 * 2.0 ** -53 * m
+    eps = 2.0 ** -24 if f32 else 2.0 ** -53
+    return rel * np.abs(want) + 16 * eps * m
+
+
+def test_laplacian_all_routes(case):
+    """Laplacian on the materialised stages 3 and 4 and straight from the
+    stream via D_q and D_f, whole field and boxes, against the oracle."""
+    c = case["c"]
+    qbuf = hsz.decompress_to_stage(c, hsz.QUANT)
+    fbuf = hsz.decompress_to_stage(c, hsz.FLOAT)
+    nd = len(case["shape"])
+    for box in boxes_for(case["shape"], seed=nd * 17 + case["S"], count=2):
+        for route, st, buf, base in (("int", hsz.QUANT, qbuf, case["xh64"]),
+                                     ("float", hsz.FLOAT, fbuf, case["x_stored"])):
+            want = oracle.laplacian(base, box)
+            tol = _lap_tol(case, want, route)
+            for got in (hsz.op_on_stage(buf, c.header, st, "laplacian", box=box),
+                        hsz.op_fused(c, st, "laplacian", box=box)):
+                got = got.cpu().numpy().astype(np.float64)
+                assert got.shape == want.shape
+                err = np.abs(got - want)
+                bad = err > tol
+                assert not bad.any(), (route, box, int(bad.sum()), float(err.max()))
+            if route == "int":
+                # the integer route is exact before its one rounding: stage and fused agree bit for bit
+                a = hsz.op_on_stage(buf, c.header, st, "laplacian", box=box)
+                b = hsz.op_fused(c, st, "laplacian", box=box)
+                assert torch.equal(a, b)
+    with pytest.raises(hsz.HszError) as e:
+        hsz.op_fused(c, hsz.DELTA, "laplacian")
+    assert e.value.code == hsz.ERR_UNSUPPORTED
+
+
+def test_laplacian_large_integers_and_batches():
+    """max|q| >= 2^27: the integer Laplacian is refused (its 32-bit numerator
+    could overflow) while the float route still matches the oracle; batches
+    do not take the Laplacian."""
+    say("[case] laplacian: max|q| >= 2^27, batch refusal")
+    x = field((6, 9, 40), np.float64, seed=77)
+    c = hsz.compress(torch.from_numpy(x).to(DEV), 1e-9, rel=True, block=32)
+    assert c.header.max_abs_q >= 2 ** 27
+    with pytest.raises(hsz.HszError) as e:
+        hsz.op_fused(c, hsz.QUANT, "laplacian")
+    assert e.value.code == hsz.ERR_UNSUPPORTED
+    ref = oracle.compress(x, 1e-9, rel=True, block=32)
+    xs = oracle.decompress(ref, oracle.FLOAT).astype(np.float64)
+    want = oracle.laplacian(xs)
+    got = hsz.op_fused(c, hsz.FLOAT, "laplacian").cpu().numpy()
+    assert np.all(np.abs(got - want) <= 1e-12 * np.abs(want) + 16 * 2.0 ** -53 * float(np.max(np.abs(xs))))
+    with pytest.raises(hsz.HszError) as e:
+        hsz.Plan([hsz.Job(c, "laplacian", hsz.FLOAT)])
+    assert e.value.code == hsz.ERR_UNSUPPORTED
+
+
 def test_repeat_runs_identical(case):
     c = case["c"]
     a = hsz.op_fused(c, hsz.QUANT, "var")
