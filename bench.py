@@ -54,6 +54,7 @@ def parse():
                          "to scale memory counters under rocprofv3")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workloads")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--no-vector", action="store_true", help="skip the vector-field (divergence, curl) workload")
     ap.add_argument("--snapshots", type=int, default=64)
     ap.add_argument("--queries", type=int, default=20000)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -339,6 +340,9 @@ def main():
 
     del copies, plans, gbuf, qbuf, fbuf, dbuf
     torch.cuda.empty_cache()
+    if not a.no_vector:
+        out["vector_field"] = bench_vector(a, log)
+        torch.cuda.empty_cache()
     if not a.no_batch:
         out["batching"] = bench_batches(a, log)
         torch.cuda.empty_cache()
@@ -363,6 +367,61 @@ def _events_ms(fn, reps, stream):
         e1.synchronize()
         ts.append(e0.elapsed_time(e1))
     return float(np.median(ts))
+
+
+def bench_vector(a, log):
+    """A three-component 512^3 binary32 vector field (NYX-velocity sized; each
+    component the large-field recipe with its own seed, rel eb 1e-4, S=32):
+    divergence and curl straight from the three streams through D_q, on the
+    materialised quantized stage, and after full decompression of every
+    component (decode to floats + the operation on the floats)."""
+    import torch
+
+    from paper_2603_25206_amd import hsz, synth
+
+    shape = (512, 512, 512)
+    comps, orig = [], 0
+    for k in range(3):
+        f = synth.make_field_torch(synth.large_field_spec(seed=400 + k, shape=shape), "cuda")
+        comps.append(hsz.compress(f, a.eb, rel=True, block=32))
+        orig += f.numel() * f.element_size()
+        del f
+    torch.cuda.synchronize()
+    dev = comps[0].data.device
+    cur = torch.cuda.current_stream()
+    headers = [c.header for c in comps]
+    n = comps[0].header.n
+    outs = [torch.empty(4 * n, dtype=torch.uint8, device=dev) for _ in range(3)]
+    ws = hsz.workspace(hsz.vector_workspace_bytes(headers), dev, key="bench-vec")
+    res = {"components": 3, "shape": list(shape), "orig_bytes": orig,
+           "compressed_bytes": sum(c.nbytes for c in comps)}
+    qbufs = [torch.empty(4 * n, dtype=torch.uint8, device=dev) for _ in range(3)]
+    fbufs = [torch.empty(4 * n + 64, dtype=torch.uint8, device=dev) for _ in range(3)]
+    for op in ("divergence", "curl"):
+        nout = 3 if op == "curl" else 1
+
+        def fused():
+            hsz.vector_op_fused(comps, op, outs=outs[:nout], ws=ws, check=False)
+
+        def on_q():
+            for c, b in zip(comps, qbufs):
+                hsz.decompress_to_stage(c, hsz.QUANT, out=b)
+            hsz.vector_op_on_stage([b[: 4 * n] for b in qbufs], headers, hsz.QUANT, op, outs=outs[:nout], ws=ws,
+                                   check=False)
+
+        def full():
+            for c, b in zip(comps, fbufs):
+                hsz.decompress_to_stage(c, hsz.FLOAT, out=b)
+            hsz.vector_op_on_stage(fbufs, headers, hsz.FLOAT, op, outs=outs[:nout], ws=ws, check=False)
+        ms_f = _events_ms(fused, 5, cur)
+        ms_q = _events_ms(on_q, 5, cur)
+        ms_b = _events_ms(full, 5, cur)
+        res[op] = {"fused_quant_ms": round(ms_f, 4), "gbs_orig": round(orig / ms_f / 1e6, 1),
+                   "decompress_quant_then_op_ms": round(ms_q, 4), "full_decompress_then_op_ms": round(ms_b, 4),
+                   "speedup_vs_full_decompress": round(ms_b / ms_f, 3)}
+    log(f"[bench] vector field: {res}")
+    del comps, outs, qbufs, fbufs
+    return res
 
 
 def bench_batches(a, log):

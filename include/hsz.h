@@ -55,7 +55,8 @@ enum {
 
 enum { HSZ_F32 = 1, HSZ_F64 = 2 };                                  /* field dtype */
 enum { HSZ_META = 1, HSZ_DELTA = 2, HSZ_QUANT = 3, HSZ_FLOAT = 4 }; /* Table I     */
-enum { HSZ_MEAN = 1, HSZ_VAR = 2, HSZ_DERIV = 3, HSZ_GRADMAG = 4, HSZ_LAPLACIAN = 5 }; /* operations */
+enum { HSZ_MEAN = 1, HSZ_VAR = 2, HSZ_DERIV = 3, HSZ_GRADMAG = 4, HSZ_LAPLACIAN = 5, /* operations */
+       HSZ_DIVERGENCE = 6, HSZ_CURL = 7 };                  /* vector fields (below) */
 
 /* Size of the fixed header at the start of every compressed stream. */
 #define HSZ_HEADER_BYTES 256
@@ -207,6 +208,44 @@ int hsz_op_on_stage(const void *d_stage, const hsz_header *h, int stage, int op,
 int hsz_op_fused(const void *d_c, const hsz_header *h, int via, int op, int axis,
                  const hsz_box *h_box, void *d_result, uint64_t cap, void *d_workspace,
                  uint64_t workspace_bytes, void *stream);
+
+/* ---- vector fields: divergence and curl, Sec. III-B and Sec. V-C -----------------
+ * A vector field of an n-dimensional grid (n = 1..3) is held as n streams of
+ * the same dims, dtype and block size, component k paired with the field's
+ * own axis k (delta_x = axis 0, the slowest).  Each component keeps its own
+ * error bound and quantum.  The derivative is the one of HSZ_DERIV (central
+ * differences inside, one-sided at the ends of an axis, 0 on an axis of
+ * length 1), taken over the whole field even where it lies outside the box.
+ *   HSZ_DIVERGENCE (Eq. (divergence)): sum_k delta_k F_k; one result.
+ *   HSZ_CURL (Eq. (curl)), n = 2: delta_1 F_0 - delta_0 F_1 (as printed);
+ *     one result.  n = 3: three results, (delta_2 F_1 - delta_1 F_2,
+ *     delta_0 F_2 - delta_2 F_0, delta_1 F_0 - delta_0 F_1), the last being
+ *     the 2D formula.
+ * Results are box-shaped C-order arrays of the field dtype, each at
+ * d_result[o] (16-byte aligned, 'cap' bytes each).  On the quantized
+ * stage every term is an exact integer numerator of one component times
+ * that component's Delta/2, the terms of a result summed in binary64 in a
+ * fixed order and rounded once; on the float stage the same differences are
+ * taken on the decompressed values in the field's precision.  Stage 1, 2:
+ * HSZ_ERR_UNSUPPORTED (the 1D partition keeps no multidimensional
+ * neighbours, Sec. V-B).  Arrays d_stage / d_c / h hold ncomp entries. */
+
+/* Workspace of a vector-field operation (status words and one block index
+ * per component). */
+int hsz_vector_workspace(const hsz_header *const *h, int ncomp, uint64_t *h_bytes);
+
+/* On materialised stage buffers (stage = HSZ_QUANT or HSZ_FLOAT, one buffer
+ * per component from hsz_decompress_to_stage). */
+int hsz_vector_op_on_stage(const void *const *d_stage, const hsz_header *const *h, int ncomp, int stage,
+                           int op, const hsz_box *h_box, void *const *d_result, uint64_t cap,
+                           void *d_workspace, uint64_t workspace_bytes, void *stream);
+
+/* Straight from the component streams through D_q (via = HSZ_QUANT): each
+ * component's planes are decoded on chip in turn; the result equals
+ * hsz_vector_op_on_stage on the quantized stage bit for bit. */
+int hsz_vector_op_fused(const void *const *d_c, const hsz_header *const *h, int ncomp, int via, int op,
+                        const hsz_box *h_box, void *const *d_result, uint64_t cap, void *d_workspace,
+                        uint64_t workspace_bytes, void *stream);
 
 /* ---- batches: many fields, boxes and operations in one pass ------------------
  * One persistent launch per kernel family works through a device table of

@@ -287,4 +287,96 @@ int hsz_op_fused(const void* d_c, const hsz_header* h, int via, int op, int axis
   return e == hipSuccess ? HSZ_OK : hip_fail(e);
 }
 
+// ---- vector fields ------------------------------------------------------------
+namespace {
+// Validate the component headers of a vector field and fill the job.
+int vec_common(const hsz_header* const* h, int nc, int op, const hsz_box* box, void* const* d_result,
+               uint64_t cap, void* d_ws, uint64_t ws_bytes, hsz::VecJob* j) {
+  if (!h || nc < 1 || nc > 3 || !d_result) return HSZ_ERR_INVALID_ARG;
+  if (op != HSZ_DIVERGENCE && op != HSZ_CURL) return HSZ_ERR_INVALID_ARG;
+  for (int c = 0; c < nc; ++c) {
+    if (!h[c]) return HSZ_ERR_INVALID_ARG;
+    int rc = check_header(h[c]);
+    if (rc) return rc;
+  }
+  const hsz_header* h0 = h[0];
+  if (h0->ndim != nc) return HSZ_ERR_INVALID_ARG;  // one component per axis of the field
+  if (op == HSZ_CURL && nc < 2) return HSZ_ERR_INVALID_ARG;
+  for (int c = 1; c < nc; ++c) {
+    if (h[c]->ndim != nc || h[c]->dtype != h0->dtype || h[c]->block != h0->block) return HSZ_ERR_INVALID_ARG;
+    for (int k = 0; k < nc; ++k)
+      if (h[c]->dims[k] != h0->dims[k]) return HSZ_ERR_INVALID_ARG;
+  }
+  if (!d_ws || !aligned16(d_ws)) return HSZ_ERR_INVALID_ARG;
+  int64_t nb[3] = {0, 0, 0};
+  for (int c = 0; c < nc; ++c) nb[c] = h[c]->nb;
+  if (ws_bytes < hsz::vector_workspace_bytes(nb, nc)) return HSZ_ERR_CAPACITY;
+  int64_t d3[3], n;
+  dims3_of(h0->ndim, h0->dims, d3, &n);
+  *j = hsz::VecJob{};
+  j->d = hsz::Dims3{d3[0], d3[1], d3[2]};
+  if (!box3_of(h0, box, &j->b)) return HSZ_ERR_INVALID_ARG;
+  j->nc = nc;
+  j->op = op == HSZ_DIVERGENCE ? hsz::kOpDivergence : hsz::kOpCurl;
+  const int nout = (op == HSZ_CURL && nc == 3) ? 3 : 1;
+  const uint64_t esz = h0->dtype == HSZ_F32 ? 4 : 8;
+  if (cap < esz * (uint64_t)j->b.volume()) return HSZ_ERR_CAPACITY;
+  for (int o = 0; o < nout; ++o) {
+    if (!d_result[o] || !aligned16(d_result[o])) return HSZ_ERR_INVALID_ARG;
+    j->out[o] = d_result[o];
+  }
+  for (int c = 0; c < nc; ++c) j->halfq[c] = 0.5 * h[c]->quantum;
+  return HSZ_OK;
+}
+}  // namespace
+
+int hsz_vector_workspace(const hsz_header* const* h, int ncomp, uint64_t* h_bytes) {
+  if (!h || !h_bytes || ncomp < 1 || ncomp > 3) return HSZ_ERR_INVALID_ARG;
+  int64_t nb[3] = {0, 0, 0};
+  for (int c = 0; c < ncomp; ++c) {
+    if (!h[c]) return HSZ_ERR_INVALID_ARG;
+    nb[c] = h[c]->nb;
+  }
+  *h_bytes = hsz::vector_workspace_bytes(nb, ncomp);
+  return HSZ_OK;
+}
+
+int hsz_vector_op_on_stage(const void* const* d_stage, const hsz_header* const* h, int ncomp, int stage, int op,
+                           const hsz_box* h_box, void* const* d_result, uint64_t cap, void* d_workspace,
+                           uint64_t workspace_bytes, void* stream) {
+  hsz::VecJob j;
+  int rc = vec_common(h, ncomp, op, h_box, d_result, cap, d_workspace, workspace_bytes, &j);
+  if (rc) return rc;
+  if (!d_stage) return HSZ_ERR_INVALID_ARG;
+  if (stage == HSZ_META || stage == HSZ_DELTA) return HSZ_ERR_UNSUPPORTED;
+  if (stage != HSZ_QUANT && stage != HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
+  for (int c = 0; c < ncomp; ++c) {
+    if (!d_stage[c] || !aligned16(d_stage[c])) return HSZ_ERR_INVALID_ARG;
+    j.buf[c] = d_stage[c];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = reset_status(d_workspace, s))) return rc;
+  hipError_t e = hsz::launch_vector_stage(j, stage, h[0]->dtype, s);
+  return e == hipSuccess ? HSZ_OK : hip_fail(e);
+}
+
+int hsz_vector_op_fused(const void* const* d_c, const hsz_header* const* h, int ncomp, int via, int op,
+                        const hsz_box* h_box, void* const* d_result, uint64_t cap, void* d_workspace,
+                        uint64_t workspace_bytes, void* stream) {
+  hsz::VecJob j;
+  int rc = vec_common(h, ncomp, op, h_box, d_result, cap, d_workspace, workspace_bytes, &j);
+  if (rc) return rc;
+  if (!d_c) return HSZ_ERR_INVALID_ARG;
+  if (via == HSZ_META || via == HSZ_DELTA || via == HSZ_FLOAT) return HSZ_ERR_UNSUPPORTED;
+  if (via != HSZ_QUANT) return HSZ_ERR_INVALID_ARG;
+  for (int c = 0; c < ncomp; ++c) {
+    if (!d_c[c] || !aligned16(d_c[c])) return HSZ_ERR_INVALID_ARG;
+    j.v[c] = view_of(d_c[c], h[c]);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = reset_status(d_workspace, s))) return rc;
+  hipError_t e = hsz::launch_vector_fused(j, (uint8_t*)d_workspace, s);
+  return e == hipSuccess ? HSZ_OK : hip_fail(e);
+}
+
 }  // extern "C"

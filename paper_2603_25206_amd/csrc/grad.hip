@@ -444,73 +444,6 @@ struct QRow {
   static constexpr int kStageOff = (kRows * kPitch + 63) / 64 * 64;
 };
 
-// Decode one staged block (column 'col', stride kFusedThreads) and write its
-// S values of q to dst[j + j/32 + pad_j], pad_j = ((j & 31) >= jx) (jx = 32:
-// none).  Reads are issued eight slots at a time, ahead of the writes.
-template <int S, bool ALIGNED>
-__device__ __forceinline__ void decode_block_q(const uint32_t* col, int w, int q0, int* dst, int jx) {
-  const uint32_t sg0 = col[0];
-  const uint32_t sg1 = S == 64 ? col[kFusedThreads] : 0u;
-  const uint32_t* mag = col + (S / 32) * kFusedThreads;
-  int* dst1 = dst + 1;
-  int q = q0;
-  uint32_t uw = (uint32_t)w;
-#pragma unroll
-  for (int g = 0; g < S; g += 8) {
-    // an empty asm that "changes" uw keeps the compiler from computing the
-    // bit positions of all S slots up front (S live registers)
-    asm volatile("" : "+v"(uw));
-    uint32_t lo[8], hi[8], pos[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      pos[u] = __umul24((uint32_t)(g + u), uw);  // full-rate 24-bit multiply
-      uint32_t k = pos[u] >> 5;
-      asm("" : "+v"(k));  // one shift-add per address (see decode_lane_block)
-      const uint32_t* a = mag + k * kFusedThreads;
-      lo[u] = a[0];
-      hi[u] = a[kFusedThreads];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int j = g + u;
-      const uint32_t m = __builtin_amdgcn_ubfe(__builtin_amdgcn_alignbit(hi[u], lo[u], pos[u]), 0u, uw);
-      const int sg = __builtin_amdgcn_sbfe((int)(j < 32 ? sg0 : sg1), (uint32_t)(j & 31), 1u);
-      q = (int)((m ^ (uint32_t)sg) + (uint32_t)q) - sg;  // q += (m ^ sg) - sg
-      if constexpr (ALIGNED) {
-        dst[j + (j >> 5)] = q;
-      } else {
-        int* d = ((j & 31) >= jx) ? dst1 : dst;
-        d[j + (j >> 5)] = q;
-      }
-    }
-  }
-}
-
-// Words [0, min(words, N)) of a block at payload word 'off' into w[] (the
-// rest 0).  A block's words are contiguous and the blocks of a decoded row
-// follow each other in the payload, so each lane reads its words four at a
-// time: one 16-byte load per four words (dword aligned) instead of four
-// scattered dword loads.  Four-word groups may run into the next block's
-// words (ignored); near the end of the payload the lane reads word by word.
-template <int N>
-__device__ __forceinline__ void prefetch_words(const uint32_t* __restrict__ payload, uint64_t payload_words,
-                                               uint64_t off, int words, uint32_t (&w)[N]) {
-  static_assert(N % 4 == 0, "four-word groups");
-  typedef uint32_t u4 __attribute__((ext_vector_type(4), aligned(4)));
-  const uint32_t* src = payload + off;
-  if (off + N <= payload_words) {
-#pragma unroll
-    for (int k = 0; k < N; k += 4) {
-      u4 t = {0u, 0u, 0u, 0u};
-      if (k < words) t = *(const u4*)(src + k);
-      w[k] = t.x; w[k + 1] = t.y; w[k + 2] = t.z; w[k + 3] = t.w;
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < N; ++k) w[k] = (k < words) ? src[k] : 0u;
-  }
-}
-
 template <int S, int OP, typename T, int ACC, bool SMALL>
 __device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, uint32_t* smem, int* status) {
   static_assert(!SMALL || (OP == 4 && sizeof(T) == 4), "32-bit squared sums: binary32 magnitude only");
@@ -593,8 +526,8 @@ __device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, ui
     if (!m.valid) return;
     const int cb = m.e0 - (int)(x0 - 1) + R::kOff;  // extended column of slot 0 (>= 0)
     int* dst = prow + R::at(cb);
-    if (aligned) decode_block_q<S, true>(col, m.w, m.q0, dst, 32);
-    else decode_block_q<S, false>(col, m.w, m.q0, dst, 32 - (cb & 31));
+    if (aligned) decode_block_q<S, true, kFusedThreads>(col, m.w, m.q0, dst, 32);
+    else decode_block_q<S, false, kFusedThreads>(col, m.w, m.q0, dst, 32 - (cb & 31));
   };
 
   // stencil column of this thread and its neighbours (row-relative offsets)

@@ -154,4 +154,21 @@ hipError_t launch_grad_stage(const void* stage_buf, int stage, const StreamView&
 hipError_t launch_grad_fused(const StreamView& v, int via, int op, int axis3, const OpTarget& t,
                              void* result, uint8_t* ws, hipStream_t s);
 
+// ---- vector fields: divergence and curl, one stream (or buffer) per component ----
+constexpr int kOpDivergence = 6, kOpCurl = 7;
+struct VecJob {
+  StreamView v[3];         // component streams (fused route)
+  const uint16_t* rel[3];  // their block indexes (filled by launch_vector_fused)
+  const void* buf[3];      // component stage buffers (stage route)
+  double halfq[3];         // Delta/2 of each component
+  Dims3 d;
+  Box3 b;
+  int nc, op, tz, kmax;    // components (= field dims), kOpDivergence / kOpCurl
+  void* out[3];            // result buffers (1, or 3 for the curl of a 3D field)
+};
+// status words, then one block index per component
+uint64_t vector_workspace_bytes(const int64_t* nb, int nc);
+hipError_t launch_vector_stage(const VecJob& j, int stage, int dtype, hipStream_t s);
+hipError_t launch_vector_fused(const VecJob& j, uint8_t* ws, hipStream_t s);
+
 }  // namespace hsz

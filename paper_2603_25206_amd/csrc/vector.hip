@@ -1,0 +1,433 @@
+// vector.hip -- divergence and curl of vector fields (Eq. (divergence),
+// Eq. (curl), Sec. V-C "multivariate derivation"), one compressed stream per
+// component.
+//
+// Both reduce to derivatives of single components (Eq. (derivatives)):
+// component k of the field pairs with the field's own axis k, interior
+// points take central differences and the two ends of an axis one-sided
+// ones.  Divergence = sum_k delta_k F_k.  Curl of a 2D field = delta_1 F_0 -
+// delta_0 F_1 (Eq. (curl) as printed); of a 3D field the vector
+// (delta_2 F_1 - delta_1 F_2, delta_0 F_2 - delta_2 F_0, delta_1 F_0 -
+// delta_0 F_1), whose last component is the 2D formula.
+//
+// Integer route (D_q): every term is an exact integer numerator n of one
+// component (q_{+1} - q_{-1}, or 2 (q_1 - q_0) at an end), scaled by that
+// component's Delta/2; the terms of an output are summed in binary64 in a
+// fixed order and rounded once to the field dtype.  The fused kernel decodes
+// each component's plane from its stream into one LDS plane in turn (the
+// blockwise window of Alg. 3 with one window per component); the stage
+// kernel reads materialised q buffers and sums the same terms in the same
+// order, so the two agree bit for bit.  Float route (D_f, stage buffers):
+// the same differences on the decompressed values in the field's precision.
+#include <algorithm>
+
+#include "hsz_device.hpp"
+#include "hsz_launch.hpp"
+
+namespace hsz {
+
+namespace {
+
+// One derivative term: component c, axis a of the 3D view (0 z, 1 y, 2 x),
+// sign s, output o.
+struct VTerm {
+  int c, a, s, o;
+};
+
+template <int OP, int NC>
+struct VTerms;
+// divergence of 1D, 2D, 3D fields (field axis k = view axis k + 3 - NC)
+template <>
+struct VTerms<kOpDivergence, 1> {
+  static constexpr int n = 1, nout = 1;
+  static constexpr VTerm t[1] = {{0, 2, 1, 0}};
+};
+template <>
+struct VTerms<kOpDivergence, 2> {
+  static constexpr int n = 2, nout = 1;
+  static constexpr VTerm t[2] = {{0, 1, 1, 0}, {1, 2, 1, 0}};
+};
+template <>
+struct VTerms<kOpDivergence, 3> {
+  static constexpr int n = 3, nout = 1;
+  static constexpr VTerm t[3] = {{0, 0, 1, 0}, {1, 1, 1, 0}, {2, 2, 1, 0}};
+};
+// curl of a 2D field: delta_1 F_0 - delta_0 F_1 (field axes 0, 1 = view y, x)
+template <>
+struct VTerms<kOpCurl, 2> {
+  static constexpr int n = 2, nout = 1;
+  static constexpr VTerm t[2] = {{0, 2, 1, 0}, {1, 1, -1, 0}};
+};
+// curl of a 3D field, output by output
+template <>
+struct VTerms<kOpCurl, 3> {
+  static constexpr int n = 6, nout = 3;
+  static constexpr VTerm t[6] = {{1, 2, 1, 0}, {2, 1, -1, 0}, {2, 0, 1, 1},
+                                 {0, 2, -1, 1}, {0, 1, 1, 2}, {1, 0, -1, 2}};
+};
+
+// integer numerator along one axis at coordinate i of length L
+__device__ __forceinline__ int vnum(int vm, int v0, int vp, int64_t i, int64_t L) {
+  if (L < 2) return 0;
+  if (i == 0) return 2 * (vp - v0);
+  if (i == L - 1) return 2 * (v0 - vm);
+  return vp - vm;
+}
+// float derivative along one axis in the field's precision
+template <typename T>
+__device__ __forceinline__ T vder(T vm, T v0, T vp, int64_t i, int64_t L) {
+  if (L < 2) return T(0);
+  if (i == 0) return vp - v0;
+  if (i == L - 1) return v0 - vm;
+  return (vp - vm) * T(0.5);
+}
+
+// ---- stage buffers: one thread per output point --------------------------------
+template <int SRC, int OP, int NC, typename T>
+__global__ void __launch_bounds__(256) k_vector_buf(VecJob j) {
+  using Tm = VTerms<OP, NC>;
+  const Box3 b = j.b;
+  const Dims3 d = j.d;
+  const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0;
+  const int64_t vol = bx * by * (b.z1 - b.z0);
+  const int64_t sy = d.x, sz = d.x * d.y;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < vol; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = b.x0 + e % bx, y = b.y0 + (e / bx) % by, z = b.z0 + e / (bx * by);
+    const int64_t pos[3] = {z, y, x}, len[3] = {d.z, d.y, d.x}, str[3] = {sz, sy, 1};
+    const int64_t f = z * sz + y * sy + x;
+    double acc[Tm::nout];
+    T facc[Tm::nout];
+#pragma unroll
+    for (int o = 0; o < Tm::nout; ++o) { acc[o] = 0.0; facc[o] = T(0); }
+#pragma unroll
+    for (int k = 0; k < Tm::n; ++k) {
+      const VTerm tm = Tm::t[k];
+      const int64_t i = pos[tm.a], L = len[tm.a], st = str[tm.a];
+      if constexpr (SRC == 3) {
+        const int32_t* q = (const int32_t*)j.buf[tm.c];
+        const int v0 = q[f], vm = i > 0 ? q[f - st] : v0, vp = i + 1 < L ? q[f + st] : v0;
+        acc[tm.o] += (double)(tm.s * vnum(vm, v0, vp, i, L)) * j.halfq[tm.c];
+      } else {
+        const T* v = (const T*)j.buf[tm.c];
+        const T v0 = v[f], vm = i > 0 ? v[f - st] : v0, vp = i + 1 < L ? v[f + st] : v0;
+        const T g = vder<T>(vm, v0, vp, i, L);
+        facc[tm.o] = tm.s > 0 ? facc[tm.o] + g : facc[tm.o] - g;
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < Tm::nout; ++o) ((T*)j.out[o])[e] = SRC == 3 ? (T)acc[o] : facc[o];
+  }
+}
+
+// ---- fused from the compressed streams (D_q) ------------------------------------
+constexpr int kVTx = 256, kVThreads = 256;
+
+template <int S, int TY>
+struct VRow {
+  static constexpr int kRows = TY + 2, kCols = kVTx + 2;
+  static constexpr int kNbr = (kCols + S - 2) / S + 1;  // blocks covering one decoded row
+  static constexpr int kOff = S - 1;                    // extended column of tile column 0
+  static constexpr int kExt = kCols + 2 * (S - 1);
+  // a pitch congruent to kNbr (S + S/32) mod 64: decode lane i writes slot j
+  // of its block to bank i (S + S/32) + const, distinct over a wave for S = 32
+  static constexpr int pitch() {
+    int p = kExt + (kExt >> 5);
+    while (p % 64 != (kNbr * (S + S / 32)) % 64) ++p;
+    return p;
+  }
+  static constexpr int kPitch = pitch();
+  static constexpr int kStageOff = (kRows * kPitch + 63) / 64 * 64;
+  static __host__ __device__ constexpr int at(int e) { return e + (e >> 5); }
+};
+
+template <int OP, int NC>
+constexpr int vty() { return (OP == kOpCurl && NC == 3) ? 4 : 8; }
+
+// One workgroup: a tile of kVTx columns x TY rows over tz planes.  Per plane
+// p, for each component c: its decode items stage and decode their blocks
+// of plane p (rows y0-1 .. y0+TY) into the LDS plane; after a barrier every
+// column thread writes the one-sided ghosts of its column and takes the
+// in-plane numerators of c's terms (plane p) and the z numerators (plane
+// p-1, from q of planes p and p-2 kept in registers); a barrier frees the
+// plane for the next component.  Then plane p-1 is emitted.
+template <int S, int OP, int NC, typename T>
+__global__ void __launch_bounds__(kVThreads) k_vector_fused(VecJob j, int* status) {
+  using Tm = VTerms<OP, NC>;
+  constexpr int TY = vty<OP, NC>();
+  using R = VRow<S, TY>;
+  constexpr int P = R::kPitch, NBR = R::kNbr, NT = Tm::n;
+  static_assert(R::kRows * NBR <= kVThreads, "one decode item per thread");
+  extern __shared__ uint32_t smem[];
+  int* const pl = (int*)smem;
+  uint32_t* const stage = smem + R::kStageOff;
+  const int t = threadIdx.x;
+  const Dims3 d = j.d;
+  const Box3 b = j.b;
+  const int tz = j.tz, kmax = j.kmax;
+
+  const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0;
+  const int64_t ntx = (bx + kVTx - 1) / kVTx, nty = (by + TY - 1) / TY;
+  int64_t blk = blockIdx.x;
+  const int64_t tx = blk % ntx;
+  blk /= ntx;
+  const int64_t ty = blk % nty;
+  const int64_t tzi = blk / nty;
+  const int64_t x0 = b.x0 + tx * kVTx, y0 = b.y0 + ty * TY, z0 = b.z0 + tzi * tz;
+  if (z0 >= b.z1) return;
+  const int xs = (int)min((int64_t)kVTx, b.x1 - x0), ys = (int)min((int64_t)TY, b.y1 - y0);
+  const int64_t zs = min((int64_t)tz, b.z1 - z0);
+  const int64_t cA = max((int64_t)0, x0 - 1), cB = min(d.x, x0 + xs + 1);
+  const int64_t rA = max((int64_t)0, y0 - 1), rB = min(d.y, y0 + ys + 1);
+  const int64_t za = max((int64_t)0, z0 - 1), zb = min(d.z, z0 + zs + 1);
+  const int nrows = (int)(rB - rA);
+  const bool aligned = (d.x & 31) == 0 && (x0 & 31) == 0;
+
+  // decode item of this thread
+  const int dr = t / NBR, dk = t % NBR;
+  const int64_t dy = rA + dr;
+  const bool decoder = dr < nrows;
+  int* const prow = pl + (int)(dy - (y0 - 1)) * P;
+  uint32_t* const col = stage + t;
+
+  // stencil column of this thread
+  const int ec = R::at(t + 1 + R::kOff), em = R::at(t + R::kOff), ep = R::at(t + 2 + R::kOff);
+  const int64_t x = x0 + t;
+  const bool active = t < xs;
+  const bool ylo = y0 == 0, yhi = y0 + ys == d.y, xlo = x == 0, xhi = x == d.x - 1;
+  const bool y2 = d.y >= 2, x2 = d.x >= 2;
+
+  int ipc[NT][TY], ipp[NT][TY], zn[NT][TY], h1[NT][TY], h2[NT][TY];
+#pragma unroll
+  for (int k = 0; k < NT; ++k)
+#pragma unroll
+    for (int i = 0; i < TY; ++i) { ipc[k][i] = 0; ipp[k][i] = 0; zn[k][i] = 0; h1[k][i] = 0; h2[k][i] = 0; }
+
+  // Staging of one (component, plane): the decode item's metadata and the
+  // first PF payload words of its block, loaded into registers ahead of use.
+  constexpr int PF = 16 * (S / 32);
+  struct Pending {
+    int w, q0, words, e0, c;
+    uint64_t off;
+    bool valid;
+    uint32_t pw[PF];
+  };
+  auto issue = [&](int c, int64_t p, Pending& m) {
+    m.valid = false;
+    m.c = c;
+    m.w = 0;
+    m.words = 0;
+    if (!decoder || p >= zb) return;
+    const StreamView& v = j.v[c];
+    const int64_t f = (p * d.y + dy) * d.x;
+    const int64_t bA = (f + cA) / S, bB = (f + cB - 1) / S, bk = bA + dk;
+    if (bk > bB) return;
+    m.valid = true;
+    m.w = (int)v.width[bk];
+    m.q0 = v.q0[bk];
+    m.off = v.chunk_off[bk / kChunkBlocks] + j.rel[c][bk];
+    m.e0 = (int)(bk * S - f);
+    m.words = block_words<S>(m.w);
+    if (m.w > kMaxWidth || m.words > kmax || m.off + (uint64_t)m.words > v.payload_words) {
+      record_status(status, kErrBadStream);
+      m.w = 0;
+      m.words = 0;
+    }
+    prefetch_words<PF>(v.payload, v.payload_words, m.off, m.words, m.pw);
+  };
+  // staged words to this thread's column, then the block into the LDS plane
+  auto commit = [&](const Pending& m) {
+    if (!m.valid) return;
+#pragma unroll
+    for (int k = 0; k < PF; ++k)
+      if (k < m.words) col[k * kVThreads] = m.pw[k];
+    const uint32_t* src = j.v[m.c].payload + m.off;
+    for (int k = PF; k < m.words; ++k) col[k * kVThreads] = src[k];
+    const int cb = m.e0 - (int)(x0 - 1) + R::kOff;  // extended column of slot 0 (>= 0)
+    int* dst = prow + R::at(cb);
+    // (a block of width 0 decodes as q0 everywhere: zero magnitudes)
+    if (aligned) decode_block_q<S, true, kVThreads>(col, m.w, m.q0, dst, 32);
+    else decode_block_q<S, false, kVThreads>(col, m.w, m.q0, dst, 32 - (cb & 31));
+  };
+  // the one-sided ghosts of this thread's column (after the decode barrier)
+  auto ghosts = [&]() {
+    if (!active) return;
+    if (ylo) pl[ec] = y2 ? 2 * pl[P + ec] - pl[2 * P + ec] : pl[P + ec];
+    if (yhi) {
+      int* r = pl + ys * P + ec;
+      r[P] = y2 ? 2 * r[0] - r[-P] : r[0];
+    }
+    if (xlo || xhi) {
+#pragma unroll
+      for (int i = 0; i < TY; ++i) {
+        int* r = pl + (i + 1) * P;
+        if (xlo) r[em] = x2 ? 2 * r[ec] - r[ep] : r[ec];
+        if (xhi) r[ep] = x2 ? 2 * r[ec] - r[em] : r[ec];
+      }
+    }
+  };
+
+  // one output value of plane o from the numerators of its terms
+  auto emit = [&](int64_t o, bool last) {
+    if (!active || o < z0 || o >= z0 + zs) return;
+#pragma unroll
+    for (int i = 0; i < TY; ++i) {
+      if (i < ys) {
+        const int64_t e = ((o - b.z0) * by + (y0 + i - b.y0)) * bx + (x - b.x0);
+#pragma unroll
+        for (int oo = 0; oo < Tm::nout; ++oo) {
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < NT; ++k) {
+            const VTerm tm = Tm::t[k];
+            if (tm.o != oo) continue;
+            int n;
+            if (tm.a == 0) n = last ? ((d.z >= 2) ? 2 * (h1[k][i] - h2[k][i]) : 0) : zn[k][i];
+            else n = ipp[k][i];
+            acc += (double)(tm.s * n) * j.halfq[tm.c];
+          }
+          ((T*)j.out[oo])[e] = (T)acc;
+        }
+      }
+    }
+  };
+
+  // (component, plane) pairs in order (p, 0), (p, 1), ..., (p + 1, 0): the
+  // next pair's metadata and words load while this pair's stencil runs
+  Pending cur, nxt;
+  issue(0, za, cur);
+  for (int64_t p = za; p < zb; ++p) {
+    const int64_t o = p - 1;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      commit(cur);
+      __syncthreads();
+      if (c + 1 < NC) issue(c + 1, p, nxt);
+      else issue(0, p + 1, nxt);
+      ghosts();
+      if (active) {
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+          const VTerm tm = Tm::t[k];
+          if (tm.c != c) continue;
+#pragma unroll
+          for (int i = 0; i < TY; ++i) {
+            const int r = i + 1;
+            const int qc = pl[r * P + ec];
+            if (tm.a == 0) {
+              // z numerator of plane o = p - 1; the field's first plane uses
+              // the ghost 2 q_0 - q_1 below it
+              if (o == 0) h2[k][i] = d.z >= 2 ? 2 * h1[k][i] - qc : h1[k][i];
+              zn[k][i] = qc - h2[k][i];
+              h2[k][i] = h1[k][i];
+              h1[k][i] = qc;
+            } else if (tm.a == 1) {
+              ipc[k][i] = pl[(r + 1) * P + ec] - pl[(r - 1) * P + ec];
+            } else {
+              ipc[k][i] = pl[r * P + ep] - pl[r * P + em];
+            }
+          }
+        }
+      }
+      __syncthreads();
+      cur = nxt;
+    }
+    emit(o, false);
+#pragma unroll
+    for (int k = 0; k < NT; ++k)
+#pragma unroll
+      for (int i = 0; i < TY; ++i) ipp[k][i] = ipc[k][i];
+  }
+  // the field's last plane: one-sided in z (or 0 on a single plane)
+  if (z0 + zs == zb && zb == d.z) emit(zb - 1, true);
+}
+
+template <int OP, int NC, typename T>
+hipError_t vec_buf(const VecJob& j, int stage, hipStream_t s) {
+  const int64_t vol = j.b.volume();
+  const int64_t g = (vol + 255) / 256;
+  const unsigned grid = (unsigned)(g < 65536 ? g : 65536);
+  if (stage == 3) hipLaunchKernelGGL((k_vector_buf<3, OP, NC, T>), dim3(grid), dim3(256), 0, s, j);
+  else hipLaunchKernelGGL((k_vector_buf<4, OP, NC, T>), dim3(grid), dim3(256), 0, s, j);
+  return hipGetLastError();
+}
+
+template <int S, int OP, int NC, typename T>
+hipError_t vec_fused(const VecJob& j0, uint8_t* ws, hipStream_t s) {
+  VecJob j = j0;
+  constexpr int TY = vty<OP, NC>();
+  using R = VRow<S, TY>;
+  const Box3& b = j.b;
+  const int64_t ntx = (b.x1 - b.x0 + kVTx - 1) / kVTx, nty = (b.y1 - b.y0 + TY - 1) / TY;
+  const int64_t bz = b.z1 - b.z0;
+  int64_t tz = bz;
+  while (tz > 8 && ntx * nty * ((bz + tz - 1) / tz) < 2048) tz = (tz + 1) / 2;
+  j.tz = (int)tz;
+  const size_t lds = (size_t)R::kStageOff * 4 + (size_t)(j.kmax + 1) * kVThreads * 4;
+  const int64_t grid = ntx * nty * ((bz + tz - 1) / tz);
+  hipLaunchKernelGGL((k_vector_fused<S, OP, NC, T>), dim3((unsigned)grid), dim3(kVThreads), lds, s, j, (int*)ws);
+  return hipGetLastError();
+}
+
+template <int OP, typename T>
+hipError_t by_nc_buf(const VecJob& j, int stage, hipStream_t s) {
+  if constexpr (OP == kOpDivergence) {
+    if (j.nc == 1) return vec_buf<OP, 1, T>(j, stage, s);
+    if (j.nc == 2) return vec_buf<OP, 2, T>(j, stage, s);
+    return vec_buf<OP, 3, T>(j, stage, s);
+  } else {
+    if (j.nc == 2) return vec_buf<OP, 2, T>(j, stage, s);
+    return vec_buf<OP, 3, T>(j, stage, s);
+  }
+}
+
+template <int S, int OP, typename T>
+hipError_t by_nc_fused(const VecJob& j, uint8_t* ws, hipStream_t s) {
+  if constexpr (OP == kOpDivergence) {
+    if (j.nc == 1) return vec_fused<S, OP, 1, T>(j, ws, s);
+    if (j.nc == 2) return vec_fused<S, OP, 2, T>(j, ws, s);
+    return vec_fused<S, OP, 3, T>(j, ws, s);
+  } else {
+    if (j.nc == 2) return vec_fused<S, OP, 2, T>(j, ws, s);
+    return vec_fused<S, OP, 3, T>(j, ws, s);
+  }
+}
+
+template <int S, typename T>
+hipError_t fused_s(const VecJob& j, uint8_t* ws, hipStream_t s) {
+  return j.op == kOpDivergence ? by_nc_fused<S, kOpDivergence, T>(j, ws, s) : by_nc_fused<S, kOpCurl, T>(j, ws, s);
+}
+
+}  // namespace
+
+uint64_t vector_workspace_bytes(const int64_t* nb, int nc) {
+  uint64_t off = kGradIndexOff;
+  for (int c = 0; c < nc; ++c) off += ((2 * (uint64_t)nb[c] + 255) / 256) * 256;
+  return off;
+}
+
+hipError_t launch_vector_stage(const VecJob& j, int stage, int dtype, hipStream_t s) {
+  if (j.op == kOpDivergence)
+    return dtype == 1 ? by_nc_buf<kOpDivergence, float>(j, stage, s) : by_nc_buf<kOpDivergence, double>(j, stage, s);
+  return dtype == 1 ? by_nc_buf<kOpCurl, float>(j, stage, s) : by_nc_buf<kOpCurl, double>(j, stage, s);
+}
+
+hipError_t launch_vector_fused(const VecJob& j0, uint8_t* ws, hipStream_t s) {
+  VecJob j = j0;
+  // per-component block indexes in the workspace after the status words
+  uint64_t off = kGradIndexOff;
+  int kmax = 1;
+  for (int c = 0; c < j.nc; ++c) {
+    uint16_t* rel = (uint16_t*)(ws + off);
+    hipError_t e = launch_block_index(j.v[c], rel, s);
+    if (e != hipSuccess) return e;
+    j.rel[c] = rel;
+    off += ((2 * (uint64_t)j.v[c].nb + 255) / 256) * 256;
+    kmax = std::max(kmax, grad_kmax(j.v[c]));
+  }
+  j.kmax = kmax;
+  const int dtype = j.v[0].dtype, S = j.v[0].block;
+  if (S == 32) return dtype == 1 ? fused_s<32, float>(j, ws, s) : fused_s<32, double>(j, ws, s);
+  return dtype == 1 ? fused_s<64, float>(j, ws, s) : fused_s<64, double>(j, ws, s);
+}
+
+}  // namespace hsz

@@ -26,10 +26,11 @@ ERR_INVALID_ARG, ERR_BAD_STREAM, ERR_UNSUPPORTED, ERR_RANGE, ERR_EB, ERR_NONFINI
     -1, -2, -3, -4, -5, -6, -7, -8)
 F32, F64 = 1, 2
 META, DELTA, QUANT, FLOAT = 1, 2, 3, 4
-MEAN, VAR, DERIV, GRADMAG, LAPLACIAN = 1, 2, 3, 4, 5
+MEAN, VAR, DERIV, GRADMAG, LAPLACIAN, DIVERGENCE, CURL = 1, 2, 3, 4, 5, 6, 7
 HEADER_BYTES = 256
 
-_OPS = {"mean": MEAN, "var": VAR, "deriv": DERIV, "gradmag": GRADMAG, "laplacian": LAPLACIAN}
+_OPS = {"mean": MEAN, "var": VAR, "deriv": DERIV, "gradmag": GRADMAG, "laplacian": LAPLACIAN,
+        "divergence": DIVERGENCE, "curl": CURL}
 _STAGES = {"meta": META, "delta": DELTA, "quant": QUANT, "float": FLOAT}
 
 
@@ -85,7 +86,8 @@ EXPORTS = (
     "hsz_compress_workspace", "hsz_compress", "hsz_read_header", "hsz_stage_bytes",
     "hsz_decompress_to_stage", "hsz_op_workspace", "hsz_op_on_stage", "hsz_op_fused",
     "hsz_batch_workspace", "hsz_batch_run", "hsz_plan_create", "hsz_plan_update", "hsz_plan_launch",
-    "hsz_plan_destroy", "hsz_block_index_bytes", "hsz_block_index",
+    "hsz_plan_destroy", "hsz_block_index_bytes", "hsz_block_index", "hsz_vector_workspace",
+    "hsz_vector_op_on_stage", "hsz_vector_op_fused",
 )
 
 _lib = None
@@ -126,6 +128,9 @@ def load(path: str = LIB_PATH):
         "hsz_plan_destroy": (None, [P]),
         "hsz_block_index_bytes": (i32, [ctypes.POINTER(Header), pu64]),
         "hsz_block_index": (i32, [P, ctypes.POINTER(Header), P, u64, P]),
+        "hsz_vector_workspace": (i32, [P, i32, pu64]),
+        "hsz_vector_op_on_stage": (i32, [P, P, i32, i32, i32, ctypes.POINTER(Box), P, u64, P, u64, P]),
+        "hsz_vector_op_fused": (i32, [P, P, i32, i32, i32, ctypes.POINTER(Box), P, u64, P, u64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -407,6 +412,73 @@ def op_fused(c: Compressed, via, op, axis: int = 0, box=None, stream=None, check
                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream(stream))),
            "op_fused")
     return _finish(buf, shape, h, op, ws, stream, check, raw)
+
+
+# ---- vector fields -------------------------------------------------------------------
+
+def _headers_array(headers):
+    arr = (ctypes.POINTER(Header) * len(headers))(*[ctypes.pointer(h) for h in headers])
+    return arr
+
+
+def vector_workspace_bytes(headers) -> int:
+    out = ctypes.c_uint64()
+    arr = _headers_array(headers)
+    _check(load().hsz_vector_workspace(ctypes.cast(arr, ctypes.c_void_p), len(headers), ctypes.byref(out)),
+           "vector_workspace")
+    return out.value
+
+
+def _vector_results(h: Header, op: int, box, device, outs):
+    nout = 3 if (op == CURL and h.ndim == 3) else 1
+    if outs is None:
+        outs = [_result_buffer(h, DERIV, box, device)[0] for _ in range(nout)]
+    shape = h.shape if box is None else tuple(int(hi) - int(lo) for lo, hi in zip(*box))
+    return outs, shape
+
+
+def _vector_call(fn_name, ptrs, headers, dev, mode, op, box, stream, check, outs, ws, what):
+    lib = load()
+    op = _OPS.get(op, op)
+    h = headers[0]
+    outs, shape = _vector_results(h, op, box, dev, outs)
+    if ws is None:
+        ws = workspace(vector_workspace_bytes(headers), dev)
+    harr = _headers_array(headers)
+    parr = (ctypes.c_void_p * len(ptrs))(*ptrs)
+    oarr = (ctypes.c_void_p * 3)(*([o.data_ptr() for o in outs] + [None] * (3 - len(outs))))
+    cap = min(o.numel() for o in outs)
+    _check(getattr(lib, fn_name)(ctypes.cast(parr, ctypes.c_void_p), ctypes.cast(harr, ctypes.c_void_p),
+                                 len(headers), mode, op, _box(box, h.ndim), ctypes.cast(oarr, ctypes.c_void_p),
+                                 cap, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                 ctypes.c_void_p(_stream(stream))), what)
+    if check:
+        st = read_status(ws, stream)
+        if st != OK:
+            raise HszError(st, what)
+    vol = 1
+    for n in shape:
+        vol *= n
+    esz = 4 if h.dtype == F32 else 8
+    res = [o[: esz * vol].view(h.torch_dtype).view(shape) for o in outs]
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def vector_op_fused(comps, op, via=QUANT, box=None, stream=None, check: bool = True, outs=None, ws=None):
+    """Divergence or curl of the vector field whose component k is the
+    compressed stream comps[k], computed from the streams through D_q.
+    Returns one tensor, or three for the curl of a 3D field."""
+    via = _STAGES.get(via, via)
+    return _vector_call("hsz_vector_op_fused", [c.data.data_ptr() for c in comps], [c.header for c in comps],
+                        comps[0].data.device, via, op, box, stream, check, outs, ws, "vector_op_fused")
+
+
+def vector_op_on_stage(bufs, headers, stage, op, box=None, stream=None, check: bool = True, outs=None, ws=None):
+    """Divergence or curl on materialised stage-3 or stage-4 buffers (one per
+    component, from decompress_to_stage)."""
+    stage = _STAGES.get(stage, stage)
+    return _vector_call("hsz_vector_op_on_stage", [b.data_ptr() for b in bufs], list(headers), bufs[0].device,
+                        stage, op, box, stream, check, outs, ws, "vector_op_on_stage")
 
 
 def from_bytes(data, device="cuda") -> Compressed:
