@@ -120,3 +120,52 @@ def test_argument_validation_before_any_launch(lib):
         hsz.ERR_CAPACITY
     assert lib.hsz_decompress_to_stage(fake, *args, 5, fake, 1 << 20, fake, 256, None) == hsz.ERR_INVALID_ARG
     assert lib.hsz_decompress_to_stage(fake, *args, hsz.QUANT, fake, 16, fake, 256, None) == hsz.ERR_CAPACITY
+
+
+def test_laplacian_and_vector_validation_before_any_launch(lib):
+    """The Laplacian and the vector-field entry points refuse, on the host,
+    what they do not define (fake aligned addresses are never touched)."""
+    fake = ctypes.c_void_p(0x10000)
+    x = np.linspace(0, 1, 6 * 7 * 8).astype(np.float32).reshape(6, 7, 8)
+    h = hsz.read_header(oracle.compress(x, 1e-3))
+    ws = ctypes.c_uint64()
+    assert lib.hsz_op_workspace(ctypes.byref(h), hsz.LAPLACIAN, ctypes.byref(ws)) == 0
+    # no Laplacian on the decorrelated stage of a 1D partition
+    assert lib.hsz_op_on_stage(fake, ctypes.byref(h), hsz.DELTA, hsz.LAPLACIAN, 0, None, fake, 4 * x.size, fake,
+                               ws.value, None) == hsz.ERR_UNSUPPORTED
+    assert lib.hsz_op_fused(fake, ctypes.byref(h), hsz.DELTA, hsz.LAPLACIAN, 0, None, fake, 4 * x.size, fake,
+                            ws.value, None) == hsz.ERR_UNSUPPORTED
+    hs = [hsz.read_header(oracle.compress(x * (k + 1), 1e-3)) for k in range(3)]
+    harr = (ctypes.POINTER(hsz.Header) * 3)(*[ctypes.pointer(v) for v in hs])
+    ptrs = (ctypes.c_void_p * 3)(0x10000, 0x20000, 0x30000)
+    outs = (ctypes.c_void_p * 3)(0x40000, 0x50000, 0x60000)
+    vws = ctypes.c_uint64()
+    assert lib.hsz_vector_workspace(ctypes.cast(harr, ctypes.c_void_p), 3, ctypes.byref(vws)) == 0
+    args = (ctypes.cast(ptrs, ctypes.c_void_p), ctypes.cast(harr, ctypes.c_void_p))
+    cap = 4 * x.size
+
+    def fused(nc, via, op, cap_=cap, w=vws.value):
+        return lib.hsz_vector_op_fused(*args, nc, via, op, None, ctypes.cast(outs, ctypes.c_void_p), cap_, fake, w,
+                                       None)
+
+    def staged(nc, stage, op):
+        return lib.hsz_vector_op_on_stage(*args, nc, stage, op, None, ctypes.cast(outs, ctypes.c_void_p), cap,
+                                          fake, vws.value, None)
+    assert fused(2, hsz.QUANT, hsz.DIVERGENCE) == hsz.ERR_INVALID_ARG  # a 3D field needs three components
+    assert fused(3, hsz.QUANT, hsz.MEAN) == hsz.ERR_INVALID_ARG
+    assert fused(3, hsz.FLOAT, hsz.CURL) == hsz.ERR_UNSUPPORTED  # fused only through D_q
+    assert fused(3, hsz.DELTA, hsz.CURL) == hsz.ERR_UNSUPPORTED
+    assert staged(3, hsz.DELTA, hsz.DIVERGENCE) == hsz.ERR_UNSUPPORTED
+    assert fused(3, hsz.QUANT, hsz.CURL, cap_=16) == hsz.ERR_CAPACITY
+    assert fused(3, hsz.QUANT, hsz.CURL, w=64) == hsz.ERR_CAPACITY
+    other = hsz.read_header(oracle.compress(x[:, :, :7].copy(), 1e-3))
+    harr2 = (ctypes.POINTER(hsz.Header) * 3)(ctypes.pointer(hs[0]), ctypes.pointer(other), ctypes.pointer(hs[2]))
+    assert lib.hsz_vector_op_fused(ctypes.cast(ptrs, ctypes.c_void_p), ctypes.cast(harr2, ctypes.c_void_p), 3,
+                                   hsz.QUANT, hsz.DIVERGENCE, None, ctypes.cast(outs, ctypes.c_void_p), cap, fake,
+                                   vws.value, None) == hsz.ERR_INVALID_ARG  # components of different dims
+    x1 = np.linspace(0, 1, 300).astype(np.float32)
+    h1 = hsz.read_header(oracle.compress(x1, 1e-3))
+    h1arr = (ctypes.POINTER(hsz.Header) * 1)(ctypes.pointer(h1))
+    assert lib.hsz_vector_op_fused(ctypes.cast(ptrs, ctypes.c_void_p), ctypes.cast(h1arr, ctypes.c_void_p), 1,
+                                   hsz.QUANT, hsz.CURL, None, ctypes.cast(outs, ctypes.c_void_p), 4 * 300, fake,
+                                   vws.value, None) == hsz.ERR_INVALID_ARG  # no curl of a 1D field
