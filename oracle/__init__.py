@@ -15,6 +15,8 @@ Functions and the passages of the paper they follow:
   compress           Alg. 1 end to end
   decompress         Alg. 2 (stages: 1 metadata, 2 decorrelated,
                      3 quantized, 4 floats)
+  compress(mean_dec) Sec. IV HSZx paragraph: block-mean decorrelation
+  meta_mean          Sec. V-A Eq. (mean_m), the mean from the metadata
   mean, var          Sec. III-B Eq. (var) on the decompressed field
   derivative,        Sec. III-B Eq. (derivatives), unit spacing, one-sided
   gradmag            at the ends of an axis
@@ -82,9 +84,11 @@ def _load():
     lib.or_quantize.restype = u64
     lib.or_quantize.argtypes = [P, u64, dbl, P]
     lib.or_encode_q.restype = i32
-    lib.or_encode_q.argtypes = [P, u32, P, u32, dbl, dbl, u32, P, u64, P]
+    lib.or_encode_q.argtypes = [P, u32, P, u32, dbl, dbl, u32, u32, P, u64, P]
     lib.or_compress.restype = i32
-    lib.or_compress.argtypes = [P, u32, u32, P, dbl, i32, u32, P, u64, P]
+    lib.or_compress.argtypes = [P, u32, u32, P, dbl, i32, u32, u32, P, u64, P]
+    lib.or_meta_mean.restype = i32
+    lib.or_meta_mean.argtypes = [P, u64, P, P]
     lib.or_read_header.restype = i32
     lib.or_read_header.argtypes = [P, u64, P]
     lib.or_stage_bytes.restype = u64
@@ -149,6 +153,7 @@ class Header:
     off_payload: int
     payload_words: int
     total_bytes: int
+    flags: int = 0  # bit 0: block-mean decorrelation
 
 
 def _ptr(a: np.ndarray) -> int:
@@ -204,18 +209,29 @@ def quantize(x, quantum: float) -> np.ndarray:
     return q
 
 
-def encode_q(q, shape, quantum: float, block: int, dtype: int = F32, eb_abs: float = 0.0) -> np.ndarray:
+def encode_q(q, shape, quantum: float, block: int, dtype: int = F32, eb_abs: float = 0.0,
+             mean_dec: bool = False) -> np.ndarray:
+    """Encode given quantization integers; mean_dec selects block-mean
+    decorrelation (HSZx) instead of in-block deltas."""
     q = np.ascontiguousarray(np.asarray(q, dtype=np.int32).ravel())
     dims = np.array([int(s) for s in shape], dtype=np.uint64)
     cap = compress_bound(q.size, block)
     out = np.zeros(cap, dtype=np.uint8)
     size = ctypes.c_uint64()
     _check(_load().or_encode_q(_ptr(q), len(shape), _ptr(dims), dtype, eb_abs, quantum, block,
-                               _ptr(out), cap, ctypes.byref(size)), "encode_q")
+                               int(bool(mean_dec)), _ptr(out), cap, ctypes.byref(size)), "encode_q")
     return out[: size.value].copy()
 
 
-def compress(x: np.ndarray, eb: float, rel: bool = True, block: int = 32) -> np.ndarray:
+def meta_mean(buf: np.ndarray):
+    """Eq. (mean_m) on a block-mean stream: -> (sum_b M_b S_b as int, mean)."""
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    ms, mean = ctypes.c_int64(), ctypes.c_double()
+    _check(_load().or_meta_mean(_ptr(buf), buf.size, ctypes.byref(ms), ctypes.byref(mean)), "meta_mean")
+    return ms.value, mean.value
+
+
+def compress(x: np.ndarray, eb: float, rel: bool = True, block: int = 32, mean_dec: bool = False) -> np.ndarray:
     x = np.ascontiguousarray(x)
     if x.dtype == np.float32:
         dt = F32
@@ -227,8 +243,8 @@ def compress(x: np.ndarray, eb: float, rel: bool = True, block: int = 32) -> np.
     cap = compress_bound(x.size, block)
     out = np.empty(cap, dtype=np.uint8)
     size = ctypes.c_uint64()
-    _check(_load().or_compress(_ptr(x), dt, x.ndim, _ptr(dims), eb, int(rel), block, _ptr(out),
-                               cap, ctypes.byref(size)), "compress")
+    _check(_load().or_compress(_ptr(x), dt, x.ndim, _ptr(dims), eb, int(rel), block, int(bool(mean_dec)),
+                               _ptr(out), cap, ctypes.byref(size)), "compress")
     return out[: size.value].copy()
 
 
@@ -242,7 +258,7 @@ def read_header(buf: np.ndarray) -> Header:
         eb_abs=h.eb_abs, quantum=h.quantum, inv_quantum=h.inv_quantum, vmin=h.vmin, vmax=h.vmax,
         max_abs_q=h.max_abs_q, nb=h.nb, nchunks=h.nchunks, off_chunk=h.off_chunk,
         off_q0=h.off_q0, off_width=h.off_width, off_payload=h.off_payload,
-        payload_words=h.payload_words, total_bytes=h.total_bytes)
+        payload_words=h.payload_words, total_bytes=h.total_bytes, flags=h.flags)
 
 
 def decompress(buf: np.ndarray, stage: int):

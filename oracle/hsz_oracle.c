@@ -51,6 +51,14 @@
  *      differences, the two ends of an axis use one-sided differences
  *      (the rule of numpy.gradient with edge_order=1); an axis of length 1
  *      has derivative 0.  Gradient magnitude = sqrt(sum_k g_k^2).
+ *   R10 block-mean decorrelation (HSZx, Sec. IV: p_i = q_i - mean(B_i0)),
+ *      selected by bit 0 of the header flags: the metadata of block b is the
+ *      integer mean M_b = round_half_down(sum of its q / S_b), i.e.
+ *      ceil((2 sum - S_b) / (2 S_b)) -- the printed M_1 = 5 for a block
+ *      mean of 5.5 and the bound |sum/S_b - M_b| <= 1/2 used by the bias
+ *      analysis of the metadata mean both hold; p_i = q_i - M_b on every
+ *      slot (none is forced to 0); q_i = M_b + p_i.  Padding slots of the
+ *      last block (past n) hold p = 0 as in the delta mode.
  *   R8 the Laplacian of Eq. (laplacian) on n axes is the sum over the axes
  *      of d_{-1} + d_{+1} - 2 d (unit spacing); at the two ends of an axis
  *      the missing neighbour is the end value itself (the field mirrored
@@ -194,6 +202,7 @@ int or_read_header(const uint8_t *buf, uint64_t len, or_header *h) {
   h->payload_words = get_u64(buf + 144);
   h->total_bytes = get_u64(buf + 152);
   if (h->dtype != 1 && h->dtype != 2) return OR_ERR_STREAM;
+  if (h->flags > 1u) return OR_ERR_STREAM;  /* bit 0: block-mean decorrelation (R10) */
   if (h->ndim < 1 || h->ndim > 3) return OR_ERR_STREAM;
   if (h->block < 1 || h->block > 64 || h->chunk_blocks != OR_CHUNK_BLOCKS) return OR_ERR_STREAM;
   uint64_t prod = 1;
@@ -297,6 +306,13 @@ static uint32_t stream_get_bits(const uint32_t *words, uint64_t bitpos, uint32_t
   return v;
 }
 
+/* round(a / b) with halves rounded down, b > 0: ceil((2a - b) / (2b)) in
+ * exact integer arithmetic (C division truncates toward zero) */
+static int64_t round_half_down_div(int64_t a, int64_t b) {
+  const int64_t num = 2 * a - b, den = 2 * b;
+  return num >= 0 ? (num + den - 1) / den : -((-num) / den);
+}
+
 /* Encode already-quantized integers q[n] (the field read as a flat array)
  * into the byte format.  'h' carries dtype, dims, eps, Delta, extremes; the
  * layout fields are filled here.  The output must be zero-filled by this
@@ -318,13 +334,20 @@ static int encode_q(const int32_t *q, or_header *h, uint8_t *out, uint64_t cap, 
   for (uint64_t b = 0; b < h->nb; b++) {
     uint64_t first = b * S;
     uint64_t len = (h->n - first < S) ? h->n - first : S;
-    q0[b] = q[first];
+    const int mean_mode = (h->flags & 1u) != 0;
+    if (mean_mode) {
+      int64_t sum = 0;
+      for (uint64_t i = 0; i < len; i++) sum += q[first + i];
+      q0[b] = (int32_t)round_half_down_div(sum, (int64_t)len);
+    } else {
+      q0[b] = q[first];
+    }
     uint32_t maxp = 0;
     for (uint64_t i = 0; i < len; i++) {
       int32_t qi = q[first + i];
       uint32_t aq = (uint32_t)(qi < 0 ? -(int64_t)qi : qi);
       if (aq > max_abs_q) max_abs_q = aq;
-      int32_t pi = (i == 0) ? 0 : qi - q[first + i - 1];
+      int32_t pi = mean_mode ? qi - q0[b] : (i == 0) ? 0 : qi - q[first + i - 1];
       p[first + i] = pi;
       uint32_t ap = (uint32_t)(pi < 0 ? -(int64_t)pi : pi);
       if (ap > maxp) maxp = ap;
@@ -369,7 +392,7 @@ static int encode_q(const int32_t *q, or_header *h, uint8_t *out, uint64_t cap, 
 /* Encode given quantization integers (used to pin the decorrelation and the
  * encoding on the paper's worked example, where the quantum is fixed). */
 int or_encode_q(const int32_t *q, uint32_t ndim, const uint64_t *dims, uint32_t dtype,
-                double eb_abs, double quantum, uint32_t S, uint8_t *out, uint64_t cap,
+                double eb_abs, double quantum, uint32_t S, uint32_t flags, uint8_t *out, uint64_t cap,
                 uint64_t *out_size) {
   if (!q || !dims || ndim < 1 || ndim > 3 || S < 1 || S > 64 || (dtype != 1 && dtype != 2))
     return OR_ERR_ARG;
@@ -387,13 +410,15 @@ int or_encode_q(const int32_t *q, uint32_t ndim, const uint64_t *dims, uint32_t 
   h.inv_quantum = 1.0 / quantum;
   h.vmin = 0.0;
   h.vmax = 0.0;
+  if (flags > 1u) return OR_ERR_ARG;
+  h.flags = flags;
   return encode_q(q, &h, out, cap, out_size);
 }
 
 /* Full compressor C(d, eps): extremes -> parameters -> quantize -> encode. */
 int or_compress(const void *x, uint32_t dtype, uint32_t ndim, const uint64_t *dims, double eb,
-                int eb_is_rel, uint32_t S, uint8_t *out, uint64_t cap, uint64_t *out_size) {
-  if (!x || !dims || ndim < 1 || ndim > 3 || S < 1 || S > 64 || (dtype != 1 && dtype != 2))
+                int eb_is_rel, uint32_t S, uint32_t flags, uint8_t *out, uint64_t cap, uint64_t *out_size) {
+  if (!x || !dims || ndim < 1 || ndim > 3 || S < 1 || S > 64 || (dtype != 1 && dtype != 2) || flags > 1u)
     return OR_ERR_ARG;
   or_header h;
   memset(&h, 0, sizeof h);
@@ -404,6 +429,7 @@ int or_compress(const void *x, uint32_t dtype, uint32_t ndim, const uint64_t *di
   for (uint32_t k = 0; k < ndim; k++) { h.dims[3 - ndim + k] = dims[k]; h.n *= dims[k]; }
   if (h.n == 0) return OR_ERR_ARG;
   h.block = S;
+  h.flags = flags;
 
   double *xd = (double *)malloc(h.n * sizeof(double));
   if (!xd) return OR_ERR_ARG;
@@ -498,12 +524,14 @@ int or_decompress(const uint8_t *buf, uint64_t len, int stage, void *out) {
     return OR_OK;
   }
 
-  /* recorrelate: q_i = q_{i-1} + p_i inside a block, starting from q0 */
+  /* recorrelate: q_i = q_{i-1} + p_i inside a block, starting from q0 (delta
+     mode), or q_i = M_b + p_i (block-mean mode, R10) */
   int32_t *q = (int32_t *)malloc(h.n * sizeof(int32_t));
   if (!q) { free(p); free(q0); return OR_ERR_ARG; }
   for (uint64_t e = 0; e < h.n; e++) {
     uint64_t b = e / S;
-    q[e] = (e % S == 0) ? q0[b] : q[e - 1] + p[e];
+    if (h.flags & 1u) q[e] = q0[b] + p[e];
+    else q[e] = (e % S == 0) ? q0[b] : q[e - 1] + p[e];
   }
   free(p); free(q0);
   if (stage == 3) { memcpy(out, q, h.n * sizeof(int32_t)); free(q); return OR_OK; }
@@ -701,6 +729,25 @@ int or_curl(const double *const *comp, int ndim, const uint64_t *d, const int64_
         }
         o++;
       }
+  return OR_OK;
+}
+
+/* Eq. (mean_m): mean from the metadata alone, (1/N sum_b M_b S_b) * Delta,
+ * for a block-mean stream (R10); the exact integer sum_b M_b S_b is returned
+ * too.  The stream is read from its bytes. */
+int or_meta_mean(const uint8_t *buf, uint64_t len, int64_t *msum, double *mean) {
+  or_header h;
+  int rc = or_read_header(buf, len, &h);
+  if (rc != OR_OK) return rc;
+  if (!(h.flags & 1u)) return OR_ERR_UNSUPPORTED;
+  int64_t s = 0;
+  for (uint64_t b = 0; b < h.nb; b++) {
+    const uint64_t first = b * h.block;
+    const int64_t sb = (int64_t)((h.n - first < h.block) ? h.n - first : h.block);
+    s += (int64_t)(int32_t)get_u32(buf + h.off_q0 + 4 * b) * sb;
+  }
+  *msum = s;
+  *mean = (double)s / (double)h.n * h.quantum;
   return OR_OK;
 }
 
