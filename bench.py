@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workloads")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--no-vector", action="store_true", help="skip the vector-field (divergence, curl) workload")
+    ap.add_argument("--no-hszx", action="store_true", help="skip the block-mean (HSZx) workload")
     ap.add_argument("--snapshots", type=int, default=64)
     ap.add_argument("--queries", type=int, default=20000)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -343,6 +344,9 @@ def main():
     if not a.no_vector:
         out["vector_field"] = bench_vector(a, log)
         torch.cuda.empty_cache()
+    if not a.no_hszx:
+        out["block_mean"] = bench_hszx(a, log)
+        torch.cuda.empty_cache()
     if not a.no_batch:
         out["batching"] = bench_batches(a, log)
         torch.cuda.empty_cache()
@@ -421,6 +425,77 @@ def bench_vector(a, log):
                    "speedup_vs_full_decompress": round(ms_b / ms_f, 3)}
     log(f"[bench] vector field: {res}")
     del comps, outs, qbufs, fbufs
+    return res
+
+
+def bench_hszx(a, log):
+    """The step's 512^3 binary32 field compressed in both decorrelation modes
+    (rel eb 1e-4, S=32): compression time and ratio, the mean from the block
+    means alone (Eq. (mean_m)), the exact mean via D_p, the variance via D_q,
+    the gradient magnitude (fused from the delta stream; decode to D_q then
+    the stencil for block-mean streams), and full decompression + the mean
+    on floats."""
+    import torch
+
+    from paper_2603_25206_amd import hsz, synth
+
+    shape = tuple(int(v) for v in a.shape.split(","))
+    x = synth.make_field_torch(synth.large_field_spec(seed=0, shape=shape), "cuda")
+    dev, cur = x.device, torch.cuda.current_stream()
+    orig = x.numel() * x.element_size()
+    n = x.numel()
+    res = {"shape": list(shape), "orig_bytes": orig}
+    s48 = torch.empty(64, dtype=torch.uint8, device=dev)
+    gbuf = torch.empty(4 * n, dtype=torch.uint8, device=dev)
+    qbuf = torch.empty(4 * n, dtype=torch.uint8, device=dev)
+    fbuf = torch.empty(4 * n + 64, dtype=torch.uint8, device=dev)
+    for mode, mean_dec in (("delta", False), ("block_mean", True)):
+        c = hsz.compress(x, a.eb, rel=True, block=a.block, mean_dec=mean_dec)
+        torch.cuda.synchronize()
+        h = c.header
+        ws = hsz.workspace(max(hsz.op_workspace_bytes(h, op) for op in (hsz.MEAN, hsz.VAR, hsz.GRADMAG)), dev,
+                           key="bench-hszx")
+
+        def comp():
+            hsz.compress(x, a.eb, rel=True, block=a.block, mean_dec=mean_dec)
+
+        def stat(via, op):
+            return lambda: hsz.op_fused(c, via, op, out=s48, ws=ws, check=False, raw=True)
+
+        def grad():
+            if mean_dec:
+                hsz.decompress_to_stage(c, hsz.QUANT, out=qbuf)
+                hsz.op_on_stage(hsz.stage_view(qbuf, h, hsz.QUANT), h, hsz.QUANT, hsz.GRADMAG, out=gbuf, ws=ws,
+                                check=False, raw=True)
+            else:
+                hsz.op_fused(c, hsz.QUANT, hsz.GRADMAG, out=gbuf, ws=ws, check=False, raw=True)
+
+        fview = hsz.stage_view(fbuf, h, hsz.FLOAT)
+
+        def full_mean():
+            hsz.decompress_to_stage(c, hsz.FLOAT, out=fbuf)
+            hsz.op_on_stage(fview, h, hsz.FLOAT, hsz.MEAN, out=s48, ws=ws, check=False, raw=True)
+
+        r = {"ratio": round(c.ratio, 3), "compress_ms": round(_events_ms(comp, 5, cur), 4)}
+        if mean_dec:
+            r["mean_meta_ms"] = round(_events_ms(stat(hsz.META, hsz.MEAN), 10, cur), 4)
+            m_meta = hsz.stats_of(s48)["mean"]
+        r["mean_delta_ms"] = round(_events_ms(stat(hsz.DELTA, hsz.MEAN), 10, cur), 4)
+        m_exact = hsz.stats_of(s48)["mean"]
+        r["var_quant_ms"] = round(_events_ms(stat(hsz.QUANT, hsz.VAR), 10, cur), 4)
+        r["gradmag_ms"] = round(_events_ms(grad, 5, cur), 4)
+        r["full_decompress_mean_ms"] = round(_events_ms(full_mean, 5, cur), 4)
+        if mean_dec:
+            r["mean_meta_gbs_orig"] = round(orig / r["mean_meta_ms"] / 1e6, 1)
+            r["speedup_mean_meta_vs_full"] = round(r["full_decompress_mean_ms"] / r["mean_meta_ms"], 2)
+            r["mean_meta_minus_exact"] = m_meta - m_exact
+            if abs(m_meta - m_exact) > h.eb_abs:
+                raise RuntimeError("mean from the block means is farther than eps from the exact mean")
+        r["eb_abs"] = h.eb_abs
+        res[mode] = r
+        del c, ws
+    log(f"[bench] block-mean: {res}")
+    del x, gbuf, qbuf, fbuf
     return res
 
 

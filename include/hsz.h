@@ -74,7 +74,7 @@ typedef struct hsz_header {
   double inv_quantum;     /* 1 / Delta, the quantizer's multiplier           */
   double vmin, vmax;      /* extremes of the input field                     */
   uint32_t max_abs_q;     /* max |q| over the field                          */
-  uint32_t flags;         /* reserved, 0                                     */
+  uint32_t flags;         /* 0, or HSZ_FLAG_BLOCK_MEAN (block-mean mode)     */
   int64_t nb;             /* number of blocks = ceil(n / S)                  */
   int64_t nchunks;        /* ceil(nb / 64)                                   */
   uint64_t off_chunk;     /* byte offsets of the sections in the stream      */
@@ -146,6 +146,22 @@ int hsz_compress_workspace(int ndim, const int64_t *h_dims, int block, uint64_t 
 int hsz_compress(const void *d_x, int dtype, int ndim, const int64_t *h_dims, double eb,
                  int eb_is_rel, int block, void *d_out, uint64_t cap, void *d_workspace,
                  uint64_t workspace_bytes, void *stream);
+
+/* The same with header flags: HSZ_FLAG_BLOCK_MEAN selects the block-mean
+ * decorrelation of HSZx (Sec. IV): the metadata of each block is its
+ * integer mean M_b = sum q / S_b rounded to the nearest integer, halves
+ * down, and p_i = q_i - M_b on every slot (none is forced to 0); decoding is
+ * q_i = M_b + p_i.  The stage-1 buffer (and the q0 section) then holds the
+ * block means, and HSZ_MEAN is defined on stage 1 (Eq. (mean_m), the whole
+ * field only): mean = (sum_b M_b S_b / n) * Delta, exact integer sum in s1,
+ * within eps of the mean of the decompressed field.  Streams of this mode
+ * support every statistic and the materialised stages 3 and 4 of the
+ * stencil operations; fused stencils, vector fields and batches return
+ * HSZ_ERR_UNSUPPORTED for them. */
+#define HSZ_FLAG_BLOCK_MEAN 1u
+int hsz_compress_flags(const void *d_x, int dtype, int ndim, const int64_t *h_dims, double eb,
+                       int eb_is_rel, int block, uint32_t flags, void *d_out, uint64_t cap,
+                       void *d_workspace, uint64_t workspace_bytes, void *stream);
 
 /* Parse and validate a header held in HOST memory.  'len' is the number of
  * stream bytes the caller holds (at least HSZ_HEADER_BYTES); the stream's

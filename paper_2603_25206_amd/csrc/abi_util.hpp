@@ -72,6 +72,7 @@ inline hsz::StreamView view_of(const void* d_c, const hsz_header* h) {
   v.dtype = h->dtype;
   v.quantum = h->quantum;
   v.max_abs_q = h->max_abs_q;
+  v.flags = h->flags;
   return v;
 }
 
@@ -88,6 +89,7 @@ inline int check_header(const hsz_header* h) {
     return HSZ_ERR_BAD_STREAM;
   if (h->total_bytes != h->off_payload + 4 * h->payload_words) return HSZ_ERR_BAD_STREAM;
   if (!(h->quantum > 0.0) || h->max_abs_q > (uint32_t)hsz::kQMax) return HSZ_ERR_BAD_STREAM;
+  if (h->flags > HSZ_FLAG_BLOCK_MEAN) return HSZ_ERR_BAD_STREAM;
   return HSZ_OK;
 }
 

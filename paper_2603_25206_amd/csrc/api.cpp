@@ -17,6 +17,14 @@ __global__ void k_reset_status(int* status) {
   if (threadIdx.x == 0) *status = 0;
 }
 
+// Stage 1 supports one operation: the mean of a block-mean stream over the
+// whole field (Eq. (mean_m)).
+bool meta_mean_ok(const hsz_header* h, int op, const hsz::OpTarget& t) {
+  const hsz::Box3& b = t.box;
+  const bool whole = b.z0 == 0 && b.y0 == 0 && b.x0 == 0 && b.z1 == t.d.z && b.y1 == t.d.y && b.x1 == t.d.x;
+  return (h->flags & HSZ_FLAG_BLOCK_MEAN) && op == HSZ_MEAN && whole;
+}
+
 // The integer Laplacian numerator is a sum of 12 terms of |q| in 32 bits.
 constexpr uint32_t kLapMaxQ = 1u << 27;
 
@@ -105,7 +113,15 @@ int hsz_compress_workspace(int ndim, const int64_t* h_dims, int block, uint64_t*
 
 int hsz_compress(const void* d_x, int dtype, int ndim, const int64_t* h_dims, double eb, int eb_is_rel, int block,
                  void* d_out, uint64_t cap, void* d_workspace, uint64_t workspace_bytes, void* stream) {
+  return hsz_compress_flags(d_x, dtype, ndim, h_dims, eb, eb_is_rel, block, 0u, d_out, cap, d_workspace,
+                            workspace_bytes, stream);
+}
+
+int hsz_compress_flags(const void* d_x, int dtype, int ndim, const int64_t* h_dims, double eb, int eb_is_rel,
+                       int block, uint32_t flags, void* d_out, uint64_t cap, void* d_workspace,
+                       uint64_t workspace_bytes, void* stream) {
   int64_t d3[3], n;
+  if (flags > HSZ_FLAG_BLOCK_MEAN) return HSZ_ERR_INVALID_ARG;
   if (!d_x || !d_out || !d_workspace || (dtype != HSZ_F32 && dtype != HSZ_F64) || !dims3_of(ndim, h_dims, d3, &n))
     return HSZ_ERR_INVALID_ARG;
   if (!aligned16(d_x) || !aligned16(d_out) || !aligned16(d_workspace)) return HSZ_ERR_INVALID_ARG;
@@ -123,6 +139,7 @@ int hsz_compress(const void* d_x, int dtype, int ndim, const int64_t* h_dims, do
   a.dims[2] = d3[2];
   a.eb = eb;
   a.eb_is_rel = eb_is_rel ? 1 : 0;
+  a.flags = flags;
   a.lay = L;
   a.out = (uint8_t*)d_out;
   a.cap = cap;
@@ -160,6 +177,7 @@ int hsz_read_header(const void* h_bytes, uint64_t len, uint64_t len_stream, hsz_
   h.vmax = rdf64(p + 80);
   h.max_abs_q = rd32(p + 88);
   h.flags = rd32(p + 92);
+  if (h.flags > HSZ_FLAG_BLOCK_MEAN) return HSZ_ERR_BAD_STREAM;
   h.nb = (int64_t)rd64(p + 96);
   h.nchunks = (int64_t)rd64(p + 104);
   h.off_chunk = rd64(p + 112);
@@ -248,8 +266,10 @@ int hsz_op_on_stage(const void* d_stage, const hsz_header* h, int stage, int op,
   int rc = op_common(h, op, axis, h_box, cap, d_result, d_workspace, workspace_bytes, &t, &axis3);
   if (rc) return rc;
   if (!d_stage || !aligned16(d_stage)) return HSZ_ERR_INVALID_ARG;
-  if (stage == HSZ_META) return HSZ_ERR_UNSUPPORTED;
-  if (stage < HSZ_DELTA || stage > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
+  if (stage == HSZ_META && !meta_mean_ok(h, op, t)) return HSZ_ERR_UNSUPPORTED;
+  if (stage < HSZ_META || stage > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
+  // a block-mean stream keeps no deltas between neighbours: no stencil on its stage 2
+  if ((h->flags & HSZ_FLAG_BLOCK_MEAN) && op >= HSZ_DERIV && stage == HSZ_DELTA) return HSZ_ERR_UNSUPPORTED;
   // on the decorrelated stage only the derivative along the fast axis is
   // defined (the 1D partition keeps no other neighbour relation)
   if (op >= HSZ_DERIV && stage == HSZ_DELTA && !(op == HSZ_DERIV && axis3 == 2)) return HSZ_ERR_UNSUPPORTED;
@@ -270,8 +290,10 @@ int hsz_op_fused(const void* d_c, const hsz_header* h, int via, int op, int axis
   int rc = op_common(h, op, axis, h_box, cap, d_result, d_workspace, workspace_bytes, &t, &axis3);
   if (rc) return rc;
   if (!d_c || !aligned16(d_c)) return HSZ_ERR_INVALID_ARG;
-  if (via == HSZ_META) return HSZ_ERR_UNSUPPORTED;
-  if (via < HSZ_DELTA || via > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
+  if (via == HSZ_META && !meta_mean_ok(h, op, t)) return HSZ_ERR_UNSUPPORTED;
+  if (via < HSZ_META || via > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
+  // fused stencils decode delta streams only
+  if ((h->flags & HSZ_FLAG_BLOCK_MEAN) && op >= HSZ_DERIV) return HSZ_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   const hsz::StreamView v = view_of(d_c, h);
   if (op >= HSZ_DERIV) {
@@ -371,6 +393,7 @@ int hsz_vector_op_fused(const void* const* d_c, const hsz_header* const* h, int 
   if (via != HSZ_QUANT) return HSZ_ERR_INVALID_ARG;
   for (int c = 0; c < ncomp; ++c) {
     if (!d_c[c] || !aligned16(d_c[c])) return HSZ_ERR_INVALID_ARG;
+    if (h[c]->flags & HSZ_FLAG_BLOCK_MEAN) return HSZ_ERR_UNSUPPORTED;  // fused windows decode delta streams
     j.v[c] = view_of(d_c[c], h[c]);
   }
   hipStream_t s = (hipStream_t)stream;

@@ -19,6 +19,15 @@
 // length of the OR of |p| over its lanes; its sign word is a ballot; each
 // magnitude is OR-ed into its (at most two) words of the LDS chunk image.
 //
+// Block-mean mode (MEAN; the HSZx decorrelation of Sec. IV): the metadata of
+// a block is its integer mean M = round-half-down(sum q / S_b), p = q - M on
+// every slot.  The block sum comes from a segmented DPP scan of the low and
+// high 16-bit halves of q (neither sum can overflow 32 bits); M is
+// ceil((2 sum - S_b) / (2 S_b)) through one binary64 division, which is exact
+// here: a quotient that is not an integer lies at least 1/128 from one,
+// far beyond the division's rounding.  k_pack reads M back from the
+// metadata section.
+//
 // Quantization is q = floor(x * (1/Delta) + 0.5) in binary64 with no fused
 // multiply-add (compiled with contraction off); the same expression and
 // parameter arithmetic as the CPU reference, so streams are byte-identical.
@@ -216,6 +225,39 @@ __device__ __forceinline__ int block_or_scan(int v) {
   return v;
 }
 
+// Sum over each block's lanes by DPP (rows of 16, then row 0 -> 1 and
+// 2 -> 3; with S = 64 the first half into the second): the block's sum ends
+// up in its last lane.  Exact for |v| sums below 2^31.
+template <int S>
+__device__ __forceinline__ int block_add_scan(int v) {
+  v += dpp<0x111>(v);
+  v += dpp<0x112>(v);
+  v += dpp<0x114>(v);
+  v += dpp<0x118>(v);
+  v += dpp<0x142, 0xa>(v);
+  if (S == 64) v += dpp<0x143, 0xc>(v);
+  return v;
+}
+
+// Integer mean of each block, rounded half down, for the lanes of one step
+// (q of invalid lanes is 0; 'len' is the lane's block length, >= 1).
+template <int S>
+__device__ __forceinline__ int block_mean(int q, int len) {
+  const int lo = block_add_scan<S>(q & 0xffff), hi = block_add_scan<S>(q >> 16);
+  int slo, shi;
+  if (S == 32) {
+    const bool up = lane_id() >= 32;
+    slo = up ? __builtin_amdgcn_readlane(lo, 63) : __builtin_amdgcn_readlane(lo, 31);
+    shi = up ? __builtin_amdgcn_readlane(hi, 63) : __builtin_amdgcn_readlane(hi, 31);
+  } else {
+    slo = __builtin_amdgcn_readlane(lo, 63);
+    shi = __builtin_amdgcn_readlane(hi, 63);
+  }
+  const int64_t sum = (int64_t)shi * 65536 + (int64_t)slo;
+  const double num = 2.0 * (double)sum - (double)len, den = 2.0 * (double)len;
+  return (int)ceil(num / den);
+}
+
 // the value of the lane below (wave shift right by one; lane 0 gets 0).  The
 // empty asm keeps the shifted value in a register of its own: folded into
 // the subtraction that follows (as a v_subrev with a DPP operand) it gave
@@ -236,7 +278,7 @@ constexpr int kAhead = 16;
 // kernel.
 constexpr int kMetaGroups = 4096;
 
-template <typename T, int S>
+template <typename T, int S, bool MEAN>
 __global__ void __launch_bounds__(kThreads) k_quant_meta(const T* __restrict__ x, int64_t n, int64_t nb,
                                                         int64_t nchunks, CompressWs* ws, int32_t* q0s,
                                                         uint8_t* widths, uint32_t* chunk_words,
@@ -279,10 +321,20 @@ __global__ void __launch_bounds__(kThreads) k_quant_meta(const T* __restrict__ x
         const int q = valid ? quantize((double)v[u], inv, over) : 0;
         const uint32_t aq = (uint32_t)(q < 0 ? -q : q);
         maxq = aq > maxq ? aq : maxq;
-        const int qp = from_lane_below(q);
-        const int p = (slot == 0 || !valid) ? 0 : q - qp;
+        int p, meta;
+        if constexpr (MEAN) {
+          const int64_t bstart = e0 + (int64_t)(st + u) * kWave + (l / S) * S;
+          const int64_t rem = n - bstart;
+          const int len = FULL ? S : (int)(rem < S ? (rem > 0 ? rem : 1) : S);
+          meta = block_mean<S>(q, len);
+          p = valid ? q - meta : 0;
+        } else {
+          const int qp = from_lane_below(q);
+          p = (slot == 0 || !valid) ? 0 : q - qp;
+          meta = q;
+        }
         ab[u] = p < 0 ? -p : p;
-        if (slot == 0) mq0[(st + u) * (kWave / S) + l / S] = q;
+        if (slot == 0) mq0[(st + u) * (kWave / S) + l / S] = meta;
       }
 #pragma unroll
       for (int u = 0; u < kAhead; ++u) ab[u] |= dpp<0x111>(ab[u]);
@@ -401,9 +453,10 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_write(const uint32_t* __r
   }
 }
 
-template <typename T, int S>
+template <typename T, int S, bool MEAN>
 __global__ void __launch_bounds__(kThreads) k_pack(const T* __restrict__ x, int64_t n, int64_t nb,
                                                   int64_t nchunks, const CompressWs* ws,
+                                                  const int32_t* __restrict__ metas,
                                                   const uint8_t* __restrict__ widths,
                                                   const uint64_t* __restrict__ chunk_off,
                                                   uint32_t* payload) {
@@ -419,6 +472,7 @@ __global__ void __launch_bounds__(kThreads) k_pack(const T* __restrict__ x, int6
     // word offsets of the chunk's blocks (lane l <-> block 64c + l)
     const int64_t bl = c * kChunkBlocks + l;
     const int wl = bl < nb ? (int)widths[bl] : 0;
+    const int ml = (MEAN && bl < nb) ? metas[bl] : 0;  // block means (block-mean mode)
     const int nwl = block_words<S>(wl);
     const int incl = wave_incl_scan(nwl);
     const int offl = incl - nwl;
@@ -442,9 +496,16 @@ __global__ void __launch_bounds__(kThreads) k_pack(const T* __restrict__ x, int6
         const bool valid = FULL || base + l < n;
         bool ov = false;
         const int q = valid ? quantize((double)v[u], inv, ov) : 0;
-        const int qp = from_lane_below(q);
-        const int p = (slot == 0 || !valid) ? 0 : q - qp;
         const int blk = (st + u) * (kWave / S);  // first block of the step within the chunk
+        int p;
+        if constexpr (MEAN) {
+          int mb = __builtin_amdgcn_readlane(ml, blk);
+          if (S == 32 && l >= 32) mb = __builtin_amdgcn_readlane(ml, blk + 1);
+          p = valid ? q - mb : 0;
+        } else {
+          const int qp = from_lane_below(q);
+          p = (slot == 0 || !valid) ? 0 : q - qp;
+        }
         int w = __builtin_amdgcn_readlane(wl, blk), off = __builtin_amdgcn_readlane(offl, blk);
         if (S == 32 && l >= 32) {
           w = __builtin_amdgcn_readlane(wl, blk + 1);
@@ -490,7 +551,8 @@ __device__ void put_bytes(uint8_t* h, int off, const void* v, int nbytes) {
 
 // Header and zero padding.  One workgroup.
 __global__ void k_header(uint8_t* out, CompressWs* ws, const uint32_t* __restrict__ group_max, int groups,
-                         int dtype, int ndim, int64_t d0, int64_t d1, int64_t d2, int64_t n, int block, int64_t nb,
+                         uint32_t flags, int dtype, int ndim, int64_t d0, int64_t d1, int64_t d2, int64_t n,
+                         int block, int64_t nb,
                          int64_t nchunks, uint64_t off_chunk, uint64_t off_q0, uint64_t off_width,
                          uint64_t off_payload) {
   __shared__ uint8_t h[kHeaderBytes];
@@ -526,7 +588,6 @@ __global__ void k_header(uint8_t* out, CompressWs* ws, const uint32_t* __restric
     put_bytes(h, 72, &ws->vmin, 8);
     put_bytes(h, 80, &ws->vmax, 8);
     put_bytes(h, 88, &ws->max_abs_q, 4);
-    uint32_t flags = 0;
     put_bytes(h, 92, &flags, 4);
     uint64_t v[8] = {(uint64_t)nb, (uint64_t)nchunks, off_chunk, off_q0, off_width, off_payload,
                      ws->total_words, off_payload + 4 * ws->total_words};
@@ -551,7 +612,7 @@ uint64_t ws_group_max_off(const Layout& L) {
   return align_up(ws_range_sums_off(L) + 8 * ranges, 256);
 }
 
-template <typename T, int S>
+template <typename T, int S, bool MEAN>
 hipError_t run(const CompressArgs& a, hipStream_t s) {
   const Layout& L = a.lay;
   CompressWs* ws = (CompressWs*)a.ws;
@@ -566,18 +627,19 @@ hipError_t run(const CompressArgs& a, hipStream_t s) {
   const int64_t cg = (L.nchunks + 3) / 4;
   const int grid = (int)(cg < kMetaGroups ? cg : kMetaGroups);
   uint32_t* group_max = (uint32_t*)(a.ws + ws_group_max_off(L));
-  hipLaunchKernelGGL((k_quant_meta<T, S>), dim3(grid), dim3(kThreads), 0, s, x, L.n, L.nb, L.nchunks, ws,
+  hipLaunchKernelGGL((k_quant_meta<T, S, MEAN>), dim3(grid), dim3(kThreads), 0, s, x, L.n, L.nb, L.nchunks, ws,
                      (int32_t*)(out + L.off_q0), out + L.off_width, chunk_words, group_max);
   const unsigned ranges = (unsigned)((L.nchunks + kScanRange - 1) / kScanRange);
   uint64_t* range_sums = (uint64_t*)(a.ws + ws_range_sums_off(L));
   hipLaunchKernelGGL(k_scan_sums, dim3(ranges), dim3(kScanThreads), 0, s, chunk_words, L.nchunks, range_sums);
   hipLaunchKernelGGL(k_scan_write, dim3(ranges), dim3(kScanThreads), 0, s, chunk_words, L.nchunks, range_sums,
                      (uint64_t*)(out + L.off_chunk), ws, L.off_payload, a.cap);
-  hipLaunchKernelGGL((k_pack<T, S>), dim3(grid), dim3(kThreads), 0, s, x, L.n, L.nb, L.nchunks, ws,
-                     (const uint8_t*)(out + L.off_width), (const uint64_t*)(out + L.off_chunk),
+  hipLaunchKernelGGL((k_pack<T, S, MEAN>), dim3(grid), dim3(kThreads), 0, s, x, L.n, L.nb, L.nchunks, ws,
+                     (const int32_t*)(out + L.off_q0), (const uint8_t*)(out + L.off_width),
+                     (const uint64_t*)(out + L.off_chunk),
                      (uint32_t*)(out + L.off_payload));
   hipLaunchKernelGGL(k_header, dim3(1), dim3(kHeaderBytes), 0, s, out, ws, (const uint32_t*)group_max, grid,
-                     a.dtype, a.ndim, a.dims[0], a.dims[1], a.dims[2], L.n, L.block, L.nb, L.nchunks, L.off_chunk,
+                     MEAN ? 1u : 0u, a.dtype, a.ndim, a.dims[0], a.dims[1], a.dims[2], L.n, L.block, L.nb, L.nchunks, L.off_chunk,
                      L.off_q0, L.off_width, L.off_payload);
   return hipGetLastError();
 }
@@ -599,10 +661,15 @@ Layout make_layout(int64_t n, int block) {
 
 uint64_t compress_workspace_bytes(const Layout& lay) { return ws_group_max_off(lay) + 4 * (uint64_t)kMetaGroups; }
 
-hipError_t launch_compress(const CompressArgs& a, hipStream_t s) {
+template <bool MEAN>
+hipError_t compress_mode(const CompressArgs& a, hipStream_t s) {
   if (a.dtype == 1)
-    return a.lay.block == 32 ? run<float, 32>(a, s) : run<float, 64>(a, s);
-  return a.lay.block == 32 ? run<double, 32>(a, s) : run<double, 64>(a, s);
+    return a.lay.block == 32 ? run<float, 32, MEAN>(a, s) : run<float, 64, MEAN>(a, s);
+  return a.lay.block == 32 ? run<double, 32, MEAN>(a, s) : run<double, 64, MEAN>(a, s);
+}
+
+hipError_t launch_compress(const CompressArgs& a, hipStream_t s) {
+  return (a.flags & 1u) ? compress_mode<true>(a, s) : compress_mode<false>(a, s);
 }
 
 }  // namespace hsz

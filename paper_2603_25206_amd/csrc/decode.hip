@@ -6,6 +6,7 @@
 // whole 16-byte vectors, so every lane stores one full 128- or 256-byte
 // segment of the output.
 //   stage 2 (D_p): p[n] then q0[nb]      stage 3 (D_q): q[n]
+//   (block-mean streams: q0 holds the block means and q = M + p)
 //   stage 4 (D_f): (dtype)(q * Delta)    stage 1 (D_m): q0[nb] (a copy)
 #include "hsz_device.hpp"
 #include "hsz_launch.hpp"
@@ -41,7 +42,7 @@ __device__ __forceinline__ void store_block(T* dst, const T (&v)[S], int len) {
 // values to row l of a (64 x (S+1))-word tile (the +1 keeps the writes
 // conflict-free), then every lane reads four consecutive outputs of the
 // chunk and the wave stores 1 KB of contiguous memory per instruction.
-template <int S, int STAGE, typename T>
+template <int S, int STAGE, typename T, bool MEAN>
 __global__ void __launch_bounds__(kThreads) k_decode(StreamView v, int kmax, int wave_words, T* __restrict__ out,
                                                     int32_t* __restrict__ out_q0, int* status) {
   extern __shared__ uint32_t smem[];
@@ -56,7 +57,7 @@ __global__ void __launch_bounds__(kThreads) k_decode(StreamView v, int kmax, int
     stage_chunk<S>(v.width, v.q0, v.chunk_off, v.payload, v.payload_words, v.n, v.nb, c, tile, kmax, lb,
                    status);
     T vals[S];
-    decode_lane_block<S>(tile + l, lb.w, lb.q0, [&](int j, int p, int q) {
+    decode_lane_block<S, kWave, MEAN>(tile + l, lb.w, lb.q0, [&](int j, int p, int q) {
       if constexpr (STAGE == 2) vals[j] = p;
       else if constexpr (STAGE == 3) vals[j] = q;
       else vals[j] = (T)dequant64(q, quantum);
@@ -154,8 +155,12 @@ hipError_t run(const StreamView& v, void* out, int* status, hipStream_t s) {
   const int64_t groups = (v.nchunks + kWavesPerGroup - 1) / kWavesPerGroup;
   const int grid = (int)(groups < 8192 ? groups : 8192);
   int32_t* q0out = (STAGE == 2) ? (int32_t*)out + v.n : nullptr;
-  hipLaunchKernelGGL((k_decode<S, STAGE, T>), dim3(grid), dim3(kThreads), lds, s, v, kmax, wave_words, (T*)out,
-                     q0out, status);
+  if (v.flags & 1u)
+    hipLaunchKernelGGL((k_decode<S, STAGE, T, true>), dim3(grid), dim3(kThreads), lds, s, v, kmax, wave_words,
+                       (T*)out, q0out, status);
+  else
+    hipLaunchKernelGGL((k_decode<S, STAGE, T, false>), dim3(grid), dim3(kThreads), lds, s, v, kmax, wave_words,
+                       (T*)out, q0out, status);
   return hipGetLastError();
 }
 

@@ -172,8 +172,10 @@ struct StreamViewG {
   int dtype;
   double quantum;
   uint32_t max_abs_q;
+  uint32_t flags;
 };
 static_assert(sizeof(StreamViewG) == sizeof(StreamView), "mirror layout");
+static_assert(offsetof(StreamViewG, flags) == offsetof(StreamView, flags), "mirror layout");
 static_assert(offsetof(StreamViewG, payload_words) == offsetof(StreamView, payload_words), "mirror layout");
 static_assert(offsetof(StreamViewG, max_abs_q) == offsetof(StreamView, max_abs_q), "mirror layout");
 
@@ -222,6 +224,7 @@ __device__ __forceinline__ StreamView view_of(const StreamViewG& g) {
   v.dtype = g.dtype;
   v.quantum = g.quantum;
   v.max_abs_q = g.max_abs_q;
+  v.flags = g.flags;
   return v;
 }
 
@@ -441,7 +444,8 @@ __device__ __forceinline__ int stage_block(const uint8_t* __restrict__ width, co
 // q the recorrelated quantization integer (stage 3).  Slot 0 has p = 0 and
 // q = q0.  col = tile + lane (column base); rows hold sign word(s) first,
 // then magnitude words.
-template <int S, int STRIDE = kWave, class Sink>
+// MEAN: a block-mean stream (q0 holds the block mean M): q_j = M + p_j.
+template <int S, int STRIDE = kWave, bool MEAN = false, class Sink>
 __device__ __forceinline__ void decode_lane_block(const uint32_t* col, int w, int q0, Sink&& sink) {
   const uint32_t sg0 = w ? col[0] : 0u;
   const uint32_t sg1 = (S == 64 && w) ? col[STRIDE] : 0u;
@@ -476,7 +480,8 @@ __device__ __forceinline__ void decode_lane_block(const uint32_t* col, int w, in
       // ((m ^ sg) + q) - sg so that a sink using only q costs one xor-add
       const uint32_t x = m ^ (uint32_t)sg;
       const int p = (int)x - sg;
-      q = (int)(x + (uint32_t)q) - sg;
+      if constexpr (MEAN) q = (int)(x + (uint32_t)q0) - sg;
+      else q = (int)(x + (uint32_t)q) - sg;
       sink(j, p, q);
     }
   }

@@ -39,6 +39,7 @@ struct StreamView {
   int dtype;
   double quantum;
   uint32_t max_abs_q;
+  uint32_t flags;  // bit 0: block-mean decorrelation (metadata = block means)
 };
 
 // ---- compression -------------------------------------------------------------
@@ -49,6 +50,7 @@ struct CompressArgs {
   int64_t dims[3];  // 3D view
   double eb;
   int eb_is_rel;
+  uint32_t flags;  // bit 0: block-mean decorrelation
   Layout lay;
   uint8_t* out;
   uint64_t cap;

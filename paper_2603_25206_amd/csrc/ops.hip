@@ -288,6 +288,38 @@ __global__ void __launch_bounds__(kThreads) k_stats_delta(const int32_t* __restr
   store_int_partial(acc, parts);
 }
 
+// ---- block-mean streams (HSZx) ---------------------------------------------------------
+// Stage-2 buffer (p[n], M[nb]) of a block-mean stream: q = M_b + p over the
+// box rows (the D_p mean of Sec. V-A: sum_b (sum p + M_b S_b)).
+template <int S, int OP>
+__global__ void __launch_bounds__(kThreads) k_stats_delta_mean(const int32_t* __restrict__ p,
+                                                              const int32_t* __restrict__ ms, Rows rows,
+                                                              Partial* parts) {
+  IntAcc acc;
+  const int64_t segs = (rows.len + kSeg - 1) / kSeg;
+  const int64_t items = rows.count() * segs;
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t r = it / segs, sg = it % segs;
+    const int64_t lo = sg * kSeg, hi = min(rows.len, lo + kSeg);
+    const int64_t f0 = rows.start(r);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) acc.add(ms[(f0 + i) / S] + p[f0 + i], OP == 2);
+  }
+  store_int_partial(acc, parts);
+}
+
+// Eq. (mean_m): the mean from the metadata alone, sum_b M_b S_b (S_b = S but
+// for a shorter last block), as an exact integer partial per workgroup.
+__global__ void __launch_bounds__(kThreads) k_meta_mean(const int32_t* __restrict__ ms, int64_t n, int64_t nb,
+                                                       int S, Partial* parts) {
+  IntAcc acc;
+  for (int64_t b = blockIdx.x * (int64_t)kThreads + threadIdx.x; b < nb; b += (int64_t)gridDim.x * kThreads) {
+    const int64_t sb = min((int64_t)S, n - b * S);
+    acc.s1 += (int64_t)ms[b] * sb;
+    acc.cnt += sb;
+  }
+  store_int_partial(acc, parts);
+}
+
 // ---- whole blocks of streams with small integers -----------------------------------
 // Exact sums over one whole block (slots 0 .. S-1 all counted) when the
 // stream's max|q| is below small_q_limit<MODE>(): the block's terms are
@@ -300,17 +332,21 @@ __global__ void __launch_bounds__(kThreads) k_stats_delta(const int32_t* __restr
 template <int MODE>
 __host__ __device__ constexpr uint32_t small_q_limit() { return MODE == 2 ? 8192u : (1u << 22); }
 
-template <int S, int MODE>
+// MEAN: a block-mean stream (q0 = M): the stage-2 block sum is S M + sum p.
+template <int S, int MODE, bool MEAN = false>
 __device__ __forceinline__ void whole_block_sums(const uint32_t* col, int w, int q0, IntAcc& a) {
   int s1 = 0;
   uint32_t s2 = 0;
-  if constexpr (MODE == 0) {
+  if constexpr (MODE == 0 && MEAN) {
+    decode_lane_block<S, kWave, true>(col, w, q0, [&](int, int p, int) { s1 += p; });
+    a.s1 += (int64_t)S * q0 + s1;
+  } else if constexpr (MODE == 0) {
     decode_lane_block<S>(col, w, q0, [&](int j, int p, int) {
       if (j >= 1) s1 = __mul24(S - j, p) + s1;
     });
     a.s1 += (int64_t)S * q0 + s1;
   } else {
-    decode_lane_block<S>(col, w, q0, [&](int, int, int q) {
+    decode_lane_block<S, kWave, MEAN>(col, w, q0, [&](int, int, int q) {
       s1 += q;
       if constexpr (MODE == 2) s2 = (uint32_t)__mul24(q, q) + s2;
     });
@@ -323,7 +359,7 @@ __device__ __forceinline__ void whole_block_sums(const uint32_t* col, int w, int
 // ---- fused statistics straight from the compressed stream ------------------------
 // VIA: 2 (decorrelated), 3 (quantized), 4 (floats).  WHOLE: the items are
 // every block in order (chunk-aligned waves use the chunk scan).
-template <int S, int VIA, int OP, typename T, bool WHOLE>
+template <int S, int VIA, int OP, typename T, bool WHOLE, bool MEAN>
 __global__ void __launch_bounds__(kThreads) k_stats_fused(StreamView v, Segs<S> segs, int kmax, const double* Kp,
                                                          Partial* parts, int* status) {
   extern __shared__ uint32_t smem[];
@@ -343,11 +379,19 @@ __global__ void __launch_bounds__(kThreads) k_stats_fused(StreamView v, Segs<S> 
   auto process = [&](int w, int q0, int a, int z) {
     if constexpr (VIA != 4) {
       if (small && a == 0 && z == S - 1) {
-        whole_block_sums<S, kMode>(tile + l, w, q0, acc);
+        whole_block_sums<S, kMode, MEAN>(tile + l, w, q0, acc);
         return;
       }
     }
-    if constexpr (VIA == 2 && OP == 1) {
+    if constexpr (VIA == 2 && OP == 1 && MEAN) {
+      // block-mean stream: (z - a + 1) M + the sum of its deltas
+      int64_t s = (int64_t)(z - a + 1) * q0;
+      decode_lane_block<S, kWave, true>(tile + l, w, q0, [&](int j, int p, int) {
+        if (j >= a && j <= z) s += p;
+      });
+      acc.s1 += s;
+      acc.cnt += z - a + 1;
+    } else if constexpr (VIA == 2 && OP == 1) {
       // weighted block sum, no recorrelation
       int64_t s = (int64_t)(z - a + 1) * q0;
       decode_lane_block<S>(tile + l, w, q0, [&](int j, int p, int) {
@@ -356,7 +400,7 @@ __global__ void __launch_bounds__(kThreads) k_stats_fused(StreamView v, Segs<S> 
       acc.s1 += s;
       acc.cnt += z - a + 1;
     } else if constexpr (VIA == 4) {
-      decode_lane_block<S>(tile + l, w, q0, [&](int j, int, int q) {
+      decode_lane_block<S, kWave, MEAN>(tile + l, w, q0, [&](int j, int, int q) {
         if (j >= a && j <= z) {
           const double e = (double)(T)dequant64(q, quantum) - K;
           f1 += e;
@@ -365,7 +409,7 @@ __global__ void __launch_bounds__(kThreads) k_stats_fused(StreamView v, Segs<S> 
         }
       });
     } else {
-      decode_lane_block<S>(tile + l, w, q0, [&](int j, int, int q) {
+      decode_lane_block<S, kWave, MEAN>(tile + l, w, q0, [&](int j, int, int q) {
         if (j >= a && j <= z) acc.add(q, OP == 2);
       });
     }
@@ -647,7 +691,7 @@ int kmax_for(const StreamView& v) {
 
 // One wave: decode the value at flat index f (the shift of the binary64
 // float-route sums) into *K.
-template <int S, typename T>
+template <int S, typename T, bool MEAN>
 __global__ void k_first_value(StreamView v, int64_t f, int kmax, double* K, int* status) {
   extern __shared__ uint32_t smem[];
   const int64_t b = f / S;
@@ -656,30 +700,37 @@ __global__ void k_first_value(StreamView v, int64_t f, int kmax, double* K, int*
   const int w = lane_id() == 0 ? stage_block<S, kWave>(v.width, v.q0, v.chunk_off, v.payload, v.payload_words, v.nb, b, smem, kmax, q0, status) : 0;
   if (lane_id() != 0) return;
   int qv = 0;
-  decode_lane_block<S>(smem, w, q0, [&](int j, int, int q) {
+  decode_lane_block<S, kWave, MEAN>(smem, w, q0, [&](int j, int, int q) {
     if (j == slot) qv = q;
   });
   *K = (double)(T)dequant64(qv, v.quantum);
 }
 
-template <int S, int VIA, int OP, typename T>
-hipError_t run_fused_stats(const StreamView& v, const Rows& rows, bool whole, double* K, Partial* parts, int& grid,
-                           int* status, hipStream_t s) {
+template <int S, int VIA, int OP, typename T, bool MEAN>
+hipError_t run_fused_stats_m(const StreamView& v, const Rows& rows, bool whole, double* K, Partial* parts, int& grid,
+                             int* status, hipStream_t s) {
   const int kmax = kmax_for(v);
   const size_t lds = (size_t)kWavesPerGroup * (kmax + 1) * kWave * sizeof(uint32_t);
   Segs<S> segs = make_segs<S>(rows);
   if (VIA == 4)
-    hipLaunchKernelGGL((k_first_value<S, T>), dim3(1), dim3(kWave), (kmax + 1) * kWave * sizeof(uint32_t), s, v,
+    hipLaunchKernelGGL((k_first_value<S, T, MEAN>), dim3(1), dim3(kWave), (kmax + 1) * kWave * sizeof(uint32_t), s, v,
                        rows.base, kmax, K, status);
   const int64_t items = whole ? v.nchunks * kChunkBlocks : segs.count();
   grid = grid_for(items, kThreads);
   if (whole)
-    hipLaunchKernelGGL((k_stats_fused<S, VIA, OP, T, true>), dim3(grid), dim3(kThreads), lds, s, v, segs, kmax, K,
-                       parts, status);
+    hipLaunchKernelGGL((k_stats_fused<S, VIA, OP, T, true, MEAN>), dim3(grid), dim3(kThreads), lds, s, v, segs,
+                       kmax, K, parts, status);
   else
-    hipLaunchKernelGGL((k_stats_fused<S, VIA, OP, T, false>), dim3(grid), dim3(kThreads), lds, s, v, segs, kmax,
-                       K, parts, status);
+    hipLaunchKernelGGL((k_stats_fused<S, VIA, OP, T, false, MEAN>), dim3(grid), dim3(kThreads), lds, s, v, segs,
+                       kmax, K, parts, status);
   return hipGetLastError();
+}
+
+template <int S, int VIA, int OP, typename T>
+hipError_t run_fused_stats(const StreamView& v, const Rows& rows, bool whole, double* K, Partial* parts, int& grid,
+                           int* status, hipStream_t s) {
+  return (v.flags & 1u) ? run_fused_stats_m<S, VIA, OP, T, true>(v, rows, whole, K, parts, grid, status, s)
+                        : run_fused_stats_m<S, VIA, OP, T, false>(v, rows, whole, K, parts, grid, status, s);
 }
 
 template <int S, int OP>
@@ -767,6 +818,22 @@ hipError_t launch_stats_stage(const void* buf, int stage, const StreamView& v, i
       hipLaunchKernelGGL(k_stats_f<float>, dim3(grid), dim3(kThreads), 0, s, (const float*)buf, rows, parts);
     else
       hipLaunchKernelGGL(k_stats_f<double>, dim3(grid), dim3(kThreads), 0, s, (const double*)buf, rows, parts);
+  } else if (stage == 1) {
+    // metadata (block means) of a block-mean stream, whole field (checked by the caller)
+    grid = grid_for(v.nb, kThreads);
+    hipLaunchKernelGGL(k_meta_mean, dim3(grid), dim3(kThreads), 0, s, (const int32_t*)buf, v.n, v.nb, v.block, parts);
+  } else if (stage == 2 && (v.flags & 1u)) {
+    const int32_t* p = (const int32_t*)buf;
+    const int32_t* ms = p + v.n;
+    grid = grid_for(rows.count() * ((rows.len + kSeg - 1) / kSeg), 1);
+    if (v.block == 32 && op == 1)
+      hipLaunchKernelGGL((k_stats_delta_mean<32, 1>), dim3(grid), dim3(kThreads), 0, s, p, ms, rows, parts);
+    else if (v.block == 32)
+      hipLaunchKernelGGL((k_stats_delta_mean<32, 2>), dim3(grid), dim3(kThreads), 0, s, p, ms, rows, parts);
+    else if (op == 1)
+      hipLaunchKernelGGL((k_stats_delta_mean<64, 1>), dim3(grid), dim3(kThreads), 0, s, p, ms, rows, parts);
+    else
+      hipLaunchKernelGGL((k_stats_delta_mean<64, 2>), dim3(grid), dim3(kThreads), 0, s, p, ms, rows, parts);
   } else if (stage == 2) {
     const int32_t* p = (const int32_t*)buf;
     const int32_t* q0 = p + v.n;
@@ -811,6 +878,15 @@ hipError_t launch_stats_fused(const StreamView& v, int via, int op, const OpTarg
   double* K = (double*)(ws + 8);
   int grid = 1;
   hipError_t e;
+  if (via == 1) {  // the stream's own metadata section (block means)
+    grid = grid_for(v.nb, kThreads);
+    hipLaunchKernelGGL(k_meta_mean, dim3(grid), dim3(kThreads), 0, s, v.q0, v.n, v.nb, v.block, parts);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, parts, grid, op, 0, v.quantum,
+                       (StatsOut*)result);
+    return hipGetLastError();
+  }
   if (v.block == 32)
     e = op == 1 ? fused_by_via<32, 1>(v, via, rows, whole, K, parts, grid, status, s)
                 : fused_by_via<32, 2>(v, via, rows, whole, K, parts, grid, status, s);

@@ -27,6 +27,7 @@ ERR_INVALID_ARG, ERR_BAD_STREAM, ERR_UNSUPPORTED, ERR_RANGE, ERR_EB, ERR_NONFINI
 F32, F64 = 1, 2
 META, DELTA, QUANT, FLOAT = 1, 2, 3, 4
 MEAN, VAR, DERIV, GRADMAG, LAPLACIAN, DIVERGENCE, CURL = 1, 2, 3, 4, 5, 6, 7
+FLAG_BLOCK_MEAN = 1  # header flag: block-mean decorrelation (HSZx)
 HEADER_BYTES = 256
 
 _OPS = {"mean": MEAN, "var": VAR, "deriv": DERIV, "gradmag": GRADMAG, "laplacian": LAPLACIAN,
@@ -83,7 +84,7 @@ class Tuning(ctypes.Structure):
 
 EXPORTS = (
     "hsz_strerror", "hsz_version", "hsz_last_hip_error", "hsz_read_status", "hsz_compress_bound",
-    "hsz_compress_workspace", "hsz_compress", "hsz_read_header", "hsz_stage_bytes",
+    "hsz_compress_workspace", "hsz_compress", "hsz_compress_flags", "hsz_read_header", "hsz_stage_bytes",
     "hsz_decompress_to_stage", "hsz_op_workspace", "hsz_op_on_stage", "hsz_op_fused",
     "hsz_batch_workspace", "hsz_batch_run", "hsz_plan_create", "hsz_plan_update", "hsz_plan_launch",
     "hsz_plan_destroy", "hsz_block_index_bytes", "hsz_block_index", "hsz_vector_workspace",
@@ -111,6 +112,7 @@ def load(path: str = LIB_PATH):
         "hsz_compress_bound": (i32, [i32, i32, pi64, i32, pu64]),
         "hsz_compress_workspace": (i32, [i32, pi64, i32, pu64]),
         "hsz_compress": (i32, [P, i32, i32, pi64, dbl, i32, i32, P, u64, P, u64, P]),
+        "hsz_compress_flags": (i32, [P, i32, i32, pi64, dbl, i32, i32, ctypes.c_uint32, P, u64, P, u64, P]),
         "hsz_read_header": (i32, [P, u64, u64, ctypes.POINTER(Header)]),
         "hsz_stage_bytes": (i32, [ctypes.POINTER(Header), i32, pu64]),
         "hsz_decompress_to_stage": (i32, [P, ctypes.POINTER(Header), i32, P, u64, P, u64, P]),
@@ -255,8 +257,9 @@ def compress_bound(shape, dtype: int, block: int) -> int:
 
 
 def compress(x: torch.Tensor, eb: float, rel: bool = True, block: int = 32, stream=None,
-             out: torch.Tensor | None = None, check: bool = True) -> Compressed:
-    """c = C(x, eb) on the GPU.  x: contiguous float32/float64 CUDA tensor."""
+             out: torch.Tensor | None = None, check: bool = True, mean_dec: bool = False) -> Compressed:
+    """c = C(x, eb) on the GPU.  x: contiguous float32/float64 CUDA tensor.
+    mean_dec selects the block-mean decorrelation (HSZx) instead of deltas."""
     lib = load()
     if not x.is_cuda or not x.is_contiguous():
         raise ValueError("x must be a contiguous GPU tensor")
@@ -272,9 +275,10 @@ def compress(x: torch.Tensor, eb: float, rel: bool = True, block: int = 32, stre
     _check(lib.hsz_compress_workspace(len(shape), dims, block, ctypes.byref(wsb)), "compress_workspace")
     ws = workspace(wsb.value, x.device, key="compress")
     s = _stream(stream)
-    _check(lib.hsz_compress(ctypes.c_void_p(x.data_ptr()), dt, len(shape), dims, float(eb), int(rel), block,
-                            ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.c_void_p(ws.data_ptr()),
-                            ws.numel(), ctypes.c_void_p(s)), "compress")
+    _check(lib.hsz_compress_flags(ctypes.c_void_p(x.data_ptr()), dt, len(shape), dims, float(eb), int(rel),
+                                  block, FLAG_BLOCK_MEAN if mean_dec else 0, ctypes.c_void_p(out.data_ptr()),
+                                  out.numel(), ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(s)),
+           "compress")
     if not check:
         return Compressed(out, Header())
     st = read_status(ws, stream)

@@ -1,0 +1,162 @@
+"""GPU parity for block-mean (HSZx) streams against the oracle: compressed
+bytes, every decompression stage, the mean from the metadata (Eq. (mean_m)),
+mean and variance through D_p, D_q and D_f (fused and materialised), the
+gradient on the materialised quantized stage, and the routes this mode does
+not take.
+
+Bars: bytes, stages and integer sums bit-exact; means and variances 1e-12
+relative (the mean against max(|mean|, mean |d'|)); the metadata mean
+equals the oracle's to 1e-15 relative and lies within eps of the mean of the
+decompressed field (the bias bound of the error analysis).
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU visible", allow_module_level=True)
+
+from paper_2603_25206_amd import hsz, synth  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+CASES = [
+    ((64, 64, 64), np.float32, 1e-3, 32),
+    ((37, 41, 29), np.float32, 1e-4, 32),  # ragged: n % 32 != 0
+    ((37, 41, 29), np.float32, 1e-2, 64),
+    ((181, 367), np.float64, 1e-6, 32),
+    ((100003,), np.float32, 1e-3, 32),
+    ((3, 5, 7), np.float32, 1e-3, 32),  # one partial block
+]
+
+
+def case_id(c):
+    shape, dt, rel, S = c
+    return f"{'x'.join(map(str, shape))}-{np.dtype(dt).name}-{rel:g}-S{S}"
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[case_id(c) for c in CASES])
+def mcase(request):
+    shape, dt, rel, S = request.param
+    say(f"[case] block-mean {case_id(request.param)}")
+    f = synth.gaussian_mixture(shape, 6, (2.0, max(3.0, min(shape) / 3.0)), seed=sum(shape) + 3 * S)
+    rng = np.random.default_rng(sum(shape) + 1)
+    x = np.ascontiguousarray((f * np.exp(rng.normal(0.0, 0.05, size=shape))).astype(dt))
+    ref = oracle.compress(x, rel, rel=True, block=S, mean_dec=True)
+    c = hsz.compress(torch.from_numpy(x).to(DEV), rel, rel=True, block=S, mean_dec=True)
+    torch.cuda.synchronize()
+    h = oracle.read_header(ref)
+    q = oracle.decompress(ref, oracle.QUANT)
+    return dict(x=x, ref=ref, c=c, h=h, q=q, xh64=oracle.dequantize64(q, h.quantum),
+                x_stored=oracle.decompress(ref, oracle.FLOAT).astype(np.float64), shape=shape, S=S)
+
+
+def test_bytes_and_stages_bit_exact(mcase):
+    c, ref = mcase["c"], mcase["ref"]
+    assert c.header.flags == hsz.FLAG_BLOCK_MEAN
+    assert np.array_equal(c.to_bytes(), ref)
+    for cc in (c, hsz.from_bytes(ref, DEV)):
+        assert np.array_equal(hsz.decompress_to_stage(cc, hsz.META, check=True).cpu().numpy(),
+                              oracle.decompress(ref, oracle.META))
+        p, m = hsz.decompress_to_stage(cc, hsz.DELTA, check=True)
+        op_, om = oracle.decompress(ref, oracle.DELTA)
+        assert np.array_equal(p.cpu().numpy(), op_) and np.array_equal(m.cpu().numpy(), om)
+        assert np.array_equal(hsz.decompress_to_stage(cc, hsz.QUANT, check=True).cpu().numpy(), mcase["q"])
+        f = hsz.decompress_to_stage(cc, hsz.FLOAT, check=True).cpu().numpy()
+        assert np.array_equal(f.view(np.uint8), oracle.decompress(ref, oracle.FLOAT).view(np.uint8))
+
+
+def test_mean_from_metadata(mcase):
+    c, h = mcase["c"], mcase["h"]
+    msum, mmean = oracle.meta_mean(mcase["ref"])
+    meta = hsz.decompress_to_stage(c, hsz.META)
+    for got in (hsz.op_fused(c, hsz.META, "mean"), hsz.op_on_stage(meta, c.header, hsz.META, "mean")):
+        assert got["s1"] == msum and got["n"] == h.n
+        assert got["mean"] == pytest.approx(mmean, rel=1e-15, abs=1e-300)
+        assert abs(got["mean"] - oracle.mean(mcase["xh64"])) <= h.eb_abs  # bias bound of Eq. (mean_m)
+    for bad in (lambda: hsz.op_fused(c, hsz.META, "var"),
+                lambda: hsz.op_fused(c, hsz.META, "mean", box=tuple(zip(*[(0, s) for s in mcase["shape"][:-1]]
+                                                                      + [(0, mcase["shape"][-1] - 1)])))):
+        with pytest.raises(hsz.HszError) as e:
+            bad()
+        assert e.value.code == hsz.ERR_UNSUPPORTED
+
+
+def _boxes(shape, seed):
+    rng = np.random.default_rng(seed)
+    out = [None]
+    for _ in range(2):
+        lo, hi = [], []
+        for s in shape:
+            a = int(rng.integers(0, s))
+            lo.append(a)
+            hi.append(int(rng.integers(a + 1, s + 1)))
+        out.append((tuple(lo), tuple(hi)))
+    return out
+
+
+@pytest.mark.parametrize("op", ["mean", "var"])
+def test_stats_all_routes(mcase, op):
+    c = mcase["c"]
+    bufs = {st: hsz.decompress_to_stage(c, st) for st in (hsz.DELTA, hsz.QUANT, hsz.FLOAT)}
+    for box in _boxes(mcase["shape"], seed=len(mcase["shape"]) + mcase["S"]):
+        n, s1, s2 = oracle.int_sums(mcase["q"], box)
+        if n < 2 and op == "var":
+            continue
+        m64, v64 = oracle.mean(mcase["xh64"], box), oracle.var(mcase["xh64"], box)
+        ms, vs = oracle.mean(mcase["x_stored"], box), oracle.var(mcase["x_stored"], box)
+        sl = tuple(slice(l, hh) for l, hh in zip(*box)) if box else tuple(slice(None) for _ in mcase["shape"])
+        scale = max(abs(m64), float(np.mean(np.abs(mcase["xh64"][sl]))))
+        for st in (hsz.DELTA, hsz.QUANT, hsz.FLOAT):
+            for got in (hsz.op_fused(c, st, op, box=box), hsz.op_on_stage(bufs[st], c.header, st, op, box=box)):
+                wm, wv = (m64, v64) if st != hsz.FLOAT else (ms, vs)
+                assert got["mean"] == pytest.approx(wm, rel=0, abs=1e-12 * scale)
+                if op == "var":
+                    assert got["var"] == pytest.approx(wv, rel=1e-12, abs=0)
+                if st != hsz.FLOAT:
+                    assert got["n"] == n and got["s1"] == s1
+                    if op == "var":
+                        assert got["s2"] == s2
+
+
+def test_gradient_on_materialised_stage_and_refusals(mcase):
+    c = mcase["c"]
+    qbuf = hsz.decompress_to_stage(c, hsz.QUANT)
+    want = oracle.gradmag(mcase["xh64"])
+    got = hsz.op_on_stage(qbuf, c.header, hsz.QUANT, "gradmag").cpu().numpy().astype(np.float64)
+    if mcase["x"].dtype == np.float32:
+        tol = 1e-6 * np.abs(want)
+    else:
+        tol = 1e-12 * np.abs(want) + 4 * 2.0 ** -53 * float(np.max(np.abs(mcase["xh64"])))
+    assert np.all(np.abs(got - want) <= tol)
+    nd = len(mcase["shape"])
+    for bad in (lambda: hsz.op_fused(c, hsz.QUANT, "gradmag"),
+                lambda: hsz.op_fused(c, hsz.QUANT, "laplacian"),
+                lambda: hsz.op_on_stage(hsz.decompress_to_stage(c, hsz.DELTA), c.header, hsz.DELTA, "deriv",
+                                        axis=nd - 1),
+                lambda: hsz.Plan([hsz.Job(c, "mean", hsz.QUANT)])):
+        with pytest.raises(hsz.HszError) as e:
+            bad()
+        assert e.value.code == hsz.ERR_UNSUPPORTED
+
+
+def test_metadata_stage_refused_for_delta_streams():
+    x = np.ascontiguousarray(np.linspace(0, 1, 5000, dtype=np.float32))
+    c = hsz.compress(torch.from_numpy(x).to(DEV), 1e-3)
+    with pytest.raises(hsz.HszError) as e:
+        hsz.op_fused(c, hsz.META, "mean")
+    assert e.value.code == hsz.ERR_UNSUPPORTED
