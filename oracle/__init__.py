@@ -89,6 +89,8 @@ def _load():
     lib.or_compress.argtypes = [P, u32, u32, P, dbl, i32, u32, u32, P, u64, P]
     lib.or_meta_mean.restype = i32
     lib.or_meta_mean.argtypes = [P, u64, P, P]
+    lib.or_var_mt.restype = i32
+    lib.or_var_mt.argtypes = [P, u64, P, P, P, P, P, P]
     lib.or_read_header.restype = i32
     lib.or_read_header.argtypes = [P, u64, P]
     lib.or_stage_bytes.restype = u64
@@ -229,6 +231,18 @@ def meta_mean(buf: np.ndarray):
     ms, mean = ctypes.c_int64(), ctypes.c_double()
     _check(_load().or_meta_mean(_ptr(buf), buf.size, ctypes.byref(ms), ctypes.byref(mean)), "meta_mean")
     return ms.value, mean.value
+
+
+def var_mt(buf: np.ndarray) -> dict:
+    """Standard deviation on D_p of a block-mean stream (Sec. V-A, about
+    the integer metadata mean mu~): -> {n, msum, mu_t, s2 (exact
+    sum (p + M_b - mu~)^2 as int), var}."""
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    n, ms, mt, hi = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    lo, var = ctypes.c_uint64(), ctypes.c_double()
+    _check(_load().or_var_mt(_ptr(buf), buf.size, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(mt),
+                             ctypes.byref(lo), ctypes.byref(hi), ctypes.byref(var)), "var_mt")
+    return {"n": n.value, "msum": ms.value, "mu_t": mt.value, "s2": (hi.value << 64) + lo.value, "var": var.value}
 
 
 def compress(x: np.ndarray, eb: float, rel: bool = True, block: int = 32, mean_dec: bool = False) -> np.ndarray:

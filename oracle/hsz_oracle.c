@@ -59,6 +59,11 @@
  *      analysis of the metadata mean both hold; p_i = q_i - M_b on every
  *      slot (none is forced to 0); q_i = M_b + p_i.  Padding slots of the
  *      last block (past n) hold p = 0 as in the delta mode.
+ *   R11 the integer mean of the standard deviation on D_p for HSZx
+ *      (Sec. V-A), mu~ = round(sum_b M_b S_b / N), rounds halves down like
+ *      the block means of R10 (the paper's example, 16 / 8 = 2, has no
+ *      tie); the spread is taken over the whole field only, since mu~ comes
+ *      from the metadata of every block.
  *   R8 the Laplacian of Eq. (laplacian) on n axes is the sum over the axes
  *      of d_{-1} + d_{+1} - 2 d (unit spacing); at the two ends of an axis
  *      the missing neighbour is the end value itself (the field mirrored
@@ -748,6 +753,49 @@ int or_meta_mean(const uint8_t *buf, uint64_t len, int64_t *msum, double *mean) 
   }
   *msum = s;
   *mean = (double)s / (double)h.n * h.quantum;
+  return OR_OK;
+}
+
+/* Standard deviation on D_p for a block-mean stream (Sec. V-A): with the
+ * integer mean mu~ = round(sum_b M_b S_b / N) (R11), every term of Eq. (var)
+ * is split as (q_i - M_b) + (M_b - mu~) = p_i + M_b - mu~, and
+ * sigma^2 = sum_b sum_{p in D_p[B_b]} (p + M_b - mu~)^2 / (N - 1) * Delta^2.
+ * The sum of squares is exact (128-bit, split into lo/hi words); msum is
+ * sum_b M_b S_b and mu~ the integer mean.  var is NaN when N = 1.  The
+ * stream is decoded to stage 2 from its bytes. */
+int or_var_mt(const uint8_t *buf, uint64_t len, int64_t *n, int64_t *msum, int64_t *mu_t, uint64_t *s2_lo,
+              int64_t *s2_hi, double *var) {
+  or_header h;
+  int rc = or_read_header(buf, len, &h);
+  if (rc != OR_OK) return rc;
+  if (!(h.flags & 1u)) return OR_ERR_UNSUPPORTED;
+  int32_t *st = (int32_t *)malloc((h.n + h.nb) * sizeof(int32_t));
+  if (!st) return OR_ERR_ARG;
+  rc = or_decompress(buf, len, 2, st);
+  if (rc != OR_OK) { free(st); return rc; }
+  const int32_t *p = st, *M = st + h.n;
+  int64_t ms = 0;
+  for (uint64_t b = 0; b < h.nb; b++) {
+    const uint64_t first = b * h.block;
+    ms += (int64_t)M[b] * (int64_t)((h.n - first < h.block) ? h.n - first : h.block);
+  }
+  const int64_t mt = round_half_down_div(ms, (int64_t)h.n);
+  __int128 acc = 0;
+  for (uint64_t b = 0; b < h.nb; b++) {
+    const uint64_t first = b * h.block;
+    const uint64_t last = (h.n - first < h.block) ? h.n : first + h.block;
+    for (uint64_t e = first; e < last; e++) {
+      const int64_t t = (int64_t)p[e] + (int64_t)M[b] - mt;
+      acc += (__int128)t * t;
+    }
+  }
+  free(st);
+  *n = (int64_t)h.n;
+  *msum = ms;
+  *mu_t = mt;
+  *s2_lo = (uint64_t)acc;
+  *s2_hi = (int64_t)(acc >> 64);
+  *var = h.n > 1 ? (double)acc / (double)(h.n - 1) * (h.quantum * h.quantum) : NAN;
   return OR_OK;
 }
 

@@ -123,3 +123,73 @@ def test_rejects_unknown_flags_and_meta_mean_of_delta_streams():
     with pytest.raises(oracle.OracleError) as e:
         oracle.read_header(bad)
     assert e.value.code == oracle.ERR_STREAM
+
+
+# ---- standard deviation on D_p about the integer metadata mean (Sec. V-A) ----------------
+
+def test_std_about_metadata_mean_worked_example():
+    """Sec. V-A continues the example of Sec. IV: mu~ = round((5*4 + (-1)*4) / 8)
+    = 2 and sigma = 2.000 on Y_p (the exact sample deviation would be 1.9993)."""
+    g = _golden()
+    yq = np.array(g["Yq"], dtype=np.int32).reshape(2, 4)
+    blocks = np.concatenate([yq[:, 0:2].ravel(), yq[:, 2:4].ravel()])
+    buf = oracle.encode_q(blocks, (8,), quantum=0.2, block=4, eb_abs=0.1, mean_dec=True)
+    r = oracle.var_mt(buf)
+    assert (r["n"], r["msum"], r["mu_t"]) == (8, 16, 2)
+    assert r["s2"] == sum((int(v) - 2) ** 2 for v in blocks) == 700
+    assert round(math.sqrt(r["var"]), 3) == g["sigma_hszx_p"][0]
+    assert math.sqrt(r["var"]) == pytest.approx(2.0, rel=1e-15)
+    exact = float(np.std(blocks.astype(np.float64), ddof=1)) * 0.2
+    assert round(exact, 3) != g["sigma_hszx_p"][0]  # the printed value is the mu~ form
+
+
+@pytest.mark.parametrize("S,N", [(1, 4), (2, 5), (3, 4), (4, 6)])
+def test_std_about_metadata_mean_brute_force(S, N):
+    """Every integer vector in [-2, 2]^N (ragged last block when S does not
+    divide N): mu~ is the rounded (halves down) mean of the block means
+    weighted by their sizes, and the sum is of (q - mu~)^2 taken straight
+    from q, with exact rationals."""
+    for vals in itertools.product(range(-2, 3), repeat=N):
+        q = np.array(vals, dtype=np.int32)
+        buf = oracle.encode_q(q, (N,), quantum=1.0, block=S, mean_dec=True)
+        r = oracle.var_mt(buf)
+        ms = 0
+        for b in range(0, N, S):
+            blk = vals[b:b + S]
+            ms += _round_half_down(Fraction(sum(blk), len(blk))) * len(blk)
+        mt = _round_half_down(Fraction(ms, N))
+        want = sum((v - mt) ** 2 for v in vals)
+        assert (r["msum"], r["mu_t"], r["s2"]) == (ms, mt, want), vals
+        assert r["var"] == pytest.approx(want / (N - 1), rel=1e-15, abs=0)
+
+
+@pytest.mark.parametrize("shape,S,rel", [((7, 9, 35), 32, 1e-3), ((3001,), 64, 1e-5), ((1,), 32, 1e-3)])
+def test_std_about_metadata_mean_shift_identity(shape, S, rel):
+    """Sum (q - mu~)^2 = sum (q - mu)^2 + N (mu - mu~)^2 exactly (mu = the exact
+    mean of q): the spread about mu~ exceeds the sample variance by the
+    squared shift only, and |mu - mu~| <= 1 (each rounding moves by at most
+    one half)."""
+    rng = np.random.default_rng(sum(shape) * S)
+    x = (rng.normal(size=shape) * 2 - 5).astype(np.float32)
+    buf = oracle.compress(x, rel, rel=True, block=S, mean_dec=True)
+    h = oracle.read_header(buf)
+    q = [int(v) for v in oracle.decompress(buf, oracle.QUANT).ravel()]
+    r = oracle.var_mt(buf)
+    n = len(q)
+    mu = Fraction(sum(q), n)
+    assert abs(mu - r["mu_t"]) <= 1
+    assert r["msum"] == oracle.meta_mean(buf)[0]
+    assert Fraction(r["s2"]) == sum((Fraction(v) - mu) ** 2 for v in q) + n * (mu - r["mu_t"]) ** 2
+    if n > 1:
+        assert r["var"] == pytest.approx(r["s2"] / (n - 1) * h.quantum ** 2, rel=1e-15)
+    else:
+        assert math.isnan(r["var"])
+
+
+def test_std_about_metadata_mean_constant_field_and_delta_streams():
+    x = np.full((5, 70), 3.25, dtype=np.float32)
+    r = oracle.var_mt(oracle.compress(x, 1e-3, block=32, mean_dec=True))
+    assert r["s2"] == 0 and r["var"] == 0.0
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.var_mt(oracle.compress(x, 1e-3, block=32))
+    assert e.value.code == oracle.ERR_UNSUPPORTED
