@@ -432,6 +432,7 @@ def bench_hszx(a, log):
     """The step's 512^3 binary32 field compressed in both decorrelation modes
     (rel eb 1e-4, S=32): compression time and ratio, the mean from the block
     means alone (Eq. (mean_m)), the exact mean via D_p, the variance via D_q,
+    the spread about the integer metadata mean via D_p (Sec. V-A),
     the gradient magnitude (fused from the delta stream; decode to D_q then
     the stencil for block-mean streams), and full decompression + the mean
     on floats."""
@@ -483,6 +484,8 @@ def bench_hszx(a, log):
         r["mean_delta_ms"] = round(_events_ms(stat(hsz.DELTA, hsz.MEAN), 10, cur), 4)
         m_exact = hsz.stats_of(s48)["mean"]
         r["var_quant_ms"] = round(_events_ms(stat(hsz.QUANT, hsz.VAR), 10, cur), 4)
+        if mean_dec:
+            r["var_mt_delta_ms"] = round(_events_ms(stat(hsz.DELTA, hsz.VAR_MT), 10, cur), 4)
         r["gradmag_ms"] = round(_events_ms(grad, 5, cur), 4)
         r["full_decompress_mean_ms"] = round(_events_ms(full_mean, 5, cur), 4)
         if mean_dec:

@@ -56,7 +56,8 @@ enum {
 enum { HSZ_F32 = 1, HSZ_F64 = 2 };                                  /* field dtype */
 enum { HSZ_META = 1, HSZ_DELTA = 2, HSZ_QUANT = 3, HSZ_FLOAT = 4 }; /* Table I     */
 enum { HSZ_MEAN = 1, HSZ_VAR = 2, HSZ_DERIV = 3, HSZ_GRADMAG = 4, HSZ_LAPLACIAN = 5, /* operations */
-       HSZ_DIVERGENCE = 6, HSZ_CURL = 7 };                  /* vector fields (below) */
+       HSZ_DIVERGENCE = 6, HSZ_CURL = 7,                    /* vector fields (below) */
+       HSZ_VAR_MT = 8 };            /* spread about the metadata mean (block-mean streams) */
 
 /* Size of the fixed header at the start of every compressed stream. */
 #define HSZ_HEADER_BYTES 256
@@ -97,7 +98,10 @@ typedef struct hsz_box {
  * integer s2_hi:s2_lo); mean = s1*Delta/n and var = (n*s2 - s1^2) /
  * (n*(n-1)) * Delta^2 are rounded once from the exact integers.  HSZ_MEAN
  * leaves s2 = 0 and var = NaN.  On stage 4 the sums are 0 and mean/var are
- * computed from the floats in binary64. */
+ * computed from the floats in binary64.  HSZ_VAR_MT: n; s1 = sum_b M_b S_b
+ * (the block means times their sizes); s2 = sum (q - mu~)^2, exact, with
+ * mu~ = round(s1 / n) (halves down); mean = mu~ * Delta; var = s2 / (n - 1)
+ * * Delta^2 (NaN for n = 1). */
 typedef struct hsz_stats {
   int64_t n;
   int64_t s1;
@@ -187,6 +191,13 @@ int hsz_decompress_to_stage(const void *d_c, const hsz_header *h, int stage, voi
 /* ---- operations Q_i(d^(i)), Sec. V ------------------------------------------
  * op = HSZ_MEAN, HSZ_VAR : result = one hsz_stats (Eq. (var), sample
  *      variance with N - 1; the standard deviation is sqrt(var)).
+ * op = HSZ_VAR_MT        : result = one hsz_stats; the standard deviation
+ *      on D_p of HSZx (Sec. V-A): each term of Eq. (var) is taken about the
+ *      integer mean mu~ of the block means instead of the exact mean, so
+ *      var = sum_b sum_{p in D_p[B_b]} (p + M_b - mu~)^2 / (N - 1) * Delta^2
+ *      (the sample variance plus N (mu - mu~)^2 / (N - 1) Delta^2).  Block-
+ *      mean streams only, the whole field only, via stage 2 (on_stage and
+ *      fused) or stage 3 (fused); anything else HSZ_ERR_UNSUPPORTED.
  * op = HSZ_DERIV (axis)  : result = derivative along 'axis' (0 = slowest)
  *      at every point of the box, field dtype, box-shaped C order.
  * op = HSZ_GRADMAG       : result = sqrt(sum over axes of derivative^2).

@@ -25,6 +25,19 @@ bool meta_mean_ok(const hsz_header* h, int op, const hsz::OpTarget& t) {
   return (h->flags & HSZ_FLAG_BLOCK_MEAN) && op == HSZ_MEAN && whole;
 }
 
+bool is_stats(int op) { return op == HSZ_MEAN || op == HSZ_VAR || op == HSZ_VAR_MT; }
+bool is_stencil(int op) { return op >= HSZ_DERIV && op <= HSZ_LAPLACIAN; }
+
+// The spread about the integer metadata mean (Sec. V-A, standard deviation
+// on D_p of HSZx) needs the block means of every block: block-mean streams,
+// whole field, through stage 2 (or 3 in the fused path, whose stream still
+// holds the metadata).
+bool var_mt_ok(const hsz_header* h, const hsz::OpTarget& t, int stage, bool fused) {
+  const hsz::Box3& b = t.box;
+  const bool whole = b.z0 == 0 && b.y0 == 0 && b.x0 == 0 && b.z1 == t.d.z && b.y1 == t.d.y && b.x1 == t.d.x;
+  return (h->flags & HSZ_FLAG_BLOCK_MEAN) && whole && (stage == HSZ_DELTA || (fused && stage == HSZ_QUANT));
+}
+
 // The integer Laplacian numerator is a sum of 12 terms of |q| in 32 bits.
 constexpr uint32_t kLapMaxQ = 1u << 27;
 
@@ -38,7 +51,7 @@ int op_common(const hsz_header* h, int op, int axis, const hsz_box* box, uint64_
               void* d_ws, uint64_t ws_bytes, hsz::OpTarget* t, int* axis3) {
   int rc = check_header(h);
   if (rc) return rc;
-  if (op < HSZ_MEAN || op > HSZ_LAPLACIAN) return HSZ_ERR_INVALID_ARG;
+  if (!is_stats(op) && !is_stencil(op)) return HSZ_ERR_INVALID_ARG;
   if (!d_result || !d_ws || !aligned16(d_ws)) return HSZ_ERR_INVALID_ARG;
   if (ws_bytes < hsz::op_workspace_bytes()) return HSZ_ERR_CAPACITY;
   int64_t d3[3], n;
@@ -51,11 +64,11 @@ int op_common(const hsz_header* h, int op, int axis, const hsz_box* box, uint64_
   } else {
     *axis3 = 0;
   }
-  if (op >= HSZ_DERIV && ws_bytes < hsz::grad_workspace_bytes(h->nb)) return HSZ_ERR_CAPACITY;
+  if (is_stencil(op) && ws_bytes < hsz::grad_workspace_bytes(h->nb)) return HSZ_ERR_CAPACITY;
   const uint64_t esz = h->dtype == HSZ_F32 ? 4 : 8;
-  const uint64_t need = (op <= HSZ_VAR) ? sizeof(hsz_stats) : esz * (uint64_t)t->box.volume();
+  const uint64_t need = is_stats(op) ? sizeof(hsz_stats) : esz * (uint64_t)t->box.volume();
   if (cap < need) return HSZ_ERR_CAPACITY;
-  if (op >= HSZ_DERIV && !aligned16(d_result)) return HSZ_ERR_INVALID_ARG;
+  if (is_stencil(op) && !aligned16(d_result)) return HSZ_ERR_INVALID_ARG;
   return HSZ_OK;
 }
 
@@ -253,9 +266,9 @@ int hsz_block_index(const void* d_c, const hsz_header* h, void* d_index, uint64_
 }
 
 int hsz_op_workspace(const hsz_header* h, int op, uint64_t* h_bytes) {
-  if (!h || !h_bytes || op < HSZ_MEAN || op > HSZ_LAPLACIAN) return HSZ_ERR_INVALID_ARG;
+  if (!h || !h_bytes || (!is_stats(op) && !is_stencil(op))) return HSZ_ERR_INVALID_ARG;
   uint64_t a = hsz::op_workspace_bytes(), b = hsz::grad_workspace_bytes(h->nb);
-  *h_bytes = (op >= HSZ_DERIV && b > a) ? b : a;
+  *h_bytes = (is_stencil(op) && b > a) ? b : a;
   return HSZ_OK;
 }
 
@@ -268,16 +281,17 @@ int hsz_op_on_stage(const void* d_stage, const hsz_header* h, int stage, int op,
   if (!d_stage || !aligned16(d_stage)) return HSZ_ERR_INVALID_ARG;
   if (stage == HSZ_META && !meta_mean_ok(h, op, t)) return HSZ_ERR_UNSUPPORTED;
   if (stage < HSZ_META || stage > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
+  if (op == HSZ_VAR_MT && !var_mt_ok(h, t, stage, false)) return HSZ_ERR_UNSUPPORTED;
   // a block-mean stream keeps no deltas between neighbours: no stencil on its stage 2
-  if ((h->flags & HSZ_FLAG_BLOCK_MEAN) && op >= HSZ_DERIV && stage == HSZ_DELTA) return HSZ_ERR_UNSUPPORTED;
+  if ((h->flags & HSZ_FLAG_BLOCK_MEAN) && is_stencil(op) && stage == HSZ_DELTA) return HSZ_ERR_UNSUPPORTED;
   // on the decorrelated stage only the derivative along the fast axis is
   // defined (the 1D partition keeps no other neighbour relation)
-  if (op >= HSZ_DERIV && stage == HSZ_DELTA && !(op == HSZ_DERIV && axis3 == 2)) return HSZ_ERR_UNSUPPORTED;
+  if (is_stencil(op) && stage == HSZ_DELTA && !(op == HSZ_DERIV && axis3 == 2)) return HSZ_ERR_UNSUPPORTED;
   if (op == HSZ_LAPLACIAN && stage == HSZ_QUANT && h->max_abs_q >= kLapMaxQ) return HSZ_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   if ((rc = reset_status(d_workspace, s))) return rc;
   const hsz::StreamView v = view_of(nullptr, h);
-  hipError_t e = (op <= HSZ_VAR)
+  hipError_t e = is_stats(op)
                      ? hsz::launch_stats_stage(d_stage, stage, v, op, t, d_result, (uint8_t*)d_workspace, s)
                      : hsz::launch_grad_stage(d_stage, stage, v, op, axis3, t, d_result, (uint8_t*)d_workspace, s);
   return e == hipSuccess ? HSZ_OK : hip_fail(e);
@@ -292,11 +306,12 @@ int hsz_op_fused(const void* d_c, const hsz_header* h, int via, int op, int axis
   if (!d_c || !aligned16(d_c)) return HSZ_ERR_INVALID_ARG;
   if (via == HSZ_META && !meta_mean_ok(h, op, t)) return HSZ_ERR_UNSUPPORTED;
   if (via < HSZ_META || via > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
+  if (op == HSZ_VAR_MT && !var_mt_ok(h, t, via, true)) return HSZ_ERR_UNSUPPORTED;
   // fused stencils decode delta streams only
-  if ((h->flags & HSZ_FLAG_BLOCK_MEAN) && op >= HSZ_DERIV) return HSZ_ERR_UNSUPPORTED;
+  if ((h->flags & HSZ_FLAG_BLOCK_MEAN) && is_stencil(op)) return HSZ_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   const hsz::StreamView v = view_of(d_c, h);
-  if (op >= HSZ_DERIV) {
+  if (is_stencil(op)) {
     if (via == HSZ_DELTA && !(op == HSZ_DERIV && axis3 == 2)) return HSZ_ERR_UNSUPPORTED;
     if (op == HSZ_LAPLACIAN && via == HSZ_QUANT && h->max_abs_q >= kLapMaxQ) return HSZ_ERR_UNSUPPORTED;
     if ((rc = reset_status(d_workspace, s))) return rc;

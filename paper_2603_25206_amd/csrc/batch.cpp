@@ -85,7 +85,7 @@ int classify(const hsz_work& w, Item* it) {
     it->axis3 = 0;
     return HSZ_OK;
   }
-  if (w.op == HSZ_LAPLACIAN) return HSZ_ERR_UNSUPPORTED;  // single operations only
+  if (w.op == HSZ_LAPLACIAN || w.op == HSZ_VAR_MT) return HSZ_ERR_UNSUPPORTED;  // single operations only
   if (w.op == HSZ_DERIV || w.op == HSZ_GRADMAG) {
     if (w.via != HSZ_QUANT && w.via != HSZ_FLOAT) return HSZ_ERR_UNSUPPORTED;
     if (w.op == HSZ_DERIV && (w.axis < 0 || w.axis >= h->ndim)) return HSZ_ERR_INVALID_ARG;

@@ -116,7 +116,9 @@ hipError_t launch_batch_stats(int S, const StatsJob* jobs, const int64_t* unit_s
 hipError_t launch_batch_finalize(const StatsJob* const jobs[2], const int64_t* const counts[2],
                                  const BatchAcc* const acc[2], const int n[2], hipStream_t s);
 
-// Statistics (op = 1 mean, 2 var) on a stage buffer or fused from a stream.
+// Statistics (op = 1 mean, 2 var, 8 var about the integer metadata mean of a
+// block-mean stream) on a stage buffer or fused from a stream.
+constexpr int kOpVarMetaMean = 8;
 hipError_t launch_stats_stage(const void* stage_buf, int stage, const StreamView& v, int op,
                               const OpTarget& t, void* result, uint8_t* ws, hipStream_t s);
 hipError_t launch_stats_fused(const StreamView& v, int via, int op, const OpTarget& t, void* result,

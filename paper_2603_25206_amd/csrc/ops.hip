@@ -21,6 +21,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWavesPerGroup = kThreads / kWave;
 constexpr uint64_t kPartialOff = 256;
+constexpr uint64_t kMetaOff = 64;  // finalized metadata sum (op 8), 48 bytes
 
 // Per-workgroup partial: integer sums or binary64 sums.
 struct Partial {
@@ -481,13 +482,42 @@ __device__ StatsOut stats_from_sums(int64_t n, int64_t s1, uint64_t s2lo, uint64
   return r;
 }
 
+// The standard deviation on D_p of a block-mean stream (Sec. V-A) is taken
+// about the integer mean mu~ = round(sum_b M_b S_b / n), halves down like the
+// block means.  With the exact sums s1 = sum q and s2 = sum q^2 the spread is
+// sum (q - mu~)^2 = s2 - 2 mu~ s1 + n mu~^2, an exact 128-bit integer equal
+// to the paper's sum over blocks of (p + M_b - mu~)^2.  The result holds n,
+// s1 = sum_b M_b S_b, s2 = that spread, mean = mu~ Delta and var = spread /
+// (n - 1) Delta^2.
+__device__ int64_t round_half_down_div(int64_t a, int64_t b) {
+  const int64_t num = 2 * a - b, den = 2 * b;
+  return num >= 0 ? (num + den - 1) / den : -((-num) / den);
+}
+
+__device__ StatsOut stats_about_meta_mean(int64_t n, int64_t s1, uint64_t s2lo, uint64_t s2hi, int64_t msum,
+                                          double quantum) {
+  StatsOut r{};
+  const int64_t mt = round_half_down_div(msum, n);
+  const __int128 S2 = (__int128)(((unsigned __int128)s2hi << 64) | s2lo);
+  const __int128 spread = S2 - (__int128)2 * mt * s1 + (__int128)n * ((__int128)mt * mt);
+  r.n = n;
+  r.s1 = msum;
+  r.s2lo = (uint64_t)spread;
+  r.s2hi = (int64_t)(spread >> 64);
+  r.mean = (double)mt * quantum;
+  r.var = n > 1 ? u128_to_f64((unsigned __int128)spread) / (double)(n - 1) * (quantum * quantum)
+                : __builtin_nan("");
+  return r;
+}
+
 // One workgroup of 256 threads: thread t sums partials t, t+256, ... in
 // order, then a fixed-shape tree combines the 256 sums, so the result does
-// not depend on timing.
+// not depend on timing.  op 8 takes the metadata sum from 'meta' (the
+// finalized k_meta_mean of the same stream).
 constexpr int kFinThreads = 256;
 
 __global__ void __launch_bounds__(kFinThreads) k_finalize(const Partial* parts, int groups, int op, int fl,
-                                                          double quantum, StatsOut* out) {
+                                                          double quantum, const StatsOut* meta, StatsOut* out) {
   __shared__ int64_t s1s[kFinThreads], cnts[kFinThreads];
   __shared__ uint64_t los[kFinThreads], his[kFinThreads];
   __shared__ double f1s[kFinThreads], f2s[kFinThreads];
@@ -522,7 +552,9 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(const Partial* parts, 
   StatsOut r{};
   r.n = cnts[0];
   const int64_t n = cnts[0];
-  if (!fl) {
+  if (op == kOpVarMetaMean) {
+    r = stats_about_meta_mean(n, s1s[0], los[0], his[0], meta->s1, quantum);
+  } else if (!fl) {
     r = stats_from_sums(n, s1s[0], los[0], his[0], op, quantum);
   } else {
     const double K = parts[0].pad0;
@@ -787,9 +819,26 @@ int stats_kmax(const StreamView& v) { return kmax_for(v); }
 
 uint64_t op_workspace_bytes() { return kPartialOff + sizeof(Partial) * (uint64_t)kOpWorkgroups; }
 
-hipError_t launch_stats_stage(const void* buf, int stage, const StreamView& v, int op, const OpTarget& t,
+// Sum of the block means (k_meta_mean, finalized into the workspace at
+// kMetaOff) that the spread about the metadata mean needs first.
+hipError_t launch_meta_sum(const int32_t* ms, const StreamView& v, Partial* parts, uint8_t* ws, hipStream_t s) {
+  const int grid = grid_for(v.nb, kThreads);
+  hipLaunchKernelGGL(k_meta_mean, dim3(grid), dim3(kThreads), 0, s, ms, v.n, v.nb, v.block, parts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, parts, grid, 1, 0, v.quantum,
+                     (const StatsOut*)nullptr, (StatsOut*)(ws + kMetaOff));
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_stage(const void* buf, int stage, const StreamView& v, int op_in, const OpTarget& t,
                               void* result, uint8_t* ws, hipStream_t s) {
   Partial* parts = (Partial*)(ws + kPartialOff);
+  if (op_in == kOpVarMetaMean) {  // stage 2 of a block-mean stream, whole field (checked by the caller)
+    hipError_t e = launch_meta_sum((const int32_t*)buf + v.n, v, parts, ws, s);
+    if (e != hipSuccess) return e;
+  }
+  const int op = op_in == kOpVarMetaMean ? 2 : op_in;
   const Rows rows = make_rows(t.d, t.box);
   const bool contiguous = rows.count() == 1 && rows.base % 4 == 0;
   const bool whole = contiguous && rows.base == 0 && rows.len == v.n;
@@ -864,14 +913,19 @@ hipError_t launch_stats_stage(const void* buf, int stage, const StreamView& v, i
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // stage 4 sums are shifted by the box's first value; every partial carries it
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, parts, grid, op, stage == 4 ? 1 : 0, v.quantum,
-                     (StatsOut*)result);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, parts, grid, op_in, stage == 4 ? 1 : 0,
+                     v.quantum, (const StatsOut*)(ws + kMetaOff), (StatsOut*)result);
   return hipGetLastError();
 }
 
-hipError_t launch_stats_fused(const StreamView& v, int via, int op, const OpTarget& t, void* result, uint8_t* ws,
+hipError_t launch_stats_fused(const StreamView& v, int via, int op_in, const OpTarget& t, void* result, uint8_t* ws,
                               hipStream_t s) {
   Partial* parts = (Partial*)(ws + kPartialOff);
+  if (op_in == kOpVarMetaMean) {  // via 2 or 3 of a block-mean stream, whole field (checked by the caller)
+    hipError_t e = launch_meta_sum(v.q0, v, parts, ws, s);
+    if (e != hipSuccess) return e;
+  }
+  const int op = op_in == kOpVarMetaMean ? 2 : op_in;
   int* status = (int*)ws;
   const Rows rows = make_rows(t.d, t.box);
   const bool whole = rows.count() == 1 && rows.base == 0 && rows.len == v.n;
@@ -884,7 +938,7 @@ hipError_t launch_stats_fused(const StreamView& v, int via, int op, const OpTarg
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, parts, grid, op, 0, v.quantum,
-                       (StatsOut*)result);
+                       (const StatsOut*)nullptr, (StatsOut*)result);
     return hipGetLastError();
   }
   if (v.block == 32)
@@ -894,8 +948,8 @@ hipError_t launch_stats_fused(const StreamView& v, int via, int op, const OpTarg
     e = op == 1 ? fused_by_via<64, 1>(v, via, rows, whole, K, parts, grid, status, s)
                 : fused_by_via<64, 2>(v, via, rows, whole, K, parts, grid, status, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, parts, grid, op, via == 4 ? 1 : 0, v.quantum,
-                     (StatsOut*)result);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, parts, grid, op_in, via == 4 ? 1 : 0, v.quantum,
+                     (const StatsOut*)(ws + kMetaOff), (StatsOut*)result);
   return hipGetLastError();
 }
 

@@ -26,13 +26,14 @@ ERR_INVALID_ARG, ERR_BAD_STREAM, ERR_UNSUPPORTED, ERR_RANGE, ERR_EB, ERR_NONFINI
     -1, -2, -3, -4, -5, -6, -7, -8)
 F32, F64 = 1, 2
 META, DELTA, QUANT, FLOAT = 1, 2, 3, 4
-MEAN, VAR, DERIV, GRADMAG, LAPLACIAN, DIVERGENCE, CURL = 1, 2, 3, 4, 5, 6, 7
+MEAN, VAR, DERIV, GRADMAG, LAPLACIAN, DIVERGENCE, CURL, VAR_MT = 1, 2, 3, 4, 5, 6, 7, 8
 FLAG_BLOCK_MEAN = 1  # header flag: block-mean decorrelation (HSZx)
 HEADER_BYTES = 256
 
-_OPS = {"mean": MEAN, "var": VAR, "deriv": DERIV, "gradmag": GRADMAG, "laplacian": LAPLACIAN,
+_OPS = {"mean": MEAN, "var": VAR, "var_mt": VAR_MT, "deriv": DERIV, "gradmag": GRADMAG, "laplacian": LAPLACIAN,
         "divergence": DIVERGENCE, "curl": CURL}
 _STAGES = {"meta": META, "delta": DELTA, "quant": QUANT, "float": FLOAT}
+_STATS = (MEAN, VAR, VAR_MT)
 
 
 class HszError(RuntimeError):
@@ -343,7 +344,7 @@ def _stats_from_raw(raw: bytes) -> dict:
 
 
 def _result_buffer(h: Header, op: int, box, device):
-    if op in (MEAN, VAR):
+    if op in _STATS:
         return _empty_bytes(48, device), None
     if box is None:
         shape = h.shape
@@ -368,7 +369,7 @@ def _finish(buf, shape, h, op, ws, stream, check, raw=False):
         st = read_status(ws, stream)
         if st != OK:
             raise HszError(st, "operation")
-    if op in (MEAN, VAR):
+    if op in _STATS:
         return _stats_from_raw(buf[:48].cpu().numpy().tobytes())
     vol = 1
     for s in shape:
@@ -387,7 +388,7 @@ def op_on_stage(stage_buf, h: Header, stage, op, axis: int = 0, box=None, stream
     base = stage_buf[0] if isinstance(stage_buf, tuple) else stage_buf
     dev = base.device
     buf, shape = _result_buffer(h, op, box, dev) if out is None else (out, None)
-    if shape is None and op not in (MEAN, VAR):
+    if shape is None and op not in _STATS:
         shape = h.shape if box is None else tuple(int(hi) - int(lo) for lo, hi in zip(*box))
     if ws is None:
         ws = workspace(op_workspace_bytes(h, op), dev)
@@ -407,7 +408,7 @@ def op_fused(c: Compressed, via, op, axis: int = 0, box=None, stream=None, check
     h = c.header
     dev = c.data.device
     buf, shape = _result_buffer(h, op, box, dev) if out is None else (out, None)
-    if shape is None and op not in (MEAN, VAR):
+    if shape is None and op not in _STATS:
         shape = h.shape if box is None else tuple(int(hi) - int(lo) for lo, hi in zip(*box))
     if ws is None:
         ws = workspace(op_workspace_bytes(h, op), dev)

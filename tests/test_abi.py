@@ -169,3 +169,42 @@ def test_laplacian_and_vector_validation_before_any_launch(lib):
     assert lib.hsz_vector_op_fused(ctypes.cast(ptrs, ctypes.c_void_p), ctypes.cast(h1arr, ctypes.c_void_p), 1,
                                    hsz.QUANT, hsz.CURL, None, ctypes.cast(outs, ctypes.c_void_p), 4 * 300, fake,
                                    vws.value, None) == hsz.ERR_INVALID_ARG  # no curl of a 1D field
+
+
+def test_block_mean_statistics_validation_before_any_launch(lib):
+    """The spread about the metadata mean (HSZ_VAR_MT) and the mean from
+    the metadata are refused on the host wherever they are not defined:
+    delta streams, boxes, stages that hold no block means, batches; an
+    unknown operation code is an invalid argument (fake aligned addresses
+    are never touched)."""
+    fake = ctypes.c_void_p(0x10000)
+    x = np.linspace(-1, 2, 6 * 7 * 40).astype(np.float32).reshape(6, 7, 40)
+    hm = hsz.read_header(oracle.compress(x, 1e-3, mean_dec=True))
+    hd = hsz.read_header(oracle.compress(x, 1e-3))
+    assert hm.flags == hsz.FLAG_BLOCK_MEAN and hd.flags == 0
+    ws = ctypes.c_uint64()
+    assert lib.hsz_op_workspace(ctypes.byref(hm), hsz.VAR_MT, ctypes.byref(ws)) == 0
+    assert lib.hsz_op_workspace(ctypes.byref(hm), 9, ctypes.byref(ws)) == hsz.ERR_INVALID_ARG
+    ws.value = max(ws.value, 1 << 20)
+    box = hsz._box(((0, 0, 0), (6, 7, 39)), 3)
+
+    def on_stage(h, stage, op, b=None, cap=48):
+        return lib.hsz_op_on_stage(fake, ctypes.byref(h), stage, op, 0, b, fake, cap, fake, ws.value, None)
+
+    def fused(h, via, op, b=None, cap=48):
+        return lib.hsz_op_fused(fake, ctypes.byref(h), via, op, 0, b, fake, cap, fake, ws.value, None)
+    for st in (hsz.META, hsz.QUANT, hsz.FLOAT):
+        assert on_stage(hm, st, hsz.VAR_MT) == hsz.ERR_UNSUPPORTED  # no block means in these buffers
+    for via in (hsz.META, hsz.FLOAT):
+        assert fused(hm, via, hsz.VAR_MT) == hsz.ERR_UNSUPPORTED
+    assert on_stage(hm, hsz.DELTA, hsz.VAR_MT, box) == hsz.ERR_UNSUPPORTED  # mu~ is of the whole field
+    assert fused(hm, hsz.QUANT, hsz.VAR_MT, box) == hsz.ERR_UNSUPPORTED
+    assert fused(hm, hsz.META, hsz.MEAN, box) == hsz.ERR_UNSUPPORTED
+    assert fused(hm, hsz.META, hsz.VAR) == hsz.ERR_UNSUPPORTED
+    for via in (hsz.DELTA, hsz.QUANT):
+        assert fused(hd, via, hsz.VAR_MT) == hsz.ERR_UNSUPPORTED  # delta streams keep first values
+    assert fused(hd, hsz.META, hsz.MEAN) == hsz.ERR_UNSUPPORTED
+    assert on_stage(hd, hsz.DELTA, hsz.VAR_MT) == hsz.ERR_UNSUPPORTED
+    assert fused(hm, hsz.DELTA, hsz.VAR_MT, cap=47) == hsz.ERR_CAPACITY
+    assert fused(hm, hsz.DELTA, 9) == hsz.ERR_INVALID_ARG
+    assert fused(hm, hsz.QUANT, hsz.GRADMAG, cap=4 * x.size) == hsz.ERR_UNSUPPORTED  # fused stencils: delta streams

@@ -1,7 +1,8 @@
 """GPU parity for block-mean (HSZx) streams against the oracle: compressed
 bytes, every decompression stage, the mean from the metadata (Eq. (mean_m)),
 mean and variance through D_p, D_q and D_f (fused and materialised), the
-gradient on the materialised quantized stage, and the routes this mode does
+spread about the integer metadata mean (Sec. V-A, standard deviation on
+D_p), the gradient on the materialised quantized stage, and the routes this mode does
 not take.
 
 Bars: bytes, stages and integer sums bit-exact; means and variances 1e-12
@@ -91,6 +92,34 @@ def test_mean_from_metadata(mcase):
     for bad in (lambda: hsz.op_fused(c, hsz.META, "var"),
                 lambda: hsz.op_fused(c, hsz.META, "mean", box=tuple(zip(*[(0, s) for s in mcase["shape"][:-1]]
                                                                       + [(0, mcase["shape"][-1] - 1)])))):
+        with pytest.raises(hsz.HszError) as e:
+            bad()
+        assert e.value.code == hsz.ERR_UNSUPPORTED
+
+
+def test_spread_about_metadata_mean(mcase):
+    """Sec. V-A, the standard deviation on D_p of HSZx: the exact integers
+    (sum of block means, sum (q - mu~)^2) equal the oracle's on every route,
+    var within 1e-12 relative."""
+    c, h = mcase["c"], mcase["h"]
+    want = oracle.var_mt(mcase["ref"])
+    dbuf = hsz.decompress_to_stage(c, hsz.DELTA)
+    dflat = torch.cat([dbuf[0].reshape(-1), dbuf[1].reshape(-1)])
+    for got in (hsz.op_fused(c, hsz.DELTA, "var_mt"), hsz.op_fused(c, hsz.QUANT, "var_mt"),
+                hsz.op_on_stage(dflat, c.header, hsz.DELTA, "var_mt"), hsz.op_on_stage(dbuf, c.header, hsz.DELTA,
+                                                                                      "var_mt")):
+        assert (got["n"], got["s1"], got["s2"]) == (want["n"], want["msum"], want["s2"])
+        assert got["mean"] == want["mu_t"] * h.quantum
+        if want["n"] > 1:
+            assert got["var"] == pytest.approx(want["var"], rel=1e-12, abs=0)
+            # the sample variance plus the squared shift of the mean: never below it
+            assert got["var"] >= hsz.op_fused(c, hsz.QUANT, "var")["var"] * (1 - 1e-12)
+    shape = mcase["shape"]
+    box = (tuple(0 for _ in shape), tuple(shape[:-1]) + (shape[-1] - 1,))
+    qbuf = hsz.decompress_to_stage(c, hsz.QUANT)
+    for bad in (lambda: hsz.op_fused(c, hsz.DELTA, "var_mt", box=box),
+                lambda: hsz.op_fused(c, hsz.FLOAT, "var_mt"),
+                lambda: hsz.op_on_stage(qbuf, c.header, hsz.QUANT, "var_mt")):
         with pytest.raises(hsz.HszError) as e:
             bad()
         assert e.value.code == hsz.ERR_UNSUPPORTED
