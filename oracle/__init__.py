@@ -77,6 +77,14 @@ def _load():
     u64, u32, i32, dbl = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_double
     lib.or_compress_bound.restype = u64
     lib.or_compress_bound.argtypes = [u64, u32]
+    lib.or_compress_bound_dims.restype = u64
+    lib.or_compress_bound_dims.argtypes = [u32, P, u32, u32]
+    lib.or_lz_mean_p.restype = i32
+    lib.or_lz_mean_p.argtypes = [P, u32, P, dbl, P, P]
+    lib.or_lz_var_p.restype = i32
+    lib.or_lz_var_p.argtypes = [P, u32, P, dbl, P, P, P, P, P]
+    lib.or_lz_deriv_p.restype = i32
+    lib.or_lz_deriv_p.argtypes = [P, u32, P, i32, dbl, P, P]
     lib.or_ulp.restype = dbl
     lib.or_ulp.argtypes = [dbl, i32]
     lib.or_quant_params.restype = i32
@@ -189,6 +197,17 @@ def compress_bound(n: int, block: int) -> int:
     return int(_load().or_compress_bound(n, block))
 
 
+def _flags(mean_dec: bool, lorenzo: bool) -> int:
+    if mean_dec and lorenzo:
+        raise ValueError("block-mean and Lorenzo decorrelation are exclusive")
+    return 1 if mean_dec else (2 if lorenzo else 0)
+
+
+def compress_bound_dims(shape, block: int, flags: int = 0) -> int:
+    dims = np.array([int(v) for v in shape], dtype=np.uint64)
+    return int(_load().or_compress_bound_dims(len(shape), _ptr(dims), block, flags))
+
+
 def ulp(v: float, dtype: int) -> float:
     return float(_load().or_ulp(v, dtype))
 
@@ -212,16 +231,18 @@ def quantize(x, quantum: float) -> np.ndarray:
 
 
 def encode_q(q, shape, quantum: float, block: int, dtype: int = F32, eb_abs: float = 0.0,
-             mean_dec: bool = False) -> np.ndarray:
+             mean_dec: bool = False, lorenzo: bool = False) -> np.ndarray:
     """Encode given quantization integers; mean_dec selects block-mean
-    decorrelation (HSZx) instead of in-block deltas."""
+    decorrelation (HSZx), lorenzo the nd Lorenzo decorrelation of HSZp-nd,
+    instead of in-block deltas."""
     q = np.ascontiguousarray(np.asarray(q, dtype=np.int32).ravel())
     dims = np.array([int(s) for s in shape], dtype=np.uint64)
-    cap = compress_bound(q.size, block)
+    fl = _flags(mean_dec, lorenzo)
+    cap = max(compress_bound_dims(shape, block, fl), 1)
     out = np.zeros(cap, dtype=np.uint8)
     size = ctypes.c_uint64()
     _check(_load().or_encode_q(_ptr(q), len(shape), _ptr(dims), dtype, eb_abs, quantum, block,
-                               int(bool(mean_dec)), _ptr(out), cap, ctypes.byref(size)), "encode_q")
+                               fl, _ptr(out), cap, ctypes.byref(size)), "encode_q")
     return out[: size.value].copy()
 
 
@@ -245,7 +266,39 @@ def var_mt(buf: np.ndarray) -> dict:
     return {"n": n.value, "msum": ms.value, "mu_t": mt.value, "s2": (hi.value << 64) + lo.value, "var": var.value}
 
 
-def compress(x: np.ndarray, eb: float, rel: bool = True, block: int = 32, mean_dec: bool = False) -> np.ndarray:
+def lz_mean_p(p: np.ndarray, quantum: float):
+    """Mean on D_p of HSZp-nd (Sec. V-A, nd weights): -> (sum q as int, mean)."""
+    pp = np.ascontiguousarray(p, dtype=np.int32)
+    dims = np.array(pp.shape, dtype=np.uint64)
+    s1, mean = ctypes.c_int64(), ctypes.c_double()
+    _check(_load().or_lz_mean_p(_ptr(pp), pp.ndim, _ptr(dims), quantum, ctypes.byref(s1), ctypes.byref(mean)),
+           "lz_mean_p")
+    return s1.value, mean.value
+
+
+def lz_var_p(p: np.ndarray, quantum: float) -> dict:
+    """Alg. 4 (and its 3D form) on D_p of HSZp-nd: -> {n, s1, s2, var}."""
+    pp = np.ascontiguousarray(p, dtype=np.int32)
+    dims = np.array(pp.shape, dtype=np.uint64)
+    n, s1, hi, lo, var = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint64(), ctypes.c_double()
+    _check(_load().or_lz_var_p(_ptr(pp), pp.ndim, _ptr(dims), quantum, ctypes.byref(n), ctypes.byref(s1),
+                               ctypes.byref(lo), ctypes.byref(hi), ctypes.byref(var)), "lz_var_p")
+    return {"n": n.value, "s1": s1.value, "s2": (hi.value << 64) + lo.value, "var": var.value}
+
+
+def lz_deriv_p(p: np.ndarray, axis: int, quantum: float):
+    """Eq. (derivative_Dp) on D_p of HSZp-nd along 'axis': -> (integer
+    numerators int64, derivative = num * quantum / 2 in binary64)."""
+    pp = np.ascontiguousarray(p, dtype=np.int32)
+    dims = np.array(pp.shape, dtype=np.uint64)
+    num = np.empty(pp.shape, dtype=np.int64)
+    out = np.empty(pp.shape, dtype=np.float64)
+    _check(_load().or_lz_deriv_p(_ptr(pp), pp.ndim, _ptr(dims), axis, quantum, _ptr(num), _ptr(out)), "lz_deriv_p")
+    return num, out
+
+
+def compress(x: np.ndarray, eb: float, rel: bool = True, block: int = 32, mean_dec: bool = False,
+             lorenzo: bool = False) -> np.ndarray:
     x = np.ascontiguousarray(x)
     if x.dtype == np.float32:
         dt = F32
@@ -254,10 +307,11 @@ def compress(x: np.ndarray, eb: float, rel: bool = True, block: int = 32, mean_d
     else:
         raise TypeError("field must be float32 or float64")
     dims = np.array(x.shape, dtype=np.uint64)
-    cap = compress_bound(x.size, block)
+    fl = _flags(mean_dec, lorenzo)
+    cap = max(compress_bound_dims(x.shape, block, fl), 1)
     out = np.empty(cap, dtype=np.uint8)
     size = ctypes.c_uint64()
-    _check(_load().or_compress(_ptr(x), dt, x.ndim, _ptr(dims), eb, int(rel), block, int(bool(mean_dec)),
+    _check(_load().or_compress(_ptr(x), dt, x.ndim, _ptr(dims), eb, int(rel), block, fl,
                                _ptr(out), cap, ctypes.byref(size)), "compress")
     return out[: size.value].copy()
 
@@ -279,12 +333,14 @@ def decompress(buf: np.ndarray, stage: int):
     """Alg. 2 to the given stage.
 
     stage 1 -> q0 (int32[nb]); stage 2 -> (p int32[n] shaped like the field,
-    q0 int32[nb]); stage 3 -> q int32 shaped like the field; stage 4 -> the
-    decompressed field in its own dtype.
+    q0 int32[nb], empty for HSZp-nd streams); stage 3 -> q int32 shaped like
+    the field; stage 4 -> the decompressed field in its own dtype.
     """
     buf = np.ascontiguousarray(buf, dtype=np.uint8)
     h = read_header(buf)
     lib = _load()
+    if stage == META and h.flags & 2:
+        raise OracleError(ERR_UNSUPPORTED, "decompress: an HSZp-nd stream has no metadata stage")
     nbytes = int(lib.or_stage_bytes(_ptr(buf), buf.size, stage))
     if nbytes == 0:
         raise OracleError(ERR_ARG, "decompress: bad stage")

@@ -64,6 +64,20 @@
  *      the block means of R10 (the paper's example, 16 / 8 = 2, has no
  *      tie); the spread is taken over the whole field only, since mu~ comes
  *      from the metadata of every block.
+ *   R12 HSZp-nd (Sec. IV): bit 1 of the header flags.  Decorrelation is
+ *      the Lorenzo residual over the whole field (prediction crosses block
+ *      boundaries, as HSZp's does), with q = 0 outside the field:
+ *      p = sum over the corners c of {0,1}^3 of (-1)^|c| q(i - c) in the
+ *      3D view (a 2D field is one plane, so this is the printed 2D form).
+ *      The partition for encoding is into blocks of S = 2^k elements shaped
+ *      by splitting k over the axes as evenly as possible, the faster axes
+ *      taking the remainder (2D: 4x8 for S = 32, 8x8 for 64; 3D: 2x4x4
+ *      and 4x4x4), blocks and their slots in raster order, slots outside
+ *      the field p = 0.  No metadata is stored (the q0 section is empty);
+ *      stage 2 is p in the field's own layout.  For 2D and 3D fields only.
+ *   R13 the residual of HSZp-nd sums up to eight quantization integers, so
+ *      besides R6 it must satisfy |p| <= 2^30 - 1 (the delta mode's width
+ *      limit), else the compressor reports a range error.
  *   R8 the Laplacian of Eq. (laplacian) on n axes is the sum over the axes
  *      of d_{-1} + d_{+1} - 2 d (unit spacing); at the two ends of an axis
  *      the missing neighbour is the end value itself (the field mirrored
@@ -99,6 +113,9 @@
 #define OR_SECTION_ALIGN 256u
 #define OR_CHUNK_BLOCKS 64u
 #define OR_QMAX 536870911 /* 2^29 - 1 */
+#define OR_PMAX 1073741823 /* 2^30 - 1 (R13) */
+#define OR_FLAG_MEAN 1u
+#define OR_FLAG_LORENZO 2u
 
 typedef struct {
   uint32_t dtype;   /* 1 = binary32, 2 = binary64 */
@@ -132,13 +149,35 @@ static double get_f64(const uint8_t *p) { uint64_t v = get_u64(p); double d; mem
 static uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 static uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
-/* Section placement: header, chunk offsets, q0, widths, payload. */
+/* Block shape of the HSZp-nd partition (R12) in the 3D view (slow -> fast);
+ * 0 if ndim or S does not allow one. */
+static int nd_block_shape(uint32_t ndim, uint32_t S, uint64_t b[3]) {
+  if (ndim < 2 || ndim > 3 || S < 4 || S > 64 || (S & (S - 1))) return 0;
+  int k = 0;
+  while ((1u << k) < S) k++;
+  const int ez = ndim == 3 ? k / 3 : 0;
+  const int ey = (k - ez) / 2;
+  const int ex = k - ez - ey;
+  b[0] = 1ull << ez;
+  b[1] = 1ull << ey;
+  b[2] = 1ull << ex;
+  return 1;
+}
+
+/* Section placement: header, chunk offsets, q0, widths, payload.  HSZp-nd
+ * streams count blocks over the nd partition and store no q0. */
 static void layout(or_header *h) {
-  h->nb = ceil_div(h->n, h->block);
+  uint64_t bs[3];
+  if ((h->flags & OR_FLAG_LORENZO) && nd_block_shape(h->ndim, h->block, bs)) {
+    h->nb = 1;
+    for (int k = 0; k < 3; k++) h->nb *= ceil_div(h->dims[k], bs[k]);
+  } else {
+    h->nb = ceil_div(h->n, h->block);
+  }
   h->nchunks = ceil_div(h->nb, h->chunk_blocks);
   h->off_chunk = OR_HEADER_BYTES;
   h->off_q0 = round_up(h->off_chunk + 8 * (h->nchunks + 1), OR_SECTION_ALIGN);
-  h->off_width = round_up(h->off_q0 + 4 * h->nb, OR_SECTION_ALIGN);
+  h->off_width = round_up(h->off_q0 + ((h->flags & OR_FLAG_LORENZO) ? 0 : 4 * h->nb), OR_SECTION_ALIGN);
   h->off_payload = round_up(h->off_width + h->nb, OR_SECTION_ALIGN);
 }
 
@@ -207,8 +246,11 @@ int or_read_header(const uint8_t *buf, uint64_t len, or_header *h) {
   h->payload_words = get_u64(buf + 144);
   h->total_bytes = get_u64(buf + 152);
   if (h->dtype != 1 && h->dtype != 2) return OR_ERR_STREAM;
-  if (h->flags > 1u) return OR_ERR_STREAM;  /* bit 0: block-mean decorrelation (R10) */
+  /* bit 0: block-mean decorrelation (R10); bit 1: HSZp-nd (R12); not both */
+  if (h->flags > 2u) return OR_ERR_STREAM;
   if (h->ndim < 1 || h->ndim > 3) return OR_ERR_STREAM;
+  uint64_t bs[3];
+  if ((h->flags & OR_FLAG_LORENZO) && !nd_block_shape(h->ndim, h->block, bs)) return OR_ERR_STREAM;
   if (h->block < 1 || h->block > 64 || h->chunk_blocks != OR_CHUNK_BLOCKS) return OR_ERR_STREAM;
   uint64_t prod = 1;
   for (int k = 0; k < 3; k++) {
@@ -237,6 +279,25 @@ uint64_t or_compress_bound(uint64_t n, uint32_t S) {
   h.chunk_blocks = OR_CHUNK_BLOCKS;
   layout(&h);
   /* |q| <= 2^29 - 1 (R6) bounds |p| below 2^30, so no block is wider than 30 bits */
+  return h.off_payload + 4 * h.nb * block_words(S, 30);
+}
+
+/* The same bound for a stream of the given flags over a field of the given
+ * dims (HSZp-nd streams count blocks over the nd partition). */
+uint64_t or_compress_bound_dims(uint32_t ndim, const uint64_t *dims, uint32_t S, uint32_t flags) {
+  if (!dims || ndim < 1 || ndim > 3 || S < 1 || S > 64 || flags > 2u) return 0;
+  or_header h;
+  memset(&h, 0, sizeof h);
+  h.ndim = ndim;
+  for (int k = 0; k < 3; k++) h.dims[k] = 1;
+  h.n = 1;
+  for (uint32_t k = 0; k < ndim; k++) { h.dims[3 - ndim + k] = dims[k]; h.n *= dims[k]; }
+  uint64_t bs[3];
+  if (h.n == 0 || ((flags & OR_FLAG_LORENZO) && !nd_block_shape(ndim, S, bs))) return 0;
+  h.block = S;
+  h.flags = flags;
+  h.chunk_blocks = OR_CHUNK_BLOCKS;
+  layout(&h);
   return h.off_payload + 4 * h.nb * block_words(S, 30);
 }
 
@@ -324,36 +385,72 @@ static int64_t round_half_down_div(int64_t a, int64_t b) {
  * function's caller or it is cleared here up to the bound. */
 static int encode_q(const int32_t *q, or_header *h, uint8_t *out, uint64_t cap, uint64_t *out_size) {
   const uint32_t S = h->block;
+  const int mean_mode = (h->flags & OR_FLAG_MEAN) != 0;
+  const int lorenzo = (h->flags & OR_FLAG_LORENZO) != 0;
+  uint64_t bs[3] = {1, 1, 1};
+  if (lorenzo && !nd_block_shape(h->ndim, S, bs)) return OR_ERR_ARG;
   h->chunk_blocks = OR_CHUNK_BLOCKS;
   layout(h);
   uint64_t bound = h->off_payload + 4 * h->nb * block_words(S, 30);
   if (cap < h->off_payload) { if (out_size) *out_size = bound; return OR_ERR_CAPACITY; }
 
-  /* metadata (first q of each block) and decorrelated data p, block by block */
+  uint32_t max_abs_q = 0;
+  for (uint64_t e = 0; e < h->n; e++) {
+    uint32_t aq = (uint32_t)(q[e] < 0 ? -(int64_t)q[e] : q[e]);
+    if (aq > max_abs_q) max_abs_q = aq;
+  }
+
+  /* decorrelated data p, block by block (slot i of block b at b*S + i; slots
+     outside the field stay 0), and the metadata of the 1D modes */
   int32_t *p = (int32_t *)calloc(h->nb * S, sizeof(int32_t));
   uint32_t *width = (uint32_t *)calloc(h->nb, sizeof(uint32_t));
   int32_t *q0 = (int32_t *)calloc(h->nb, sizeof(int32_t));
   if (!p || !width || !q0) { free(p); free(width); free(q0); return OR_ERR_ARG; }
-  uint32_t max_abs_q = 0;
+  if (lorenzo) {
+    /* Lorenzo residual of every point (R12), q = 0 outside the field */
+    const uint64_t Z = h->dims[0], Y = h->dims[1], X = h->dims[2];
+    const uint64_t nbz = ceil_div(Z, bs[0]), nby = ceil_div(Y, bs[1]), nbx = ceil_div(X, bs[2]);
+    for (uint64_t bz = 0; bz < nbz; bz++)
+      for (uint64_t by = 0; by < nby; by++)
+        for (uint64_t bx = 0; bx < nbx; bx++) {
+          const uint64_t b = (bz * nby + by) * nbx + bx;
+          uint32_t i = 0;
+          for (uint64_t sz = 0; sz < bs[0]; sz++)
+            for (uint64_t sy = 0; sy < bs[1]; sy++)
+              for (uint64_t sx = 0; sx < bs[2]; sx++, i++) {
+                const uint64_t z = bz * bs[0] + sz, y = by * bs[1] + sy, x = bx * bs[2] + sx;
+                if (z >= Z || y >= Y || x >= X) continue;
+                int64_t r = 0;
+                for (int c = 0; c < 8; c++) {
+                  const int dz = (c >> 2) & 1, dy = (c >> 1) & 1, dx = c & 1;
+                  if ((dz && z == 0) || (dy && y == 0) || (dx && x == 0)) continue;
+                  const int64_t v = q[((z - dz) * Y + (y - dy)) * X + (x - dx)];
+                  r += ((dz + dy + dx) & 1) ? -v : v;
+                }
+                if (r > OR_PMAX || r < -OR_PMAX) { free(p); free(width); free(q0); return OR_ERR_RANGE; }
+                p[b * S + i] = (int32_t)r;
+              }
+        }
+  } else {
+    for (uint64_t b = 0; b < h->nb; b++) {
+      uint64_t first = b * S;
+      uint64_t len = (h->n - first < S) ? h->n - first : S;
+      if (mean_mode) {
+        int64_t sum = 0;
+        for (uint64_t i = 0; i < len; i++) sum += q[first + i];
+        q0[b] = (int32_t)round_half_down_div(sum, (int64_t)len);
+      } else {
+        q0[b] = q[first];
+      }
+      for (uint64_t i = 0; i < len; i++)
+        p[first + i] = mean_mode ? q[first + i] - q0[b] : (i == 0) ? 0 : q[first + i] - q[first + i - 1];
+    }
+  }
   uint64_t words = 0;
   for (uint64_t b = 0; b < h->nb; b++) {
-    uint64_t first = b * S;
-    uint64_t len = (h->n - first < S) ? h->n - first : S;
-    const int mean_mode = (h->flags & 1u) != 0;
-    if (mean_mode) {
-      int64_t sum = 0;
-      for (uint64_t i = 0; i < len; i++) sum += q[first + i];
-      q0[b] = (int32_t)round_half_down_div(sum, (int64_t)len);
-    } else {
-      q0[b] = q[first];
-    }
     uint32_t maxp = 0;
-    for (uint64_t i = 0; i < len; i++) {
-      int32_t qi = q[first + i];
-      uint32_t aq = (uint32_t)(qi < 0 ? -(int64_t)qi : qi);
-      if (aq > max_abs_q) max_abs_q = aq;
-      int32_t pi = mean_mode ? qi - q0[b] : (i == 0) ? 0 : qi - q[first + i - 1];
-      p[first + i] = pi;
+    for (uint32_t i = 0; i < S; i++) {
+      int32_t pi = p[b * S + i];
       uint32_t ap = (uint32_t)(pi < 0 ? -(int64_t)pi : pi);
       if (ap > maxp) maxp = ap;
     }
@@ -373,15 +470,14 @@ static int encode_q(const int32_t *q, or_header *h, uint8_t *out, uint64_t cap, 
   uint64_t pos = 0;
   for (uint64_t b = 0; b < h->nb; b++) {
     if (b % OR_CHUNK_BLOCKS == 0) put_u64(out + h->off_chunk + 8 * (b / OR_CHUNK_BLOCKS), pos);
-    put_u32(out + h->off_q0 + 4 * b, (uint32_t)q0[b]);
+    if (!lorenzo) put_u32(out + h->off_q0 + 4 * b, (uint32_t)q0[b]);
     out[h->off_width + b] = (uint8_t)width[b];
     uint32_t w = width[b];
     if (w == 0) continue;
     uint32_t *sign = payload + pos;
     uint32_t *mag = sign + ceil_div(S, 32);
     for (uint32_t i = 0; i < S; i++) {
-      uint64_t e = b * S + i;
-      int32_t pi = (e < h->n) ? p[e] : 0;
+      int32_t pi = p[b * S + i];
       if (pi < 0) sign[i / 32] |= 1u << (i % 32);
       uint32_t ap = (uint32_t)(pi < 0 ? -(int64_t)pi : pi);
       stream_set_bits(mag, (uint64_t)i * w, ap, w);
@@ -415,7 +511,7 @@ int or_encode_q(const int32_t *q, uint32_t ndim, const uint64_t *dims, uint32_t 
   h.inv_quantum = 1.0 / quantum;
   h.vmin = 0.0;
   h.vmax = 0.0;
-  if (flags > 1u) return OR_ERR_ARG;
+  if (flags > 2u) return OR_ERR_ARG;
   h.flags = flags;
   return encode_q(q, &h, out, cap, out_size);
 }
@@ -423,7 +519,7 @@ int or_encode_q(const int32_t *q, uint32_t ndim, const uint64_t *dims, uint32_t 
 /* Full compressor C(d, eps): extremes -> parameters -> quantize -> encode. */
 int or_compress(const void *x, uint32_t dtype, uint32_t ndim, const uint64_t *dims, double eb,
                 int eb_is_rel, uint32_t S, uint32_t flags, uint8_t *out, uint64_t cap, uint64_t *out_size) {
-  if (!x || !dims || ndim < 1 || ndim > 3 || S < 1 || S > 64 || (dtype != 1 && dtype != 2) || flags > 1u)
+  if (!x || !dims || ndim < 1 || ndim > 3 || S < 1 || S > 64 || (dtype != 1 && dtype != 2) || flags > 2u)
     return OR_ERR_ARG;
   or_header h;
   memset(&h, 0, sizeof h);
@@ -474,69 +570,109 @@ int or_compress(const void *x, uint32_t dtype, uint32_t ndim, const uint64_t *di
 uint64_t or_stage_bytes(const uint8_t *buf, uint64_t len, int stage) {
   or_header h;
   if (or_read_header(buf, len, &h) != OR_OK) return 0;
+  const int lorenzo = (h.flags & OR_FLAG_LORENZO) != 0;
   switch (stage) {
-    case 1: return 4 * h.nb;
-    case 2: return 4 * h.n + 4 * h.nb;
+    case 1: return lorenzo ? 0 : 4 * h.nb;
+    case 2: return 4 * h.n + (lorenzo ? 0 : 4 * h.nb);
     case 3: return 4 * h.n;
     case 4: return (h.dtype == 1 ? 4 : 8) * h.n;
     default: return 0;
   }
 }
 
+/* stage 1 of an HSZp-nd stream does not exist (no metadata): OR_ERR_UNSUPPORTED */
 int or_decompress(const uint8_t *buf, uint64_t len, int stage, void *out) {
   or_header h;
   int rc = or_read_header(buf, len, &h);
   if (rc != OR_OK) return rc;
   if (!out || stage < 1 || stage > 4) return OR_ERR_ARG;
   const uint32_t S = h.block;
-  int32_t *q0 = (int32_t *)malloc(h.nb * sizeof(int32_t));
+  const int lorenzo = (h.flags & OR_FLAG_LORENZO) != 0;
+  if (lorenzo && stage == 1) return OR_ERR_UNSUPPORTED;
+  int32_t *q0 = (int32_t *)calloc(h.nb, sizeof(int32_t));
   if (!q0) return OR_ERR_ARG;
-  for (uint64_t b = 0; b < h.nb; b++) q0[b] = (int32_t)get_u32(buf + h.off_q0 + 4 * b);
+  if (!lorenzo)
+    for (uint64_t b = 0; b < h.nb; b++) q0[b] = (int32_t)get_u32(buf + h.off_q0 + 4 * b);
   if (stage == 1) { memcpy(out, q0, h.nb * sizeof(int32_t)); free(q0); return OR_OK; }
 
-  /* decode: signs and magnitudes -> p */
-  int32_t *p = (int32_t *)calloc(h.n, sizeof(int32_t));
-  if (!p) { free(q0); return OR_ERR_ARG; }
+  /* decode: signs and magnitudes -> pb (slot i of block b at b*S + i) */
+  int32_t *pb = (int32_t *)calloc(h.nb * S, sizeof(int32_t));
+  if (!pb) { free(q0); return OR_ERR_ARG; }
   uint64_t pos = 0;
   for (uint64_t b = 0; b < h.nb; b++) {
     if (b % OR_CHUNK_BLOCKS == 0 && get_u64(buf + h.off_chunk + 8 * (b / OR_CHUNK_BLOCKS)) != pos) {
-      free(p); free(q0); return OR_ERR_STREAM;
+      free(pb); free(q0); return OR_ERR_STREAM;
     }
     uint32_t w = buf[h.off_width + b];
-    if (w > 30) { free(p); free(q0); return OR_ERR_STREAM; }
+    if (w > 30) { free(pb); free(q0); return OR_ERR_STREAM; }
     if (w == 0) continue;
     uint64_t nw = block_words(S, w);
-    if (pos + nw > h.payload_words) { free(p); free(q0); return OR_ERR_STREAM; }
+    if (pos + nw > h.payload_words) { free(pb); free(q0); return OR_ERR_STREAM; }
     uint32_t *blk = (uint32_t *)malloc(nw * sizeof(uint32_t));
-    if (!blk) { free(p); free(q0); return OR_ERR_ARG; }
+    if (!blk) { free(pb); free(q0); return OR_ERR_ARG; }
     for (uint64_t k = 0; k < nw; k++) blk[k] = get_u32(buf + h.off_payload + 4 * (pos + k));
     const uint32_t *mag = blk + ceil_div(S, 32);
     for (uint32_t i = 0; i < S; i++) {
-      uint64_t e = b * S + i;
-      if (e >= h.n) break;
       uint32_t a = stream_get_bits(mag, (uint64_t)i * w, w);
       int neg = (blk[i / 32] >> (i % 32)) & 1u;
-      p[e] = neg ? -(int32_t)a : (int32_t)a;
+      pb[b * S + i] = neg ? -(int32_t)a : (int32_t)a;
     }
     free(blk);
     pos += nw;
   }
-  if (pos != h.payload_words) { free(p); free(q0); return OR_ERR_STREAM; }
+  if (pos != h.payload_words) { free(pb); free(q0); return OR_ERR_STREAM; }
+
+  /* p in the field's own layout: the 1D modes read blocks in order; HSZp-nd
+     places each slot of each nd block at its coordinates (R12) */
+  int32_t *p = (int32_t *)calloc(h.n, sizeof(int32_t));
+  if (!p) { free(pb); free(q0); return OR_ERR_ARG; }
+  const uint64_t Z = h.dims[0], Y = h.dims[1], X = h.dims[2];
+  if (lorenzo) {
+    uint64_t bs[3];
+    nd_block_shape(h.ndim, S, bs);
+    const uint64_t nby = ceil_div(Y, bs[1]), nbx = ceil_div(X, bs[2]);
+    for (uint64_t b = 0; b < h.nb; b++) {
+      const uint64_t bz = b / (nby * nbx), by = (b / nbx) % nby, bx = b % nbx;
+      for (uint32_t i = 0; i < S; i++) {
+        const uint64_t sz = i / (bs[1] * bs[2]), sy = (i / bs[2]) % bs[1], sx = i % bs[2];
+        const uint64_t z = bz * bs[0] + sz, y = by * bs[1] + sy, x = bx * bs[2] + sx;
+        if (z < Z && y < Y && x < X) p[(z * Y + y) * X + x] = pb[b * S + i];
+      }
+    }
+  } else {
+    memcpy(p, pb, h.n * sizeof(int32_t));
+  }
+  free(pb);
   if (stage == 2) {
     memcpy(out, p, h.n * sizeof(int32_t));
-    memcpy((int32_t *)out + h.n, q0, h.nb * sizeof(int32_t));
+    if (!lorenzo) memcpy((int32_t *)out + h.n, q0, h.nb * sizeof(int32_t));
     free(p); free(q0);
     return OR_OK;
   }
 
   /* recorrelate: q_i = q_{i-1} + p_i inside a block, starting from q0 (delta
-     mode), or q_i = M_b + p_i (block-mean mode, R10) */
+     mode); q_i = M_b + p_i (block-mean mode, R10); HSZp-nd: q = p plus the
+     Lorenzo prediction from the points before it in raster order (R12) */
   int32_t *q = (int32_t *)malloc(h.n * sizeof(int32_t));
   if (!q) { free(p); free(q0); return OR_ERR_ARG; }
   for (uint64_t e = 0; e < h.n; e++) {
     uint64_t b = e / S;
-    if (h.flags & 1u) q[e] = q0[b] + p[e];
-    else q[e] = (e % S == 0) ? q0[b] : q[e - 1] + p[e];
+    if (lorenzo) {
+      const uint64_t z = e / (Y * X), y = (e / X) % Y, x = e % X;
+      int64_t v = p[e];
+      for (int c = 1; c < 8; c++) {
+        const int dz = (c >> 2) & 1, dy = (c >> 1) & 1, dx = c & 1;
+        if ((dz && z == 0) || (dy && y == 0) || (dx && x == 0)) continue;
+        const int64_t u = q[((z - dz) * Y + (y - dy)) * X + (x - dx)];
+        v += ((dz + dy + dx) & 1) ? u : -u;
+      }
+      if (v > OR_QMAX || v < -OR_QMAX) { free(q); free(p); free(q0); return OR_ERR_STREAM; }
+      q[e] = (int32_t)v;
+    } else if (h.flags & OR_FLAG_MEAN) {
+      q[e] = q0[b] + p[e];
+    } else {
+      q[e] = (e % S == 0) ? q0[b] : q[e - 1] + p[e];
+    }
   }
   free(p); free(q0);
   if (stage == 3) { memcpy(out, q, h.n * sizeof(int32_t)); free(q); return OR_OK; }
@@ -796,6 +932,130 @@ int or_var_mt(const uint8_t *buf, uint64_t len, int64_t *n, int64_t *msum, int64
   *s2_lo = (uint64_t)acc;
   *s2_hi = (int64_t)(acc >> 64);
   *var = h.n > 1 ? (double)acc / (double)(h.n - 1) * (h.quantum * h.quantum) : NAN;
+  return OR_OK;
+}
+
+/* ---- HSZp-nd on its decorrelated data D_p (Sec. V) ------------------------
+ * p is stage 2 of an HSZp-nd stream (the field's layout); dims are the
+ * field's own (ndim of them, slow -> fast).  q at index -1 of any axis is 0. */
+
+static void dims3_from(uint32_t ndim, const uint64_t *dims, uint64_t d[3]) {
+  for (int k = 0; k < 3; k++) d[k] = 1;
+  for (uint32_t k = 0; k < ndim; k++) d[3 - ndim + k] = dims[k];
+}
+
+/* Sec. V-A, mean on D_p of HSZp-nd: q is the nd prefix sum of p, so
+ * sum q = sum over points of prod_k (n_k - i_k) p_i (0-based i_k; the
+ * paper's 2D weights (n_1 - s + 1)(n_2 - t + 1) with 1-based s, t). */
+int or_lz_mean_p(const int32_t *p, uint32_t ndim, const uint64_t *dims, double quantum, int64_t *s1,
+                 double *mean) {
+  if (!p || !dims || ndim < 1 || ndim > 3) return OR_ERR_ARG;
+  uint64_t d[3];
+  dims3_from(ndim, dims, d);
+  __int128 acc = 0;
+  for (uint64_t z = 0; z < d[0]; z++)
+    for (uint64_t y = 0; y < d[1]; y++)
+      for (uint64_t x = 0; x < d[2]; x++) {
+        const __int128 w = (__int128)(d[0] - z) * (__int128)(d[1] - y) * (__int128)(d[2] - x);
+        acc += w * p[(z * d[1] + y) * d[2] + x];
+      }
+  const uint64_t n = d[0] * d[1] * d[2];
+  *s1 = (int64_t)acc;
+  *mean = (double)acc / (double)n * quantum;
+  return OR_OK;
+}
+
+/* Alg. 4 (standard deviation with D_p, written for 2D) in the 3D view: per
+ * plane, a running sum along the row (prefSum) and a column buffer (colSum)
+ * rebuild the plane's 2D Lorenzo prefix sums r; a plane buffer adds r over
+ * the planes, giving q = q(z-1) + r (for a 2D field the plane buffer is
+ * zero before the only plane, which is Alg. 4 itself).  s1 = sum q and
+ * s2 = sum q^2 are exact; var as Eq. (var) with N - 1, rounded once from
+ * (n s2 - s1^2) / (n (n - 1)) Delta^2. */
+int or_lz_var_p(const int32_t *p, uint32_t ndim, const uint64_t *dims, double quantum, int64_t *n_out,
+                int64_t *s1, uint64_t *s2_lo, int64_t *s2_hi, double *var) {
+  if (!p || !dims || ndim < 1 || ndim > 3) return OR_ERR_ARG;
+  uint64_t d[3];
+  dims3_from(ndim, dims, d);
+  const uint64_t Y = d[1], X = d[2];
+  int64_t *plane = (int64_t *)calloc(Y * X, sizeof(int64_t));
+  int64_t *col = (int64_t *)calloc(X, sizeof(int64_t));
+  if (!plane || !col) { free(plane); free(col); return OR_ERR_ARG; }
+  int64_t a1 = 0;
+  __int128 a2 = 0;
+  for (uint64_t z = 0; z < d[0]; z++) {
+    for (uint64_t x = 0; x < X; x++) col[x] = 0;
+    for (uint64_t y = 0; y < Y; y++) {
+      int64_t pref = 0;
+      for (uint64_t x = 0; x < X; x++) {
+        pref += p[(z * Y + y) * X + x];
+        col[x] += pref;
+        plane[y * X + x] += col[x];
+        const int64_t q = plane[y * X + x];
+        a1 += q;
+        a2 += (__int128)q * q;
+      }
+    }
+  }
+  free(plane);
+  free(col);
+  const int64_t n = (int64_t)(d[0] * Y * X);
+  *n_out = n;
+  *s1 = a1;
+  *s2_lo = (uint64_t)a2;
+  *s2_hi = (int64_t)(a2 >> 64);
+  const __int128 num = (__int128)n * a2 - (__int128)a1 * a1;
+  *var = n > 1 ? (double)num / ((double)n * (double)(n - 1)) * (quantum * quantum) : NAN;
+  return OR_OK;
+}
+
+/* Eq. (derivative_Dp) in the 3D view: along axis a (of the field's axes),
+ * q_{i+1} - q_{i-1} is the prefix sum over the other axes of
+ * t_i = p_i + p_{i+1}; the one-sided ends (R7) use 2 (q_1 - q_0) with
+ * t_0 = 2 p_1 and 2 (q_{n-1} - q_{n-2}) with t = 2 p_{n-1}; an axis of
+ * length 1 has t = 0.  The prefix sums follow the paper's recursion: along
+ * the fastest other axis a running sum per point (the scalar eta), then a
+ * running sum per column over the slower other axis.  num holds the exact
+ * integers; out = num * Delta / 2 (the paper's factor eps_q). */
+int or_lz_deriv_p(const int32_t *p, uint32_t ndim, const uint64_t *dims, int axis, double quantum, int64_t *num,
+                  double *out) {
+  if (!p || !dims || !num || !out || ndim < 1 || ndim > 3 || axis < 0 || axis >= (int)ndim) return OR_ERR_ARG;
+  uint64_t d[3];
+  dims3_from(ndim, dims, d);
+  const int a = axis + 3 - (int)ndim;
+  const uint64_t na = d[a];
+  /* t along axis a */
+  for (uint64_t z = 0; z < d[0]; z++)
+    for (uint64_t y = 0; y < d[1]; y++)
+      for (uint64_t x = 0; x < d[2]; x++) {
+        const uint64_t c[3] = {z, y, x};
+        const uint64_t i = c[a];
+        uint64_t cn[3] = {z, y, x};
+        int64_t t;
+        if (na == 1) {
+          t = 0;
+        } else if (i == 0) {
+          cn[a] = 1;
+          t = 2 * (int64_t)p[(cn[0] * d[1] + cn[1]) * d[2] + cn[2]];
+        } else if (i == na - 1) {
+          t = 2 * (int64_t)p[(z * d[1] + y) * d[2] + x];
+        } else {
+          cn[a] = i + 1;
+          t = (int64_t)p[(z * d[1] + y) * d[2] + x] + p[(cn[0] * d[1] + cn[1]) * d[2] + cn[2]];
+        }
+        num[(z * d[1] + y) * d[2] + x] = t;
+      }
+  /* prefix sums over each of the other axes, fastest first */
+  for (int o = 2; o >= 0; o--) {
+    if (o == a) continue;
+    const uint64_t stride = o == 2 ? 1 : (o == 1 ? d[2] : d[1] * d[2]);
+    for (uint64_t e = 0; e < d[0] * d[1] * d[2]; e++) {
+      const uint64_t c[3] = {e / (d[1] * d[2]), (e / d[2]) % d[1], e % d[2]};
+      if (c[o] > 0) num[e] += num[e - stride];
+    }
+  }
+  const double half = quantum * 0.5;
+  for (uint64_t e = 0; e < d[0] * d[1] * d[2]; e++) out[e] = (double)num[e] * half;
   return OR_OK;
 }
 

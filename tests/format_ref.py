@@ -11,7 +11,9 @@ Format (little-endian):
   widths, payload), u64 payload words, u64 total bytes.
   sections, each 256-byte aligned: u64 chunk_off[nchunks+1] (payload word
   index of each 64-block chunk's first block, then the total);
-  i32 q0[nb]; u8 width[nb]; u32 payload[].
+  i32 q0[nb] (absent when flags bit 1, HSZp-nd, is set); u8 width[nb];
+  u32 payload[].  'pblocks' returns every block's S values of p in slot
+  order; p and q read the blocks in order (the 1D partition).
   block with width w > 0: ceil(S/32) sign words (bit i set iff p_i < 0),
   then ceil(S*w/32) magnitude words, element i in stream bits
   [i*w, i*w+w), bit k = bit k%32 of word k//32.  w = 0: no words.
@@ -35,7 +37,8 @@ def parse(buf: bytes):
     max_abs_q, flags = struct.unpack_from("<2I", buf, 88)
     nb, nchunks, off_chunk, off_q0, off_width, off_payload, pwords, total = struct.unpack_from("<8Q", buf, 96)
     chunk_off = struct.unpack_from(f"<{nchunks + 1}Q", buf, off_chunk)
-    q0 = list(struct.unpack_from(f"<{nb}i", buf, off_q0))
+    nd = bool(flags & 2)  # HSZp-nd: no q0 section, blocks of the nd partition
+    q0 = [] if nd else list(struct.unpack_from(f"<{nb}i", buf, off_q0))
     width = list(buf[off_width:off_width + nb])
     payload = struct.unpack_from(f"<{pwords}I", buf, off_payload)
     p = [0] * (nb * S)
@@ -59,12 +62,14 @@ def parse(buf: bytes):
         pos += nsign + nmag
     assert chunk_off[nchunks] == pos == pwords
     assert total == off_payload + 4 * pwords
+    pblocks = np.array(p, dtype=np.int64).reshape(nb, S)
     p = p[:n]
     q = []
-    for e in range(n):
-        q.append(q0[e // S] if e % S == 0 else q[-1] + p[e])
+    if not nd:
+        for e in range(n):
+            q.append(q0[e // S] if e % S == 0 else q[-1] + p[e])
     return dict(version=version, dtype=dtype, ndim=ndim, dims=dims, n=n, S=S, eps=eps,
                 quantum=quantum, inv_quantum=inv_quantum, vmin=vmin, vmax=vmax,
                 max_abs_q=max_abs_q, flags=flags, nb=nb, nchunks=nchunks, q0=q0, width=width,
                 payload=list(payload), p=np.array(p, dtype=np.int64), q=np.array(q, dtype=np.int64),
-                total=total)
+                total=total, pblocks=pblocks, off_q0=off_q0, off_width=off_width)
