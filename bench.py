@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--no-vector", action="store_true", help="skip the vector-field (divergence, curl) workload")
     ap.add_argument("--no-hszx", action="store_true", help="skip the block-mean (HSZx) workload")
+    ap.add_argument("--no-lorenzo", action="store_true", help="skip the HSZp-nd (Lorenzo) workload")
     ap.add_argument("--snapshots", type=int, default=64)
     ap.add_argument("--queries", type=int, default=20000)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -347,6 +348,9 @@ def main():
     if not a.no_hszx:
         out["block_mean"] = bench_hszx(a, log)
         torch.cuda.empty_cache()
+    if not a.no_lorenzo:
+        out["lorenzo_nd"] = bench_lorenzo(a, log)
+        torch.cuda.empty_cache()
     if not a.no_batch:
         out["batching"] = bench_batches(a, log)
         torch.cuda.empty_cache()
@@ -499,6 +503,59 @@ def bench_hszx(a, log):
         del c, ws
     log(f"[bench] block-mean: {res}")
     del x, gbuf, qbuf, fbuf
+    return res
+
+
+def bench_lorenzo(a, log):
+    """The step's 512^3 binary32 field as an HSZp-nd stream (rel eb 1e-4,
+    S=32, 2x4x4 blocks): compression time and ratio, decoding to each stage,
+    the mean with nd weights and Alg. 4 on D_p, the derivative along each
+    axis on D_p (Eq. (derivative_Dp)) against the same derivative from D_q
+    (decode to D_q + stencil) and after full decompression."""
+    import torch
+
+    from paper_2603_25206_amd import hsz, synth
+
+    shape = tuple(int(v) for v in a.shape.split(","))
+    x = synth.make_field_torch(synth.large_field_spec(seed=0, shape=shape), "cuda")
+    dev, cur = x.device, torch.cuda.current_stream()
+    orig = x.numel() * x.element_size()
+    n = x.numel()
+    c = hsz.compress(x, a.eb, rel=True, block=a.block, lorenzo=True)
+    torch.cuda.synchronize()
+    h = c.header
+    ws = hsz.workspace(hsz.op_workspace_bytes(h, hsz.DERIV), dev, key="bench-lz")
+    s48 = torch.empty(64, dtype=torch.uint8, device=dev)
+    obuf = torch.empty(4 * n, dtype=torch.uint8, device=dev)
+    sbuf = torch.empty(4 * n, dtype=torch.uint8, device=dev)
+    res = {"shape": list(shape), "orig_bytes": orig, "ratio": round(c.ratio, 3),
+           "compress_ms": round(_events_ms(lambda: hsz.compress(x, a.eb, rel=True, block=a.block, lorenzo=True), 5,
+                                           cur), 4)}
+    for st, name in ((hsz.DELTA, "decode_p_ms"), (hsz.QUANT, "decode_q_ms"), (hsz.FLOAT, "decode_f_ms")):
+        res[name] = round(_events_ms(lambda: hsz.decompress_to_stage(c, st, out=sbuf), 5, cur), 4)
+    res["mean_p_ms"] = round(_events_ms(lambda: hsz.op_fused(c, hsz.DELTA, hsz.MEAN, out=s48, ws=ws, check=False,
+                                                             raw=True), 10, cur), 4)
+    res["var_p_ms"] = round(_events_ms(lambda: hsz.op_fused(c, hsz.DELTA, hsz.VAR, out=s48, ws=ws, check=False,
+                                                            raw=True), 10, cur), 4)
+    fview = hsz.stage_view(sbuf, h, hsz.FLOAT)
+    qview = hsz.stage_view(sbuf, h, hsz.QUANT)
+    for ax in range(len(shape)):
+        r = {}
+        r["via_p_ms"] = round(_events_ms(lambda: hsz.op_fused(c, hsz.DELTA, hsz.DERIV, axis=ax, out=obuf, ws=ws,
+                                                              check=False, raw=True), 5, cur), 4)
+
+        def via_q():
+            hsz.decompress_to_stage(c, hsz.QUANT, out=sbuf)
+            hsz.op_on_stage(qview, h, hsz.QUANT, hsz.DERIV, axis=ax, out=obuf, ws=ws, check=False, raw=True)
+
+        def full():
+            hsz.decompress_to_stage(c, hsz.FLOAT, out=sbuf)
+            hsz.op_on_stage(fview, h, hsz.FLOAT, hsz.DERIV, axis=ax, out=obuf, ws=ws, check=False, raw=True)
+        r["decode_q_then_deriv_ms"] = round(_events_ms(via_q, 5, cur), 4)
+        r["full_decompress_then_deriv_ms"] = round(_events_ms(full, 5, cur), 4)
+        res[f"deriv_axis{ax}"] = r
+    log(f"[bench] lorenzo-nd: {res}")
+    del x, c, ws, obuf, sbuf
     return res
 
 

@@ -75,7 +75,7 @@ typedef struct hsz_header {
   double inv_quantum;     /* 1 / Delta, the quantizer's multiplier           */
   double vmin, vmax;      /* extremes of the input field                     */
   uint32_t max_abs_q;     /* max |q| over the field                          */
-  uint32_t flags;         /* 0, or HSZ_FLAG_BLOCK_MEAN (block-mean mode)     */
+  uint32_t flags;         /* 0, HSZ_FLAG_BLOCK_MEAN or HSZ_FLAG_LORENZO      */
   int64_t nb;             /* number of blocks = ceil(n / S)                  */
   int64_t nchunks;        /* ceil(nb / 64)                                   */
   uint64_t off_chunk;     /* byte offsets of the sections in the stream      */
@@ -137,10 +137,11 @@ int hsz_read_status(const void *d_workspace, void *stream, int *h_status);
  * Delta = 2*(eps - m*ulp(max|x| + eps)) with m = 1 (binary32) or 8
  * (binary64), so |x - x'| <= eps holds for every element after rounding. */
 
-/* Worst-case stream size for a field (bytes). */
+/* Worst-case stream size for a field (bytes), in any decorrelation mode
+ * (for 2D and 3D fields the larger of the 1D and the nd partition). */
 int hsz_compress_bound(int dtype, int ndim, const int64_t *h_dims, int block, uint64_t *h_bytes);
 
-/* Workspace hsz_compress needs (bytes). */
+/* Workspace hsz_compress / hsz_compress_flags need (bytes), any mode. */
 int hsz_compress_workspace(int ndim, const int64_t *h_dims, int block, uint64_t *h_bytes);
 
 /* Compress d_x (dtype, dims) into d_out (capacity 'cap' bytes, at least
@@ -163,6 +164,22 @@ int hsz_compress(const void *d_x, int dtype, int ndim, const int64_t *h_dims, do
  * stencil operations; fused stencils, vector fields and batches return
  * HSZ_ERR_UNSUPPORTED for them. */
 #define HSZ_FLAG_BLOCK_MEAN 1u
+/* HSZ_FLAG_LORENZO selects HSZp-nd (Sec. IV) for 2D and 3D fields: the
+ * Lorenzo residual over the whole field, p = sum over the corners c of
+ * {0,1}^d of (-1)^|c| q(i - c) with q = 0 before index 0 on every axis (the
+ * paper's 2D and 3D formulas), encoded in nd blocks of S elements (2D: 4x8
+ * for S = 32, 8x8 for 64; 3D: 2x4x4, 4x4x4; blocks and their slots in
+ * raster order, slots outside the field 0).  There is no metadata: stage 1
+ * is HSZ_ERR_UNSUPPORTED and the stage-2 buffer is p int32[n] in the field's
+ * layout.  A residual beyond 2^30 - 1 is HSZ_ERR_RANGE (status word).  On
+ * stage 2 (materialised or fused, whole field only): HSZ_MEAN through the
+ * nd weights of Sec. V-A, HSZ_VAR through the prefix sums of Alg. 4, and
+ * HSZ_DERIV along any axis through Eq. (derivative_Dp); stages 3 and 4
+ * take every operation of a delta stream.  The fused routes rebuild what
+ * they need in the workspace (hsz_op_workspace: 4 bytes per point, 8 for
+ * binary64 fields, beyond the operation's own).  Batches, block indexes and
+ * fused vector fields return HSZ_ERR_UNSUPPORTED for these streams. */
+#define HSZ_FLAG_LORENZO 2u
 int hsz_compress_flags(const void *d_x, int dtype, int ndim, const int64_t *h_dims, double eb,
                        int eb_is_rel, int block, uint32_t flags, void *d_out, uint64_t cap,
                        void *d_workspace, uint64_t workspace_bytes, void *stream);

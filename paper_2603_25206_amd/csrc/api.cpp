@@ -1,6 +1,7 @@
 // api.cpp -- the C ABI of libhsz (declared in include/hsz.h): argument and
 // stream validation on the host, then stream-ordered kernel launches.
 #include "abi_util.hpp"
+#include "hsz_nd.hpp"
 
 namespace hsz_abi {
 int& last_hip() {
@@ -26,6 +27,30 @@ bool meta_mean_ok(const hsz_header* h, int op, const hsz::OpTarget& t) {
 }
 
 bool is_stats(int op) { return op == HSZ_MEAN || op == HSZ_VAR || op == HSZ_VAR_MT; }
+
+bool whole_box(const hsz::OpTarget& t) {
+  const hsz::Box3& b = t.box;
+  return b.z0 == 0 && b.y0 == 0 && b.x0 == 0 && b.z1 == t.d.z && b.y1 == t.d.y && b.x1 == t.d.x;
+}
+
+bool is_nd(const hsz_header* h) { return (h->flags & HSZ_FLAG_LORENZO) != 0; }
+
+hsz::NdGrid grid_of(const hsz_header* h) {
+  int64_t d3[3], n;
+  dims3_of(h->ndim, h->dims, d3, &n);
+  return hsz::nd_grid(d3, h->ndim, h->block);
+}
+
+// HSZp-nd streams: the fused routes and the D_p operations rebuild a stage
+// in scratch memory after the operation's own workspace (4 bytes per point,
+// 8 for the binary64 floats of stage 4).
+uint64_t nd_scratch_off(const hsz_header* h) {
+  const uint64_t a = hsz::op_workspace_bytes(), b = hsz::grad_workspace_bytes(h->nb);
+  return ((a > b ? a : b) + 255) / 256 * 256;
+}
+uint64_t nd_workspace(const hsz_header* h) {
+  return nd_scratch_off(h) + (h->dtype == HSZ_F64 ? 8 : 4) * (uint64_t)h->n;
+}
 bool is_stencil(int op) { return op >= HSZ_DERIV && op <= HSZ_LAPLACIAN; }
 
 // The spread about the integer metadata mean (Sec. V-A, standard deviation
@@ -72,6 +97,49 @@ int op_common(const hsz_header* h, int op, int axis, const hsz_box* box, uint64_
   return HSZ_OK;
 }
 
+// Operations on HSZp-nd streams.  d_c != nullptr: fused from the stream
+// through 'stage' (decoded into the scratch area as far as needed); else on
+// the caller's stage buffer d_stage.  Stage 2 (D_p, whole field): the mean
+// with nd weights, Alg. 4 and Eq. (derivative_Dp) along any axis; stages 3
+// and 4 hold the field's layout, so the kernels of delta streams apply.
+int nd_op(const void* d_c, const void* d_stage, const hsz_header* h, int stage, int op, int axis3,
+          const hsz::OpTarget& t, void* d_result, void* d_ws, uint64_t ws_bytes, hipStream_t s) {
+  if (stage == HSZ_META) return HSZ_ERR_UNSUPPORTED;  // no metadata
+  if (stage < HSZ_DELTA || stage > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
+  if (op == HSZ_VAR_MT) return HSZ_ERR_UNSUPPORTED;  // block-mean streams only
+  if (stage == HSZ_DELTA && (!whole_box(t) || !(op == HSZ_MEAN || op == HSZ_VAR || op == HSZ_DERIV)))
+    return HSZ_ERR_UNSUPPORTED;
+  if (op == HSZ_LAPLACIAN && stage == HSZ_QUANT && h->max_abs_q >= kLapMaxQ) return HSZ_ERR_UNSUPPORTED;
+  if (ws_bytes < nd_workspace(h)) return HSZ_ERR_CAPACITY;
+  uint8_t* ws = (uint8_t*)d_ws;
+  int32_t* scratch = (int32_t*)(ws + nd_scratch_off(h));
+  const hsz::StreamView v = view_of(d_c, h);
+  const hsz::NdGrid g = grid_of(h);
+  int rc = reset_status(d_ws, s);
+  if (rc) return rc;
+  hipError_t e = hipSuccess;
+  if (stage == HSZ_DELTA && op != HSZ_DERIV) {
+    e = hsz::launch_lz_stats(d_c ? nullptr : (const int32_t*)d_stage, v, g, op, d_result, ws, scratch, s);
+  } else if (stage == HSZ_DELTA) {
+    const int32_t* p = (const int32_t*)d_stage;
+    if (d_c) {
+      e = hsz::lz_decode(v, g, HSZ_DELTA, scratch, (int*)d_ws, s);
+      p = scratch;
+    }
+    if (e == hipSuccess) e = hsz::lz_deriv_p(p, v, g, axis3, d_result, s);
+  } else {
+    const void* buf = d_stage;
+    if (d_c) {
+      e = hsz::lz_decode(v, g, stage, scratch, (int*)d_ws, s);
+      buf = scratch;
+    }
+    if (e == hipSuccess)
+      e = is_stats(op) ? hsz::launch_stats_stage(buf, stage, v, op, t, d_result, ws, s)
+                       : hsz::launch_grad_stage(buf, stage, v, op, axis3, t, d_result, ws, s);
+  }
+  return e == hipSuccess ? HSZ_OK : hip_fail(e);
+}
+
 }  // namespace
 
 extern "C" {
@@ -111,8 +179,16 @@ int hsz_compress_bound(int dtype, int ndim, const int64_t* h_dims, int block, ui
   if (!h_bytes || (dtype != HSZ_F32 && dtype != HSZ_F64) || !dims3_of(ndim, h_dims, d3, &n))
     return HSZ_ERR_INVALID_ARG;
   if (!valid_block(block)) return HSZ_ERR_UNSUPPORTED;
-  hsz::Layout L = hsz::make_layout(n, block);
-  *h_bytes = L.off_payload + 4 * (uint64_t)L.nb * (uint64_t)((block / 32) * (1 + hsz::kMaxWidth));
+  // the larger of the 1D partition and (2D / 3D fields) the nd partition
+  const uint64_t per_block = 4 * (uint64_t)((block / 32) * (1 + hsz::kMaxWidth));
+  const hsz::Layout L = hsz::make_layout(n, block);
+  uint64_t bound = L.off_payload + per_block * (uint64_t)L.nb;
+  if (ndim >= 2) {
+    const hsz::Layout Ln = hsz::make_layout_nd(d3, ndim, block);
+    const uint64_t bn = Ln.off_payload + per_block * (uint64_t)Ln.nb;
+    bound = bn > bound ? bn : bound;
+  }
+  *h_bytes = bound;
   return HSZ_OK;
 }
 
@@ -120,7 +196,12 @@ int hsz_compress_workspace(int ndim, const int64_t* h_dims, int block, uint64_t*
   int64_t d3[3], n;
   if (!h_bytes || !dims3_of(ndim, h_dims, d3, &n)) return HSZ_ERR_INVALID_ARG;
   if (!valid_block(block)) return HSZ_ERR_UNSUPPORTED;
-  *h_bytes = hsz::compress_workspace_bytes(hsz::make_layout(n, block));
+  uint64_t w = hsz::compress_workspace_bytes(hsz::make_layout(n, block));
+  if (ndim >= 2) {
+    const uint64_t wn = hsz::compress_workspace_bytes(hsz::make_layout_nd(d3, ndim, block));
+    w = wn > w ? wn : w;
+  }
+  *h_bytes = w;
   return HSZ_OK;
 }
 
@@ -134,13 +215,14 @@ int hsz_compress_flags(const void* d_x, int dtype, int ndim, const int64_t* h_di
                        int block, uint32_t flags, void* d_out, uint64_t cap, void* d_workspace,
                        uint64_t workspace_bytes, void* stream) {
   int64_t d3[3], n;
-  if (flags > HSZ_FLAG_BLOCK_MEAN) return HSZ_ERR_INVALID_ARG;
+  if (flags != 0 && flags != HSZ_FLAG_BLOCK_MEAN && flags != HSZ_FLAG_LORENZO) return HSZ_ERR_INVALID_ARG;
   if (!d_x || !d_out || !d_workspace || (dtype != HSZ_F32 && dtype != HSZ_F64) || !dims3_of(ndim, h_dims, d3, &n))
     return HSZ_ERR_INVALID_ARG;
   if (!aligned16(d_x) || !aligned16(d_out) || !aligned16(d_workspace)) return HSZ_ERR_INVALID_ARG;
   if (!valid_block(block)) return HSZ_ERR_UNSUPPORTED;
+  if (flags == HSZ_FLAG_LORENZO && ndim < 2) return HSZ_ERR_UNSUPPORTED;  // the nd partition needs 2D / 3D
   if (!(eb > 0.0) || eb != eb || eb > 1e300) return HSZ_ERR_EB;
-  hsz::Layout L = hsz::make_layout(n, block);
+  hsz::Layout L = flags == HSZ_FLAG_LORENZO ? hsz::make_layout_nd(d3, ndim, block) : hsz::make_layout(n, block);
   if (workspace_bytes < hsz::compress_workspace_bytes(L)) return HSZ_ERR_CAPACITY;
   if (cap < L.off_payload) return HSZ_ERR_CAPACITY;
   hsz::CompressArgs a;
@@ -158,7 +240,8 @@ int hsz_compress_flags(const void* d_x, int dtype, int ndim, const int64_t* h_di
   a.cap = cap;
   a.ws = (uint8_t*)d_workspace;
   a.ws_bytes = workspace_bytes;
-  hipError_t e = hsz::launch_compress(a, (hipStream_t)stream);
+  hipError_t e = flags == HSZ_FLAG_LORENZO ? hsz::launch_compress_nd(a, (hipStream_t)stream)
+                                           : hsz::launch_compress(a, (hipStream_t)stream);
   return e == hipSuccess ? HSZ_OK : hip_fail(e);
 }
 
@@ -190,7 +273,7 @@ int hsz_read_header(const void* h_bytes, uint64_t len, uint64_t len_stream, hsz_
   h.vmax = rdf64(p + 80);
   h.max_abs_q = rd32(p + 88);
   h.flags = rd32(p + 92);
-  if (h.flags > HSZ_FLAG_BLOCK_MEAN) return HSZ_ERR_BAD_STREAM;
+  if (h.flags != 0 && h.flags != HSZ_FLAG_BLOCK_MEAN && h.flags != HSZ_FLAG_LORENZO) return HSZ_ERR_BAD_STREAM;
   h.nb = (int64_t)rd64(p + 96);
   h.nchunks = (int64_t)rd64(p + 104);
   h.off_chunk = rd64(p + 112);
@@ -204,15 +287,15 @@ int hsz_read_header(const void* h_bytes, uint64_t len, uint64_t len_stream, hsz_
   int64_t dd[3], n;
   if (!dims3_of(h.ndim, h.dims, dd, &n) || n != h.n) return HSZ_ERR_BAD_STREAM;
   if (!(h.quantum > 0.0) || h.max_abs_q > (uint32_t)hsz::kQMax) return HSZ_ERR_BAD_STREAM;
-  // layout depends only on n and S
-  const int64_t nb = (h.n + h.block - 1) / h.block;
-  const int64_t nch = (nb + 63) / 64;
-  const uint64_t oc = HSZ_HEADER_BYTES;
-  const uint64_t oq = (oc + 8 * (uint64_t)(nch + 1) + 255) / 256 * 256;
-  const uint64_t ow = (oq + 4 * (uint64_t)nb + 255) / 256 * 256;
-  const uint64_t op = (ow + (uint64_t)nb + 255) / 256 * 256;
-  if (h.nb != nb || h.nchunks != nch || h.off_chunk != oc || h.off_q0 != oq || h.off_width != ow ||
-      h.off_payload != op)
+  // the layout follows from n and S (the 1D partition) or from the dims and S
+  // (the nd partition of HSZp-nd, which has no q0 section)
+  if (h.flags == HSZ_FLAG_LORENZO && (h.ndim < 2 || (h.block != 32 && h.block != 64))) return HSZ_ERR_BAD_STREAM;
+  const hsz::Layout L = h.flags == HSZ_FLAG_LORENZO ? hsz::make_layout_nd(dd, h.ndim, h.block)
+                                                    : hsz::make_layout(h.n, h.block);
+  const int64_t nb = L.nb;
+  const uint64_t op = L.off_payload;
+  if (h.nb != L.nb || h.nchunks != L.nchunks || h.off_chunk != L.off_chunk || h.off_q0 != L.off_q0 ||
+      h.off_width != L.off_width || h.off_payload != L.off_payload)
     return HSZ_ERR_BAD_STREAM;
   if (h.payload_words > (uint64_t)nb * 64 || h.total_bytes != op + 4 * h.payload_words) return HSZ_ERR_BAD_STREAM;
   if (h.total_bytes > len_stream) return HSZ_ERR_BAD_STREAM;
@@ -223,9 +306,13 @@ int hsz_read_header(const void* h_bytes, uint64_t len, uint64_t len_stream, hsz_
 int hsz_stage_bytes(const hsz_header* h, int stage, uint64_t* h_bytes) {
   if (!h || !h_bytes) return HSZ_ERR_INVALID_ARG;
   const uint64_t n = (uint64_t)h->n, nb = (uint64_t)h->nb;
+  const bool nd = (h->flags & HSZ_FLAG_LORENZO) != 0;  // HSZp-nd: no metadata
   switch (stage) {
-    case HSZ_META: *h_bytes = 4 * nb; return HSZ_OK;
-    case HSZ_DELTA: *h_bytes = 4 * n + 4 * nb; return HSZ_OK;
+    case HSZ_META:
+      if (nd) return HSZ_ERR_UNSUPPORTED;
+      *h_bytes = 4 * nb;
+      return HSZ_OK;
+    case HSZ_DELTA: *h_bytes = 4 * n + (nd ? 0 : 4 * nb); return HSZ_OK;
     case HSZ_QUANT: *h_bytes = 4 * n; return HSZ_OK;
     case HSZ_FLOAT: *h_bytes = (h->dtype == HSZ_F32 ? 4 : 8) * n; return HSZ_OK;
   }
@@ -240,11 +327,12 @@ int hsz_decompress_to_stage(const void* d_c, const hsz_header* h, int stage, voi
     return HSZ_ERR_INVALID_ARG;
   if (workspace_bytes < 256) return HSZ_ERR_CAPACITY;
   uint64_t need = 0;
-  if (hsz_stage_bytes(h, stage, &need)) return HSZ_ERR_INVALID_ARG;
+  if ((rc = hsz_stage_bytes(h, stage, &need))) return rc == HSZ_ERR_UNSUPPORTED ? rc : HSZ_ERR_INVALID_ARG;
   if (cap < need) return HSZ_ERR_CAPACITY;
   hipStream_t s = (hipStream_t)stream;
   if ((rc = reset_status(d_workspace, s))) return rc;
-  hipError_t e = hsz::launch_decode(view_of(d_c, h), stage, d_out, (int*)d_workspace, s);
+  hipError_t e = is_nd(h) ? hsz::lz_decode(view_of(d_c, h), grid_of(h), stage, d_out, (int*)d_workspace, s)
+                          : hsz::launch_decode(view_of(d_c, h), stage, d_out, (int*)d_workspace, s);
   return e == hipSuccess ? HSZ_OK : hip_fail(e);
 }
 
@@ -261,6 +349,7 @@ int hsz_block_index(const void* d_c, const hsz_header* h, void* d_index, uint64_
   if (rc) return rc;
   if (!d_c || !d_index || !aligned16(d_c) || !aligned16(d_index)) return HSZ_ERR_INVALID_ARG;
   if (cap < 2 * (uint64_t)h->nb) return HSZ_ERR_CAPACITY;
+  if (is_nd(h)) return HSZ_ERR_UNSUPPORTED;  // the index serves the fused tiles of 1D partitions
   hipError_t e = hsz::launch_block_index(view_of(d_c, h), (uint16_t*)d_index, (hipStream_t)stream);
   return e == hipSuccess ? HSZ_OK : hip_fail(e);
 }
@@ -269,6 +358,7 @@ int hsz_op_workspace(const hsz_header* h, int op, uint64_t* h_bytes) {
   if (!h || !h_bytes || (!is_stats(op) && !is_stencil(op))) return HSZ_ERR_INVALID_ARG;
   uint64_t a = hsz::op_workspace_bytes(), b = hsz::grad_workspace_bytes(h->nb);
   *h_bytes = (is_stencil(op) && b > a) ? b : a;
+  if (is_nd(h)) *h_bytes = nd_workspace(h);
   return HSZ_OK;
 }
 
@@ -279,6 +369,8 @@ int hsz_op_on_stage(const void* d_stage, const hsz_header* h, int stage, int op,
   int rc = op_common(h, op, axis, h_box, cap, d_result, d_workspace, workspace_bytes, &t, &axis3);
   if (rc) return rc;
   if (!d_stage || !aligned16(d_stage)) return HSZ_ERR_INVALID_ARG;
+  if (is_nd(h))
+    return nd_op(nullptr, d_stage, h, stage, op, axis3, t, d_result, d_workspace, workspace_bytes, (hipStream_t)stream);
   if (stage == HSZ_META && !meta_mean_ok(h, op, t)) return HSZ_ERR_UNSUPPORTED;
   if (stage < HSZ_META || stage > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
   if (op == HSZ_VAR_MT && !var_mt_ok(h, t, stage, false)) return HSZ_ERR_UNSUPPORTED;
@@ -304,6 +396,8 @@ int hsz_op_fused(const void* d_c, const hsz_header* h, int via, int op, int axis
   int rc = op_common(h, op, axis, h_box, cap, d_result, d_workspace, workspace_bytes, &t, &axis3);
   if (rc) return rc;
   if (!d_c || !aligned16(d_c)) return HSZ_ERR_INVALID_ARG;
+  if (is_nd(h))
+    return nd_op(d_c, nullptr, h, via, op, axis3, t, d_result, d_workspace, workspace_bytes, (hipStream_t)stream);
   if (via == HSZ_META && !meta_mean_ok(h, op, t)) return HSZ_ERR_UNSUPPORTED;
   if (via < HSZ_META || via > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
   if (op == HSZ_VAR_MT && !var_mt_ok(h, t, via, true)) return HSZ_ERR_UNSUPPORTED;
@@ -408,7 +502,7 @@ int hsz_vector_op_fused(const void* const* d_c, const hsz_header* const* h, int 
   if (via != HSZ_QUANT) return HSZ_ERR_INVALID_ARG;
   for (int c = 0; c < ncomp; ++c) {
     if (!d_c[c] || !aligned16(d_c[c])) return HSZ_ERR_INVALID_ARG;
-    if (h[c]->flags & HSZ_FLAG_BLOCK_MEAN) return HSZ_ERR_UNSUPPORTED;  // fused windows decode delta streams
+    if (h[c]->flags) return HSZ_ERR_UNSUPPORTED;  // fused windows decode delta streams
     j.v[c] = view_of(d_c[c], h[c]);
   }
   hipStream_t s = (hipStream_t)stream;

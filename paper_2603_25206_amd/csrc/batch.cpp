@@ -77,7 +77,7 @@ int classify(const hsz_work& w, Item* it) {
   it->out = w.d_result;
   it->index = (const uint16_t*)w.d_index;
   if (w.d_index && ((uintptr_t)w.d_index & 1u)) return HSZ_ERR_INVALID_ARG;
-  if (h->flags & HSZ_FLAG_BLOCK_MEAN) return HSZ_ERR_UNSUPPORTED;  // batch kernels decode delta streams
+  if (h->flags) return HSZ_ERR_UNSUPPORTED;  // batch kernels decode delta streams
   if (w.op == HSZ_MEAN || w.op == HSZ_VAR) {
     if (w.via != HSZ_DELTA && w.via != HSZ_QUANT) return HSZ_ERR_UNSUPPORTED;  // exact integer routes only
     if (w.result_bytes < sizeof(hsz_stats)) return HSZ_ERR_CAPACITY;

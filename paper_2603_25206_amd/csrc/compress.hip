@@ -33,6 +33,7 @@
 // parameter arithmetic as the CPU reference, so streams are byte-identical.
 #include "hsz_device.hpp"
 #include "hsz_launch.hpp"
+#include "hsz_nd.hpp"
 
 #include <math.h>
 
@@ -644,7 +645,212 @@ hipError_t run(const CompressArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- HSZp-nd: Lorenzo residual over the whole field, nd blocks ------------------
+// The same wave-per-chunk walk as k_quant_meta / k_pack, but lane l of step
+// st owns slot l % S of block 64c + st (64/S) + l/S of the nd partition, at
+// the coordinates of that slot.  The residual of a point is the sum over the
+// corners c of {0,1}^ND of (-1)^|c| q(point - c), q = 0 before index 0; each
+// corner is quantized from the field again (neighbouring lanes and blocks
+// read the same values through the caches).  |p| beyond 2^30 - 1 is a range
+// error.
+template <typename T, int ND>
+__device__ __forceinline__ int64_t lz_residual(const T* __restrict__ x, int64_t Y, int64_t X, int64_t z, int64_t y,
+                                               int64_t xx, double inv, bool& over, int& qself) {
+  int64_t r = 0;
+  constexpr int kCorners = ND == 3 ? 8 : 4;
+#pragma unroll
+  for (int c = 0; c < kCorners; ++c) {
+    const int dz = ND == 3 ? (c >> 2) & 1 : 0, dy = (c >> 1) & 1, dx = c & 1;
+    if ((dz && z == 0) || (dy && y == 0) || (dx && xx == 0)) continue;
+    const int q = quantize((double)x[((z - dz) * Y + (y - dy)) * X + (xx - dx)], inv, over);
+    if (c == 0) qself = q;
+    r += ((dz + dy + dx) & 1) ? -(int64_t)q : (int64_t)q;
+  }
+  return r;
+}
+
+// residual of the lane's slot of block b (0 outside the field or past nb)
+template <typename T, int S, int ND>
+__device__ __forceinline__ int64_t lz_slot_residual(const T* __restrict__ x, const NdGrid& g, int64_t nb, int64_t b,
+                                                    int slot, double inv, bool& over, int& qself) {
+  using Sh = NdShape<ND, S>;
+  qself = 0;
+  if (b >= nb) return 0;
+  const int sz = slot / (Sh::BY * Sh::BX), sy = (slot / Sh::BX) % Sh::BY, sx = slot % Sh::BX;
+  const int64_t bz = b / (g.nby * g.nbx), by = (b / g.nbx) % g.nby, bx = b % g.nbx;
+  const int64_t z = bz * Sh::BZ + sz, y = by * Sh::BY + sy, xx = bx * Sh::BX + sx;
+  if (z >= g.Z || y >= g.Y || xx >= g.X) return 0;
+  return lz_residual<T, ND>(x, g.Y, g.X, z, y, xx, inv, over, qself);
+}
+
+template <typename T, int S, int ND>
+__global__ void __launch_bounds__(kThreads) k_quant_meta_nd(const T* __restrict__ x, NdGrid g, int64_t nb,
+                                                           int64_t nchunks, CompressWs* ws, uint8_t* widths,
+                                                           uint32_t* chunk_words, uint32_t* group_max) {
+  if (ws->status != 0) {
+    if (threadIdx.x == 0) group_max[blockIdx.x] = 0;
+    return;
+  }
+  __shared__ int w_all[(kThreads / kWave) * kChunkBlocks];
+  int* mw = w_all + wave_in_group() * kChunkBlocks;
+  const double inv = ws->inv_quantum;
+  const int l = lane_id();
+  const int slot = l % S;
+  const int64_t waves = (int64_t)gridDim.x * (kThreads / kWave);
+  uint32_t maxq = 0;
+  bool over = false, wide = false;
+  for (int64_t c = blockIdx.x * (int64_t)(kThreads / kWave) + wave_in_group(); c < nchunks; c += waves) {
+    for (int st = 0; st < kSteps<S>; ++st) {
+      const int bl = st * (kWave / S) + l / S;
+      int qs = 0;
+      const int64_t r = lz_slot_residual<T, S, ND>(x, g, nb, c * kChunkBlocks + bl, slot, inv, over, qs);
+      const uint32_t aq = (uint32_t)(qs < 0 ? -qs : qs);
+      maxq = aq > maxq ? aq : maxq;
+      const int64_t ar = r < 0 ? -r : r;
+      wide |= ar > kPMax;
+      const int ab = block_or_scan<S>((int)(ar > kPMax ? kPMax : ar));
+      if (slot == S - 1) mw[bl] = bitlen((uint32_t)ab);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int64_t b = c * kChunkBlocks + l;
+    const bool exists = b < nb;
+    const int my_w = mw[l];
+    if (exists) widths[b] = (uint8_t)my_w;
+    const int words = wave_incl_scan(exists ? block_words<S>(my_w) : 0);
+    if (l == kWave - 1) chunk_words[c] = (uint32_t)words;
+    __builtin_amdgcn_wave_barrier();
+  }
+  maxq = (uint32_t)wave_max((int)maxq);
+  __shared__ uint32_t wmax[kThreads / kWave];
+  if (l == 0) wmax[wave_in_group()] = maxq;
+  if (__any(over || wide) && l == 0) record_status(&ws->status, kErrRange);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = 0;
+    for (int k = 0; k < kThreads / kWave; ++k) m = wmax[k] > m ? wmax[k] : m;
+    group_max[blockIdx.x] = m;
+  }
+}
+
+template <typename T, int S, int ND>
+__global__ void __launch_bounds__(kThreads) k_pack_nd(const T* __restrict__ x, NdGrid g, int64_t nb, int64_t nchunks,
+                                                     const CompressWs* ws, const uint8_t* __restrict__ widths,
+                                                     const uint64_t* __restrict__ chunk_off, uint32_t* payload) {
+  if (ws->status != 0) return;
+  constexpr int kRows = (S / 32) * (1 + kMaxWidth);  // words of the widest block
+  __shared__ uint32_t lin_all[(kThreads / kWave) * kRows * kWave];
+  uint32_t* lin = lin_all + wave_in_group() * kRows * kWave;
+  const double inv = ws->inv_quantum;
+  const int l = lane_id();
+  const int slot = l % S;
+  const int64_t waves = (int64_t)gridDim.x * (kThreads / kWave);
+  for (int64_t c = blockIdx.x * (int64_t)(kThreads / kWave) + wave_in_group(); c < nchunks; c += waves) {
+    const int64_t bl = c * kChunkBlocks + l;
+    const int wl = bl < nb ? (int)widths[bl] : 0;
+    const int nwl = block_words<S>(wl);
+    const int incl = wave_incl_scan(nwl);
+    const int offl = incl - nwl;
+    const int total = __shfl(incl, kWave - 1);
+    if (total < 0 || total > kRows * kWave) continue;  // widths are <= 30, so never taken
+    for (int k = l; k < total; k += kWave) lin[k] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    for (int st = 0; st < kSteps<S>; ++st) {
+      const int blk = st * (kWave / S);  // first block of the step within the chunk
+      bool ov = false;
+      int qs = 0;
+      const int p = (int)lz_slot_residual<T, S, ND>(x, g, nb, c * kChunkBlocks + blk + l / S, slot, inv, ov, qs);
+      int w = __builtin_amdgcn_readlane(wl, blk), off = __builtin_amdgcn_readlane(offl, blk);
+      if (S == 32 && l >= 32) {
+        w = __builtin_amdgcn_readlane(wl, blk + 1);
+        off = __builtin_amdgcn_readlane(offl, blk + 1);
+      }
+      const uint64_t neg = __ballot(p < 0);
+      if (w > 0) {
+        if (S == 32) {
+          if (slot == 0) lin[off] = (uint32_t)(l < 32 ? neg : neg >> 32);
+        } else {
+          if (l == 0) lin[off] = (uint32_t)neg;
+          if (l == 32) lin[off + 1] = (uint32_t)(neg >> 32);
+        }
+        const uint32_t m = (uint32_t)(p < 0 ? -p : p);
+        if (m) {
+          const uint32_t pos = (uint32_t)slot * (uint32_t)w;
+          const uint32_t k = pos >> 5, sh = pos & 31u;
+          uint32_t* mag = lin + off + S / 32;
+          atomicOr(&mag[k], m << sh);
+          if (sh + (uint32_t)w > 32u) atomicOr(&mag[k + 1], m >> (32u - sh));
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    uint32_t* dst = payload + chunk_off[c];
+    for (int k = l; k < total; k += kWave) dst[k] = lin[k];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+template <typename T, int S, int ND>
+hipError_t run_nd(const CompressArgs& a, hipStream_t s) {
+  const Layout& L = a.lay;
+  CompressWs* ws = (CompressWs*)a.ws;
+  double* partial = (double*)(a.ws + kWsPartials);
+  uint32_t* chunk_words = (uint32_t*)(a.ws + kWsPartials + 24 * kMinmaxGroups);
+  uint8_t* out = a.out;
+  const T* x = (const T*)a.x;
+  const NdGrid g = nd_grid(a.dims, a.ndim, S);
+  int gm = (int)((L.n + kThreads * 16 - 1) / (kThreads * 16));
+  gm = gm < 1 ? 1 : (gm > kMinmaxGroups ? kMinmaxGroups : gm);
+  hipLaunchKernelGGL(k_minmax<T>, dim3(gm), dim3(kThreads), 0, s, x, L.n, partial);
+  hipLaunchKernelGGL(k_params, dim3(1), dim3(kThreads), 0, s, partial, gm, a.eb, a.eb_is_rel, a.dtype, ws);
+  const int64_t cg = (L.nchunks + 3) / 4;
+  const int grid = (int)(cg < kMetaGroups ? cg : kMetaGroups);
+  uint32_t* group_max = (uint32_t*)(a.ws + ws_group_max_off(L));
+  hipLaunchKernelGGL((k_quant_meta_nd<T, S, ND>), dim3(grid), dim3(kThreads), 0, s, x, g, L.nb, L.nchunks, ws,
+                     out + L.off_width, chunk_words, group_max);
+  const unsigned ranges = (unsigned)((L.nchunks + kScanRange - 1) / kScanRange);
+  uint64_t* range_sums = (uint64_t*)(a.ws + ws_range_sums_off(L));
+  hipLaunchKernelGGL(k_scan_sums, dim3(ranges), dim3(kScanThreads), 0, s, chunk_words, L.nchunks, range_sums);
+  hipLaunchKernelGGL(k_scan_write, dim3(ranges), dim3(kScanThreads), 0, s, chunk_words, L.nchunks, range_sums,
+                     (uint64_t*)(out + L.off_chunk), ws, L.off_payload, a.cap);
+  hipLaunchKernelGGL((k_pack_nd<T, S, ND>), dim3(grid), dim3(kThreads), 0, s, x, g, L.nb, L.nchunks, ws,
+                     (const uint8_t*)(out + L.off_width), (const uint64_t*)(out + L.off_chunk),
+                     (uint32_t*)(out + L.off_payload));
+  hipLaunchKernelGGL(k_header, dim3(1), dim3(kHeaderBytes), 0, s, out, ws, (const uint32_t*)group_max, grid,
+                     kFlagLorenzo, a.dtype, a.ndim, a.dims[0], a.dims[1], a.dims[2], L.n, L.block, L.nb, L.nchunks,
+                     L.off_chunk, L.off_q0, L.off_width, L.off_payload);
+  return hipGetLastError();
+}
+
+template <typename T, int ND>
+hipError_t compress_nd_block(const CompressArgs& a, hipStream_t s) {
+  return a.lay.block == 32 ? run_nd<T, 32, ND>(a, s) : run_nd<T, 64, ND>(a, s);
+}
+
 }  // namespace
+
+Layout make_layout_nd(const int64_t d3[3], int ndim, int block) {
+  const NdGrid g = nd_grid(d3, ndim, block);
+  Layout L;
+  L.n = d3[0] * d3[1] * d3[2];
+  L.block = block;
+  L.nb = g.nbz * g.nby * g.nbx;
+  L.nchunks = (L.nb + kChunkBlocks - 1) / kChunkBlocks;
+  L.off_chunk = kHeaderBytes;
+  L.off_q0 = align_up(L.off_chunk + 8 * (uint64_t)(L.nchunks + 1), kSectionAlign);
+  L.off_width = L.off_q0;  // no metadata
+  L.off_payload = align_up(L.off_width + (uint64_t)L.nb, kSectionAlign);
+  return L;
+}
+
+hipError_t launch_compress_nd(const CompressArgs& a, hipStream_t s) {
+  if (a.ndim == 3)
+    return a.dtype == 1 ? compress_nd_block<float, 3>(a, s) : compress_nd_block<double, 3>(a, s);
+  return a.dtype == 1 ? compress_nd_block<float, 2>(a, s) : compress_nd_block<double, 2>(a, s);
+}
 
 Layout make_layout(int64_t n, int block) {
   Layout L;

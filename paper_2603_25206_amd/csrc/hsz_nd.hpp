@@ -1,0 +1,117 @@
+// hsz_nd.hpp -- HSZp-nd streams (Sec. IV): the multidimensional Lorenzo
+// decorrelation over the whole field, encoded in nd blocks.  Host and device
+// helpers shared by the compressor, the decoder, the operations and the ABI.
+#pragma once
+
+#include "hsz_device.hpp"
+#include "hsz_launch.hpp"
+
+namespace hsz {
+
+constexpr uint32_t kFlagLorenzo = 2u;  // header flags bit 1
+constexpr int32_t kPMax = (1 << 30) - 1;  // largest |p| of a Lorenzo residual
+
+// Block shape (slow -> fast, in the 3D view) of the nd partition: S = 2^k
+// elements with k split over the field's axes as evenly as possible, the
+// faster axes taking the remainder (2D: 4x8 for S = 32, 8x8 for 64; 3D:
+// 2x4x4 and 4x4x4).  false for a 1D field or another S.
+__host__ __device__ constexpr bool nd_block_shape(int ndim, int S, int b[3]) {
+  if (ndim < 2 || ndim > 3 || (S != 32 && S != 64)) return false;
+  const int k = S == 32 ? 5 : 6;
+  const int ez = ndim == 3 ? k / 3 : 0;
+  const int ey = (k - ez) / 2;
+  const int ex = k - ez - ey;
+  b[0] = 1 << ez;
+  b[1] = 1 << ey;
+  b[2] = 1 << ex;
+  return true;
+}
+
+template <int ND, int S>
+struct NdShape {
+  static constexpr int k = S == 32 ? 5 : 6;
+  static constexpr int ez = ND == 3 ? k / 3 : 0;
+  static constexpr int ey = (k - ez) / 2;
+  static constexpr int ex = k - ez - ey;
+  static constexpr int BZ = 1 << ez, BY = 1 << ey, BX = 1 << ex;
+};
+
+// Block grid of a field in the 3D view.
+struct NdGrid {
+  int64_t Z, Y, X;  // field dims (leading ones)
+  int64_t nbz, nby, nbx;
+  int ndim;         // the field's own rank (2 or 3): it fixes the block shape
+};
+
+inline NdGrid nd_grid(const int64_t d3[3], int ndim, int S) {
+  int b[3] = {1, 1, 1};
+  nd_block_shape(ndim, S, b);
+  return NdGrid{d3[0], d3[1], d3[2], (d3[0] + b[0] - 1) / b[0], (d3[1] + b[1] - 1) / b[1],
+                (d3[2] + b[2] - 1) / b[2], ndim};
+}
+
+// Sections of an HSZp-nd stream: blocks counted over the nd partition, an
+// empty q0 section.
+Layout make_layout_nd(const int64_t d3[3], int ndim, int block);
+
+// Compression of an HSZp-nd stream (args as launch_compress; a.lay from
+// make_layout_nd).
+hipError_t launch_compress_nd(const CompressArgs& a, hipStream_t s);
+
+// Rows of a chunk's LDS staging tile: |p| of a residual is at most 2^ND max|q|
+// (and at most 2^30 - 1).
+template <int S, int ND>
+inline int lz_kmax(uint32_t max_abs_q) {
+  uint64_t pm = (uint64_t)max_abs_q << ND;
+  if (pm > (uint64_t)kPMax) pm = kPMax;
+  const int wmax = pm ? 64 - __builtin_clzll(pm) : 1;
+  return tile_rows<S>(wmax > kMaxWidth ? kMaxWidth : wmax) - 1;
+}
+
+// Stage the payload of chunk c into the lane columns of 'tile' (row k at
+// tile + k*64, lane l <-> block 64c + l) and return the lane's block width;
+// an inconsistent chunk records a status and its blocks decode as zeros.
+template <int S>
+__device__ __forceinline__ int lz_stage(const StreamView& v, int64_t c, uint32_t* tile, int kmax, int* status) {
+  const int l = lane_id();
+  const int64_t b = c * kChunkBlocks + l;
+  int w = b < v.nb ? (int)v.width[b] : 0;
+  int nw = block_words<S>(w);
+  const bool bad = (w > kMaxWidth) || (nw > kmax);
+  const int incl = wave_incl_scan(bad ? 0 : nw);
+  const int woff = incl - (bad ? 0 : nw);
+  const int total = __shfl(incl, kWave - 1);
+  const uint64_t base = v.chunk_off[c], next = v.chunk_off[c + 1];
+  if (__any(bad) || next - base != (uint64_t)total || next > v.payload_words) {
+    if (l == 0) record_status(status, kErrBadStream);
+    w = 0;
+    nw = 0;
+  }
+  const uint32_t* src = v.payload + base + woff;
+  for (int k = 0; k < nw; ++k) tile[k * kWave + l] = src[k];
+  return w;
+}
+
+// Decoding of an HSZp-nd stream to stage 2 (p, int32, the field's layout),
+// 3 (q, int32) or 4 (the field's dtype).  Stage 3 and 4 rebuild q with
+// prefix sums along every axis (the inverse of the Lorenzo residual) in the
+// output itself; the binary64 stage 4 keeps q in the low word of each
+// element until its conversion, so no scratch memory is needed.
+hipError_t lz_decode(const StreamView& v, const NdGrid& g, int stage, void* out, int* status, hipStream_t s);
+
+// Derivative along axis3 (of the 3D view) on D_p (Eq. (derivative_Dp)):
+// p (int32, the field's layout) -> out (field dtype, whole field).
+hipError_t lz_deriv_p(const int32_t* p, const StreamView& v, const NdGrid& g, int axis3, void* out, hipStream_t s);
+
+// Prefix sums along the 3D view's axes z..x except 'skip' (-1: none) of an
+// int32 field stored at element stride es (1 or 2 words), in place.
+hipError_t lz_scan_axes(int32_t* buf, int64_t Z, int64_t Y, int64_t X, int es, int skip, hipStream_t s);
+
+// Statistics of an HSZp-nd stream on D_p (whole field): MEAN through the
+// nd weights of Sec. V-A (from a stage-2 buffer, or fused from the stream
+// when p == nullptr), VAR through the prefix sums of Alg. 4 (p copied to
+// 'scratch', 4n bytes, and rebuilt there; fused: decoded there).
+hipError_t launch_lz_stats(const int32_t* p, const StreamView& v, const NdGrid& g, int op, void* result,
+                           uint8_t* ws, int32_t* scratch, hipStream_t s);
+
+}  // namespace hsz

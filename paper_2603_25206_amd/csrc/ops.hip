@@ -13,6 +13,7 @@
 
 #include "hsz_device.hpp"
 #include "hsz_launch.hpp"
+#include "hsz_nd.hpp"
 
 namespace hsz {
 
@@ -950,6 +951,134 @@ hipError_t launch_stats_fused(const StreamView& v, int via, int op_in, const OpT
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, parts, grid, op_in, via == 4 ? 1 : 0, v.quantum,
                      (const StatsOut*)(ws + kMetaOff), (StatsOut*)result);
+  return hipGetLastError();
+}
+
+// ---- HSZp-nd on D_p (Sec. V-A) ------------------------------------------------------
+namespace {
+
+// Mean: sum q = sum over points of (Z - z)(Y - y)(X - x) p (0-based), the nd
+// weights of Sec. V-A.  Products and running sums wrap modulo 2^64, which is
+// exact because the total, sum q, fits in 64 bits.  One row (z, y) per
+// workgroup step.
+__global__ void __launch_bounds__(kThreads) k_lz_mean_buf(const int32_t* __restrict__ p, NdGrid g, Partial* parts) {
+  IntAcc acc;
+  uint64_t s = 0;
+  const int64_t rows = g.Z * g.Y;
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int64_t z = r / g.Y, y = r % g.Y;
+    const uint64_t wzy = (uint64_t)(g.Z - z) * (uint64_t)(g.Y - y);
+    const int32_t* row = p + r * g.X;
+    for (int64_t x = threadIdx.x; x < g.X; x += kThreads) {
+      s += wzy * (uint64_t)(g.X - x) * (uint64_t)(int64_t)row[x];
+      acc.cnt += 1;
+    }
+  }
+  acc.s1 = (int64_t)s;
+  store_int_partial(acc, parts);
+}
+
+// The same sum straight from the stream: a wave per 64-block chunk, a lane
+// per nd block, each decoded slot weighted by its coordinates.
+template <int S, int ND>
+__global__ void __launch_bounds__(kThreads) k_lz_mean_fused(StreamView v, NdGrid g, int kmax, Partial* parts,
+                                                           int* status) {
+  using Sh = NdShape<ND, S>;
+  extern __shared__ uint32_t smem[];
+  uint32_t* tile = smem + wave_in_group() * (kmax + 1) * kWave;
+  const int l = lane_id();
+  const int64_t waves = (int64_t)gridDim.x * kWavesPerGroup;
+  IntAcc acc;
+  uint64_t s = 0;
+  for (int64_t c = blockIdx.x * (int64_t)kWavesPerGroup + wave_in_group(); c < v.nchunks; c += waves) {
+    const int w = lz_stage<S>(v, c, tile, kmax, status);
+    const int64_t b = c * kChunkBlocks + l;
+    if (b < v.nb) {
+      const int64_t oz = (b / (g.nby * g.nbx)) * Sh::BZ, oy = ((b / g.nbx) % g.nby) * Sh::BY,
+                    ox = (b % g.nbx) * Sh::BX;
+      decode_lane_block<S, kWave, true>(tile + l, w, 0, [&](int j, int p, int) {
+        const int sz = j / (Sh::BY * Sh::BX), sy = (j / Sh::BX) % Sh::BY, sx = j % Sh::BX;
+        const int64_t z = oz + sz, y = oy + sy, x = ox + sx;
+        if (z < g.Z && y < g.Y && x < g.X) {
+          s += (uint64_t)(g.Z - z) * (uint64_t)(g.Y - y) * (uint64_t)(g.X - x) * (uint64_t)(int64_t)p;
+          acc.cnt += 1;
+        }
+      });
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  acc.s1 = (int64_t)s;
+  store_int_partial(acc, parts);
+}
+
+__global__ void __launch_bounds__(kThreads) k_copy_i32(const int32_t* __restrict__ a, int64_t n, int32_t* __restrict__ b) {
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) b[i] = a[i];
+}
+
+// Alg. 4 on the GPU: with the prefix sums over every axis but the field's
+// slowest already taken, one thread per column walks that axis with a
+// running sum, which is q, and sums q and q^2 (nothing is written back).
+__global__ void __launch_bounds__(kThreads) k_lz_scan_stats(const int32_t* __restrict__ buf, int64_t len,
+                                                           int64_t inner, Partial* parts) {
+  IntAcc acc;
+  for (int64_t t = blockIdx.x * (int64_t)kThreads + threadIdx.x; t < inner; t += (int64_t)gridDim.x * kThreads) {
+    int run = 0;
+#pragma unroll 8
+    for (int64_t i = 0; i < len; ++i) {
+      run += buf[i * inner + t];
+      acc.add(run, true);
+    }
+  }
+  store_int_partial(acc, parts);
+}
+
+template <int S, int ND>
+int launch_lz_mean_fused(const StreamView& v, const NdGrid& g, Partial* parts, int* status, hipStream_t s) {
+  const int kmax = lz_kmax<S, ND>(v.max_abs_q);
+  const size_t lds = (size_t)kWavesPerGroup * (kmax + 1) * kWave * sizeof(uint32_t);
+  const int grid = grid_for(v.nchunks, kWavesPerGroup);
+  hipLaunchKernelGGL((k_lz_mean_fused<S, ND>), dim3(grid), dim3(kThreads), lds, s, v, g, kmax, parts, status);
+  return grid;
+}
+
+}  // namespace
+
+hipError_t launch_lz_stats(const int32_t* p, const StreamView& v, const NdGrid& g, int op, void* result,
+                           uint8_t* ws, int32_t* scratch, hipStream_t s) {
+  Partial* parts = (Partial*)(ws + kPartialOff);
+  int* status = (int*)ws;
+  int grid = 1;
+  if (op == 1 && p) {
+    const int64_t rows = g.Z * g.Y;
+    grid = (int)(rows < kOpWorkgroups ? rows : kOpWorkgroups);
+    hipLaunchKernelGGL(k_lz_mean_buf, dim3(grid), dim3(kThreads), 0, s, p, g, parts);
+  } else if (op == 1) {
+    if (g.ndim == 3)
+      grid = v.block == 32 ? launch_lz_mean_fused<32, 3>(v, g, parts, status, s)
+                           : launch_lz_mean_fused<64, 3>(v, g, parts, status, s);
+    else
+      grid = v.block == 32 ? launch_lz_mean_fused<32, 2>(v, g, parts, status, s)
+                           : launch_lz_mean_fused<64, 2>(v, g, parts, status, s);
+  } else if (op == 2) {
+    const int64_t n = g.Z * g.Y * g.X;
+    if (p) hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n, kThreads * 4)), dim3(kThreads), 0, s, p, n, scratch);
+    else {
+      hipError_t e = lz_decode(v, g, 2, scratch, status, s);
+      if (e != hipSuccess) return e;
+    }
+    const int last = g.ndim == 3 ? 0 : 1;  // the field's slowest axis in the 3D view
+    hipError_t e = lz_scan_axes(scratch, g.Z, g.Y, g.X, 1, last, s);
+    if (e != hipSuccess) return e;
+    const int64_t len = last == 0 ? g.Z : g.Y, inner = last == 0 ? g.Y * g.X : g.X;
+    grid = grid_for(inner, kThreads);
+    hipLaunchKernelGGL(k_lz_scan_stats, dim3(grid), dim3(kThreads), 0, s, scratch, len, inner, parts);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, parts, grid, op, 0, v.quantum,
+                     (const StatsOut*)nullptr, (StatsOut*)result);
   return hipGetLastError();
 }
 

@@ -28,6 +28,7 @@ F32, F64 = 1, 2
 META, DELTA, QUANT, FLOAT = 1, 2, 3, 4
 MEAN, VAR, DERIV, GRADMAG, LAPLACIAN, DIVERGENCE, CURL, VAR_MT = 1, 2, 3, 4, 5, 6, 7, 8
 FLAG_BLOCK_MEAN = 1  # header flag: block-mean decorrelation (HSZx)
+FLAG_LORENZO = 2  # header flag: Lorenzo decorrelation over the whole field, nd blocks (HSZp-nd)
 HEADER_BYTES = 256
 
 _OPS = {"mean": MEAN, "var": VAR, "var_mt": VAR_MT, "deriv": DERIV, "gradmag": GRADMAG, "laplacian": LAPLACIAN,
@@ -258,9 +259,13 @@ def compress_bound(shape, dtype: int, block: int) -> int:
 
 
 def compress(x: torch.Tensor, eb: float, rel: bool = True, block: int = 32, stream=None,
-             out: torch.Tensor | None = None, check: bool = True, mean_dec: bool = False) -> Compressed:
+             out: torch.Tensor | None = None, check: bool = True, mean_dec: bool = False,
+             lorenzo: bool = False) -> Compressed:
     """c = C(x, eb) on the GPU.  x: contiguous float32/float64 CUDA tensor.
-    mean_dec selects the block-mean decorrelation (HSZx) instead of deltas."""
+    mean_dec selects the block-mean decorrelation (HSZx), lorenzo the nd
+    Lorenzo decorrelation of HSZp-nd (2D / 3D fields), instead of deltas."""
+    if mean_dec and lorenzo:
+        raise ValueError("block-mean and Lorenzo decorrelation are exclusive")
     lib = load()
     if not x.is_cuda or not x.is_contiguous():
         raise ValueError("x must be a contiguous GPU tensor")
@@ -277,7 +282,8 @@ def compress(x: torch.Tensor, eb: float, rel: bool = True, block: int = 32, stre
     ws = workspace(wsb.value, x.device, key="compress")
     s = _stream(stream)
     _check(lib.hsz_compress_flags(ctypes.c_void_p(x.data_ptr()), dt, len(shape), dims, float(eb), int(rel),
-                                  block, FLAG_BLOCK_MEAN if mean_dec else 0, ctypes.c_void_p(out.data_ptr()),
+                                  block, FLAG_BLOCK_MEAN if mean_dec else (FLAG_LORENZO if lorenzo else 0),
+                                  ctypes.c_void_p(out.data_ptr()),
                                   out.numel(), ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(s)),
            "compress")
     if not check:
@@ -330,7 +336,8 @@ def stage_view(buf: torch.Tensor, h: Header, stage: int):
     if stage == META:
         return buf[: 4 * nb].view(torch.int32)
     if stage == DELTA:
-        v = buf[: 4 * (n + nb)].view(torch.int32)
+        nq = 0 if h.flags & FLAG_LORENZO else nb  # HSZp-nd streams carry no metadata
+        v = buf[: 4 * (n + nq)].view(torch.int32)
         return v[:n].view(h.shape), v[n:]
     if stage == QUANT:
         return buf[: 4 * n].view(torch.int32).view(h.shape)
