@@ -197,10 +197,10 @@ def compress_bound(n: int, block: int) -> int:
     return int(_load().or_compress_bound(n, block))
 
 
-def _flags(mean_dec: bool, lorenzo: bool) -> int:
-    if mean_dec and lorenzo:
-        raise ValueError("block-mean and Lorenzo decorrelation are exclusive")
-    return 1 if mean_dec else (2 if lorenzo else 0)
+def _flags(mean_dec: bool, lorenzo: bool, inter_block: bool = False) -> int:
+    if int(bool(mean_dec)) + int(bool(lorenzo)) + int(bool(inter_block)) > 1:
+        raise ValueError("block-mean, Lorenzo and inter-block decorrelation are exclusive")
+    return 1 if mean_dec else (2 if lorenzo else (4 if inter_block else 0))
 
 
 def compress_bound_dims(shape, block: int, flags: int = 0) -> int:
@@ -231,13 +231,14 @@ def quantize(x, quantum: float) -> np.ndarray:
 
 
 def encode_q(q, shape, quantum: float, block: int, dtype: int = F32, eb_abs: float = 0.0,
-             mean_dec: bool = False, lorenzo: bool = False) -> np.ndarray:
+             mean_dec: bool = False, lorenzo: bool = False, inter_block: bool = False) -> np.ndarray:
     """Encode given quantization integers; mean_dec selects block-mean
     decorrelation (HSZx), lorenzo the nd Lorenzo decorrelation of HSZp-nd,
-    instead of in-block deltas."""
+    inter_block HSZp's deltas across block borders, instead of in-block
+    deltas."""
     q = np.ascontiguousarray(np.asarray(q, dtype=np.int32).ravel())
     dims = np.array([int(s) for s in shape], dtype=np.uint64)
-    fl = _flags(mean_dec, lorenzo)
+    fl = _flags(mean_dec, lorenzo, inter_block)
     cap = max(compress_bound_dims(shape, block, fl), 1)
     out = np.zeros(cap, dtype=np.uint8)
     size = ctypes.c_uint64()
@@ -298,7 +299,7 @@ def lz_deriv_p(p: np.ndarray, axis: int, quantum: float):
 
 
 def compress(x: np.ndarray, eb: float, rel: bool = True, block: int = 32, mean_dec: bool = False,
-             lorenzo: bool = False) -> np.ndarray:
+             lorenzo: bool = False, inter_block: bool = False) -> np.ndarray:
     x = np.ascontiguousarray(x)
     if x.dtype == np.float32:
         dt = F32
@@ -307,7 +308,7 @@ def compress(x: np.ndarray, eb: float, rel: bool = True, block: int = 32, mean_d
     else:
         raise TypeError("field must be float32 or float64")
     dims = np.array(x.shape, dtype=np.uint64)
-    fl = _flags(mean_dec, lorenzo)
+    fl = _flags(mean_dec, lorenzo, inter_block)
     cap = max(compress_bound_dims(x.shape, block, fl), 1)
     out = np.empty(cap, dtype=np.uint8)
     size = ctypes.c_uint64()
@@ -339,8 +340,8 @@ def decompress(buf: np.ndarray, stage: int):
     buf = np.ascontiguousarray(buf, dtype=np.uint8)
     h = read_header(buf)
     lib = _load()
-    if stage == META and h.flags & 2:
-        raise OracleError(ERR_UNSUPPORTED, "decompress: an HSZp-nd stream has no metadata stage")
+    if stage == META and h.flags & 6:
+        raise OracleError(ERR_UNSUPPORTED, "decompress: an HSZp-nd or HSZp stream has no metadata stage")
     nbytes = int(lib.or_stage_bytes(_ptr(buf), buf.size, stage))
     if nbytes == 0:
         raise OracleError(ERR_ARG, "decompress: bad stage")

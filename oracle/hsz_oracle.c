@@ -75,6 +75,11 @@
  *      and 4x4x4), blocks and their slots in raster order, slots outside
  *      the field p = 0.  No metadata is stored (the q0 section is empty);
  *      stage 2 is p in the field's own layout.  For 2D and 3D fields only.
+ *   R14 HSZp (Sec. IV, inter-block prediction): bit 2 of the header flags.
+ *      p_i = q_i - q_{i-1} over the field read as one flat array, across
+ *      block borders, with q_{-1} = 0 (so p_0 = q_0); the 1D partition of S
+ *      elements; no metadata.  This is R12's residual in one dimension, and
+ *      it applies to fields of any rank.
  *   R13 the residual of HSZp-nd sums up to eight quantization integers, so
  *      besides R6 it must satisfy |p| <= 2^30 - 1 (the delta mode's width
  *      limit), else the compressor reports a range error.
@@ -116,6 +121,7 @@
 #define OR_PMAX 1073741823 /* 2^30 - 1 (R13) */
 #define OR_FLAG_MEAN 1u
 #define OR_FLAG_LORENZO 2u
+#define OR_FLAG_INTER 4u
 
 typedef struct {
   uint32_t dtype;   /* 1 = binary32, 2 = binary64 */
@@ -164,20 +170,40 @@ static int nd_block_shape(uint32_t ndim, uint32_t S, uint64_t b[3]) {
   return 1;
 }
 
-/* Section placement: header, chunk offsets, q0, widths, payload.  HSZp-nd
- * streams count blocks over the nd partition and store no q0. */
+/* The residual's view of the field for the Lorenzo family: HSZp-nd (R12)
+ * uses the field's own dims and the nd block shape; HSZp (R14) the field as
+ * one row of n with blocks of S.  0 for the other modes. */
+static int lz_view(const or_header *h, uint64_t d[3], uint64_t bs[3]) {
+  if (h->flags & OR_FLAG_INTER) {
+    d[0] = d[1] = 1;
+    d[2] = h->n;
+    bs[0] = bs[1] = 1;
+    bs[2] = h->block;
+    return 1;
+  }
+  if (h->flags & OR_FLAG_LORENZO) {
+    if (!nd_block_shape(h->ndim, h->block, bs)) return 0;
+    for (int k = 0; k < 3; k++) d[k] = h->dims[k];
+    return 1;
+  }
+  return 0;
+}
+
+/* Section placement: header, chunk offsets, q0, widths, payload.  Streams of
+ * the Lorenzo family count blocks over their partition and store no q0. */
 static void layout(or_header *h) {
-  uint64_t bs[3];
-  if ((h->flags & OR_FLAG_LORENZO) && nd_block_shape(h->ndim, h->block, bs)) {
+  uint64_t d[3], bs[3];
+  const int lz = lz_view(h, d, bs);
+  if (lz) {
     h->nb = 1;
-    for (int k = 0; k < 3; k++) h->nb *= ceil_div(h->dims[k], bs[k]);
+    for (int k = 0; k < 3; k++) h->nb *= ceil_div(d[k], bs[k]);
   } else {
     h->nb = ceil_div(h->n, h->block);
   }
   h->nchunks = ceil_div(h->nb, h->chunk_blocks);
   h->off_chunk = OR_HEADER_BYTES;
   h->off_q0 = round_up(h->off_chunk + 8 * (h->nchunks + 1), OR_SECTION_ALIGN);
-  h->off_width = round_up(h->off_q0 + ((h->flags & OR_FLAG_LORENZO) ? 0 : 4 * h->nb), OR_SECTION_ALIGN);
+  h->off_width = round_up(h->off_q0 + (lz ? 0 : 4 * h->nb), OR_SECTION_ALIGN);
   h->off_payload = round_up(h->off_width + h->nb, OR_SECTION_ALIGN);
 }
 
@@ -246,8 +272,9 @@ int or_read_header(const uint8_t *buf, uint64_t len, or_header *h) {
   h->payload_words = get_u64(buf + 144);
   h->total_bytes = get_u64(buf + 152);
   if (h->dtype != 1 && h->dtype != 2) return OR_ERR_STREAM;
-  /* bit 0: block-mean decorrelation (R10); bit 1: HSZp-nd (R12); not both */
-  if (h->flags > 2u) return OR_ERR_STREAM;
+  /* bit 0: block-mean decorrelation (R10); bit 1: HSZp-nd (R12); bit 2:
+     HSZp's inter-block prediction (R14); at most one */
+  if (h->flags != 0 && h->flags != 1u && h->flags != 2u && h->flags != 4u) return OR_ERR_STREAM;
   if (h->ndim < 1 || h->ndim > 3) return OR_ERR_STREAM;
   uint64_t bs[3];
   if ((h->flags & OR_FLAG_LORENZO) && !nd_block_shape(h->ndim, h->block, bs)) return OR_ERR_STREAM;
@@ -285,7 +312,8 @@ uint64_t or_compress_bound(uint64_t n, uint32_t S) {
 /* The same bound for a stream of the given flags over a field of the given
  * dims (HSZp-nd streams count blocks over the nd partition). */
 uint64_t or_compress_bound_dims(uint32_t ndim, const uint64_t *dims, uint32_t S, uint32_t flags) {
-  if (!dims || ndim < 1 || ndim > 3 || S < 1 || S > 64 || flags > 2u) return 0;
+  if (!dims || ndim < 1 || ndim > 3 || S < 1 || S > 64 || (flags != 0 && flags != 1u && flags != 2u && flags != 4u))
+    return 0;
   or_header h;
   memset(&h, 0, sizeof h);
   h.ndim = ndim;
@@ -386,9 +414,9 @@ static int64_t round_half_down_div(int64_t a, int64_t b) {
 static int encode_q(const int32_t *q, or_header *h, uint8_t *out, uint64_t cap, uint64_t *out_size) {
   const uint32_t S = h->block;
   const int mean_mode = (h->flags & OR_FLAG_MEAN) != 0;
-  const int lorenzo = (h->flags & OR_FLAG_LORENZO) != 0;
-  uint64_t bs[3] = {1, 1, 1};
-  if (lorenzo && !nd_block_shape(h->ndim, S, bs)) return OR_ERR_ARG;
+  const int lorenzo = (h->flags & (OR_FLAG_LORENZO | OR_FLAG_INTER)) != 0;
+  uint64_t vd[3] = {1, 1, 1}, bs[3] = {1, 1, 1};
+  if (lorenzo && !lz_view(h, vd, bs)) return OR_ERR_ARG;
   h->chunk_blocks = OR_CHUNK_BLOCKS;
   layout(h);
   uint64_t bound = h->off_payload + 4 * h->nb * block_words(S, 30);
@@ -407,8 +435,8 @@ static int encode_q(const int32_t *q, or_header *h, uint8_t *out, uint64_t cap, 
   int32_t *q0 = (int32_t *)calloc(h->nb, sizeof(int32_t));
   if (!p || !width || !q0) { free(p); free(width); free(q0); return OR_ERR_ARG; }
   if (lorenzo) {
-    /* Lorenzo residual of every point (R12), q = 0 outside the field */
-    const uint64_t Z = h->dims[0], Y = h->dims[1], X = h->dims[2];
+    /* Lorenzo residual of every point (R12, R14), q = 0 outside the field */
+    const uint64_t Z = vd[0], Y = vd[1], X = vd[2];
     const uint64_t nbz = ceil_div(Z, bs[0]), nby = ceil_div(Y, bs[1]), nbx = ceil_div(X, bs[2]);
     for (uint64_t bz = 0; bz < nbz; bz++)
       for (uint64_t by = 0; by < nby; by++)
@@ -511,7 +539,7 @@ int or_encode_q(const int32_t *q, uint32_t ndim, const uint64_t *dims, uint32_t 
   h.inv_quantum = 1.0 / quantum;
   h.vmin = 0.0;
   h.vmax = 0.0;
-  if (flags > 2u) return OR_ERR_ARG;
+  if (flags != 0 && flags != 1u && flags != 2u && flags != 4u) return OR_ERR_ARG;
   h.flags = flags;
   return encode_q(q, &h, out, cap, out_size);
 }
@@ -519,7 +547,8 @@ int or_encode_q(const int32_t *q, uint32_t ndim, const uint64_t *dims, uint32_t 
 /* Full compressor C(d, eps): extremes -> parameters -> quantize -> encode. */
 int or_compress(const void *x, uint32_t dtype, uint32_t ndim, const uint64_t *dims, double eb,
                 int eb_is_rel, uint32_t S, uint32_t flags, uint8_t *out, uint64_t cap, uint64_t *out_size) {
-  if (!x || !dims || ndim < 1 || ndim > 3 || S < 1 || S > 64 || (dtype != 1 && dtype != 2) || flags > 2u)
+  if (!x || !dims || ndim < 1 || ndim > 3 || S < 1 || S > 64 || (dtype != 1 && dtype != 2) ||
+      (flags != 0 && flags != 1u && flags != 2u && flags != 4u))
     return OR_ERR_ARG;
   or_header h;
   memset(&h, 0, sizeof h);
@@ -570,7 +599,7 @@ int or_compress(const void *x, uint32_t dtype, uint32_t ndim, const uint64_t *di
 uint64_t or_stage_bytes(const uint8_t *buf, uint64_t len, int stage) {
   or_header h;
   if (or_read_header(buf, len, &h) != OR_OK) return 0;
-  const int lorenzo = (h.flags & OR_FLAG_LORENZO) != 0;
+  const int lorenzo = (h.flags & (OR_FLAG_LORENZO | OR_FLAG_INTER)) != 0;
   switch (stage) {
     case 1: return lorenzo ? 0 : 4 * h.nb;
     case 2: return 4 * h.n + (lorenzo ? 0 : 4 * h.nb);
@@ -580,14 +609,15 @@ uint64_t or_stage_bytes(const uint8_t *buf, uint64_t len, int stage) {
   }
 }
 
-/* stage 1 of an HSZp-nd stream does not exist (no metadata): OR_ERR_UNSUPPORTED */
+/* stage 1 of an HSZp-nd or HSZp stream does not exist (no metadata):
+ * OR_ERR_UNSUPPORTED */
 int or_decompress(const uint8_t *buf, uint64_t len, int stage, void *out) {
   or_header h;
   int rc = or_read_header(buf, len, &h);
   if (rc != OR_OK) return rc;
   if (!out || stage < 1 || stage > 4) return OR_ERR_ARG;
   const uint32_t S = h.block;
-  const int lorenzo = (h.flags & OR_FLAG_LORENZO) != 0;
+  const int lorenzo = (h.flags & (OR_FLAG_LORENZO | OR_FLAG_INTER)) != 0;
   if (lorenzo && stage == 1) return OR_ERR_UNSUPPORTED;
   int32_t *q0 = (int32_t *)calloc(h.nb, sizeof(int32_t));
   if (!q0) return OR_ERR_ARG;
@@ -626,10 +656,10 @@ int or_decompress(const uint8_t *buf, uint64_t len, int stage, void *out) {
      places each slot of each nd block at its coordinates (R12) */
   int32_t *p = (int32_t *)calloc(h.n, sizeof(int32_t));
   if (!p) { free(pb); free(q0); return OR_ERR_ARG; }
-  const uint64_t Z = h.dims[0], Y = h.dims[1], X = h.dims[2];
+  uint64_t vd[3] = {h.dims[0], h.dims[1], h.dims[2]}, bs[3] = {1, 1, 1};
+  if (lorenzo) lz_view(&h, vd, bs);
+  const uint64_t Z = vd[0], Y = vd[1], X = vd[2];
   if (lorenzo) {
-    uint64_t bs[3];
-    nd_block_shape(h.ndim, S, bs);
     const uint64_t nby = ceil_div(Y, bs[1]), nbx = ceil_div(X, bs[2]);
     for (uint64_t b = 0; b < h.nb; b++) {
       const uint64_t bz = b / (nby * nbx), by = (b / nbx) % nby, bx = b % nbx;

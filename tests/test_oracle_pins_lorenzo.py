@@ -177,3 +177,57 @@ def test_derivative_recursion_on_dp(shape, S):
         assert np.array_equal(out, num * (h.quantum * 0.5))
         deriv_ref = oracle.derivative(oracle.dequantize64(q.astype(np.int32), h.quantum), ax)
         assert np.allclose(out, deriv_ref, rtol=1e-12, atol=8 * 2.0 ** -53 * float(np.max(np.abs(q))) * h.quantum)
+
+
+# ---- HSZp: deltas across block borders over the flat field (Sec. IV) -------------------
+
+@pytest.mark.parametrize("shape,S", [((5, 9, 13), 32), ((1000,), 64), ((33, 41), 32), ((3,), 32), ((7, 70), 64)])
+def test_inter_block_deltas(shape, S):
+    """p = numpy.diff of the flat q with a leading 0 (crossing block borders),
+    q = numpy.cumsum of p; blocks of S in flat order (read back by the
+    independent format reader); the paper's HSZp mean and running-sum
+    standard deviation on D_p give sum q and sum q^2 exactly."""
+    x = _field(shape, 3 + sum(shape))
+    buf = oracle.compress(x, 1e-3, rel=True, block=S, inter_block=True)
+    h = oracle.read_header(buf)
+    assert h.flags == 4 and h.off_width == h.off_q0 and h.nb == -(-h.n // S)
+    q_ref = oracle.decompress(oracle.compress(x, 1e-3, rel=True, block=S), oracle.QUANT).ravel().astype(np.int64)
+    p, q0 = oracle.decompress(buf, oracle.DELTA)
+    assert q0.size == 0
+    assert np.array_equal(p.ravel(), np.diff(q_ref, prepend=0))
+    assert np.array_equal(oracle.decompress(buf, oracle.QUANT).ravel(), q_ref)
+    assert np.array_equal(np.cumsum(p.ravel().astype(np.int64)), q_ref)
+    fr = parse(buf.tobytes())
+    padded = np.zeros(h.nb * S, dtype=np.int64)
+    padded[: h.n] = p.ravel()
+    assert np.array_equal(fr["pblocks"], padded.reshape(h.nb, S))
+    qi = [int(v) for v in q_ref]
+    s1, _ = oracle.lz_mean_p(p.ravel(), h.quantum)  # weights N - i + 1 (1-based)
+    assert s1 == sum(qi)
+    r = oracle.lz_var_p(p.ravel(), h.quantum)  # the running sum eta of Sec. V-A
+    assert (r["s1"], r["s2"]) == (sum(qi), sum(v * v for v in qi))
+
+
+@pytest.mark.parametrize("S,N", [(2, 5), (3, 5), (4, 4)])
+def test_inter_block_brute_force(S, N):
+    """Every integer vector in [-2, 2]^N, ragged last block included."""
+    import itertools
+    for vals in itertools.product(range(-2, 3), repeat=N):
+        q = np.array(vals, dtype=np.int32)
+        buf = oracle.encode_q(q, (N,), 1.0, S, inter_block=True)
+        p, _ = oracle.decompress(buf, oracle.DELTA)
+        assert np.array_equal(p, np.diff(q.astype(np.int64), prepend=0)), vals
+        assert np.array_equal(oracle.decompress(buf, oracle.QUANT), q), vals
+
+
+def test_flag_values():
+    buf = oracle.compress(_field((6, 7), 2), 1e-3, inter_block=True)
+    for fl in (3, 5, 6, 8):
+        bad = buf.copy()
+        bad[92] = fl
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.read_header(bad)
+        assert e.value.code == oracle.ERR_STREAM
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.decompress(buf, oracle.META)
+    assert e.value.code == oracle.ERR_UNSUPPORTED
