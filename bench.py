@@ -511,7 +511,9 @@ def bench_lorenzo(a, log):
     S=32, 2x4x4 blocks): compression time and ratio, decoding to each stage,
     the mean with nd weights and Alg. 4 on D_p, the derivative along each
     axis on D_p (Eq. (derivative_Dp)) against the same derivative from D_q
-    (decode to D_q + stencil) and after full decompression."""
+    (decode to D_q + stencil) and after full decompression; and the same
+    field as an HSZp stream (deltas across block borders of the flat field):
+    ratio, compression, D_p and D_q decoding, mean and variance on D_p."""
     import torch
 
     from paper_2603_25206_amd import hsz, synth
@@ -554,8 +556,22 @@ def bench_lorenzo(a, log):
         r["decode_q_then_deriv_ms"] = round(_events_ms(via_q, 5, cur), 4)
         r["full_decompress_then_deriv_ms"] = round(_events_ms(full, 5, cur), 4)
         res[f"deriv_axis{ax}"] = r
-    log(f"[bench] lorenzo-nd: {res}")
-    del x, c, ws, obuf, sbuf
+    # HSZp: deltas across the blocks of the flat field (device-wide prefix sum for D_q)
+    cf = hsz.compress(x, a.eb, rel=True, block=a.block, inter_block=True)
+    torch.cuda.synchronize()
+    wsf = hsz.workspace(hsz.op_workspace_bytes(cf.header, hsz.VAR), dev, key="bench-flat")
+    flat = {"ratio": round(cf.ratio, 3),
+            "compress_ms": round(_events_ms(lambda: hsz.compress(x, a.eb, rel=True, block=a.block,
+                                                                 inter_block=True), 5, cur), 4)}
+    for st, name in ((hsz.DELTA, "decode_p_ms"), (hsz.QUANT, "decode_q_ms")):
+        flat[name] = round(_events_ms(lambda: hsz.decompress_to_stage(cf, st, out=sbuf), 5, cur), 4)
+    flat["mean_p_ms"] = round(_events_ms(lambda: hsz.op_fused(cf, hsz.DELTA, hsz.MEAN, out=s48, ws=wsf, check=False,
+                                                              raw=True), 10, cur), 4)
+    flat["var_p_ms"] = round(_events_ms(lambda: hsz.op_fused(cf, hsz.DELTA, hsz.VAR, out=s48, ws=wsf, check=False,
+                                                             raw=True), 10, cur), 4)
+    res["inter_block_1d"] = flat
+    log(f"[bench] lorenzo-nd / inter-block: {res}")
+    del x, c, cf, ws, wsf, obuf, sbuf
     return res
 
 

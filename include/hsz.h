@@ -75,7 +75,7 @@ typedef struct hsz_header {
   double inv_quantum;     /* 1 / Delta, the quantizer's multiplier           */
   double vmin, vmax;      /* extremes of the input field                     */
   uint32_t max_abs_q;     /* max |q| over the field                          */
-  uint32_t flags;         /* 0, HSZ_FLAG_BLOCK_MEAN or HSZ_FLAG_LORENZO      */
+  uint32_t flags;         /* 0 or one HSZ_FLAG_* decorrelation mode          */
   int64_t nb;             /* number of blocks = ceil(n / S)                  */
   int64_t nchunks;        /* ceil(nb / 64)                                   */
   uint64_t off_chunk;     /* byte offsets of the sections in the stream      */
@@ -180,6 +180,17 @@ int hsz_compress(const void *d_x, int dtype, int ndim, const int64_t *h_dims, do
  * binary64 fields, beyond the operation's own).  Batches, block indexes and
  * fused vector fields return HSZ_ERR_UNSUPPORTED for these streams. */
 #define HSZ_FLAG_LORENZO 2u
+/* HSZ_FLAG_INTER_BLOCK selects HSZp's decorrelation (Sec. IV, prediction
+ * across block borders) for fields of any rank: p_i = q_i - q_{i-1} over the
+ * field read as one flat array, q_{-1} = 0, in the 1D partition of S; no
+ * metadata (stage 1 is HSZ_ERR_UNSUPPORTED, stage 2 is p int32[n]).  q is
+ * the prefix sum of p over the whole field, computed device-wide in tiles
+ * (stages 3 and 4 need hsz_decompress_workspace bytes).  On stage 2 (whole
+ * field): HSZ_MEAN through the weights N - i of Sec. V-A and HSZ_VAR through
+ * the running sum of q; derivatives need stage 3 (a 1D partition keeps no
+ * multidimensional layout); stages 3 and 4 take every operation.  Batches,
+ * block indexes and fused vector fields return HSZ_ERR_UNSUPPORTED. */
+#define HSZ_FLAG_INTER_BLOCK 4u
 int hsz_compress_flags(const void *d_x, int dtype, int ndim, const int64_t *h_dims, double eb,
                        int eb_is_rel, int block, uint32_t flags, void *d_out, uint64_t cap,
                        void *d_workspace, uint64_t workspace_bytes, void *stream);
@@ -197,8 +208,13 @@ int hsz_read_header(const void *h_bytes, uint64_t len, uint64_t len_stream, hsz_
  *   HSZ_FLOAT : d' = (dtype)(q * Delta), dtype[n] */
 int hsz_stage_bytes(const hsz_header *h, int stage, uint64_t *h_bytes);
 
+/* Workspace hsz_decompress_to_stage needs for this stream and stage: 256
+ * bytes (the status word), plus tile sums for stages 3 and 4 of
+ * HSZ_FLAG_INTER_BLOCK streams. */
+int hsz_decompress_workspace(const hsz_header *h, int stage, uint64_t *h_bytes);
+
 /* Decode the stream d_c (device) to 'stage' into d_out (capacity 'cap').
- * d_workspace (at least 256 bytes) receives the status word: a block whose
+ * d_workspace (hsz_decompress_workspace bytes) receives the status word: a block whose
  * width or payload disagrees with the chunk table is reported as
  * HSZ_ERR_BAD_STREAM and decoded as constant q0 (never read out of bounds). */
 int hsz_decompress_to_stage(const void *d_c, const hsz_header *h, int stage, void *d_out,

@@ -84,10 +84,13 @@ inline int check_header(const hsz_header* h) {
   int64_t d3[3], n;
   if (!dims3_of(h->ndim, h->dims, d3, &n) || n != h->n) return HSZ_ERR_BAD_STREAM;
   if (!valid_block(h->block)) return HSZ_ERR_UNSUPPORTED;
-  if (h->flags != 0 && h->flags != HSZ_FLAG_BLOCK_MEAN && h->flags != HSZ_FLAG_LORENZO) return HSZ_ERR_BAD_STREAM;
+  if (h->flags != 0 && h->flags != HSZ_FLAG_BLOCK_MEAN && h->flags != HSZ_FLAG_LORENZO &&
+      h->flags != HSZ_FLAG_INTER_BLOCK)
+    return HSZ_ERR_BAD_STREAM;
   if (h->flags == HSZ_FLAG_LORENZO && h->ndim < 2) return HSZ_ERR_BAD_STREAM;
-  hsz::Layout L = h->flags == HSZ_FLAG_LORENZO ? hsz::make_layout_nd(d3, h->ndim, h->block)
-                                               : hsz::make_layout(h->n, h->block);
+  hsz::Layout L = h->flags == HSZ_FLAG_LORENZO       ? hsz::make_layout_nd(d3, h->ndim, h->block)
+                  : h->flags == HSZ_FLAG_INTER_BLOCK ? hsz::make_layout_flat(h->n, h->block)
+                                                     : hsz::make_layout(h->n, h->block);
   if (L.nb != h->nb || L.nchunks != h->nchunks || L.off_chunk != h->off_chunk || L.off_q0 != h->off_q0 ||
       L.off_width != h->off_width || L.off_payload != h->off_payload)
     return HSZ_ERR_BAD_STREAM;

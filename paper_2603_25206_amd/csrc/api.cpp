@@ -33,13 +33,20 @@ bool whole_box(const hsz::OpTarget& t) {
   return b.z0 == 0 && b.y0 == 0 && b.x0 == 0 && b.z1 == t.d.z && b.y1 == t.d.y && b.x1 == t.d.x;
 }
 
-bool is_nd(const hsz_header* h) { return (h->flags & HSZ_FLAG_LORENZO) != 0; }
+// the Lorenzo family: HSZp-nd (nd blocks) and HSZp (deltas across the blocks
+// of the flat field); neither stores metadata
+bool is_nd(const hsz_header* h) { return (h->flags & (HSZ_FLAG_LORENZO | HSZ_FLAG_INTER_BLOCK)) != 0; }
+bool is_flat(const hsz_header* h) { return (h->flags & HSZ_FLAG_INTER_BLOCK) != 0; }
 
 hsz::NdGrid grid_of(const hsz_header* h) {
+  if (is_flat(h)) return hsz::flat_grid(h->n, h->block);
   int64_t d3[3], n;
   dims3_of(h->ndim, h->dims, d3, &n);
   return hsz::nd_grid(d3, h->ndim, h->block);
 }
+
+// tile sums of the device-wide scan of HSZp's single row (stages 3 and 4)
+uint64_t flat_tmp_bytes(const hsz_header* h) { return is_flat(h) ? hsz::lz_scan_tmp_bytes(h->n) : 0; }
 
 // HSZp-nd streams: the fused routes and the D_p operations rebuild a stage
 // in scratch memory after the operation's own workspace (4 bytes per point,
@@ -48,9 +55,10 @@ uint64_t nd_scratch_off(const hsz_header* h) {
   const uint64_t a = hsz::op_workspace_bytes(), b = hsz::grad_workspace_bytes(h->nb);
   return ((a > b ? a : b) + 255) / 256 * 256;
 }
-uint64_t nd_workspace(const hsz_header* h) {
-  return nd_scratch_off(h) + (h->dtype == HSZ_F64 ? 8 : 4) * (uint64_t)h->n;
+uint64_t nd_scratch_bytes(const hsz_header* h) {
+  return ((h->dtype == HSZ_F64 ? 8 : 4) * (uint64_t)h->n + 255) / 256 * 256;
 }
+uint64_t nd_workspace(const hsz_header* h) { return nd_scratch_off(h) + nd_scratch_bytes(h) + flat_tmp_bytes(h); }
 bool is_stencil(int op) { return op >= HSZ_DERIV && op <= HSZ_LAPLACIAN; }
 
 // The spread about the integer metadata mean (Sec. V-A, standard deviation
@@ -107,30 +115,33 @@ int nd_op(const void* d_c, const void* d_stage, const hsz_header* h, int stage, 
   if (stage == HSZ_META) return HSZ_ERR_UNSUPPORTED;  // no metadata
   if (stage < HSZ_DELTA || stage > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
   if (op == HSZ_VAR_MT) return HSZ_ERR_UNSUPPORTED;  // block-mean streams only
-  if (stage == HSZ_DELTA && (!whole_box(t) || !(op == HSZ_MEAN || op == HSZ_VAR || op == HSZ_DERIV)))
+  // on D_p: the whole field; the derivative for HSZp-nd only (a 1D partition
+  // keeps no multidimensional layout)
+  if (stage == HSZ_DELTA && (!whole_box(t) || !(op == HSZ_MEAN || op == HSZ_VAR || (op == HSZ_DERIV && !is_flat(h)))))
     return HSZ_ERR_UNSUPPORTED;
   if (op == HSZ_LAPLACIAN && stage == HSZ_QUANT && h->max_abs_q >= kLapMaxQ) return HSZ_ERR_UNSUPPORTED;
   if (ws_bytes < nd_workspace(h)) return HSZ_ERR_CAPACITY;
   uint8_t* ws = (uint8_t*)d_ws;
   int32_t* scratch = (int32_t*)(ws + nd_scratch_off(h));
+  int32_t* tmp = is_flat(h) ? (int32_t*)(ws + nd_scratch_off(h) + nd_scratch_bytes(h)) : nullptr;
   const hsz::StreamView v = view_of(d_c, h);
   const hsz::NdGrid g = grid_of(h);
   int rc = reset_status(d_ws, s);
   if (rc) return rc;
   hipError_t e = hipSuccess;
   if (stage == HSZ_DELTA && op != HSZ_DERIV) {
-    e = hsz::launch_lz_stats(d_c ? nullptr : (const int32_t*)d_stage, v, g, op, d_result, ws, scratch, s);
+    e = hsz::launch_lz_stats(d_c ? nullptr : (const int32_t*)d_stage, v, g, op, d_result, ws, scratch, tmp, s);
   } else if (stage == HSZ_DELTA) {
     const int32_t* p = (const int32_t*)d_stage;
     if (d_c) {
-      e = hsz::lz_decode(v, g, HSZ_DELTA, scratch, (int*)d_ws, s);
+      e = hsz::lz_decode(v, g, HSZ_DELTA, scratch, (int*)d_ws, tmp, s);
       p = scratch;
     }
     if (e == hipSuccess) e = hsz::lz_deriv_p(p, v, g, axis3, d_result, s);
   } else {
     const void* buf = d_stage;
     if (d_c) {
-      e = hsz::lz_decode(v, g, stage, scratch, (int*)d_ws, s);
+      e = hsz::lz_decode(v, g, stage, scratch, (int*)d_ws, tmp, s);
       buf = scratch;
     }
     if (e == hipSuccess)
@@ -215,14 +226,17 @@ int hsz_compress_flags(const void* d_x, int dtype, int ndim, const int64_t* h_di
                        int block, uint32_t flags, void* d_out, uint64_t cap, void* d_workspace,
                        uint64_t workspace_bytes, void* stream) {
   int64_t d3[3], n;
-  if (flags != 0 && flags != HSZ_FLAG_BLOCK_MEAN && flags != HSZ_FLAG_LORENZO) return HSZ_ERR_INVALID_ARG;
+  if (flags != 0 && flags != HSZ_FLAG_BLOCK_MEAN && flags != HSZ_FLAG_LORENZO && flags != HSZ_FLAG_INTER_BLOCK)
+    return HSZ_ERR_INVALID_ARG;
   if (!d_x || !d_out || !d_workspace || (dtype != HSZ_F32 && dtype != HSZ_F64) || !dims3_of(ndim, h_dims, d3, &n))
     return HSZ_ERR_INVALID_ARG;
   if (!aligned16(d_x) || !aligned16(d_out) || !aligned16(d_workspace)) return HSZ_ERR_INVALID_ARG;
   if (!valid_block(block)) return HSZ_ERR_UNSUPPORTED;
   if (flags == HSZ_FLAG_LORENZO && ndim < 2) return HSZ_ERR_UNSUPPORTED;  // the nd partition needs 2D / 3D
   if (!(eb > 0.0) || eb != eb || eb > 1e300) return HSZ_ERR_EB;
-  hsz::Layout L = flags == HSZ_FLAG_LORENZO ? hsz::make_layout_nd(d3, ndim, block) : hsz::make_layout(n, block);
+  hsz::Layout L = flags == HSZ_FLAG_LORENZO       ? hsz::make_layout_nd(d3, ndim, block)
+                  : flags == HSZ_FLAG_INTER_BLOCK ? hsz::make_layout_flat(n, block)
+                                                  : hsz::make_layout(n, block);
   if (workspace_bytes < hsz::compress_workspace_bytes(L)) return HSZ_ERR_CAPACITY;
   if (cap < L.off_payload) return HSZ_ERR_CAPACITY;
   hsz::CompressArgs a;
@@ -240,8 +254,9 @@ int hsz_compress_flags(const void* d_x, int dtype, int ndim, const int64_t* h_di
   a.cap = cap;
   a.ws = (uint8_t*)d_workspace;
   a.ws_bytes = workspace_bytes;
-  hipError_t e = flags == HSZ_FLAG_LORENZO ? hsz::launch_compress_nd(a, (hipStream_t)stream)
-                                           : hsz::launch_compress(a, (hipStream_t)stream);
+  hipError_t e = (flags == HSZ_FLAG_LORENZO || flags == HSZ_FLAG_INTER_BLOCK)
+                     ? hsz::launch_compress_nd(a, (hipStream_t)stream)
+                     : hsz::launch_compress(a, (hipStream_t)stream);
   return e == hipSuccess ? HSZ_OK : hip_fail(e);
 }
 
@@ -273,7 +288,9 @@ int hsz_read_header(const void* h_bytes, uint64_t len, uint64_t len_stream, hsz_
   h.vmax = rdf64(p + 80);
   h.max_abs_q = rd32(p + 88);
   h.flags = rd32(p + 92);
-  if (h.flags != 0 && h.flags != HSZ_FLAG_BLOCK_MEAN && h.flags != HSZ_FLAG_LORENZO) return HSZ_ERR_BAD_STREAM;
+  if (h.flags != 0 && h.flags != HSZ_FLAG_BLOCK_MEAN && h.flags != HSZ_FLAG_LORENZO &&
+      h.flags != HSZ_FLAG_INTER_BLOCK)
+    return HSZ_ERR_BAD_STREAM;
   h.nb = (int64_t)rd64(p + 96);
   h.nchunks = (int64_t)rd64(p + 104);
   h.off_chunk = rd64(p + 112);
@@ -290,8 +307,9 @@ int hsz_read_header(const void* h_bytes, uint64_t len, uint64_t len_stream, hsz_
   // the layout follows from n and S (the 1D partition) or from the dims and S
   // (the nd partition of HSZp-nd, which has no q0 section)
   if (h.flags == HSZ_FLAG_LORENZO && (h.ndim < 2 || (h.block != 32 && h.block != 64))) return HSZ_ERR_BAD_STREAM;
-  const hsz::Layout L = h.flags == HSZ_FLAG_LORENZO ? hsz::make_layout_nd(dd, h.ndim, h.block)
-                                                    : hsz::make_layout(h.n, h.block);
+  const hsz::Layout L = h.flags == HSZ_FLAG_LORENZO       ? hsz::make_layout_nd(dd, h.ndim, h.block)
+                        : h.flags == HSZ_FLAG_INTER_BLOCK ? hsz::make_layout_flat(h.n, h.block)
+                                                          : hsz::make_layout(h.n, h.block);
   const int64_t nb = L.nb;
   const uint64_t op = L.off_payload;
   if (h.nb != L.nb || h.nchunks != L.nchunks || h.off_chunk != L.off_chunk || h.off_q0 != L.off_q0 ||
@@ -306,7 +324,7 @@ int hsz_read_header(const void* h_bytes, uint64_t len, uint64_t len_stream, hsz_
 int hsz_stage_bytes(const hsz_header* h, int stage, uint64_t* h_bytes) {
   if (!h || !h_bytes) return HSZ_ERR_INVALID_ARG;
   const uint64_t n = (uint64_t)h->n, nb = (uint64_t)h->nb;
-  const bool nd = (h->flags & HSZ_FLAG_LORENZO) != 0;  // HSZp-nd: no metadata
+  const bool nd = is_nd(h);  // HSZp-nd and HSZp: no metadata
   switch (stage) {
     case HSZ_META:
       if (nd) return HSZ_ERR_UNSUPPORTED;
@@ -319,19 +337,30 @@ int hsz_stage_bytes(const hsz_header* h, int stage, uint64_t* h_bytes) {
   return HSZ_ERR_INVALID_ARG;
 }
 
+int hsz_decompress_workspace(const hsz_header* h, int stage, uint64_t* h_bytes) {
+  int rc = check_header(h);
+  if (rc) return rc;
+  if (!h_bytes || stage < HSZ_META || stage > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
+  *h_bytes = 256 + (stage >= HSZ_QUANT ? flat_tmp_bytes(h) : 0);
+  return HSZ_OK;
+}
+
 int hsz_decompress_to_stage(const void* d_c, const hsz_header* h, int stage, void* d_out, uint64_t cap,
                             void* d_workspace, uint64_t workspace_bytes, void* stream) {
   int rc = check_header(h);
   if (rc) return rc;
   if (!d_c || !d_out || !d_workspace || !aligned16(d_c) || !aligned16(d_out) || !aligned16(d_workspace))
     return HSZ_ERR_INVALID_ARG;
-  if (workspace_bytes < 256) return HSZ_ERR_CAPACITY;
+  uint64_t wneed = 0;
+  if ((rc = hsz_decompress_workspace(h, stage, &wneed))) return rc;
+  if (workspace_bytes < wneed) return HSZ_ERR_CAPACITY;
   uint64_t need = 0;
   if ((rc = hsz_stage_bytes(h, stage, &need))) return rc == HSZ_ERR_UNSUPPORTED ? rc : HSZ_ERR_INVALID_ARG;
   if (cap < need) return HSZ_ERR_CAPACITY;
   hipStream_t s = (hipStream_t)stream;
   if ((rc = reset_status(d_workspace, s))) return rc;
-  hipError_t e = is_nd(h) ? hsz::lz_decode(view_of(d_c, h), grid_of(h), stage, d_out, (int*)d_workspace, s)
+  hipError_t e = is_nd(h) ? hsz::lz_decode(view_of(d_c, h), grid_of(h), stage, d_out, (int*)d_workspace,
+                                           (int32_t*)((uint8_t*)d_workspace + 256), s)
                           : hsz::launch_decode(view_of(d_c, h), stage, d_out, (int*)d_workspace, s);
   return e == hipSuccess ? HSZ_OK : hip_fail(e);
 }

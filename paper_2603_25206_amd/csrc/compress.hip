@@ -645,7 +645,9 @@ hipError_t run(const CompressArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// ---- HSZp-nd: Lorenzo residual over the whole field, nd blocks ------------------
+// ---- HSZp-nd and HSZp: Lorenzo residual over the whole field -------------------
+// (HSZp-nd: the field's own axes, nd blocks; HSZp: the field as one row of n,
+// ND = 1, blocks of S consecutive elements)
 // The same wave-per-chunk walk as k_quant_meta / k_pack, but lane l of step
 // st owns slot l % S of block 64c + st (64/S) + l/S of the nd partition, at
 // the coordinates of that slot.  The residual of a point is the sum over the
@@ -657,7 +659,7 @@ template <typename T, int ND>
 __device__ __forceinline__ int64_t lz_residual(const T* __restrict__ x, int64_t Y, int64_t X, int64_t z, int64_t y,
                                                int64_t xx, double inv, bool& over, int& qself) {
   int64_t r = 0;
-  constexpr int kCorners = ND == 3 ? 8 : 4;
+  constexpr int kCorners = 1 << ND;
 #pragma unroll
   for (int c = 0; c < kCorners; ++c) {
     const int dz = ND == 3 ? (c >> 2) & 1 : 0, dy = (c >> 1) & 1, dx = c & 1;
@@ -794,14 +796,13 @@ __global__ void __launch_bounds__(kThreads) k_pack_nd(const T* __restrict__ x, N
 }
 
 template <typename T, int S, int ND>
-hipError_t run_nd(const CompressArgs& a, hipStream_t s) {
+hipError_t run_nd(const CompressArgs& a, const NdGrid& g, hipStream_t s) {
   const Layout& L = a.lay;
   CompressWs* ws = (CompressWs*)a.ws;
   double* partial = (double*)(a.ws + kWsPartials);
   uint32_t* chunk_words = (uint32_t*)(a.ws + kWsPartials + 24 * kMinmaxGroups);
   uint8_t* out = a.out;
   const T* x = (const T*)a.x;
-  const NdGrid g = nd_grid(a.dims, a.ndim, S);
   int gm = (int)((L.n + kThreads * 16 - 1) / (kThreads * 16));
   gm = gm < 1 ? 1 : (gm > kMinmaxGroups ? kMinmaxGroups : gm);
   hipLaunchKernelGGL(k_minmax<T>, dim3(gm), dim3(kThreads), 0, s, x, L.n, partial);
@@ -820,14 +821,15 @@ hipError_t run_nd(const CompressArgs& a, hipStream_t s) {
                      (const uint8_t*)(out + L.off_width), (const uint64_t*)(out + L.off_chunk),
                      (uint32_t*)(out + L.off_payload));
   hipLaunchKernelGGL(k_header, dim3(1), dim3(kHeaderBytes), 0, s, out, ws, (const uint32_t*)group_max, grid,
-                     kFlagLorenzo, a.dtype, a.ndim, a.dims[0], a.dims[1], a.dims[2], L.n, L.block, L.nb, L.nchunks,
+                     a.flags, a.dtype, a.ndim, a.dims[0], a.dims[1], a.dims[2], L.n, L.block, L.nb, L.nchunks,
                      L.off_chunk, L.off_q0, L.off_width, L.off_payload);
   return hipGetLastError();
 }
 
 template <typename T, int ND>
 hipError_t compress_nd_block(const CompressArgs& a, hipStream_t s) {
-  return a.lay.block == 32 ? run_nd<T, 32, ND>(a, s) : run_nd<T, 64, ND>(a, s);
+  const NdGrid g = ND == 1 ? flat_grid(a.lay.n, a.lay.block) : nd_grid(a.dims, a.ndim, a.lay.block);
+  return a.lay.block == 32 ? run_nd<T, 32, ND>(a, g, s) : run_nd<T, 64, ND>(a, g, s);
 }
 
 }  // namespace
@@ -846,7 +848,16 @@ Layout make_layout_nd(const int64_t d3[3], int ndim, int block) {
   return L;
 }
 
+Layout make_layout_flat(int64_t n, int block) {
+  Layout L = make_layout(n, block);
+  L.off_width = L.off_q0;  // no metadata
+  L.off_payload = align_up(L.off_width + (uint64_t)L.nb, kSectionAlign);
+  return L;
+}
+
 hipError_t launch_compress_nd(const CompressArgs& a, hipStream_t s) {
+  if (a.flags == kFlagInterBlock)
+    return a.dtype == 1 ? compress_nd_block<float, 1>(a, s) : compress_nd_block<double, 1>(a, s);
   if (a.ndim == 3)
     return a.dtype == 1 ? compress_nd_block<float, 3>(a, s) : compress_nd_block<double, 3>(a, s);
   return a.dtype == 1 ? compress_nd_block<float, 2>(a, s) : compress_nd_block<double, 2>(a, s);

@@ -8,7 +8,8 @@
 
 namespace hsz {
 
-constexpr uint32_t kFlagLorenzo = 2u;  // header flags bit 1
+constexpr uint32_t kFlagLorenzo = 2u;  // header flags bit 1: HSZp-nd
+constexpr uint32_t kFlagInterBlock = 4u;  // header flags bit 2: HSZp, deltas across blocks of the flat field
 constexpr int32_t kPMax = (1 << 30) - 1;  // largest |p| of a Lorenzo residual
 
 // Block shape (slow -> fast, in the 3D view) of the nd partition: S = 2^k
@@ -27,11 +28,12 @@ __host__ __device__ constexpr bool nd_block_shape(int ndim, int S, int b[3]) {
   return true;
 }
 
+// ND = 1: the flat field of HSZp, blocks of S consecutive elements.
 template <int ND, int S>
 struct NdShape {
   static constexpr int k = S == 32 ? 5 : 6;
   static constexpr int ez = ND == 3 ? k / 3 : 0;
-  static constexpr int ey = (k - ez) / 2;
+  static constexpr int ey = ND >= 2 ? (k - ez) / 2 : 0;
   static constexpr int ex = k - ez - ey;
   static constexpr int BZ = 1 << ez, BY = 1 << ey, BX = 1 << ex;
 };
@@ -43,6 +45,9 @@ struct NdGrid {
   int ndim;         // the field's own rank (2 or 3): it fixes the block shape
 };
 
+// HSZp: the field as one row of n (ndim 1 selects blocks of S in a row)
+inline NdGrid flat_grid(int64_t n, int S) { return NdGrid{1, 1, n, 1, 1, (n + S - 1) / S, 1}; }
+
 inline NdGrid nd_grid(const int64_t d3[3], int ndim, int S) {
   int b[3] = {1, 1, 1};
   nd_block_shape(ndim, S, b);
@@ -53,9 +58,11 @@ inline NdGrid nd_grid(const int64_t d3[3], int ndim, int S) {
 // Sections of an HSZp-nd stream: blocks counted over the nd partition, an
 // empty q0 section.
 Layout make_layout_nd(const int64_t d3[3], int ndim, int block);
+// Sections of an HSZp stream (inter-block deltas): the 1D partition, no q0.
+Layout make_layout_flat(int64_t n, int block);
 
-// Compression of an HSZp-nd stream (args as launch_compress; a.lay from
-// make_layout_nd).
+// Compression of an HSZp-nd (a.flags = kFlagLorenzo, a.lay from
+// make_layout_nd) or HSZp stream (kFlagInterBlock, make_layout_flat).
 hipError_t launch_compress_nd(const CompressArgs& a, hipStream_t s);
 
 // Rows of a chunk's LDS staging tile: |p| of a residual is at most 2^ND max|q|
@@ -97,21 +104,28 @@ __device__ __forceinline__ int lz_stage(const StreamView& v, int64_t c, uint32_t
 // prefix sums along every axis (the inverse of the Lorenzo residual) in the
 // output itself; the binary64 stage 4 keeps q in the low word of each
 // element until its conversion, so no scratch memory is needed.
-hipError_t lz_decode(const StreamView& v, const NdGrid& g, int stage, void* out, int* status, hipStream_t s);
+// 'tmp' holds lz_scan_tmp_bytes(n) bytes for a single long row (HSZp).
+hipError_t lz_decode(const StreamView& v, const NdGrid& g, int stage, void* out, int* status, int32_t* tmp,
+                     hipStream_t s);
 
 // Derivative along axis3 (of the 3D view) on D_p (Eq. (derivative_Dp)):
 // p (int32, the field's layout) -> out (field dtype, whole field).
 hipError_t lz_deriv_p(const int32_t* p, const StreamView& v, const NdGrid& g, int axis3, void* out, hipStream_t s);
 
 // Prefix sums along the 3D view's axes z..x except 'skip' (-1: none) of an
-// int32 field stored at element stride es (1 or 2 words), in place.
-hipError_t lz_scan_axes(int32_t* buf, int64_t Z, int64_t Y, int64_t X, int es, int skip, hipStream_t s);
+// int32 field stored at element stride es (1 or 2 words), in place.  A
+// single row (Z = Y = 1) is scanned device-wide in tiles of 4096 words whose
+// sums go to 'tmp' (lz_scan_tmp_bytes(X) bytes).
+hipError_t lz_scan_axes(int32_t* buf, int64_t Z, int64_t Y, int64_t X, int es, int skip, int32_t* tmp,
+                        hipStream_t s);
+constexpr int64_t kFlatTile = 4096;
+inline uint64_t lz_scan_tmp_bytes(int64_t n) { return ((uint64_t)(4 * ((n + kFlatTile - 1) / kFlatTile)) + 255) / 256 * 256; }
 
 // Statistics of an HSZp-nd stream on D_p (whole field): MEAN through the
 // nd weights of Sec. V-A (from a stage-2 buffer, or fused from the stream
 // when p == nullptr), VAR through the prefix sums of Alg. 4 (p copied to
 // 'scratch', 4n bytes, and rebuilt there; fused: decoded there).
 hipError_t launch_lz_stats(const int32_t* p, const StreamView& v, const NdGrid& g, int op, void* result,
-                           uint8_t* ws, int32_t* scratch, hipStream_t s);
+                           uint8_t* ws, int32_t* scratch, int32_t* tmp, hipStream_t s);
 
 }  // namespace hsz

@@ -1,6 +1,7 @@
 // lorenzo.hip -- decoding of HSZp-nd streams (Sec. IV, multidimensional
-// Lorenzo decorrelation) and the derivative on their decorrelated data
-// (Eq. (derivative_Dp)).
+// Lorenzo decorrelation) and HSZp streams (deltas across block borders, the
+// one-dimensional case over the flat field), and the derivative on the
+// decorrelated data of HSZp-nd (Eq. (derivative_Dp)).
 //
 // D_p: one wavefront per 64-block chunk, one lane per nd block; the lane
 // decodes its block slot by slot from its LDS column and writes each slot to
@@ -9,7 +10,9 @@
 // place with one pass per axis: along x a wave per row (four words per lane,
 // a wave scan, a carry across 256-word segments), along y and z a thread per
 // column walking the axis with a running sum (consecutive threads own
-// consecutive x, so every step is a coalesced row).  Partial sums never
+// consecutive x, so every step is a coalesced row).  HSZp's single row of n
+// is scanned device-wide instead: tile sums, a scan of those, and each tile
+// scanned again with its offset.  Partial sums never
 // overflow 32 bits: after the x pass a value is a mixed difference of at most
 // four q (|q| < 2^29), after the y pass of two.
 // D_f: D_q, then each word is converted in place.  A binary64 output keeps q
@@ -31,29 +34,69 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWavesPerGroup = kThreads / kWave;
 
-// D_p -> out (int32 words at element stride es), the field's layout.
+// D_p -> out (int32 words at element stride es), the field's layout.  The
+// flat field (ND = 1) covers 64 S consecutive words per chunk: each lane
+// puts its block's S values in row l of a (64 x (S+1))-word LDS tile (the +1
+// keeps the writes conflict-free) and the wave stores the chunk 64 words at
+// a time; nd blocks are written row by row (BX consecutive words).
 template <int S, int ND>
-__global__ void __launch_bounds__(kThreads) k_lz_decode_p(StreamView v, NdGrid g, int kmax, int32_t* __restrict__ out,
-                                                         int es, int* status) {
+__global__ void __launch_bounds__(kThreads) k_lz_decode_p(StreamView v, NdGrid g, int kmax, int wave_words,
+                                                         int32_t* __restrict__ out, int es, int* status) {
   using Sh = NdShape<ND, S>;
   extern __shared__ uint32_t smem[];
   const int wv = wave_in_group();
-  uint32_t* tile = smem + wv * (kmax + 1) * kWave;
+  uint32_t* tile = smem + wv * wave_words;
   const int l = lane_id();
   const int64_t waves = (int64_t)gridDim.x * kWavesPerGroup;
   for (int64_t c = blockIdx.x * (int64_t)kWavesPerGroup + wv; c < v.nchunks; c += waves) {
     const int w = lz_stage<S>(v, c, tile, kmax, status);
     const int64_t b = c * kChunkBlocks + l;
+    if constexpr (ND == 1) {
+      int vals[S];
+      decode_lane_block<S, kWave, true>(tile + l, w, 0, [&](int j, int p, int) { vals[j] = p; });
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int j = 0; j < S; ++j) tile[l * (S + 1) + j] = (uint32_t)vals[j];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const int64_t base = c * kChunkBlocks * S;
+#pragma unroll
+      for (int m = 0; m < S; ++m) {
+        const int e = m * kWave + l;
+        const int64_t i = base + e;
+        if (i < g.X) out[i * es] = (int32_t)tile[(e / S) * (S + 1) + (e % S)];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      continue;
+    }
     if (b < v.nb) {
       const int64_t oz = (b / (g.nby * g.nbx)) * Sh::BZ, oy = ((b / g.nbx) % g.nby) * Sh::BY,
                     ox = (b % g.nbx) * Sh::BX;
       const bool whole = oz + Sh::BZ <= g.Z && oy + Sh::BY <= g.Y && ox + Sh::BX <= g.X;
       int32_t* base = out + ((oz * g.Y + oy) * g.X + ox) * es;
-      decode_lane_block<S, kWave, true>(tile + l, w, 0, [&](int j, int p, int) {
-        const int sz = j / (Sh::BY * Sh::BX), sy = (j / Sh::BX) % Sh::BY, sx = j % Sh::BX;
-        if (whole || (oz + sz < g.Z && oy + sy < g.Y && ox + sx < g.X))
-          base[((sz * g.Y + sy) * g.X + sx) * es] = p;
-      });
+      int vals[S];
+      decode_lane_block<S, kWave, true>(tile + l, w, 0, [&](int j, int p, int) { vals[j] = p; });
+      if (whole && es == 1 && (g.X & 3) == 0) {
+        // rows of BX (4 or 8) words start 16-byte aligned: vector stores
+        typedef int i4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int r = 0; r < Sh::BZ * Sh::BY; ++r) {
+          int32_t* row = base + ((r / Sh::BY) * g.Y + (r % Sh::BY)) * g.X;
+#pragma unroll
+          for (int x4 = 0; x4 < Sh::BX; x4 += 4)
+            *(i4*)(row + x4) = i4{vals[r * Sh::BX + x4], vals[r * Sh::BX + x4 + 1], vals[r * Sh::BX + x4 + 2],
+                                  vals[r * Sh::BX + x4 + 3]};
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+          const int sz = j / (Sh::BY * Sh::BX), sy = (j / Sh::BX) % Sh::BY, sx = j % Sh::BX;
+          if (whole || (oz + sz < g.Z && oy + sy < g.Y && ox + sx < g.X))
+            base[((sz * g.Y + sy) * g.X + sx) * es] = vals[j];
+        }
+      }
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -66,6 +109,21 @@ __global__ void __launch_bounds__(kThreads) k_scan_x(int32_t* __restrict__ buf, 
   for (int64_t r = blockIdx.x * (int64_t)kWavesPerGroup + wave_in_group(); r < rows; r += waves) {
     int32_t* row = buf + r * X * es;
     int carry = 0;
+    if (es == 1 && (X & 3) == 0) {  // 16-byte loads and stores, lane l <-> words 4l .. 4l+3
+      typedef int i4 __attribute__((ext_vector_type(4)));
+      for (int64_t x0 = 0; x0 < X; x0 += 4 * kWave) {
+        const int64_t x = x0 + 4 * l;
+        i4 v = x < X ? *(const i4*)(row + x) : i4{0, 0, 0, 0};
+        v.y += v.x;
+        v.z += v.y;
+        v.w += v.z;
+        const int incl = wave_incl_scan(v.w);
+        const int before = carry + incl - v.w;
+        if (x < X) *(i4*)(row + x) = i4{v.x + before, v.y + before, v.z + before, v.w + before};
+        carry += __shfl(incl, kWave - 1);
+      }
+      continue;
+    }
     for (int64_t x0 = 0; x0 < X; x0 += 4 * kWave) {
       int v[4];
 #pragma unroll
@@ -88,6 +146,8 @@ __global__ void __launch_bounds__(kThreads) k_scan_x(int32_t* __restrict__ buf, 
   }
 }
 
+constexpr int kBatch = 16;  // rows in flight per thread in the column scans
+
 // prefix sum along a strided axis: element (o, i, k) at ((o len + i) inner + k) es,
 // one thread per (o, k) walking i
 __global__ void __launch_bounds__(kThreads) k_scan_strided(int32_t* __restrict__ buf, int64_t outer, int64_t len,
@@ -98,10 +158,157 @@ __global__ void __launch_bounds__(kThreads) k_scan_strided(int32_t* __restrict__
     const int64_t o = t / inner, k = t % inner;
     int32_t* p = buf + (o * len * inner + k) * es;
     int run = 0;
-#pragma unroll 8
-    for (int64_t i = 0; i < len; ++i) {
+    // a batch of kBatch rows is loaded before any is stored (a store could
+    // alias the next load, so the compiler would not move loads ahead)
+    int64_t i = 0;
+    for (; i + kBatch <= len; i += kBatch) {
+      int v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) v[u] = p[(i + u) * step];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        run += v[u];
+        p[(i + u) * step] = run;
+      }
+    }
+    for (; i < len; ++i) {
       run += p[i * step];
       p[i * step] = run;
+    }
+  }
+}
+
+// ---- one long row (HSZp's flat field): reduce, scan the tile sums, apply ----------
+// Tiles of kFlatTile words; a workgroup of 256 threads, 16 words per thread.
+constexpr int kFlatPer = (int)(kFlatTile / kThreads);
+
+// workgroup inclusive scan of one int per thread; 'total' gets the sum
+__device__ __forceinline__ int group_incl_scan(int v, int* wsum, int& total) {
+  const int incl = wave_incl_scan(v);
+  const int wv = wave_in_group();
+  if (lane_id() == kWave - 1) wsum[wv] = incl;
+  __syncthreads();
+  int before = 0;
+  total = 0;
+  for (int k = 0; k < kWavesPerGroup; ++k) {
+    const int t = wsum[k];
+    before += k < wv ? t : 0;
+    total += t;
+  }
+  __syncthreads();
+  return before + incl;
+}
+
+__global__ void __launch_bounds__(kThreads) k_flat_tile_sums(const int32_t* __restrict__ buf, int64_t n, int es,
+                                                            int32_t* __restrict__ sums) {
+  __shared__ int wsum[kWavesPerGroup];
+  const int64_t ntiles = (n + kFlatTile - 1) / kFlatTile;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int v = 0;
+#pragma unroll
+    for (int k = 0; k < kFlatPer; ++k) {
+      const int64_t i = t * kFlatTile + (int64_t)k * kThreads + threadIdx.x;
+      v += i < n ? buf[i * es] : 0;
+    }
+    int total;
+    group_incl_scan(v, wsum, total);
+    if (threadIdx.x == 0) sums[t] = total;
+  }
+}
+
+// exclusive scan of the tile sums in place (one workgroup; each thread owns
+// kSumsPer consecutive sums per step)
+constexpr int kSumsPer = 32;
+__global__ void __launch_bounds__(kThreads) k_flat_scan_sums(int32_t* __restrict__ sums, int64_t ntiles) {
+  __shared__ int wsum[kWavesPerGroup];
+  int carry = 0;
+  for (int64_t b = 0; b < ntiles; b += (int64_t)kThreads * kSumsPer) {
+    const int64_t i0 = b + (int64_t)threadIdx.x * kSumsPer;
+    int v[kSumsPer];
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < kSumsPer; ++k) {
+      v[k] = i0 + k < ntiles ? sums[i0 + k] : 0;
+      tot += v[k];
+    }
+    int total;
+    const int incl = group_incl_scan(tot, wsum, total);
+    int run = carry + incl - tot;
+#pragma unroll
+    for (int k = 0; k < kSumsPer; ++k) {
+      if (i0 + k < ntiles) sums[i0 + k] = run;
+      run += v[k];
+    }
+    carry += total;
+  }
+}
+
+// each tile: word k*256 + t of the tile is thread t's k-th (coalesced loads
+// and stores); each wave scans its 64 words of every row of 256, the wave
+// totals of all 16 rows meet in LDS once, and every word gets the tile's
+// offset plus the rows before it plus the waves before it in its row
+__global__ void __launch_bounds__(kThreads) k_flat_apply(int32_t* __restrict__ buf, int64_t n, int es,
+                                                        const int32_t* __restrict__ sums) {
+  __shared__ int wt[kFlatPer * kWavesPerGroup];
+  const int64_t ntiles = (n + kFlatTile - 1) / kFlatTile;
+  const int wv = wave_in_group();
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t i0 = t * kFlatTile + threadIdx.x;
+    int v[kFlatPer];
+#pragma unroll
+    for (int k = 0; k < kFlatPer; ++k) {
+      const int64_t i = i0 + (int64_t)k * kThreads;
+      v[k] = i < n ? buf[i * es] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kFlatPer; ++k) {
+      v[k] = wave_incl_scan(v[k]);
+      if (lane_id() == kWave - 1) wt[k * kWavesPerGroup + wv] = v[k];
+    }
+    __syncthreads();
+    int run = sums[t];
+#pragma unroll
+    for (int k = 0; k < kFlatPer; ++k) {
+      int before = 0, row = 0;
+#pragma unroll
+      for (int w = 0; w < kWavesPerGroup; ++w) {
+        const int x = wt[k * kWavesPerGroup + w];
+        before += w < wv ? x : 0;
+        row += x;
+      }
+      const int64_t i = i0 + (int64_t)k * kThreads;
+      if (i < n) buf[i * es] = run + before + v[k];
+      run += row;
+    }
+    __syncthreads();
+  }
+}
+
+// the same over four neighbouring columns per thread with 16-byte loads
+// (es = 1, inner a multiple of 4)
+__global__ void __launch_bounds__(kThreads) k_scan_strided4(int32_t* __restrict__ buf, int64_t outer, int64_t len,
+                                                           int64_t inner) {
+  typedef int i4 __attribute__((ext_vector_type(4)));
+  const int64_t q4 = inner / 4;
+  const int64_t cols = outer * q4;
+  for (int64_t t = blockIdx.x * (int64_t)kThreads + threadIdx.x; t < cols; t += (int64_t)gridDim.x * kThreads) {
+    const int64_t o = t / q4, k = t % q4;
+    i4* p = (i4*)(buf + o * len * inner) + k;
+    i4 run = {0, 0, 0, 0};
+    int64_t i = 0;
+    for (; i + kBatch <= len; i += kBatch) {
+      i4 v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) v[u] = p[(i + u) * q4];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        run += v[u];
+        p[(i + u) * q4] = run;
+      }
+    }
+    for (; i < len; ++i) {
+      run += p[i * q4];
+      p[i * q4] = run;
     }
   }
 }
@@ -109,6 +316,19 @@ __global__ void __launch_bounds__(kThreads) k_scan_strided(int32_t* __restrict__
 // q (int32 at element stride es) -> T in place
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_lz_dequant(void* buf, int64_t n, int es, double quantum) {
+  if (sizeof(T) == 4 && es == 1) {  // four words per thread, 16-byte accesses, then the tail
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int64_t n4 = n / 4;
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n4; i += (int64_t)gridDim.x * kThreads) {
+      const i4 q = ((const i4*)buf)[i];
+      ((f4*)buf)[i] = f4{(float)dequant64(q.x, quantum), (float)dequant64(q.y, quantum),
+                         (float)dequant64(q.z, quantum), (float)dequant64(q.w, quantum)};
+    }
+    for (int64_t i = 4 * n4 + blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+      ((T*)buf)[i] = (T)dequant64(((const int32_t*)buf)[i], quantum);
+    return;
+  }
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
     const int q = ((const int32_t*)buf)[i * es];
     ((T*)buf)[i] = (T)dequant64(q, quantum);
@@ -121,6 +341,22 @@ __global__ void __launch_bounds__(kThreads) k_lz_pair(const int32_t* __restrict_
   const int64_t n = g.Z * g.Y * g.X;
   const int64_t L = a == 0 ? g.Z : a == 1 ? g.Y : g.X;
   const int64_t stride = a == 0 ? g.Y * g.X : a == 1 ? g.X : 1;
+  if (a != 2 && es == 1 && (g.X & 3) == 0) {
+    // four neighbours along x share their index along the axis: 16-byte accesses
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    const int64_t n4 = n / 4, s4 = stride / 4;
+    const i4* p4 = (const i4*)p;
+    for (int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x; e < n4; e += (int64_t)gridDim.x * kThreads) {
+      const int64_t i = (e / s4) % L;
+      i4 t;
+      if (L < 2) t = i4{0, 0, 0, 0};
+      else if (i == 0) t = 2 * p4[e + s4];
+      else if (i == L - 1) t = 2 * p4[e];
+      else t = p4[e] + p4[e + s4];
+      ((i4*)out)[e] = t;
+    }
+    return;
+  }
   for (int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
     const int64_t i = (e / stride) % L;
     int t;
@@ -136,6 +372,18 @@ __global__ void __launch_bounds__(kThreads) k_lz_pair(const int32_t* __restrict_
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_lz_scale(void* buf, int64_t n, int es, double halfq) {
   const T h = (T)halfq;
+  if (sizeof(T) == 4 && es == 1) {
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int64_t n4 = n / 4;
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n4; i += (int64_t)gridDim.x * kThreads) {
+      const i4 q = ((const i4*)buf)[i];
+      ((f4*)buf)[i] = f4{(float)q.x * (float)h, (float)q.y * (float)h, (float)q.z * (float)h, (float)q.w * (float)h};
+    }
+    for (int64_t i = 4 * n4 + blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+      ((T*)buf)[i] = (T)((const int32_t*)buf)[i] * h;
+    return;
+  }
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
     const int num = ((const int32_t*)buf)[i * es];
     ((T*)buf)[i] = (T)num * h;
@@ -150,39 +398,61 @@ unsigned grid_of(int64_t items, int per) {
 template <int S, int ND>
 hipError_t decode_p(const StreamView& v, const NdGrid& g, int32_t* out, int es, int* status, hipStream_t s) {
   const int kmax = lz_kmax<S, ND>(v.max_abs_q);
-  const size_t lds = (size_t)kWavesPerGroup * (kmax + 1) * kWave * sizeof(uint32_t);
+  int wave_words = (kmax + 1) * kWave;
+  if (ND == 1 && wave_words < kWave * (S + 1)) wave_words = kWave * (S + 1);
+  const size_t lds = (size_t)kWavesPerGroup * wave_words * sizeof(uint32_t);
   const int64_t groups = (v.nchunks + kWavesPerGroup - 1) / kWavesPerGroup;
   const unsigned grid = (unsigned)(groups < 8192 ? (groups < 1 ? 1 : groups) : 8192);
-  hipLaunchKernelGGL((k_lz_decode_p<S, ND>), dim3(grid), dim3(kThreads), lds, s, v, g, kmax, out, es, status);
+  hipLaunchKernelGGL((k_lz_decode_p<S, ND>), dim3(grid), dim3(kThreads), lds, s, v, g, kmax, wave_words, out, es,
+                     status);
   return hipGetLastError();
 }
 
 hipError_t decode_p_any(const StreamView& v, const NdGrid& g, int32_t* out, int es, int* status, hipStream_t s) {
   if (g.ndim == 3) return v.block == 32 ? decode_p<32, 3>(v, g, out, es, status, s) : decode_p<64, 3>(v, g, out, es, status, s);
-  return v.block == 32 ? decode_p<32, 2>(v, g, out, es, status, s) : decode_p<64, 2>(v, g, out, es, status, s);
+  if (g.ndim == 2) return v.block == 32 ? decode_p<32, 2>(v, g, out, es, status, s) : decode_p<64, 2>(v, g, out, es, status, s);
+  return v.block == 32 ? decode_p<32, 1>(v, g, out, es, status, s) : decode_p<64, 1>(v, g, out, es, status, s);
 }
 
 }  // namespace
 
-hipError_t lz_scan_axes(int32_t* buf, int64_t Z, int64_t Y, int64_t X, int es, int skip, hipStream_t s) {
-  if (skip != 2) {
+hipError_t lz_scan_axes(int32_t* buf, int64_t Z, int64_t Y, int64_t X, int es, int skip, int32_t* tmp,
+                        hipStream_t s) {
+  if (skip != 2 && Z * Y == 1 && X > kFlatTile) {
+    if (!tmp) return hipErrorInvalidValue;
+    const int64_t ntiles = (X + kFlatTile - 1) / kFlatTile;
+    hipLaunchKernelGGL(k_flat_tile_sums, dim3(grid_of(ntiles, 1)), dim3(kThreads), 0, s, buf, X, es, tmp);
+    hipLaunchKernelGGL(k_flat_scan_sums, dim3(1), dim3(kThreads), 0, s, tmp, ntiles);
+    hipLaunchKernelGGL(k_flat_apply, dim3(grid_of(ntiles, 1)), dim3(kThreads), 0, s, buf, X, es, tmp);
+  } else if (skip != 2) {
     const int64_t rows = Z * Y;
     hipLaunchKernelGGL(k_scan_x, dim3(grid_of(rows, kWavesPerGroup)), dim3(kThreads), 0, s, buf, rows, X, es);
   }
-  if (skip != 1 && Y > 1)
-    hipLaunchKernelGGL(k_scan_strided, dim3(grid_of(Z * X, kThreads)), dim3(kThreads), 0, s, buf, Z, Y, X, es);
-  if (skip != 0 && Z > 1)
-    hipLaunchKernelGGL(k_scan_strided, dim3(grid_of(Y * X, kThreads)), dim3(kThreads), 0, s, buf, (int64_t)1, Z,
-                       Y * X, es);
+  const bool v4 = es == 1 && (X & 3) == 0;
+  if (skip != 1 && Y > 1) {
+    if (v4)
+      hipLaunchKernelGGL(k_scan_strided4, dim3(grid_of(Z * X / 4, kThreads)), dim3(kThreads), 0, s, buf, Z, Y, X);
+    else
+      hipLaunchKernelGGL(k_scan_strided, dim3(grid_of(Z * X, kThreads)), dim3(kThreads), 0, s, buf, Z, Y, X, es);
+  }
+  if (skip != 0 && Z > 1) {
+    if (v4)
+      hipLaunchKernelGGL(k_scan_strided4, dim3(grid_of(Y * X / 4, kThreads)), dim3(kThreads), 0, s, buf, (int64_t)1,
+                         Z, Y * X);
+    else
+      hipLaunchKernelGGL(k_scan_strided, dim3(grid_of(Y * X, kThreads)), dim3(kThreads), 0, s, buf, (int64_t)1, Z,
+                         Y * X, es);
+  }
   return hipGetLastError();
 }
 
-hipError_t lz_decode(const StreamView& v, const NdGrid& g, int stage, void* out, int* status, hipStream_t s) {
+hipError_t lz_decode(const StreamView& v, const NdGrid& g, int stage, void* out, int* status, int32_t* tmp,
+                     hipStream_t s) {
   if (stage < 2 || stage > 4) return hipErrorInvalidValue;
   const int es = (stage == 4 && v.dtype == 2) ? 2 : 1;
   hipError_t e = decode_p_any(v, g, (int32_t*)out, es, status, s);
   if (e != hipSuccess || stage == 2) return e;
-  e = lz_scan_axes((int32_t*)out, g.Z, g.Y, g.X, es, -1, s);
+  e = lz_scan_axes((int32_t*)out, g.Z, g.Y, g.X, es, -1, tmp, s);
   if (e != hipSuccess || stage == 3) return e;
   const int64_t n = g.Z * g.Y * g.X;
   if (v.dtype == 1)
@@ -197,7 +467,7 @@ hipError_t lz_deriv_p(const int32_t* p, const StreamView& v, const NdGrid& g, in
   const int es = v.dtype == 2 ? 2 : 1;
   const int64_t n = g.Z * g.Y * g.X;
   hipLaunchKernelGGL(k_lz_pair, dim3(grid_of(n, kThreads)), dim3(kThreads), 0, s, p, g, axis3, (int32_t*)out, es);
-  hipError_t e = lz_scan_axes((int32_t*)out, g.Z, g.Y, g.X, es, axis3, s);
+  hipError_t e = lz_scan_axes((int32_t*)out, g.Z, g.Y, g.X, es, axis3, nullptr, s);
   if (e != hipSuccess) return e;
   const double halfq = 0.5 * v.quantum;
   if (v.dtype == 1)

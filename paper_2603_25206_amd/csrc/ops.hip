@@ -958,18 +958,21 @@ hipError_t launch_stats_fused(const StreamView& v, int via, int op_in, const OpT
 namespace {
 
 // Mean: sum q = sum over points of (Z - z)(Y - y)(X - x) p (0-based), the nd
-// weights of Sec. V-A.  Products and running sums wrap modulo 2^64, which is
-// exact because the total, sum q, fits in 64 bits.  One row (z, y) per
-// workgroup step.
+// weights of Sec. V-A (HSZp's flat field: N - i).  Products and running sums
+// wrap modulo 2^64, which is exact because the total, sum q, fits in 64
+// bits.  One segment of kSeg points of a row (z, y) per workgroup step.
 __global__ void __launch_bounds__(kThreads) k_lz_mean_buf(const int32_t* __restrict__ p, NdGrid g, Partial* parts) {
   IntAcc acc;
   uint64_t s = 0;
-  const int64_t rows = g.Z * g.Y;
-  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+  const int64_t segs = (g.X + kSeg - 1) / kSeg;
+  const int64_t items = g.Z * g.Y * segs;
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t r = it / segs, x0 = (it % segs) * kSeg;
     const int64_t z = r / g.Y, y = r % g.Y;
     const uint64_t wzy = (uint64_t)(g.Z - z) * (uint64_t)(g.Y - y);
     const int32_t* row = p + r * g.X;
-    for (int64_t x = threadIdx.x; x < g.X; x += kThreads) {
+    const int64_t x1 = min(g.X, x0 + (int64_t)kSeg);
+    for (int64_t x = x0 + threadIdx.x; x < x1; x += kThreads) {
       s += wzy * (uint64_t)(g.X - x) * (uint64_t)(int64_t)row[x];
       acc.cnt += 1;
     }
@@ -1044,32 +1047,37 @@ int launch_lz_mean_fused(const StreamView& v, const NdGrid& g, Partial* parts, i
 }  // namespace
 
 hipError_t launch_lz_stats(const int32_t* p, const StreamView& v, const NdGrid& g, int op, void* result,
-                           uint8_t* ws, int32_t* scratch, hipStream_t s) {
+                           uint8_t* ws, int32_t* scratch, int32_t* tmp, hipStream_t s) {
   Partial* parts = (Partial*)(ws + kPartialOff);
   int* status = (int*)ws;
   int grid = 1;
   if (op == 1 && p) {
-    const int64_t rows = g.Z * g.Y;
-    grid = (int)(rows < kOpWorkgroups ? rows : kOpWorkgroups);
+    grid = grid_for(g.Z * g.Y * ((g.X + kSeg - 1) / kSeg), 1);
     hipLaunchKernelGGL(k_lz_mean_buf, dim3(grid), dim3(kThreads), 0, s, p, g, parts);
   } else if (op == 1) {
     if (g.ndim == 3)
       grid = v.block == 32 ? launch_lz_mean_fused<32, 3>(v, g, parts, status, s)
                            : launch_lz_mean_fused<64, 3>(v, g, parts, status, s);
-    else
+    else if (g.ndim == 2)
       grid = v.block == 32 ? launch_lz_mean_fused<32, 2>(v, g, parts, status, s)
                            : launch_lz_mean_fused<64, 2>(v, g, parts, status, s);
+    else
+      grid = v.block == 32 ? launch_lz_mean_fused<32, 1>(v, g, parts, status, s)
+                           : launch_lz_mean_fused<64, 1>(v, g, parts, status, s);
   } else if (op == 2) {
     const int64_t n = g.Z * g.Y * g.X;
     if (p) hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n, kThreads * 4)), dim3(kThreads), 0, s, p, n, scratch);
     else {
-      hipError_t e = lz_decode(v, g, 2, scratch, status, s);
+      hipError_t e = lz_decode(v, g, 2, scratch, status, tmp, s);
       if (e != hipSuccess) return e;
     }
-    const int last = g.ndim == 3 ? 0 : 1;  // the field's slowest axis in the 3D view
-    hipError_t e = lz_scan_axes(scratch, g.Z, g.Y, g.X, 1, last, s);
+    // the prefix sums over every axis but the field's slowest (3D view: z for
+    // 3D, y for 2D); HSZp's single row is scanned whole and then only read
+    const int last = g.ndim == 3 ? 0 : (g.ndim == 2 ? 1 : -1);
+    hipError_t e = lz_scan_axes(scratch, g.Z, g.Y, g.X, 1, last, tmp, s);
     if (e != hipSuccess) return e;
-    const int64_t len = last == 0 ? g.Z : g.Y, inner = last == 0 ? g.Y * g.X : g.X;
+    const int64_t len = last == 0 ? g.Z : (last == 1 ? g.Y : 1);
+    const int64_t inner = last == 0 ? g.Y * g.X : g.X;
     grid = grid_for(inner, kThreads);
     hipLaunchKernelGGL(k_lz_scan_stats, dim3(grid), dim3(kThreads), 0, s, scratch, len, inner, parts);
   } else {

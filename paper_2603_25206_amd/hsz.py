@@ -29,6 +29,7 @@ META, DELTA, QUANT, FLOAT = 1, 2, 3, 4
 MEAN, VAR, DERIV, GRADMAG, LAPLACIAN, DIVERGENCE, CURL, VAR_MT = 1, 2, 3, 4, 5, 6, 7, 8
 FLAG_BLOCK_MEAN = 1  # header flag: block-mean decorrelation (HSZx)
 FLAG_LORENZO = 2  # header flag: Lorenzo decorrelation over the whole field, nd blocks (HSZp-nd)
+FLAG_INTER_BLOCK = 4  # header flag: deltas across the blocks of the flat field (HSZp)
 HEADER_BYTES = 256
 
 _OPS = {"mean": MEAN, "var": VAR, "var_mt": VAR_MT, "deriv": DERIV, "gradmag": GRADMAG, "laplacian": LAPLACIAN,
@@ -87,7 +88,7 @@ class Tuning(ctypes.Structure):
 EXPORTS = (
     "hsz_strerror", "hsz_version", "hsz_last_hip_error", "hsz_read_status", "hsz_compress_bound",
     "hsz_compress_workspace", "hsz_compress", "hsz_compress_flags", "hsz_read_header", "hsz_stage_bytes",
-    "hsz_decompress_to_stage", "hsz_op_workspace", "hsz_op_on_stage", "hsz_op_fused",
+    "hsz_decompress_to_stage", "hsz_decompress_workspace", "hsz_op_workspace", "hsz_op_on_stage", "hsz_op_fused",
     "hsz_batch_workspace", "hsz_batch_run", "hsz_plan_create", "hsz_plan_update", "hsz_plan_launch",
     "hsz_plan_destroy", "hsz_block_index_bytes", "hsz_block_index", "hsz_vector_workspace",
     "hsz_vector_op_on_stage", "hsz_vector_op_fused",
@@ -118,6 +119,7 @@ def load(path: str = LIB_PATH):
         "hsz_read_header": (i32, [P, u64, u64, ctypes.POINTER(Header)]),
         "hsz_stage_bytes": (i32, [ctypes.POINTER(Header), i32, pu64]),
         "hsz_decompress_to_stage": (i32, [P, ctypes.POINTER(Header), i32, P, u64, P, u64, P]),
+        "hsz_decompress_workspace": (i32, [ctypes.POINTER(Header), i32, ctypes.POINTER(ctypes.c_uint64)]),
         "hsz_op_workspace": (i32, [ctypes.POINTER(Header), i32, pu64]),
         "hsz_op_on_stage": (i32, [P, ctypes.POINTER(Header), i32, i32, i32, ctypes.POINTER(Box), P, u64, P,
                                   u64, P]),
@@ -260,12 +262,14 @@ def compress_bound(shape, dtype: int, block: int) -> int:
 
 def compress(x: torch.Tensor, eb: float, rel: bool = True, block: int = 32, stream=None,
              out: torch.Tensor | None = None, check: bool = True, mean_dec: bool = False,
-             lorenzo: bool = False) -> Compressed:
+             lorenzo: bool = False, inter_block: bool = False) -> Compressed:
     """c = C(x, eb) on the GPU.  x: contiguous float32/float64 CUDA tensor.
     mean_dec selects the block-mean decorrelation (HSZx), lorenzo the nd
-    Lorenzo decorrelation of HSZp-nd (2D / 3D fields), instead of deltas."""
-    if mean_dec and lorenzo:
-        raise ValueError("block-mean and Lorenzo decorrelation are exclusive")
+    Lorenzo decorrelation of HSZp-nd (2D / 3D fields), inter_block HSZp's
+    deltas across block borders, instead of in-block deltas."""
+    if int(bool(mean_dec)) + int(bool(lorenzo)) + int(bool(inter_block)) > 1:
+        raise ValueError("block-mean, Lorenzo and inter-block decorrelation are exclusive")
+    flags = FLAG_BLOCK_MEAN if mean_dec else (FLAG_LORENZO if lorenzo else (FLAG_INTER_BLOCK if inter_block else 0))
     lib = load()
     if not x.is_cuda or not x.is_contiguous():
         raise ValueError("x must be a contiguous GPU tensor")
@@ -282,8 +286,7 @@ def compress(x: torch.Tensor, eb: float, rel: bool = True, block: int = 32, stre
     ws = workspace(wsb.value, x.device, key="compress")
     s = _stream(stream)
     _check(lib.hsz_compress_flags(ctypes.c_void_p(x.data_ptr()), dt, len(shape), dims, float(eb), int(rel),
-                                  block, FLAG_BLOCK_MEAN if mean_dec else (FLAG_LORENZO if lorenzo else 0),
-                                  ctypes.c_void_p(out.data_ptr()),
+                                  block, flags, ctypes.c_void_p(out.data_ptr()),
                                   out.numel(), ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(s)),
            "compress")
     if not check:
@@ -319,7 +322,9 @@ def decompress_to_stage(c: Compressed, stage, stream=None, out: torch.Tensor | N
     nbytes = stage_bytes(h, stage)
     if out is None:
         out = _empty_bytes(nbytes, c.data.device)
-    ws = workspace(256, c.data.device, key="decode")
+    wsb = ctypes.c_uint64()
+    _check(lib.hsz_decompress_workspace(ctypes.byref(h), stage, ctypes.byref(wsb)), "decompress_workspace")
+    ws = workspace(wsb.value, c.data.device, key="decode")
     _check(lib.hsz_decompress_to_stage(ctypes.c_void_p(c.data.data_ptr()), ctypes.byref(h), stage,
                                        ctypes.c_void_p(out.data_ptr()), out.numel(),
                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(),
@@ -336,7 +341,7 @@ def stage_view(buf: torch.Tensor, h: Header, stage: int):
     if stage == META:
         return buf[: 4 * nb].view(torch.int32)
     if stage == DELTA:
-        nq = 0 if h.flags & FLAG_LORENZO else nb  # HSZp-nd streams carry no metadata
+        nq = 0 if h.flags & (FLAG_LORENZO | FLAG_INTER_BLOCK) else nb  # no metadata in these modes
         v = buf[: 4 * (n + nq)].view(torch.int32)
         return v[:n].view(h.shape), v[n:]
     if stage == QUANT:

@@ -1,7 +1,9 @@
 """GPU parity for HSZp-nd streams (Sec. IV, multidimensional Lorenzo
-decorrelation) against the oracle: compressed bytes, stages 2-4, the mean
-with nd weights and Alg. 4 on D_p, the derivative of Eq. (derivative_Dp) on
-D_p, every operation through D_q and D_f, and the routes this mode refuses.
+decorrelation) and HSZp streams (deltas across the blocks of the flat
+field) against the oracle: compressed bytes, stages 2-4, the mean with its
+weights and Alg. 4 (the running sum for HSZp) on D_p, the derivative of
+Eq. (derivative_Dp) on D_p of HSZp-nd, every operation through D_q and D_f,
+and the routes these modes refuse.
 
 Bars: bytes, stages and integer sums bit-exact; means and variances 1e-12
 relative (the mean against max(|mean|, mean |d'|)); the D_p derivative
@@ -229,3 +231,73 @@ def test_residual_range_error():
     with pytest.raises(hsz.HszError) as e:
         hsz.compress(torch.from_numpy(x).to(DEV), 1e-9, rel=True, block=64, lorenzo=True)
     assert e.value.code == hsz.ERR_RANGE
+
+
+# ---- HSZp: deltas across the blocks of the flat field ---------------------------------
+
+FLAT_CASES = [
+    ((1000003,), np.float32, 1e-3, 32),  # 245 scan tiles, ragged last tile and block
+    ((64, 64, 64), np.float32, 1e-4, 64),
+    ((181, 367), np.float64, 1e-6, 32),
+    ((3000,), np.float32, 1e-3, 32),  # below one scan tile
+    ((5,), np.float32, 1e-3, 32),
+]
+
+
+@pytest.fixture(scope="module", params=FLAT_CASES, ids=[case_id(c) for c in FLAT_CASES])
+def fcase(request):
+    shape, dt, rel, S = request.param
+    say(f"[case] inter-block {case_id(request.param)}")
+    f = synth.gaussian_mixture(shape, 5, (2.0, max(3.0, min(shape) / 3.0)), seed=sum(shape) + 2 * S)
+    x = np.ascontiguousarray(f.astype(dt))
+    ref = oracle.compress(x, rel, rel=True, block=S, inter_block=True)
+    c = hsz.compress(torch.from_numpy(x).to(DEV), rel, rel=True, block=S, inter_block=True)
+    torch.cuda.synchronize()
+    h = oracle.read_header(ref)
+    q = oracle.decompress(ref, oracle.QUANT)
+    p, _ = oracle.decompress(ref, oracle.DELTA)
+    return dict(x=x, ref=ref, c=c, h=h, q=q, p=p, xh64=oracle.dequantize64(q, h.quantum), shape=shape)
+
+
+def test_inter_block_bytes_stages_and_dp_statistics(fcase):
+    c, ref, h = fcase["c"], fcase["ref"], fcase["h"]
+    assert c.header.flags == hsz.FLAG_INTER_BLOCK
+    assert np.array_equal(c.to_bytes(), ref)
+    p, q0 = hsz.decompress_to_stage(c, hsz.DELTA, check=True)
+    assert q0.numel() == 0 and np.array_equal(p.cpu().numpy(), fcase["p"])
+    assert np.array_equal(hsz.decompress_to_stage(c, hsz.QUANT, check=True).cpu().numpy(), fcase["q"])
+    f = hsz.decompress_to_stage(c, hsz.FLOAT, check=True).cpu().numpy()
+    assert np.array_equal(f.view(np.uint8), oracle.decompress(ref, oracle.FLOAT).view(np.uint8))
+    n, s1, s2 = oracle.int_sums(fcase["q"], None)
+    ms1, mmean = oracle.lz_mean_p(fcase["p"].ravel(), h.quantum)
+    vr = oracle.lz_var_p(fcase["p"].ravel(), h.quantum)
+    assert (ms1, vr["s2"]) == (s1, s2)
+    scale = max(abs(mmean), float(np.mean(np.abs(fcase["xh64"]))))
+    dbuf = (p, q0)
+    for got in (hsz.op_fused(c, hsz.DELTA, "mean"), hsz.op_on_stage(dbuf, c.header, hsz.DELTA, "mean")):
+        assert (got["n"], got["s1"]) == (n, s1)
+        assert got["mean"] == pytest.approx(mmean, rel=0, abs=1e-12 * scale)
+    for got in (hsz.op_fused(c, hsz.DELTA, "var"), hsz.op_on_stage(dbuf, c.header, hsz.DELTA, "var"),
+                hsz.op_fused(c, hsz.QUANT, "var")):
+        assert (got["n"], got["s1"], got["s2"]) == (n, s1, s2)
+        if n > 1:
+            assert got["var"] == pytest.approx(vr["var"], rel=1e-12, abs=0)
+
+
+def test_inter_block_stencils_and_refusals(fcase):
+    c = fcase["c"]
+    nd = len(fcase["shape"])
+    qbuf = hsz.decompress_to_stage(c, hsz.QUANT)
+    a = hsz.op_on_stage(qbuf, c.header, hsz.QUANT, "gradmag").cpu().numpy()
+    f = hsz.op_fused(c, hsz.QUANT, "gradmag").cpu().numpy()
+    assert np.array_equal(a.view(np.uint8), f.view(np.uint8))
+    want = oracle.gradmag(fcase["xh64"])
+    m = float(np.max(np.abs(fcase["xh64"])))
+    tol = (1e-6 if fcase["x"].dtype == np.float32 else 1e-12) * np.abs(want) + 4 * 2.0 ** -53 * m
+    assert not (np.abs(a.astype(np.float64) - want) > tol).any()
+    for fn in (lambda: hsz.op_fused(c, hsz.DELTA, "deriv", axis=nd - 1),
+               lambda: hsz.decompress_to_stage(c, hsz.META),
+               lambda: hsz.Plan([hsz.Job(c, "var", hsz.QUANT)])):
+        with pytest.raises(hsz.HszError) as e:
+            fn()
+        assert e.value.code == hsz.ERR_UNSUPPORTED
