@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--no-vector", action="store_true", help="skip the vector-field (divergence, curl) workload")
     ap.add_argument("--no-hszx", action="store_true", help="skip the block-mean (HSZx) workload")
     ap.add_argument("--no-lorenzo", action="store_true", help="skip the HSZp-nd (Lorenzo) workload")
+    ap.add_argument("--no-ooc", action="store_true", help="skip the out-of-core (host-resident slabs) workload")
     ap.add_argument("--snapshots", type=int, default=64)
     ap.add_argument("--queries", type=int, default=20000)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -351,6 +352,9 @@ def main():
     if not a.no_lorenzo:
         out["lorenzo_nd"] = bench_lorenzo(a, log)
         torch.cuda.empty_cache()
+    if not a.no_ooc:
+        out["out_of_core"] = bench_ooc(a, log)
+        torch.cuda.empty_cache()
     if not a.no_batch:
         out["batching"] = bench_batches(a, log)
         torch.cuda.empty_cache()
@@ -572,6 +576,45 @@ def bench_lorenzo(a, log):
     res["inter_block_1d"] = flat
     log(f"[bench] lorenzo-nd / inter-block: {res}")
     del x, c, cf, ws, wsf, obuf, sbuf
+    return res
+
+
+def bench_ooc(a, log):
+    """The step's 512^3 binary32 field in pinned host memory, compressed as 8
+    slabs of 64 planes with the whole field's quantizer and kept on the host;
+    mean, variance and gradient magnitude streamed through the device slab by
+    slab (Alg. 3's window; the results equal the whole field's).  Host-device
+    copies are inside every time, so these rates are bound by the link, not
+    by HBM; the in-HBM step is the headline."""
+    import torch
+
+    from paper_2603_25206_amd import hsz, synth
+
+    shape = tuple(int(v) for v in a.shape.split(","))
+    xg = synth.make_field_torch(synth.large_field_spec(seed=0, shape=shape), "cuda")
+    x = torch.empty(xg.shape, dtype=xg.dtype, pin_memory=True)
+    x.copy_(xg)
+    del xg
+    torch.cuda.synchronize()
+    orig = x.numel() * x.element_size()
+    planes = max(1, shape[0] // 8)
+    t0 = time.time()
+    slabs = hsz.compress_slabs(x, a.eb, planes, rel=True, block=a.block)
+    torch.cuda.synchronize()
+    res = {"slabs": len(slabs), "planes_per_slab": planes, "orig_bytes": orig,
+           "compressed_bytes": sum(int(h.total_bytes) for _, h in slabs),
+           "compress_slabs_s": round(time.time() - t0, 3)}
+    for op in ("mean", "var", "gradmag"):
+        hsz.ooc_op(slabs, op)  # warm-up (workspace, streams)
+        ts = []
+        for _ in range(3):
+            t1 = time.time()
+            hsz.ooc_op(slabs, op)
+            ts.append(time.time() - t1)
+        ms = float(np.median(ts)) * 1e3
+        res[op] = {"ms": round(ms, 3), "gbs_orig": round(orig / ms / 1e6, 1)}
+    log(f"[bench] out-of-core: {res}")
+    del x, slabs
     return res
 
 

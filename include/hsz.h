@@ -195,6 +195,24 @@ int hsz_compress_flags(const void *d_x, int dtype, int ndim, const int64_t *h_di
                        int eb_is_rel, int block, uint32_t flags, void *d_out, uint64_t cap,
                        void *d_workspace, uint64_t workspace_bytes, void *stream);
 
+/* The same for one slab of a larger field (a range of its slowest axis):
+ * eps and the quantum are derived from the given extremes [vmin, vmax] of
+ * the whole field (as hsz_compress_flags derives them from a field's own),
+ * so every slab shares the whole field's quantizer and q.  The header
+ * records vmin and vmax as given; a slab value outside them is
+ * HSZ_ERR_EB (status word). */
+int hsz_compress_range(const void *d_x, int dtype, int ndim, const int64_t *h_dims, double eb,
+                       int eb_is_rel, double vmin, double vmax, int block, uint32_t flags, void *d_out,
+                       uint64_t cap, void *d_workspace, uint64_t workspace_bytes, void *stream);
+
+/* Extremes of a field: d_out (device, 3 doubles) = {vmin, vmax, 1.0 if a
+ * value is NaN or infinite else 0.0}; d_workspace of
+ * hsz_extremes_workspace bytes.  Reduce the slabs' extremes to the field's
+ * before hsz_compress_range. */
+int hsz_extremes_workspace(uint64_t *h_bytes);
+int hsz_extremes(const void *d_x, int dtype, uint64_t n, double *d_out, void *d_workspace,
+                 uint64_t workspace_bytes, void *stream);
+
 /* Parse and validate a header held in HOST memory.  'len' is the number of
  * stream bytes the caller holds (at least HSZ_HEADER_BYTES); the stream's
  * own length must not exceed 'len_stream' (pass the device buffer size). */
@@ -268,6 +286,27 @@ int hsz_op_on_stage(const void *d_stage, const hsz_header *h, int stage, int op,
 int hsz_op_fused(const void *d_c, const hsz_header *h, int via, int op, int axis,
                  const hsz_box *h_box, void *d_result, uint64_t cap, void *d_workspace,
                  uint64_t workspace_bytes, void *stream);
+
+/* ---- out of core: a field as compressed slabs in host memory (Alg. 3) -----
+ * h_slabs[k] (HOST memory; pinned memory lets the copies overlap) holds the
+ * stream of slab k, hdrs[k] its header: consecutive ranges of the field's
+ * slowest axis in order, compressed by hsz_compress_range with the whole
+ * field's extremes (same dtype, rank, block, quantum and other dims; delta
+ * or block-mean streams).  The slabs pass through the device a few at a
+ * time: at most three compressed slabs, and for stencils two windows of
+ * D_q and two result slabs.
+ *   op = HSZ_MEAN / HSZ_VAR, via HSZ_DELTA or HSZ_QUANT: h_result = one
+ *        hsz_stats of the whole field, from exact per-slab integer sums.
+ *   op = HSZ_DERIV (axis) / HSZ_GRADMAG / HSZ_LAPLACIAN, via HSZ_QUANT:
+ *        h_result (HOST, n * dtype bytes) = the whole field's result; each
+ *        slab is decoded between one-plane halos from its neighbours (the
+ *        window of Alg. 3), so it equals the operation on the whole field.
+ * d_workspace: hsz_ooc_workspace bytes.  Synchronous: returns when the
+ * result is in h_result (or a status code of the stream decoding). */
+int hsz_ooc_workspace(const hsz_header *const *hdrs, int nslabs, int op, uint64_t *h_bytes);
+int hsz_ooc_op(const void *const *h_slabs, const hsz_header *const *hdrs, int nslabs, int via, int op,
+               int axis, void *h_result, uint64_t result_bytes, void *d_workspace,
+               uint64_t workspace_bytes, void *stream);
 
 /* ---- vector fields: divergence and curl, Sec. III-B and Sec. V-C -----------------
  * A vector field of an n-dimensional grid (n = 1..3) is held as n streams of

@@ -222,9 +222,9 @@ int hsz_compress(const void* d_x, int dtype, int ndim, const int64_t* h_dims, do
                             workspace_bytes, stream);
 }
 
-int hsz_compress_flags(const void* d_x, int dtype, int ndim, const int64_t* h_dims, double eb, int eb_is_rel,
-                       int block, uint32_t flags, void* d_out, uint64_t cap, void* d_workspace,
-                       uint64_t workspace_bytes, void* stream) {
+static int compress_impl(const void* d_x, int dtype, int ndim, const int64_t* h_dims, double eb, int eb_is_rel,
+                         int block, uint32_t flags, int fixed, double vmin, double vmax, void* d_out, uint64_t cap,
+                         void* d_workspace, uint64_t workspace_bytes, void* stream) {
   int64_t d3[3], n;
   if (flags != 0 && flags != HSZ_FLAG_BLOCK_MEAN && flags != HSZ_FLAG_LORENZO && flags != HSZ_FLAG_INTER_BLOCK)
     return HSZ_ERR_INVALID_ARG;
@@ -249,6 +249,9 @@ int hsz_compress_flags(const void* d_x, int dtype, int ndim, const int64_t* h_di
   a.eb = eb;
   a.eb_is_rel = eb_is_rel ? 1 : 0;
   a.flags = flags;
+  a.fixed_range = fixed;
+  a.vmin = vmin;
+  a.vmax = vmax;
   a.lay = L;
   a.out = (uint8_t*)d_out;
   a.cap = cap;
@@ -258,6 +261,22 @@ int hsz_compress_flags(const void* d_x, int dtype, int ndim, const int64_t* h_di
                      ? hsz::launch_compress_nd(a, (hipStream_t)stream)
                      : hsz::launch_compress(a, (hipStream_t)stream);
   return e == hipSuccess ? HSZ_OK : hip_fail(e);
+}
+
+int hsz_compress_flags(const void* d_x, int dtype, int ndim, const int64_t* h_dims, double eb, int eb_is_rel,
+                       int block, uint32_t flags, void* d_out, uint64_t cap, void* d_workspace,
+                       uint64_t workspace_bytes, void* stream) {
+  return compress_impl(d_x, dtype, ndim, h_dims, eb, eb_is_rel, block, flags, 0, 0.0, 0.0, d_out, cap, d_workspace,
+                       workspace_bytes, stream);
+}
+
+int hsz_compress_range(const void* d_x, int dtype, int ndim, const int64_t* h_dims, double eb, int eb_is_rel,
+                       double vmin, double vmax, int block, uint32_t flags, void* d_out, uint64_t cap,
+                       void* d_workspace, uint64_t workspace_bytes, void* stream) {
+  if (!(vmin <= vmax) || vmin != vmin || vmax != vmax || vmin - vmin != 0.0 || vmax - vmax != 0.0)
+    return HSZ_ERR_INVALID_ARG;
+  return compress_impl(d_x, dtype, ndim, h_dims, eb, eb_is_rel, block, flags, 1, vmin, vmax, d_out, cap,
+                       d_workspace, workspace_bytes, stream);
 }
 
 int hsz_read_header(const void* h_bytes, uint64_t len, uint64_t len_stream, hsz_header* o) {

@@ -137,8 +137,11 @@ __device__ double ulp_of(double v, int dtype) {
 
 // One workgroup: reduce the min/max partials (256 threads, then a tree),
 // then thread 0 derives eps, eps_q, Delta and 1/Delta.
+// fixed: derive eps and the quantum from the given extremes (those of the
+// whole field a slab belongs to) instead of the reduced ones; a reduced
+// extreme outside them is an error-bound failure (the margin would not hold).
 __global__ void __launch_bounds__(kThreads) k_params(const double* partial, int groups, double eb, int eb_is_rel,
-                                                     int dtype, CompressWs* ws) {
+                                                     int dtype, int fixed, double gmin, double gmax, CompressWs* ws) {
   __shared__ double slo[kThreads], shi[kThreads];
   __shared__ int sbad[kThreads];
   const int t = threadIdx.x;
@@ -167,6 +170,11 @@ __global__ void __launch_bounds__(kThreads) k_params(const double* partial, int 
   // + 0.0 turns a -0.0 extreme into +0.0 so the stored bytes are canonical
   lo = lo + 0.0;
   hi = hi + 0.0;
+  const bool outside = fixed && !bad && (lo < gmin || hi > gmax);
+  if (fixed) {
+    lo = gmin + 0.0;
+    hi = gmax + 0.0;
+  }
   ws->vmin = lo;
   ws->vmax = hi;
   ws->max_abs_q = 0;
@@ -190,7 +198,7 @@ __global__ void __launch_bounds__(kThreads) k_params(const double* partial, int 
   double maxabs = fabs(lo) > fabs(hi) ? fabs(lo) : fabs(hi);
   double margin = (dtype == 1 ? 1.0 : 8.0) * ulp_of(maxabs + eps, dtype);
   double eps_q = eps - margin;
-  if (!(eps_q > 0.0)) {
+  if (!(eps_q > 0.0) || outside) {
     record_status(&ws->status, kErrEb);
     ws->quantum = 1.0;
     ws->inv_quantum = 1.0;
@@ -624,7 +632,8 @@ hipError_t run(const CompressArgs& a, hipStream_t s) {
   int g = (int)((L.n + kThreads * 16 - 1) / (kThreads * 16));
   g = g < 1 ? 1 : (g > kMinmaxGroups ? kMinmaxGroups : g);
   hipLaunchKernelGGL(k_minmax<T>, dim3(g), dim3(kThreads), 0, s, x, L.n, partial);
-  hipLaunchKernelGGL(k_params, dim3(1), dim3(kThreads), 0, s, partial, g, a.eb, a.eb_is_rel, a.dtype, ws);
+  hipLaunchKernelGGL(k_params, dim3(1), dim3(kThreads), 0, s, partial, g, a.eb, a.eb_is_rel, a.dtype,
+                     a.fixed_range, a.vmin, a.vmax, ws);
   const int64_t cg = (L.nchunks + 3) / 4;
   const int grid = (int)(cg < kMetaGroups ? cg : kMetaGroups);
   uint32_t* group_max = (uint32_t*)(a.ws + ws_group_max_off(L));
@@ -806,7 +815,8 @@ hipError_t run_nd(const CompressArgs& a, const NdGrid& g, hipStream_t s) {
   int gm = (int)((L.n + kThreads * 16 - 1) / (kThreads * 16));
   gm = gm < 1 ? 1 : (gm > kMinmaxGroups ? kMinmaxGroups : gm);
   hipLaunchKernelGGL(k_minmax<T>, dim3(gm), dim3(kThreads), 0, s, x, L.n, partial);
-  hipLaunchKernelGGL(k_params, dim3(1), dim3(kThreads), 0, s, partial, gm, a.eb, a.eb_is_rel, a.dtype, ws);
+  hipLaunchKernelGGL(k_params, dim3(1), dim3(kThreads), 0, s, partial, gm, a.eb, a.eb_is_rel, a.dtype,
+                     a.fixed_range, a.vmin, a.vmax, ws);
   const int64_t cg = (L.nchunks + 3) / 4;
   const int grid = (int)(cg < kMetaGroups ? cg : kMetaGroups);
   uint32_t* group_max = (uint32_t*)(a.ws + ws_group_max_off(L));
@@ -824,6 +834,34 @@ hipError_t run_nd(const CompressArgs& a, const NdGrid& g, hipStream_t s) {
                      a.flags, a.dtype, a.ndim, a.dims[0], a.dims[1], a.dims[2], L.n, L.block, L.nb, L.nchunks,
                      L.off_chunk, L.off_q0, L.off_width, L.off_payload);
   return hipGetLastError();
+}
+
+// extremes and the non-finite flag of a field from the k_minmax partials:
+// out = {vmin, vmax, 1.0 if a value is NaN or infinite else 0.0}
+__global__ void __launch_bounds__(kThreads) k_extremes(const double* partial, int groups, double* out) {
+  __shared__ double slo[kThreads], shi[kThreads], sbad[kThreads];
+  const int t = threadIdx.x;
+  double lo = INFINITY, hi = -INFINITY, bad = 0.0;
+  for (int g = t; g < groups; g += kThreads) {
+    lo = fmin(lo, partial[3 * g + 0]);
+    hi = fmax(hi, partial[3 * g + 1]);
+    bad = partial[3 * g + 2] != 0.0 ? 1.0 : bad;
+  }
+  slo[t] = lo; shi[t] = hi; sbad[t] = bad;
+  __syncthreads();
+  for (int half = kThreads / 2; half >= 1; half >>= 1) {
+    if (t < half) {
+      slo[t] = fmin(slo[t], slo[t + half]);
+      shi[t] = fmax(shi[t], shi[t + half]);
+      sbad[t] = fmax(sbad[t], sbad[t + half]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = slo[0] + 0.0;
+    out[1] = shi[0] + 0.0;
+    out[2] = sbad[0];
+  }
 }
 
 template <typename T, int ND>
@@ -846,6 +884,18 @@ Layout make_layout_nd(const int64_t d3[3], int ndim, int block) {
   L.off_width = L.off_q0;  // no metadata
   L.off_payload = align_up(L.off_width + (uint64_t)L.nb, kSectionAlign);
   return L;
+}
+
+uint64_t extremes_workspace_bytes() { return 24 * (uint64_t)kMinmaxGroups; }
+
+hipError_t launch_extremes(const void* x, int dtype, int64_t n, double* out, uint8_t* ws, hipStream_t s) {
+  double* partial = (double*)ws;
+  int g = (int)((n + kThreads * 16 - 1) / (kThreads * 16));
+  g = g < 1 ? 1 : (g > kMinmaxGroups ? kMinmaxGroups : g);
+  if (dtype == 1) hipLaunchKernelGGL(k_minmax<float>, dim3(g), dim3(kThreads), 0, s, (const float*)x, n, partial);
+  else hipLaunchKernelGGL(k_minmax<double>, dim3(g), dim3(kThreads), 0, s, (const double*)x, n, partial);
+  hipLaunchKernelGGL(k_extremes, dim3(1), dim3(kThreads), 0, s, partial, g, out);
+  return hipGetLastError();
 }
 
 Layout make_layout_flat(int64_t n, int block) {

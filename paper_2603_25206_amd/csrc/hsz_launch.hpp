@@ -51,6 +51,8 @@ struct CompressArgs {
   double eb;
   int eb_is_rel;
   uint32_t flags;  // bit 0: block-mean decorrelation
+  int fixed_range = 0;  // quantizer parameters from [vmin, vmax] (a slab of a larger field)
+  double vmin = 0.0, vmax = 0.0;
   Layout lay;
   uint8_t* out;
   uint64_t cap;

@@ -61,6 +61,12 @@ Layout make_layout_nd(const int64_t d3[3], int ndim, int block);
 // Sections of an HSZp stream (inter-block deltas): the 1D partition, no q0.
 Layout make_layout_flat(int64_t n, int block);
 
+// Extremes of a field ({vmin, vmax, non-finite flag} as three doubles at
+// 'out'), with extremes_workspace_bytes() of scratch: the first pass of a
+// field compressed slab by slab with the whole field's quantizer.
+uint64_t extremes_workspace_bytes();
+hipError_t launch_extremes(const void* x, int dtype, int64_t n, double* out, uint8_t* ws, hipStream_t s);
+
 // Compression of an HSZp-nd (a.flags = kFlagLorenzo, a.lay from
 // make_layout_nd) or HSZp stream (kFlagInterBlock, make_layout_flat).
 hipError_t launch_compress_nd(const CompressArgs& a, hipStream_t s);

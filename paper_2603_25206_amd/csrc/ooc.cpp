@@ -1,0 +1,339 @@
+// ooc.cpp -- operations on a field held as compressed slabs (consecutive
+// ranges of its slowest axis, each an independent stream with the whole
+// field's quantizer) that live in host memory and pass through the device a
+// few at a time: the GPU form of the sliding window of Alg. 3, for fields
+// whose compressed or decompressed form does not fit in device memory.
+//
+// Pipeline (one copy stream beside the caller's compute stream, events
+// between them):
+//   - the compressed slabs go host -> device into a ring of three buffers,
+//     up to two slabs ahead of the one being decoded;
+//   - statistics: the fused integer route of each slab adds (n, sum q,
+//     sum q^2) into its own record; the records are combined exactly at
+//     the end, so the result equals the whole field's;
+//   - stencils: slab k is decoded to D_q into one of two window buffers
+//     between a one-plane halo on each side (the last plane of slab k-1,
+//     kept from the previous window, and the first plane of slab k+1,
+//     decoded into the other window next), the stage-3 kernel runs on the
+//     window with the slab as its box, and the slab of results goes device
+//     -> host from one of two output buffers while the next slab computes.
+// At most three compressed slabs, two windows and two output slabs are in
+// device memory at any time.
+#include <vector>
+
+#include "abi_util.hpp"
+#include "hsz_nd.hpp"
+
+using namespace hsz_abi;
+
+namespace {
+
+__global__ void k_ooc_reset(int* status) {
+  if (threadIdx.x == 0) *status = 0;
+}
+
+uint64_t a256(uint64_t v) { return (v + 255) / 256 * 256; }
+
+struct SlabSet {
+  int K = 0, ndim = 0, dtype = 0;
+  int64_t plane = 1;                   // elements per index of the slowest axis
+  int64_t dims[3] = {0, 0, 0};          // the whole field's dims (its own axes)
+  std::vector<int64_t> planes, first;   // per slab: its planes, its first plane
+  int64_t max_planes = 0;
+  uint64_t max_bytes = 0;
+  uint32_t max_abs_q = 0;
+};
+
+bool is_stencil_op(int op) { return op == HSZ_DERIV || op == HSZ_GRADMAG || op == HSZ_LAPLACIAN; }
+
+// The slabs must be one field cut along its slowest axis: same dtype, rank,
+// block, decorrelation (delta or block-mean), quantum and other dims.
+int describe(const hsz_header* const* h, int K, SlabSet* S) {
+  if (!h || K < 1) return HSZ_ERR_INVALID_ARG;
+  for (int k = 0; k < K; ++k) {
+    if (!h[k]) return HSZ_ERR_INVALID_ARG;
+    int rc = check_header(h[k]);
+    if (rc) return rc;
+  }
+  const hsz_header* h0 = h[0];
+  if (h0->flags > HSZ_FLAG_BLOCK_MEAN) return HSZ_ERR_UNSUPPORTED;
+  S->K = K;
+  S->ndim = h0->ndim;
+  S->dtype = h0->dtype;
+  S->plane = 1;
+  for (int a = 1; a < h0->ndim; ++a) S->plane *= h0->dims[a];
+  int64_t total = 0;
+  for (int k = 0; k < K; ++k) {
+    const hsz_header* hk = h[k];
+    if (hk->dtype != h0->dtype || hk->ndim != h0->ndim || hk->block != h0->block || hk->flags != h0->flags ||
+        hk->quantum != h0->quantum || hk->eb_abs != h0->eb_abs)
+      return HSZ_ERR_INVALID_ARG;
+    for (int a = 1; a < h0->ndim; ++a)
+      if (hk->dims[a] != h0->dims[a]) return HSZ_ERR_INVALID_ARG;
+    S->planes.push_back(hk->dims[0]);
+    S->first.push_back(total);
+    total += hk->dims[0];
+    if (hk->dims[0] > S->max_planes) S->max_planes = hk->dims[0];
+    if (hk->total_bytes > S->max_bytes) S->max_bytes = hk->total_bytes;
+    if (hk->max_abs_q > S->max_abs_q) S->max_abs_q = hk->max_abs_q;
+  }
+  S->dims[0] = total;
+  for (int a = 1; a < h0->ndim; ++a) S->dims[a] = h0->dims[a];
+  return HSZ_OK;
+}
+
+// Workspace: op workspace (status word first) | 3 compressed slabs | 2
+// windows + 2 output slabs (stencils) or K statistics records.
+struct WsLayout {
+  uint64_t cbuf[3], win[2], out[2], stats, total;
+};
+
+WsLayout ws_layout(const SlabSet& S, int op) {
+  WsLayout L{};
+  uint64_t off = a256(hsz::op_workspace_bytes());
+  for (int i = 0; i < 3; ++i) {
+    L.cbuf[i] = off;
+    off += a256(S.max_bytes);
+  }
+  if (is_stencil_op(op)) {
+    const uint64_t esz = S.dtype == HSZ_F32 ? 4 : 8;
+    for (int i = 0; i < 2; ++i) {
+      L.win[i] = off;
+      off += a256(4 * (uint64_t)(S.max_planes + 2) * (uint64_t)S.plane);
+    }
+    for (int i = 0; i < 2; ++i) {
+      L.out[i] = off;
+      off += a256(esz * (uint64_t)S.max_planes * (uint64_t)S.plane);
+    }
+  } else {
+    L.stats = off;
+    off += a256(48 * (uint64_t)S.K);
+  }
+  L.total = off;
+  return L;
+}
+
+// the 3D view of a field of this rank with 'p' indices on its slowest axis
+hsz::Dims3 view_dims(const SlabSet& S, int64_t p) {
+  int64_t d[3] = {p, S.dims[1], S.dims[2]};
+  int64_t d3[3], n;
+  dims3_of(S.ndim, d, d3, &n);
+  return hsz::Dims3{d3[0], d3[1], d3[2]};
+}
+
+struct Events {
+  hipEvent_t h2d[3], used[3], out_ready[2], out_done[2];
+  bool used_set[3] = {false, false, false}, done_set[2] = {false, false};
+  int made = 0;
+  hipError_t create() {
+    hipEvent_t* all[10] = {&h2d[0], &h2d[1], &h2d[2], &used[0], &used[1], &used[2],
+                           &out_ready[0], &out_ready[1], &out_done[0], &out_done[1]};
+    for (; made < 10; ++made) {
+      hipError_t e = hipEventCreateWithFlags(all[made], hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  ~Events() {
+    hipEvent_t all[10] = {h2d[0], h2d[1], h2d[2], used[0], used[1], used[2],
+                          out_ready[0], out_ready[1], out_done[0], out_done[1]};
+    for (int i = 0; i < made; ++i) hipEventDestroy(all[i]);
+  }
+};
+
+// combine per-slab statistics records exactly and finish them as one
+// (the device finalize's formulas, in the same order)
+void combine(const std::vector<uint8_t>& rec, int K, int op, double quantum, hsz_stats* out) {
+  int64_t n = 0, s1 = 0;
+  unsigned __int128 s2 = 0;
+  for (int k = 0; k < K; ++k) {
+    hsz_stats r;
+    memcpy(&r, rec.data() + 48 * (size_t)k, sizeof r);
+    n += r.n;
+    s1 += r.s1;
+    s2 += ((unsigned __int128)(uint64_t)r.s2_hi << 64) | r.s2_lo;
+  }
+  hsz_stats o;
+  memset(&o, 0, sizeof o);
+  o.n = n;
+  o.s1 = s1;
+  o.mean = (double)s1 * quantum / (double)n;
+  o.var = __builtin_nan("");
+  if (op == HSZ_VAR) {
+    o.s2_lo = (uint64_t)s2;
+    o.s2_hi = (int64_t)(uint64_t)(s2 >> 64);
+    const unsigned __int128 a = (unsigned __int128)(uint64_t)n * s2;
+    const uint64_t m = (uint64_t)(s1 < 0 ? -s1 : s1);
+    const unsigned __int128 b = (unsigned __int128)m * m;
+    const unsigned __int128 d = a - b;
+    const double num = (double)(uint64_t)(d >> 64) * 18446744073709551616.0 + (double)(uint64_t)d;
+    if (n > 1) o.var = num / ((double)n * (double)(n - 1)) * (quantum * quantum);
+  }
+  *out = o;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hsz_extremes(const void* d_x, int dtype, uint64_t n, double* d_out, void* d_workspace, uint64_t workspace_bytes,
+                 void* stream) {
+  if (!d_x || !d_out || !d_workspace || n == 0 || (dtype != HSZ_F32 && dtype != HSZ_F64)) return HSZ_ERR_INVALID_ARG;
+  if (!aligned16(d_x) || !aligned16(d_workspace) || ((uintptr_t)d_out & 7u)) return HSZ_ERR_INVALID_ARG;
+  if (workspace_bytes < hsz::extremes_workspace_bytes()) return HSZ_ERR_CAPACITY;
+  hipError_t e = hsz::launch_extremes(d_x, dtype, (int64_t)n, d_out, (uint8_t*)d_workspace, (hipStream_t)stream);
+  return e == hipSuccess ? HSZ_OK : hip_fail(e);
+}
+
+int hsz_extremes_workspace(uint64_t* h_bytes) {
+  if (!h_bytes) return HSZ_ERR_INVALID_ARG;
+  *h_bytes = hsz::extremes_workspace_bytes();
+  return HSZ_OK;
+}
+
+int hsz_ooc_workspace(const hsz_header* const* h_slabs, int nslabs, int op, uint64_t* h_bytes) {
+  if (!h_bytes) return HSZ_ERR_INVALID_ARG;
+  SlabSet S;
+  int rc = describe(h_slabs, nslabs, &S);
+  if (rc) return rc;
+  *h_bytes = ws_layout(S, op).total;
+  return HSZ_OK;
+}
+
+int hsz_ooc_op(const void* const* h_slabs, const hsz_header* const* hdrs, int nslabs, int via, int op, int axis,
+               void* h_result, uint64_t result_bytes, void* d_workspace, uint64_t workspace_bytes, void* stream) {
+  SlabSet S;
+  int rc = describe(hdrs, nslabs, &S);
+  if (rc) return rc;
+  if (!h_slabs || !h_result || !d_workspace || !aligned16(d_workspace)) return HSZ_ERR_INVALID_ARG;
+  for (int k = 0; k < nslabs; ++k)
+    if (!h_slabs[k]) return HSZ_ERR_INVALID_ARG;
+  const bool stencil = is_stencil_op(op);
+  if (!stencil && op != HSZ_MEAN && op != HSZ_VAR) return HSZ_ERR_INVALID_ARG;
+  if (stencil && via != HSZ_QUANT) return HSZ_ERR_UNSUPPORTED;
+  if (!stencil && via != HSZ_DELTA && via != HSZ_QUANT) return HSZ_ERR_UNSUPPORTED;
+  if (op == HSZ_DERIV && (axis < 0 || axis >= S.ndim)) return HSZ_ERR_INVALID_ARG;
+  if (op == HSZ_LAPLACIAN && S.max_abs_q >= (1u << 27)) return HSZ_ERR_UNSUPPORTED;
+  const uint64_t esz = S.dtype == HSZ_F32 ? 4 : 8;
+  int64_t n_total = S.dims[0] * S.plane;
+  if (result_bytes < (stencil ? esz * (uint64_t)n_total : sizeof(hsz_stats))) return HSZ_ERR_CAPACITY;
+  const WsLayout L = ws_layout(S, op);
+  if (workspace_bytes < L.total) return HSZ_ERR_CAPACITY;
+
+  uint8_t* ws = (uint8_t*)d_workspace;
+  int* status = (int*)ws;
+  hipStream_t s = (hipStream_t)stream;
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e);
+  Events ev;
+  e = ev.create();
+  const int K = nslabs;
+  const int64_t P = S.plane;
+  auto issue = [&](int k) -> hipError_t {  // compressed slab k -> ring slot k % 3
+    const int slot = k % 3;
+    if (ev.used_set[slot]) {
+      hipError_t r = hipStreamWaitEvent(cs, ev.used[slot], 0);
+      if (r != hipSuccess) return r;
+    }
+    hipError_t r = hipMemcpyAsync(ws + L.cbuf[slot], h_slabs[k], hdrs[k]->total_bytes, hipMemcpyHostToDevice, cs);
+    if (r != hipSuccess) return r;
+    return hipEventRecord(ev.h2d[slot], cs);
+  };
+  auto mark_used = [&](int k) -> hipError_t {
+    ev.used_set[k % 3] = true;
+    return hipEventRecord(ev.used[k % 3], s);
+  };
+  auto chk = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+    return e == hipSuccess;
+  };
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_ooc_reset, dim3(1), dim3(64), 0, s, status);
+    e = hipGetLastError();
+  }
+  std::vector<uint8_t> records;
+  if (e == hipSuccess && !stencil) {
+    // statistics: every slab through the fused integer route, one record each
+    chk(issue(0));
+    if (K > 1) chk(issue(1));
+    for (int k = 0; k < K && e == hipSuccess; ++k) {
+      if (!chk(hipStreamWaitEvent(s, ev.h2d[k % 3], 0))) break;
+      hsz::OpTarget t;
+      t.d = view_dims(S, S.planes[k]);
+      t.box = hsz::Box3{0, t.d.z, 0, t.d.y, 0, t.d.x};
+      chk(hsz::launch_stats_fused(view_of(ws + L.cbuf[k % 3], hdrs[k]), via, op, t, ws + L.stats + 48 * (uint64_t)k,
+                                  ws, s));
+      chk(mark_used(k));
+      if (k + 2 < K) chk(issue(k + 2));
+    }
+    if (e == hipSuccess) {
+      records.resize(48 * (size_t)K);
+      if (chk(hipStreamSynchronize(cs)) && chk(hipStreamSynchronize(s)))
+        chk(hipMemcpy(records.data(), ws + L.stats, records.size(), hipMemcpyDeviceToHost));
+    }
+  } else if (e == hipSuccess) {
+    // stencils: windows of D_q with one-plane halos, results streamed out
+    const int axis3 = op == HSZ_DERIV ? axis + 3 - S.ndim : 0;
+    const int a_s = 3 - S.ndim;  // the slowest axis in the 3D view
+    uint8_t* win[2] = {ws + L.win[0], ws + L.win[1]};
+    uint8_t* out[2] = {ws + L.out[0], ws + L.out[1]};
+    const uint64_t pb = 4 * (uint64_t)P;  // bytes of one plane of q
+    hsz::StreamView vq = view_of(nullptr, hdrs[0]);
+    auto decode = [&](int k, uint8_t* dst) -> bool {
+      if (!chk(hipStreamWaitEvent(s, ev.h2d[k % 3], 0))) return false;
+      if (!chk(hsz::launch_decode(view_of(ws + L.cbuf[k % 3], hdrs[k]), HSZ_QUANT, dst, status, s))) return false;
+      return chk(mark_used(k));
+    };
+    chk(issue(0));
+    if (K > 1) chk(issue(1));
+    if (e == hipSuccess) decode(0, win[0] + pb);
+    if (K > 2) chk(issue(2));
+    for (int k = 0; k < K && e == hipSuccess; ++k) {
+      uint8_t* cur = win[k % 2];
+      uint8_t* nxt = win[(k + 1) % 2];
+      if (k >= 1)  // the halo before: the last plane of slab k-1, still in the other window
+        chk(hipMemcpyAsync(cur, nxt + pb * (uint64_t)S.planes[k - 1], pb, hipMemcpyDeviceToDevice, s));
+      if (k + 1 < K && e == hipSuccess) {
+        if (!decode(k + 1, nxt + pb)) break;
+        if (k + 3 < K) chk(issue(k + 3));
+        // the halo after: the first plane of slab k+1
+        chk(hipMemcpyAsync(cur + pb * (uint64_t)(1 + S.planes[k]), nxt + pb, pb, hipMemcpyDeviceToDevice, s));
+      }
+      if (e != hipSuccess) break;
+      const int before = k > 0 ? 1 : 0, after = k + 1 < K ? 1 : 0;
+      const int64_t wplanes = S.planes[k] + before + after;
+      hsz::OpTarget t;
+      t.d = view_dims(S, wplanes);
+      t.box = hsz::Box3{0, t.d.z, 0, t.d.y, 0, t.d.x};
+      if (a_s == 0) { t.box.z0 = before; t.box.z1 = before + S.planes[k]; }
+      else if (a_s == 1) { t.box.y0 = before; t.box.y1 = before + S.planes[k]; }
+      else { t.box.x0 = before; t.box.x1 = before + S.planes[k]; }
+      const int o = k % 2;
+      if (ev.done_set[o] && !chk(hipStreamWaitEvent(s, ev.out_done[o], 0))) break;
+      const uint8_t* wbuf = cur + (before ? 0 : pb);
+      if (!chk(hsz::launch_grad_stage(wbuf, HSZ_QUANT, vq, op, axis3, t, out[o], ws, s))) break;
+      if (!chk(hipEventRecord(ev.out_ready[o], s))) break;
+      if (!chk(hipStreamWaitEvent(cs, ev.out_ready[o], 0))) break;
+      const uint64_t ob = esz * (uint64_t)S.planes[k] * (uint64_t)P;
+      if (!chk(hipMemcpyAsync((uint8_t*)h_result + esz * (uint64_t)S.first[k] * (uint64_t)P, out[o], ob,
+                              hipMemcpyDeviceToHost, cs)))
+        break;
+      ev.done_set[o] = true;
+      chk(hipEventRecord(ev.out_done[o], cs));
+    }
+  }
+  // drain both streams whatever happened, so no copy is in flight on return
+  hipError_t e1 = cs ? hipStreamSynchronize(cs) : hipSuccess;
+  hipError_t e2 = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = e1 != hipSuccess ? e1 : e2;
+  int st = 0;
+  if (e == hipSuccess) e = hipMemcpy(&st, status, sizeof st, hipMemcpyDeviceToHost);
+  if (cs) hipStreamDestroy(cs);
+  if (e != hipSuccess) return hip_fail(e);
+  if (st != 0) return st;
+  if (!stencil) combine(records, K, op, hdrs[0]->quantum, (hsz_stats*)h_result);
+  return HSZ_OK;
+}
+
+}  // extern "C"

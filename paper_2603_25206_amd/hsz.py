@@ -91,7 +91,8 @@ EXPORTS = (
     "hsz_decompress_to_stage", "hsz_decompress_workspace", "hsz_op_workspace", "hsz_op_on_stage", "hsz_op_fused",
     "hsz_batch_workspace", "hsz_batch_run", "hsz_plan_create", "hsz_plan_update", "hsz_plan_launch",
     "hsz_plan_destroy", "hsz_block_index_bytes", "hsz_block_index", "hsz_vector_workspace",
-    "hsz_vector_op_on_stage", "hsz_vector_op_fused",
+    "hsz_vector_op_on_stage", "hsz_vector_op_fused", "hsz_compress_range", "hsz_extremes_workspace",
+    "hsz_extremes", "hsz_ooc_workspace", "hsz_ooc_op",
 )
 
 _lib = None
@@ -137,6 +138,12 @@ def load(path: str = LIB_PATH):
         "hsz_vector_workspace": (i32, [P, i32, pu64]),
         "hsz_vector_op_on_stage": (i32, [P, P, i32, i32, i32, ctypes.POINTER(Box), P, u64, P, u64, P]),
         "hsz_vector_op_fused": (i32, [P, P, i32, i32, i32, ctypes.POINTER(Box), P, u64, P, u64, P]),
+        "hsz_compress_range": (i32, [P, i32, i32, pi64, dbl, i32, dbl, dbl, i32, ctypes.c_uint32, P, u64, P, u64,
+                                     P]),
+        "hsz_extremes_workspace": (i32, [pu64]),
+        "hsz_extremes": (i32, [P, i32, u64, P, P, u64, P]),
+        "hsz_ooc_workspace": (i32, [P, i32, i32, pu64]),
+        "hsz_ooc_op": (i32, [P, P, i32, i32, i32, i32, P, u64, P, u64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -649,3 +656,101 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ---- slabs and out-of-core operations (Alg. 3's window over host-resident slabs) ------
+
+def extremes(x: torch.Tensor, stream=None):
+    """(vmin, vmax, has_nonfinite) of a contiguous float32/float64 GPU tensor."""
+    lib = load()
+    dt = F32 if x.dtype == torch.float32 else F64
+    wsb = ctypes.c_uint64()
+    _check(lib.hsz_extremes_workspace(ctypes.byref(wsb)), "extremes_workspace")
+    ws = workspace(wsb.value, x.device, key="extremes")
+    out = torch.empty(4, dtype=torch.float64, device=x.device)
+    _check(lib.hsz_extremes(ctypes.c_void_p(x.data_ptr()), dt, x.numel(), ctypes.c_void_p(out.data_ptr()),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream(stream))),
+           "extremes")
+    v = out.cpu().tolist()
+    return v[0], v[1], bool(v[2])
+
+
+def compress_range(x: torch.Tensor, eb: float, vmin: float, vmax: float, rel: bool = True, block: int = 32,
+                   stream=None, mean_dec: bool = False) -> Compressed:
+    """Compress one slab of a larger field with the whole field's quantizer:
+    eps and the quantum come from the field's extremes [vmin, vmax]."""
+    lib = load()
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous GPU tensor")
+    dt = F32 if x.dtype == torch.float32 else F64
+    shape = tuple(x.shape)
+    dims = _dims(shape)
+    out = _empty_bytes(compress_bound(shape, dt, block), x.device)
+    wsb = ctypes.c_uint64()
+    _check(lib.hsz_compress_workspace(len(shape), dims, block, ctypes.byref(wsb)), "compress_workspace")
+    ws = workspace(wsb.value, x.device, key="compress")
+    _check(lib.hsz_compress_range(ctypes.c_void_p(x.data_ptr()), dt, len(shape), dims, float(eb), int(rel),
+                                  float(vmin), float(vmax), block, FLAG_BLOCK_MEAN if mean_dec else 0,
+                                  ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.c_void_p(ws.data_ptr()),
+                                  ws.numel(), ctypes.c_void_p(_stream(stream))), "compress_range")
+    st = read_status(ws, stream)
+    if st != OK:
+        raise HszError(st, "compress_range")
+    return Compressed(out, read_header(out))
+
+
+def compress_slabs(x: torch.Tensor, eb: float, planes: int, rel: bool = True, block: int = 32,
+                   mean_dec: bool = False, device="cuda"):
+    """Compress a host-resident field slab by slab (ranges of 'planes' indices
+    of its slowest axis) with the whole field's quantizer, keeping only one
+    slab on the device at a time: a first pass reduces the extremes, a
+    second compresses.  Returns [(pinned host uint8 tensor, Header)]."""
+    if x.is_cuda:
+        raise ValueError("x must be a host tensor")
+    n0 = x.shape[0]
+    lo, hi = float("inf"), float("-inf")
+    for a in range(0, n0, planes):
+        vmin, vmax, bad = extremes(x[a:a + planes].contiguous().to(device))
+        if bad:
+            raise HszError(ERR_NONFINITE, "compress_slabs")
+        lo, hi = min(lo, vmin), max(hi, vmax)
+    out = []
+    for a in range(0, n0, planes):
+        c = compress_range(x[a:a + planes].contiguous().to(device), eb, lo, hi, rel=rel, block=block,
+                           mean_dec=mean_dec)
+        nbytes = int(c.header.total_bytes)
+        host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        host.copy_(c.data[:nbytes])
+        out.append((host, c.header))
+    return out
+
+
+def ooc_op(slabs, op, via=QUANT, axis: int = 0, stream=None, device="cuda"):
+    """An operation on the field held as host-resident compressed slabs
+    (compress_slabs), streamed through the device: a stats dict for mean /
+    var, else a pinned host tensor shaped like the whole field."""
+    lib = load()
+    op = _OPS.get(op, op)
+    via = _STAGES.get(via, via)
+    hdrs = [h for _, h in slabs]
+    harr = _headers_array(hdrs)
+    ptrs = (ctypes.c_void_p * len(slabs))(*[t.data_ptr() for t, _ in slabs])
+    wsb = ctypes.c_uint64()
+    _check(lib.hsz_ooc_workspace(ctypes.cast(harr, ctypes.c_void_p), len(slabs), op, ctypes.byref(wsb)),
+           "ooc_workspace")
+    ws = workspace(wsb.value, torch.device(device), key="ooc")
+    h0 = hdrs[0]
+    if op in _STATS:
+        res = torch.empty(48, dtype=torch.uint8, pin_memory=True)
+    else:
+        shape = (sum(int(h.dims[0]) for h in hdrs),) + tuple(h0.shape[1:])
+        n = 1
+        for v in shape:
+            n *= v
+        res = torch.empty(n * (4 if h0.dtype == F32 else 8), dtype=torch.uint8, pin_memory=True)
+    _check(lib.hsz_ooc_op(ctypes.cast(ptrs, ctypes.c_void_p), ctypes.cast(harr, ctypes.c_void_p), len(slabs), via,
+                          op, axis, ctypes.c_void_p(res.data_ptr()), res.numel(), ctypes.c_void_p(ws.data_ptr()),
+                          ws.numel(), ctypes.c_void_p(_stream(stream))), "ooc_op")
+    if op in _STATS:
+        return _stats_from_raw(res.numpy().tobytes())
+    return res.view(h0.torch_dtype).view(shape)
