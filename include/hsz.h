@@ -385,6 +385,10 @@ typedef struct hsz_tuning {
                                   (by default a mean/variance job over the same stream
                                   and box as a gradient job through D_q is summed
                                   inside that job's tiles; results are identical)  */
+  int32_t graph_replay;        /* plans: 1 replays the HIP graph captured at create;
+                                  0 (default) enqueues the pass's kernels directly,
+                                  which reaches the GPU sooner for these few-kernel
+                                  passes (the work table is on the device either way) */
 } hsz_tuning;
 
 /* Workspace a batch needs (bytes). */
@@ -394,9 +398,11 @@ int hsz_batch_workspace(const hsz_work *h_items, int n, uint64_t *h_bytes);
 int hsz_batch_run(const hsz_work *h_items, int n, const hsz_tuning *h_tune, void *d_workspace,
                   uint64_t workspace_bytes, void *stream);
 
-/* A batch captured once as a HIP graph of its kernels and replayed.  The
- * work table is uploaded (synchronously) by hsz_plan_create and by
- * hsz_plan_update, never by a replay.  'stream' must be a created
+/* A batch prepared once and launched many times: its work table is
+ * uploaded (synchronously) by hsz_plan_create and by hsz_plan_update, never
+ * by a launch, and its kernels are captured as a HIP graph.  A launch
+ * enqueues the kernels, or replays the graph when the tuning's
+ * graph_replay is set.  'stream' must be a created
  * (non-null) stream.  hsz_plan_update rewrites the table for a batch of the
  * same structure (same jobs per kernel variant, the same classes with
  * separately summed statistics, no larger index or staging needs) -- new

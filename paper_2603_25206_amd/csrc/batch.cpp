@@ -453,8 +453,15 @@ int hsz_plan_update(hsz_plan* p, const hsz_work* items, int n) {
 int hsz_plan_launch(hsz_plan* p, void* stream) {
   if (!p || !p->exec) return HSZ_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = hipGraphLaunch(p->exec, s);
-  if (e != hipSuccess) return hip_fail(e);
+  hipError_t e;
+  if (p->tune.graph_replay) {
+    if ((e = hipGraphLaunch(p->exec, s)) != hipSuccess) return hip_fail(e);
+  } else {
+    // the table is on the device since create/update: the pass is a handful
+    // of kernel launches, which reach the GPU sooner than a graph launch
+    const int erc = enqueue(p->built, p->d_ws, p->tune, s);
+    if (erc != HSZ_OK) return erc;
+  }
   if ((e = hipEventRecord(p->done, s)) != hipSuccess) return hip_fail(e);
   p->launched = true;
   return HSZ_OK;

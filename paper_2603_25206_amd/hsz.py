@@ -82,7 +82,7 @@ class Work(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("stats_waves_per_cu", ctypes.c_int32), ("grad_groups_per_cu", ctypes.c_int32),
-                ("grad_tz", ctypes.c_int32), ("separate_stats", ctypes.c_int32)]
+                ("grad_tz", ctypes.c_int32), ("separate_stats", ctypes.c_int32), ("graph_replay", ctypes.c_int32)]
 
 
 EXPORTS = (
@@ -591,6 +591,7 @@ def _tuning(tune):
     t.grad_groups_per_cu = int(tune.get("grad_groups_per_cu", 0))
     t.grad_tz = int(tune.get("grad_tz", 0))
     t.separate_stats = int(bool(tune.get("separate_stats", False)))
+    t.graph_replay = int(bool(tune.get("graph_replay", False)))
     return ctypes.byref(t)
 
 

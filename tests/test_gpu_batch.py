@@ -125,10 +125,11 @@ def test_results_independent_of_launch_shape(streams, tune):
         assert same(a, b), k
 
 
-def test_plan_replays_and_updates(streams):
-    say("[case] graph plan")
+@pytest.mark.parametrize("graph_replay", [0, 1])
+def test_plan_replays_and_updates(streams, graph_replay):
+    say(f"[case] plan, graph replay {graph_replay}")
     jobs1 = make_jobs(streams, seed=3)
-    plan = hsz.Plan(jobs1, tune={"grad_tz": 16})
+    plan = hsz.Plan(jobs1, tune={"grad_tz": 16, "graph_replay": graph_replay})
     want1 = [alone(j) for j in jobs1]
     for rep in range(3):
         plan.launch()
