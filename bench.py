@@ -85,11 +85,9 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic():
-    """HBM bytes per launch of the step's gradient kernel from the committed
-    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the same
-    counter reads for a streaming kernel of known size), or None when there is
-    no summary or the kernel sources changed since it was taken."""
+def counter_record():
+    """The committed counter summary of the step's gradient kernel, or None
+    when there is none or the kernel sources changed since it was taken."""
     try:
         with open(COUNTERS) as f:
             lines = f.read().splitlines()
@@ -99,8 +97,32 @@ def counter_traffic():
         if line.startswith("TRAFFIC_JSON:"):
             rec = json.loads(line.split(":", 1)[1])
             if rec.get("source_sha") == kernel_source_sha():
-                return int(rec["bytes_per_launch"])
+                return rec
     return None
+
+
+def counter_traffic():
+    """HBM bytes per launch of the step's gradient kernel (FETCH_SIZE and
+    WRITE_SIZE, each scaled by what the same counter reads for a streaming
+    kernel of known size), or None."""
+    rec = counter_record()
+    return int(rec["bytes_per_launch"]) if rec else None
+
+
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3 T 32-bit lane operations per second
+
+
+def counter_valu(launch_ms):
+    """VALU work of the step's gradient kernel from the committed SQ_INSTS_VALU
+    count (wave instructions per launch, 64 lanes each), as a rate over the
+    measured launch time against the chip's 32-bit VALU peak, or None."""
+    rec = counter_record()
+    if not rec or "valu_insts" not in rec:
+        return None
+    ops = float(rec["valu_insts"]) * 64
+    tops = ops / (launch_ms * 1e-3) / 1e12
+    return {"lane_ops_per_launch": int(ops), "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 1),
+            "unit": "T lane-ops/s", "frac": round(tops / VALU_PEAK_TOPS, 4)}
 
 
 def main():
@@ -301,6 +323,7 @@ def main():
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": a.traffic if a.traffic is not None else counter_traffic(),
+                "valu": counter_valu(ms_replay),
                 "alg_bytes_per_launch": int(alg_step), "launch_ms": round(ms_replay, 4)}
     dom = "gradmag_quant"
     ach_sep = alg[dom] / (per_sep[dom] * 1e-3) / 1e9
