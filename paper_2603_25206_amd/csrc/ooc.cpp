@@ -137,7 +137,7 @@ struct Events {
   ~Events() {
     hipEvent_t all[10] = {h2d[0], h2d[1], h2d[2], used[0], used[1], used[2],
                           out_ready[0], out_ready[1], out_done[0], out_done[1]};
-    for (int i = 0; i < made; ++i) hipEventDestroy(all[i]);
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(all[i]);
   }
 };
 
@@ -329,7 +329,7 @@ int hsz_ooc_op(const void* const* h_slabs, const hsz_header* const* hdrs, int ns
   if (e == hipSuccess) e = e1 != hipSuccess ? e1 : e2;
   int st = 0;
   if (e == hipSuccess) e = hipMemcpy(&st, status, sizeof st, hipMemcpyDeviceToHost);
-  if (cs) hipStreamDestroy(cs);
+  if (cs) (void)hipStreamDestroy(cs);
   if (e != hipSuccess) return hip_fail(e);
   if (st != 0) return st;
   if (!stencil) combine(records, K, op, hdrs[0]->quantum, (hsz_stats*)h_result);

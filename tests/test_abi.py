@@ -211,3 +211,60 @@ def test_block_mean_statistics_validation_before_any_launch(lib):
     assert fused(hm, hsz.DELTA, hsz.VAR_MT, cap=47) == hsz.ERR_CAPACITY
     assert fused(hm, hsz.DELTA, 9) == hsz.ERR_INVALID_ARG
     assert fused(hm, hsz.QUANT, hsz.GRADMAG, cap=4 * x.size) == hsz.ERR_UNSUPPORTED  # fused stencils: delta streams
+
+
+def test_slab_and_out_of_core_validation_before_any_launch(lib):
+    """Slab compression, extremes, out-of-core and decode-workspace entry
+    points refuse bad arguments on the host (fake aligned addresses are
+    never touched)."""
+    fake = ctypes.c_void_p(0x10000)
+    dims = (ctypes.c_int64 * 3)(8, 9, 10)
+    # extremes the wrong way round, or not finite
+    for lo, hi in ((2.0, 1.0), (float("nan"), 1.0), (0.0, float("inf"))):
+        assert lib.hsz_compress_range(fake, hsz.F32, 3, dims, 1e-3, 1, lo, hi, 32, 0, fake, 1 << 20, fake, 1 << 20,
+                                      None) == hsz.ERR_INVALID_ARG
+    w = ctypes.c_uint64()
+    assert lib.hsz_extremes_workspace(ctypes.byref(w)) == 0 and w.value > 0
+    assert lib.hsz_extremes(fake, hsz.F32, 0, fake, fake, w.value, None) == hsz.ERR_INVALID_ARG  # empty field
+    assert lib.hsz_extremes(fake, hsz.F32, 100, fake, fake, w.value - 1, None) == hsz.ERR_CAPACITY
+    # decode workspace: 256 bytes, plus tile sums for stages 3 and 4 of inter-block streams
+    x = np.linspace(-1, 1, 20000).astype(np.float32)
+    hd = hsz.read_header(oracle.compress(x, 1e-3))
+    hi = hsz.read_header(oracle.compress(x, 1e-3, inter_block=True))
+    for stage in (1, 2, 3, 4):
+        assert lib.hsz_decompress_workspace(ctypes.byref(hd), stage, ctypes.byref(w)) == 0 and w.value == 256
+    assert lib.hsz_decompress_workspace(ctypes.byref(hi), 2, ctypes.byref(w)) == 0 and w.value == 256
+    assert lib.hsz_decompress_workspace(ctypes.byref(hi), 3, ctypes.byref(w)) == 0 and w.value > 256
+    assert lib.hsz_decompress_to_stage(fake, ctypes.byref(hi), 3, fake, 4 * x.size, fake, 256,
+                                       None) == hsz.ERR_CAPACITY
+    assert lib.hsz_decompress_to_stage(fake, ctypes.byref(hi), 1, fake, 4 * x.size, fake, 1 << 20,
+                                       None) == hsz.ERR_UNSUPPORTED
+    # out of core: slabs of one field only (same quantum and other dims), delta / block-mean streams
+    f = np.random.default_rng(1).normal(size=(12, 9, 10)).astype(np.float32)
+    a = hsz.read_header(oracle.compress(f[:6], 1e-3))
+    b = hsz.read_header(oracle.compress(f[6:] * 4, 1e-3))  # another quantum
+    c = hsz.read_header(oracle.compress(f[6:, :, :9].copy(), 1e-3))  # other dims
+    nd = hsz.read_header(oracle.compress(f[:6], 1e-3, lorenzo=True))
+
+    def ws_of(hs, op=hsz.MEAN):
+        arr = (ctypes.POINTER(hsz.Header) * len(hs))(*[ctypes.pointer(h) for h in hs])
+        return lib.hsz_ooc_workspace(ctypes.cast(arr, ctypes.c_void_p), len(hs), op, ctypes.byref(w))
+    assert ws_of([a]) == 0
+    assert ws_of([a, b]) == hsz.ERR_INVALID_ARG
+    assert ws_of([a, c]) == hsz.ERR_INVALID_ARG
+    assert ws_of([nd]) == hsz.ERR_UNSUPPORTED
+    assert ws_of([]) == hsz.ERR_INVALID_ARG
+    arr = (ctypes.POINTER(hsz.Header) * 1)(ctypes.pointer(a))
+    ptrs = (ctypes.c_void_p * 1)(0x20000)
+    assert ws_of([a], hsz.GRADMAG) == 0
+    need = w.value
+
+    def run(via, op, axis=0, cap=4 * f.size, wsb=need):
+        return lib.hsz_ooc_op(ctypes.cast(ptrs, ctypes.c_void_p), ctypes.cast(arr, ctypes.c_void_p), 1, via, op, axis,
+                              fake, cap, fake, wsb, None)
+    assert run(hsz.DELTA, hsz.GRADMAG) == hsz.ERR_UNSUPPORTED  # stencils go through D_q
+    assert run(hsz.FLOAT, hsz.MEAN) == hsz.ERR_UNSUPPORTED
+    assert run(hsz.QUANT, hsz.DERIV, axis=3) == hsz.ERR_INVALID_ARG
+    assert run(hsz.QUANT, hsz.GRADMAG, cap=16) == hsz.ERR_CAPACITY
+    assert run(hsz.QUANT, hsz.GRADMAG, wsb=need - 1) == hsz.ERR_CAPACITY
+    assert run(hsz.QUANT, hsz.VAR_MT) == hsz.ERR_INVALID_ARG
