@@ -999,14 +999,24 @@ __global__ void __launch_bounds__(kThreads) k_lz_mean_fused(StreamView v, NdGrid
     if (b < v.nb) {
       const int64_t oz = (b / (g.nby * g.nbx)) * Sh::BZ, oy = ((b / g.nbx) % g.nby) * Sh::BY,
                     ox = (b % g.nbx) * Sh::BX;
-      decode_lane_block<S, kWave, true>(tile + l, w, 0, [&](int j, int p, int) {
-        const int sz = j / (Sh::BY * Sh::BX), sy = (j / Sh::BX) % Sh::BY, sx = j % Sh::BX;
-        const int64_t z = oz + sz, y = oy + sy, x = ox + sx;
-        if (z < g.Z && y < g.Y && x < g.X) {
-          s += (uint64_t)(g.Z - z) * (uint64_t)(g.Y - y) * (uint64_t)(g.X - x) * (uint64_t)(int64_t)p;
-          acc.cnt += 1;
+      int vals[S];
+      decode_lane_block<S, kWave, true>(tile + l, w, 0, [&](int j, int p, int) { vals[j] = p; });
+      // weights factor as (Z - z)(Y - y)(X - x): each row of the block sums
+      // (X - x) p, then is scaled once by (Z - z)(Y - y); slots outside the
+      // field carry a weight factor <= 0 and are skipped
+      const int64_t A = g.Z - oz, B = g.Y - oy, C = g.X - ox;
+#pragma unroll
+      for (int r = 0; r < Sh::BZ * Sh::BY; ++r) {
+        const int64_t wz = A - r / Sh::BY, wy = B - r % Sh::BY;
+        uint64_t row = 0;
+#pragma unroll
+        for (int sx = 0; sx < Sh::BX; ++sx) {
+          const int64_t wx = C - sx;
+          row += wx > 0 ? (uint64_t)wx * (uint64_t)(int64_t)vals[r * Sh::BX + sx] : 0;
         }
-      });
+        if (wz > 0 && wy > 0) s += (uint64_t)(wz * wy) * row;
+      }
+      acc.cnt += min(A, (int64_t)Sh::BZ) * min(B, (int64_t)Sh::BY) * min(C, (int64_t)Sh::BX);
     }
     __builtin_amdgcn_wave_barrier();
   }
