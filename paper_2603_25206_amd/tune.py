@@ -1,6 +1,6 @@
 """Autotuner for batched passes: picks the launch shape (waves per CU of the
 statistics launch, workgroups per CU of the gradient launch, planes per
-gradient tile) by timing graph replays of the actual batch.
+gradient tile) by timing plan launches of the actual batch.
 
 Every candidate must reproduce the reference results bit for bit (they are
 exact integer sums and identical per-element arithmetic whatever the launch
