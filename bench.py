@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--no-hszx", action="store_true", help="skip the block-mean (HSZx) workload")
     ap.add_argument("--no-lorenzo", action="store_true", help="skip the HSZp-nd (Lorenzo) workload")
     ap.add_argument("--no-ooc", action="store_true", help="skip the out-of-core (host-resident slabs) workload")
+    ap.add_argument("--no-tune", action="store_true", help="time the step with the default launch shape")
     ap.add_argument("--snapshots", type=int, default=64)
     ap.add_argument("--queries", type=int, default=20000)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -212,6 +213,14 @@ def main():
     # stream, as a resident stream keeps them.
     for c in copies:
         c.build_index()
+    if a.tune is None and not a.no_tune:
+        # the launch shape of the step's plan: the autotuner times each
+        # candidate on the actual jobs and rejects any that changes a result
+        from paper_2603_25206_amd import tune as tuner
+        jobs0 = [hsz.Job(copies[0], "mean", hsz.DELTA), hsz.Job(copies[0], "var", hsz.QUANT),
+                 hsz.Job(copies[0], "gradmag", hsz.QUANT)]
+        a.tune, _ = tuner.tune(jobs0, reps=5, cache_path=None)
+        log(f"[bench] step launch shape (autotuned): {a.tune}")
     step_stream = torch.cuda.Stream()
     plans = []
     for c in copies:
@@ -361,6 +370,7 @@ def main():
                                      "speedup_homomorphic": round(ms_base / ms_step, 3),
                                      "speedup_separate_ops": round(ms_base / ms_sep, 3)},
         "stage_table_ms": {k: round(v, 4) for k, v in extra.items()},
+        "step_launch_shape": a.tune,
         "roofline": roofline,
         "check": {"var_int_route": st_v["var"], "var_float_route": st_bv["var"], "mean": st_m["mean"]},
     }
