@@ -313,6 +313,117 @@ __global__ void __launch_bounds__(kThreads) k_scan_strided4(int32_t* __restrict_
   }
 }
 
+// ---- the derivative on D_p with its first and last passes fused ---------------
+// For binary32 outputs (element stride 1, X a multiple of 4) and a derivative
+// along z or y (so four x neighbours share their index along the axis): the
+// first pass forms t along the axis from p on the fly and scans it along x;
+// the last pass of the prefix sums writes (float)num * (float)(Delta/2)
+// instead of the integer.  Two passes over the field fewer than pair, scans
+// and scale one after another.
+typedef int i4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ i4v pair4(const i4v* __restrict__ p4, int64_t e4, int64_t i, int64_t L, int64_t s4) {
+  if (L < 2) return i4v{0, 0, 0, 0};
+  if (i == 0) return 2 * p4[e4 + s4];
+  if (i == L - 1) return 2 * p4[e4];
+  return p4[e4] + p4[e4 + s4];
+}
+
+// first pass (t along axis a in {0, 1}) scanned along x, one wave per row; with
+// SCALE it is also the last pass (a 2D field's derivative along its rows' axis)
+template <bool SCALE>
+__global__ void __launch_bounds__(kThreads) k_scan_x_pair(const int32_t* __restrict__ p, NdGrid g, int a,
+                                                         int32_t* __restrict__ out, float h) {
+  const int l = lane_id();
+  const int64_t rows = g.Z * g.Y, X = g.X;
+  const int64_t L = a == 0 ? g.Z : g.Y;
+  const int64_t s4 = (a == 0 ? g.Y * g.X : g.X) / 4;
+  const int64_t waves = (int64_t)gridDim.x * kWavesPerGroup;
+  const i4v* p4 = (const i4v*)p;
+  for (int64_t r = blockIdx.x * (int64_t)kWavesPerGroup + wave_in_group(); r < rows; r += waves) {
+    const int64_t i = a == 0 ? r / g.Y : r % g.Y;  // the row's index along the axis
+    int carry = 0;
+    for (int64_t x0 = 0; x0 < X; x0 += 4 * kWave) {
+      const int64_t x = x0 + 4 * l;
+      i4v v = x < X ? pair4(p4, (r * X + x) / 4, i, L, s4) : i4v{0, 0, 0, 0};
+      v.y += v.x;
+      v.z += v.y;
+      v.w += v.z;
+      const int incl = wave_incl_scan(v.w);
+      const int before = carry + incl - v.w;
+      if (x < X) {
+        const i4v o = i4v{v.x + before, v.y + before, v.z + before, v.w + before};
+        if constexpr (SCALE) *(f4v*)(out + r * X + x) = f4v{(float)o.x * h, (float)o.y * h, (float)o.z * h, (float)o.w * h};
+        else *(i4v*)(out + r * X + x) = o;
+      }
+      carry += __shfl(incl, kWave - 1);
+    }
+  }
+}
+
+// first pass for a derivative along x: t along x (p_x + p_{x+1}; 2 p_1 and
+// 2 p_{X-1} at the ends) formed from four words and the next one, scanned
+// along the strided axis (y); with SCALE also the last pass (a 2D field)
+template <bool SCALE>
+__global__ void __launch_bounds__(kThreads) k_scan_strided4_pairx(const int32_t* __restrict__ p,
+                                                                 int32_t* __restrict__ out, int64_t outer,
+                                                                 int64_t len, int64_t X, float h) {
+  const int64_t q4 = X / 4;
+  const int64_t cols = outer * q4;
+  for (int64_t t = blockIdx.x * (int64_t)kThreads + threadIdx.x; t < cols; t += (int64_t)gridDim.x * kThreads) {
+    const int64_t o = t / q4, k = t % q4;
+    const int64_t x = 4 * k;
+    const int64_t base = o * len * X + x;
+    i4v run = {0, 0, 0, 0};
+    for (int64_t i = 0; i < len; ++i) {
+      const int64_t e = base + i * X;
+      const i4v v = *(const i4v*)(p + e);
+      const int nx = x + 4 < X ? p[e + 4] : 0;
+      i4v tv;
+      if (X < 2) {
+        tv = i4v{0, 0, 0, 0};
+      } else {
+        tv = i4v{v.x + v.y, v.y + v.z, v.z + v.w, v.w + nx};
+        if (x == 0) tv.x = 2 * v.y;
+        if (x + 3 == X - 1) tv.w = 2 * v.w;
+      }
+      run += tv;
+      if constexpr (SCALE)
+        *(f4v*)(out + e) = f4v{(float)run.x * h, (float)run.y * h, (float)run.z * h, (float)run.w * h};
+      else
+        *(i4v*)(out + e) = run;
+    }
+  }
+}
+
+// last pass: the prefix sum along a strided axis, written as the scaled float
+__global__ void __launch_bounds__(kThreads) k_scan_strided4_scale(int32_t* __restrict__ buf, int64_t outer,
+                                                                 int64_t len, int64_t inner, float h) {
+  const int64_t q4 = inner / 4;
+  const int64_t cols = outer * q4;
+  for (int64_t t = blockIdx.x * (int64_t)kThreads + threadIdx.x; t < cols; t += (int64_t)gridDim.x * kThreads) {
+    const int64_t o = t / q4, k = t % q4;
+    i4v* p = (i4v*)(buf + o * len * inner) + k;
+    i4v run = {0, 0, 0, 0};
+    int64_t i = 0;
+    for (; i + kBatch <= len; i += kBatch) {
+      i4v v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) v[u] = p[(i + u) * q4];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        run += v[u];
+        *(f4v*)&p[(i + u) * q4] = f4v{(float)run.x * h, (float)run.y * h, (float)run.z * h, (float)run.w * h};
+      }
+    }
+    for (; i < len; ++i) {
+      run += p[i * q4];
+      *(f4v*)&p[i * q4] = f4v{(float)run.x * h, (float)run.y * h, (float)run.z * h, (float)run.w * h};
+    }
+  }
+}
+
 // q (int32 at element stride es) -> T in place
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_lz_dequant(void* buf, int64_t n, int es, double quantum) {
@@ -466,6 +577,35 @@ hipError_t lz_decode(const StreamView& v, const NdGrid& g, int stage, void* out,
 hipError_t lz_deriv_p(const int32_t* p, const StreamView& v, const NdGrid& g, int axis3, void* out, hipStream_t s) {
   const int es = v.dtype == 2 ? 2 : 1;
   const int64_t n = g.Z * g.Y * g.X;
+  if (v.dtype == 1 && (g.X & 3) == 0 && axis3 == 2) {
+    const float h = (float)(0.5 * v.quantum);
+    if (g.ndim == 2) {  // y is the only other axis: one pass
+      hipLaunchKernelGGL(k_scan_strided4_pairx<true>, dim3(grid_of(g.X / 4, kThreads)), dim3(kThreads), 0, s, p,
+                         (int32_t*)out, (int64_t)1, g.Y, g.X, h);
+      return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_strided4_pairx<false>, dim3(grid_of(g.Z * g.X / 4, kThreads)), dim3(kThreads), 0, s,
+                       p, (int32_t*)out, g.Z, g.Y, g.X, h);
+    hipLaunchKernelGGL(k_scan_strided4_scale, dim3(grid_of(g.Y * g.X / 4, kThreads)), dim3(kThreads), 0, s,
+                       (int32_t*)out, (int64_t)1, g.Z, g.Y * g.X, h);
+    return hipGetLastError();
+  }
+  if (v.dtype == 1 && (g.X & 3) == 0 && axis3 != 2) {
+    const float h = (float)(0.5 * v.quantum);
+    const unsigned gx = grid_of(g.Z * g.Y, kWavesPerGroup);
+    if (g.ndim == 2) {  // the rows' axis is the only other one: one pass
+      hipLaunchKernelGGL(k_scan_x_pair<true>, dim3(gx), dim3(kThreads), 0, s, p, g, axis3, (int32_t*)out, h);
+      return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_x_pair<false>, dim3(gx), dim3(kThreads), 0, s, p, g, axis3, (int32_t*)out, h);
+    if (axis3 == 0)  // then along y, scaled
+      hipLaunchKernelGGL(k_scan_strided4_scale, dim3(grid_of(g.Z * g.X / 4, kThreads)), dim3(kThreads), 0, s,
+                         (int32_t*)out, g.Z, g.Y, g.X, h);
+    else  // then along z, scaled
+      hipLaunchKernelGGL(k_scan_strided4_scale, dim3(grid_of(g.Y * g.X / 4, kThreads)), dim3(kThreads), 0, s,
+                         (int32_t*)out, (int64_t)1, g.Z, g.Y * g.X, h);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_lz_pair, dim3(grid_of(n, kThreads)), dim3(kThreads), 0, s, p, g, axis3, (int32_t*)out, es);
   hipError_t e = lz_scan_axes((int32_t*)out, g.Z, g.Y, g.X, es, axis3, nullptr, s);
   if (e != hipSuccess) return e;
