@@ -424,6 +424,36 @@ __global__ void __launch_bounds__(kThreads) k_scan_strided4_scale(int32_t* __res
   }
 }
 
+// last pass of D_f (binary32): the prefix sum along a strided axis written as
+// (float)(q * Delta), the dequantization of Alg. 2, in place
+__global__ void __launch_bounds__(kThreads) k_scan_strided4_deq(int32_t* __restrict__ buf, int64_t outer,
+                                                               int64_t len, int64_t inner, double quantum) {
+  const int64_t q4 = inner / 4;
+  const int64_t cols = outer * q4;
+  for (int64_t t = blockIdx.x * (int64_t)kThreads + threadIdx.x; t < cols; t += (int64_t)gridDim.x * kThreads) {
+    const int64_t o = t / q4, k = t % q4;
+    i4v* p = (i4v*)(buf + o * len * inner) + k;
+    i4v run = {0, 0, 0, 0};
+    int64_t i = 0;
+    for (; i + kBatch <= len; i += kBatch) {
+      i4v v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) v[u] = p[(i + u) * q4];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        run += v[u];
+        *(f4v*)&p[(i + u) * q4] = f4v{(float)dequant64(run.x, quantum), (float)dequant64(run.y, quantum),
+                                      (float)dequant64(run.z, quantum), (float)dequant64(run.w, quantum)};
+      }
+    }
+    for (; i < len; ++i) {
+      run += p[i * q4];
+      *(f4v*)&p[i * q4] = f4v{(float)dequant64(run.x, quantum), (float)dequant64(run.y, quantum),
+                              (float)dequant64(run.z, quantum), (float)dequant64(run.w, quantum)};
+    }
+  }
+}
+
 // q (int32 at element stride es) -> T in place
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_lz_dequant(void* buf, int64_t n, int es, double quantum) {
@@ -563,6 +593,19 @@ hipError_t lz_decode(const StreamView& v, const NdGrid& g, int stage, void* out,
   const int es = (stage == 4 && v.dtype == 2) ? 2 : 1;
   hipError_t e = decode_p_any(v, g, (int32_t*)out, es, status, s);
   if (e != hipSuccess || stage == 2) return e;
+  if (stage == 4 && v.dtype == 1 && g.ndim >= 2 && (g.X & 3) == 0) {
+    // all axes but the field's slowest, then the slowest writing the floats
+    const int last = g.ndim == 3 ? 0 : 1;
+    e = lz_scan_axes((int32_t*)out, g.Z, g.Y, g.X, 1, last, tmp, s);
+    if (e != hipSuccess) return e;
+    if (last == 0)
+      hipLaunchKernelGGL(k_scan_strided4_deq, dim3(grid_of(g.Y * g.X / 4, kThreads)), dim3(kThreads), 0, s,
+                         (int32_t*)out, (int64_t)1, g.Z, g.Y * g.X, v.quantum);
+    else
+      hipLaunchKernelGGL(k_scan_strided4_deq, dim3(grid_of(g.X / 4, kThreads)), dim3(kThreads), 0, s, (int32_t*)out,
+                         (int64_t)1, g.Y, g.X, v.quantum);
+    return hipGetLastError();
+  }
   e = lz_scan_axes((int32_t*)out, g.Z, g.Y, g.X, es, -1, tmp, s);
   if (e != hipSuccess || stage == 3) return e;
   const int64_t n = g.Z * g.Y * g.X;
