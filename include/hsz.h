@@ -161,8 +161,8 @@ int hsz_compress(const void *d_x, int dtype, int ndim, const int64_t *h_dims, do
  * field only): mean = (sum_b M_b S_b / n) * Delta, exact integer sum in s1,
  * within eps of the mean of the decompressed field.  Streams of this mode
  * support every statistic and the materialised stages 3 and 4 of the
- * stencil operations; fused stencils, vector fields and batches return
- * HSZ_ERR_UNSUPPORTED for them. */
+ * stencil and vector-field operations; fused stencils, fused vector fields
+ * and batches return HSZ_ERR_UNSUPPORTED for them. */
 #define HSZ_FLAG_BLOCK_MEAN 1u
 /* HSZ_FLAG_LORENZO selects HSZp-nd (Sec. IV) for 2D and 3D fields: the
  * Lorenzo residual over the whole field, p = sum over the corners c of
