@@ -141,7 +141,10 @@ int hsz_read_status(const void *d_workspace, void *stream, int *h_status);
  * (for 2D and 3D fields the larger of the 1D and the nd partition). */
 int hsz_compress_bound(int dtype, int ndim, const int64_t *h_dims, int block, uint64_t *h_bytes);
 
-/* Workspace hsz_compress / hsz_compress_flags need (bytes), any mode. */
+/* Workspace hsz_compress / hsz_compress_flags need (bytes), any mode.  The
+ * Lorenzo modes (HSZ_FLAG_LORENZO, HSZ_FLAG_INTER_BLOCK) keep one int32
+ * residual per slot of their partition there, about 4 bytes per element;
+ * the other modes need a few kilobytes plus 4 bytes per 64 blocks. */
 int hsz_compress_workspace(int ndim, const int64_t *h_dims, int block, uint64_t *h_bytes);
 
 /* Compress d_x (dtype, dims) into d_out (capacity 'cap' bytes, at least

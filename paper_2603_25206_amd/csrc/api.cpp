@@ -208,8 +208,10 @@ int hsz_compress_workspace(int ndim, const int64_t* h_dims, int block, uint64_t*
   if (!h_bytes || !dims3_of(ndim, h_dims, d3, &n)) return HSZ_ERR_INVALID_ARG;
   if (!valid_block(block)) return HSZ_ERR_UNSUPPORTED;
   uint64_t w = hsz::compress_workspace_bytes(hsz::make_layout(n, block));
+  const uint64_t wf = hsz::compress_workspace_bytes_nd(hsz::make_layout_flat(n, block));
+  w = wf > w ? wf : w;
   if (ndim >= 2) {
-    const uint64_t wn = hsz::compress_workspace_bytes(hsz::make_layout_nd(d3, ndim, block));
+    const uint64_t wn = hsz::compress_workspace_bytes_nd(hsz::make_layout_nd(d3, ndim, block));
     w = wn > w ? wn : w;
   }
   *h_bytes = w;
@@ -237,7 +239,9 @@ static int compress_impl(const void* d_x, int dtype, int ndim, const int64_t* h_
   hsz::Layout L = flags == HSZ_FLAG_LORENZO       ? hsz::make_layout_nd(d3, ndim, block)
                   : flags == HSZ_FLAG_INTER_BLOCK ? hsz::make_layout_flat(n, block)
                                                   : hsz::make_layout(n, block);
-  if (workspace_bytes < hsz::compress_workspace_bytes(L)) return HSZ_ERR_CAPACITY;
+  const bool lorenzo = flags == HSZ_FLAG_LORENZO || flags == HSZ_FLAG_INTER_BLOCK;
+  if (workspace_bytes < (lorenzo ? hsz::compress_workspace_bytes_nd(L) : hsz::compress_workspace_bytes(L)))
+    return HSZ_ERR_CAPACITY;
   if (cap < L.off_payload) return HSZ_ERR_CAPACITY;
   hsz::CompressArgs a;
   a.x = d_x;
@@ -257,8 +261,7 @@ static int compress_impl(const void* d_x, int dtype, int ndim, const int64_t* h_
   a.cap = cap;
   a.ws = (uint8_t*)d_workspace;
   a.ws_bytes = workspace_bytes;
-  hipError_t e = (flags == HSZ_FLAG_LORENZO || flags == HSZ_FLAG_INTER_BLOCK)
-                     ? hsz::launch_compress_nd(a, (hipStream_t)stream)
+  hipError_t e = lorenzo ? hsz::launch_compress_nd(a, (hipStream_t)stream)
                      : hsz::launch_compress(a, (hipStream_t)stream);
   return e == hipSuccess ? HSZ_OK : hip_fail(e);
 }

@@ -620,6 +620,8 @@ uint64_t ws_group_max_off(const Layout& L) {
   const uint64_t ranges = (L.nchunks + kScanRange - 1) / kScanRange;
   return align_up(ws_range_sums_off(L) + 8 * ranges, 256);
 }
+// residuals of the Lorenzo modes, one int32 per slot of the partition
+uint64_t ws_resid_off(const Layout& L) { return align_up(ws_group_max_off(L) + 4 * (uint64_t)kMetaGroups, 256); }
 
 template <typename T, int S, bool MEAN>
 hipError_t run(const CompressArgs& a, hipStream_t s) {
@@ -657,101 +659,176 @@ hipError_t run(const CompressArgs& a, hipStream_t s) {
 // ---- HSZp-nd and HSZp: Lorenzo residual over the whole field -------------------
 // (HSZp-nd: the field's own axes, nd blocks; HSZp: the field as one row of n,
 // ND = 1, blocks of S consecutive elements)
-// The same wave-per-chunk walk as k_quant_meta / k_pack, but lane l of step
-// st owns slot l % S of block 64c + st (64/S) + l/S of the nd partition, at
-// the coordinates of that slot.  The residual of a point is the sum over the
-// corners c of {0,1}^ND of (-1)^|c| q(point - c), q = 0 before index 0; each
-// corner is quantized from the field again (neighbouring lanes and blocks
-// read the same values through the caches).  |p| beyond 2^30 - 1 is a range
-// error.
-template <typename T, int ND>
-__device__ __forceinline__ int64_t lz_residual(const T* __restrict__ x, int64_t Y, int64_t X, int64_t z, int64_t y,
-                                               int64_t xx, double inv, bool& over, int& qself) {
-  int64_t r = 0;
-  constexpr int kCorners = 1 << ND;
-#pragma unroll
-  for (int c = 0; c < kCorners; ++c) {
-    const int dz = ND == 3 ? (c >> 2) & 1 : 0, dy = (c >> 1) & 1, dx = c & 1;
-    if ((dz && z == 0) || (dy && y == 0) || (dx && xx == 0)) continue;
-    const int q = quantize((double)x[((z - dz) * Y + (y - dy)) * X + (xx - dx)], inv, over);
-    if (c == 0) qself = q;
-    r += ((dz + dy + dx) & 1) ? -(int64_t)q : (int64_t)q;
-  }
-  return r;
-}
+// The residual of a point is the sum over the corners c of {0,1}^ND of
+// (-1)^|c| q(point - c), with q = 0 before index 0 on any axis.  Three
+// passes: k_resid_nd quantizes the field row by row and writes every slot's
+// residual in block order into the workspace (4 bytes per slot of the
+// partition, 0 on the slots past the field's end) and each block's width;
+// k_chunk_words_nd sums the payload words per chunk and k_pack_nd takes the
+// same wave-per-chunk walk as k_pack over the residuals.  |p| beyond
+// 2^30 - 1 is a range error.
 
-// residual of the lane's slot of block b (0 outside the field or past nb)
+// One tile: U x 256 consecutive x positions of one row of blocks (BZ planes
+// by BY rows).  A thread loads its columns (and the columns before them) on
+// those rows and on the row and plane before them (the corners' halo), every
+// load issued before any is used, then forms the BZ x BY residuals of each
+// column.  The nd modes gather the tile's blocks in LDS (BX pad words after
+// each block keep the column writes on distinct banks) and store them as one
+// contiguous run; the flat mode's blocks are already in field order.  Either
+// way the lanes then hold whole blocks (slot l % S), and the last lane of each
+// writes the block's width.
 template <typename T, int S, int ND>
-__device__ __forceinline__ int64_t lz_slot_residual(const T* __restrict__ x, const NdGrid& g, int64_t nb, int64_t b,
-                                                    int slot, double inv, bool& over, int& qself) {
+struct ResidTile {
   using Sh = NdShape<ND, S>;
-  qself = 0;
-  if (b >= nb) return 0;
-  const int sz = slot / (Sh::BY * Sh::BX), sy = (slot / Sh::BX) % Sh::BY, sx = slot % Sh::BX;
-  const int64_t bz = b / (g.nby * g.nbx), by = (b / g.nbx) % g.nby, bx = b % g.nbx;
-  const int64_t z = bz * Sh::BZ + sz, y = by * Sh::BY + sy, xx = bx * Sh::BX + sx;
-  if (z >= g.Z || y >= g.Y || xx >= g.X) return 0;
-  return lz_residual<T, ND>(x, g.Y, g.X, z, y, xx, inv, over, qself);
-}
+  static constexpr int HZ = ND == 3 ? 1 : 0, HY = ND >= 2 ? 1 : 0;  // halo plane / row
+  static constexpr int NZ = Sh::BZ + HZ, NY = Sh::BY + HY;
+  static constexpr int U = ND == 1 ? 8 : (NZ * NY * (int)sizeof(T) <= 64 ? 2 : 1);
+  static constexpr int kSpan = U * kThreads;
+  static constexpr int kPad = Sh::BX;
+  static constexpr int kLds = ND == 1 ? 1 : kSpan / Sh::BX * (S + kPad);
+};
 
 template <typename T, int S, int ND>
-__global__ void __launch_bounds__(kThreads) k_quant_meta_nd(const T* __restrict__ x, NdGrid g, int64_t nb,
-                                                           int64_t nchunks, CompressWs* ws, uint8_t* widths,
-                                                           uint32_t* chunk_words, uint32_t* group_max) {
-  if (ws->status != 0) {
-    if (threadIdx.x == 0) group_max[blockIdx.x] = 0;
-    return;
-  }
-  __shared__ int w_all[(kThreads / kWave) * kChunkBlocks];
-  int* mw = w_all + wave_in_group() * kChunkBlocks;
+__global__ void __launch_bounds__(kThreads) k_resid_nd(const T* __restrict__ x, NdGrid g, int64_t nxt,
+                                                      int64_t count, CompressWs* ws, int32_t* __restrict__ resid,
+                                                      uint8_t* __restrict__ widths, uint32_t* group_max, int groups) {
+  using Sh = NdShape<ND, S>;
+  using R = ResidTile<T, S, ND>;
+  constexpr int HZ = R::HZ, HY = R::HY, NZ = R::NZ, NY = R::NY, U = R::U;
+  __shared__ int32_t tile[R::kLds];
+  if (ws->status != 0) return;
   const double inv = ws->inv_quantum;
-  const int l = lane_id();
-  const int slot = l % S;
-  const int64_t waves = (int64_t)gridDim.x * (kThreads / kWave);
+  const int t = threadIdx.x, l = lane_id();
+  const int64_t xp = g.nbx * Sh::BX;  // padded row length
   uint32_t maxq = 0;
   bool over = false, wide = false;
-  for (int64_t c = blockIdx.x * (int64_t)(kThreads / kWave) + wave_in_group(); c < nchunks; c += waves) {
-    for (int st = 0; st < kSteps<S>; ++st) {
-      const int bl = st * (kWave / S) + l / S;
-      int qs = 0;
-      const int64_t r = lz_slot_residual<T, S, ND>(x, g, nb, c * kChunkBlocks + bl, slot, inv, over, qs);
-      const uint32_t aq = (uint32_t)(qs < 0 ? -qs : qs);
-      maxq = aq > maxq ? aq : maxq;
-      const int64_t ar = r < 0 ? -r : r;
-      wide |= ar > kPMax;
-      const int ab = block_or_scan<S>((int)(ar > kPMax ? kPMax : ar));
-      if (slot == S - 1) mw[bl] = bitlen((uint32_t)ab);
+  for (int64_t w = blockIdx.x; w < count; w += gridDim.x) {
+    const int64_t xt = w % nxt, rest = w / nxt;
+    const int64_t by = rest % g.nby, bz = rest / g.nby;
+    const int64_t xbase = xt * R::kSpan;
+    T va[U][NZ][NY], vb[U][NZ][NY];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t xx = xbase + u * kThreads + t;
+#pragma unroll
+      for (int iz = 0; iz < NZ; ++iz) {
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy) {
+          const int64_t z = bz * Sh::BZ + iz - HZ, y = by * Sh::BY + iy - HY;
+          const bool row = z >= 0 && z < g.Z && y >= 0 && y < g.Y;
+          const int64_t base = row ? (z * g.Y + y) * g.X : 0;
+          const bool ia = row && xx < g.X, ib = row && xx >= 1 && xx - 1 < g.X;
+          va[u][iz][iy] = x[ia ? base + xx : 0];
+          vb[u][iz][iy] = x[ib ? base + xx - 1 : 0];
+        }
+      }
     }
-    __builtin_amdgcn_wave_barrier();
-    const int64_t b = c * kChunkBlocks + l;
-    const bool exists = b < nb;
-    const int my_w = mw[l];
-    if (exists) widths[b] = (uint8_t)my_w;
-    const int words = wave_incl_scan(exists ? block_words<S>(my_w) : 0);
-    if (l == kWave - 1) chunk_words[c] = (uint32_t)words;
-    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t xx = xbase + u * kThreads + t;
+      const bool inx = xx < g.X;
+      int qa[NZ][NY], qb[NZ][NY];
+#pragma unroll
+      for (int iz = 0; iz < NZ; ++iz) {
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy) {
+          const int64_t z = bz * Sh::BZ + iz - HZ, y = by * Sh::BY + iy - HY;
+          const bool row = z >= 0 && z < g.Z && y >= 0 && y < g.Y;
+          const bool ia = row && inx, ib = row && xx >= 1 && xx - 1 < g.X;
+          qa[iz][iy] = ia ? quantize((double)va[u][iz][iy], inv, over) : 0;
+          qb[iz][iy] = ib ? quantize((double)vb[u][iz][iy], inv, over) : 0;
+          if (iz >= HZ && iy >= HY) {
+            const uint32_t aq = (uint32_t)(qa[iz][iy] < 0 ? -qa[iz][iy] : qa[iz][iy]);
+            maxq = aq > maxq ? aq : maxq;
+          }
+        }
+      }
+      const int loc = u * kThreads + t;  // column within the tile
+#pragma unroll
+      for (int dz = 0; dz < Sh::BZ; ++dz) {
+#pragma unroll
+        for (int dy = 0; dy < Sh::BY; ++dy) {
+          const int iz = dz + HZ, iy = dy + HY;
+          const bool inside = inx && bz * Sh::BZ + dz < g.Z && by * Sh::BY + dy < g.Y;
+          int64_t r = (int64_t)qa[iz][iy] - qb[iz][iy];
+          if constexpr (ND >= 2) r += (int64_t)qb[iz][iy - 1] - qa[iz][iy - 1];
+          if constexpr (ND == 3) {
+            r += (int64_t)qb[iz - 1][iy] - qa[iz - 1][iy];
+            r += (int64_t)qa[iz - 1][iy - 1] - qb[iz - 1][iy - 1];
+          }
+          if (!inside) r = 0;  // a slot past the field's end
+          const int64_t ar = r < 0 ? -r : r;
+          wide |= ar > kPMax;
+          if constexpr (ND == 1) {
+            // one row of blocks: slot order is field order, block xx / S in lanes of l / S
+            const int ab = block_or_scan<S>((int)(ar > kPMax ? kPMax : ar));
+            if (xx < xp) {
+              resid[xx] = (int32_t)r;
+              if (l % S == S - 1) widths[xx / S] = (uint8_t)bitlen((uint32_t)ab);
+            }
+          } else {
+            tile[(loc / Sh::BX) * (S + R::kPad) + (dz * Sh::BY + dy) * Sh::BX + loc % Sh::BX] = (int32_t)r;
+          }
+        }
+      }
+    }
+    if constexpr (ND >= 2) {
+      __syncthreads();
+      const int64_t xe = xp < xbase + R::kSpan ? xp : xbase + R::kSpan;
+      const int total = (int)((xe - xbase) / Sh::BX) * S;  // words of the tile's blocks inside the partition
+      const int64_t b0 = (bz * g.nby + by) * g.nbx + xbase / Sh::BX;
+      int32_t* dst = resid + b0 * S;
+      for (int k0 = 0; k0 < total; k0 += kThreads) {  // every lane takes part in the block OR
+        const int k = k0 + t;
+        const int v = k < total ? tile[(k / S) * (S + R::kPad) + k % S] : 0;
+        const int ab = block_or_scan<S>(v < 0 ? -v : v);  // |v| <= kPMax unless a range error stops the stream
+        if (k < total) {
+          dst[k] = v;
+          if (l % S == S - 1) widths[b0 + k / S] = (uint8_t)bitlen((uint32_t)ab);
+        }
+      }
+      __syncthreads();
+    }
   }
   maxq = (uint32_t)wave_max((int)maxq);
   __shared__ uint32_t wmax[kThreads / kWave];
   if (l == 0) wmax[wave_in_group()] = maxq;
   if (__any(over || wide) && l == 0) record_status(&ws->status, kErrRange);
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     uint32_t m = 0;
     for (int k = 0; k < kThreads / kWave; ++k) m = wmax[k] > m ? wmax[k] : m;
-    group_max[blockIdx.x] = m;
+    if (m) atomicMax(&group_max[blockIdx.x % groups], m);
   }
 }
 
-template <typename T, int S, int ND>
-__global__ void __launch_bounds__(kThreads) k_pack_nd(const T* __restrict__ x, NdGrid g, int64_t nb, int64_t nchunks,
+__global__ void __launch_bounds__(kThreads) k_zero_u32(uint32_t* p, int n) {
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) p[i] = 0u;
+}
+
+// payload words of each chunk of 64 blocks from the widths k_resid_nd wrote
+template <int S>
+__global__ void __launch_bounds__(kThreads) k_chunk_words_nd(const uint8_t* __restrict__ widths, int64_t nb,
+                                                            int64_t nchunks, const CompressWs* ws,
+                                                            uint32_t* chunk_words) {
+  if (ws->status != 0) return;
+  const int l = lane_id();
+  const int64_t waves = (int64_t)gridDim.x * (kThreads / kWave);
+  for (int64_t c = blockIdx.x * (int64_t)(kThreads / kWave) + wave_in_group(); c < nchunks; c += waves) {
+    const int64_t b = c * kChunkBlocks + l;
+    const int words = wave_incl_scan(b < nb ? block_words<S>((int)widths[b]) : 0);
+    if (l == kWave - 1) chunk_words[c] = (uint32_t)words;
+  }
+}
+
+template <int S>
+__global__ void __launch_bounds__(kThreads) k_pack_nd(const int32_t* __restrict__ resid, int64_t nb, int64_t nchunks,
                                                      const CompressWs* ws, const uint8_t* __restrict__ widths,
                                                      const uint64_t* __restrict__ chunk_off, uint32_t* payload) {
   if (ws->status != 0) return;
   constexpr int kRows = (S / 32) * (1 + kMaxWidth);  // words of the widest block
   __shared__ uint32_t lin_all[(kThreads / kWave) * kRows * kWave];
   uint32_t* lin = lin_all + wave_in_group() * kRows * kWave;
-  const double inv = ws->inv_quantum;
   const int l = lane_id();
   const int slot = l % S;
   const int64_t waves = (int64_t)gridDim.x * (kThreads / kWave);
@@ -767,9 +844,8 @@ __global__ void __launch_bounds__(kThreads) k_pack_nd(const T* __restrict__ x, N
     __builtin_amdgcn_wave_barrier();
     for (int st = 0; st < kSteps<S>; ++st) {
       const int blk = st * (kWave / S);  // first block of the step within the chunk
-      bool ov = false;
-      int qs = 0;
-      const int p = (int)lz_slot_residual<T, S, ND>(x, g, nb, c * kChunkBlocks + blk + l / S, slot, inv, ov, qs);
+      const int64_t bk = c * kChunkBlocks + blk + l / S;
+      const int p = bk < nb ? resid[bk * S + slot] : 0;
       int w = __builtin_amdgcn_readlane(wl, blk), off = __builtin_amdgcn_readlane(offl, blk);
       if (S == 32 && l >= 32) {
         w = __builtin_amdgcn_readlane(wl, blk + 1);
@@ -820,14 +896,23 @@ hipError_t run_nd(const CompressArgs& a, const NdGrid& g, hipStream_t s) {
   const int64_t cg = (L.nchunks + 3) / 4;
   const int grid = (int)(cg < kMetaGroups ? cg : kMetaGroups);
   uint32_t* group_max = (uint32_t*)(a.ws + ws_group_max_off(L));
-  hipLaunchKernelGGL((k_quant_meta_nd<T, S, ND>), dim3(grid), dim3(kThreads), 0, s, x, g, L.nb, L.nchunks, ws,
-                     out + L.off_width, chunk_words, group_max);
+  int32_t* resid = (int32_t*)(a.ws + ws_resid_off(L));
+  using Sh = NdShape<ND, S>;
+  const int64_t nxt = (g.nbx * Sh::BX + ResidTile<T, S, ND>::kSpan - 1) / ResidTile<T, S, ND>::kSpan;
+  const int64_t rcount = nxt * g.nby * g.nbz;
+  const int rgrid = (int)(rcount < (int64_t)(1 << 20) ? rcount : (int64_t)(1 << 20));
+  hipLaunchKernelGGL(k_zero_u32, dim3((grid + kThreads - 1) / kThreads), dim3(kThreads), 0, s, group_max, grid);
+  if (rgrid > 0)
+    hipLaunchKernelGGL((k_resid_nd<T, S, ND>), dim3(rgrid), dim3(kThreads), 0, s, x, g, nxt, rcount, ws, resid,
+                       out + L.off_width, group_max, grid);
+  hipLaunchKernelGGL((k_chunk_words_nd<S>), dim3(grid), dim3(kThreads), 0, s, (const uint8_t*)(out + L.off_width),
+                     L.nb, L.nchunks, ws, chunk_words);
   const unsigned ranges = (unsigned)((L.nchunks + kScanRange - 1) / kScanRange);
   uint64_t* range_sums = (uint64_t*)(a.ws + ws_range_sums_off(L));
   hipLaunchKernelGGL(k_scan_sums, dim3(ranges), dim3(kScanThreads), 0, s, chunk_words, L.nchunks, range_sums);
   hipLaunchKernelGGL(k_scan_write, dim3(ranges), dim3(kScanThreads), 0, s, chunk_words, L.nchunks, range_sums,
                      (uint64_t*)(out + L.off_chunk), ws, L.off_payload, a.cap);
-  hipLaunchKernelGGL((k_pack_nd<T, S, ND>), dim3(grid), dim3(kThreads), 0, s, x, g, L.nb, L.nchunks, ws,
+  hipLaunchKernelGGL((k_pack_nd<S>), dim3(grid), dim3(kThreads), 0, s, resid, L.nb, L.nchunks, ws,
                      (const uint8_t*)(out + L.off_width), (const uint64_t*)(out + L.off_chunk),
                      (uint32_t*)(out + L.off_payload));
   hipLaunchKernelGGL(k_header, dim3(1), dim3(kHeaderBytes), 0, s, out, ws, (const uint32_t*)group_max, grid,
@@ -927,6 +1012,9 @@ Layout make_layout(int64_t n, int block) {
 }
 
 uint64_t compress_workspace_bytes(const Layout& lay) { return ws_group_max_off(lay) + 4 * (uint64_t)kMetaGroups; }
+uint64_t compress_workspace_bytes_nd(const Layout& lay) {
+  return ws_resid_off(lay) + 4 * (uint64_t)lay.nb * (uint64_t)lay.block;
+}
 
 template <bool MEAN>
 hipError_t compress_mode(const CompressArgs& a, hipStream_t s) {
