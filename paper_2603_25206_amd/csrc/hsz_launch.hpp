@@ -60,8 +60,6 @@ struct CompressArgs {
   uint64_t ws_bytes;
 };
 uint64_t compress_workspace_bytes(const Layout& lay);
-// the Lorenzo modes (nd or flat layout) also keep every slot's residual
-uint64_t compress_workspace_bytes_nd(const Layout& lay);
 hipError_t launch_compress(const CompressArgs& a, hipStream_t s);
 
 // ---- decompression -----------------------------------------------------------

@@ -60,6 +60,9 @@ inline NdGrid nd_grid(const int64_t d3[3], int ndim, int S) {
 Layout make_layout_nd(const int64_t d3[3], int ndim, int block);
 // Sections of an HSZp stream (inter-block deltas): the 1D partition, no q0.
 Layout make_layout_flat(int64_t n, int block);
+// Compression workspace of the Lorenzo modes (nd or flat layout): the delta
+// mode's plus one int32 residual per slot of the partition.
+uint64_t compress_workspace_bytes_nd(const Layout& lay);
 
 // Extremes of a field ({vmin, vmax, non-finite flag} as three doubles at
 // 'out'), with extremes_workspace_bytes() of scratch: the first pass of a

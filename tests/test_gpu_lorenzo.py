@@ -44,6 +44,10 @@ CASES = [
     ((90, 300), np.float32, 1e-3, 64),
     ((1, 17, 40), np.float32, 1e-3, 32),  # a 3D field of one plane
     ((3, 5), np.float32, 1e-3, 32),  # one partial block
+    ((19, 23, 70), np.float64, 1e-6, 32),  # binary64 3D
+    ((6, 9, 1100), np.float32, 1e-3, 32),  # rows of several residual tiles, the last partial
+    ((30, 1300), np.float32, 1e-3, 64),
+    ((13, 21, 45), np.float64, 1e-5, 64),
 ]
 
 
