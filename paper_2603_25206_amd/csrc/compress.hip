@@ -842,30 +842,42 @@ __global__ void __launch_bounds__(kThreads) k_pack_nd(const int32_t* __restrict_
     if (total < 0 || total > kRows * kWave) continue;  // widths are <= 30, so never taken
     for (int k = l; k < total; k += kWave) lin[k] = 0u;
     __builtin_amdgcn_wave_barrier();
-    for (int st = 0; st < kSteps<S>; ++st) {
-      const int blk = st * (kWave / S);  // first block of the step within the chunk
-      const int64_t bk = c * kChunkBlocks + blk + l / S;
-      const int p = bk < nb ? resid[bk * S + slot] : 0;
-      int w = __builtin_amdgcn_readlane(wl, blk), off = __builtin_amdgcn_readlane(offl, blk);
-      if (S == 32 && l >= 32) {
-        w = __builtin_amdgcn_readlane(wl, blk + 1);
-        off = __builtin_amdgcn_readlane(offl, blk + 1);
+    // slot l % S of block 64c + st (64/S) + l/S is residual word 64 S c + 64 st + l
+    const int64_t e0 = c * (int64_t)(kChunkBlocks * S), words = nb * (int64_t)S;
+#pragma unroll
+    for (int st0 = 0; st0 < kSteps<S>; st0 += kAhead) {
+      int pv[kAhead];
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const int64_t e = e0 + (int64_t)(st0 + u) * kWave + l;
+        pv[u] = e < words ? resid[e] : 0;
       }
-      const uint64_t neg = __ballot(p < 0);
-      if (w > 0) {
-        if (S == 32) {
-          if (slot == 0) lin[off] = (uint32_t)(l < 32 ? neg : neg >> 32);
-        } else {
-          if (l == 0) lin[off] = (uint32_t)neg;
-          if (l == 32) lin[off + 1] = (uint32_t)(neg >> 32);
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const int st = st0 + u;
+        const int blk = st * (kWave / S);  // first block of the step within the chunk
+        const int p = pv[u];
+        int w = __builtin_amdgcn_readlane(wl, blk), off = __builtin_amdgcn_readlane(offl, blk);
+        if (S == 32 && l >= 32) {
+          w = __builtin_amdgcn_readlane(wl, blk + 1);
+          off = __builtin_amdgcn_readlane(offl, blk + 1);
         }
-        const uint32_t m = (uint32_t)(p < 0 ? -p : p);
-        if (m) {
-          const uint32_t pos = (uint32_t)slot * (uint32_t)w;
-          const uint32_t k = pos >> 5, sh = pos & 31u;
-          uint32_t* mag = lin + off + S / 32;
-          atomicOr(&mag[k], m << sh);
-          if (sh + (uint32_t)w > 32u) atomicOr(&mag[k + 1], m >> (32u - sh));
+        const uint64_t neg = __ballot(p < 0);
+        if (w > 0) {
+          if (S == 32) {
+            if (slot == 0) lin[off] = (uint32_t)(l < 32 ? neg : neg >> 32);
+          } else {
+            if (l == 0) lin[off] = (uint32_t)neg;
+            if (l == 32) lin[off + 1] = (uint32_t)(neg >> 32);
+          }
+          const uint32_t m = (uint32_t)(p < 0 ? -p : p);
+          if (m) {
+            const uint32_t pos = (uint32_t)slot * (uint32_t)w;
+            const uint32_t k = pos >> 5, sh = pos & 31u;
+            uint32_t* mag = lin + off + S / 32;
+            atomicOr(&mag[k], m << sh);
+            if (sh + (uint32_t)w > 32u) atomicOr(&mag[k + 1], m >> (32u - sh));
+          }
         }
       }
     }
