@@ -670,9 +670,11 @@ hipError_t run(const CompressArgs& a, hipStream_t s) {
 
 // One tile: U x 256 consecutive x positions of one row of blocks (BZ planes
 // by BY rows).  A thread loads its columns (and the columns before them) on
-// those rows and on the row and plane before them (the corners' halo), every
-// load issued before any is used, then forms the BZ x BY residuals of each
-// column.  The nd modes gather the tile's blocks in LDS (BX pad words after
+// those rows and on the row before them (the corners' halo), every load
+// issued before any is used, then forms the BZ x BY residuals of each
+// column.  In 3D a work item walks a run of zper block planes of the same
+// row of blocks: the halo plane is loaded once per run, and each block
+// plane's last plane is carried, quantized, as the next one's halo.  The nd modes gather the tile's blocks in LDS (BX pad words after
 // each block keep the column writes on distinct banks) and store them as one
 // contiguous run; the flat mode's blocks are already in field order.  Either
 // way the lanes then hold whole blocks (slot l % S), and the last lane of each
@@ -689,12 +691,12 @@ struct ResidTile {
 };
 
 template <typename T, int S, int ND>
-__global__ void __launch_bounds__(kThreads) k_resid_nd(const T* __restrict__ x, NdGrid g, int64_t nxt,
+__global__ void __launch_bounds__(kThreads) k_resid_nd(const T* __restrict__ x, NdGrid g, int64_t nxt, int64_t zper,
                                                       int64_t count, CompressWs* ws, int32_t* __restrict__ resid,
                                                       uint8_t* __restrict__ widths, uint32_t* group_max, int groups) {
   using Sh = NdShape<ND, S>;
   using R = ResidTile<T, S, ND>;
-  constexpr int HZ = R::HZ, HY = R::HY, NZ = R::NZ, NY = R::NY, U = R::U;
+  constexpr int HZ = R::HZ, HY = R::HY, NY = R::NY, U = R::U;
   __shared__ int32_t tile[R::kLds];
   if (ws->status != 0) return;
   const double inv = ws->inv_quantum;
@@ -702,92 +704,127 @@ __global__ void __launch_bounds__(kThreads) k_resid_nd(const T* __restrict__ x, 
   const int64_t xp = g.nbx * Sh::BX;  // padded row length
   uint32_t maxq = 0;
   bool over = false, wide = false;
+  // q on (x, x - 1) of one row of the field, 0 outside it
+  auto load_row = [&](int64_t z, int64_t y, int64_t xx, T& va, T& vb) {
+    const bool row = z >= 0 && z < g.Z && y >= 0 && y < g.Y;
+    const int64_t base = row ? (z * g.Y + y) * g.X : 0;
+    const bool ia = row && xx < g.X, ib = row && xx >= 1 && xx - 1 < g.X;
+    va = x[ia ? base + xx : 0];
+    vb = x[ib ? base + xx - 1 : 0];
+  };
+  auto quant_row = [&](int64_t z, int64_t y, int64_t xx, T va, T vb, int& qa, int& qb) {
+    const bool row = z >= 0 && z < g.Z && y >= 0 && y < g.Y;
+    const bool ia = row && xx < g.X, ib = row && xx >= 1 && xx - 1 < g.X;
+    qa = ia ? quantize((double)va, inv, over) : 0;
+    qb = ib ? quantize((double)vb, inv, over) : 0;
+  };
   for (int64_t w = blockIdx.x; w < count; w += gridDim.x) {
+    // work item: x tile, row of blocks, run of zper block planes
     const int64_t xt = w % nxt, rest = w / nxt;
-    const int64_t by = rest % g.nby, bz = rest / g.nby;
+    const int64_t by = rest % g.nby, zc = rest / g.nby;
     const int64_t xbase = xt * R::kSpan;
-    T va[U][NZ][NY], vb[U][NZ][NY];
+    const int64_t bz0 = zc * zper, bz1 = ND < 3 ? bz0 + 1 : (bz0 + zper < g.nbz ? bz0 + zper : g.nbz);
+    // the plane before the run (the corners' halo plane), carried from one
+    // block plane to the next
+    int ha[U][NY], hb[U][NY];
+    if constexpr (HZ) {
+      T pa[U][NY], pb[U][NY];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t xx = xbase + u * kThreads + t;
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int iz = 0; iz < NZ; ++iz) {
+        for (int iy = 0; iy < NY; ++iy)
+          load_row(bz0 * Sh::BZ - 1, by * Sh::BY + iy - HY, xbase + u * kThreads + t, pa[u][iy], pb[u][iy]);
 #pragma unroll
-        for (int iy = 0; iy < NY; ++iy) {
-          const int64_t z = bz * Sh::BZ + iz - HZ, y = by * Sh::BY + iy - HY;
-          const bool row = z >= 0 && z < g.Z && y >= 0 && y < g.Y;
-          const int64_t base = row ? (z * g.Y + y) * g.X : 0;
-          const bool ia = row && xx < g.X, ib = row && xx >= 1 && xx - 1 < g.X;
-          va[u][iz][iy] = x[ia ? base + xx : 0];
-          vb[u][iz][iy] = x[ib ? base + xx - 1 : 0];
-        }
-      }
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy)
+          quant_row(bz0 * Sh::BZ - 1, by * Sh::BY + iy - HY, xbase + u * kThreads + t, pa[u][iy], pb[u][iy],
+                    ha[u][iy], hb[u][iy]);
     }
+    for (int64_t bz = bz0; bz < bz1; ++bz) {
+      T va[U][Sh::BZ][NY], vb[U][Sh::BZ][NY];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t xx = xbase + u * kThreads + t;
-      const bool inx = xx < g.X;
-      int qa[NZ][NY], qb[NZ][NY];
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int iz = 0; iz < NZ; ++iz) {
+        for (int dz = 0; dz < Sh::BZ; ++dz)
+#pragma unroll
+          for (int iy = 0; iy < NY; ++iy)
+            load_row(bz * Sh::BZ + dz, by * Sh::BY + iy - HY, xbase + u * kThreads + t, va[u][dz][iy], vb[u][dz][iy]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t xx = xbase + u * kThreads + t;
+        const bool inx = xx < g.X;
+        int qa[Sh::BZ + HZ][NY], qb[Sh::BZ + HZ][NY];
 #pragma unroll
         for (int iy = 0; iy < NY; ++iy) {
-          const int64_t z = bz * Sh::BZ + iz - HZ, y = by * Sh::BY + iy - HY;
-          const bool row = z >= 0 && z < g.Z && y >= 0 && y < g.Y;
-          const bool ia = row && inx, ib = row && xx >= 1 && xx - 1 < g.X;
-          qa[iz][iy] = ia ? quantize((double)va[u][iz][iy], inv, over) : 0;
-          qb[iz][iy] = ib ? quantize((double)vb[u][iz][iy], inv, over) : 0;
-          if (iz >= HZ && iy >= HY) {
-            const uint32_t aq = (uint32_t)(qa[iz][iy] < 0 ? -qa[iz][iy] : qa[iz][iy]);
-            maxq = aq > maxq ? aq : maxq;
+          if constexpr (HZ) {
+            qa[0][iy] = ha[u][iy];
+            qb[0][iy] = hb[u][iy];
           }
-        }
-      }
-      const int loc = u * kThreads + t;  // column within the tile
 #pragma unroll
-      for (int dz = 0; dz < Sh::BZ; ++dz) {
-#pragma unroll
-        for (int dy = 0; dy < Sh::BY; ++dy) {
-          const int iz = dz + HZ, iy = dy + HY;
-          const bool inside = inx && bz * Sh::BZ + dz < g.Z && by * Sh::BY + dy < g.Y;
-          int64_t r = (int64_t)qa[iz][iy] - qb[iz][iy];
-          if constexpr (ND >= 2) r += (int64_t)qb[iz][iy - 1] - qa[iz][iy - 1];
-          if constexpr (ND == 3) {
-            r += (int64_t)qb[iz - 1][iy] - qa[iz - 1][iy];
-            r += (int64_t)qa[iz - 1][iy - 1] - qb[iz - 1][iy - 1];
-          }
-          if (!inside) r = 0;  // a slot past the field's end
-          const int64_t ar = r < 0 ? -r : r;
-          wide |= ar > kPMax;
-          if constexpr (ND == 1) {
-            // one row of blocks: slot order is field order, block xx / S in lanes of l / S
-            const int ab = block_or_scan<S>((int)(ar > kPMax ? kPMax : ar));
-            if (xx < xp) {
-              resid[xx] = (int32_t)r;
-              if (l % S == S - 1) widths[xx / S] = (uint8_t)bitlen((uint32_t)ab);
+          for (int dz = 0; dz < Sh::BZ; ++dz) {
+            quant_row(bz * Sh::BZ + dz, by * Sh::BY + iy - HY, xx, va[u][dz][iy], vb[u][dz][iy], qa[dz + HZ][iy],
+                      qb[dz + HZ][iy]);
+            if (iy >= HY) {
+              const int q = qa[dz + HZ][iy];
+              const uint32_t aq = (uint32_t)(q < 0 ? -q : q);
+              maxq = aq > maxq ? aq : maxq;
             }
-          } else {
-            tile[(loc / Sh::BX) * (S + R::kPad) + (dz * Sh::BY + dy) * Sh::BX + loc % Sh::BX] = (int32_t)r;
+          }
+        }
+        const int loc = u * kThreads + t;  // column within the tile
+#pragma unroll
+        for (int dz = 0; dz < Sh::BZ; ++dz) {
+#pragma unroll
+          for (int dy = 0; dy < Sh::BY; ++dy) {
+            const int iz = dz + HZ, iy = dy + HY;
+            const bool inside = inx && bz * Sh::BZ + dz < g.Z && by * Sh::BY + dy < g.Y;
+            int64_t r = (int64_t)qa[iz][iy] - qb[iz][iy];
+            if constexpr (ND >= 2) r += (int64_t)qb[iz][iy - 1] - qa[iz][iy - 1];
+            if constexpr (ND == 3) {
+              r += (int64_t)qb[iz - 1][iy] - qa[iz - 1][iy];
+              r += (int64_t)qa[iz - 1][iy - 1] - qb[iz - 1][iy - 1];
+            }
+            if (!inside) r = 0;  // a slot past the field's end
+            const int64_t ar = r < 0 ? -r : r;
+            wide |= ar > kPMax;
+            if constexpr (ND == 1) {
+              // one row of blocks: slot order is field order, block xx / S in lanes of l / S
+              const int ab = block_or_scan<S>((int)(ar > kPMax ? kPMax : ar));
+              if (xx < xp) {
+                resid[xx] = (int32_t)r;
+                if (l % S == S - 1) widths[xx / S] = (uint8_t)bitlen((uint32_t)ab);
+              }
+            } else {
+              tile[(loc / Sh::BX) * (S + R::kPad) + (dz * Sh::BY + dy) * Sh::BX + loc % Sh::BX] = (int32_t)r;
+            }
+          }
+        }
+        if constexpr (HZ) {
+#pragma unroll
+          for (int iy = 0; iy < NY; ++iy) {
+            ha[u][iy] = qa[Sh::BZ][iy];
+            hb[u][iy] = qb[Sh::BZ][iy];
           }
         }
       }
-    }
-    if constexpr (ND >= 2) {
-      __syncthreads();
-      const int64_t xe = xp < xbase + R::kSpan ? xp : xbase + R::kSpan;
-      const int total = (int)((xe - xbase) / Sh::BX) * S;  // words of the tile's blocks inside the partition
-      const int64_t b0 = (bz * g.nby + by) * g.nbx + xbase / Sh::BX;
-      int32_t* dst = resid + b0 * S;
-      for (int k0 = 0; k0 < total; k0 += kThreads) {  // every lane takes part in the block OR
-        const int k = k0 + t;
-        const int v = k < total ? tile[(k / S) * (S + R::kPad) + k % S] : 0;
-        const int ab = block_or_scan<S>(v < 0 ? -v : v);  // |v| <= kPMax unless a range error stops the stream
-        if (k < total) {
-          dst[k] = v;
-          if (l % S == S - 1) widths[b0 + k / S] = (uint8_t)bitlen((uint32_t)ab);
+      if constexpr (ND >= 2) {
+        __syncthreads();
+        const int64_t xe = xp < xbase + R::kSpan ? xp : xbase + R::kSpan;
+        const int total = (int)((xe - xbase) / Sh::BX) * S;  // words of the tile's blocks inside the partition
+        const int64_t b0 = (bz * g.nby + by) * g.nbx + xbase / Sh::BX;
+        int32_t* dst = resid + b0 * S;
+        for (int k0 = 0; k0 < total; k0 += kThreads) {  // every lane takes part in the block OR
+          const int k = k0 + t;
+          const int v = k < total ? tile[(k / S) * (S + R::kPad) + k % S] : 0;
+          const int ab = block_or_scan<S>(v < 0 ? -v : v);  // |v| <= kPMax unless a range error stops the stream
+          if (k < total) {
+            dst[k] = v;
+            if (l % S == S - 1) widths[b0 + k / S] = (uint8_t)bitlen((uint32_t)ab);
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
   maxq = (uint32_t)wave_max((int)maxq);
@@ -911,11 +948,16 @@ hipError_t run_nd(const CompressArgs& a, const NdGrid& g, hipStream_t s) {
   int32_t* resid = (int32_t*)(a.ws + ws_resid_off(L));
   using Sh = NdShape<ND, S>;
   const int64_t nxt = (g.nbx * Sh::BX + ResidTile<T, S, ND>::kSpan - 1) / ResidTile<T, S, ND>::kSpan;
-  const int64_t rcount = nxt * g.nby * g.nbz;
+  // runs of block planes per work item (3D): long enough to amortise the
+  // halo plane, short enough to leave about 4096 work items
+  const int64_t tiles2 = nxt * g.nby;
+  int64_t zper = ND == 3 ? (tiles2 * g.nbz) / 4096 : 1;
+  zper = zper < 1 ? 1 : (zper > 16 ? 16 : zper);
+  const int64_t rcount = tiles2 * ((g.nbz + zper - 1) / zper);
   const int rgrid = (int)(rcount < (int64_t)(1 << 20) ? rcount : (int64_t)(1 << 20));
   hipLaunchKernelGGL(k_zero_u32, dim3((grid + kThreads - 1) / kThreads), dim3(kThreads), 0, s, group_max, grid);
   if (rgrid > 0)
-    hipLaunchKernelGGL((k_resid_nd<T, S, ND>), dim3(rgrid), dim3(kThreads), 0, s, x, g, nxt, rcount, ws, resid,
+    hipLaunchKernelGGL((k_resid_nd<T, S, ND>), dim3(rgrid), dim3(kThreads), 0, s, x, g, nxt, zper, rcount, ws, resid,
                        out + L.off_width, group_max, grid);
   hipLaunchKernelGGL((k_chunk_words_nd<S>), dim3(grid), dim3(kThreads), 0, s, (const uint8_t*)(out + L.off_width),
                      L.nb, L.nchunks, ws, chunk_words);

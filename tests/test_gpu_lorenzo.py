@@ -224,6 +224,20 @@ def test_vector_fields_and_one_dimensional_fields_refused():
     assert e.value.code == hsz.ERR_UNSUPPORTED
 
 
+@pytest.mark.parametrize("shape,dt,S", [((201, 400, 40), np.float32, 32), ((201, 400, 40), np.float64, 32),
+                                        ((180, 400, 300), np.float32, 64)],
+                         ids=["201x400x40-f32-S32", "201x400x40-f64-S32", "180x400x300-f32-S64"])
+def test_compress_runs_of_block_planes(shape, dt, S):
+    """Fields with enough rows of blocks that one residual work item walks
+    several block planes (the halo plane carried between them), the last run
+    shorter: the stream equals the oracle's byte for byte."""
+    say(f"[case] lorenzo long runs {shape} {np.dtype(dt).name} S{S}")
+    x = np.ascontiguousarray(synth.gaussian_mixture(shape, 4, (3.0, 30.0), seed=7).astype(dt))
+    ref = oracle.compress(x, 1e-4, rel=True, block=S, lorenzo=True)
+    c = hsz.compress(torch.from_numpy(x).to(DEV), 1e-4, rel=True, block=S, lorenzo=True)
+    assert np.array_equal(c.to_bytes(), ref)
+
+
 def test_residual_range_error():
     """A binary64 checkerboard with |q| near 2.5e8 has 3D residuals near 2e9,
     beyond 2^30 - 1: the compressor reports a range error, as the oracle."""
