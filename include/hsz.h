@@ -147,6 +147,11 @@ int hsz_compress_bound(int dtype, int ndim, const int64_t *h_dims, int block, ui
  * the other modes need a few kilobytes plus 4 bytes per 64 blocks. */
 int hsz_compress_workspace(int ndim, const int64_t *h_dims, int block, uint64_t *h_bytes);
 
+/* Workspace of one mode (flags as for hsz_compress_flags): what that mode
+ * needs, at most hsz_compress_workspace().  INVALID_ARG for other flags,
+ * UNSUPPORTED for HSZ_FLAG_LORENZO on a 1D field or a block other than 32 / 64. */
+int hsz_compress_workspace_mode(int ndim, const int64_t *h_dims, int block, uint32_t flags, uint64_t *h_bytes);
+
 /* Compress d_x (dtype, dims) into d_out (capacity 'cap' bytes, at least
  * hsz_compress_bound()).  The stream's length is header.total_bytes; after
  * the stream completes, read the header back (HSZ_HEADER_BYTES from d_out)

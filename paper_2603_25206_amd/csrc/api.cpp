@@ -218,6 +218,19 @@ int hsz_compress_workspace(int ndim, const int64_t* h_dims, int block, uint64_t*
   return HSZ_OK;
 }
 
+int hsz_compress_workspace_mode(int ndim, const int64_t* h_dims, int block, uint32_t flags, uint64_t* h_bytes) {
+  int64_t d3[3], n;
+  if (!h_bytes || !dims3_of(ndim, h_dims, d3, &n)) return HSZ_ERR_INVALID_ARG;
+  if (flags != 0 && flags != HSZ_FLAG_BLOCK_MEAN && flags != HSZ_FLAG_LORENZO && flags != HSZ_FLAG_INTER_BLOCK)
+    return HSZ_ERR_INVALID_ARG;
+  if (!valid_block(block)) return HSZ_ERR_UNSUPPORTED;
+  if (flags == HSZ_FLAG_LORENZO && ndim < 2) return HSZ_ERR_UNSUPPORTED;
+  *h_bytes = flags == HSZ_FLAG_LORENZO       ? hsz::compress_workspace_bytes_nd(hsz::make_layout_nd(d3, ndim, block))
+             : flags == HSZ_FLAG_INTER_BLOCK ? hsz::compress_workspace_bytes_nd(hsz::make_layout_flat(n, block))
+                                             : hsz::compress_workspace_bytes(hsz::make_layout(n, block));
+  return HSZ_OK;
+}
+
 int hsz_compress(const void* d_x, int dtype, int ndim, const int64_t* h_dims, double eb, int eb_is_rel, int block,
                  void* d_out, uint64_t cap, void* d_workspace, uint64_t workspace_bytes, void* stream) {
   return hsz_compress_flags(d_x, dtype, ndim, h_dims, eb, eb_is_rel, block, 0u, d_out, cap, d_workspace,

@@ -92,7 +92,7 @@ EXPORTS = (
     "hsz_batch_workspace", "hsz_batch_run", "hsz_plan_create", "hsz_plan_update", "hsz_plan_launch",
     "hsz_plan_destroy", "hsz_block_index_bytes", "hsz_block_index", "hsz_vector_workspace",
     "hsz_vector_op_on_stage", "hsz_vector_op_fused", "hsz_compress_range", "hsz_extremes_workspace",
-    "hsz_extremes", "hsz_ooc_workspace", "hsz_ooc_op",
+    "hsz_extremes", "hsz_ooc_workspace", "hsz_ooc_op", "hsz_compress_workspace_mode",
 )
 
 _lib = None
@@ -115,6 +115,7 @@ def load(path: str = LIB_PATH):
         "hsz_read_status": (i32, [P, P, ctypes.POINTER(ctypes.c_int)]),
         "hsz_compress_bound": (i32, [i32, i32, pi64, i32, pu64]),
         "hsz_compress_workspace": (i32, [i32, pi64, i32, pu64]),
+        "hsz_compress_workspace_mode": (i32, [i32, pi64, i32, ctypes.c_uint32, pu64]),
         "hsz_compress": (i32, [P, i32, i32, pi64, dbl, i32, i32, P, u64, P, u64, P]),
         "hsz_compress_flags": (i32, [P, i32, i32, pi64, dbl, i32, i32, ctypes.c_uint32, P, u64, P, u64, P]),
         "hsz_read_header": (i32, [P, u64, u64, ctypes.POINTER(Header)]),
@@ -289,7 +290,7 @@ def compress(x: torch.Tensor, eb: float, rel: bool = True, block: int = 32, stre
     if out is None:
         out = _empty_bytes(cap, x.device)
     wsb = ctypes.c_uint64()
-    _check(lib.hsz_compress_workspace(len(shape), dims, block, ctypes.byref(wsb)), "compress_workspace")
+    _check(lib.hsz_compress_workspace_mode(len(shape), dims, block, flags, ctypes.byref(wsb)), "compress_workspace")
     ws = workspace(wsb.value, x.device, key="compress")
     s = _stream(stream)
     _check(lib.hsz_compress_flags(ctypes.c_void_p(x.data_ptr()), dt, len(shape), dims, float(eb), int(rel),
@@ -688,7 +689,8 @@ def compress_range(x: torch.Tensor, eb: float, vmin: float, vmax: float, rel: bo
     dims = _dims(shape)
     out = _empty_bytes(compress_bound(shape, dt, block), x.device)
     wsb = ctypes.c_uint64()
-    _check(lib.hsz_compress_workspace(len(shape), dims, block, ctypes.byref(wsb)), "compress_workspace")
+    _check(lib.hsz_compress_workspace_mode(len(shape), dims, block, FLAG_BLOCK_MEAN if mean_dec else 0,
+                                           ctypes.byref(wsb)), "compress_workspace")
     ws = workspace(wsb.value, x.device, key="compress")
     _check(lib.hsz_compress_range(ctypes.c_void_p(x.data_ptr()), dt, len(shape), dims, float(eb), int(rel),
                                   float(vmin), float(vmax), block, FLAG_BLOCK_MEAN if mean_dec else 0,

@@ -268,3 +268,30 @@ def test_slab_and_out_of_core_validation_before_any_launch(lib):
     assert run(hsz.QUANT, hsz.GRADMAG, cap=16) == hsz.ERR_CAPACITY
     assert run(hsz.QUANT, hsz.GRADMAG, wsb=need - 1) == hsz.ERR_CAPACITY
     assert run(hsz.QUANT, hsz.VAR_MT) == hsz.ERR_INVALID_ARG
+
+
+def test_compress_workspace_per_mode(lib):
+    """The delta and block-mean modes need a few kilobytes plus the chunk
+    counts; the Lorenzo modes add one int32 residual per slot of their
+    partition; the any-mode query is the largest of them."""
+    u = ctypes.c_uint64
+    dims = (ctypes.c_int64 * 3)(37, 41, 29)
+    anym = u()
+    assert lib.hsz_compress_workspace(3, dims, 32, ctypes.byref(anym)) == 0
+    w = {}
+    for f in (0, hsz.FLAG_BLOCK_MEAN, hsz.FLAG_LORENZO, hsz.FLAG_INTER_BLOCK):
+        v = u()
+        assert lib.hsz_compress_workspace_mode(3, dims, 32, f, ctypes.byref(v)) == 0
+        w[f] = v.value
+    n = 37 * 41 * 29
+    nd_slots = (37 // 2 + 1) * (41 // 4 + 1) * (29 // 4 + 1) * 32  # 2x4x4 blocks, ragged on every axis
+    assert w[0] == w[hsz.FLAG_BLOCK_MEAN] < 65536
+    assert w[hsz.FLAG_INTER_BLOCK] >= w[0] + 4 * n
+    assert w[hsz.FLAG_LORENZO] >= w[0] + 4 * nd_slots
+    assert max(w.values()) == anym.value
+    v = u()
+    assert lib.hsz_compress_workspace_mode(3, dims, 32, 3, ctypes.byref(v)) == hsz.ERR_INVALID_ARG
+    assert lib.hsz_compress_workspace_mode(3, dims, 48, 0, ctypes.byref(v)) == hsz.ERR_UNSUPPORTED
+    one = (ctypes.c_int64 * 1)(1000)
+    assert lib.hsz_compress_workspace_mode(1, one, 32, hsz.FLAG_LORENZO, ctypes.byref(v)) == hsz.ERR_UNSUPPORTED
+    assert lib.hsz_compress_workspace_mode(1, one, 32, hsz.FLAG_INTER_BLOCK, ctypes.byref(v)) == 0
