@@ -674,11 +674,12 @@ hipError_t run(const CompressArgs& a, hipStream_t s) {
 // issued before any is used, then forms the BZ x BY residuals of each
 // column.  In 3D a work item walks a run of zper block planes of the same
 // row of blocks: the halo plane is loaded once per run, and each block
-// plane's last plane is carried, quantized, as the next one's halo.  The nd modes gather the tile's blocks in LDS (BX pad words after
-// each block keep the column writes on distinct banks) and store them as one
-// contiguous run; the flat mode's blocks are already in field order.  Either
-// way the lanes then hold whole blocks (slot l % S), and the last lane of each
-// writes the block's width.
+// plane's last plane is carried, quantized, as the next one's halo.  The nd
+// modes gather the tile's blocks in LDS (BX pad words after each block keep
+// the column writes on distinct banks) and store them as one contiguous run;
+// the flat mode's blocks are already in field order.  Either way the lanes
+// then hold whole blocks (slot l % S), and the last lane of each writes the
+// block's width.
 template <typename T, int S, int ND>
 struct ResidTile {
   using Sh = NdShape<ND, S>;
