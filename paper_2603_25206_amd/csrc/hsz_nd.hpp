@@ -124,9 +124,10 @@ hipError_t lz_deriv_p(const int32_t* p, const StreamView& v, const NdGrid& g, in
 // Prefix sums along the 3D view's axes z..x except 'skip' (-1: none) of an
 // int32 field stored at element stride es (1 or 2 words), in place.  A
 // single row (Z = Y = 1) is scanned device-wide in tiles of 4096 words whose
-// sums go to 'tmp' (lz_scan_tmp_bytes(X) bytes).
+// sums go to 'tmp' (lz_scan_tmp_bytes(X) bytes); sums_ready: the decoder
+// already wrote them there.
 hipError_t lz_scan_axes(int32_t* buf, int64_t Z, int64_t Y, int64_t X, int es, int skip, int32_t* tmp,
-                        hipStream_t s);
+                        hipStream_t s, bool sums_ready = false);
 constexpr int64_t kFlatTile = 4096;
 inline uint64_t lz_scan_tmp_bytes(int64_t n) { return ((uint64_t)(4 * ((n + kFlatTile - 1) / kFlatTile)) + 255) / 256 * 256; }
 

@@ -38,10 +38,14 @@ constexpr int kWavesPerGroup = kThreads / kWave;
 // flat field (ND = 1) covers 64 S consecutive words per chunk: each lane
 // puts its block's S values in row l of a (64 x (S+1))-word LDS tile (the +1
 // keeps the writes conflict-free) and the wave stores the chunk 64 words at
-// a time; nd blocks are written row by row (BX consecutive words).
+// a time; nd blocks are written row by row (BX consecutive words).  With
+// tsums the flat decoder also adds each chunk's residuals (the words inside
+// the field) to the sum of its kFlatTile-word scan tile, which the device-wide
+// scan then takes instead of reading the field again.
 template <int S, int ND>
 __global__ void __launch_bounds__(kThreads) k_lz_decode_p(StreamView v, NdGrid g, int kmax, int wave_words,
-                                                         int32_t* __restrict__ out, int es, int* status) {
+                                                         int32_t* __restrict__ out, int es, int* status,
+                                                         int32_t* __restrict__ tsums) {
   using Sh = NdShape<ND, S>;
   extern __shared__ uint32_t smem[];
   const int wv = wave_in_group();
@@ -54,6 +58,20 @@ __global__ void __launch_bounds__(kThreads) k_lz_decode_p(StreamView v, NdGrid g
     if constexpr (ND == 1) {
       int vals[S];
       decode_lane_block<S, kWave, true>(tile + l, w, 0, [&](int j, int p, int) { vals[j] = p; });
+      if (tsums) {
+        // a chunk's words are one tile (S = 64) or half of one (S = 32); the
+        // sum of any run of p is a difference of two q, so it fits 32 bits
+        // (partial sums may wrap, hence unsigned)
+        uint32_t bs = 0;
+#pragma unroll
+        for (int j = 0; j < S; ++j) bs += (b * S + j < g.X) ? (uint32_t)vals[j] : 0u;
+        for (int m = kWave / 2; m >= 1; m >>= 1) bs += (uint32_t)__shfl_xor((int)bs, m);
+        constexpr int kPerTile = (int)(kFlatTile / (S * kChunkBlocks));
+        if (l == 0) {
+          if (kPerTile == 1) tsums[c] = (int32_t)bs;
+          else atomicAdd(&tsums[c / kPerTile], (int)bs);
+        }
+      }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -536,8 +554,13 @@ unsigned grid_of(int64_t items, int per) {
   return (unsigned)(g < 1 ? 1 : (g > 65535 ? 65535 : g));
 }
 
+__global__ void __launch_bounds__(kThreads) k_clear_i32(int32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) p[i] = 0;
+}
+
 template <int S, int ND>
-hipError_t decode_p(const StreamView& v, const NdGrid& g, int32_t* out, int es, int* status, hipStream_t s) {
+hipError_t decode_p(const StreamView& v, const NdGrid& g, int32_t* out, int es, int* status, hipStream_t s,
+                    int32_t* tsums) {
   const int kmax = lz_kmax<S, ND>(v.max_abs_q);
   int wave_words = (kmax + 1) * kWave;
   if (ND == 1 && wave_words < kWave * (S + 1)) wave_words = kWave * (S + 1);
@@ -545,24 +568,36 @@ hipError_t decode_p(const StreamView& v, const NdGrid& g, int32_t* out, int es, 
   const int64_t groups = (v.nchunks + kWavesPerGroup - 1) / kWavesPerGroup;
   const unsigned grid = (unsigned)(groups < 8192 ? (groups < 1 ? 1 : groups) : 8192);
   hipLaunchKernelGGL((k_lz_decode_p<S, ND>), dim3(grid), dim3(kThreads), lds, s, v, g, kmax, wave_words, out, es,
-                     status);
+                     status, ND == 1 ? tsums : nullptr);
   return hipGetLastError();
 }
 
-hipError_t decode_p_any(const StreamView& v, const NdGrid& g, int32_t* out, int es, int* status, hipStream_t s) {
-  if (g.ndim == 3) return v.block == 32 ? decode_p<32, 3>(v, g, out, es, status, s) : decode_p<64, 3>(v, g, out, es, status, s);
-  if (g.ndim == 2) return v.block == 32 ? decode_p<32, 2>(v, g, out, es, status, s) : decode_p<64, 2>(v, g, out, es, status, s);
-  return v.block == 32 ? decode_p<32, 1>(v, g, out, es, status, s) : decode_p<64, 1>(v, g, out, es, status, s);
+// tsums: tile sums of the flat field's scan (ND = 1 only; cleared here), or null
+hipError_t decode_p_any(const StreamView& v, const NdGrid& g, int32_t* out, int es, int* status, hipStream_t s,
+                        int32_t* tsums = nullptr) {
+  if (g.ndim == 3)
+    return v.block == 32 ? decode_p<32, 3>(v, g, out, es, status, s, nullptr)
+                         : decode_p<64, 3>(v, g, out, es, status, s, nullptr);
+  if (g.ndim == 2)
+    return v.block == 32 ? decode_p<32, 2>(v, g, out, es, status, s, nullptr)
+                         : decode_p<64, 2>(v, g, out, es, status, s, nullptr);
+  if (tsums) {
+    const int64_t ntiles = (g.X + kFlatTile - 1) / kFlatTile;
+    hipLaunchKernelGGL(k_clear_i32, dim3(grid_of(ntiles, kThreads)), dim3(kThreads), 0, s, tsums, ntiles);
+  }
+  return v.block == 32 ? decode_p<32, 1>(v, g, out, es, status, s, tsums)
+                       : decode_p<64, 1>(v, g, out, es, status, s, tsums);
 }
 
 }  // namespace
 
 hipError_t lz_scan_axes(int32_t* buf, int64_t Z, int64_t Y, int64_t X, int es, int skip, int32_t* tmp,
-                        hipStream_t s) {
+                        hipStream_t s, bool sums_ready) {
   if (skip != 2 && Z * Y == 1 && X > kFlatTile) {
     if (!tmp) return hipErrorInvalidValue;
     const int64_t ntiles = (X + kFlatTile - 1) / kFlatTile;
-    hipLaunchKernelGGL(k_flat_tile_sums, dim3(grid_of(ntiles, 1)), dim3(kThreads), 0, s, buf, X, es, tmp);
+    if (!sums_ready)
+      hipLaunchKernelGGL(k_flat_tile_sums, dim3(grid_of(ntiles, 1)), dim3(kThreads), 0, s, buf, X, es, tmp);
     hipLaunchKernelGGL(k_flat_scan_sums, dim3(1), dim3(kThreads), 0, s, tmp, ntiles);
     hipLaunchKernelGGL(k_flat_apply, dim3(grid_of(ntiles, 1)), dim3(kThreads), 0, s, buf, X, es, tmp);
   } else if (skip != 2) {
@@ -591,7 +626,9 @@ hipError_t lz_decode(const StreamView& v, const NdGrid& g, int stage, void* out,
                      hipStream_t s) {
   if (stage < 2 || stage > 4) return hipErrorInvalidValue;
   const int es = (stage == 4 && v.dtype == 2) ? 2 : 1;
-  hipError_t e = decode_p_any(v, g, (int32_t*)out, es, status, s);
+  // the flat field's device-wide scan takes its tile sums from the decoder
+  const bool fused_sums = stage >= 3 && g.ndim == 1 && g.Z * g.Y == 1 && g.X > kFlatTile && tmp;
+  hipError_t e = decode_p_any(v, g, (int32_t*)out, es, status, s, fused_sums ? tmp : nullptr);
   if (e != hipSuccess || stage == 2) return e;
   if (stage == 4 && v.dtype == 1 && g.ndim >= 2 && (g.X & 3) == 0) {
     // all axes but the field's slowest, then the slowest writing the floats
@@ -606,7 +643,7 @@ hipError_t lz_decode(const StreamView& v, const NdGrid& g, int stage, void* out,
                          (int64_t)1, g.Y, g.X, v.quantum);
     return hipGetLastError();
   }
-  e = lz_scan_axes((int32_t*)out, g.Z, g.Y, g.X, es, -1, tmp, s);
+  e = lz_scan_axes((int32_t*)out, g.Z, g.Y, g.X, es, -1, tmp, s, fused_sums);
   if (e != hipSuccess || stage == 3) return e;
   const int64_t n = g.Z * g.Y * g.X;
   if (v.dtype == 1)
