@@ -1076,16 +1076,21 @@ hipError_t launch_lz_stats(const int32_t* p, const StreamView& v, const NdGrid& 
                            : launch_lz_mean_fused<64, 1>(v, g, parts, status, s);
   } else if (op == 2) {
     const int64_t n = g.Z * g.Y * g.X;
+    // the prefix sums over every axis but the field's slowest (3D view: z for
+    // 3D, y for 2D); HSZp's single row is scanned whole and then only read,
+    // so from compressed bytes it is decoded straight to D_q (the decoder
+    // then also provides the scan's tile sums)
+    const int last = g.ndim == 3 ? 0 : (g.ndim == 2 ? 1 : -1);
+    const bool to_q = !p && g.ndim == 1;
     if (p) hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n, kThreads * 4)), dim3(kThreads), 0, s, p, n, scratch);
     else {
-      hipError_t e = lz_decode(v, g, 2, scratch, status, tmp, s);
+      hipError_t e = lz_decode(v, g, to_q ? 3 : 2, scratch, status, tmp, s);
       if (e != hipSuccess) return e;
     }
-    // the prefix sums over every axis but the field's slowest (3D view: z for
-    // 3D, y for 2D); HSZp's single row is scanned whole and then only read
-    const int last = g.ndim == 3 ? 0 : (g.ndim == 2 ? 1 : -1);
-    hipError_t e = lz_scan_axes(scratch, g.Z, g.Y, g.X, 1, last, tmp, s);
-    if (e != hipSuccess) return e;
+    if (!to_q) {
+      hipError_t e = lz_scan_axes(scratch, g.Z, g.Y, g.X, 1, last, tmp, s);
+      if (e != hipSuccess) return e;
+    }
     const int64_t len = last == 0 ? g.Z : (last == 1 ? g.Y : 1);
     const int64_t inner = last == 0 ? g.Y * g.X : g.X;
     grid = grid_for(inner, kThreads);
