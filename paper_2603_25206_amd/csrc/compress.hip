@@ -249,8 +249,12 @@ __device__ __forceinline__ int block_add_scan(int v) {
 }
 
 // Integer mean of each block, rounded half down, for the lanes of one step
-// (q of invalid lanes is 0; 'len' is the lane's block length, >= 1).
-template <int S>
+// (q of invalid lanes is 0; 'len' is the lane's block length, >= 1): the
+// ceiling of (2 sum - len) / (2 len).  A whole block (FULL, len = S) divides
+// by the power of two 2S, so the ceiling is exact in integers:
+// floor((2 sum + S - 1) / 2S), an arithmetic shift; a partial block takes
+// the binary64 quotient (exact: both operands are integers below 2^36).
+template <int S, bool FULL>
 __device__ __forceinline__ int block_mean(int q, int len) {
   const int lo = block_add_scan<S>(q & 0xffff), hi = block_add_scan<S>(q >> 16);
   int slo, shi;
@@ -263,8 +267,13 @@ __device__ __forceinline__ int block_mean(int q, int len) {
     shi = __builtin_amdgcn_readlane(hi, 63);
   }
   const int64_t sum = (int64_t)shi * 65536 + (int64_t)slo;
-  const double num = 2.0 * (double)sum - (double)len, den = 2.0 * (double)len;
-  return (int)ceil(num / den);
+  if constexpr (FULL) {
+    constexpr int kShift = S == 32 ? 6 : 7;  // log2(2S)
+    return (int)((2 * sum + (S - 1)) >> kShift);
+  } else {
+    const double num = 2.0 * (double)sum - (double)len, den = 2.0 * (double)len;
+    return (int)ceil(num / den);
+  }
 }
 
 // the value of the lane below (wave shift right by one; lane 0 gets 0).  The
@@ -335,7 +344,7 @@ __global__ void __launch_bounds__(kThreads) k_quant_meta(const T* __restrict__ x
           const int64_t bstart = e0 + (int64_t)(st + u) * kWave + (l / S) * S;
           const int64_t rem = n - bstart;
           const int len = FULL ? S : (int)(rem < S ? (rem > 0 ? rem : 1) : S);
-          meta = block_mean<S>(q, len);
+          meta = block_mean<S, FULL>(q, len);
           p = valid ? q - meta : 0;
         } else {
           const int qp = from_lane_below(q);
