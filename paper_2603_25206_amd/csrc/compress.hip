@@ -254,19 +254,24 @@ __device__ __forceinline__ int block_add_scan(int v) {
 // by the power of two 2S, so the ceiling is exact in integers:
 // floor((2 sum + S - 1) / 2S), an arithmetic shift; a partial block takes
 // the binary64 quotient (exact: both operands are integers below 2^36).
-template <int S, bool FULL>
+// SMALL: every |q| of the step is below 2^30 / S, so the block sum fits one
+// 32-bit scan; otherwise the low and high 16 bits are summed apart.
+template <int S, bool FULL, bool SMALL>
 __device__ __forceinline__ int block_mean(int q, int len) {
-  const int lo = block_add_scan<S>(q & 0xffff), hi = block_add_scan<S>(q >> 16);
-  int slo, shi;
-  if (S == 32) {
-    const bool up = lane_id() >= 32;
-    slo = up ? __builtin_amdgcn_readlane(lo, 63) : __builtin_amdgcn_readlane(lo, 31);
-    shi = up ? __builtin_amdgcn_readlane(hi, 63) : __builtin_amdgcn_readlane(hi, 31);
+  auto block_total = [](int t) {  // the scan's value in the block's last lane
+    if (S == 32) {
+      const bool up = lane_id() >= 32;
+      return up ? __builtin_amdgcn_readlane(t, 63) : __builtin_amdgcn_readlane(t, 31);
+    }
+    return __builtin_amdgcn_readlane(t, 63);
+  };
+  int64_t sum;
+  if constexpr (SMALL) {
+    sum = block_total(block_add_scan<S>(q));
   } else {
-    slo = __builtin_amdgcn_readlane(lo, 63);
-    shi = __builtin_amdgcn_readlane(hi, 63);
+    const int lo = block_add_scan<S>(q & 0xffff), hi = block_add_scan<S>(q >> 16);
+    sum = (int64_t)block_total(hi) * 65536 + (int64_t)block_total(lo);
   }
-  const int64_t sum = (int64_t)shi * 65536 + (int64_t)slo;
   if constexpr (FULL) {
     constexpr int kShift = S == 32 ? 6 : 7;  // log2(2S)
     return (int)((2 * sum + (S - 1)) >> kShift);
@@ -332,27 +337,45 @@ __global__ void __launch_bounds__(kThreads) k_quant_meta(const T* __restrict__ x
       // quantize and decorrelate the kAhead steps, then run their block
       // prefix-OR scans stage by stage: the independent DPP chains interleave
       // instead of stalling on each other's results
-      int ab[kAhead];
+      int qv[kAhead];
+      uint32_t step_max = 0;
 #pragma unroll
       for (int u = 0; u < kAhead; ++u) {
         const bool valid = FULL || e0 + (int64_t)(st + u) * kWave + l < n;
-        const int q = valid ? quantize((double)v[u], inv, over) : 0;
-        const uint32_t aq = (uint32_t)(q < 0 ? -q : q);
-        maxq = aq > maxq ? aq : maxq;
-        int p, meta;
-        if constexpr (MEAN) {
-          const int64_t bstart = e0 + (int64_t)(st + u) * kWave + (l / S) * S;
-          const int64_t rem = n - bstart;
-          const int len = FULL ? S : (int)(rem < S ? (rem > 0 ? rem : 1) : S);
-          meta = block_mean<S, FULL>(q, len);
-          p = valid ? q - meta : 0;
-        } else {
-          const int qp = from_lane_below(q);
-          p = (slot == 0 || !valid) ? 0 : q - qp;
-          meta = q;
+        qv[u] = valid ? quantize((double)v[u], inv, over) : 0;
+        const uint32_t aq = (uint32_t)(qv[u] < 0 ? -qv[u] : qv[u]);
+        step_max = aq > step_max ? aq : step_max;
+      }
+      maxq = step_max > maxq ? step_max : maxq;
+      int ab[kAhead];
+      auto decorrelate = [&](auto small_tag) {
+        constexpr bool SMALL = decltype(small_tag)::value;
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+          const bool valid = FULL || e0 + (int64_t)(st + u) * kWave + l < n;
+          const int q = qv[u];
+          int p, meta;
+          if constexpr (MEAN) {
+            const int64_t bstart = e0 + (int64_t)(st + u) * kWave + (l / S) * S;
+            const int64_t rem = n - bstart;
+            const int len = FULL ? S : (int)(rem < S ? (rem > 0 ? rem : 1) : S);
+            meta = block_mean<S, FULL, SMALL>(q, len);
+            p = valid ? q - meta : 0;
+          } else {
+            const int qp = from_lane_below(q);
+            p = (slot == 0 || !valid) ? 0 : q - qp;
+            meta = q;
+          }
+          ab[u] = p < 0 ? -p : p;
+          if (slot == 0) mq0[(st + u) * (kWave / S) + l / S] = meta;
         }
-        ab[u] = p < 0 ? -p : p;
-        if (slot == 0) mq0[(st + u) * (kWave / S) + l / S] = meta;
+      };
+      if constexpr (MEAN) {
+        // one vote per kAhead steps, so the branch is the whole wave's
+        if (__all(step_max < (uint32_t)((1 << 30) / S))) decorrelate(std::true_type{});
+        else decorrelate(std::false_type{});
+      } else {
+        decorrelate(std::false_type{});
       }
 #pragma unroll
       for (int u = 0; u < kAhead; ++u) ab[u] |= dpp<0x111>(ab[u]);

@@ -42,6 +42,8 @@ CASES = [
     ((181, 367), np.float64, 1e-6, 32),
     ((100003,), np.float32, 1e-3, 32),
     ((3, 5, 7), np.float32, 1e-3, 32),  # one partial block
+    ((201, 399), np.float64, 1e-9, 32),  # |q| up to ~2.5e8: block sums past 32 bits
+    ((150, 170), np.float64, 1e-8, 64),  # steps on both sides of the 32-bit block-sum limit
 ]
 
 
