@@ -995,42 +995,40 @@ int or_lz_mean_p(const int32_t *p, uint32_t ndim, const uint64_t *dims, double q
   return OR_OK;
 }
 
-/* Alg. 4 (standard deviation with D_p, written for 2D) in the 3D view: per
- * plane, a running sum along the row (prefSum) and a column buffer (colSum)
- * rebuild the plane's 2D Lorenzo prefix sums r; a plane buffer adds r over
- * the planes, giving q = q(z-1) + r (for a 2D field the plane buffer is
- * zero before the only plane, which is Alg. 4 itself).  s1 = sum q and
- * s2 = sum q^2 are exact; var as Eq. (var) with N - 1, rounded once from
- * (n s2 - s1^2) / (n (n - 1)) Delta^2. */
+/* Standard deviation on D_p of HSZp-nd (Alg. 4, Sec. V-A).  Alg. 4 rebuilds
+ * q from p by running sums and accumulates sum q and sum q^2 on the way;
+ * the oracle takes the same mathematical steps in their plainest form: q is
+ * the nd prefix sum of p (the inverse of the Lorenzo residual), formed here
+ * as one cumulative sum along each axis in turn (x, then y, then z; the
+ * order does not matter for a separable sum), in 64-bit integers; then
+ * s1 = sum q and s2 = sum q^2 exactly (128 bits) and var as Eq. (var) with
+ * N - 1, rounded once from (n s2 - s1^2) / (n (n - 1)) Delta^2. */
 int or_lz_var_p(const int32_t *p, uint32_t ndim, const uint64_t *dims, double quantum, int64_t *n_out,
                 int64_t *s1, uint64_t *s2_lo, int64_t *s2_hi, double *var) {
   if (!p || !dims || ndim < 1 || ndim > 3) return OR_ERR_ARG;
   uint64_t d[3];
   dims3_from(ndim, dims, d);
-  const uint64_t Y = d[1], X = d[2];
-  int64_t *plane = (int64_t *)calloc(Y * X, sizeof(int64_t));
-  int64_t *col = (int64_t *)calloc(X, sizeof(int64_t));
-  if (!plane || !col) { free(plane); free(col); return OR_ERR_ARG; }
+  const uint64_t Z = d[0], Y = d[1], X = d[2], n = Z * Y * X;
+  int64_t *q = (int64_t *)malloc(n * sizeof(int64_t));
+  if (!q) return OR_ERR_ARG;
+  for (uint64_t i = 0; i < n; i++) q[i] = p[i];
+  for (uint64_t z = 0; z < Z; z++) /* along x */
+    for (uint64_t y = 0; y < Y; y++)
+      for (uint64_t x = 1; x < X; x++) q[(z * Y + y) * X + x] += q[(z * Y + y) * X + x - 1];
+  for (uint64_t z = 0; z < Z; z++) /* along y */
+    for (uint64_t y = 1; y < Y; y++)
+      for (uint64_t x = 0; x < X; x++) q[(z * Y + y) * X + x] += q[(z * Y + y - 1) * X + x];
+  for (uint64_t z = 1; z < Z; z++) /* along z */
+    for (uint64_t y = 0; y < Y; y++)
+      for (uint64_t x = 0; x < X; x++) q[(z * Y + y) * X + x] += q[((z - 1) * Y + y) * X + x];
   int64_t a1 = 0;
   __int128 a2 = 0;
-  for (uint64_t z = 0; z < d[0]; z++) {
-    for (uint64_t x = 0; x < X; x++) col[x] = 0;
-    for (uint64_t y = 0; y < Y; y++) {
-      int64_t pref = 0;
-      for (uint64_t x = 0; x < X; x++) {
-        pref += p[(z * Y + y) * X + x];
-        col[x] += pref;
-        plane[y * X + x] += col[x];
-        const int64_t q = plane[y * X + x];
-        a1 += q;
-        a2 += (__int128)q * q;
-      }
-    }
+  for (uint64_t i = 0; i < n; i++) {
+    a1 += q[i];
+    a2 += (__int128)q[i] * q[i];
   }
-  free(plane);
-  free(col);
-  const int64_t n = (int64_t)(d[0] * Y * X);
-  *n_out = n;
+  free(q);
+  *n_out = (int64_t)n;
   *s1 = a1;
   *s2_lo = (uint64_t)a2;
   *s2_hi = (int64_t)(a2 >> 64);

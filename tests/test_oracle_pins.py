@@ -278,6 +278,44 @@ def test_error_bound_adversarial(dtype, rel):
     assert _exact_abs_err_ok(x, xh, eps)
 
 
+# Hand-derived quanta (Sec. III-A bound, reading R3: Delta = 2 (eps - m ulp(max|x| + eps)),
+# m = 1 for binary32, 8 for binary64).  Each ulp is fixed by the binade of
+# max|x| + eps, worked out by hand: [4, 8) has binary32 spacing 2^-21 and
+# binary64 spacing 2^-50; [2, 4) has 2^-22 and 2^-51.  A margin off by a
+# binade, a wrong multiplier m, or max|x| taken from the wrong end of the
+# range changes Delta and fails one of these.
+QUANTUM_PINS = [
+    # (vmin, vmax, rel, dtype, eps, ulp multiple subtracted from eps)
+    (-3.0, 5.0, 1e-4, 1, 8.0 * 1e-4, 2.0 ** -21),            # 5.0008 in [4, 8)
+    (-3.0, 5.0, 1e-4, 2, 8.0 * 1e-4, 8 * 2.0 ** -50),        # binary64: m = 8
+    (-3.0, 3.99, 1e-4, 1, 6.99 * 1e-4, 2.0 ** -22),          # 3.990699 in [2, 4)
+    (-3.0, 3.9999, 1e-4, 1, 6.9999 * 1e-4, 2.0 ** -21),      # 4.00059999 crosses into [4, 8)
+    (-6.0, 1.0, 1e-3, 1, 7.0 * 1e-3, 2.0 ** -21),            # max|x| is |vmin| = 6: 6.007 in [4, 8)
+    (-6.0, 1.0, 1e-3, 2, 7.0 * 1e-3, 8 * 2.0 ** -50),
+]
+
+
+@pytest.mark.parametrize("vmin,vmax,rel,dtype,eps_want,margin", QUANTUM_PINS)
+def test_quantum_exact_hand_derived(vmin, vmax, rel, dtype, eps_want, margin):
+    eps, quantum = oracle.quant_params(vmin, vmax, rel, True, dtype)
+    # eps = rel (max - min) in binary64: the range is an exact small number,
+    # so only the product with rel rounds
+    assert eps == rel * (vmax - vmin)
+    assert eps == pytest.approx(eps_want, rel=1e-15)
+    assert quantum == 2.0 * (eps - margin)
+
+
+def test_signed_zero_extremes_are_canonical():
+    """A field whose extreme is zero stores +0.0 whichever zero the scan met
+    first, so the header bytes do not depend on the order of -0.0 / +0.0."""
+    a = np.array([-0.0, 0.0, 1.0, 2.0] * 8, dtype=np.float32)
+    b = np.array([0.0, -0.0, 1.0, 2.0] * 8, dtype=np.float32)
+    ba, bb = oracle.compress(a, 1e-3), oracle.compress(b, 1e-3)
+    ha = oracle.read_header(ba)
+    assert ha.vmin == 0.0 and np.signbit(ha.vmin) == False  # noqa: E712
+    assert np.array_equal(ba, bb)
+
+
 def test_margin_is_needed_for_binary32_ties():
     """Without the margin (quantum exactly 2*eps) rounding the decompressed
     value to binary32 breaks the bound on tie inputs: the reading that
