@@ -295,6 +295,26 @@ int hsz_op_fused(const void *d_c, const hsz_header *h, int via, int op, int axis
                  const hsz_box *h_box, void *d_result, uint64_t cap, void *d_workspace,
                  uint64_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, serving loops that must not call the allocator): hsz_op_fused
+ * with its workspace taken from a fixed device array the library owns, of
+ * HSZ_NOALLOC_SCRATCH_BYTES per device, held until the process ends.  The
+ * caller passes the stream, the result buffer and, optionally, d_status
+ * (device, 4-byte aligned, or NULL): after the operation the call's status
+ * word (HSZ_OK or the first data-dependent error) is copied there.  The
+ * call itself never allocates or frees memory; its first call on a device
+ * resolves the array's device address (with that device current).
+ * HSZ_ERR_CAPACITY when hsz_op_workspace(h, op) exceeds the array (e.g. a
+ * gradient of more than about 8.4 million blocks, or fused HSZp-nd routes
+ * beyond about 4 million points).  Every call on a device shares that
+ * device's array and leaves its contents behind: calls that overlap on one
+ * device (different streams, or host threads) race and must be serialised
+ * by the caller. */
+#define HSZ_NOALLOC_SCRATCH_BYTES (16u << 20)
+int hsz_op_fused_noalloc(const void *d_c, const hsz_header *h, int via, int op, int axis,
+                         const hsz_box *h_box, void *d_result, uint64_t cap, int *d_status,
+                         void *stream);
+
 /* ---- out of core: a field as compressed slabs in host memory (Alg. 3) -----
  * h_slabs[k] (HOST memory; pinned memory lets the copies overlap) holds the
  * stream of slab k, hdrs[k] its header: consecutive ranges of the field's

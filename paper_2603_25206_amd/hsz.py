@@ -36,6 +36,7 @@ _OPS = {"mean": MEAN, "var": VAR, "var_mt": VAR_MT, "deriv": DERIV, "gradmag": G
         "divergence": DIVERGENCE, "curl": CURL}
 _STAGES = {"meta": META, "delta": DELTA, "quant": QUANT, "float": FLOAT}
 _STATS = (MEAN, VAR, VAR_MT)
+NOALLOC_SCRATCH_BYTES = 16 << 20  # HSZ_NOALLOC_SCRATCH_BYTES: the fixed workspace of op_fused_noalloc
 
 
 class HszError(RuntimeError):
@@ -92,7 +93,7 @@ EXPORTS = (
     "hsz_batch_workspace", "hsz_batch_run", "hsz_plan_create", "hsz_plan_update", "hsz_plan_launch",
     "hsz_plan_destroy", "hsz_block_index_bytes", "hsz_block_index", "hsz_vector_workspace",
     "hsz_vector_op_on_stage", "hsz_vector_op_fused", "hsz_compress_range", "hsz_extremes_workspace",
-    "hsz_extremes", "hsz_ooc_workspace", "hsz_ooc_op", "hsz_compress_workspace_mode",
+    "hsz_extremes", "hsz_ooc_workspace", "hsz_ooc_op", "hsz_compress_workspace_mode", "hsz_op_fused_noalloc",
 )
 
 _lib = None
@@ -127,6 +128,8 @@ def load(path: str = LIB_PATH):
                                   u64, P]),
         "hsz_op_fused": (i32, [P, ctypes.POINTER(Header), i32, i32, i32, ctypes.POINTER(Box), P, u64, P, u64,
                                P]),
+        "hsz_op_fused_noalloc": (i32, [P, ctypes.POINTER(Header), i32, i32, i32, ctypes.POINTER(Box), P, u64,
+                                       P, P]),
         "hsz_batch_workspace": (i32, [ctypes.POINTER(Work), i32, pu64]),
         "hsz_batch_run": (i32, [ctypes.POINTER(Work), i32, ctypes.POINTER(Tuning), P, u64, P]),
         "hsz_plan_create": (i32, [ctypes.POINTER(Work), i32, ctypes.POINTER(Tuning), P, u64, P,
@@ -437,6 +440,26 @@ def op_fused(c: Compressed, via, op, axis: int = 0, box=None, stream=None, check
                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream(stream))),
            "op_fused")
     return _finish(buf, shape, h, op, ws, stream, check, raw)
+
+
+def op_fused_noalloc(c: Compressed, via, op, axis: int = 0, box=None, stream=None, out: torch.Tensor | None = None,
+                     status: torch.Tensor | None = None):
+    """op_fused without a caller workspace: the library's fixed per-device
+    scratch array serves as the workspace, so the call allocates nothing
+    (pass 'out' and 'status' to keep this wrapper allocation-free too).
+    Returns the raw result buffer; 'status' (int32 on the device) receives
+    the call's status word.  Calls on one device must not overlap."""
+    lib = load()
+    via = _STAGES.get(via, via)
+    op = _OPS.get(op, op)
+    h = c.header
+    dev = c.data.device
+    buf = _result_buffer(h, op, box, dev)[0] if out is None else out
+    st_ptr = ctypes.c_void_p(status.data_ptr()) if status is not None else None
+    _check(lib.hsz_op_fused_noalloc(ctypes.c_void_p(c.data.data_ptr()), ctypes.byref(h), via, op, axis,
+                                    _box(box, h.ndim), ctypes.c_void_p(buf.data_ptr()), buf.numel(), st_ptr,
+                                    ctypes.c_void_p(_stream(stream))), "op_fused_noalloc")
+    return buf
 
 
 # ---- vector fields -------------------------------------------------------------------

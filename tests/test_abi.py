@@ -295,3 +295,16 @@ def test_compress_workspace_per_mode(lib):
     one = (ctypes.c_int64 * 1)(1000)
     assert lib.hsz_compress_workspace_mode(1, one, 32, hsz.FLAG_LORENZO, ctypes.byref(v)) == hsz.ERR_UNSUPPORTED
     assert lib.hsz_compress_workspace_mode(1, one, 32, hsz.FLAG_INTER_BLOCK, ctypes.byref(v)) == 0
+
+
+def test_noalloc_validation_before_any_launch(lib):
+    fake = ctypes.c_void_p(0x10000)
+    x = np.linspace(0, 1, 5000).astype(np.float32)
+    h = hsz.read_header(oracle.compress(x, 1e-3))
+    hp = ctypes.byref(h)
+    assert lib.hsz_op_fused_noalloc(fake, None, hsz.QUANT, hsz.VAR, 0, None, fake, 48, None, None) == \
+        hsz.ERR_INVALID_ARG
+    assert lib.hsz_op_fused_noalloc(fake, hp, hsz.QUANT, 9, 0, None, fake, 48, None, None) == hsz.ERR_INVALID_ARG
+    # the status output must be a 4-byte aligned device word
+    assert lib.hsz_op_fused_noalloc(fake, hp, hsz.QUANT, hsz.VAR, 0, None, fake, 48, ctypes.c_void_p(0x10002),
+                                    None) == hsz.ERR_INVALID_ARG
