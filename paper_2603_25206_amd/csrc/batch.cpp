@@ -24,7 +24,11 @@ namespace {
 
 using namespace hsz_abi;
 
-constexpr int kVariants = 48;  // S(2) x via(2) x op(2) x dtype(2) x shared-statistics mode(3)
+// S(2) x via(2) x op(2) x dtype(2) x shared-statistics mode(3) for the general
+// tile, then S(2) x column tile(2) x shared-statistics mode(2) for the
+// four-column binary32 magnitude tile (grad4.hip)
+constexpr int kVariantsGeneral = 48;
+constexpr int kVariants = kVariantsGeneral + 8;
 constexpr uint64_t kAlign = 256;
 
 uint64_t up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -32,6 +36,8 @@ uint64_t up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 int variant_of(int S, int via, int op, int dtype, int acc) {
   return 16 * acc + (((S == 64) << 3) | ((via == HSZ_FLOAT) << 2) | ((op == HSZ_GRADMAG) << 1) | (dtype == HSZ_F64));
 }
+int variant_q4(int S, int txl, int acc) { return kVariantsGeneral + 4 * (S == 64) + 2 * (txl == 512) + acc; }
+bool is_q4(int g) { return g >= kVariantsGeneral; }
 
 struct Layout {
   uint64_t counts = 0;                   // int64[2 * (2 + kVariants + 1)]
@@ -148,7 +154,9 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
     const Item& it = items[i];
     if (it.kind == 0) order_stats[it.S == 64].push_back(i);
     else {
-      order_grad[variant_of(it.S, it.via, it.op, it.dtype, acc_mode[i])].push_back(i);
+      const bool q4 = acc_mode[i] != 2 && hsz::q4_eligible(it.v, it.via, it.op, it.t.d, it.t.box);
+      order_grad[q4 ? variant_q4(it.S, hsz::q4_txl(it.t.box), acc_mode[i])
+                    : variant_of(it.S, it.via, it.op, it.dtype, acc_mode[i])].push_back(i);
       if (!it.index) grads.push_back(i);  // jobs that need an index built here
     }
   }
@@ -245,7 +253,7 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
       const hsz::GradJob& J = gj[order_grad[g][k]];
       ((hsz::GradJob*)at(L.grad_jobs[g]))[k] = J;
       ((int64_t*)at(L.grad_start[g]))[k] = tiles;
-      tiles += hsz::grad_tiles(J.b, J.tz);
+      tiles += is_q4(g) ? hsz::q4_tiles(J.b, J.tz, J.d) : hsz::grad_tiles(J.b, J.tz);
       km = std::max(km, J.kmax);
     }
     counts[2 * cslot_grad(g)] = (int64_t)order_grad[g].size();
@@ -304,6 +312,17 @@ int enqueue(const Built& B, uint8_t* d_ws, const hsz_tuning& tune, hipStream_t s
   }
   for (int g = 0; g < kVariants; ++g) {
     if (B.n_grad[g] == 0) continue;
+    if (is_q4(g)) {
+      // persistent: as many workgroups as fit at once (two per compute unit by
+      // their LDS), at most the tuning's count
+      const int q = g - kVariantsGeneral, per_cu = std::min(2, tune.grad_groups_per_cu > 0 ? tune.grad_groups_per_cu : 2);
+      if ((e = hsz::launch_batch_gradmag_q4(32, (q & 2) ? 512 : 256, q & 1,
+                                            (const hsz::GradJob*)(d_ws + L.grad_jobs[g]),
+                                            (const int64_t*)(d_ws + L.grad_start[g]), counts + 2 * cslot_grad(g),
+                                            std::max(1, cus * per_cu), status, s)) != hipSuccess)
+        return hip_fail(e);
+      continue;
+    }
     const int S = ((g >> 3) & 1) ? 64 : 32, via = ((g >> 2) & 1) ? HSZ_FLOAT : HSZ_QUANT;
     const int op = ((g >> 1) & 1) ? HSZ_GRADMAG : HSZ_DERIV, dtype = (g & 1) ? HSZ_F64 : HSZ_F32, acc = g >> 4;
     if ((e = hsz::launch_batch_grad(S, via, op, dtype, acc, (const hsz::GradJob*)(d_ws + L.grad_jobs[g]),

@@ -1012,6 +1012,14 @@ hipError_t launch_grad_fused(const StreamView& v, int via, int op, int axis3, co
     if (op != 3 || axis3 != 2) return hipErrorNotSupported;
     return fast_delta<true>(nullptr, v, t, result, status, s);
   }
+  if (q4_eligible(v, via, op, t.d, t.box)) {
+    uint16_t* rel = (uint16_t*)(ws + kGradIndexOff);
+    hipError_t e = launch_block_index(v, rel, s);
+    if (e != hipSuccess) return e;
+    const int tz = q4_tz(t.box);
+    GradJob job{v, rel, t.d, t.box, 0, tz, kmax_for(v), 0.5 * v.quantum, result};
+    return launch_gradmag_q4(job, status, s);
+  }
   return v.block == 32 ? fused_by_via<32>(v, via, op, axis3, t, result, ws, s)
                        : fused_by_via<64>(v, via, op, axis3, t, result, ws, s);
 }

@@ -1,0 +1,528 @@
+// grad4.hip -- the binary32 gradient magnitude (Eq. (derivatives), Sec. V-B)
+// straight from the compressed stream through D_q, laid out for the common
+// case of the quantized route: blocks of 32, max|q| < 8192 (every numerator
+// below 2^15, the squared sum exact in 32 bits) and rows whose blocks start
+// on 32-column boundaries (the field's width and the box's first column
+// multiples of 32, the box width a multiple of 4).  Other streams and boxes take
+// the general tile of grad.hip; both give the same values bit for bit.
+//
+// A workgroup of 256 threads owns a tile of TXL columns x kTY rows and marches
+// along z (the blockwise window of Alg. 3 with the planes as its blocks).
+//  * Every stencil lane owns 4 consecutive columns x 4 rows: one 16-byte LDS
+//    read per row gives a row's four values (x-neighbours inside the lane in
+//    registers), one 16-byte store writes four results.
+//  * The decoded planes are double-buffered in LDS, so one barrier per plane
+//    separates "plane p+1 decoded" from "plane p read".  A decode thread owns
+//    one block of one decoded row (rows y0-1 .. y0+kTY, the blocks covering
+//    columns x0-1 .. x0+TXL); its payload words are staged in a private LDS
+//    column, so staging needs no barrier.  The two plane buffers and the
+//    staging columns take under 64 KiB, two workgroups per compute unit.  While the stencil of plane p runs,
+//    the payload of plane p+2 and the metadata of plane p+3 are in flight.
+//  * A block is decoded two slots per 32-bit window (2 w <= 28 bits), and four
+//    decoded slots go to LDS in one 16-byte write.  A row of the plane buffer
+//    holds one 4-word pad per 32 columns, which keeps both the decode writes
+//    and the stencil reads free of bank conflicts.
+//  * z-neighbours live in registers: the loop is unrolled by three so the
+//    planes p-2, p-1, p rotate through three register sets without copies.
+//  * Domain edges use ghost values q_{-1} = 2 q_0 - q_1 (and the mirror at the
+//    far end), formed in registers: the central numerator then equals the
+//    one-sided 2 (q_1 - q_0) exactly in integers (a length-1 axis adds 0).
+//  * ACC (batches): the exact sums of q and q^2 over the tile's own elements,
+//    for statistics sharing this decode; per plane in 32 bits (16 values of
+//    |q| < 8192), then widened.
+#include "hsz_device.hpp"
+#include "hsz_launch.hpp"
+
+namespace hsz {
+
+namespace {
+
+constexpr int kQ4Threads = 256;
+constexpr int kQ4MaxW = 14;  // |p| < 2^14 when max|q| < 8192
+constexpr int kQ4NS = 256;   // staging columns (words between two rows of a column)
+
+typedef __attribute__((address_space(3))) int lds_i32;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef int i4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int S, int TXL>
+struct Q4 {
+  static constexpr int kG = TXL / 4;            // stencil lanes per row group
+  static constexpr int kRG = kQ4Threads / kG;   // row groups (one or more whole waves each)
+  static constexpr int kRY = 4;                 // rows per stencil lane
+  static constexpr int kTY = kRG * kRY;         // output rows per tile
+  static constexpr int kRows = kTY + 2;         // decoded rows (one halo row each side)
+  static constexpr int kNBR = TXL / S + 2;      // blocks per decoded row, at most
+  static constexpr int kItems = kRows * kNBR;   // decode items
+  static constexpr int kIPW = (kItems + 3) / 4; // decode items per wave
+  static constexpr int kPitch = 36 * ((TXL + 2 * S) / 32);  // words per LDS row
+  static constexpr int kPlane = kRows * kPitch;             // words per plane buffer
+  static constexpr int kPF = (S / 32) * (1 + kQ4MaxW) + 1;  // words staged per block (+ the spare a window reads)
+  static constexpr int kStageOff = (2 * kPlane + 63) / 64 * 64;  // 256-byte aligned: row offsets fold into ds_read2st64
+  static constexpr int kLdsWords = kStageOff + kPF * kQ4NS;
+  static_assert(S == 32 && kPF == 16, "blocks of 32: at most 15 payload words");
+  static_assert(kIPW <= kWave && 3 * kIPW + kWave <= kQ4NS, "one staging column per item, spares for idle lanes");
+  static_assert(kG % kWave == 0 && kRG * kG == kQ4Threads, "whole waves per row group");
+  static_assert(kStageOff * 4 < 65536, "staging rows addressed with instruction offsets");
+};
+
+// LDS word of extended column e of a row (e = x - x0 + S, so the block that
+// holds column x0 - 1 starts at e = 0): one 4-word pad per 32 columns
+__device__ __forceinline__ int q4w(int e) { return 36 * (e >> 5) + (e & 31); }
+
+// buffer descriptor of 'bytes' bytes at 'base': loads past the end return 0
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t q4_rsrc(const void* base, uint64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(uint32_t)bytes, 0x00020000);
+}
+
+// Decode one staged block (payload words in LDS column 'col', rows kQ4NS
+// words apart) into row[q4w(e0 + j)], e0 a multiple of 32: two slots per
+// 32-bit window, four slots per 16-byte LDS write.  gl / gr: also write the
+// ghost column before the row (2 q_0 - q_1) / after it (2 q_31 - q_30).
+template <int S>
+__device__ __forceinline__ void decode_q4(const lds_u32* col, int w, int q0, lds_i32* row, int e0, bool gl,
+                                          bool gr) {
+  const uint32_t sg0 = col[0];
+  const lds_u32* mag = col + kQ4NS;
+  int q = q0;
+  uint32_t uw = (uint32_t)w, pos = 0;
+  const uint32_t w2 = 2u * uw;
+  int first[2] = {0, 0}, last[2] = {0, 0};
+#pragma unroll
+  for (int g = 0; g < S; g += 8) {
+    // bit positions j w of the four pairs, by additions (the empty asm keeps
+    // the compiler from folding them into multiplies or hoisting later groups)
+    asm volatile("" : "+v"(pos));
+    uint32_t lo[4], hi[4], pp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      pp[u] = pos;
+      pos += w2;
+      uint32_t k = pp[u] >> 5;
+      asm("" : "+v"(k));  // one shift-add per address
+      const lds_u32* a = mag + k * kQ4NS;
+      lo[u] = a[0];
+      hi[u] = a[kQ4NS];
+    }
+    int vals[8];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = g + 2 * u;
+      const uint32_t win = __builtin_amdgcn_alignbit(hi[u], lo[u], pp[u]);
+      const uint32_t m0 = __builtin_amdgcn_ubfe(win, 0u, uw);
+      const uint32_t m1 = __builtin_amdgcn_ubfe(win, uw, uw);
+      const int s0 = __builtin_amdgcn_sbfe((int)sg0, (uint32_t)j, 1u);
+      const int s1 = __builtin_amdgcn_sbfe((int)sg0, (uint32_t)(j + 1), 1u);
+      q = (int)((m0 ^ (uint32_t)s0) + (uint32_t)q) - s0;  // q += (m ^ s) - s
+      vals[2 * u] = q;
+      q = (int)((m1 ^ (uint32_t)s1) + (uint32_t)q) - s1;
+      vals[2 * u + 1] = q;
+    }
+    *(__attribute__((address_space(3))) i4*)(row + q4w(e0 + g)) = i4{vals[0], vals[1], vals[2], vals[3]};
+    *(__attribute__((address_space(3))) i4*)(row + q4w(e0 + g + 4)) = i4{vals[4], vals[5], vals[6], vals[7]};
+    if (g == 0) { first[0] = vals[0]; first[1] = vals[1]; }
+    if (g == S - 8) { last[0] = vals[7]; last[1] = vals[6]; }
+  }
+  if (gl) row[q4w(e0 - 1)] = 2 * first[0] - first[1];
+  if (gr) row[q4w(e0 + S)] = 2 * last[0] - last[1];
+}
+
+template <int S, int TXL, int ACC>
+__device__ __forceinline__ void gradmag_tile_q4(const GradJob& job, int64_t tile, uint32_t* smem_g, int* status) {
+  using L = Q4<S, TXL>;
+  constexpr int P = L::kPitch;
+  const StreamView& v = job.v;
+  const Dims3 d = job.d;
+  const Box3 b = job.b;
+  const int tz = job.tz, kmax = job.kmax;
+  const float h = (float)job.halfq;
+  lds_u32* const smem = (lds_u32*)smem_g;
+  lds_i32* const planes = (lds_i32*)smem;
+  lds_u32* const stage = smem + L::kStageOff;
+  const int t = threadIdx.x;
+
+  // bounds-checked views of the stream's sections and of the result
+  // metadata sections through one view of the stream (section offsets as the
+  // scalar offset; every metadata index is in range), the payload through its
+  // own (words past its end read 0)
+  const __amdgpu_buffer_rsrc_t r_meta = q4_rsrc(v.base, (const uint8_t*)v.payload - v.base);
+  const int so_w = (int)(v.width - v.base), so_q0 = (int)((const uint8_t*)v.q0 - v.base);
+  const int so_co = (int)((const uint8_t*)v.chunk_off - v.base);
+  const __amdgpu_buffer_rsrc_t r_pay = q4_rsrc(v.payload, v.payload_words * 4);
+  const __amdgpu_buffer_rsrc_t r_rel = q4_rsrc(job.rel, 2 * (uint64_t)v.nb);
+  const __amdgpu_buffer_rsrc_t r_out = q4_rsrc(job.out, 4 * (uint64_t)((b.z1 - b.z0) * (b.y1 - b.y0) * (b.x1 - b.x0)));
+
+  const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0;
+  const int64_t ntx = (bx + TXL - 1) / TXL, nty = (by + L::kTY - 1) / L::kTY;
+  int64_t blk = tile;
+  const int64_t tx = blk % ntx;
+  blk /= ntx;
+  const int64_t ty = blk % nty;
+  const int64_t tzi = blk / nty;
+  const int64_t x0 = b.x0 + tx * TXL, y0 = b.y0 + ty * L::kTY, z0 = b.z0 + tzi * tz;
+  const int xs = (int)min((int64_t)TXL, b.x1 - x0), ys = (int)min((int64_t)L::kTY, b.y1 - y0);
+  const int64_t zs = min((int64_t)tz, b.z1 - z0);
+  const int64_t za = max((int64_t)0, z0 - 1), zb = min(d.z, z0 + zs + 1);
+  const uint32_t bpr = (uint32_t)(d.x / S);  // blocks per field row (d.x is a multiple of S)
+
+  // ---- decode item of this thread: the items are spread evenly over the four
+  // waves, and consecutive lanes own consecutive staging columns
+  const int lane = t % kWave;
+  const int item = (t / kWave) * L::kIPW + lane;
+  const int dr = item / L::kNBR, dk = item % L::kNBR;
+  const int64_t dy = y0 - 1 + dr;
+  const int64_t fb = x0 > 0 ? x0 / S - 1 : 0;      // first block of the row range
+  const int64_t lb = min((int64_t)bpr - 1, (x0 + xs) / S);  // last block
+  const bool decoder = lane < L::kIPW && item < L::kItems && dr <= ys + 1 && dy >= 0 && dy < d.y && fb + dk <= lb;
+  const int e0 = (int)((fb + dk) * S - x0 + S);     // extended column of slot 0
+  const bool gl = decoder && x0 == 0 && dk == 0;    // ghost column before the field's first column
+  const bool gr = decoder && x0 + xs == d.x && fb + dk == (int64_t)bpr - 1;  // after its last
+  const int drow = dr * P;
+  // staging column: the item's own; idle lanes write their (unused) words to
+  // columns no decode item owns
+  lds_u32* const col = stage + (lane < L::kIPW ? item : 4 * L::kIPW + (lane - L::kIPW));
+  // block of this item in plane za, and the step from one plane to the next
+  const uint32_t bk0 = decoder ? (uint32_t)((za * d.y + dy) * (int64_t)bpr + fb + dk) : 0u;
+  const uint32_t pstride = (uint32_t)(d.y * (int64_t)bpr);
+
+  struct Meta {
+    int w, q0, words;
+    uint32_t off;
+    bool valid;
+  };
+  auto meta_of = [&](int64_t p) {
+    Meta m;
+    m.valid = decoder && p < zb;
+    const uint32_t bk = m.valid ? bk0 + (uint32_t)(p - za) * pstride : 0u;
+    m.w = (int)__builtin_amdgcn_raw_buffer_load_b8(r_meta, bk, so_w, 0);
+    m.q0 = (int)__builtin_amdgcn_raw_buffer_load_b32(r_meta, 4 * bk, so_q0, 0);
+    const uint32_t rel = __builtin_amdgcn_raw_buffer_load_b16(r_rel, 2 * bk, 0, 0);
+    const uint32_t cl = __builtin_amdgcn_raw_buffer_load_b32(r_meta, 8 * (bk / kChunkBlocks), so_co, 0);
+    m.off = cl + rel;  // payload words stay below 2^29 (the eligibility test)
+    m.words = 0;
+    return m;
+  };
+  auto check = [&](Meta& m) {
+    m.words = m.valid ? block_words<S>(m.w) : 0;
+    if (m.valid && (m.w > kQ4MaxW || m.words > kmax || (uint64_t)m.off + (uint64_t)m.words > v.payload_words)) {
+      record_status(status, kErrBadStream);
+      m.w = 0;
+      m.words = 0;
+    }
+  };
+  // the block's first kPF payload words (loads past the payload return 0;
+  // an invalid block reads nothing) into registers, then to the staging column
+  auto fetch = [&](const Meta& m, uint32_t (&pw)[L::kPF]) {
+    const uint32_t base = m.words ? 4 * m.off : 0x80000000u;
+#pragma unroll
+    for (int k = 0; k < L::kPF; ++k) pw[k] = __builtin_amdgcn_raw_buffer_load_b32(r_pay, base + 4 * k, 0, 0);
+  };
+  auto stage_words = [&](const uint32_t (&pw)[L::kPF]) {
+#pragma unroll
+    for (int k = 0; k < L::kPF; ++k) col[k * kQ4NS] = pw[k];
+  };
+
+  // ---- stencil lanes: 4 columns x 4 rows; the row group is wave-uniform
+  const int rg = __builtin_amdgcn_readfirstlane(t / L::kG);
+  const int c4 = 4 * (t % L::kG);
+  const bool active = c4 < xs;
+  const int cw = q4w(S + c4), cwm = q4w(S + c4 - 1), cwp = q4w(S + c4 + 4);
+  const bool top = y0 == 0 && rg == 0;                          // row 0 of the tile: ghost above the field
+  const int kb = (y0 + ys == d.y) ? ys + 1 - L::kRY * rg : -1;  // lane-row of the ghost below, if any
+  const bool y2 = d.y >= 2, z2 = d.z >= 2;
+  int nrows = ys - L::kRY * rg;                                 // output rows of the row group
+  nrows = nrows < 0 ? 0 : (nrows > L::kRY ? L::kRY : nrows);
+  // byte offsets in the result: this lane's columns, and the row group's first row
+  const uint32_t ocol = 4u * (uint32_t)((x0 - b.x0) + c4);
+  const int64_t orow0 = (y0 + L::kRY * rg - b.y0) * bx;
+
+  int Q[3][4][4];    // q of three consecutive planes (rotating roles)
+  uint32_t G[4][4];  // nx^2 + ny^2 of the previous plane
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Q[r][i][j] = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) G[i][j] = 0u;
+  int as1 = 0;
+  uint64_t as2 = 0;
+
+  // one output plane o from the numerators of plane o (G, nz); sums of its q
+  auto emit = [&](int64_t o, const int (&qo)[4][4], const int (&nz)[4][4]) {
+    const int64_t orow = ((o - b.z0) * by) * bx + orow0;
+    uint32_t s2p = 0;
+    int s1p = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i < nrows) {
+        f4 r;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t s = G[i][j] + (uint32_t)__mul24(nz[i][j], nz[i][j]);
+          r[j] = __builtin_amdgcn_sqrtf((float)s) * h;
+        }
+        if (active)
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4, r), r_out, ocol,
+                                                 (int)(4 * (orow + i * bx)), 0);
+        if constexpr (ACC == 1) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            s1p += qo[i][j];
+            s2p += (uint32_t)__mul24(qo[i][j], qo[i][j]);
+          }
+        }
+      }
+    }
+    if constexpr (ACC == 1) {
+      if (active) {
+        as1 += s1p;
+        as2 += s2p;
+      }
+    }
+  };
+
+  // plane p is in buffer 'buf'; emits plane p - 1.  C: register set of plane p.
+  auto stencil = [&](auto RC, int64_t p, const lds_i32* buf) {
+    constexpr int C = decltype(RC)::value, M1 = (C + 2) % 3, M2 = (C + 1) % 3;
+    const lds_i32* rb = buf + L::kRY * rg * P;
+    int vv[6][4];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const i4 a = *(const __attribute__((address_space(3))) i4*)(rb + k * P + cw);
+      vv[k][0] = a.x; vv[k][1] = a.y; vv[k][2] = a.z; vv[k][3] = a.w;
+    }
+    int xm[4], xp[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      xm[i] = rb[(i + 1) * P + cwm];
+      xp[i] = rb[(i + 1) * P + cwp];
+    }
+    if (top) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) vv[0][j] = y2 ? 2 * vv[1][j] - vv[2][j] : vv[1][j];
+    }
+    if (kb >= 2 && kb <= 5) {
+#pragma unroll
+      for (int k = 2; k < 6; ++k)
+        if (k == kb) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) vv[k][j] = y2 ? 2 * vv[k - 1][j] - vv[k - 2][j] : vv[k - 1][j];
+        }
+    }
+    const int64_t o = p - 1;
+    if (o == 0) {  // the field's first plane: ghost plane q_{-1} = 2 q_0 - q_1 (q_0 on a length-1 axis)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Q[M2][i][j] = z2 ? 2 * Q[M1][i][j] - vv[i + 1][j] : Q[M1][i][j];
+    }
+    if (o >= z0 && o < z0 + zs) {
+      int nz[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) nz[i][j] = vv[i + 1][j] - Q[M2][i][j];
+      emit(o, Q[M1], nz);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int qc = vv[i + 1][j];
+        const int nx = (j < 3 ? vv[i + 1][j + 1] : xp[i]) - (j > 0 ? vv[i + 1][j - 1] : xm[i]);
+        const int ny = vv[i + 2][j] - vv[i][j];
+        G[i][j] = (uint32_t)__mul24(nx, nx) + (uint32_t)__mul24(ny, ny);
+        Q[C][i][j] = qc;
+      }
+    }
+  };
+
+  // one plane of the march: decode plane p+1 into the other buffer, fetch
+  // plane p+2's payload and plane p+3's metadata, stencil on plane p
+  Meta cur, nn;
+  auto step = [&](auto RC, int64_t p) {
+    const bool odd = ((p - za) & 1) != 0;
+    const lds_i32* buf = planes + (odd ? L::kPlane : 0);
+    lds_i32* nbuf = planes + (odd ? 0 : L::kPlane);
+    if (cur.valid) decode_q4<S>(col, cur.w, cur.q0, nbuf + drow, e0, gl, gr);
+    check(nn);
+    uint32_t pw[L::kPF];
+    fetch(nn, pw);
+    const Meta n3 = meta_of(p + 3);
+    stencil(RC, p, buf);
+    stage_words(pw);
+    cur = nn;
+    nn = n3;
+    __syncthreads();
+  };
+
+  // prologue: plane za decoded into buffer 0, plane za+1 staged, metadata of za+2 in flight
+  {
+    uint32_t pw[L::kPF];
+    cur = meta_of(za);
+    Meta nx = meta_of(za + 1);
+    check(cur);
+    fetch(cur, pw);
+    stage_words(pw);
+    if (cur.valid) decode_q4<S>(col, cur.w, cur.q0, planes + drow, e0, gl, gr);
+    check(nx);
+    fetch(nx, pw);
+    stage_words(pw);
+    cur = nx;
+    nn = meta_of(za + 2);
+    __syncthreads();
+  }
+
+  // the march, unrolled by three (plane p's values go to register set (p - za) % 3)
+  int64_t p = za;
+  for (; p + 3 <= zb; p += 3) {
+    step(std::integral_constant<int, 0>{}, p);
+    step(std::integral_constant<int, 1>{}, p + 1);
+    step(std::integral_constant<int, 2>{}, p + 2);
+  }
+  const int rem = (int)(zb - p);
+  if (rem >= 1) step(std::integral_constant<int, 0>{}, p);
+  if (rem >= 2) step(std::integral_constant<int, 1>{}, p + 1);
+
+  // the field's last plane has no plane after it: one-sided (0 if d.z = 1)
+  if (z0 + zs == zb) {
+    const int64_t o = zb - 1;
+    const int last = rem == 0 ? 2 : rem - 1;  // register set of plane zb - 1
+    auto tail = [&](auto RC) {
+      constexpr int C = decltype(RC)::value, M1 = (C + 2) % 3;
+      int nz[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) nz[i][j] = z2 ? 2 * (Q[C][i][j] - Q[M1][i][j]) : 0;
+      emit(o, Q[C], nz);
+    };
+    if (last == 0) tail(std::integral_constant<int, 0>{});
+    else if (last == 1) tail(std::integral_constant<int, 1>{});
+    else tail(std::integral_constant<int, 2>{});
+  }
+  if constexpr (ACC == 1) {
+    const int64_t cnt = active ? (int64_t)nrows * 4 * zs : 0;
+    U128 s2 = {as2, 0};
+    acc_add_wave((BatchAcc*)job.acc, (int64_t)as1, cnt, s2);
+  }
+}
+
+// Tiles handed out so that the workgroups of one XCD (launch order modulo 8)
+// take consecutive tiles -- neighbours in y, sharing their halo rows in that
+// XCD's L2 -- in every full round of the grid.
+__device__ __forceinline__ int64_t xcd_tile(int64_t base, int64_t total) {
+  const int64_t g = gridDim.x;
+  if ((g & 7) == 0 && base + g <= total) return base + (int64_t)(blockIdx.x & 7) * (g >> 3) + (blockIdx.x >> 3);
+  return base + blockIdx.x;
+}
+
+template <int S, int TXL>
+__global__ void __launch_bounds__(kQ4Threads, 2) k_gradmag_q4(GradJob job, int* status) {
+  extern __shared__ uint32_t smem[];
+  gradmag_tile_q4<S, TXL, 0>(job, xcd_tile(0, gridDim.x), smem, status);
+}
+
+template <int S, int TXL, int ACC>
+__global__ void __launch_bounds__(kQ4Threads, 2) k_batch_gradmag_q4(const GradJob* __restrict__ jobs,
+                                                                      const int64_t* __restrict__ tile_start,
+                                                                      const int64_t* __restrict__ counts, int* status) {
+  extern __shared__ uint32_t smem[];
+  const int n = (int)counts[0];
+  const int64_t total = counts[1];
+  for (int64_t base = 0; base < total; base += gridDim.x) {
+    const int64_t tile = xcd_tile(base, total);
+    if (tile >= total) break;
+    int lo = 0, hi = n - 1;  // last job whose first tile is <= tile
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (tile_start[mid] <= tile) lo = mid;
+      else hi = mid - 1;
+    }
+    const GradJob job = load_job(jobs, lo);
+    gradmag_tile_q4<S, TXL, ACC>(job, tile - tile_start[lo], smem, status);
+  }
+}
+
+template <int S, int TXL>
+size_t q4_lds() {
+  return (size_t)Q4<S, TXL>::kLdsWords * sizeof(uint32_t);
+}
+
+template <int S, int TXL>
+hipError_t run_q4(const GradJob& job, int* status, hipStream_t s) {
+  const size_t lds = q4_lds<S, TXL>();
+  const int64_t grid = q4_tiles(job.b, job.tz, job.d);
+  hipLaunchKernelGGL((k_gradmag_q4<S, TXL>), dim3((unsigned)grid), dim3(kQ4Threads), lds, s, job, status);
+  return hipGetLastError();
+}
+
+template <int S, int TXL>
+hipError_t batch_q4(int acc, const GradJob* jobs, const int64_t* tile_start, const int64_t* counts, int grid,
+                    int* status, hipStream_t s) {
+  const size_t lds = q4_lds<S, TXL>();
+  if (acc == 1)
+    hipLaunchKernelGGL((k_batch_gradmag_q4<S, TXL, 1>), dim3(grid), dim3(kQ4Threads), lds, s, jobs, tile_start,
+                       counts, status);
+  else
+    hipLaunchKernelGGL((k_batch_gradmag_q4<S, TXL, 0>), dim3(grid), dim3(kQ4Threads), lds, s, jobs, tile_start,
+                       counts, status);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Column tile width for a box: the whole row when the box is wider than 256
+// columns (no x-halo blocks), else 256.
+int q4_txl(const Box3& b) { return (b.x1 - b.x0) > 256 ? 512 : 256; }
+
+bool q4_eligible(const StreamView& v, int via, int op, const Dims3& d, const Box3& b) {
+  // 32-bit offsets: every section and the result below 2 GiB
+  return via == 3 && op == 4 && v.dtype == 1 && v.flags == 0 && v.max_abs_q < 8192u && v.block == 32 &&
+         d.x % 32 == 0 && b.x0 % 32 == 0 && (b.x1 - b.x0) % 4 == 0 && v.payload_words < (1ull << 29) &&
+         v.nb < (1ll << 29) && b.volume() < (1ll << 29);
+}
+
+int64_t q4_tiles(const Box3& b, int tz, const Dims3&) {
+  const int txl = q4_txl(b);
+  const int ty = txl == 512 ? Q4<32, 512>::kTY : Q4<32, 256>::kTY;
+  const int64_t ntx = (b.x1 - b.x0 + txl - 1) / txl, nty = (b.y1 - b.y0 + ty - 1) / ty;
+  return ntx * nty * ((b.z1 - b.z0 + tz - 1) / tz);
+}
+
+int q4_kmax(int S) { return (S / 32) * (1 + kQ4MaxW); }
+
+// Planes per tile for a single launch: long runs along z, but enough tiles to
+// fill the chip.
+int q4_tz(const Box3& b) {
+  const int txl = q4_txl(b);
+  const int ty = txl == 512 ? Q4<32, 512>::kTY : Q4<32, 256>::kTY;
+  const int64_t ntx = (b.x1 - b.x0 + txl - 1) / txl, nty = (b.y1 - b.y0 + ty - 1) / ty;
+  const int64_t bz = b.z1 - b.z0;
+  int64_t tz = bz;
+  while (tz > 8 && ntx * nty * ((bz + tz - 1) / tz) < 1024) tz = (tz + 1) / 2;
+  return (int)tz;
+}
+
+hipError_t launch_gradmag_q4(const GradJob& job, int* status, hipStream_t s) {
+  return q4_txl(job.b) == 512 ? run_q4<32, 512>(job, status, s) : run_q4<32, 256>(job, status, s);
+}
+
+hipError_t launch_batch_gradmag_q4(int S, int txl, int acc, const GradJob* jobs, const int64_t* tile_start,
+                                   const int64_t* counts, int grid, int* status, hipStream_t s) {
+  if (S != 32) return hipErrorInvalidValue;
+  return txl == 512 ? batch_q4<32, 512>(acc, jobs, tile_start, counts, grid, status, s)
+                    : batch_q4<32, 256>(acc, jobs, tile_start, counts, grid, status, s);
+}
+
+size_t batch_gradmag_q4_lds(int S, int txl) {
+  if (S != 32) return 0;
+  return txl == 512 ? q4_lds<32, 512>() : q4_lds<32, 256>();
+}
+
+}  // namespace hsz

@@ -154,6 +154,19 @@ int grad_tiles(const Box3& b, int tz);  // tiles of one fused-gradient job
 int grad_kmax(const StreamView& v);     // staging rows a stream needs
 int stats_kmax(const StreamView& v);
 
+// Binary32 gradient magnitude through D_q with four columns per lane
+// (grad4.hip): streams with max|q| < 8192 and boxes whose rows start on block
+// boundaries (q4_eligible); the same values as the general tile, bit for bit.
+bool q4_eligible(const StreamView& v, int via, int op, const Dims3& d, const Box3& b);
+int q4_txl(const Box3& b);                            // column tile: 256 or 512
+int64_t q4_tiles(const Box3& b, int tz, const Dims3& d);
+int q4_tz(const Box3& b);                             // planes per tile of a single launch
+int q4_kmax(int S);
+hipError_t launch_gradmag_q4(const GradJob& job, int* status, hipStream_t s);
+hipError_t launch_batch_gradmag_q4(int S, int txl, int acc, const GradJob* jobs, const int64_t* tile_start,
+                                   const int64_t* counts, int grid, int* status, hipStream_t s);
+size_t batch_gradmag_q4_lds(int S, int txl);
+
 // Derivative (op = 3, axis in the 3D view) or gradient magnitude (op = 4).
 hipError_t launch_grad_stage(const void* stage_buf, int stage, const StreamView& v, int op, int axis3,
                              const OpTarget& t, void* result, uint8_t* ws, hipStream_t s);

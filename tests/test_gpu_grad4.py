@@ -1,0 +1,133 @@
+"""GPU parity of the four-column gradient-magnitude tile (grad4.hip).
+
+Binary32 streams with blocks of 32 and max|q| < 8192 whose rows start on
+32-column boundaries take this tile (fused route, and gradient jobs of
+batches); everything else takes the general tile.  The fields below are
+eligible, with widths of one and several column tiles (256 and 512 wide
+tiles, ragged last tiles), rows and planes that leave ragged last tiles,
+axes of length 1 and 2 (ghost values at every edge), boxes aligned to 32
+columns (this tile) and not aligned (the general tile), and plans whose
+statistics are summed inside the tiles.  Bars (Sec. III-B Eq.
+(derivatives)): the magnitude within 1e-6 relative of the oracle's gradient
+of d' = q Delta per element, exact zeros stay zero; sums of q and q^2 exact;
+the batch equal to the single operation bit for bit.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU visible", allow_module_level=True)
+
+from paper_2603_25206_amd import hsz, synth  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+SHAPES = [
+    (20, 33, 512),    # one 512-wide column tile, ragged rows
+    (9, 17, 800),     # 512 + 288 columns
+    (5, 40, 256),     # one 256-wide tile
+    (3, 8, 96),       # narrow, z = 3
+    (1, 19, 544),     # one plane
+    (2, 1, 64),       # one row, two planes
+    (37, 12, 32),     # one block per row
+    (70, 320),        # 2D field (d.z = 1 in the kernel's view)
+]
+
+
+def sid(s):
+    return "x".join(map(str, s))
+
+
+@pytest.fixture(scope="module", params=SHAPES, ids=[sid(s) for s in SHAPES])
+def fld(request):
+    shape = request.param
+    say(f"[case] grad4 {sid(shape)}")
+    x = synth.make_field(synth.FieldSpec(shape, "f32", k=5, sigma=(2.0, 9.0), noise=1e-3, seed=sum(shape)))
+    ref = oracle.compress(x, 1e-3, rel=True, block=32)
+    c = hsz.compress(torch.from_numpy(x).to(DEV), 1e-3, rel=True, block=32)
+    torch.cuda.synchronize()
+    h = oracle.read_header(ref)
+    assert h.max_abs_q < 8192
+    q = oracle.decompress(ref, oracle.QUANT)
+    xh = oracle.dequantize64(q, h.quantum)
+    return dict(x=x, ref=ref, c=c, q=q, xh=xh, shape=shape)
+
+
+def _check(got, want, what):
+    got = got.cpu().numpy().astype(np.float64)
+    assert got.shape == want.shape, what
+    err = np.abs(got - want)
+    bad = err > 1e-6 * np.abs(want)
+    assert not bad.any(), (what, int(bad.sum()), float(err.max()))
+    assert np.all(got[want == 0] == 0), what
+
+
+def test_bytes(fld):
+    assert np.array_equal(fld["c"].to_bytes(), fld["ref"])
+
+
+def test_whole_field(fld):
+    _check(hsz.op_fused(fld["c"], hsz.QUANT, "gradmag"), oracle.gradmag(fld["xh"]), "whole")
+
+
+def _boxes(shape, aligned, rng, n=4):
+    out = []
+    for _ in range(n):
+        lo, hi = [], []
+        for k, s in enumerate(shape):
+            if k == len(shape) - 1 and aligned:
+                a = 32 * int(rng.integers(0, s // 32))
+                w = 4 * int(rng.integers(1, (s - a) // 4 + 1))
+                lo.append(a)
+                hi.append(a + w)
+            else:
+                a = int(rng.integers(0, s))
+                lo.append(a)
+                hi.append(int(rng.integers(a + 1, s + 1)))
+        out.append((tuple(lo), tuple(hi)))
+    return out
+
+
+@pytest.mark.parametrize("aligned", [True, False])
+def test_boxes(fld, aligned):
+    rng = np.random.default_rng(len(fld["shape"]) * 7 + aligned)
+    for box in _boxes(fld["shape"], aligned, rng):
+        _check(hsz.op_fused(fld["c"], hsz.QUANT, "gradmag", box=box), oracle.gradmag(fld["xh"], box), box)
+
+
+def test_batch_shared_statistics(fld):
+    c = fld["c"]
+    c.build_index()
+    rng = np.random.default_rng(3)
+    box = _boxes(fld["shape"], True, rng, 1)[0]
+    jobs = [hsz.Job(c, "mean", hsz.DELTA), hsz.Job(c, "var", hsz.QUANT), hsz.Job(c, "gradmag", hsz.QUANT),
+            hsz.Job(c, "var", hsz.QUANT, box=box), hsz.Job(c, "gradmag", hsz.QUANT, box=box)]
+    for tz in (0, 5):
+        plan = hsz.Plan(jobs, tune={"grad_tz": tz} if tz else None)
+        plan.launch()
+        mean, var, mag, bvar, bmag = plan.results()
+        plan.close()
+        n, s1, s2 = oracle.int_sums(fld["q"])
+        assert (mean["n"], mean["s1"]) == (n, s1)
+        assert (var["n"], var["s1"], var["s2"]) == (n, s1, s2)
+        sl = tuple(slice(a, b) for a, b in zip(*box))
+        assert (bvar["n"], bvar["s1"], bvar["s2"]) == oracle.int_sums(fld["q"][sl])
+        _check(mag, oracle.gradmag(fld["xh"]), "batch")
+        _check(bmag, oracle.gradmag(fld["xh"], box), "batch box")
+        assert torch.equal(mag, hsz.op_fused(c, hsz.QUANT, "gradmag"))
+        assert torch.equal(bmag, hsz.op_fused(c, hsz.QUANT, "gradmag", box=box))
