@@ -76,6 +76,16 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t q4_rsrc(const void* base, uint
   return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(uint32_t)bytes, 0x00020000);
 }
 
+// 16-byte store at byte offset 'off' of r, the whole offset in the vector
+// operand and soffset zero.  The store reads its data registers after issue,
+// and a VALU write to them in the very next instruction corrupts the last
+// lanes read; the backend pads that case with a wait state only for stores
+// whose soffset is not a register, so an offset split into an SGPR soffset
+// would leave it unguarded.
+__device__ __forceinline__ void store_b128(const f4& v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4, v), r, off, 0, 0);
+}
+
 // Decode one staged block (payload words in LDS column 'col', rows kQ4NS
 // words apart) into row[q4w(e0 + j)], e0 a multiple of 32: two slots per
 // 32-bit window, four slots per 16-byte LDS write.  gl / gr: also write the
@@ -266,9 +276,7 @@ __device__ __forceinline__ void gradmag_tile_q4(const GradJob& job, int64_t tile
           const uint32_t s = G[i][j] + (uint32_t)__mul24(nz[i][j], nz[i][j]);
           r[j] = __builtin_amdgcn_sqrtf((float)s) * h;
         }
-        if (active)
-          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4, r), r_out, ocol,
-                                                 (int)(4 * (orow + i * bx)), 0);
+        if (active) store_b128(r, r_out, ocol + (uint32_t)(4 * (orow + i * bx)));
         if constexpr (ACC == 1) {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
@@ -413,6 +421,419 @@ __device__ __forceinline__ void gradmag_tile_q4(const GradJob& job, int64_t tile
   }
 }
 
+// ---- wide rows: q as 16-bit pairs -------------------------------------------------
+// Boxes wider than 256 columns take a 512 x 16 tile of 512 threads (eight
+// waves).  With max|q| < 8192 every q, every ghost value (2 q_0 - q_1) and
+// every numerator fits 16 bits, so the decoded planes hold q as 16-bit pairs
+// (half the LDS of the tile above: two workgroups of eight waves per compute
+// unit) and the stencil works on pairs: numerators by packed subtractions,
+// squares summed by 16-bit dot products into 32 bits (exact: three squares
+// of |n| < 2^15 stay below 2^32).  Wave w
+// owns rows 2w, 2w+1 of the tile and lane l the columns 4l .. 4l+3 and
+// 256+4l .. 256+4l+3, so each 16-byte store of a wave writes 1 KiB of one
+// row contiguously; a lane's x-neighbours come from the lanes beside it
+// (wave shifts), the wave's outer ones from LDS.
+constexpr int kQ8Threads = 512;
+constexpr int kQ8TXL = 512;
+constexpr int kQ8RY = 2;                             // rows per lane
+constexpr int kQ8TY = kQ8RY * (kQ8Threads / kWave);  // 16
+constexpr int kQ8Rows = kQ8TY + 2;
+constexpr int kQ8NBR = kQ8TXL / 32 + 2;              // blocks per decoded row, at most
+constexpr int kQ8Items = kQ8Rows * kQ8NBR;           // 324
+constexpr int kQ8NS = 512;                           // staging columns
+// words per LDS row: 576 16-bit columns (288 words), padded to 4 (mod 64) so
+// the 16-byte decode writes of consecutive rows fall in distinct banks
+constexpr int kQ8Pitch = 324;
+constexpr int kQ8Plane = kQ8Rows * kQ8Pitch;
+constexpr int kQ8StageOff = (2 * kQ8Plane + 63) / 64 * 64;
+constexpr int kQ8PF = 16;
+constexpr int kQ8LdsWords = kQ8StageOff + kQ8PF * kQ8NS;
+static_assert(kQ8Items + kWave <= kQ8NS, "a staging column per item, spares for the idle lanes of a wave");
+static_assert(kQ8Pitch * 2 >= (kQ8TXL + 64) && kQ8Pitch % 64 == 4, "row pitch");
+static_assert(kQ8LdsWords * 4 * 2 <= 163840, "two workgroups per compute unit");
+
+typedef short s2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) short lds_i16;
+
+__device__ __forceinline__ int pk_sub(int a, int b) {
+  return __builtin_bit_cast(int, __builtin_bit_cast(s2, a) - __builtin_bit_cast(s2, b));
+}
+__device__ __forceinline__ int pk_add(int a, int b) {
+  return __builtin_bit_cast(int, __builtin_bit_cast(s2, a) + __builtin_bit_cast(s2, b));
+}
+// squares of 16-bit halves through 16-bit dot products (all 32-bit sums are
+// taken modulo 2^32 and read as unsigned: a sum of three squares of |n| < 2^15
+// stays below 2^32): sq2lo(x, y, c) = c + x.lo^2 + y.lo^2, sq2hi the high
+// halves; sq1lo(z, c) = c + z.lo^2, sq1hi(z, c) = c + z.hi^2
+__device__ __forceinline__ int dot2(int a, int b, int c);
+__device__ __forceinline__ uint32_t sq2lo(int x, int y, uint32_t c) {
+  const int p = (int)__builtin_amdgcn_perm((uint32_t)y, (uint32_t)x, 0x05040100u);  // (x.lo, y.lo)
+  return (uint32_t)dot2(p, p, (int)c);
+}
+__device__ __forceinline__ uint32_t sq2hi(int x, int y, uint32_t c) {
+  const int p = (int)__builtin_amdgcn_perm((uint32_t)y, (uint32_t)x, 0x07060302u);  // (x.hi, y.hi)
+  return (uint32_t)dot2(p, p, (int)c);
+}
+__device__ __forceinline__ uint32_t sq1lo(int z, uint32_t c) { return (uint32_t)dot2(z, z & 0xffff, (int)c); }
+__device__ __forceinline__ uint32_t sq1hi(int z, uint32_t c) { return (uint32_t)dot2(z, z & (int)0xffff0000u, (int)c); }
+__device__ __forceinline__ int dot2(int a, int b, int c) {
+  return __builtin_amdgcn_sdot2(__builtin_bit_cast(s2, a), __builtin_bit_cast(s2, b), c, false);
+}
+// the 16-bit pair (lo, hi)
+__device__ __forceinline__ int pk(int lo, int hi) { return (int)__builtin_amdgcn_perm((uint32_t)hi, (uint32_t)lo, 0x05040100u); }
+
+// Decode one staged block into 16-bit q at halfwords e0 .. e0+31 of 'row'
+// (e0 a multiple of 32), with the optional ghost columns before and after.
+__device__ __forceinline__ void decode_q8(const lds_u32* col, int w, int q0, lds_i16* row, int e0, bool gl, bool gr) {
+  const uint32_t sg0 = col[0];
+  const lds_u32* mag = col + kQ8NS;
+  int q = q0;
+  uint32_t uw = (uint32_t)w, pos = 0;
+  const uint32_t w2 = 2u * uw;
+  int first[2] = {0, 0}, last[2] = {0, 0};
+#pragma unroll
+  for (int g = 0; g < 32; g += 8) {
+    asm volatile("" : "+v"(pos));
+    uint32_t lo[4], hi[4], pp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      pp[u] = pos;
+      pos += w2;
+      uint32_t k = pp[u] >> 5;
+      asm("" : "+v"(k));
+      const lds_u32* a = mag + k * kQ8NS;
+      lo[u] = a[0];
+      hi[u] = a[kQ8NS];
+    }
+    int packed[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = g + 2 * u;
+      const uint32_t win = __builtin_amdgcn_alignbit(hi[u], lo[u], pp[u]);
+      const uint32_t m0 = __builtin_amdgcn_ubfe(win, 0u, uw);
+      const uint32_t m1 = __builtin_amdgcn_ubfe(win, uw, uw);
+      const int s0 = __builtin_amdgcn_sbfe((int)sg0, (uint32_t)j, 1u);
+      const int s1 = __builtin_amdgcn_sbfe((int)sg0, (uint32_t)(j + 1), 1u);
+      const int qa = (int)((m0 ^ (uint32_t)s0) + (uint32_t)q) - s0;
+      q = (int)((m1 ^ (uint32_t)s1) + (uint32_t)qa) - s1;
+      packed[u] = pk(qa, q);
+      if (g == 0 && u == 0) { first[0] = qa; first[1] = q; }
+      if (g == 24 && u == 3) { last[0] = q; last[1] = qa; }
+    }
+    *(__attribute__((address_space(3))) i4*)(row + e0 + g) = i4{packed[0], packed[1], packed[2], packed[3]};
+  }
+  if (gl) row[e0 - 1] = (short)(2 * first[0] - first[1]);
+  if (gr) row[e0 + 32] = (short)(2 * last[0] - last[1]);
+}
+
+template <int ACC>
+__device__ __forceinline__ void gradmag_tile_q8(const GradJob& job, int64_t tile, uint32_t* smem_g, int* status) {
+  constexpr int S = 32, P = kQ8Pitch;
+  const StreamView& v = job.v;
+  const Dims3 d = job.d;
+  const Box3 b = job.b;
+  const int tz = job.tz, kmax = job.kmax;
+  const float h = (float)job.halfq;
+  lds_u32* const smem = (lds_u32*)smem_g;
+  lds_u32* const stage = smem + kQ8StageOff;
+  const int t = threadIdx.x;
+
+  const __amdgpu_buffer_rsrc_t r_meta = q4_rsrc(v.base, (const uint8_t*)v.payload - v.base);
+  const int so_w = (int)(v.width - v.base), so_q0 = (int)((const uint8_t*)v.q0 - v.base);
+  const int so_co = (int)((const uint8_t*)v.chunk_off - v.base);
+  const __amdgpu_buffer_rsrc_t r_pay = q4_rsrc(v.payload, v.payload_words * 4);
+  const __amdgpu_buffer_rsrc_t r_rel = q4_rsrc(job.rel, 2 * (uint64_t)v.nb);
+  const __amdgpu_buffer_rsrc_t r_out =
+      q4_rsrc(job.out, 4 * (uint64_t)((b.z1 - b.z0) * (b.y1 - b.y0) * (b.x1 - b.x0)));
+
+  const int64_t bx = b.x1 - b.x0, by = b.y1 - b.y0;
+  const int64_t ntx = (bx + kQ8TXL - 1) / kQ8TXL, nty = (by + kQ8TY - 1) / kQ8TY;
+  int64_t blk = tile;
+  const int64_t tx = blk % ntx;
+  blk /= ntx;
+  const int64_t ty = blk % nty;
+  const int64_t tzi = blk / nty;
+  const int64_t x0 = b.x0 + tx * kQ8TXL, y0 = b.y0 + ty * kQ8TY, z0 = b.z0 + tzi * tz;
+  const int xs = (int)min((int64_t)kQ8TXL, b.x1 - x0), ys = (int)min((int64_t)kQ8TY, b.y1 - y0);
+  const int64_t zs = min((int64_t)tz, b.z1 - z0);
+  const int64_t za = max((int64_t)0, z0 - 1), zb = min(d.z, z0 + zs + 1);
+  const uint32_t bpr = (uint32_t)(d.x / S);
+
+  // ---- decode item: block k of decoded row dr (consecutive lanes take
+  // consecutive rows of one block column)
+  // The tile's items (rows x blocks of a row) are spread evenly over as few
+  // waves as hold them; the other waves neither fetch nor decode.
+  const int lane = t % kWave, wv = __builtin_amdgcn_readfirstlane(t / kWave);
+  const int64_t fb = x0 > 0 ? x0 / S - 1 : 0;
+  const int64_t lb = min((int64_t)bpr - 1, (x0 + xs) / S);
+  const int items = kQ8Rows * (int)(lb - fb + 1);
+  const int ndw = (items + kWave - 1) / kWave, ipw = (items + ndw - 1) / ndw;
+  const bool dwave = wv < ndw;
+  const int item = wv * ipw + lane;
+  const int dk = item / kQ8Rows, dr = item % kQ8Rows;
+  const int64_t dy = y0 - 1 + dr;
+  const bool decoder = dwave && lane < ipw && item < items && dr <= ys + 1 && dy >= 0 && dy < d.y;
+  const int e0 = (int)((fb + dk) * S - x0 + S);
+  const bool gl = decoder && x0 == 0 && dk == 0;
+  const bool gr = decoder && x0 + xs == d.x && fb + dk == (int64_t)bpr - 1;
+  const int drow = dr * P;
+  lds_u32* const col = stage + (lane < ipw ? item : kQ8Items + (lane - ipw));
+  const uint32_t bk0 = decoder ? (uint32_t)((za * d.y + dy) * (int64_t)bpr + fb + dk) : 0u;
+  const uint32_t pstride = (uint32_t)(d.y * (int64_t)bpr);
+
+  struct Meta {
+    int w, q0, words;
+    uint32_t off;
+    bool valid;
+  };
+  auto meta_of = [&](int64_t p) {
+    Meta m;
+    m.valid = decoder && p < zb;
+    const uint32_t bk = m.valid ? bk0 + (uint32_t)(p - za) * pstride : 0u;
+    m.w = (int)__builtin_amdgcn_raw_buffer_load_b8(r_meta, bk, so_w, 0);
+    m.q0 = (int)__builtin_amdgcn_raw_buffer_load_b32(r_meta, 4 * bk, so_q0, 0);
+    const uint32_t rel = __builtin_amdgcn_raw_buffer_load_b16(r_rel, 2 * bk, 0, 0);
+    const uint32_t cl = __builtin_amdgcn_raw_buffer_load_b32(r_meta, 8 * (bk / kChunkBlocks), so_co, 0);
+    m.off = cl + rel;
+    m.words = 0;
+    return m;
+  };
+  auto check = [&](Meta& m) {
+    m.words = m.valid ? block_words<S>(m.w) : 0;
+    if (m.valid && (m.w > kQ4MaxW || m.words > kmax || (uint64_t)m.off + (uint64_t)m.words > v.payload_words)) {
+      record_status(status, kErrBadStream);
+      m.w = 0;
+      m.words = 0;
+    }
+  };
+  auto fetch = [&](const Meta& m, uint32_t (&pw)[kQ8PF]) {
+    const uint32_t base = m.words ? 4 * m.off : 0x80000000u;
+#pragma unroll
+    for (int k = 0; k < kQ8PF; ++k) pw[k] = __builtin_amdgcn_raw_buffer_load_b32(r_pay, base + 4 * k, 0, 0);
+  };
+  auto stage_words = [&](const uint32_t (&pw)[kQ8PF]) {
+#pragma unroll
+    for (int k = 0; k < kQ8PF; ++k) col[k * kQ8NS] = pw[k];
+  };
+
+  // ---- stencil: wave wv owns rows 2 wv, 2 wv + 1 of the tile, lane the
+  // column groups A = 4 lane .. 4 lane + 3 and B = 256 + 4 lane .. + 3
+  // (halfwords S + .. of a row)
+  const bool actA = 4 * lane < xs, actB = kQ8TXL / 2 + 4 * lane < xs;
+  const int cwA = (S + 4 * lane) / 2, cwB = (S + kQ8TXL / 2 + 4 * lane) / 2;  // words of the groups
+  const bool top = y0 == 0 && wv == 0;
+  const int kb = (y0 + ys == d.y) ? ys + 1 - kQ8RY * wv : -1;  // window row of the ghost below
+  const bool y2 = d.y >= 2, z2 = d.z >= 2;
+  int nrows = ys - kQ8RY * wv;
+  nrows = nrows < 0 ? 0 : (nrows > kQ8RY ? kQ8RY : nrows);
+  const uint32_t ocol = 4u * (uint32_t)((x0 - b.x0) + 4 * lane);  // group A; group B 1 KiB further
+  const int64_t orow0 = (y0 + kQ8RY * wv - b.y0) * bx;
+
+  int Q[3][kQ8RY][4];        // q of three consecutive planes, 16-bit pairs
+  uint32_t G[kQ8RY][8];      // nx^2 + ny^2 of the previous plane
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int i = 0; i < kQ8RY; ++i)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) Q[r][i][m] = 0;
+#pragma unroll
+  for (int i = 0; i < kQ8RY; ++i)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) G[i][e] = 0u;
+  int as1 = 0;
+  uint64_t as2 = 0;
+
+  auto emit = [&](int64_t o, const int (&qo)[kQ8RY][4], const int (&nz)[kQ8RY][4]) {
+    const int64_t orow = ((o - b.z0) * by) * bx + orow0;
+    int s1p = 0, s2p = 0;
+#pragma unroll
+    for (int i = 0; i < kQ8RY; ++i) {
+      if (i < nrows) {
+        f4 r0, r1;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          r0[2 * m] = __builtin_amdgcn_sqrtf((float)sq1lo(nz[i][m], G[i][2 * m])) * h;
+          r0[2 * m + 1] = __builtin_amdgcn_sqrtf((float)sq1hi(nz[i][m], G[i][2 * m + 1])) * h;
+          r1[2 * m] = __builtin_amdgcn_sqrtf((float)sq1lo(nz[i][m + 2], G[i][2 * m + 4])) * h;
+          r1[2 * m + 1] = __builtin_amdgcn_sqrtf((float)sq1hi(nz[i][m + 2], G[i][2 * m + 5])) * h;
+        }
+        const uint32_t so = ocol + (uint32_t)(4 * (orow + i * bx));
+        if (actA) store_b128(r0, r_out, so);
+        if (actB) store_b128(r1, r_out, so + 2 * kQ8TXL);
+        if constexpr (ACC == 1) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int qm = (m < 2 ? actA : actB) ? qo[i][m] : 0;
+            const int lo = (int)(short)(qm & 0xffff), hi = qm >> 16;
+            s1p += lo + hi;
+            s2p += __mul24(lo, lo) + __mul24(hi, hi);
+          }
+        }
+      }
+    }
+    if constexpr (ACC == 1) {
+      as1 += s1p;
+      as2 += (uint32_t)s2p;
+    }
+  };
+
+  auto stencil = [&](auto RC, int64_t p, const lds_u32* buf) {
+    constexpr int C = decltype(RC)::value, M1 = (C + 2) % 3, M2 = (C + 1) % 3;
+    const lds_u32* rb = buf + kQ8RY * wv * P;
+    typedef int i2 __attribute__((ext_vector_type(2)));
+    int A[4][4];  // per window row: group A's two pairs, then group B's
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const i2 a = *(const __attribute__((address_space(3))) i2*)(rb + k * P + cwA);
+      const i2 c = *(const __attribute__((address_space(3))) i2*)(rb + k * P + cwB);
+      A[k][0] = a.x; A[k][1] = a.y; A[k][2] = c.x; A[k][3] = c.y;
+    }
+    // the columns beside each group: from the neighbouring lanes; the wave's
+    // outer ones from LDS (the high half of word S/2 - 1 is column x0 - 1,
+    // the low half of word S/2 + 128 column x0 + 256, the high half of the
+    // word before it column x0 + 255, the low half of word S/2 + 256 column
+    // x0 + 512)
+    int XM[kQ8RY][2], XP[kQ8RY][2];
+#pragma unroll
+    for (int i = 0; i < kQ8RY; ++i) {
+      const lds_u32* r = rb + (i + 1) * P;
+      const int emA = (int)r[S / 2 - 1], epA = (int)r[S / 2 + kQ8TXL / 4];
+      const int emB = (int)r[S / 2 + kQ8TXL / 4 - 1], epB = (int)r[S / 2 + kQ8TXL / 2];
+      XM[i][0] = __builtin_amdgcn_update_dpp(emA, A[i + 1][1], 0x138, 0xf, 0xf, false);  // wave_shr:1
+      XP[i][0] = __builtin_amdgcn_update_dpp(epA, A[i + 1][0], 0x130, 0xf, 0xf, false);  // wave_shl:1
+      XM[i][1] = __builtin_amdgcn_update_dpp(emB, A[i + 1][3], 0x138, 0xf, 0xf, false);
+      XP[i][1] = __builtin_amdgcn_update_dpp(epB, A[i + 1][2], 0x130, 0xf, 0xf, false);
+    }
+    if (top) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) A[0][m] = y2 ? pk_sub(pk_add(A[1][m], A[1][m]), A[2][m]) : A[1][m];
+    }
+    if (kb >= 2 && kb <= 3) {
+#pragma unroll
+      for (int k = 2; k < 4; ++k)
+        if (k == kb) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) A[k][m] = y2 ? pk_sub(pk_add(A[k - 1][m], A[k - 1][m]), A[k - 2][m]) : A[k - 1][m];
+        }
+    }
+    const int64_t o = p - 1;
+    if (o == 0) {  // ghost plane q_{-1} = 2 q_0 - q_1 (q_0 on a length-1 axis)
+#pragma unroll
+      for (int i = 0; i < kQ8RY; ++i)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          Q[M2][i][m] = z2 ? pk_sub(pk_add(Q[M1][i][m], Q[M1][i][m]), A[i + 1][m]) : Q[M1][i][m];
+    }
+    if (o >= z0 && o < z0 + zs) {
+      int nz[kQ8RY][4];
+#pragma unroll
+      for (int i = 0; i < kQ8RY; ++i)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) nz[i][m] = pk_sub(A[i + 1][m], Q[M2][i][m]);
+      emit(o, Q[M1], nz);
+    }
+#pragma unroll
+    for (int i = 0; i < kQ8RY; ++i) {
+      const int* a = A[i + 1];
+      // per group g: (x-1, x), (x+1, x+2), (x+3, x+4) for its columns x .. x+3
+      int T[2][3];
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        T[g][0] = (int)__builtin_amdgcn_alignbit((uint32_t)a[2 * g], (uint32_t)XM[i][g], 16u);
+        T[g][1] = (int)__builtin_amdgcn_alignbit((uint32_t)a[2 * g + 1], (uint32_t)a[2 * g], 16u);
+        T[g][2] = (int)__builtin_amdgcn_alignbit((uint32_t)XP[i][g], (uint32_t)a[2 * g + 1], 16u);
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int nx = pk_sub(T[m / 2][m % 2 + 1], T[m / 2][m % 2]), ny = pk_sub(A[i + 2][m], A[i][m]);
+        G[i][2 * m] = sq2lo(nx, ny, 0u);
+        G[i][2 * m + 1] = sq2hi(nx, ny, 0u);
+        Q[C][i][m] = a[m];
+      }
+    }
+  };
+
+  // One plane: decode waves fetch plane p+2's payload (into registers) and
+  // plane p+3's metadata and decode plane p+1 into the other buffer; every
+  // wave then runs the stencil on plane p; the fetched words are staged last,
+  // so the loads have the decode and the stencil to land.
+  Meta cur, nn;
+  uint32_t pw[kQ8PF];
+  auto step = [&](auto RC, int64_t p) {
+    const bool odd = ((p - za) & 1) != 0;
+    const lds_u32* buf = smem + (odd ? kQ8Plane : 0);
+    lds_u32* nbuf = smem + (odd ? 0 : kQ8Plane);
+    Meta n3;
+    if (dwave) {
+      check(nn);
+      fetch(nn, pw);
+      n3 = meta_of(p + 3);
+      if (cur.valid) decode_q8(col, cur.w, cur.q0, (lds_i16*)(nbuf + drow), e0, gl, gr);
+    }
+    stencil(RC, p, buf);
+    if (dwave) {
+      stage_words(pw);
+      cur = nn;
+      nn = n3;
+    }
+    __syncthreads();
+  };
+
+  // prologue: plane za decoded into buffer 0, plane za+1's words staged,
+  // plane za+2's metadata in flight
+  if (dwave) {
+    cur = meta_of(za);
+    Meta nx = meta_of(za + 1);
+    check(cur);
+    fetch(cur, pw);
+    stage_words(pw);
+    if (cur.valid) decode_q8(col, cur.w, cur.q0, (lds_i16*)(smem + drow), e0, gl, gr);
+    check(nx);
+    fetch(nx, pw);
+    stage_words(pw);
+    cur = nx;
+    nn = meta_of(za + 2);
+  }
+  __syncthreads();
+
+  // the march, unrolled by three (plane p's values go to register set (p - za) % 3)
+  int64_t p = za;
+  for (; p + 3 <= zb; p += 3) {
+    step(std::integral_constant<int, 0>{}, p);
+    step(std::integral_constant<int, 1>{}, p + 1);
+    step(std::integral_constant<int, 2>{}, p + 2);
+  }
+  const int rem = (int)(zb - p);
+  if (rem >= 1) step(std::integral_constant<int, 0>{}, p);
+  if (rem >= 2) step(std::integral_constant<int, 1>{}, p + 1);
+
+  if (z0 + zs == zb) {
+    const int64_t o = zb - 1;
+    const int last = rem == 0 ? 2 : rem - 1;
+    auto tail = [&](auto RC) {
+      constexpr int C = decltype(RC)::value, M1 = (C + 2) % 3;
+      int nz[kQ8RY][4];
+#pragma unroll
+      for (int i = 0; i < kQ8RY; ++i)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int dlt = pk_sub(Q[C][i][m], Q[M1][i][m]);
+          nz[i][m] = z2 ? pk_add(dlt, dlt) : 0;
+        }
+      emit(o, Q[C], nz);
+    };
+    if (last == 0) tail(std::integral_constant<int, 0>{});
+    else if (last == 1) tail(std::integral_constant<int, 1>{});
+    else tail(std::integral_constant<int, 2>{});
+  }
+  if constexpr (ACC == 1) {
+    const int64_t cnt = (int64_t)nrows * 4 * ((int)actA + (int)actB) * zs;
+    U128 s2v = {as2, 0};
+    acc_add_wave((BatchAcc*)job.acc, (int64_t)as1, cnt, s2v);
+  }
+}
+
 // Tiles handed out so that the workgroups of one XCD (launch order modulo 8)
 // take consecutive tiles -- neighbours in y, sharing their halo rows in that
 // XCD's L2 -- in every full round of the grid.
@@ -449,37 +870,56 @@ __global__ void __launch_bounds__(kQ4Threads, 2) k_batch_gradmag_q4(const GradJo
   }
 }
 
+__global__ void __launch_bounds__(kQ8Threads, 4) k_gradmag_q8(GradJob job, int* status) {
+  extern __shared__ uint32_t smem[];
+  gradmag_tile_q8<0>(job, xcd_tile(0, gridDim.x), smem, status);
+}
+
+template <int ACC>
+__global__ void __launch_bounds__(kQ8Threads, 4) k_batch_gradmag_q8(const GradJob* __restrict__ jobs,
+                                                                   const int64_t* __restrict__ tile_start,
+                                                                   const int64_t* __restrict__ counts, int* status) {
+  extern __shared__ uint32_t smem[];
+  const int n = (int)counts[0];
+  const int64_t total = counts[1];
+  for (int64_t base = 0; base < total; base += gridDim.x) {
+    const int64_t tile = xcd_tile(base, total);
+    if (tile >= total) break;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (tile_start[mid] <= tile) lo = mid;
+      else hi = mid - 1;
+    }
+    const GradJob job = load_job(jobs, lo);
+    gradmag_tile_q8<ACC>(job, tile - tile_start[lo], smem, status);
+  }
+}
+
 template <int S, int TXL>
 size_t q4_lds() {
   return (size_t)Q4<S, TXL>::kLdsWords * sizeof(uint32_t);
 }
+size_t q8_lds() { return (size_t)kQ8LdsWords * sizeof(uint32_t); }
 
-template <int S, int TXL>
 hipError_t run_q4(const GradJob& job, int* status, hipStream_t s) {
-  const size_t lds = q4_lds<S, TXL>();
   const int64_t grid = q4_tiles(job.b, job.tz, job.d);
-  hipLaunchKernelGGL((k_gradmag_q4<S, TXL>), dim3((unsigned)grid), dim3(kQ4Threads), lds, s, job, status);
-  return hipGetLastError();
-}
-
-template <int S, int TXL>
-hipError_t batch_q4(int acc, const GradJob* jobs, const int64_t* tile_start, const int64_t* counts, int grid,
-                    int* status, hipStream_t s) {
-  const size_t lds = q4_lds<S, TXL>();
-  if (acc == 1)
-    hipLaunchKernelGGL((k_batch_gradmag_q4<S, TXL, 1>), dim3(grid), dim3(kQ4Threads), lds, s, jobs, tile_start,
-                       counts, status);
+  if (q4_txl(job.b) == 512)
+    hipLaunchKernelGGL(k_gradmag_q8, dim3((unsigned)grid), dim3(kQ8Threads), q8_lds(), s, job, status);
   else
-    hipLaunchKernelGGL((k_batch_gradmag_q4<S, TXL, 0>), dim3(grid), dim3(kQ4Threads), lds, s, jobs, tile_start,
-                       counts, status);
+    hipLaunchKernelGGL((k_gradmag_q4<32, 256>), dim3((unsigned)grid), dim3(kQ4Threads), (q4_lds<32, 256>()), s, job,
+                       status);
   return hipGetLastError();
 }
 
 }  // namespace
 
-// Column tile width for a box: the whole row when the box is wider than 256
-// columns (no x-halo blocks), else 256.
-int q4_txl(const Box3& b) { return (b.x1 - b.x0) > 256 ? 512 : 256; }
+// Column tile: 512 (the sixteen-bit tile) for boxes wider than 256 columns
+// whose width is a multiple of 8, else 256.
+int q4_txl(const Box3& b) {
+  const int64_t bx = b.x1 - b.x0;
+  return (bx > 256 && bx % 8 == 0) ? 512 : 256;
+}
 
 bool q4_eligible(const StreamView& v, int via, int op, const Dims3& d, const Box3& b) {
   // 32-bit offsets: every section and the result below 2 GiB
@@ -490,7 +930,7 @@ bool q4_eligible(const StreamView& v, int via, int op, const Dims3& d, const Box
 
 int64_t q4_tiles(const Box3& b, int tz, const Dims3&) {
   const int txl = q4_txl(b);
-  const int ty = txl == 512 ? Q4<32, 512>::kTY : Q4<32, 256>::kTY;
+  const int ty = txl == 512 ? kQ8TY : Q4<32, 256>::kTY;
   const int64_t ntx = (b.x1 - b.x0 + txl - 1) / txl, nty = (b.y1 - b.y0 + ty - 1) / ty;
   return ntx * nty * ((b.z1 - b.z0 + tz - 1) / tz);
 }
@@ -501,7 +941,7 @@ int q4_kmax(int S) { return (S / 32) * (1 + kQ4MaxW); }
 // fill the chip.
 int q4_tz(const Box3& b) {
   const int txl = q4_txl(b);
-  const int ty = txl == 512 ? Q4<32, 512>::kTY : Q4<32, 256>::kTY;
+  const int ty = txl == 512 ? kQ8TY : Q4<32, 256>::kTY;
   const int64_t ntx = (b.x1 - b.x0 + txl - 1) / txl, nty = (b.y1 - b.y0 + ty - 1) / ty;
   const int64_t bz = b.z1 - b.z0;
   int64_t tz = bz;
@@ -509,20 +949,32 @@ int q4_tz(const Box3& b) {
   return (int)tz;
 }
 
-hipError_t launch_gradmag_q4(const GradJob& job, int* status, hipStream_t s) {
-  return q4_txl(job.b) == 512 ? run_q4<32, 512>(job, status, s) : run_q4<32, 256>(job, status, s);
-}
+hipError_t launch_gradmag_q4(const GradJob& job, int* status, hipStream_t s) { return run_q4(job, status, s); }
 
 hipError_t launch_batch_gradmag_q4(int S, int txl, int acc, const GradJob* jobs, const int64_t* tile_start,
                                    const int64_t* counts, int grid, int* status, hipStream_t s) {
   if (S != 32) return hipErrorInvalidValue;
-  return txl == 512 ? batch_q4<32, 512>(acc, jobs, tile_start, counts, grid, status, s)
-                    : batch_q4<32, 256>(acc, jobs, tile_start, counts, grid, status, s);
+  if (txl == 512) {
+    if (acc == 1)
+      hipLaunchKernelGGL(k_batch_gradmag_q8<1>, dim3(grid), dim3(kQ8Threads), q8_lds(), s, jobs, tile_start, counts,
+                         status);
+    else
+      hipLaunchKernelGGL(k_batch_gradmag_q8<0>, dim3(grid), dim3(kQ8Threads), q8_lds(), s, jobs, tile_start, counts,
+                         status);
+  } else {
+    if (acc == 1)
+      hipLaunchKernelGGL((k_batch_gradmag_q4<32, 256, 1>), dim3(grid), dim3(kQ4Threads), (q4_lds<32, 256>()), s, jobs,
+                         tile_start, counts, status);
+    else
+      hipLaunchKernelGGL((k_batch_gradmag_q4<32, 256, 0>), dim3(grid), dim3(kQ4Threads), (q4_lds<32, 256>()), s, jobs,
+                         tile_start, counts, status);
+  }
+  return hipGetLastError();
 }
 
 size_t batch_gradmag_q4_lds(int S, int txl) {
   if (S != 32) return 0;
-  return txl == 512 ? q4_lds<32, 512>() : q4_lds<32, 256>();
+  return txl == 512 ? q8_lds() : q4_lds<32, 256>();
 }
 
 }  // namespace hsz

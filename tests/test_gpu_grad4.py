@@ -1,10 +1,12 @@
-"""GPU parity of the four-column gradient-magnitude tile (grad4.hip).
+"""GPU parity of the binary32 gradient-magnitude tiles of grad4.hip.
 
 Binary32 streams with blocks of 32 and max|q| < 8192 whose rows start on
-32-column boundaries take this tile (fused route, and gradient jobs of
-batches); everything else takes the general tile.  The fields below are
-eligible, with widths of one and several column tiles (256 and 512 wide
-tiles, ragged last tiles), rows and planes that leave ragged last tiles,
+32-column boundaries take these tiles (fused route, and gradient jobs of
+batches): boxes wider than 256 columns with a width divisible by 8 the
+sixteen-bit 512 x 16 tile, the others the four-column 256 x 16 tile;
+everything else takes the general tile.  The fields below are eligible,
+with widths of one and several column tiles (256 and 512 wide tiles,
+ragged last tiles, a 300-column box that takes the 256 tile), rows and planes that leave ragged last tiles,
 axes of length 1 and 2 (ghost values at every edge), boxes aligned to 32
 columns (this tile) and not aligned (the general tile), and plans whose
 statistics are summed inside the tiles.  Bars (Sec. III-B Eq.
@@ -46,6 +48,7 @@ SHAPES = [
     (2, 1, 64),       # one row, two planes
     (37, 12, 32),     # one block per row
     (70, 320),        # 2D field (d.z = 1 in the kernel's view)
+    (6, 21, 300),     # 300 columns: not a multiple of 8, the 256-column tile
 ]
 
 
@@ -117,7 +120,7 @@ def test_batch_shared_statistics(fld):
     box = _boxes(fld["shape"], True, rng, 1)[0]
     jobs = [hsz.Job(c, "mean", hsz.DELTA), hsz.Job(c, "var", hsz.QUANT), hsz.Job(c, "gradmag", hsz.QUANT),
             hsz.Job(c, "var", hsz.QUANT, box=box), hsz.Job(c, "gradmag", hsz.QUANT, box=box)]
-    for tz in (0, 5):
+    for tz in (0, 3, 5):
         plan = hsz.Plan(jobs, tune={"grad_tz": tz} if tz else None)
         plan.launch()
         mean, var, mag, bvar, bmag = plan.results()
