@@ -18,8 +18,12 @@ several distinct copies of the compressed stream (together well above the
 Also measured on the same GPU and reported beside it: the full-decompress
 baseline (decode to floats, then the same three operations on the floats),
 every stage of partial decompression, every operation on every
-materialised stage, compression, and the CPU checker (oracle) timed on a
-bounded slab of the same field.
+materialised stage, compression, the same step at the large field's other
+configurations (rel eb 1e-4 and 1e-2, S = 32 and 64; each with its
+roofline), the plan both enqueued directly and replayed as a HIP graph, the
+secondary workloads (vector field, block-mean streams, HSZp-nd, out-of-core
+slabs, batches, serving), each over three copies of its inputs in turn, and
+the CPU checker (oracle) timed on a bounded slab of the same field.
 """
 from __future__ import annotations
 
@@ -58,6 +62,8 @@ def parse():
     ap.add_argument("--no-hszx", action="store_true", help="skip the block-mean (HSZx) workload")
     ap.add_argument("--no-lorenzo", action="store_true", help="skip the HSZp-nd (Lorenzo) workload")
     ap.add_argument("--no-ooc", action="store_true", help="skip the out-of-core (host-resident slabs) workload")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other eb / block-size configurations of the large field")
     ap.add_argument("--no-tune", action="store_true", help="time the step with the default launch shape")
     ap.add_argument("--snapshots", type=int, default=64)
     ap.add_argument("--queries", type=int, default=20000)
@@ -73,8 +79,9 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "k_batch_grad_gradmag_512cube_counters.txt")
-KERNEL_SOURCES = ("grad.hip", "hsz_device.hpp", "hsz_launch.hpp")
+COUNTERS = os.path.join(ROOT, "profiles", "k_batch_gradmag_q8_512cube_counters.txt")
+KTRACE = os.path.join(ROOT, "profiles", "k_batch_gradmag_q8_512cube_kernel_trace.txt")
+KERNEL_SOURCES = ("grad4.hip", "hsz_device.hpp", "hsz_launch.hpp", "batch.cpp")
 
 
 def kernel_source_sha() -> str:
@@ -86,20 +93,31 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_record():
-    """The committed counter summary of the step's gradient kernel, or None
-    when there is none or the kernel sources changed since it was taken."""
+def _record(path, tag):
     try:
-        with open(COUNTERS) as f:
+        with open(path) as f:
             lines = f.read().splitlines()
     except OSError:
         return None
     for line in lines:
-        if line.startswith("TRAFFIC_JSON:"):
+        if line.startswith(tag + ":"):
             rec = json.loads(line.split(":", 1)[1])
             if rec.get("source_sha") == kernel_source_sha():
                 return rec
     return None
+
+
+def counter_record():
+    """The committed counter summary of the step's gradient kernel, or None
+    when there is none or the kernel sources changed since it was taken."""
+    return _record(COUNTERS, "TRAFFIC_JSON")
+
+
+def ktrace_record():
+    """The committed kernel-trace summary of the step (the gradient kernel's
+    own average duration under rocprofv3), or None when there is none or the
+    kernel sources changed since it was taken."""
+    return _record(KTRACE, "KTRACE_JSON")
 
 
 def counter_traffic():
@@ -126,6 +144,227 @@ def counter_valu(launch_ms):
             "unit": "T lane-ops/s", "frac": round(tops / VALU_PEAK_TOPS, 4)}
 
 
+def grad_kernel_label(h, block, tune):
+    """Name of the batched gradient kernel a plan of the step runs for this
+    stream and launch shape (informational)."""
+    tile_x = int((tune or {}).get("grad_tile_x", 0))
+    acc = 1 if h.max_abs_q < 65536 else 2
+    if block == 32 and h.max_abs_q < 8192 and tile_x >= 0:
+        return "k_batch_gradmag_q8<1>" if tile_x != 256 else "k_batch_gradmag_q4<32,256,1>"
+    return f"k_batch_grad<{block},3,4,float,{acc}>"
+
+
+def measure_config(a, xg, eb, block, full, tune=None):
+    """One configuration of the large field: the step (one batched pass of
+    mean via D_p + variance via D_q + gradient magnitude via D_q), the three
+    operations launched separately, full decompression + the same operations,
+    and (full) the table of every stage and every operation on every stage.
+    Compressed inputs rotate over a.copies copies and materialised stages
+    over three buffers (3 x 512 MiB per stage), so no row is timed on bytes
+    left in the last-level caches by the previous launch."""
+    import torch
+
+    from paper_2603_25206_amd import hsz
+
+    dev = xg.device
+    n = xg.numel()
+    orig_bytes = n * xg.element_size()
+    c0 = hsz.compress(xg, eb, rel=True, block=block)
+    h = c0.header
+    copies = [c0] + [hsz.Compressed(c0.data.clone(), h) for _ in range(a.copies - 1)]
+    torch.cuda.synchronize()
+    log(f"[bench] eb {eb:g} S {block}: {c0.nbytes / 2**20:.1f} MiB, ratio {c0.ratio:.2f}, max|q| {h.max_abs_q}")
+    nc, R = len(copies), 3
+    stream = torch.cuda.current_stream()
+    S48 = [torch.empty(64, dtype=torch.uint8, device=dev) for _ in range(3)]
+    gbuf = torch.empty(n * 4, dtype=torch.uint8, device=dev)
+    qbufs = [torch.empty(n * 4, dtype=torch.uint8, device=dev) for _ in range(R)]
+    fbufs = [torch.empty(n * 4 + 64, dtype=torch.uint8, device=dev) for _ in range(R)]
+    dbufs = [torch.empty(4 * (n + h.nb) + 64, dtype=torch.uint8, device=dev) for _ in range(R)] if full else []
+    ws_bytes = max(hsz.op_workspace_bytes(h, op) for op in (hsz.MEAN, hsz.VAR, hsz.GRADMAG, hsz.LAPLACIAN))
+    ws = [hsz.workspace(ws_bytes, dev, key=f"bench{k}") for k in range(3)]
+
+    def C(k):
+        return copies[k % nc]
+
+    def timed(fns, steps, warmup):
+        """Run the list of (label, fn(k)) for steps k; per-label HIP event times."""
+        for k in range(warmup):
+            for _, fn in fns:
+                fn(k)
+        torch.cuda.synchronize()
+        evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in fns]
+               for _ in range(steps)]
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for k in range(steps):
+            for j, (_, fn) in enumerate(fns):
+                evs[k][j][0].record(stream)
+                fn(k)
+                evs[k][j][1].record(stream)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        per = {lab: float(np.mean([evs[k][j][0].elapsed_time(evs[k][j][1]) for k in range(steps)]))
+               for j, (lab, _) in enumerate(fns)}
+        return start.elapsed_time(stop) / steps, per
+
+    # ---- the three operations launched one by one -------------------------------------
+    def f_mean(k):
+        hsz.op_fused(C(k), hsz.DELTA, hsz.MEAN, out=S48[0], ws=ws[0], check=False, raw=True)
+
+    def f_var(k):
+        hsz.op_fused(C(k), hsz.QUANT, hsz.VAR, out=S48[1], ws=ws[1], check=False, raw=True)
+
+    def f_grad(k):
+        hsz.op_fused(C(k), hsz.QUANT, hsz.GRADMAG, out=gbuf, ws=ws[2], check=False, raw=True)
+
+    sep_fns = [("mean_fused_delta", f_mean), ("var_fused_quant", f_var), ("gradmag_quant", f_grad)]
+    ms_sep, per_sep = timed(sep_fns, a.steps, a.warmup)
+    st_v, st_m = hsz.stats_of(S48[1]), hsz.stats_of(S48[0])
+
+    # ---- the step: one batched pass, the three analytics sharing one decode -------------
+    # Per copy, a plan of three jobs over the whole field; mean and variance
+    # are summed inside the gradient tiles.  Block indexes are built once per
+    # stream, as a resident stream keeps them.
+    for c in copies:
+        c.build_index()
+
+    def jobs_of(c):
+        return [hsz.Job(c, "mean", hsz.DELTA), hsz.Job(c, "var", hsz.QUANT), hsz.Job(c, "gradmag", hsz.QUANT)]
+    if tune is None and not a.no_tune:
+        # the autotuner times each candidate over all the copies in turn and
+        # rejects any that changes a result
+        from paper_2603_25206_amd import tune as tuner
+        tune, _ = tuner.tune(jobs_of(copies[0]), reps=3, cache_path=None,
+                             alternates=[jobs_of(c) for c in copies[1:]])
+        log(f"[bench] eb {eb:g} S {block}: launch shape (autotuned) {tune}")
+    step_stream = torch.cuda.Stream()
+    plans = [hsz.Plan(jobs_of(c), tune=tune, stream=step_stream) for c in copies]
+
+    def step_times(pl, steps, warmup):
+        for k in range(warmup):
+            pl[k % len(pl)].launch()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(step_stream)
+        for k in range(steps):
+            evs[k][0].record(step_stream)
+            pl[k % len(pl)].launch()
+            evs[k][1].record(step_stream)
+        stop.record(step_stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / steps, float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+
+    ms_step, ms_replay = step_times(plans, a.steps, a.warmup)
+    res = plans[0].results()
+    if (res[1]["s1"], res[1]["s2"], res[1]["var"]) != (st_v["s1"], st_v["s2"], st_v["var"]) or \
+            res[0]["mean"] != st_m["mean"] or not torch.equal(res[2].reshape(-1), gbuf.view(torch.float32)):
+        raise RuntimeError("batched step disagrees with the separate operations")
+    for pl in plans:
+        pl.close()
+    # the same plans replaying the HIP graph captured at creation
+    gtune = dict(tune or {}, graph_replay=1)
+    gplans = [hsz.Plan(jobs_of(c), tune=gtune, stream=step_stream) for c in copies]
+    ms_graph, _ = step_times(gplans, max(5, a.steps // 2), 2)
+    gres = gplans[0].results()
+    if not torch.equal(gres[2], res[2]) or gres[1]["s2"] != res[1]["s2"]:
+        raise RuntimeError("graph replay disagrees with direct launch")
+    for pl in gplans:
+        pl.close()
+
+    # ---- baseline: full decompression + the same ops on floats ------------------------
+    fviews = [hsz.stage_view(b, h, hsz.FLOAT) for b in fbufs]
+
+    def b_dec(k):
+        hsz.decompress_to_stage(C(k), hsz.FLOAT, out=fbufs[k % R])
+
+    def b_op(op, out, w):
+        return lambda k: hsz.op_on_stage(fviews[k % R], h, hsz.FLOAT, op, out=out, ws=w, check=False, raw=True)
+
+    base_fns = [("decompress_float", b_dec), ("mean_float", b_op(hsz.MEAN, S48[0], ws[0])),
+                ("var_float", b_op(hsz.VAR, S48[1], ws[1])), ("gradmag_float", b_op(hsz.GRADMAG, gbuf, ws[2]))]
+    ms_base, per_base = timed(base_fns, max(5, a.steps // 2), 2)
+    st_bv = hsz.stats_of(S48[1])
+
+    # ---- per-stage table ------------------------------------------------------------
+    extra = {}
+    if full:
+        def dec(stage, bufs):
+            return lambda k: hsz.decompress_to_stage(C(k), stage, out=bufs[k % R])
+        _, per = timed([("decompress_delta", dec(hsz.DELTA, dbufs)), ("decompress_quant", dec(hsz.QUANT, qbufs)),
+                        ("decompress_float", dec(hsz.FLOAT, fbufs))], 6, 2)
+        extra.update(per)
+        views = {"delta": (hsz.DELTA, [hsz.stage_view(b, h, hsz.DELTA) for b in dbufs]),
+                 "quant": (hsz.QUANT, [hsz.stage_view(b, h, hsz.QUANT) for b in qbufs]),
+                 "float": (hsz.FLOAT, fviews)}
+
+        def on(stn, op, out):
+            st, vs = views[stn]
+            return lambda k: hsz.op_on_stage(vs[k % R], h, st, op, out=out, ws=ws[2], check=False, raw=True)
+
+        def fu(st, op, out):
+            return lambda k: hsz.op_fused(C(k), st, op, out=out, ws=ws[2], check=False, raw=True)
+        rows = []
+        for stn, st in (("delta", hsz.DELTA), ("quant", hsz.QUANT), ("float", hsz.FLOAT)):
+            for opn, op in (("mean", hsz.MEAN), ("var", hsz.VAR)):
+                rows += [(f"{opn}_on_{stn}", on(stn, op, S48[2])), (f"{opn}_fused_{stn}", fu(st, op, S48[2]))]
+        for stn, st in (("quant", hsz.QUANT), ("float", hsz.FLOAT)):
+            rows += [(f"gradmag_on_{stn}", on(stn, hsz.GRADMAG, gbuf)),
+                     (f"laplacian_on_{stn}", on(stn, hsz.LAPLACIAN, gbuf)),
+                     (f"laplacian_fused_{stn}", fu(st, hsz.LAPLACIAN, gbuf))]
+        _, per = timed(rows, 6, 2)
+        extra.update(per)
+        cbuf = torch.empty_like(c0.data)
+
+        def comp(k):
+            hsz.compress(xg, eb, rel=True, block=block, out=cbuf, check=False)
+        _, per = timed([("compress", comp)], 4, 1)
+        extra.update(per)
+
+    # ---- roofline of the step's dominant kernel ---------------------------------------
+    # Its algorithmic bytes: the compressed stream read once plus the f32
+    # magnitude written (the sums add none, the avoided floats are never
+    # counted).  Its duration here is the HIP-event time of one plan launch,
+    # which also holds the reset and finalize kernels and the gaps between
+    # them: 'frac' is a lower bound on the kernel's own fraction.
+    cbytes = c0.nbytes
+    alg_step = cbytes + 4 * n
+    achieved = alg_step / (ms_replay * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": grad_kernel_label(h, block, tune) + " (mean+var+gradmag, one decode)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": int(alg_step),
+                "launch_ms": round(ms_replay, 4)}
+    ach_sep = alg_step / (per_sep["gradmag_quant"] * 1e-3) / 1e9
+    roofline_sep = {"bound": "hbm", "kernel": "gradient magnitude alone (op_fused)",
+                    "achieved": round(ach_sep, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach_sep / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": int(alg_step),
+                    "launch_ms": round(per_sep["gradmag_quant"], 4)}
+    row = {
+        "eb": eb, "block": block, "ratio": round(c0.ratio, 3), "compressed_bytes": cbytes,
+        "max_abs_q": int(h.max_abs_q), "copies": nc,
+        "ms_per_step": round(ms_step, 4), "gbs_orig": round(orig_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "plan_ms_direct": round(ms_replay, 4), "plan_ms_graph_replay": round(ms_graph, 4),
+        "launch_shape": tune, "roofline": roofline,
+        "separate_ops": {"gbs_orig": round(orig_bytes / (ms_sep * 1e-3) / 1e9, 1), "ms_per_step": round(ms_sep, 4),
+                         "per_op_ms": {k: round(v, 4) for k, v in per_sep.items()}, "roofline": roofline_sep},
+        "full_decompress_baseline": {"gbs_orig": round(orig_bytes / (ms_base * 1e-3) / 1e9, 1),
+                                     "ms_per_step": round(ms_base, 4),
+                                     "per_op_ms": {k: round(v, 4) for k, v in per_base.items()},
+                                     "speedup_homomorphic": round(ms_base / ms_step, 3),
+                                     "speedup_separate_ops": round(ms_base / ms_sep, 3)},
+        "check": {"var_int_route": st_v["var"], "var_float_route": st_bv["var"], "mean": st_m["mean"]},
+    }
+    if full:
+        row["stage_table_ms"] = {k: round(v, 4) for k, v in extra.items()}
+    log(f"[bench] eb {eb:g} S {block}: step {ms_step:.4f} ms (plan {ms_replay:.4f} direct, {ms_graph:.4f} graph), "
+        f"separate {ms_sep:.4f}, full-decompress {ms_base:.4f}, frac {roofline['frac']}")
+    del copies, plans, gplans, gbuf, qbufs, fbufs, dbufs, ws, S48
+    torch.cuda.empty_cache()
+    return row, h
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -145,161 +384,8 @@ def main():
     n = x.size
     orig_bytes = x.nbytes
     xg = torch.from_numpy(x).to(dev)
-    c0 = hsz.compress(xg, a.eb, rel=True, block=a.block)
-    h = c0.header
-    log(f"[bench] compressed: {c0.nbytes / 2**20:.1f} MiB, ratio {c0.ratio:.2f}, max|q| {h.max_abs_q}")
-    copies = [c0] + [hsz.Compressed(c0.data.clone(), h) for _ in range(a.copies - 1)]
-    torch.cuda.synchronize()
 
-    stream = torch.cuda.current_stream()
-    S48 = [torch.empty(64, dtype=torch.uint8, device=dev) for _ in range(3)]
-    gbuf = torch.empty(n * 4, dtype=torch.uint8, device=dev)
-    qbuf = torch.empty(n * 4, dtype=torch.uint8, device=dev)
-    fbuf = torch.empty(n * 4 + 64, dtype=torch.uint8, device=dev)
-    dbuf = torch.empty(4 * (n + h.nb) + 64, dtype=torch.uint8, device=dev)
-    ws_bytes = max(hsz.op_workspace_bytes(h, op) for op in (hsz.MEAN, hsz.VAR, hsz.GRADMAG))
-    ws = [hsz.workspace(ws_bytes, dev, key=f"bench{k}") for k in range(3)]
-
-    def timed(name, fns, steps, warmup):
-        """Run the list of (label, fn(copy)) per step; per-label HIP event times."""
-        for i in range(warmup):
-            for _, fn in fns:
-                fn(copies[i % len(copies)])
-        torch.cuda.synchronize()
-        evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in fns]
-               for _ in range(steps)]
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        start.record(stream)
-        for i in range(steps):
-            c = copies[i % len(copies)]
-            for j, (_, fn) in enumerate(fns):
-                evs[i][j][0].record(stream)
-                fn(c)
-                evs[i][j][1].record(stream)
-        stop.record(stream)
-        torch.cuda.synchronize()
-        total_ms = start.elapsed_time(stop)
-        per = {lab: float(np.mean([evs[i][j][0].elapsed_time(evs[i][j][1]) for i in range(steps)]))
-               for j, (lab, _) in enumerate(fns)}
-        return total_ms / steps, per
-
-    # ---- the step: homomorphic analytics from compressed bytes ----------------------
-    def f_mean(c):
-        hsz.op_fused(c, hsz.DELTA, hsz.MEAN, out=S48[0], ws=ws[0], check=False, raw=True)
-
-    def f_var(c):
-        hsz.op_fused(c, hsz.QUANT, hsz.VAR, out=S48[1], ws=ws[1], check=False, raw=True)
-
-    def f_grad(c):
-        try:
-            hsz.op_fused(c, hsz.QUANT, hsz.GRADMAG, out=gbuf, ws=ws[2], check=False, raw=True)
-        except hsz.HszError as e:
-            if e.code != hsz.ERR_UNSUPPORTED:
-                raise
-            hsz.decompress_to_stage(c, hsz.QUANT, out=qbuf)
-            hsz.op_on_stage(hsz.stage_view(qbuf, h, hsz.QUANT), h, hsz.QUANT, hsz.GRADMAG, out=gbuf, ws=ws[2],
-                            check=False, raw=True)
-
-    sep_fns = [("mean_fused_delta", f_mean), ("var_fused_quant", f_var), ("gradmag_quant", f_grad)]
-    ms_sep, per_sep = timed("separate", sep_fns, a.steps, a.warmup)
-    st_v = hsz.stats_of(S48[1])
-    st_m = hsz.stats_of(S48[0])
-
-    # ---- the step: one batched pass, the three analytics sharing one decode -------------
-    # Per copy, a plan of three jobs (mean via D_p, variance via D_q,
-    # gradient magnitude via D_q) over the whole field; mean and variance are
-    # summed inside the gradient tiles.  Block indexes are built once per
-    # stream, as a resident stream keeps them.
-    for c in copies:
-        c.build_index()
-    if a.tune is None and not a.no_tune:
-        # the launch shape of the step's plan: the autotuner times each
-        # candidate on the actual jobs and rejects any that changes a result
-        from paper_2603_25206_amd import tune as tuner
-        jobs0 = [hsz.Job(copies[0], "mean", hsz.DELTA), hsz.Job(copies[0], "var", hsz.QUANT),
-                 hsz.Job(copies[0], "gradmag", hsz.QUANT)]
-        a.tune, _ = tuner.tune(jobs0, reps=5, cache_path=None)
-        log(f"[bench] step launch shape (autotuned): {a.tune}")
-    step_stream = torch.cuda.Stream()
-    plans = []
-    for c in copies:
-        jobs = [hsz.Job(c, "mean", hsz.DELTA), hsz.Job(c, "var", hsz.QUANT), hsz.Job(c, "gradmag", hsz.QUANT)]
-        plans.append(hsz.Plan(jobs, tune=a.tune, stream=step_stream))
-    for i in range(a.warmup):
-        plans[i % len(plans)].launch()
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(step_stream)
-    for i in range(a.steps):
-        evs[i][0].record(step_stream)
-        plans[i % len(plans)].launch()
-        evs[i][1].record(step_stream)
-    stop.record(step_stream)
-    torch.cuda.synchronize()
-    ms_step = start.elapsed_time(stop) / a.steps
-    ms_replay = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
-    res = plans[0].results()
-    if (res[1]["s1"], res[1]["s2"], res[1]["var"]) != (st_v["s1"], st_v["s2"], st_v["var"]) or \
-            res[0]["mean"] != st_m["mean"] or not torch.equal(res[2].reshape(-1), gbuf.view(torch.float32)):
-        raise RuntimeError("batched step disagrees with the separate operations")
-    for pl in plans:
-        pl.close()
-
-    # ---- baseline: full decompression + the same ops on floats ------------------------
-    def b_dec(c):
-        hsz.decompress_to_stage(c, hsz.FLOAT, out=fbuf)
-
-    fview = hsz.stage_view(fbuf, h, hsz.FLOAT)
-
-    def b_mean(c):
-        hsz.op_on_stage(fview, h, hsz.FLOAT, hsz.MEAN, out=S48[0], ws=ws[0], check=False, raw=True)
-
-    def b_var(c):
-        hsz.op_on_stage(fview, h, hsz.FLOAT, hsz.VAR, out=S48[1], ws=ws[1], check=False, raw=True)
-
-    def b_grad(c):
-        hsz.op_on_stage(fview, h, hsz.FLOAT, hsz.GRADMAG, out=gbuf, ws=ws[2], check=False, raw=True)
-
-    base_fns = [("decompress_float", b_dec), ("mean_float", b_mean), ("var_float", b_var), ("gradmag_float", b_grad)]
-    ms_base, per_base = timed("baseline", base_fns, max(5, a.steps // 2), 2)
-    st_bv = hsz.stats_of(S48[1])
-
-    # ---- per-stage table ------------------------------------------------------------
-    extra = {}
-    if not a.no_extra:
-        def dec(stage, out):
-            return lambda c: hsz.decompress_to_stage(c, stage, out=out)
-        rows = [("decompress_delta", dec(hsz.DELTA, dbuf)), ("decompress_quant", dec(hsz.QUANT, qbuf)),
-                ("decompress_float", dec(hsz.FLOAT, fbuf))]
-        _, per = timed("decode", rows, 6, 2)
-        extra.update(per)
-        dview = hsz.stage_view(dbuf, h, hsz.DELTA)
-        qview = hsz.stage_view(qbuf, h, hsz.QUANT)
-        rows = []
-        for stn, st, view in (("delta", hsz.DELTA, dview), ("quant", hsz.QUANT, qview), ("float", hsz.FLOAT, fview)):
-            for opn, op in (("mean", hsz.MEAN), ("var", hsz.VAR)):
-                rows.append((f"{opn}_on_{stn}", (lambda v, s_, o: lambda c: hsz.op_on_stage(
-                    v, h, s_, o, out=S48[2], ws=ws[2], check=False, raw=True))(view, st, op)))
-                rows.append((f"{opn}_fused_{stn}", (lambda s_, o: lambda c: hsz.op_fused(
-                    c, s_, o, out=S48[2], ws=ws[2], check=False, raw=True))(st, op)))
-        for stn, st, view in (("quant", hsz.QUANT, qview), ("float", hsz.FLOAT, fview)):
-            rows.append((f"gradmag_on_{stn}", (lambda v, s_: lambda c: hsz.op_on_stage(
-                v, h, s_, hsz.GRADMAG, out=gbuf, ws=ws[2], check=False, raw=True))(view, st)))
-            rows.append((f"laplacian_on_{stn}", (lambda v, s_: lambda c: hsz.op_on_stage(
-                v, h, s_, hsz.LAPLACIAN, out=gbuf, ws=ws[2], check=False, raw=True))(view, st)))
-            rows.append((f"laplacian_fused_{stn}", (lambda s_: lambda c: hsz.op_fused(
-                c, s_, hsz.LAPLACIAN, out=gbuf, ws=ws[2], check=False, raw=True))(st)))
-        _, per = timed("ops", rows, 6, 2)
-        extra.update(per)
-        # compression (input resident in HBM)
-        cbuf = torch.empty_like(c0.data)
-
-        def comp(c):
-            hsz.compress(xg, a.eb, rel=True, block=a.block, out=cbuf, check=False)
-        _, per = timed("compress", [("compress", comp)], 4, 1)
-        extra.update(per)
+    main_row, h = measure_config(a, xg, a.eb, a.block, full=not a.no_extra, tune=a.tune)
     if a.calibrate_copy:
         # a plain streaming kernel of known traffic for scaling memory counters:
         # bitwise NOT of 2^27 int32 reads 512 MiB and writes 512 MiB
@@ -308,42 +394,21 @@ def main():
         for _ in range(3):
             torch.bitwise_not(src, out=dst)
         torch.cuda.synchronize()
+        del src, dst
 
-    # ---- roofline of the dominant kernel of the step -------------------------------------
-    cbytes = c0.nbytes
-    alg = {  # algorithmic bytes per launch (compressed input + outputs; never the avoided floats)
-        "mean_fused_delta": cbytes,
-        "var_fused_quant": cbytes,
-        "gradmag_quant": cbytes + 4 * n,  # fused: read the compressed stream once, write the f32 magnitude
-        "decompress_quant": cbytes + 4 * n,
-        "decompress_float": cbytes + 4 * n,
-        "decompress_delta": cbytes + 4 * n + 4 * h.nb,
-        "gradmag_on_quant": 8 * n,
-        "gradmag_float": 8 * n,
-    }
-    # dominant kernel of the step: the batched gradient kernel with shared
-    # statistics; its algorithmic bytes are the compressed stream read once
-    # plus the f32 magnitude written (the sums add none).  Its duration is
-    # the HIP-event time of one plan launch, which also holds the reset and
-    # finalize kernels and the gaps between them, so 'achieved' is a lower
-    # bound on the kernel's own rate.
-    alg_step = cbytes + 4 * n
-    achieved = alg_step / (ms_replay * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "k_batch_grad<32,3,4,float,1> (mean+var+gradmag, one decode)",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": a.traffic if a.traffic is not None else counter_traffic(),
-                "valu": counter_valu(ms_replay),
-                "alg_bytes_per_launch": int(alg_step), "launch_ms": round(ms_replay, 4)}
-    dom = "gradmag_quant"
-    ach_sep = alg[dom] / (per_sep[dom] * 1e-3) / 1e9
-    roofline_sep = {"bound": "hbm", "kernel": "k_grad_fused<32,3,4,float> (gradmag alone)",
-                    "achieved": round(ach_sep, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach_sep / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": int(alg[dom]),
-                    "launch_ms": round(per_sep[dom], 4)}
+    roofline = dict(main_row["roofline"])
+    roofline["traffic"] = a.traffic if a.traffic is not None else counter_traffic()
+    roofline["valu"] = counter_valu(main_row["plan_ms_direct"])
+    kt = ktrace_record()
+    if kt is not None and kt.get("kernel", "") in roofline["kernel"]:
+        own = roofline["alg_bytes_per_launch"] / (kt["avg_us"] * 1e-6) / 1e9
+        roofline["frac_kernel"] = round(own / HBM_PEAK_GBS, 4)
+        roofline["kernel_avg_us_profiled"] = kt["avg_us"]
+    else:
+        roofline["frac_kernel"] = None
 
+    ms_step = main_row["ms_per_step"]
     value = orig_bytes / (ms_step * 1e-3) / 1e9
-    base_value = orig_bytes / (ms_base * 1e-3) / 1e9
     out = {
         "metric": "GB/s (orig. data) homomorphic op vs full-decompress+op at eb; p50/p99 query ms",
         "value": round(value, 1),
@@ -351,7 +416,7 @@ def main():
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -360,22 +425,26 @@ def main():
         "config": {"workload": f"{'x'.join(map(str, shape))} f32 gaussian-mixture x lognormal texture, "
                                f"rel eb {a.eb:g}, S={a.block}; step = mean(D_p) + var(D_q) + gradmag(D_q) "
                                f"from the compressed bytes, one batched pass (one plan launch)",
-                   "global_batch": 1, "field_bytes": orig_bytes, "compressed_bytes": cbytes,
-                   "ratio": round(c0.ratio, 3), "parallelism": "single-gpu"},
-        "separate_ops": {"value": round(orig_bytes / (ms_sep * 1e-3) / 1e9, 1), "unit": "GB/s",
-                         "ms_per_step": round(ms_sep, 4), "per_op_ms": {k: round(v, 4) for k, v in per_sep.items()},
-                         "roofline": roofline_sep},
-        "full_decompress_baseline": {"value": round(base_value, 1), "unit": "GB/s", "ms_per_step": round(ms_base, 4),
-                                     "per_op_ms": {k: round(v, 4) for k, v in per_base.items()},
-                                     "speedup_homomorphic": round(ms_base / ms_step, 3),
-                                     "speedup_separate_ops": round(ms_base / ms_sep, 3)},
-        "stage_table_ms": {k: round(v, 4) for k, v in extra.items()},
-        "step_launch_shape": a.tune,
+                   "global_batch": 1, "field_bytes": orig_bytes, "compressed_bytes": main_row["compressed_bytes"],
+                   "ratio": main_row["ratio"], "parallelism": "single-gpu"},
+        "separate_ops": main_row["separate_ops"],
+        "full_decompress_baseline": main_row["full_decompress_baseline"],
+        "stage_table_ms": main_row.get("stage_table_ms", {}),
+        "step_launch_shape": main_row["launch_shape"],
+        "plan_ms_direct": main_row["plan_ms_direct"],
+        "plan_ms_graph_replay": main_row["plan_ms_graph_replay"],
         "roofline": roofline,
-        "check": {"var_int_route": st_v["var"], "var_float_route": st_bv["var"], "mean": st_m["mean"]},
+        "check": main_row["check"],
     }
-
-    del copies, plans, gbuf, qbuf, fbuf, dbuf
+    if not a.no_configs:
+        rows = []
+        for eb, block in ((1e-4, 32), (1e-4, 64), (1e-2, 32), (1e-2, 64)):
+            if (eb, block) == (a.eb, a.block):
+                continue
+            r, _ = measure_config(a, xg, eb, block, full=False)
+            rows.append(r)
+        out["large_field_configs"] = rows
+    del xg
     torch.cuda.empty_cache()
     if not a.no_vector:
         out["vector_field"] = bench_vector(a, log)
@@ -401,18 +470,31 @@ def main():
 
 
 def _events_ms(fn, reps, stream):
+    """Median HIP-event time of one call; fn is a callable or a list of
+    callables (the same work over distinct copies of its inputs), called in
+    turn so that no timed call reads bytes the previous one left in cache."""
     import torch
-    fn()
+    fns = fn if isinstance(fn, (list, tuple)) else [fn]
+    for f in fns:
+        f()
     torch.cuda.synchronize()
     ts = []
-    for _ in range(reps):
+    for r in range(max(reps, len(fns))):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        fn()
+        fns[r % len(fns)]()
         e1.record(stream)
         e1.synchronize()
         ts.append(e0.elapsed_time(e1))
     return float(np.median(ts))
+
+
+ROT = 3  # copies of every secondary row's inputs (each >= 512 MiB for the 512^3 fields)
+
+
+def _clones(c, k=ROT):
+    from paper_2603_25206_amd import hsz
+    return [c] + [hsz.Compressed(c.data.clone(), c.header) for _ in range(k - 1)]
 
 
 def bench_vector(a, log):
@@ -420,7 +502,8 @@ def bench_vector(a, log):
     component the large-field recipe with its own seed, rel eb 1e-4, S=32):
     divergence and curl straight from the three streams through D_q, on the
     materialised quantized stage, and after full decompression of every
-    component (decode to floats + the operation on the floats)."""
+    component (decode to floats + the operation on the floats).  Three
+    copies of the streams and of the stage buffers are used in turn."""
     import torch
 
     from paper_2603_25206_amd import hsz, synth
@@ -433,6 +516,7 @@ def bench_vector(a, log):
         orig += f.numel() * f.element_size()
         del f
     torch.cuda.synchronize()
+    sets = list(zip(*[_clones(c) for c in comps]))  # ROT sets of three components
     dev = comps[0].data.device
     cur = torch.cuda.current_stream()
     headers = [c.header for c in comps]
@@ -440,33 +524,37 @@ def bench_vector(a, log):
     outs = [torch.empty(4 * n, dtype=torch.uint8, device=dev) for _ in range(3)]
     ws = hsz.workspace(hsz.vector_workspace_bytes(headers), dev, key="bench-vec")
     res = {"components": 3, "shape": list(shape), "orig_bytes": orig,
-           "compressed_bytes": sum(c.nbytes for c in comps)}
-    qbufs = [torch.empty(4 * n, dtype=torch.uint8, device=dev) for _ in range(3)]
-    fbufs = [torch.empty(4 * n + 64, dtype=torch.uint8, device=dev) for _ in range(3)]
+           "compressed_bytes": sum(c.nbytes for c in comps), "copies": ROT}
+    qbufs = [[torch.empty(4 * n, dtype=torch.uint8, device=dev) for _ in range(3)] for _ in range(ROT)]
+    fbufs = [[torch.empty(4 * n + 64, dtype=torch.uint8, device=dev) for _ in range(3)] for _ in range(ROT)]
     for op in ("divergence", "curl"):
         nout = 3 if op == "curl" else 1
 
-        def fused():
-            hsz.vector_op_fused(comps, op, outs=outs[:nout], ws=ws, check=False)
+        def fused(k):
+            return lambda: hsz.vector_op_fused(list(sets[k]), op, outs=outs[:nout], ws=ws, check=False)
 
-        def on_q():
-            for c, b in zip(comps, qbufs):
-                hsz.decompress_to_stage(c, hsz.QUANT, out=b)
-            hsz.vector_op_on_stage([b[: 4 * n] for b in qbufs], headers, hsz.QUANT, op, outs=outs[:nout], ws=ws,
-                                   check=False)
+        def on_q(k):
+            def f():
+                for c, b in zip(sets[k], qbufs[k]):
+                    hsz.decompress_to_stage(c, hsz.QUANT, out=b)
+                hsz.vector_op_on_stage([b[: 4 * n] for b in qbufs[k]], headers, hsz.QUANT, op, outs=outs[:nout],
+                                       ws=ws, check=False)
+            return f
 
-        def full():
-            for c, b in zip(comps, fbufs):
-                hsz.decompress_to_stage(c, hsz.FLOAT, out=b)
-            hsz.vector_op_on_stage(fbufs, headers, hsz.FLOAT, op, outs=outs[:nout], ws=ws, check=False)
-        ms_f = _events_ms(fused, 5, cur)
-        ms_q = _events_ms(on_q, 5, cur)
-        ms_b = _events_ms(full, 5, cur)
+        def full(k):
+            def f():
+                for c, b in zip(sets[k], fbufs[k]):
+                    hsz.decompress_to_stage(c, hsz.FLOAT, out=b)
+                hsz.vector_op_on_stage(fbufs[k], headers, hsz.FLOAT, op, outs=outs[:nout], ws=ws, check=False)
+            return f
+        ms_f = _events_ms([fused(k) for k in range(ROT)], 6, cur)
+        ms_q = _events_ms([on_q(k) for k in range(ROT)], 6, cur)
+        ms_b = _events_ms([full(k) for k in range(ROT)], 6, cur)
         res[op] = {"fused_quant_ms": round(ms_f, 4), "gbs_orig": round(orig / ms_f / 1e6, 1),
                    "decompress_quant_then_op_ms": round(ms_q, 4), "full_decompress_then_op_ms": round(ms_b, 4),
                    "speedup_vs_full_decompress": round(ms_b / ms_f, 3)}
     log(f"[bench] vector field: {res}")
-    del comps, outs, qbufs, fbufs
+    del comps, sets, outs, qbufs, fbufs
     return res
 
 
@@ -477,7 +565,8 @@ def bench_hszx(a, log):
     the spread about the integer metadata mean via D_p (Sec. V-A),
     the gradient magnitude (fused from the delta stream; decode to D_q then
     the stencil for block-mean streams), and full decompression + the mean
-    on floats."""
+    on floats.  Three copies of each stream and stage buffer are used in
+    turn."""
     import torch
 
     from paper_2603_25206_amd import hsz, synth
@@ -487,14 +576,15 @@ def bench_hszx(a, log):
     dev, cur = x.device, torch.cuda.current_stream()
     orig = x.numel() * x.element_size()
     n = x.numel()
-    res = {"shape": list(shape), "orig_bytes": orig}
+    res = {"shape": list(shape), "orig_bytes": orig, "copies": ROT}
     s48 = torch.empty(64, dtype=torch.uint8, device=dev)
     gbuf = torch.empty(4 * n, dtype=torch.uint8, device=dev)
-    qbuf = torch.empty(4 * n, dtype=torch.uint8, device=dev)
-    fbuf = torch.empty(4 * n + 64, dtype=torch.uint8, device=dev)
+    qbufs = [torch.empty(4 * n, dtype=torch.uint8, device=dev) for _ in range(ROT)]
+    fbufs = [torch.empty(4 * n + 64, dtype=torch.uint8, device=dev) for _ in range(ROT)]
     for mode, mean_dec in (("delta", False), ("block_mean", True)):
         c = hsz.compress(x, a.eb, rel=True, block=a.block, mean_dec=mean_dec)
         torch.cuda.synchronize()
+        cs = _clones(c)
         h = c.header
         ws = hsz.workspace(max(hsz.op_workspace_bytes(h, op) for op in (hsz.MEAN, hsz.VAR, hsz.GRADMAG)), dev,
                            key="bench-hszx")
@@ -503,21 +593,24 @@ def bench_hszx(a, log):
             hsz.compress(x, a.eb, rel=True, block=a.block, mean_dec=mean_dec)
 
         def stat(via, op):
-            return lambda: hsz.op_fused(c, via, op, out=s48, ws=ws, check=False, raw=True)
+            return [lambda ck=ck: hsz.op_fused(ck, via, op, out=s48, ws=ws, check=False, raw=True) for ck in cs]
 
-        def grad():
-            if mean_dec:
-                hsz.decompress_to_stage(c, hsz.QUANT, out=qbuf)
-                hsz.op_on_stage(hsz.stage_view(qbuf, h, hsz.QUANT), h, hsz.QUANT, hsz.GRADMAG, out=gbuf, ws=ws,
+        def grad(k):
+            def f():
+                if mean_dec:
+                    hsz.decompress_to_stage(cs[k], hsz.QUANT, out=qbufs[k])
+                    hsz.op_on_stage(hsz.stage_view(qbufs[k], h, hsz.QUANT), h, hsz.QUANT, hsz.GRADMAG, out=gbuf,
+                                    ws=ws, check=False, raw=True)
+                else:
+                    hsz.op_fused(cs[k], hsz.QUANT, hsz.GRADMAG, out=gbuf, ws=ws, check=False, raw=True)
+            return f
+
+        def full_mean(k):
+            def f():
+                hsz.decompress_to_stage(cs[k], hsz.FLOAT, out=fbufs[k])
+                hsz.op_on_stage(hsz.stage_view(fbufs[k], h, hsz.FLOAT), h, hsz.FLOAT, hsz.MEAN, out=s48, ws=ws,
                                 check=False, raw=True)
-            else:
-                hsz.op_fused(c, hsz.QUANT, hsz.GRADMAG, out=gbuf, ws=ws, check=False, raw=True)
-
-        fview = hsz.stage_view(fbuf, h, hsz.FLOAT)
-
-        def full_mean():
-            hsz.decompress_to_stage(c, hsz.FLOAT, out=fbuf)
-            hsz.op_on_stage(fview, h, hsz.FLOAT, hsz.MEAN, out=s48, ws=ws, check=False, raw=True)
+            return f
 
         r = {"ratio": round(c.ratio, 3), "compress_ms": round(_events_ms(comp, 5, cur), 4)}
         if mean_dec:
@@ -528,8 +621,8 @@ def bench_hszx(a, log):
         r["var_quant_ms"] = round(_events_ms(stat(hsz.QUANT, hsz.VAR), 10, cur), 4)
         if mean_dec:
             r["var_mt_delta_ms"] = round(_events_ms(stat(hsz.DELTA, hsz.VAR_MT), 10, cur), 4)
-        r["gradmag_ms"] = round(_events_ms(grad, 5, cur), 4)
-        r["full_decompress_mean_ms"] = round(_events_ms(full_mean, 5, cur), 4)
+        r["gradmag_ms"] = round(_events_ms([grad(k) for k in range(ROT)], 6, cur), 4)
+        r["full_decompress_mean_ms"] = round(_events_ms([full_mean(k) for k in range(ROT)], 6, cur), 4)
         if mean_dec:
             r["mean_meta_gbs_orig"] = round(orig / r["mean_meta_ms"] / 1e6, 1)
             r["speedup_mean_meta_vs_full"] = round(r["full_decompress_mean_ms"] / r["mean_meta_ms"], 2)
@@ -538,9 +631,9 @@ def bench_hszx(a, log):
                 raise RuntimeError("mean from the block means is farther than eps from the exact mean")
         r["eb_abs"] = h.eb_abs
         res[mode] = r
-        del c, ws
+        del c, cs, ws
     log(f"[bench] block-mean: {res}")
-    del x, gbuf, qbuf, fbuf
+    del x, gbuf, qbufs, fbufs
     return res
 
 
@@ -551,7 +644,8 @@ def bench_lorenzo(a, log):
     axis on D_p (Eq. (derivative_Dp)) against the same derivative from D_q
     (decode to D_q + stencil) and after full decompression; and the same
     field as an HSZp stream (deltas across block borders of the flat field):
-    ratio, compression, D_p and D_q decoding, mean and variance on D_p."""
+    ratio, compression, D_p and D_q decoding, mean and variance on D_p.
+    Three copies of each stream and stage buffer are used in turn."""
     import torch
 
     from paper_2603_25206_amd import hsz, synth
@@ -563,53 +657,58 @@ def bench_lorenzo(a, log):
     n = x.numel()
     c = hsz.compress(x, a.eb, rel=True, block=a.block, lorenzo=True)
     torch.cuda.synchronize()
+    cs = _clones(c)
     h = c.header
     ws = hsz.workspace(hsz.op_workspace_bytes(h, hsz.DERIV), dev, key="bench-lz")
     s48 = torch.empty(64, dtype=torch.uint8, device=dev)
     obuf = torch.empty(4 * n, dtype=torch.uint8, device=dev)
-    sbuf = torch.empty(4 * n, dtype=torch.uint8, device=dev)
-    res = {"shape": list(shape), "orig_bytes": orig, "ratio": round(c.ratio, 3),
+    sbufs = [torch.empty(4 * n, dtype=torch.uint8, device=dev) for _ in range(ROT)]
+
+    def each(f):
+        return [(lambda k=k: f(k)) for k in range(ROT)]
+    res = {"shape": list(shape), "orig_bytes": orig, "ratio": round(c.ratio, 3), "copies": ROT,
            "compress_ms": round(_events_ms(lambda: hsz.compress(x, a.eb, rel=True, block=a.block, lorenzo=True), 5,
                                            cur), 4)}
     for st, name in ((hsz.DELTA, "decode_p_ms"), (hsz.QUANT, "decode_q_ms"), (hsz.FLOAT, "decode_f_ms")):
-        res[name] = round(_events_ms(lambda: hsz.decompress_to_stage(c, st, out=sbuf), 5, cur), 4)
-    res["mean_p_ms"] = round(_events_ms(lambda: hsz.op_fused(c, hsz.DELTA, hsz.MEAN, out=s48, ws=ws, check=False,
-                                                             raw=True), 10, cur), 4)
-    res["var_p_ms"] = round(_events_ms(lambda: hsz.op_fused(c, hsz.DELTA, hsz.VAR, out=s48, ws=ws, check=False,
-                                                            raw=True), 10, cur), 4)
-    fview = hsz.stage_view(sbuf, h, hsz.FLOAT)
-    qview = hsz.stage_view(sbuf, h, hsz.QUANT)
+        res[name] = round(_events_ms(each(lambda k: hsz.decompress_to_stage(cs[k], st, out=sbufs[k])), 6, cur), 4)
+    res["mean_p_ms"] = round(_events_ms(each(lambda k: hsz.op_fused(cs[k], hsz.DELTA, hsz.MEAN, out=s48, ws=ws,
+                                                                    check=False, raw=True)), 10, cur), 4)
+    res["var_p_ms"] = round(_events_ms(each(lambda k: hsz.op_fused(cs[k], hsz.DELTA, hsz.VAR, out=s48, ws=ws,
+                                                                   check=False, raw=True)), 10, cur), 4)
     for ax in range(len(shape)):
         r = {}
-        r["via_p_ms"] = round(_events_ms(lambda: hsz.op_fused(c, hsz.DELTA, hsz.DERIV, axis=ax, out=obuf, ws=ws,
-                                                              check=False, raw=True), 5, cur), 4)
+        r["via_p_ms"] = round(_events_ms(each(lambda k: hsz.op_fused(cs[k], hsz.DELTA, hsz.DERIV, axis=ax, out=obuf,
+                                                                     ws=ws, check=False, raw=True)), 6, cur), 4)
 
-        def via_q():
-            hsz.decompress_to_stage(c, hsz.QUANT, out=sbuf)
-            hsz.op_on_stage(qview, h, hsz.QUANT, hsz.DERIV, axis=ax, out=obuf, ws=ws, check=False, raw=True)
+        def via_q(k):
+            hsz.decompress_to_stage(cs[k], hsz.QUANT, out=sbufs[k])
+            hsz.op_on_stage(hsz.stage_view(sbufs[k], h, hsz.QUANT), h, hsz.QUANT, hsz.DERIV, axis=ax, out=obuf,
+                            ws=ws, check=False, raw=True)
 
-        def full():
-            hsz.decompress_to_stage(c, hsz.FLOAT, out=sbuf)
-            hsz.op_on_stage(fview, h, hsz.FLOAT, hsz.DERIV, axis=ax, out=obuf, ws=ws, check=False, raw=True)
-        r["decode_q_then_deriv_ms"] = round(_events_ms(via_q, 5, cur), 4)
-        r["full_decompress_then_deriv_ms"] = round(_events_ms(full, 5, cur), 4)
+        def full(k):
+            hsz.decompress_to_stage(cs[k], hsz.FLOAT, out=sbufs[k])
+            hsz.op_on_stage(hsz.stage_view(sbufs[k], h, hsz.FLOAT), h, hsz.FLOAT, hsz.DERIV, axis=ax, out=obuf,
+                            ws=ws, check=False, raw=True)
+        r["decode_q_then_deriv_ms"] = round(_events_ms(each(via_q), 6, cur), 4)
+        r["full_decompress_then_deriv_ms"] = round(_events_ms(each(full), 6, cur), 4)
         res[f"deriv_axis{ax}"] = r
     # HSZp: deltas across the blocks of the flat field (device-wide prefix sum for D_q)
     cf = hsz.compress(x, a.eb, rel=True, block=a.block, inter_block=True)
     torch.cuda.synchronize()
+    cfs = _clones(cf)
     wsf = hsz.workspace(hsz.op_workspace_bytes(cf.header, hsz.VAR), dev, key="bench-flat")
     flat = {"ratio": round(cf.ratio, 3),
             "compress_ms": round(_events_ms(lambda: hsz.compress(x, a.eb, rel=True, block=a.block,
                                                                  inter_block=True), 5, cur), 4)}
     for st, name in ((hsz.DELTA, "decode_p_ms"), (hsz.QUANT, "decode_q_ms")):
-        flat[name] = round(_events_ms(lambda: hsz.decompress_to_stage(cf, st, out=sbuf), 5, cur), 4)
-    flat["mean_p_ms"] = round(_events_ms(lambda: hsz.op_fused(cf, hsz.DELTA, hsz.MEAN, out=s48, ws=wsf, check=False,
-                                                              raw=True), 10, cur), 4)
-    flat["var_p_ms"] = round(_events_ms(lambda: hsz.op_fused(cf, hsz.DELTA, hsz.VAR, out=s48, ws=wsf, check=False,
-                                                             raw=True), 10, cur), 4)
+        flat[name] = round(_events_ms(each(lambda k: hsz.decompress_to_stage(cfs[k], st, out=sbufs[k])), 6, cur), 4)
+    flat["mean_p_ms"] = round(_events_ms(each(lambda k: hsz.op_fused(cfs[k], hsz.DELTA, hsz.MEAN, out=s48, ws=wsf,
+                                                                     check=False, raw=True)), 10, cur), 4)
+    flat["var_p_ms"] = round(_events_ms(each(lambda k: hsz.op_fused(cfs[k], hsz.DELTA, hsz.VAR, out=s48, ws=wsf,
+                                                                    check=False, raw=True)), 10, cur), 4)
     res["inter_block_1d"] = flat
     log(f"[bench] lorenzo-nd / inter-block: {res}")
-    del x, c, cf, ws, wsf, obuf, sbuf
+    del x, c, cs, cf, cfs, ws, wsf, obuf, sbufs
     return res
 
 
@@ -655,9 +754,12 @@ def bench_ooc(a, log):
 def bench_batches(a, log):
     """Many fields of uneven shapes analysed in one pass: each field gets mean
     (via D_p), variance (via D_q) and gradient magnitude (via D_q).  Timed as
-    a plan launch with the autotuned launch shape, against the same
-    jobs as separate single-field launches and against full decompression +
-    the operations on floats."""
+    a plan launch with the autotuned launch shape (workgroups per CU, planes
+    per tile, workgroup shape of the gradient tiles), enqueued directly and
+    replayed as the HIP graph captured at creation, against the same jobs as
+    separate single-field launches and against full decompression + the
+    operations on floats.  Three copies of every batch are launched in turn
+    (the tuner's candidates too)."""
     import torch
 
     from paper_2603_25206_amd import hsz, synth, tune
@@ -676,48 +778,67 @@ def bench_batches(a, log):
             comps.append(hsz.compress(f, rel, rel=True, block=32))
             orig += f.numel() * f.element_size()
             del f
-        jobs = []
-        for c in comps:
-            jobs += [hsz.Job(c, "mean", hsz.DELTA), hsz.Job(c, "var", hsz.QUANT), hsz.Job(c, "gradmag", hsz.QUANT)]
-        best, timings = tune.tune(jobs, reps=3, cache_path=None)
-        plan = hsz.Plan(jobs, tune=best)
-        ms_plan = _events_ms(plan.launch, 5, plan.stream)
-        plan.close()
-        plan = hsz.Plan(jobs, tune=dict(best, separate_stats=1))
-        ms_plan_sep = _events_ms(plan.launch, 5, plan.stream)
-        plan.close()
+        sets = list(zip(*[_clones(c) for c in comps]))
+        for cs in sets:
+            for c in cs:
+                c.build_index()
+
+        def jobs_of(cs):
+            js = []
+            for c in cs:
+                js += [hsz.Job(c, "mean", hsz.DELTA), hsz.Job(c, "var", hsz.QUANT), hsz.Job(c, "gradmag", hsz.QUANT)]
+            return js
+        jobsets = [jobs_of(cs) for cs in sets]
+        best, timings = tune.tune(jobsets[0], reps=3, cache_path=None, alternates=jobsets[1:])
+        st = torch.cuda.Stream()
+        row = {"fields": len(comps), "jobs": len(jobsets[0]), "orig_bytes": orig,
+               "compressed_bytes": sum(c.nbytes for c in comps), "copies": ROT,
+               "autotuned": best, "candidates_tried": len(timings)}
+        ref = None
+        for label, t in (("plan_ms", best), ("plan_ms_graph_replay", dict(best, graph_replay=1)),
+                         ("plan_separate_stats_ms", dict(best, separate_stats=1))):
+            plans = [hsz.Plan(js, tune=t, stream=st) for js in jobsets]
+            row[label] = round(_events_ms([p.launch for p in plans], 6, st), 4)
+            got = plans[0].results()
+            for p in plans:
+                p.close()
+            if ref is None:
+                ref = got
+            elif not all(tune._same(x, y) for x, y in zip(ref, got)):
+                raise RuntimeError(f"batch results differ between launch modes ({label})")
         cur = torch.cuda.current_stream()
-        outs = [hsz._result_for(j, comps[0].data.device)[0] for j in jobs]
+        dev = comps[0].data.device
+        outs = [hsz._result_for(j, dev)[0] for j in jobsets[0]]
         wsz = max(hsz.op_workspace_bytes(c.header, hsz.GRADMAG) for c in comps)
-        ws = hsz.workspace(wsz, comps[0].data.device, key="bench-single")
+        ws = hsz.workspace(wsz, dev, key="bench-single")
 
-        def singles():
-            for j, o in zip(jobs, outs):
-                hsz.op_fused(j.c, j.via, j.op, out=o, ws=ws, check=False, raw=True)
-        ms_single = _events_ms(singles, 3, cur)
-        fbufs = [torch.empty(c.header.n * (4 if c.header.dtype == 1 else 8) + 64, dtype=torch.uint8,
-                             device=c.data.device) for c in comps[:1]]
+        def singles(k):
+            def f():
+                for j, o in zip(jobsets[k], outs):
+                    hsz.op_fused(j.c, j.via, j.op, out=o, ws=ws, check=False, raw=True)
+            return f
+        ms_single = _events_ms([singles(k) for k in range(ROT)], 3, cur)
+        fsize = max(c.header.n * (4 if c.header.dtype == 1 else 8) for c in comps) + 64
+        fbufs = [torch.empty(fsize, dtype=torch.uint8, device=dev) for _ in range(ROT)]
 
-        def baseline():
-            for c, j0 in zip(comps, range(len(comps))):
-                fb = fbufs[0]
-                if fb.numel() < c.header.n * (4 if c.header.dtype == 1 else 8):
-                    fb = fbufs[0] = torch.empty(c.header.n * 8 + 64, dtype=torch.uint8, device=c.data.device)
-                hsz.decompress_to_stage(c, hsz.FLOAT, out=fb)
-                fv = hsz.stage_view(fb, c.header, hsz.FLOAT)
-                for op, o in ((hsz.MEAN, outs[3 * j0]), (hsz.VAR, outs[3 * j0 + 1]), (hsz.GRADMAG, outs[3 * j0 + 2])):
-                    hsz.op_on_stage(fv, c.header, hsz.FLOAT, op, out=o, ws=ws, check=False, raw=True)
-        ms_base = _events_ms(baseline, 3, cur)
-        res[name] = {"fields": len(comps), "jobs": len(jobs), "orig_bytes": orig,
-                     "compressed_bytes": sum(c.nbytes for c in comps),
-                     "plan_ms": round(ms_plan, 4), "gbs_orig": round(orig / ms_plan / 1e6, 1),
-                     "plan_separate_stats_ms": round(ms_plan_sep, 4),
-                     "single_launches_ms": round(ms_single, 4), "full_decompress_ms": round(ms_base, 4),
-                     "speedup_vs_single": round(ms_single / ms_plan, 3),
-                     "speedup_vs_full_decompress": round(ms_base / ms_plan, 3),
-                     "autotuned": best, "candidates_tried": len(timings)}
-        log(f"[bench] batch {name}: {res[name]}")
-        del comps, jobs, outs, fbufs
+        def baseline(k):
+            def f():
+                for j0, c in enumerate(sets[k]):
+                    hsz.decompress_to_stage(c, hsz.FLOAT, out=fbufs[k])
+                    fv = hsz.stage_view(fbufs[k], c.header, hsz.FLOAT)
+                    for op, o in ((hsz.MEAN, outs[3 * j0]), (hsz.VAR, outs[3 * j0 + 1]),
+                                  (hsz.GRADMAG, outs[3 * j0 + 2])):
+                        hsz.op_on_stage(fv, c.header, hsz.FLOAT, op, out=o, ws=ws, check=False, raw=True)
+            return f
+        ms_base = _events_ms([baseline(k) for k in range(ROT)], 3, cur)
+        ms_plan = row["plan_ms"]
+        row.update({"gbs_orig": round(orig / ms_plan / 1e6, 1),
+                    "single_launches_ms": round(ms_single, 4), "full_decompress_ms": round(ms_base, 4),
+                    "speedup_vs_single": round(ms_single / ms_plan, 3),
+                    "speedup_vs_full_decompress": round(ms_base / ms_plan, 3)})
+        res[name] = row
+        log(f"[bench] batch {name}: {row}")
+        del comps, sets, jobsets, outs, fbufs
         torch.cuda.empty_cache()
     return res
 

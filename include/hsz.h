@@ -417,6 +417,14 @@ typedef struct hsz_tuning {
                                   0 (default) enqueues the pass's kernels directly,
                                   which reaches the GPU sooner for these few-kernel
                                   passes (the work table is on the device either way) */
+  int32_t grad_tile_x;         /* workgroup shape of binary32 gradient-magnitude jobs
+                                  through D_q that admit the narrow tiles (max|q| < 8192,
+                                  blocks of 32, rows on block boundaries): 0 (default) the
+                                  widest admitted -- 512 columns x 16 rows by 512 threads
+                                  for boxes wider than 256 columns with a width divisible
+                                  by 8, else 256 x 16 by 256 threads; 256 always the
+                                  latter; -1 the general tile (any stream).  The values
+                                  are bit-identical whichever tile runs */
 } hsz_tuning;
 
 /* Workspace a batch needs (bytes). */

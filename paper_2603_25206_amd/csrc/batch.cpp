@@ -154,8 +154,10 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
     const Item& it = items[i];
     if (it.kind == 0) order_stats[it.S == 64].push_back(i);
     else {
-      const bool q4 = acc_mode[i] != 2 && hsz::q4_eligible(it.v, it.via, it.op, it.t.d, it.t.box);
-      order_grad[q4 ? variant_q4(it.S, hsz::q4_txl(it.t.box), acc_mode[i])
+      const bool q4 =
+          tune.grad_tile_x >= 0 && acc_mode[i] != 2 && hsz::q4_eligible(it.v, it.via, it.op, it.t.d, it.t.box);
+      const int txl = tune.grad_tile_x == 256 ? 256 : hsz::q4_txl(it.t.box);
+      order_grad[q4 ? variant_q4(it.S, txl, acc_mode[i])
                     : variant_of(it.S, it.via, it.op, it.dtype, acc_mode[i])].push_back(i);
       if (!it.index) grads.push_back(i);  // jobs that need an index built here
     }
@@ -253,7 +255,8 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
       const hsz::GradJob& J = gj[order_grad[g][k]];
       ((hsz::GradJob*)at(L.grad_jobs[g]))[k] = J;
       ((int64_t*)at(L.grad_start[g]))[k] = tiles;
-      tiles += is_q4(g) ? hsz::q4_tiles(J.b, J.tz, J.d) : hsz::grad_tiles(J.b, J.tz);
+      tiles += is_q4(g) ? hsz::q4_tiles(J.b, J.tz, ((g - kVariantsGeneral) & 2) ? 512 : 256)
+                        : hsz::grad_tiles(J.b, J.tz);
       km = std::max(km, J.kmax);
     }
     counts[2 * cslot_grad(g)] = (int64_t)order_grad[g].size();

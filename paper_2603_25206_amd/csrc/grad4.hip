@@ -903,8 +903,9 @@ size_t q4_lds() {
 size_t q8_lds() { return (size_t)kQ8LdsWords * sizeof(uint32_t); }
 
 hipError_t run_q4(const GradJob& job, int* status, hipStream_t s) {
-  const int64_t grid = q4_tiles(job.b, job.tz, job.d);
-  if (q4_txl(job.b) == 512)
+  const int txl = q4_txl(job.b);
+  const int64_t grid = q4_tiles(job.b, job.tz, txl);
+  if (txl == 512)
     hipLaunchKernelGGL(k_gradmag_q8, dim3((unsigned)grid), dim3(kQ8Threads), q8_lds(), s, job, status);
   else
     hipLaunchKernelGGL((k_gradmag_q4<32, 256>), dim3((unsigned)grid), dim3(kQ4Threads), (q4_lds<32, 256>()), s, job,
@@ -928,8 +929,7 @@ bool q4_eligible(const StreamView& v, int via, int op, const Dims3& d, const Box
          v.nb < (1ll << 29) && b.volume() < (1ll << 29);
 }
 
-int64_t q4_tiles(const Box3& b, int tz, const Dims3&) {
-  const int txl = q4_txl(b);
+int64_t q4_tiles(const Box3& b, int tz, int txl) {
   const int ty = txl == 512 ? kQ8TY : Q4<32, 256>::kTY;
   const int64_t ntx = (b.x1 - b.x0 + txl - 1) / txl, nty = (b.y1 - b.y0 + ty - 1) / ty;
   return ntx * nty * ((b.z1 - b.z0 + tz - 1) / tz);

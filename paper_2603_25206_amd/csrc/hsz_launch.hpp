@@ -158,8 +158,8 @@ int stats_kmax(const StreamView& v);
 // (grad4.hip): streams with max|q| < 8192 and boxes whose rows start on block
 // boundaries (q4_eligible); the same values as the general tile, bit for bit.
 bool q4_eligible(const StreamView& v, int via, int op, const Dims3& d, const Box3& b);
-int q4_txl(const Box3& b);                            // column tile: 256 or 512
-int64_t q4_tiles(const Box3& b, int tz, const Dims3& d);
+int q4_txl(const Box3& b);                            // column tile: 256 or 512 (widest admitted)
+int64_t q4_tiles(const Box3& b, int tz, int txl);     // tiles of a box with txl-column tiles
 int q4_tz(const Box3& b);                             // planes per tile of a single launch
 int q4_kmax(int S);
 hipError_t launch_gradmag_q4(const GradJob& job, int* status, hipStream_t s);

@@ -83,7 +83,8 @@ class Work(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("stats_waves_per_cu", ctypes.c_int32), ("grad_groups_per_cu", ctypes.c_int32),
-                ("grad_tz", ctypes.c_int32), ("separate_stats", ctypes.c_int32), ("graph_replay", ctypes.c_int32)]
+                ("grad_tz", ctypes.c_int32), ("separate_stats", ctypes.c_int32), ("graph_replay", ctypes.c_int32),
+                ("grad_tile_x", ctypes.c_int32)]
 
 
 EXPORTS = (
@@ -616,6 +617,9 @@ def _tuning(tune):
     t.grad_tz = int(tune.get("grad_tz", 0))
     t.separate_stats = int(bool(tune.get("separate_stats", False)))
     t.graph_replay = int(bool(tune.get("graph_replay", False)))
+    t.grad_tile_x = int(tune.get("grad_tile_x", 0))
+    if t.grad_tile_x not in (0, 256, 512, -1):
+        raise ValueError("grad_tile_x must be 0, 256, 512 or -1")
     return ctypes.byref(t)
 
 

@@ -1,6 +1,10 @@
 """Autotuner for batched passes: picks the launch shape (waves per CU of the
 statistics launch, workgroups per CU of the gradient launch, planes per
-gradient tile) by timing plan launches of the actual batch.
+gradient tile, and the gradient workgroup's shape: 512 x 16 columns x rows on
+512 threads, 256 x 16 on 256 threads, or the general tile) by timing plan
+launches of the actual batch.  Given several copies of the batch's streams
+(together larger than the last-level caches), it launches them in turn, so
+that no candidate is timed on cache-resident bytes.
 
 Every candidate must reproduce the reference results bit for bit (they are
 exact integer sums and identical per-element arithmetic whatever the launch
@@ -19,9 +23,12 @@ import torch
 
 from . import hsz
 
+# the narrow tiles (grad_tile_x 0 / 256) run at most two workgroups per
+# compute unit whatever grad_groups_per_cu asks, so that axis is swept for the
+# general tile only
 CANDIDATES = [
-    {"stats_waves_per_cu": w, "grad_groups_per_cu": g, "grad_tz": tz}
-    for w in (4, 8, 16) for g in (2, 4, 6) for tz in (16, 32, 64)
+    {"stats_waves_per_cu": w, "grad_groups_per_cu": g, "grad_tz": tz, "grad_tile_x": tx}
+    for w in (4, 8, 16) for tx in (0, 256, -1) for g in ((2, 4, 6) if tx == -1 else (2,)) for tz in (16, 32, 64)
 ]
 
 DEFAULT_CACHE = os.environ.get("HSZ_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "hsz_tune.json"))
@@ -50,33 +57,46 @@ def _same(a, b) -> bool:
     return torch.equal(a, b)
 
 
-def time_plan(plan: "hsz.Plan", reps: int) -> float:
-    plan.launch()  # warm
-    plan.stream.synchronize()
+def time_plan(plan, reps: int) -> float:
+    """Median HIP-event time of one launch; 'plan' is a Plan or a list of
+    Plans on one stream (the same batch over distinct copies), launched in
+    turn."""
+    plans = plan if isinstance(plan, (list, tuple)) else [plan]
+    stream = plans[0].stream
+    for p in plans:
+        p.launch()  # warm
+    stream.synchronize()
     times = []
-    for _ in range(reps):
+    for r in range(reps * len(plans)):
         start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        start.record(plan.stream)
-        plan.launch()
-        stop.record(plan.stream)
+        start.record(stream)
+        plans[r % len(plans)].launch()
+        stop.record(stream)
         stop.synchronize()
         times.append(start.elapsed_time(stop))
     return statistics.median(times)
 
 
-def tune(jobs, candidates=None, reps: int = 5, cache_path: str | None = DEFAULT_CACHE, log=None):
-    """Return (best tuning dict, {candidate index: ms}); updates the cache."""
+def tune(jobs, candidates=None, reps: int = 5, cache_path: str | None = DEFAULT_CACHE, log=None, alternates=()):
+    """Return (best tuning dict, {candidate index: ms}); updates the cache.
+
+    alternates: further job lists of the same batch over other copies of its
+    streams; each candidate's plans over all the copies are launched in turn."""
     candidates = CANDIDATES if candidates is None else candidates
     ref = hsz.batch_run(jobs)
     timings = {}
     best, best_ms = None, float("inf")
+    stream = torch.cuda.Stream()
     for k, cand in enumerate(candidates):
-        plan = hsz.Plan(jobs, tune=cand)
+        plans = []
         try:
-            ms = time_plan(plan, reps)
-            got = plan.results()
+            for js in [jobs, *alternates]:
+                plans.append(hsz.Plan(js, tune=cand, stream=stream))
+            ms = time_plan(plans, reps)
+            got = plans[0].results()
         finally:
-            plan.close()
+            for p in plans:
+                p.close()
         if not all(_same(a, b) for a, b in zip(ref, got)):
             raise RuntimeError(f"launch shape {cand} changed a result")
         timings[k] = ms

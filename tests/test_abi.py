@@ -308,3 +308,21 @@ def test_noalloc_validation_before_any_launch(lib):
     # the status output must be a 4-byte aligned device word
     assert lib.hsz_op_fused_noalloc(fake, hp, hsz.QUANT, hsz.VAR, 0, None, fake, 48, ctypes.c_void_p(0x10002),
                                     None) == hsz.ERR_INVALID_ARG
+
+
+def _struct_fields(name):
+    """Field names of a typedef'd struct in include/hsz.h, in order."""
+    import re
+    text = open(os.path.join(ROOT, "include", "hsz.h")).read()
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    return re.findall(r"\b(?:u?int\d+_t|double|float|int)\s+\**(\w+)", body)
+
+
+def test_tuning_struct_matches_header():
+    assert _struct_fields("hsz_tuning") == [f for f, _ in hsz.Tuning._fields_]
+    for bad in (1, 128, 1024, -2):
+        with pytest.raises(ValueError):
+            hsz._tuning({"grad_tile_x": bad})
+    for good in (0, 256, 512, -1):
+        assert hsz._tuning({"grad_tile_x": good}) is not None

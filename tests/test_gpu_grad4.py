@@ -134,3 +134,22 @@ def test_batch_shared_statistics(fld):
         _check(bmag, oracle.gradmag(fld["xh"], box), "batch box")
         assert torch.equal(mag, hsz.op_fused(c, hsz.QUANT, "gradmag"))
         assert torch.equal(bmag, hsz.op_fused(c, hsz.QUANT, "gradmag", box=box))
+
+
+@pytest.mark.parametrize("tile_x", [256, 512, -1])
+def test_tile_shape_axis(fld, tile_x):
+    """Every workgroup shape the tuner may pick gives the same values."""
+    c = fld["c"]
+    c.build_index()
+    jobs = [hsz.Job(c, "var", hsz.QUANT), hsz.Job(c, "gradmag", hsz.QUANT)]
+    ref = hsz.Plan(jobs)
+    ref.launch()
+    rvar, rmag = ref.results()
+    ref.close()
+    plan = hsz.Plan(jobs, tune={"grad_tile_x": tile_x})
+    plan.launch()
+    var, mag = plan.results()
+    plan.close()
+    assert (var["n"], var["s1"], var["s2"]) == (rvar["n"], rvar["s1"], rvar["s2"])
+    assert torch.equal(mag, rmag)
+    _check(mag, oracle.gradmag(fld["xh"]), f"tile {tile_x}")
