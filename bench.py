@@ -902,9 +902,69 @@ def cpu_baseline(spec, x, a):
         dt += time.perf_counter() - t0
         reps += 1
         del xf
-    return {"value": round(reps * slab.nbytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{planes}x{x.shape[1]}x{x.shape[2]} slab of the same field ({slab.nbytes / 2**20:.0f} MiB) "
-                      f"x {reps} passes: decompress to floats + mean + var + gradmag, {dt:.1f} s"}
+    out = {"value": round(reps * slab.nbytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+           "sample": f"{planes}x{x.shape[1]}x{x.shape[2]} slab of the same field ({slab.nbytes / 2**20:.0f} MiB) "
+                     f"x {reps} passes: decompress to floats + mean + var + gradmag, {dt:.1f} s"}
+    out["all_cores"] = cpu_all_cores(x, a)
+    return out
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_all_cores(x, a):
+    """The same single-thread oracle on every core of the host's share at
+    once: the field cut into one slab of consecutive planes per thread, each
+    slab compressed as a field of its own (untimed), then every thread
+    decompresses its slab to floats and computes mean, variance and gradient
+    magnitude on it (the C calls release the interpreter lock, so the
+    threads run in parallel).  Slab 0's results are checked equal to a run
+    of the same calls alone.  GB/s of original data over the wall time."""
+    import concurrent.futures as cf
+
+    import oracle
+    ncpu = os.cpu_count() or 1
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    threads = max(1, min(16, ncpu, int(os.environ.get("OMP_NUM_THREADS") or ncpu)))
+    planes = max(2, x.shape[0] // threads)
+    slabs = [np.ascontiguousarray(x[k * planes:(k + 1) * planes]) for k in range(threads)]
+    with cf.ThreadPoolExecutor(threads) as ex:
+        bufs = list(ex.map(lambda s: oracle.compress(s, a.eb, rel=True, block=a.block), slabs))
+
+    def work(k):
+        xf = oracle.decompress(bufs[k], oracle.FLOAT)
+        return oracle.mean(xf), oracle.var(xf), oracle.gradmag(xf)
+    reps, dt, first = 0, 0.0, None
+    with cf.ThreadPoolExecutor(threads) as ex:
+        while reps < 8 and (reps == 0 or dt < 6.0):
+            t0 = time.perf_counter()
+            res = list(ex.map(work, range(threads)))
+            dt += time.perf_counter() - t0
+            reps += 1
+            if first is None:
+                first = res[0]
+            del res
+    m, v, g = work(0)
+    if not (m == first[0] and v == first[1] and np.array_equal(g, first[2])):
+        raise RuntimeError("oracle run concurrently disagrees with the same run alone")
+    nbytes = sum(s.nbytes for s in slabs)
+    return {"value": round(reps * nbytes / dt / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "nproc": ncpu, "cpu_model": _cpu_model(),
+            "sample": f"{threads} slabs of {planes}x{x.shape[1]}x{x.shape[2]} (the field's first "
+                      f"{threads * planes} planes, {nbytes / 2**20:.0f} MiB), each its own stream, one thread each, "
+                      f"x {reps} passes: decompress to floats + mean + var + gradmag, {dt:.1f} s wall; "
+                      f"slab 0 equal to the same calls run alone"}
 
 
 if __name__ == "__main__":
