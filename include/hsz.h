@@ -452,6 +452,57 @@ int hsz_plan_update(hsz_plan *plan, const hsz_work *h_items, int n);
 int hsz_plan_launch(hsz_plan *plan, void *stream);
 void hsz_plan_destroy(hsz_plan *plan);
 
+/* ---- contexts: persistent scratch, staging and streams for one device ------------
+ * The decompression pipeline of Sec. III-A (compress once, then decode to a
+ * stage and operate there, many times) issued without allocation or hidden
+ * synchronisation.  A context belongs to the device current at
+ * hsz_ctx_create and owns:
+ *   - a device scratch buffer (scratch_bytes; hsz_ctx_reserve grows it) that
+ *     serves as the workspace of the calls made through the context;
+ *   - a ring of pinned host memory (host_bytes) through which batch work
+ *     tables reach the device with asynchronous copies (a region is reused
+ *     once the copy that read it has completed; a table larger than the
+ *     ring is HSZ_ERR_CAPACITY);
+ *   - the copy stream and events of the out-of-core pipeline;
+ *   - launch shapes chosen by an autotuner, per batch shape class (a string
+ *     key the caller forms; hsz_ctx_set_tuning / hsz_ctx_get_tuning).
+ * Work issued through a context runs in the order it is issued: each call
+ * orders itself after the context's previous call (device-side waits, never
+ * a host wait), so calls on different streams do not race on the scratch.
+ * hsz_ctx_scratch hands the scratch to the plain entry points (as their
+ * d_workspace) for callers that order those calls themselves.
+ * hsz_ctx_destroy waits for the context's outstanding work, then frees it. */
+typedef struct hsz_ctx hsz_ctx;
+int hsz_ctx_create(uint64_t scratch_bytes, uint64_t host_bytes, hsz_ctx **out);
+void hsz_ctx_destroy(hsz_ctx *ctx);
+/* Grow the scratch to at least 'bytes' (waits for the context's work first;
+ * a no-op when it is already that large). */
+int hsz_ctx_reserve(hsz_ctx *ctx, uint64_t bytes);
+int hsz_ctx_scratch(hsz_ctx *ctx, void **d_scratch, uint64_t *bytes);
+/* Launch shape stored under 'key' (NUL-terminated, < 1024 bytes);
+ * hsz_ctx_get_tuning returns HSZ_ERR_INVALID_ARG for an unknown key. */
+int hsz_ctx_set_tuning(hsz_ctx *ctx, const char *key, const hsz_tuning *h_tune);
+int hsz_ctx_get_tuning(hsz_ctx *ctx, const char *key, hsz_tuning *h_tune);
+/* hsz_batch_run with the context's scratch as workspace (HSZ_ERR_CAPACITY
+ * when it holds less than hsz_batch_workspace) and its table copied from
+ * the pinned ring: returns once the pass is enqueued on 'stream'.  The
+ * status word is at the start of the scratch (hsz_read_status). */
+int hsz_ctx_batch_run(hsz_ctx *ctx, const hsz_work *h_items, int n, const hsz_tuning *h_tune,
+                      void *stream);
+/* hsz_ooc_op enqueued on 'stream' and the context's copy stream, with the
+ * context's scratch as workspace (HSZ_ERR_CAPACITY below hsz_ooc_workspace):
+ * returns once the pass is enqueued.  Every part of it, the device-to-host
+ * copies of the result included, completes before any work the caller
+ * enqueues on 'stream' afterwards (record an event there to wait for it).
+ * Statistics are combined on the device, exactly as hsz_ooc_op combines
+ * them, and copied into h_result.  h_slabs and h_result should be pinned
+ * host memory: a copy from or to pageable memory can make the call wait.
+ * d_status (device int, or NULL): after completion HSZ_OK or the first
+ * data-dependent error of the pass. */
+int hsz_ooc_op_async(hsz_ctx *ctx, const void *const *h_slabs, const hsz_header *const *hdrs,
+                     int nslabs, int via, int op, int axis, void *h_result, uint64_t result_bytes,
+                     int *d_status, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "abi_util.hpp"
+#include "ctx.hpp"
 
 namespace {
 
@@ -393,6 +394,26 @@ int hsz_batch_run(const hsz_work* items, int n, const hsz_tuning* tune, void* d_
                                 hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e);
   return enqueue(B, (uint8_t*)d_workspace, t, s);
+}
+
+int hsz_ctx_batch_run(hsz_ctx* ctx, const hsz_work* items, int n, const hsz_tuning* tune, void* stream) {
+  if (!ctx) return HSZ_ERR_INVALID_ARG;
+  int rc = hsz_ctx_util::check_device(ctx);
+  if (rc) return rc;
+  std::vector<Item> its;
+  if ((rc = collect(items, n, &its))) return rc;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  hsz_tuning t = tune ? *tune : hsz_tuning{};
+  Built B;
+  build(its, t, ctx->d_scratch, &B);
+  if (!ctx->d_scratch || ctx->scratch_bytes < B.L.total) return HSZ_ERR_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hsz_ctx_util::order_after_last(ctx, s);
+  if (e != hipSuccess) return hip_fail(e);
+  if ((rc = hsz_ctx_util::stage_copy(ctx, B.table.data(), B.table.size(), ctx->d_scratch + B.L.counts, s))) return rc;
+  if ((rc = enqueue(B, ctx->d_scratch, t, s))) return rc;
+  e = hsz_ctx_util::mark_last(ctx, s);
+  return e == hipSuccess ? HSZ_OK : hip_fail(e);
 }
 
 int hsz_plan_create(const hsz_work* items, int n, const hsz_tuning* tune, void* d_workspace, uint64_t workspace_bytes,

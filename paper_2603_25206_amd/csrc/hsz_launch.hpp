@@ -115,6 +115,9 @@ hipError_t launch_batch_stats(int S, const StatsJob* jobs, const int64_t* unit_s
                               int kmax, BatchAcc* acc, int* status, int grid, hipStream_t s);
 // Finish the statistics jobs of both block-size classes (n[c] jobs each, one
 // wave per job summing its slot's stripes).
+// K per-slab statistics records (48 bytes each, the hsz_stats layout) of one
+// field combined exactly into one record at 'out' (device)
+hipError_t launch_stats_combine(const void* records, int K, int op, double quantum, void* out, hipStream_t s);
 hipError_t launch_batch_finalize(const StatsJob* const jobs[2], const int64_t* const counts[2],
                                  const BatchAcc* const acc[2], const int n[2], hipStream_t s);
 

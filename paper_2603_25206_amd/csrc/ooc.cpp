@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "abi_util.hpp"
+#include "ctx.hpp"
 #include "hsz_nd.hpp"
 
 using namespace hsz_abi;
@@ -85,7 +86,7 @@ int describe(const hsz_header* const* h, int K, SlabSet* S) {
 // Workspace: op workspace (status word first) | 3 compressed slabs | 2
 // windows + 2 output slabs (stencils) or K statistics records.
 struct WsLayout {
-  uint64_t cbuf[3], win[2], out[2], stats, total;
+  uint64_t cbuf[3], win[2], out[2], stats, final, total;
 };
 
 WsLayout ws_layout(const SlabSet& S, int op) {
@@ -108,6 +109,8 @@ WsLayout ws_layout(const SlabSet& S, int op) {
   } else {
     L.stats = off;
     off += a256(48 * (uint64_t)S.K);
+    L.final = off;  // the combined record (asynchronous calls)
+    off += 256;
   }
   L.total = off;
   return L;
@@ -121,23 +124,31 @@ hsz::Dims3 view_dims(const SlabSet& S, int64_t p) {
   return hsz::Dims3{d3[0], d3[1], d3[2]};
 }
 
+// The pipeline's events: created per call (hsz_ooc_op) or borrowed from a
+// context (hsz_ooc_op_async), indexed as in ctx.hpp.
 struct Events {
-  hipEvent_t h2d[3], used[3], out_ready[2], out_done[2];
+  hipEvent_t e[kOocEvents] = {};
   bool used_set[3] = {false, false, false}, done_set[2] = {false, false};
-  int made = 0;
+  bool owned = false;
+  hipEvent_t& h2d(int i) { return e[kOocH2d + i]; }
+  hipEvent_t& used(int i) { return e[kOocUsed + i]; }
+  hipEvent_t& out_ready(int i) { return e[kOocOutReady + i]; }
+  hipEvent_t& out_done(int i) { return e[kOocOutDone + i]; }
   hipError_t create() {
-    hipEvent_t* all[10] = {&h2d[0], &h2d[1], &h2d[2], &used[0], &used[1], &used[2],
-                           &out_ready[0], &out_ready[1], &out_done[0], &out_done[1]};
-    for (; made < 10; ++made) {
-      hipError_t e = hipEventCreateWithFlags(all[made], hipEventDisableTiming);
-      if (e != hipSuccess) return e;
+    owned = true;
+    for (int i = 0; i < kOocEvents; ++i) {
+      hipError_t r = hipEventCreateWithFlags(&e[i], hipEventDisableTiming);
+      if (r != hipSuccess) return r;
     }
     return hipSuccess;
   }
+  void borrow(const hipEvent_t* src) {
+    for (int i = 0; i < kOocEvents; ++i) e[i] = src[i];
+  }
   ~Events() {
-    hipEvent_t all[10] = {h2d[0], h2d[1], h2d[2], used[0], used[1], used[2],
-                          out_ready[0], out_ready[1], out_done[0], out_done[1]};
-    for (int i = 0; i < made; ++i) (void)hipEventDestroy(all[i]);
+    if (owned)
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
   }
 };
 
@@ -172,6 +183,142 @@ void combine(const std::vector<uint8_t>& rec, int K, int op, double quantum, hsz
   *out = o;
 }
 
+__global__ void k_ooc_status(const int* status, int* out) {
+  if (threadIdx.x == 0) *out = *status;
+}
+
+// Arguments both entry points check before anything is enqueued.
+int ooc_check(const void* const* h_slabs, const hsz_header* const* hdrs, int nslabs, int via, int op, int axis,
+              const void* h_result, uint64_t result_bytes, SlabSet* S) {
+  int rc = describe(hdrs, nslabs, S);
+  if (rc) return rc;
+  if (!h_slabs || !h_result) return HSZ_ERR_INVALID_ARG;
+  for (int k = 0; k < nslabs; ++k)
+    if (!h_slabs[k]) return HSZ_ERR_INVALID_ARG;
+  const bool stencil = is_stencil_op(op);
+  if (!stencil && op != HSZ_MEAN && op != HSZ_VAR) return HSZ_ERR_INVALID_ARG;
+  if (stencil && via != HSZ_QUANT) return HSZ_ERR_UNSUPPORTED;
+  if (!stencil && via != HSZ_DELTA && via != HSZ_QUANT) return HSZ_ERR_UNSUPPORTED;
+  if (op == HSZ_DERIV && (axis < 0 || axis >= S->ndim)) return HSZ_ERR_INVALID_ARG;
+  if (op == HSZ_LAPLACIAN && S->max_abs_q >= (1u << 27)) return HSZ_ERR_UNSUPPORTED;
+  const uint64_t esz = S->dtype == HSZ_F32 ? 4 : 8;
+  const int64_t n_total = S->dims[0] * S->plane;
+  if (result_bytes < (stencil ? esz * (uint64_t)n_total : sizeof(hsz_stats))) return HSZ_ERR_CAPACITY;
+  return HSZ_OK;
+}
+
+// Enqueue the pass: kernels on 's', host <-> device copies on 'cs', events
+// between them.  The status word is at the start of ws.  async: statistics
+// are combined on the device (ws + L.final) and copied into h_result on 's',
+// and the stencil results' last copies on 'cs' are joined into 's'; else the
+// caller drains both streams and combines the records on the host.
+hipError_t ooc_enqueue(const void* const* h_slabs, const hsz_header* const* hdrs, const SlabSet& S, int via, int op,
+                       int axis, void* h_result, uint8_t* ws, const WsLayout& L, hipStream_t s, hipStream_t cs,
+                       Events& ev, bool async) {
+  int* status = (int*)ws;
+  const int K = S.K;
+  const int64_t P = S.plane;
+  const bool stencil = is_stencil_op(op);
+  const uint64_t esz = S.dtype == HSZ_F32 ? 4 : 8;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+    return e == hipSuccess;
+  };
+  auto issue = [&](int k) -> hipError_t {  // compressed slab k -> ring slot k % 3
+    const int slot = k % 3;
+    if (ev.used_set[slot]) {
+      hipError_t r = hipStreamWaitEvent(cs, ev.used(slot), 0);
+      if (r != hipSuccess) return r;
+    }
+    hipError_t r = hipMemcpyAsync(ws + L.cbuf[slot], h_slabs[k], hdrs[k]->total_bytes, hipMemcpyHostToDevice, cs);
+    if (r != hipSuccess) return r;
+    return hipEventRecord(ev.h2d(slot), cs);
+  };
+  auto mark_used = [&](int k) -> hipError_t {
+    ev.used_set[k % 3] = true;
+    return hipEventRecord(ev.used(k % 3), s);
+  };
+  hipLaunchKernelGGL(k_ooc_reset, dim3(1), dim3(64), 0, s, status);
+  if (!chk(hipGetLastError())) return e;
+  // the first copies read the ring after the reset's predecessors on 's'
+  if (!chk(hipEventRecord(ev.e[kOocFinal], s)) || !chk(hipStreamWaitEvent(cs, ev.e[kOocFinal], 0))) return e;
+  if (!stencil) {
+    // statistics: every slab through the fused integer route, one record each
+    chk(issue(0));
+    if (K > 1) chk(issue(1));
+    for (int k = 0; k < K && e == hipSuccess; ++k) {
+      if (!chk(hipStreamWaitEvent(s, ev.h2d(k % 3), 0))) break;
+      hsz::OpTarget t;
+      t.d = view_dims(S, S.planes[k]);
+      t.box = hsz::Box3{0, t.d.z, 0, t.d.y, 0, t.d.x};
+      chk(hsz::launch_stats_fused(view_of(ws + L.cbuf[k % 3], hdrs[k]), via, op, t, ws + L.stats + 48 * (uint64_t)k,
+                                  ws, s));
+      chk(mark_used(k));
+      if (k + 2 < K) chk(issue(k + 2));
+    }
+    if (async && e == hipSuccess) {
+      chk(hsz::launch_stats_combine(ws + L.stats, K, op, hdrs[0]->quantum, ws + L.final, s));
+      chk(hipMemcpyAsync(h_result, ws + L.final, sizeof(hsz_stats), hipMemcpyDeviceToHost, s));
+    }
+    // the copy stream's last work (slab uploads) is joined into 's'
+    if (chk(hipEventRecord(ev.e[kOocFinal], cs))) chk(hipStreamWaitEvent(s, ev.e[kOocFinal], 0));
+    return e;
+  }
+  // stencils: windows of D_q with one-plane halos, results streamed out
+  const int axis3 = op == HSZ_DERIV ? axis + 3 - S.ndim : 0;
+  const int a_s = 3 - S.ndim;  // the slowest axis in the 3D view
+  uint8_t* win[2] = {ws + L.win[0], ws + L.win[1]};
+  uint8_t* out[2] = {ws + L.out[0], ws + L.out[1]};
+  const uint64_t pb = 4 * (uint64_t)P;  // bytes of one plane of q
+  hsz::StreamView vq = view_of(nullptr, hdrs[0]);
+  auto decode = [&](int k, uint8_t* dst) -> bool {
+    if (!chk(hipStreamWaitEvent(s, ev.h2d(k % 3), 0))) return false;
+    if (!chk(hsz::launch_decode(view_of(ws + L.cbuf[k % 3], hdrs[k]), HSZ_QUANT, dst, status, s))) return false;
+    return chk(mark_used(k));
+  };
+  chk(issue(0));
+  if (K > 1) chk(issue(1));
+  if (e == hipSuccess) decode(0, win[0] + pb);
+  if (K > 2) chk(issue(2));
+  for (int k = 0; k < K && e == hipSuccess; ++k) {
+    uint8_t* cur = win[k % 2];
+    uint8_t* nxt = win[(k + 1) % 2];
+    if (k >= 1)  // the halo before: the last plane of slab k-1, still in the other window
+      chk(hipMemcpyAsync(cur, nxt + pb * (uint64_t)S.planes[k - 1], pb, hipMemcpyDeviceToDevice, s));
+    if (k + 1 < K && e == hipSuccess) {
+      if (!decode(k + 1, nxt + pb)) break;
+      if (k + 3 < K) chk(issue(k + 3));
+      // the halo after: the first plane of slab k+1
+      chk(hipMemcpyAsync(cur + pb * (uint64_t)(1 + S.planes[k]), nxt + pb, pb, hipMemcpyDeviceToDevice, s));
+    }
+    if (e != hipSuccess) break;
+    const int before = k > 0 ? 1 : 0, after = k + 1 < K ? 1 : 0;
+    const int64_t wplanes = S.planes[k] + before + after;
+    hsz::OpTarget t;
+    t.d = view_dims(S, wplanes);
+    t.box = hsz::Box3{0, t.d.z, 0, t.d.y, 0, t.d.x};
+    if (a_s == 0) { t.box.z0 = before; t.box.z1 = before + S.planes[k]; }
+    else if (a_s == 1) { t.box.y0 = before; t.box.y1 = before + S.planes[k]; }
+    else { t.box.x0 = before; t.box.x1 = before + S.planes[k]; }
+    const int o = k % 2;
+    if (ev.done_set[o] && !chk(hipStreamWaitEvent(s, ev.out_done(o), 0))) break;
+    const uint8_t* wbuf = cur + (before ? 0 : pb);
+    if (!chk(hsz::launch_grad_stage(wbuf, HSZ_QUANT, vq, op, axis3, t, out[o], ws, s))) break;
+    if (!chk(hipEventRecord(ev.out_ready(o), s))) break;
+    if (!chk(hipStreamWaitEvent(cs, ev.out_ready(o), 0))) break;
+    const uint64_t ob = esz * (uint64_t)S.planes[k] * (uint64_t)P;
+    if (!chk(hipMemcpyAsync((uint8_t*)h_result + esz * (uint64_t)S.first[k] * (uint64_t)P, out[o], ob,
+                            hipMemcpyDeviceToHost, cs)))
+      break;
+    ev.done_set[o] = true;
+    chk(hipEventRecord(ev.out_done(o), cs));
+  }
+  // the result copies on the copy stream are joined into 's'
+  if (chk(hipEventRecord(ev.e[kOocFinal], cs))) chk(hipStreamWaitEvent(s, ev.e[kOocFinal], 0));
+  return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -203,137 +350,65 @@ int hsz_ooc_workspace(const hsz_header* const* h_slabs, int nslabs, int op, uint
 int hsz_ooc_op(const void* const* h_slabs, const hsz_header* const* hdrs, int nslabs, int via, int op, int axis,
                void* h_result, uint64_t result_bytes, void* d_workspace, uint64_t workspace_bytes, void* stream) {
   SlabSet S;
-  int rc = describe(hdrs, nslabs, &S);
+  int rc = ooc_check(h_slabs, hdrs, nslabs, via, op, axis, h_result, result_bytes, &S);
   if (rc) return rc;
-  if (!h_slabs || !h_result || !d_workspace || !aligned16(d_workspace)) return HSZ_ERR_INVALID_ARG;
-  for (int k = 0; k < nslabs; ++k)
-    if (!h_slabs[k]) return HSZ_ERR_INVALID_ARG;
-  const bool stencil = is_stencil_op(op);
-  if (!stencil && op != HSZ_MEAN && op != HSZ_VAR) return HSZ_ERR_INVALID_ARG;
-  if (stencil && via != HSZ_QUANT) return HSZ_ERR_UNSUPPORTED;
-  if (!stencil && via != HSZ_DELTA && via != HSZ_QUANT) return HSZ_ERR_UNSUPPORTED;
-  if (op == HSZ_DERIV && (axis < 0 || axis >= S.ndim)) return HSZ_ERR_INVALID_ARG;
-  if (op == HSZ_LAPLACIAN && S.max_abs_q >= (1u << 27)) return HSZ_ERR_UNSUPPORTED;
-  const uint64_t esz = S.dtype == HSZ_F32 ? 4 : 8;
-  int64_t n_total = S.dims[0] * S.plane;
-  if (result_bytes < (stencil ? esz * (uint64_t)n_total : sizeof(hsz_stats))) return HSZ_ERR_CAPACITY;
+  if (!d_workspace || !aligned16(d_workspace)) return HSZ_ERR_INVALID_ARG;
   const WsLayout L = ws_layout(S, op);
   if (workspace_bytes < L.total) return HSZ_ERR_CAPACITY;
-
   uint8_t* ws = (uint8_t*)d_workspace;
-  int* status = (int*)ws;
   hipStream_t s = (hipStream_t)stream;
   hipStream_t cs = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_fail(e);
   Events ev;
   e = ev.create();
-  const int K = nslabs;
-  const int64_t P = S.plane;
-  auto issue = [&](int k) -> hipError_t {  // compressed slab k -> ring slot k % 3
-    const int slot = k % 3;
-    if (ev.used_set[slot]) {
-      hipError_t r = hipStreamWaitEvent(cs, ev.used[slot], 0);
-      if (r != hipSuccess) return r;
-    }
-    hipError_t r = hipMemcpyAsync(ws + L.cbuf[slot], h_slabs[k], hdrs[k]->total_bytes, hipMemcpyHostToDevice, cs);
-    if (r != hipSuccess) return r;
-    return hipEventRecord(ev.h2d[slot], cs);
-  };
-  auto mark_used = [&](int k) -> hipError_t {
-    ev.used_set[k % 3] = true;
-    return hipEventRecord(ev.used[k % 3], s);
-  };
-  auto chk = [&](hipError_t r) {
-    if (e == hipSuccess) e = r;
-    return e == hipSuccess;
-  };
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_ooc_reset, dim3(1), dim3(64), 0, s, status);
-    e = hipGetLastError();
-  }
   std::vector<uint8_t> records;
-  if (e == hipSuccess && !stencil) {
-    // statistics: every slab through the fused integer route, one record each
-    chk(issue(0));
-    if (K > 1) chk(issue(1));
-    for (int k = 0; k < K && e == hipSuccess; ++k) {
-      if (!chk(hipStreamWaitEvent(s, ev.h2d[k % 3], 0))) break;
-      hsz::OpTarget t;
-      t.d = view_dims(S, S.planes[k]);
-      t.box = hsz::Box3{0, t.d.z, 0, t.d.y, 0, t.d.x};
-      chk(hsz::launch_stats_fused(view_of(ws + L.cbuf[k % 3], hdrs[k]), via, op, t, ws + L.stats + 48 * (uint64_t)k,
-                                  ws, s));
-      chk(mark_used(k));
-      if (k + 2 < K) chk(issue(k + 2));
-    }
-    if (e == hipSuccess) {
-      records.resize(48 * (size_t)K);
-      if (chk(hipStreamSynchronize(cs)) && chk(hipStreamSynchronize(s)))
-        chk(hipMemcpy(records.data(), ws + L.stats, records.size(), hipMemcpyDeviceToHost));
-    }
-  } else if (e == hipSuccess) {
-    // stencils: windows of D_q with one-plane halos, results streamed out
-    const int axis3 = op == HSZ_DERIV ? axis + 3 - S.ndim : 0;
-    const int a_s = 3 - S.ndim;  // the slowest axis in the 3D view
-    uint8_t* win[2] = {ws + L.win[0], ws + L.win[1]};
-    uint8_t* out[2] = {ws + L.out[0], ws + L.out[1]};
-    const uint64_t pb = 4 * (uint64_t)P;  // bytes of one plane of q
-    hsz::StreamView vq = view_of(nullptr, hdrs[0]);
-    auto decode = [&](int k, uint8_t* dst) -> bool {
-      if (!chk(hipStreamWaitEvent(s, ev.h2d[k % 3], 0))) return false;
-      if (!chk(hsz::launch_decode(view_of(ws + L.cbuf[k % 3], hdrs[k]), HSZ_QUANT, dst, status, s))) return false;
-      return chk(mark_used(k));
-    };
-    chk(issue(0));
-    if (K > 1) chk(issue(1));
-    if (e == hipSuccess) decode(0, win[0] + pb);
-    if (K > 2) chk(issue(2));
-    for (int k = 0; k < K && e == hipSuccess; ++k) {
-      uint8_t* cur = win[k % 2];
-      uint8_t* nxt = win[(k + 1) % 2];
-      if (k >= 1)  // the halo before: the last plane of slab k-1, still in the other window
-        chk(hipMemcpyAsync(cur, nxt + pb * (uint64_t)S.planes[k - 1], pb, hipMemcpyDeviceToDevice, s));
-      if (k + 1 < K && e == hipSuccess) {
-        if (!decode(k + 1, nxt + pb)) break;
-        if (k + 3 < K) chk(issue(k + 3));
-        // the halo after: the first plane of slab k+1
-        chk(hipMemcpyAsync(cur + pb * (uint64_t)(1 + S.planes[k]), nxt + pb, pb, hipMemcpyDeviceToDevice, s));
-      }
-      if (e != hipSuccess) break;
-      const int before = k > 0 ? 1 : 0, after = k + 1 < K ? 1 : 0;
-      const int64_t wplanes = S.planes[k] + before + after;
-      hsz::OpTarget t;
-      t.d = view_dims(S, wplanes);
-      t.box = hsz::Box3{0, t.d.z, 0, t.d.y, 0, t.d.x};
-      if (a_s == 0) { t.box.z0 = before; t.box.z1 = before + S.planes[k]; }
-      else if (a_s == 1) { t.box.y0 = before; t.box.y1 = before + S.planes[k]; }
-      else { t.box.x0 = before; t.box.x1 = before + S.planes[k]; }
-      const int o = k % 2;
-      if (ev.done_set[o] && !chk(hipStreamWaitEvent(s, ev.out_done[o], 0))) break;
-      const uint8_t* wbuf = cur + (before ? 0 : pb);
-      if (!chk(hsz::launch_grad_stage(wbuf, HSZ_QUANT, vq, op, axis3, t, out[o], ws, s))) break;
-      if (!chk(hipEventRecord(ev.out_ready[o], s))) break;
-      if (!chk(hipStreamWaitEvent(cs, ev.out_ready[o], 0))) break;
-      const uint64_t ob = esz * (uint64_t)S.planes[k] * (uint64_t)P;
-      if (!chk(hipMemcpyAsync((uint8_t*)h_result + esz * (uint64_t)S.first[k] * (uint64_t)P, out[o], ob,
-                              hipMemcpyDeviceToHost, cs)))
-        break;
-      ev.done_set[o] = true;
-      chk(hipEventRecord(ev.out_done[o], cs));
-    }
-  }
+  if (e == hipSuccess) e = ooc_enqueue(h_slabs, hdrs, S, via, op, axis, h_result, ws, L, s, cs, ev, false);
   // drain both streams whatever happened, so no copy is in flight on return
-  hipError_t e1 = cs ? hipStreamSynchronize(cs) : hipSuccess;
+  hipError_t e1 = hipStreamSynchronize(cs);
   hipError_t e2 = hipStreamSynchronize(s);
   if (e == hipSuccess) e = e1 != hipSuccess ? e1 : e2;
   int st = 0;
-  if (e == hipSuccess) e = hipMemcpy(&st, status, sizeof st, hipMemcpyDeviceToHost);
-  if (cs) (void)hipStreamDestroy(cs);
+  if (e == hipSuccess) e = hipMemcpy(&st, ws, sizeof st, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && !is_stencil_op(op)) {
+    records.resize(48 * (size_t)nslabs);
+    e = hipMemcpy(records.data(), ws + L.stats, records.size(), hipMemcpyDeviceToHost);
+  }
+  (void)hipStreamDestroy(cs);
   if (e != hipSuccess) return hip_fail(e);
   if (st != 0) return st;
-  if (!stencil) combine(records, K, op, hdrs[0]->quantum, (hsz_stats*)h_result);
+  if (!is_stencil_op(op)) combine(records, nslabs, op, hdrs[0]->quantum, (hsz_stats*)h_result);
   return HSZ_OK;
+}
+
+int hsz_ooc_op_async(hsz_ctx* ctx, const void* const* h_slabs, const hsz_header* const* hdrs, int nslabs, int via,
+                     int op, int axis, void* h_result, uint64_t result_bytes, int* d_status, void* stream) {
+  if (!ctx || ((uintptr_t)d_status & 3u)) return HSZ_ERR_INVALID_ARG;
+  int rc = hsz_ctx_util::check_device(ctx);
+  if (rc) return rc;
+  SlabSet S;
+  if ((rc = ooc_check(h_slabs, hdrs, nslabs, via, op, axis, h_result, result_bytes, &S))) return rc;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  const WsLayout L = ws_layout(S, op);
+  if (!ctx->d_scratch || ctx->scratch_bytes < L.total) return HSZ_ERR_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  hipStream_t cs = ctx->copy;
+  Events ev;
+  ev.borrow(ctx->ooc);
+  // after the context's previous call on both streams (the ring slots, the
+  // windows and the status word are reused)
+  hipError_t e = hsz_ctx_util::order_after_last(ctx, s);
+  if (e == hipSuccess) e = hsz_ctx_util::order_after_last(ctx, cs);
+  if (e == hipSuccess) e = ooc_enqueue(h_slabs, hdrs, S, via, op, axis, h_result, ctx->d_scratch, L, s, cs, ev, true);
+  if (e == hipSuccess && d_status) {
+    hipLaunchKernelGGL(k_ooc_status, dim3(1), dim3(64), 0, s, (const int*)ctx->d_scratch, d_status);
+    e = hipGetLastError();
+  }
+  // the context's last call ends here whatever happened: everything enqueued
+  // on either stream is joined into 's'
+  hipError_t e2 = hsz_ctx_util::mark_last(ctx, s);
+  if (e == hipSuccess) e = e2;
+  return e == hipSuccess ? HSZ_OK : hip_fail(e);
 }
 
 }  // extern "C"

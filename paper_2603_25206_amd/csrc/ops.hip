@@ -483,6 +483,20 @@ __device__ StatsOut stats_from_sums(int64_t n, int64_t s1, uint64_t s2lo, uint64
   return r;
 }
 
+// Records of the same field's slabs (each its own exact sums) combined into
+// one: the sums add exactly (int64, 128 bits) and are finished once.
+__global__ void k_stats_combine(const StatsOut* rec, int K, int op, double quantum, StatsOut* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t n = 0, s1 = 0;
+  unsigned __int128 s2 = 0;
+  for (int k = 0; k < K; ++k) {
+    n += rec[k].n;
+    s1 += rec[k].s1;
+    s2 += ((unsigned __int128)(uint64_t)rec[k].s2hi << 64) | rec[k].s2lo;
+  }
+  *out = stats_from_sums(n, s1, (uint64_t)s2, (uint64_t)(s2 >> 64), op, quantum);
+}
+
 // The standard deviation on D_p of a block-mean stream (Sec. V-A) is taken
 // about the integer mean mu~ = round(sum_b M_b S_b / n), halves down like the
 // block means.  With the exact sums s1 = sum q and s2 = sum q^2 the spread is
@@ -780,6 +794,12 @@ hipError_t fused_by_via(const StreamView& v, int via, const Rows& rows, bool who
 }
 
 }  // namespace
+
+hipError_t launch_stats_combine(const void* records, int K, int op, double quantum, void* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_combine, dim3(1), dim3(64), 0, s, (const StatsOut*)records, K, op, quantum,
+                     (StatsOut*)out);
+  return hipGetLastError();
+}
 
 hipError_t launch_batch_reset(BatchAcc* acc, int slots, int* status, hipStream_t s) {
   const int n = slots * kAccStripes;

@@ -95,6 +95,8 @@ EXPORTS = (
     "hsz_plan_destroy", "hsz_block_index_bytes", "hsz_block_index", "hsz_vector_workspace",
     "hsz_vector_op_on_stage", "hsz_vector_op_fused", "hsz_compress_range", "hsz_extremes_workspace",
     "hsz_extremes", "hsz_ooc_workspace", "hsz_ooc_op", "hsz_compress_workspace_mode", "hsz_op_fused_noalloc",
+    "hsz_ctx_create", "hsz_ctx_destroy", "hsz_ctx_reserve", "hsz_ctx_scratch", "hsz_ctx_set_tuning",
+    "hsz_ctx_get_tuning", "hsz_ctx_batch_run", "hsz_ooc_op_async",
 )
 
 _lib = None
@@ -149,6 +151,14 @@ def load(path: str = LIB_PATH):
         "hsz_extremes": (i32, [P, i32, u64, P, P, u64, P]),
         "hsz_ooc_workspace": (i32, [P, i32, i32, pu64]),
         "hsz_ooc_op": (i32, [P, P, i32, i32, i32, i32, P, u64, P, u64, P]),
+        "hsz_ctx_create": (i32, [u64, u64, ctypes.POINTER(ctypes.c_void_p)]),
+        "hsz_ctx_destroy": (None, [P]),
+        "hsz_ctx_reserve": (i32, [P, u64]),
+        "hsz_ctx_scratch": (i32, [P, ctypes.POINTER(ctypes.c_void_p), pu64]),
+        "hsz_ctx_set_tuning": (i32, [P, ctypes.c_char_p, ctypes.POINTER(Tuning)]),
+        "hsz_ctx_get_tuning": (i32, [P, ctypes.c_char_p, ctypes.POINTER(Tuning)]),
+        "hsz_ctx_batch_run": (i32, [P, ctypes.POINTER(Work), i32, ctypes.POINTER(Tuning), P]),
+        "hsz_ooc_op_async": (i32, [P, P, P, i32, i32, i32, i32, P, u64, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -324,7 +334,7 @@ def stage_bytes(h: Header, stage: int) -> int:
     return out.value
 
 
-def decompress_to_stage(c: Compressed, stage, stream=None, out: torch.Tensor | None = None,
+def decompress_to_stage(c: Compressed, stage, stream=None, out: torch.Tensor | None = None, ws=None,
                         check: bool = False):
     """Alg. 2 to stage 1..4.  Returns (for stage 2) (p, q0), else one tensor
     shaped like the field (stage 1: q0 of shape [nb])."""
@@ -336,7 +346,8 @@ def decompress_to_stage(c: Compressed, stage, stream=None, out: torch.Tensor | N
         out = _empty_bytes(nbytes, c.data.device)
     wsb = ctypes.c_uint64()
     _check(lib.hsz_decompress_workspace(ctypes.byref(h), stage, ctypes.byref(wsb)), "decompress_workspace")
-    ws = workspace(wsb.value, c.data.device, key="decode")
+    if ws is None or ws.numel() < wsb.value:
+        ws = workspace(wsb.value, c.data.device, key="decode")
     _check(lib.hsz_decompress_to_stage(ctypes.c_void_p(c.data.data_ptr()), ctypes.byref(h), stage,
                                        ctypes.c_void_p(out.data_ptr()), out.numel(),
                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(),
@@ -755,6 +766,16 @@ def compress_slabs(x: torch.Tensor, eb: float, planes: int, rel: bool = True, bl
     return out
 
 
+def ooc_workspace_bytes(slabs, op) -> int:
+    """Workspace (bytes) an out-of-core operation over these slabs needs."""
+    hdrs = [h for _, h in slabs]
+    harr = _headers_array(hdrs)
+    wsb = ctypes.c_uint64()
+    _check(load().hsz_ooc_workspace(ctypes.cast(harr, ctypes.c_void_p), len(slabs), _OPS.get(op, op),
+                                    ctypes.byref(wsb)), "ooc_workspace")
+    return wsb.value
+
+
 def ooc_op(slabs, op, via=QUANT, axis: int = 0, stream=None, device="cuda"):
     """An operation on the field held as host-resident compressed slabs
     (compress_slabs), streamed through the device: a stats dict for mean /
@@ -784,3 +805,124 @@ def ooc_op(slabs, op, via=QUANT, axis: int = 0, stream=None, device="cuda"):
     if op in _STATS:
         return _stats_from_raw(res.numpy().tobytes())
     return res.view(h0.torch_dtype).view(shape)
+
+
+# ---- contexts: persistent scratch, pinned staging and streams (hsz_ctx) ---------------
+
+class _DevBuf:
+    """A device buffer the library owns, in the form the wrappers above take
+    for a workspace (data_ptr, numel in bytes)."""
+
+    def __init__(self, ptr: int, nbytes: int):
+        self._ptr, self._n = int(ptr or 0), int(nbytes)
+
+    def data_ptr(self) -> int:
+        return self._ptr
+
+    def numel(self) -> int:
+        return self._n
+
+
+class Context:
+    """One device's hsz_ctx: a device scratch buffer that is the workspace of
+    every call made through this object, a ring of pinned host memory through
+    which batch tables reach the device, the out-of-core copy stream, and
+    stored launch shapes.  The calls return once their work is enqueued:
+    none waits on the host unless the scratch must grow (reserve() it up
+    front) or the staging ring is exhausted.  Results of statistics are read
+    after the stream has completed (status(), or outputs() of a batch)."""
+
+    def __init__(self, scratch_bytes: int = 256 << 20, host_bytes: int = 4 << 20, device=None):
+        lib = load()
+        self.device = torch.device(device if device is not None else "cuda")
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.hsz_ctx_create(int(scratch_bytes), int(host_bytes), ctypes.byref(h)), "ctx_create")
+        self.handle = h
+
+    @property
+    def scratch(self) -> _DevBuf:
+        p, n = ctypes.c_void_p(), ctypes.c_uint64()
+        _check(load().hsz_ctx_scratch(self.handle, ctypes.byref(p), ctypes.byref(n)), "ctx_scratch")
+        return _DevBuf(p.value, n.value)
+
+    def reserve(self, nbytes: int):
+        """Grow the scratch to nbytes (waits for the context's work if it grows)."""
+        _check(load().hsz_ctx_reserve(self.handle, int(nbytes)), "ctx_reserve")
+
+    def decompress_to_stage(self, c: Compressed, stage, out: torch.Tensor, stream=None):
+        return decompress_to_stage(c, stage, stream=stream, out=out, ws=self.scratch)
+
+    def op_fused(self, c: Compressed, via, op, out: torch.Tensor, axis: int = 0, box=None, stream=None):
+        return op_fused(c, via, op, axis=axis, box=box, stream=stream, check=False, out=out, ws=self.scratch,
+                        raw=True)
+
+    def op_on_stage(self, stage_buf, h: Header, stage, op, out: torch.Tensor, axis: int = 0, box=None, stream=None):
+        return op_on_stage(stage_buf, h, stage, op, axis=axis, box=box, stream=stream, check=False, out=out,
+                           ws=self.scratch, raw=True)
+
+    def batch_run(self, jobs, tune: dict | None = None, stream=None) -> "_Batch":
+        """Enqueue one pass over the jobs; call .outputs() of the returned batch
+        after the stream has completed."""
+        b = _Batch(jobs)
+        _check(load().hsz_ctx_batch_run(self.handle, b.items, len(b.jobs), _tuning(tune),
+                                        ctypes.c_void_p(_stream(stream))), "ctx_batch_run")
+        return b
+
+    def ooc_op(self, slabs, op, via=QUANT, axis: int = 0, stream=None, out: torch.Tensor | None = None,
+               status: torch.Tensor | None = None) -> torch.Tensor:
+        """Enqueue an out-of-core operation (see ooc_op); returns the pinned
+        host tensor the result lands in once the stream reaches this point:
+        48 raw bytes of statistics (stats_of_host) or the field's result."""
+        lib = load()
+        op = _OPS.get(op, op)
+        via = _STAGES.get(via, via)
+        hdrs = [h for _, h in slabs]
+        harr = _headers_array(hdrs)
+        ptrs = (ctypes.c_void_p * len(slabs))(*[t.data_ptr() for t, _ in slabs])
+        h0 = hdrs[0]
+        if out is None:
+            if op in _STATS:
+                out = torch.empty(48, dtype=torch.uint8, pin_memory=True)
+            else:
+                n = sum(int(h.dims[0]) for h in hdrs)
+                for v in h0.shape[1:]:
+                    n *= int(v)
+                out = torch.empty(n * (4 if h0.dtype == F32 else 8), dtype=torch.uint8, pin_memory=True)
+        self._keep = (ptrs, harr, hdrs, slabs)  # alive until the next call
+        _check(lib.hsz_ooc_op_async(self.handle, ctypes.cast(ptrs, ctypes.c_void_p), ctypes.cast(harr, ctypes.c_void_p),
+                                    len(slabs), via, op, axis, ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                    None if status is None else ctypes.c_void_p(status.data_ptr()),
+                                    ctypes.c_void_p(_stream(stream))), "ooc_op_async")
+        return out
+
+    def status(self, stream=None) -> int:
+        """The status word of the last call made through the context
+        (synchronises the stream)."""
+        return read_status(self.scratch, stream)
+
+    def set_tuning(self, key: str, tune: dict):
+        _check(load().hsz_ctx_set_tuning(self.handle, key.encode(), _tuning(tune)), "ctx_set_tuning")
+
+    def get_tuning(self, key: str):
+        t = Tuning()
+        rc = load().hsz_ctx_get_tuning(self.handle, key.encode(), ctypes.byref(t))
+        if rc != OK:
+            return None
+        return {f: int(getattr(t, f)) for f, _ in Tuning._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().hsz_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def stats_of_host(raw: torch.Tensor) -> dict:
+    """Statistics from the 48 raw bytes an out-of-core call left in host memory."""
+    return _stats_from_raw(raw[:48].numpy().tobytes())

@@ -326,3 +326,20 @@ def test_tuning_struct_matches_header():
             hsz._tuning({"grad_tile_x": bad})
     for good in (0, 256, 512, -1):
         assert hsz._tuning({"grad_tile_x": good}) is not None
+
+
+def test_ctx_validation_before_any_launch(lib):
+    """Context entry points reject missing objects and arguments on the host."""
+    P = ctypes.c_void_p
+    assert lib.hsz_ctx_create(1 << 20, 1 << 20, None) == hsz.ERR_INVALID_ARG
+    lib.hsz_ctx_destroy(None)  # a no-op
+    assert lib.hsz_ctx_reserve(None, 1 << 20) == hsz.ERR_INVALID_ARG
+    p, n = P(), ctypes.c_uint64()
+    assert lib.hsz_ctx_scratch(None, ctypes.byref(p), ctypes.byref(n)) == hsz.ERR_INVALID_ARG
+    t = hsz.Tuning()
+    assert lib.hsz_ctx_set_tuning(None, b"k", ctypes.byref(t)) == hsz.ERR_INVALID_ARG
+    assert lib.hsz_ctx_get_tuning(None, b"k", ctypes.byref(t)) == hsz.ERR_INVALID_ARG
+    items = (hsz.Work * 1)()
+    assert lib.hsz_ctx_batch_run(None, items, 1, None, None) == hsz.ERR_INVALID_ARG
+    assert lib.hsz_ooc_op_async(None, None, None, 1, hsz.QUANT, hsz.MEAN, 0, None, 0, None, None) == \
+        hsz.ERR_INVALID_ARG
