@@ -847,7 +847,12 @@ def bench_serving(a, log):
     """Compressed snapshots resident in HBM (even: 512^3, odd: 100x500x500,
     f32, rel eb 1e-3, S=32), a Poisson stream of queries (mean, variance or
     gradient magnitude over a random box with sides 32..256), continuous
-    batching over 4 stream slots with a 4 GiB result budget."""
+    batching over 4 stream slots within a 4 GiB budget: the slots'
+    workspaces and statistics regions and the result arena are allocated
+    when the executor is built, and each result is released by its consumer
+    as soon as it completes.  The headline rate, then a sweep of arrival
+    rates up to saturation (mean batch size, latency, the throughput
+    ceiling)."""
     import torch
 
     from paper_2603_25206_amd import hsz, synth
@@ -864,22 +869,45 @@ def bench_serving(a, log):
     torch.cuda.synchronize()
     log(f"[bench] serving: {a.snapshots} snapshots in {time.time() - t0:.1f}s, "
         f"{sum(c.nbytes for c in snaps) / 2**30:.2f} GiB compressed")
-    ex = GpuExecutor(snaps, n_slots=4)
-    srv = Server(ex, mem_budget=4 << 30, max_batch=64)
-    warm = make_queries(shapes, 200, rate_hz=a.rate, seed=1)
-    srv.run(warm)
-    srv.done.clear()
-    srv.stats = type(srv.stats)()
-    qs = make_queries(shapes, a.queries, rate_hz=a.rate, seed=7)
-    t0 = time.perf_counter()
-    done = srv.run(qs)
-    wall = time.perf_counter() - t0
-    s = summary(done, wall, bytes_per_elem=4)
+    ex = GpuExecutor(snaps, n_slots=4, mem_budget=4 << 30, max_batch=64)
+
+    def serve(qs, freeze_gc=True):
+        srv = Server(ex, mem_budget=ex.result_budget, max_batch=64, hold_results=True)
+        srv.on_done = srv.release  # the consumer takes each result as it completes
+        t1 = time.perf_counter()
+        done = srv.run(qs, freeze_gc=freeze_gc)
+        wall = time.perf_counter() - t1
+        r = summary(done, wall, bytes_per_elem=4)
+        r.update({"batches": srv.stats.launched_batches,
+                  "mean_batch": round(float(np.mean(srv.stats.batch_sizes)), 2),
+                  "max_batch": int(max(srv.stats.batch_sizes)), "max_in_flight": srv.stats.max_in_flight,
+                  "max_result_mem_mib": round(srv.stats.max_mem / 2**20, 1),
+                  "sched_max_round_gap_ms": srv.stats.max_round_gap * 1e3,
+                  "sched_max_launch_ms": srv.stats.max_launch * 1e3,
+                  "sched_max_collect_ms": srv.stats.max_collect * 1e3,
+                  "gc_pauses": srv.stats.gc_pauses, "gc_max_pause_ms": srv.stats.gc_max_pause * 1e3})
+        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+
+    serve(make_queries(shapes, 200, rate_hz=a.rate, seed=1))  # warm-up
+    s = serve(make_queries(shapes, a.queries, rate_hz=a.rate, seed=7))
+    # the same trace with the collector scanning every object (no freeze)
+    s["no_gc_freeze"] = {k: v for k, v in serve(make_queries(shapes, a.queries, rate_hz=a.rate, seed=7),
+                                                 freeze_gc=False).items()
+                         if k in ("p50_ms", "p99_ms", "p999_ms", "max_ms", "max_wait_ms", "sched_max_round_gap_ms",
+                                  "gc_pauses", "gc_max_pause_ms")}
     s.update({"snapshots": a.snapshots, "rate_hz": a.rate, "slots": ex.n_slots,
-              "batches": srv.stats.launched_batches,
-              "mean_batch": round(float(np.mean(srv.stats.batch_sizes)), 2),
-              "max_in_flight": srv.stats.max_in_flight})
-    s = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
+              "budget_bytes": 4 << 30, "workspace_and_stats_bytes": ex.budget_fixed,
+              "result_arena_bytes": ex.result_budget})
+    sweep = []
+    for rate in (500.0, 2000.0, 8000.0, 32000.0, 128000.0):
+        r = serve(make_queries(shapes, 4000, rate_hz=rate, seed=11))
+        r["rate_hz"] = rate
+        sweep.append(r)
+        log(f"[bench] serving sweep {rate:g} q/s: qps {r['qps']:.0f}, mean batch {r['mean_batch']}, "
+            f"p50 {r['p50_ms']:.3f} p99 {r['p99_ms']:.3f} max {r['max_ms']:.3f} ms")
+    s["rate_sweep"] = sweep
+    s["throughput_ceiling_qps"] = round(max(r["qps"] for r in sweep), 1)
+    ex.close()
     log(f"[bench] serving: {s}")
     return s
 

@@ -486,9 +486,11 @@ int hsz_ctx_get_tuning(hsz_ctx *ctx, const char *key, hsz_tuning *h_tune);
 /* hsz_batch_run with the context's scratch as workspace (HSZ_ERR_CAPACITY
  * when it holds less than hsz_batch_workspace) and its table copied from
  * the pinned ring: returns once the pass is enqueued on 'stream'.  The
- * status word is at the start of the scratch (hsz_read_status). */
+ * status word is at the start of the scratch (hsz_read_status); d_status
+ * (device int, 4-byte aligned, or NULL) also receives it when the pass
+ * completes. */
 int hsz_ctx_batch_run(hsz_ctx *ctx, const hsz_work *h_items, int n, const hsz_tuning *h_tune,
-                      void *stream);
+                      int *d_status, void *stream);
 /* hsz_ooc_op enqueued on 'stream' and the context's copy stream, with the
  * context's scratch as workspace (HSZ_ERR_CAPACITY below hsz_ooc_workspace):
  * returns once the pass is enqueued.  Every part of it, the device-to-host

@@ -396,8 +396,9 @@ int hsz_batch_run(const hsz_work* items, int n, const hsz_tuning* tune, void* d_
   return enqueue(B, (uint8_t*)d_workspace, t, s);
 }
 
-int hsz_ctx_batch_run(hsz_ctx* ctx, const hsz_work* items, int n, const hsz_tuning* tune, void* stream) {
-  if (!ctx) return HSZ_ERR_INVALID_ARG;
+int hsz_ctx_batch_run(hsz_ctx* ctx, const hsz_work* items, int n, const hsz_tuning* tune, int* d_status,
+                      void* stream) {
+  if (!ctx || ((uintptr_t)d_status & 3u)) return HSZ_ERR_INVALID_ARG;
   int rc = hsz_ctx_util::check_device(ctx);
   if (rc) return rc;
   std::vector<Item> its;
@@ -412,6 +413,8 @@ int hsz_ctx_batch_run(hsz_ctx* ctx, const hsz_work* items, int n, const hsz_tuni
   if (e != hipSuccess) return hip_fail(e);
   if ((rc = hsz_ctx_util::stage_copy(ctx, B.table.data(), B.table.size(), ctx->d_scratch + B.L.counts, s))) return rc;
   if ((rc = enqueue(B, ctx->d_scratch, t, s))) return rc;
+  if (d_status && (e = hsz::launch_copy_status((const int*)ctx->d_scratch, d_status, s)) != hipSuccess)
+    return hip_fail(e);
   e = hsz_ctx_util::mark_last(ctx, s);
   return e == hipSuccess ? HSZ_OK : hip_fail(e);
 }

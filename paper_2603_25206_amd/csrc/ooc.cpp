@@ -183,10 +183,6 @@ void combine(const std::vector<uint8_t>& rec, int K, int op, double quantum, hsz
   *out = o;
 }
 
-__global__ void k_ooc_status(const int* status, int* out) {
-  if (threadIdx.x == 0) *out = *status;
-}
-
 // Arguments both entry points check before anything is enqueued.
 int ooc_check(const void* const* h_slabs, const hsz_header* const* hdrs, int nslabs, int via, int op, int axis,
               const void* h_result, uint64_t result_bytes, SlabSet* S) {
@@ -401,8 +397,7 @@ int hsz_ooc_op_async(hsz_ctx* ctx, const void* const* h_slabs, const hsz_header*
   if (e == hipSuccess) e = hsz_ctx_util::order_after_last(ctx, cs);
   if (e == hipSuccess) e = ooc_enqueue(h_slabs, hdrs, S, via, op, axis, h_result, ctx->d_scratch, L, s, cs, ev, true);
   if (e == hipSuccess && d_status) {
-    hipLaunchKernelGGL(k_ooc_status, dim3(1), dim3(64), 0, s, (const int*)ctx->d_scratch, d_status);
-    e = hipGetLastError();
+    e = hsz::launch_copy_status((const int*)ctx->d_scratch, d_status, s);
   }
   // the context's last call ends here whatever happened: everything enqueued
   // on either stream is joined into 's'

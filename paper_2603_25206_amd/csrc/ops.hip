@@ -483,6 +483,10 @@ __device__ StatsOut stats_from_sums(int64_t n, int64_t s1, uint64_t s2lo, uint64
   return r;
 }
 
+__global__ void k_copy_status_word(const int* status, int* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = *status;
+}
+
 // Records of the same field's slabs (each its own exact sums) combined into
 // one: the sums add exactly (int64, 128 bits) and are finished once.
 __global__ void k_stats_combine(const StatsOut* rec, int K, int op, double quantum, StatsOut* out) {
@@ -794,6 +798,11 @@ hipError_t fused_by_via(const StreamView& v, int via, const Rows& rows, bool who
 }
 
 }  // namespace
+
+hipError_t launch_copy_status(const int* status, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_status_word, dim3(1), dim3(64), 0, s, status, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_stats_combine(const void* records, int K, int op, double quantum, void* out, hipStream_t s) {
   hipLaunchKernelGGL(k_stats_combine, dim3(1), dim3(64), 0, s, (const StatsOut*)records, K, op, quantum,

@@ -157,7 +157,7 @@ def load(path: str = LIB_PATH):
         "hsz_ctx_scratch": (i32, [P, ctypes.POINTER(ctypes.c_void_p), pu64]),
         "hsz_ctx_set_tuning": (i32, [P, ctypes.c_char_p, ctypes.POINTER(Tuning)]),
         "hsz_ctx_get_tuning": (i32, [P, ctypes.c_char_p, ctypes.POINTER(Tuning)]),
-        "hsz_ctx_batch_run": (i32, [P, ctypes.POINTER(Work), i32, ctypes.POINTER(Tuning), P]),
+        "hsz_ctx_batch_run": (i32, [P, ctypes.POINTER(Work), i32, ctypes.POINTER(Tuning), P, P]),
         "hsz_ooc_op_async": (i32, [P, P, P, i32, i32, i32, i32, P, u64, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -861,11 +861,15 @@ class Context:
         return op_on_stage(stage_buf, h, stage, op, axis=axis, box=box, stream=stream, check=False, out=out,
                            ws=self.scratch, raw=True)
 
-    def batch_run(self, jobs, tune: dict | None = None, stream=None) -> "_Batch":
-        """Enqueue one pass over the jobs; call .outputs() of the returned batch
-        after the stream has completed."""
-        b = _Batch(jobs)
+    def batch_run(self, jobs, tune: dict | None = None, stream=None, outs=None,
+                  status: torch.Tensor | None = None) -> "_Batch":
+        """Enqueue one pass over the jobs (results into 'outs', (buffer, shape)
+        per job, or fresh buffers); call .outputs() of the returned batch after
+        the stream has completed.  status: a device int32 that receives the
+        pass's status word."""
+        b = _Batch(jobs, outs=outs)
         _check(load().hsz_ctx_batch_run(self.handle, b.items, len(b.jobs), _tuning(tune),
+                                        None if status is None else ctypes.c_void_p(status.data_ptr()),
                                         ctypes.c_void_p(_stream(stream))), "ctx_batch_run")
         return b
 

@@ -340,6 +340,6 @@ def test_ctx_validation_before_any_launch(lib):
     assert lib.hsz_ctx_set_tuning(None, b"k", ctypes.byref(t)) == hsz.ERR_INVALID_ARG
     assert lib.hsz_ctx_get_tuning(None, b"k", ctypes.byref(t)) == hsz.ERR_INVALID_ARG
     items = (hsz.Work * 1)()
-    assert lib.hsz_ctx_batch_run(None, items, 1, None, None) == hsz.ERR_INVALID_ARG
+    assert lib.hsz_ctx_batch_run(None, items, 1, None, None, None) == hsz.ERR_INVALID_ARG
     assert lib.hsz_ooc_op_async(None, None, None, 1, hsz.QUANT, hsz.MEAN, 0, None, 0, None, None) == \
         hsz.ERR_INVALID_ARG

@@ -105,3 +105,55 @@ def test_query_generator_is_seeded_and_bounded():
         shape = SHAPES[q.snap]
         for lo, hi, dim in zip(q.box[0], q.box[1], shape):
             assert 0 <= lo < hi <= dim and 32 <= hi - lo <= 256
+
+
+def test_held_results_stay_charged_until_released():
+    clock = Clock()
+    ex = FakeExecutor(clock, n_slots=4)
+    budget = 80 << 20  # one 256^3 gradient result at a time
+    srv = Server(ex, mem_budget=budget, max_batch=64, clock=clock, hold_results=True)
+    released = []
+
+    def consume(q):
+        assert srv.mem_used <= budget
+        released.append(q.qid)
+        srv.release(q)
+    srv.on_done = consume
+    qs = [Query(i, 0, "gradmag", ((0, 0, 0), (256, 256, 256)), t_arrival=0.0) for i in range(5)]
+    srv.run(qs)
+    assert released == [0, 1, 2, 3, 4] and srv.mem_used == 0
+    assert all(len(b) == 1 for b in ex.launch_log)
+
+
+def test_held_results_block_admission_without_release():
+    clock = Clock()
+    ex = FakeExecutor(clock, n_slots=4)
+    srv = Server(ex, mem_budget=80 << 20, max_batch=64, clock=clock, hold_results=True)
+    qs = [Query(i, 0, "gradmag", ((0, 0, 0), (256, 256, 256)), t_arrival=0.0) for i in range(2)]
+    for q in qs:
+        srv.submit(q)
+    for _ in range(200):  # 2 ms of virtual time: the first finishes, the second waits for memory
+        srv.poll()
+        clock.t += 1e-5
+    assert len(srv.done) == 1 and len(srv.pending) == 1
+    srv.release(srv.done[0])
+    while not srv.idle():
+        srv.poll()
+        clock.t += 1e-5
+    assert len(srv.done) == 2
+
+
+def test_arena_first_fit_and_coalescing():
+    from paper_2603_25206_amd.serve import _Arena
+    a = _Arena(4096)
+    x = a.alloc(1000)  # rounded to 1024
+    y = a.alloc(1024)
+    z = a.alloc(2048)
+    assert (x, y, z) == ((0, 1024), (1024, 1024), (2048, 2048))
+    assert a.alloc(1) is None
+    a.free(*y)
+    assert a.alloc(2048) is None  # 1024 free in the middle only
+    a.free(*x)
+    assert a.free_list == [(0, 2048)]
+    a.free(*z)
+    assert a.free_list == [(0, 4096)] and a.free_bytes() == 4096
