@@ -327,7 +327,7 @@ __device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint
 
   for (int64_t p = za; p < zb; ++p) {
     decode(cur);  // A
-    __syncthreads();
+    lds_barrier();
     // B: prefetch plane p+1's payload, request plane p+2's metadata
     check(nxt);
     uint32_t pw[PF];
@@ -389,7 +389,7 @@ __device__ __forceinline__ void grad_tile(const GradJob& job, int64_t tile, uint
     stage_rest(nxt, PF);
     cur = nxt;
     nxt = nn;
-    __syncthreads();
+    lds_barrier();
   }
   // the field's last plane has no plane after it: one-sided (or 0 if nz = 1)
   if (active && z0 + zs == zb) {
@@ -650,7 +650,7 @@ __device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, ui
 
   for (int64_t p = za; p < zb; ++p) {
     decode(cur);  // A
-    __syncthreads();
+    lds_barrier();
     // B: prefetch plane p+1's payload, request plane p+2's metadata
     check(nxt);
     uint32_t pw[PF];
@@ -664,7 +664,7 @@ __device__ __forceinline__ void grad_tile_q(const GradJob& job, int64_t tile, ui
     stage_rest(nxt, PF);
     cur = nxt;
     nxt = nn;
-    __syncthreads();
+    lds_barrier();
   }
   // the field's last plane has no plane after it: one-sided (or 0 if nz = 1)
   if (active && z0 + zs == zb) {

@@ -76,14 +76,21 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t q4_rsrc(const void* base, uint
   return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(uint32_t)bytes, 0x00020000);
 }
 
+// An offset past the end of every output (outputs stay below 2 GiB): a
+// buffer store there is discarded by the hardware.
+constexpr uint32_t kNoStore = 0x80000000u;
+
 // 16-byte store at byte offset 'off' of r, the whole offset in the vector
 // operand and soffset zero.  The store reads its data registers after issue,
 // and a VALU write to them in the very next instruction corrupts the last
 // lanes read; the backend pads that case with a wait state only for stores
 // whose soffset is not a register, so an offset split into an SGPR soffset
-// would leave it unguarded.
+// would leave it unguarded.  The results are written once and not read by
+// the kernel: non-temporal (cache policy nt), which measured a few percent
+// faster for the magnitude than the default policy.
+constexpr int kStoreNT = 2;
 __device__ __forceinline__ void store_b128(const f4& v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4, v), r, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4, v), r, off, 0, kStoreNT);
 }
 
 // Decode one staged block (payload words in LDS column 'col', rows kQ4NS
@@ -366,7 +373,7 @@ __device__ __forceinline__ void gradmag_tile_q4(const GradJob& job, int64_t tile
     stage_words(pw);
     cur = nn;
     nn = n3;
-    __syncthreads();
+    lds_barrier();
   };
 
   // prologue: plane za decoded into buffer 0, plane za+1 staged, metadata of za+2 in flight
@@ -383,7 +390,7 @@ __device__ __forceinline__ void gradmag_tile_q4(const GradJob& job, int64_t tile
     stage_words(pw);
     cur = nx;
     nn = meta_of(za + 2);
-    __syncthreads();
+    lds_barrier();
   }
 
   // the march, unrolled by three (plane p's values go to register set (p - za) % 3)
@@ -417,7 +424,7 @@ __device__ __forceinline__ void gradmag_tile_q4(const GradJob& job, int64_t tile
   if constexpr (ACC == 1) {
     const int64_t cnt = active ? (int64_t)nrows * 4 * zs : 0;
     U128 s2 = {as2, 0};
-    acc_add_wave((BatchAcc*)job.acc, (int64_t)as1, cnt, s2);
+    acc_add_group((BatchAcc*)job.acc, (int64_t)as1, cnt, s2, (BatchAcc*)(smem_g + L::kLdsWords), kQ4Threads / kWave);
   }
 }
 
@@ -450,7 +457,7 @@ constexpr int kQ8PF = 16;
 constexpr int kQ8LdsWords = kQ8StageOff + kQ8PF * kQ8NS;
 static_assert(kQ8Items + kWave <= kQ8NS, "a staging column per item, spares for the idle lanes of a wave");
 static_assert(kQ8Pitch * 2 >= (kQ8TXL + 64) && kQ8Pitch % 64 == 4, "row pitch");
-static_assert(kQ8LdsWords * 4 * 2 <= 163840, "two workgroups per compute unit");
+static_assert((kQ8LdsWords * 4 + (kQ8Threads / kWave) * 32) * 2 <= 163840, "two workgroups per compute unit");
 
 typedef short s2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) short lds_i16;
@@ -581,33 +588,38 @@ __device__ __forceinline__ void gradmag_tile_q8(const GradJob& job, int64_t tile
   const uint32_t bk0 = decoder ? (uint32_t)((za * d.y + dy) * (int64_t)bpr + fb + dk) : 0u;
   const uint32_t pstride = (uint32_t)(d.y * (int64_t)bpr);
 
+  // a block's metadata: the loads are issued a plane ahead and their values
+  // combined only when used (check), never right after the loads
   struct Meta {
-    int w, q0, words;
-    uint32_t off;
-    bool valid;
+    int w, q0;
+    uint32_t cl, rel;  // chunk offset and offset in the chunk
   };
+  auto valid_at = [&](int64_t p) { return decoder && p < zb; };
   auto meta_of = [&](int64_t p) {
     Meta m;
-    m.valid = decoder && p < zb;
-    const uint32_t bk = m.valid ? bk0 + (uint32_t)(p - za) * pstride : 0u;
+    const uint32_t bk = valid_at(p) ? bk0 + (uint32_t)(p - za) * pstride : 0u;
     m.w = (int)__builtin_amdgcn_raw_buffer_load_b8(r_meta, bk, so_w, 0);
     m.q0 = (int)__builtin_amdgcn_raw_buffer_load_b32(r_meta, 4 * bk, so_q0, 0);
-    const uint32_t rel = __builtin_amdgcn_raw_buffer_load_b16(r_rel, 2 * bk, 0, 0);
-    const uint32_t cl = __builtin_amdgcn_raw_buffer_load_b32(r_meta, 8 * (bk / kChunkBlocks), so_co, 0);
-    m.off = cl + rel;
-    m.words = 0;
+    m.rel = __builtin_amdgcn_raw_buffer_load_b16(r_rel, 2 * bk, 0, 0);
+    m.cl = __builtin_amdgcn_raw_buffer_load_b32(r_meta, 8 * (bk / kChunkBlocks), so_co, 0);
     return m;
   };
-  auto check = [&](Meta& m) {
-    m.words = m.valid ? block_words<S>(m.w) : 0;
-    if (m.valid && (m.w > kQ4MaxW || m.words > kmax || (uint64_t)m.off + (uint64_t)m.words > v.payload_words)) {
+  // payload words of plane p's block (0 if it has none) and their offset; a
+  // block whose metadata disagrees with the stream is reported and decoded
+  // with width 0
+  auto check = [&](Meta& m, int64_t p, uint32_t& off) -> int {
+    off = m.cl + m.rel;
+    const bool ok = valid_at(p);
+    int words = ok ? block_words<S>(m.w) : 0;
+    if (ok && (m.w > kQ4MaxW || words > kmax || (uint64_t)off + (uint64_t)words > v.payload_words)) {
       record_status(status, kErrBadStream);
       m.w = 0;
-      m.words = 0;
+      words = 0;
     }
+    return words;
   };
-  auto fetch = [&](const Meta& m, uint32_t (&pw)[kQ8PF]) {
-    const uint32_t base = m.words ? 4 * m.off : 0x80000000u;
+  auto fetch = [&](int words, uint32_t off, uint32_t (&pw)[kQ8PF]) {
+    const uint32_t base = words ? 4 * off : 0x80000000u;
 #pragma unroll
     for (int k = 0; k < kQ8PF; ++k) pw[k] = __builtin_amdgcn_raw_buffer_load_b32(r_pay, base + 4 * k, 0, 0);
   };
@@ -644,35 +656,37 @@ __device__ __forceinline__ void gradmag_tile_q8(const GradJob& job, int64_t tile
   int as1 = 0;
   uint64_t as2 = 0;
 
-  auto emit = [&](int64_t o, const int (&qo)[kQ8RY][4], const int (&nz)[kQ8RY][4]) {
+  // output row i of plane o from its numerators (G of the row, nz) and its
+  // stores; sums of its q.  Rows are emitted one at a time between the
+  // stencil's arithmetic, which spreads a wave's stores over the plane.
+  // The stores are issued on every path (a row or group with nothing to
+  // write gets an offset past the end of the output, and the hardware
+  // discards buffer stores out of range): with the same stores on every
+  // path the compiler counts them exactly, and never waits for a step's
+  // stores before the next step's metadata.
+  auto emit_row = [&](int64_t o, int i, const int (&qo)[4], const int (&nzr)[4], bool live) {
+    live = live && i < nrows;
     const int64_t orow = ((o - b.z0) * by) * bx + orow0;
-    int s1p = 0, s2p = 0;
+    f4 r0, r1;
 #pragma unroll
-    for (int i = 0; i < kQ8RY; ++i) {
-      if (i < nrows) {
-        f4 r0, r1;
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          r0[2 * m] = __builtin_amdgcn_sqrtf((float)sq1lo(nz[i][m], G[i][2 * m])) * h;
-          r0[2 * m + 1] = __builtin_amdgcn_sqrtf((float)sq1hi(nz[i][m], G[i][2 * m + 1])) * h;
-          r1[2 * m] = __builtin_amdgcn_sqrtf((float)sq1lo(nz[i][m + 2], G[i][2 * m + 4])) * h;
-          r1[2 * m + 1] = __builtin_amdgcn_sqrtf((float)sq1hi(nz[i][m + 2], G[i][2 * m + 5])) * h;
-        }
-        const uint32_t so = ocol + (uint32_t)(4 * (orow + i * bx));
-        if (actA) store_b128(r0, r_out, so);
-        if (actB) store_b128(r1, r_out, so + 2 * kQ8TXL);
-        if constexpr (ACC == 1) {
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const int qm = (m < 2 ? actA : actB) ? qo[i][m] : 0;
-            const int lo = (int)(short)(qm & 0xffff), hi = qm >> 16;
-            s1p += lo + hi;
-            s2p += __mul24(lo, lo) + __mul24(hi, hi);
-          }
-        }
-      }
+    for (int m = 0; m < 2; ++m) {
+      r0[2 * m] = __builtin_amdgcn_sqrtf((float)sq1lo(nzr[m], G[i][2 * m])) * h;
+      r0[2 * m + 1] = __builtin_amdgcn_sqrtf((float)sq1hi(nzr[m], G[i][2 * m + 1])) * h;
+      r1[2 * m] = __builtin_amdgcn_sqrtf((float)sq1lo(nzr[m + 2], G[i][2 * m + 4])) * h;
+      r1[2 * m + 1] = __builtin_amdgcn_sqrtf((float)sq1hi(nzr[m + 2], G[i][2 * m + 5])) * h;
     }
+    const uint32_t so = ocol + (uint32_t)(4 * (orow + i * bx));
+    store_b128(r0, r_out, live && actA ? so : kNoStore);
+    store_b128(r1, r_out, live && actB ? so + 2 * kQ8TXL : kNoStore);
     if constexpr (ACC == 1) {
+      // per row and lane 8 values of |q| < 2^13: both sums exact in 32 bits
+      int s1p = 0, s2p = 0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int qm = (live && (m < 2 ? actA : actB)) ? qo[m] : 0;
+        s1p = dot2(qm, 0x00010001, s1p);
+        s2p = dot2(qm, qm, s2p);
+      }
       as1 += s1p;
       as2 += (uint32_t)s2p;
     }
@@ -725,16 +739,15 @@ __device__ __forceinline__ void gradmag_tile_q8(const GradJob& job, int64_t tile
         for (int m = 0; m < 4; ++m)
           Q[M2][i][m] = z2 ? pk_sub(pk_add(Q[M1][i][m], Q[M1][i][m]), A[i + 1][m]) : Q[M1][i][m];
     }
-    if (o >= z0 && o < z0 + zs) {
-      int nz[kQ8RY][4];
+    const bool out_plane = o >= z0 && o < z0 + zs;
+    int nz[kQ8RY][4];
 #pragma unroll
-      for (int i = 0; i < kQ8RY; ++i)
+    for (int i = 0; i < kQ8RY; ++i)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) nz[i][m] = pk_sub(A[i + 1][m], Q[M2][i][m]);
-      emit(o, Q[M1], nz);
-    }
+      for (int m = 0; m < 4; ++m) nz[i][m] = pk_sub(A[i + 1][m], Q[M2][i][m]);
 #pragma unroll
     for (int i = 0; i < kQ8RY; ++i) {
+      emit_row(o, i, Q[M1][i], nz[i], out_plane);  // before G[i] is replaced
       const int* a = A[i + 1];
       // per group g: (x-1, x), (x+1, x+2), (x+3, x+4) for its columns x .. x+3
       int T[2][3];
@@ -757,45 +770,45 @@ __device__ __forceinline__ void gradmag_tile_q8(const GradJob& job, int64_t tile
   // One plane: decode waves fetch plane p+2's payload (into registers) and
   // plane p+3's metadata and decode plane p+1 into the other buffer; every
   // wave then runs the stencil on plane p; the fetched words are staged last,
-  // so the loads have the decode and the stencil to land.
-  Meta cur, nn;
+  // so the loads have the decode and the stencil to land.  The metadata of
+  // plane q lives in M[(q - za) % 3], so no loaded value is ever copied
+  // (a copy would have to wait for its load, and with it for every store
+  // issued before).
+  Meta M[3];
   uint32_t pw[kQ8PF];
   auto step = [&](auto RC, int64_t p) {
+    constexpr int C = decltype(RC)::value, N1 = (C + 1) % 3, N2 = (C + 2) % 3;
     const bool odd = ((p - za) & 1) != 0;
     const lds_u32* buf = smem + (odd ? kQ8Plane : 0);
     lds_u32* nbuf = smem + (odd ? 0 : kQ8Plane);
-    Meta n3;
     if (dwave) {
-      check(nn);
-      fetch(nn, pw);
-      n3 = meta_of(p + 3);
-      if (cur.valid) decode_q8(col, cur.w, cur.q0, (lds_i16*)(nbuf + drow), e0, gl, gr);
+      uint32_t off;
+      const int words = check(M[N2], p + 2, off);
+      fetch(words, off, pw);
+      M[C] = meta_of(p + 3);
+      if (valid_at(p + 1)) decode_q8(col, M[N1].w, M[N1].q0, (lds_i16*)(nbuf + drow), e0, gl, gr);
     }
     stencil(RC, p, buf);
-    if (dwave) {
-      stage_words(pw);
-      cur = nn;
-      nn = n3;
-    }
-    __syncthreads();
+    if (dwave) stage_words(pw);
+    lds_barrier();
   };
 
   // prologue: plane za decoded into buffer 0, plane za+1's words staged,
   // plane za+2's metadata in flight
   if (dwave) {
-    cur = meta_of(za);
-    Meta nx = meta_of(za + 1);
-    check(cur);
-    fetch(cur, pw);
+    M[0] = meta_of(za);
+    M[1] = meta_of(za + 1);
+    uint32_t off;
+    int words = check(M[0], za, off);
+    fetch(words, off, pw);
     stage_words(pw);
-    if (cur.valid) decode_q8(col, cur.w, cur.q0, (lds_i16*)(smem + drow), e0, gl, gr);
-    check(nx);
-    fetch(nx, pw);
+    if (valid_at(za)) decode_q8(col, M[0].w, M[0].q0, (lds_i16*)(smem + drow), e0, gl, gr);
+    words = check(M[1], za + 1, off);
+    fetch(words, off, pw);
     stage_words(pw);
-    cur = nx;
-    nn = meta_of(za + 2);
+    M[2] = meta_of(za + 2);
   }
-  __syncthreads();
+  lds_barrier();
 
   // the march, unrolled by three (plane p's values go to register set (p - za) % 3)
   int64_t p = za;
@@ -821,7 +834,8 @@ __device__ __forceinline__ void gradmag_tile_q8(const GradJob& job, int64_t tile
           const int dlt = pk_sub(Q[C][i][m], Q[M1][i][m]);
           nz[i][m] = z2 ? pk_add(dlt, dlt) : 0;
         }
-      emit(o, Q[C], nz);
+#pragma unroll
+      for (int i = 0; i < kQ8RY; ++i) emit_row(o, i, Q[C][i], nz[i], true);
     };
     if (last == 0) tail(std::integral_constant<int, 0>{});
     else if (last == 1) tail(std::integral_constant<int, 1>{});
@@ -830,7 +844,7 @@ __device__ __forceinline__ void gradmag_tile_q8(const GradJob& job, int64_t tile
   if constexpr (ACC == 1) {
     const int64_t cnt = (int64_t)nrows * 4 * ((int)actA + (int)actB) * zs;
     U128 s2v = {as2, 0};
-    acc_add_wave((BatchAcc*)job.acc, (int64_t)as1, cnt, s2v);
+    acc_add_group((BatchAcc*)job.acc, (int64_t)as1, cnt, s2v, (BatchAcc*)(smem_g + kQ8LdsWords), kQ8Threads / kWave);
   }
 }
 
@@ -898,9 +912,10 @@ __global__ void __launch_bounds__(kQ8Threads, 4) k_batch_gradmag_q8(const GradJo
 
 template <int S, int TXL>
 size_t q4_lds() {
-  return (size_t)Q4<S, TXL>::kLdsWords * sizeof(uint32_t);
+  return (size_t)Q4<S, TXL>::kLdsWords * sizeof(uint32_t) + (kQ4Threads / kWave) * sizeof(BatchAcc);
 }
-size_t q8_lds() { return (size_t)kQ8LdsWords * sizeof(uint32_t); }
+// the tile's LDS, then one BatchAcc per wave for the workgroup's sums
+size_t q8_lds() { return (size_t)kQ8LdsWords * sizeof(uint32_t) + (kQ8Threads / kWave) * sizeof(BatchAcc); }
 
 hipError_t run_q4(const GradJob& job, int* status, hipStream_t s) {
   const int txl = q4_txl(job.b);

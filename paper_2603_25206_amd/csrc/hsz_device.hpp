@@ -283,6 +283,57 @@ __device__ __forceinline__ void acc_add_wave(BatchAcc* slot, int64_t s1, int64_t
   }
 }
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also fences
+// global memory, which makes every wave wait at each barrier until all its
+// global stores are acknowledged; the tiles below never read back what they
+// store (outputs) and only read global data nobody writes during the kernel,
+// so their barriers need the LDS ordering alone, and the stores of one
+// step then drain while the next step computes.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Sum (s1, cnt, s2) over the calling workgroup and add it to one stripe of
+// 'slot' with one set of atomics per workgroup rather than per wave (device-
+// scope atomics on a few addresses serialise): each wave reduces its lanes,
+// lane 0 leaves the wave's sums in red[wave] (LDS, one BatchAcc per wave),
+// and after a barrier wave 0 adds them up.  Every thread of the workgroup
+// calls it; 'red' is not touched again before the caller's next barrier.
+__device__ __forceinline__ void acc_add_group(BatchAcc* slot, int64_t s1, int64_t cnt, U128 s2, BatchAcc* red,
+                                              int nwaves) {
+  s1 = wave_sum64(s1);
+  cnt = wave_sum64(cnt);
+  for (int m = 32; m >= 1; m >>= 1) {
+    U128 o;
+    o.lo = __shfl_xor(s2.lo, m);
+    o.hi = __shfl_xor(s2.hi, m);
+    add_u128(s2, o);
+  }
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (lane_id() == 0) red[w] = BatchAcc{s1, cnt, s2.lo, s2.hi};
+  lds_barrier();
+  if (w != 0) return;
+  const bool mine = lane_id() < nwaves;
+  const BatchAcc v = mine ? red[lane_id()] : BatchAcc{0, 0, 0, 0};
+  int64_t t1 = wave_sum64(v.s1), tc = wave_sum64(v.cnt);
+  U128 t2 = {v.s2lo, v.s2hi};
+  for (int m = 32; m >= 1; m >>= 1) {
+    U128 o;
+    o.lo = __shfl_xor(t2.lo, m);
+    o.hi = __shfl_xor(t2.hi, m);
+    add_u128(t2, o);
+  }
+  if (lane_id() == 0) {
+    BatchAcc* a = slot + blockIdx.x % kAccStripes;
+    atomicAdd((unsigned long long*)&a->s1, (unsigned long long)t1);
+    atomicAdd((unsigned long long*)&a->cnt, (unsigned long long)tc);
+    atomicAdd((unsigned long long*)&a->s2lo, (unsigned long long)(t2.lo & 0xffffffffull));
+    atomicAdd((unsigned long long*)&a->s2hi, (unsigned long long)((t2.lo >> 32) | (t2.hi << 32)));
+  }
+}
+
 // Index of the calling wave within its workgroup, as a wave-uniform value.
 __device__ __forceinline__ int wave_in_group() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
 

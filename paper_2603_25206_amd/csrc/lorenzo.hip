@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(kThreads) k_flat_apply(int32_t* __restrict__ b
       v[k] = wave_incl_scan(v[k]);
       if (lane_id() == kWave - 1) wt[k * kWavesPerGroup + wv] = v[k];
     }
-    __syncthreads();
+    lds_barrier();
     int run = sums[t];
 #pragma unroll
     for (int k = 0; k < kFlatPer; ++k) {
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(kThreads) k_flat_apply(int32_t* __restrict__ b
       if (i < n) buf[i * es] = run + before + v[k];
       run += row;
     }
-    __syncthreads();
+    lds_barrier();  // each thread reads and writes only its own words of buf
   }
 }
 

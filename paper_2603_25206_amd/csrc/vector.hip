@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(kVThreads) k_vector_fused(VecJob j, int* statu
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       commit(cur);
-      __syncthreads();
+      lds_barrier();
       if (c + 1 < NC) issue(c + 1, p, nxt);
       else issue(0, p + 1, nxt);
       ghosts();
@@ -328,7 +328,7 @@ __global__ void __launch_bounds__(kVThreads) k_vector_fused(VecJob j, int* statu
           }
         }
       }
-      __syncthreads();
+      lds_barrier();
       cur = nxt;
     }
     emit(o, false);
