@@ -692,6 +692,24 @@ def bench_lorenzo(a, log):
         r["decode_q_then_deriv_ms"] = round(_events_ms(each(via_q), 6, cur), 4)
         r["full_decompress_then_deriv_ms"] = round(_events_ms(each(full), 6, cur), 4)
         res[f"deriv_axis{ax}"] = r
+    # the Laplacian: Eq. (laplacian_Dp) on D_p, the stencil on D_q, and full decompression + the float stencil
+    wsl = hsz.workspace(hsz.op_workspace_bytes(h, hsz.LAPLACIAN), dev, key="bench-lz-lap")
+
+    def lap_q(k):
+        hsz.decompress_to_stage(cs[k], hsz.QUANT, out=sbufs[k])
+        hsz.op_on_stage(hsz.stage_view(sbufs[k], h, hsz.QUANT), h, hsz.QUANT, hsz.LAPLACIAN, out=obuf, ws=wsl,
+                        check=False, raw=True)
+
+    def lap_f(k):
+        hsz.decompress_to_stage(cs[k], hsz.FLOAT, out=sbufs[k])
+        hsz.op_on_stage(hsz.stage_view(sbufs[k], h, hsz.FLOAT), h, hsz.FLOAT, hsz.LAPLACIAN, out=obuf, ws=wsl,
+                        check=False, raw=True)
+    res["laplacian"] = {
+        "via_p_ms": round(_events_ms(each(lambda k: hsz.op_fused(cs[k], hsz.DELTA, hsz.LAPLACIAN, out=obuf, ws=wsl,
+                                                                 check=False, raw=True)), 6, cur), 4),
+        "decode_q_then_laplacian_ms": round(_events_ms(each(lap_q), 6, cur), 4),
+        "full_decompress_then_laplacian_ms": round(_events_ms(each(lap_f), 6, cur), 4)}
+    del wsl
     # HSZp: deltas across the blocks of the flat field (device-wide prefix sum for D_q)
     cf = hsz.compress(x, a.eb, rel=True, block=a.block, inter_block=True)
     torch.cuda.synchronize()
@@ -709,6 +727,61 @@ def bench_lorenzo(a, log):
     res["inter_block_1d"] = flat
     log(f"[bench] lorenzo-nd / inter-block: {res}")
     del x, c, cs, cf, cfs, ws, wsf, obuf, sbufs
+    torch.cuda.empty_cache()
+    res["vector_field"] = bench_lorenzo_vector(a, log)
+    return res
+
+
+def bench_lorenzo_vector(a, log):
+    """A three-component 512^3 binary32 vector field (each component the
+    large-field recipe with its own seed) as HSZp-nd streams (rel eb 1e-4,
+    S=32): divergence and curl on D_p (every term's numerator from its
+    component's p, fused from the streams), through D_q (decode every
+    component, then the stencil) and after full decompression.  Three copies
+    of the streams and stage buffers are used in turn."""
+    import torch
+
+    from paper_2603_25206_amd import hsz, synth
+
+    shape = (512, 512, 512)
+    comps, orig = [], 0
+    for k in range(3):
+        f = synth.make_field_torch(synth.large_field_spec(seed=400 + k, shape=shape), "cuda")
+        comps.append(hsz.compress(f, a.eb, rel=True, block=32, lorenzo=True))
+        orig += f.numel() * f.element_size()
+        del f
+    torch.cuda.synchronize()
+    sets = list(zip(*[_clones(c) for c in comps]))
+    dev = comps[0].data.device
+    cur = torch.cuda.current_stream()
+    headers = [c.header for c in comps]
+    n = comps[0].header.n
+    outs = [torch.empty(4 * n, dtype=torch.uint8, device=dev) for _ in range(3)]
+    ws = hsz.workspace(hsz.vector_workspace_bytes(headers), dev, key="bench-lz-vec")
+    bufs = [[torch.empty(4 * n + 64, dtype=torch.uint8, device=dev) for _ in range(3)] for _ in range(ROT)]
+    res = {"components": 3, "shape": list(shape), "orig_bytes": orig, "compressed_bytes": sum(c.nbytes for c in comps),
+           "copies": ROT}
+    for op in ("divergence", "curl"):
+        nout = 3 if op == "curl" else 1
+
+        def via_p(k):
+            return lambda: hsz.vector_op_fused(list(sets[k]), op, via=hsz.DELTA, outs=outs[:nout], ws=ws, check=False)
+
+        def staged(k, st):
+            def f():
+                for c, b in zip(sets[k], bufs[k]):
+                    hsz.decompress_to_stage(c, st, out=b)
+                hsz.vector_op_on_stage([b[: 4 * n] for b in bufs[k]], headers, st, op, outs=outs[:nout], ws=ws,
+                                       check=False)
+            return f
+        ms_p = _events_ms([via_p(k) for k in range(ROT)], 6, cur)
+        ms_q = _events_ms([staged(k, hsz.QUANT) for k in range(ROT)], 6, cur)
+        ms_f = _events_ms([staged(k, hsz.FLOAT) for k in range(ROT)], 6, cur)
+        res[op] = {"via_p_ms": round(ms_p, 4), "decode_q_then_op_ms": round(ms_q, 4),
+                   "full_decompress_then_op_ms": round(ms_f, 4), "gbs_orig_via_p": round(orig / ms_p / 1e6, 1),
+                   "speedup_p_vs_full": round(ms_f / ms_p, 3), "speedup_q_vs_full": round(ms_f / ms_q, 3)}
+    log(f"[bench] lorenzo-nd vector field: {res}")
+    del comps, sets, outs, bufs, ws
     return res
 
 

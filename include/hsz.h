@@ -181,12 +181,17 @@ int hsz_compress(const void *d_x, int dtype, int ndim, const int64_t *h_dims, do
  * is HSZ_ERR_UNSUPPORTED and the stage-2 buffer is p int32[n] in the field's
  * layout.  A residual beyond 2^30 - 1 is HSZ_ERR_RANGE (status word).  On
  * stage 2 (materialised or fused, whole field only): HSZ_MEAN through the
- * nd weights of Sec. V-A, HSZ_VAR through the prefix sums of Alg. 4, and
- * HSZ_DERIV along any axis through Eq. (derivative_Dp); stages 3 and 4
+ * nd weights of Sec. V-A, HSZ_VAR through the prefix sums of Alg. 4,
+ * HSZ_DERIV along any axis through Eq. (derivative_Dp), HSZ_LAPLACIAN
+ * through Eq. (laplacian_Dp) in any rank (the prefix sums of p over every
+ * axis but one are q's backward differences along that one; the integer
+ * numerator, and so the result, equals the stage-3 route's; max|q| < 2^27),
+ * and divergence and curl of HSZp-nd vector fields (below); stages 3 and 4
  * take every operation of a delta stream.  The fused routes rebuild what
  * they need in the workspace (hsz_op_workspace: 4 bytes per point, 8 for
- * binary64 fields, beyond the operation's own).  Batches, block indexes and
- * fused vector fields return HSZ_ERR_UNSUPPORTED for these streams. */
+ * binary64 fields, beyond the operation's own; the Laplacian on stage 2
+ * keeps one more int32 field per axis).  Batches and block indexes return
+ * HSZ_ERR_UNSUPPORTED for these streams. */
 #define HSZ_FLAG_LORENZO 2u
 /* HSZ_FLAG_INTER_BLOCK selects HSZp's decorrelation (Sec. IV, prediction
  * across block borders) for fields of any rank: p_i = q_i - q_{i-1} over the
@@ -267,15 +272,16 @@ int hsz_decompress_to_stage(const void *d_c, const hsz_header *h, int stage, voi
  *      the fused path via 3) the integer numerator sum_k (q_{-1} + q_{+1} -
  *      2 q) is exact and scaled once by Delta (Eq. (laplacian_Dq)); this
  *      needs max|q| < 2^27 (else HSZ_ERR_UNSUPPORTED; stage 4 has no limit).
- *      Stage 2 and batches: HSZ_ERR_UNSUPPORTED (a 1D partition keeps no
- *      multidimensional neighbours, Sec. V-B).
+ *      Stage 2: HSZp-nd streams only (whole field, see HSZ_FLAG_LORENZO);
+ *      delta and block-mean streams and batches: HSZ_ERR_UNSUPPORTED (a 1D
+ *      partition keeps no multidimensional neighbours, Sec. V-B).
  * Derivatives follow Eq. (derivatives): central differences (q_{+1} -
  * q_{-1}) * Delta/2 inside the field and one-sided (q_1 - q_0) * Delta at
  * its ends, unit spacing, neighbours taken from the whole field even when
  * they lie outside the box; an axis of length 1 contributes 0.
  * Stage support: MEAN/VAR on stages 2, 3, 4; DERIV/GRADMAG on 2, 3, 4;
- * LAPLACIAN on 3, 4; stage 1 supports none (HSZ_ERR_UNSUPPORTED), as
- * Table II lists for SZp. */
+ * LAPLACIAN on 3, 4 (and 2 for HSZp-nd); stage 1 supports none
+ * (HSZ_ERR_UNSUPPORTED), as Table II lists for SZp. */
 
 /* Workspace an operation needs (bytes; at least 256). */
 int hsz_op_workspace(const hsz_header *h, int op, uint64_t *h_bytes);
@@ -353,23 +359,34 @@ int hsz_ooc_op(const void *const *h_slabs, const hsz_header *const *hdrs, int ns
  * stage every term is an exact integer numerator of one component times
  * that component's Delta/2, the terms of a result summed in binary64 in a
  * fixed order and rounded once; on the float stage the same differences are
- * taken on the decompressed values in the field's precision.  Stage 1, 2:
- * HSZ_ERR_UNSUPPORTED (the 1D partition keeps no multidimensional
- * neighbours, Sec. V-B).  Arrays d_stage / d_c / h hold ncomp entries. */
+ * taken on the decompressed values in the field's precision.  On stage 2
+ * (HSZp-nd components, whole field; on stage buffers, or fused via 2 from
+ * the streams, each decoded to D_p in the workspace): every term's integer
+ * numerator comes from the component's p through Eq. (derivative_Dp) (the
+ * pair p_i + p_{i+1} along the term's axis, prefix-summed over the other
+ * axes, one-sided at the ends), and the terms are combined exactly as on
+ * stage 3, so the results equal the stage-3 route's bit for bit.  Stage 1,
+ * and stage 2 of delta and block-mean streams: HSZ_ERR_UNSUPPORTED (the 1D
+ * partition keeps no multidimensional neighbours, Sec. V-B).  Arrays
+ * d_stage / d_c / h hold ncomp entries. */
 
 /* Workspace of a vector-field operation (status words and one block index
- * per component). */
+ * per component; for HSZp-nd components also ncomp + 6 (3D) or ncomp (1D,
+ * 2D) int32 fields for the stage-2 route). */
 int hsz_vector_workspace(const hsz_header *const *h, int ncomp, uint64_t *h_bytes);
 
-/* On materialised stage buffers (stage = HSZ_QUANT or HSZ_FLOAT, one buffer
- * per component from hsz_decompress_to_stage). */
+/* On materialised stage buffers (stage = HSZ_QUANT or HSZ_FLOAT, or
+ * HSZ_DELTA for HSZp-nd components; one buffer per component from
+ * hsz_decompress_to_stage). */
 int hsz_vector_op_on_stage(const void *const *d_stage, const hsz_header *const *h, int ncomp, int stage,
                            int op, const hsz_box *h_box, void *const *d_result, uint64_t cap,
                            void *d_workspace, uint64_t workspace_bytes, void *stream);
 
-/* Straight from the component streams through D_q (via = HSZ_QUANT): each
- * component's planes are decoded on chip in turn; the result equals
- * hsz_vector_op_on_stage on the quantized stage bit for bit. */
+/* Straight from the component streams through D_q (via = HSZ_QUANT, delta
+ * streams): each component's planes are decoded on chip in turn; the result
+ * equals hsz_vector_op_on_stage on the quantized stage bit for bit.  HSZp-nd
+ * components through D_p (via = HSZ_DELTA): each decoded to p in the
+ * workspace, then the stage-2 route. */
 int hsz_vector_op_fused(const void *const *d_c, const hsz_header *const *h, int ncomp, int via, int op,
                         const hsz_box *h_box, void *const *d_result, uint64_t cap, void *d_workspace,
                         uint64_t workspace_bytes, void *stream);

@@ -28,10 +28,10 @@ bool meta_mean_ok(const hsz_header* h, int op, const hsz::OpTarget& t) {
 
 bool is_stats(int op) { return op == HSZ_MEAN || op == HSZ_VAR || op == HSZ_VAR_MT; }
 
-bool whole_box(const hsz::OpTarget& t) {
-  const hsz::Box3& b = t.box;
-  return b.z0 == 0 && b.y0 == 0 && b.x0 == 0 && b.z1 == t.d.z && b.y1 == t.d.y && b.x1 == t.d.x;
+bool whole_box(const hsz::Box3& b, const hsz::Dims3& d) {
+  return b.z0 == 0 && b.y0 == 0 && b.x0 == 0 && b.z1 == d.z && b.y1 == d.y && b.x1 == d.x;
 }
+bool whole_box(const hsz::OpTarget& t) { return whole_box(t.box, t.d); }
 
 // the Lorenzo family: HSZp-nd (nd blocks) and HSZp (deltas across the blocks
 // of the flat field); neither stores metadata
@@ -59,6 +59,12 @@ uint64_t nd_scratch_bytes(const hsz_header* h) {
   return ((h->dtype == HSZ_F64 ? 8 : 4) * (uint64_t)h->n + 255) / 256 * 256;
 }
 uint64_t nd_workspace(const hsz_header* h) { return nd_scratch_off(h) + nd_scratch_bytes(h) + flat_tmp_bytes(h); }
+// the Laplacian on D_p of an HSZp-nd stream also keeps one int32 field per
+// axis (the prefix sums of p over the other axes)
+uint64_t nd_lap_bytes(const hsz_header* h) { return ((4 * (uint64_t)h->n + 255) / 256 * 256) * (uint64_t)h->ndim; }
+uint64_t nd_workspace_op(const hsz_header* h, int op) {
+  return nd_workspace(h) + (op == HSZ_LAPLACIAN && !is_flat(h) ? nd_lap_bytes(h) : 0);
+}
 bool is_stencil(int op) { return op >= HSZ_DERIV && op <= HSZ_LAPLACIAN; }
 
 // The spread about the integer metadata mean (Sec. V-A, standard deviation
@@ -117,10 +123,11 @@ int nd_op(const void* d_c, const void* d_stage, const hsz_header* h, int stage, 
   if (op == HSZ_VAR_MT) return HSZ_ERR_UNSUPPORTED;  // block-mean streams only
   // on D_p: the whole field; the derivative for HSZp-nd only (a 1D partition
   // keeps no multidimensional layout)
-  if (stage == HSZ_DELTA && (!whole_box(t) || !(op == HSZ_MEAN || op == HSZ_VAR || (op == HSZ_DERIV && !is_flat(h)))))
+  const bool dp_stencil = (op == HSZ_DERIV || op == HSZ_LAPLACIAN) && !is_flat(h);
+  if (stage == HSZ_DELTA && (!whole_box(t) || !(op == HSZ_MEAN || op == HSZ_VAR || dp_stencil)))
     return HSZ_ERR_UNSUPPORTED;
-  if (op == HSZ_LAPLACIAN && stage == HSZ_QUANT && h->max_abs_q >= kLapMaxQ) return HSZ_ERR_UNSUPPORTED;
-  if (ws_bytes < nd_workspace(h)) return HSZ_ERR_CAPACITY;
+  if (op == HSZ_LAPLACIAN && stage <= HSZ_QUANT && h->max_abs_q >= kLapMaxQ) return HSZ_ERR_UNSUPPORTED;
+  if (ws_bytes < (stage == HSZ_DELTA ? nd_workspace_op(h, op) : nd_workspace(h))) return HSZ_ERR_CAPACITY;
   uint8_t* ws = (uint8_t*)d_ws;
   int32_t* scratch = (int32_t*)(ws + nd_scratch_off(h));
   int32_t* tmp = is_flat(h) ? (int32_t*)(ws + nd_scratch_off(h) + nd_scratch_bytes(h)) : nullptr;
@@ -129,7 +136,7 @@ int nd_op(const void* d_c, const void* d_stage, const hsz_header* h, int stage, 
   int rc = reset_status(d_ws, s);
   if (rc) return rc;
   hipError_t e = hipSuccess;
-  if (stage == HSZ_DELTA && op != HSZ_DERIV) {
+  if (stage == HSZ_DELTA && !is_stencil(op)) {
     e = hsz::launch_lz_stats(d_c ? nullptr : (const int32_t*)d_stage, v, g, op, d_result, ws, scratch, tmp, s);
   } else if (stage == HSZ_DELTA) {
     const int32_t* p = (const int32_t*)d_stage;
@@ -137,7 +144,9 @@ int nd_op(const void* d_c, const void* d_stage, const hsz_header* h, int stage, 
       e = hsz::lz_decode(v, g, HSZ_DELTA, scratch, (int*)d_ws, tmp, s);
       p = scratch;
     }
-    if (e == hipSuccess) e = hsz::lz_deriv_p(p, v, g, axis3, d_result, s);
+    if (e == hipSuccess && op == HSZ_DERIV) e = hsz::lz_deriv_p(p, v, g, axis3, d_result, s);
+    if (e == hipSuccess && op == HSZ_LAPLACIAN)
+      e = hsz::lz_laplacian_p(p, g, h->quantum, h->dtype, (int32_t*)(ws + nd_workspace(h)), d_result, s);
   } else {
     const void* buf = d_stage;
     if (d_c) {
@@ -422,7 +431,7 @@ int hsz_op_workspace(const hsz_header* h, int op, uint64_t* h_bytes) {
   if (!h || !h_bytes || (!is_stats(op) && !is_stencil(op))) return HSZ_ERR_INVALID_ARG;
   uint64_t a = hsz::op_workspace_bytes(), b = hsz::grad_workspace_bytes(h->nb);
   *h_bytes = (is_stencil(op) && b > a) ? b : a;
-  if (is_nd(h)) *h_bytes = nd_workspace(h);
+  if (is_nd(h)) *h_bytes = nd_workspace_op(h, op);
   return HSZ_OK;
 }
 
@@ -484,6 +493,38 @@ int hsz_op_fused(const void* d_c, const hsz_header* h, int via, int op, int axis
 
 // ---- vector fields ------------------------------------------------------------
 namespace {
+// HSZp-nd components (the D_p route): the components' p and one numerator
+// field per term of the largest operation on top of the common workspace
+bool vec_nd(const hsz_header* const* h, int nc) {
+  for (int c = 0; c < nc; ++c)
+    if (h[c]->flags != HSZ_FLAG_LORENZO) return false;
+  return true;
+}
+uint64_t field4(const hsz_header* h) { return (4 * (uint64_t)h->n + 255) / 256 * 256; }
+int vec_max_terms(int nc) { return nc == 3 ? 6 : nc; }
+uint64_t vec_ws(const hsz_header* const* h, int nc) {
+  int64_t nb[3] = {0, 0, 0};
+  for (int c = 0; c < nc; ++c) nb[c] = h[c]->nb;
+  uint64_t b = hsz::vector_workspace_bytes(nb, nc);
+  if (vec_nd(h, nc)) b += (uint64_t)(nc + vec_max_terms(nc)) * field4(h[0]);
+  return b;
+}
+
+// Divergence / curl of an HSZp-nd vector field on D_p (whole field): the
+// terms' numerators from each component's p, combined like the D_q route.
+int vec_dp(const hsz::VecJob& j, const hsz_header* const* h, int nc, const int32_t* const* p, uint8_t* ws,
+           hipStream_t s) {
+  int tc[6], ta[6], ts[6], to[6], nout = 0;
+  const int nt = hsz::vector_terms(j.op, nc, tc, ta, ts, to, &nout);
+  if (nt == 0) return HSZ_ERR_INVALID_ARG;
+  int64_t nb[3] = {0, 0, 0};
+  for (int c = 0; c < nc; ++c) nb[c] = h[c]->nb;
+  int32_t* nbuf = (int32_t*)(ws + hsz::vector_workspace_bytes(nb, nc) + (uint64_t)nc * field4(h[0]));
+  void* out[3] = {j.out[0], j.out[1], j.out[2]};
+  hipError_t e = hsz::lz_vector_p(p, grid_of(h[0]), nt, tc, ta, ts, to, nout, j.halfq, h[0]->dtype, nbuf, out, s);
+  return e == hipSuccess ? HSZ_OK : hip_fail(e);
+}
+
 // Validate the component headers of a vector field and fill the job.
 int vec_common(const hsz_header* const* h, int nc, int op, const hsz_box* box, void* const* d_result,
                uint64_t cap, void* d_ws, uint64_t ws_bytes, hsz::VecJob* j) {
@@ -503,9 +544,7 @@ int vec_common(const hsz_header* const* h, int nc, int op, const hsz_box* box, v
       if (h[c]->dims[k] != h0->dims[k]) return HSZ_ERR_INVALID_ARG;
   }
   if (!d_ws || !aligned16(d_ws)) return HSZ_ERR_INVALID_ARG;
-  int64_t nb[3] = {0, 0, 0};
-  for (int c = 0; c < nc; ++c) nb[c] = h[c]->nb;
-  if (ws_bytes < hsz::vector_workspace_bytes(nb, nc)) return HSZ_ERR_CAPACITY;
+  if (ws_bytes < vec_ws(h, nc)) return HSZ_ERR_CAPACITY;
   int64_t d3[3], n;
   dims3_of(h0->ndim, h0->dims, d3, &n);
   *j = hsz::VecJob{};
@@ -527,12 +566,9 @@ int vec_common(const hsz_header* const* h, int nc, int op, const hsz_box* box, v
 
 int hsz_vector_workspace(const hsz_header* const* h, int ncomp, uint64_t* h_bytes) {
   if (!h || !h_bytes || ncomp < 1 || ncomp > 3) return HSZ_ERR_INVALID_ARG;
-  int64_t nb[3] = {0, 0, 0};
-  for (int c = 0; c < ncomp; ++c) {
+  for (int c = 0; c < ncomp; ++c)
     if (!h[c]) return HSZ_ERR_INVALID_ARG;
-    nb[c] = h[c]->nb;
-  }
-  *h_bytes = hsz::vector_workspace_bytes(nb, ncomp);
+  *h_bytes = vec_ws(h, ncomp);
   return HSZ_OK;
 }
 
@@ -543,14 +579,21 @@ int hsz_vector_op_on_stage(const void* const* d_stage, const hsz_header* const* 
   int rc = vec_common(h, ncomp, op, h_box, d_result, cap, d_workspace, workspace_bytes, &j);
   if (rc) return rc;
   if (!d_stage) return HSZ_ERR_INVALID_ARG;
-  if (stage == HSZ_META || stage == HSZ_DELTA) return HSZ_ERR_UNSUPPORTED;
-  if (stage != HSZ_QUANT && stage != HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
+  if (stage == HSZ_META) return HSZ_ERR_UNSUPPORTED;
+  // on D_p: HSZp-nd components, whole field (Eq. (derivative_Dp) per term)
+  if (stage == HSZ_DELTA && (!vec_nd(h, ncomp) || !whole_box(j.b, j.d))) return HSZ_ERR_UNSUPPORTED;
+  if (stage < HSZ_DELTA || stage > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
   for (int c = 0; c < ncomp; ++c) {
     if (!d_stage[c] || !aligned16(d_stage[c])) return HSZ_ERR_INVALID_ARG;
     j.buf[c] = d_stage[c];
   }
   hipStream_t s = (hipStream_t)stream;
   if ((rc = reset_status(d_workspace, s))) return rc;
+  if (stage == HSZ_DELTA) {
+    const int32_t* p[3] = {(const int32_t*)d_stage[0], ncomp > 1 ? (const int32_t*)d_stage[1] : nullptr,
+                           ncomp > 2 ? (const int32_t*)d_stage[2] : nullptr};
+    return vec_dp(j, h, ncomp, p, (uint8_t*)d_workspace, s);
+  }
   hipError_t e = hsz::launch_vector_stage(j, stage, h[0]->dtype, s);
   return e == hipSuccess ? HSZ_OK : hip_fail(e);
 }
@@ -562,6 +605,26 @@ int hsz_vector_op_fused(const void* const* d_c, const hsz_header* const* h, int 
   int rc = vec_common(h, ncomp, op, h_box, d_result, cap, d_workspace, workspace_bytes, &j);
   if (rc) return rc;
   if (!d_c) return HSZ_ERR_INVALID_ARG;
+  if (via == HSZ_DELTA && vec_nd(h, ncomp)) {
+    // HSZp-nd: each component decoded to D_p in the workspace, then the
+    // terms on D_p (whole field)
+    if (!whole_box(j.b, j.d)) return HSZ_ERR_UNSUPPORTED;
+    for (int c = 0; c < ncomp; ++c)
+      if (!d_c[c] || !aligned16(d_c[c])) return HSZ_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = reset_status(d_workspace, s))) return rc;
+    int64_t nb[3] = {0, 0, 0};
+    for (int c = 0; c < ncomp; ++c) nb[c] = h[c]->nb;
+    uint8_t* ws = (uint8_t*)d_workspace;
+    const int32_t* p[3] = {nullptr, nullptr, nullptr};
+    for (int c = 0; c < ncomp; ++c) {
+      int32_t* pc = (int32_t*)(ws + hsz::vector_workspace_bytes(nb, ncomp) + (uint64_t)c * field4(h[0]));
+      hipError_t e = hsz::lz_decode(view_of(d_c[c], h[c]), grid_of(h[c]), HSZ_DELTA, pc, (int*)d_workspace, nullptr, s);
+      if (e != hipSuccess) return hip_fail(e);
+      p[c] = pc;
+    }
+    return vec_dp(j, h, ncomp, p, ws, s);
+  }
   if (via == HSZ_META || via == HSZ_DELTA || via == HSZ_FLOAT) return HSZ_ERR_UNSUPPORTED;
   if (via != HSZ_QUANT) return HSZ_ERR_INVALID_ARG;
   for (int c = 0; c < ncomp; ++c) {

@@ -192,6 +192,9 @@ struct VecJob {
 };
 // status words, then one block index per component
 uint64_t vector_workspace_bytes(const int64_t* nb, int nc);
+// the terms of an operation (component c, view axis a, sign s, output o) in
+// the order the kernels add them; returns their count (0: none)
+int vector_terms(int op, int nc, int* c, int* a, int* s, int* o, int* nout);
 hipError_t launch_vector_stage(const VecJob& j, int stage, int dtype, hipStream_t s);
 hipError_t launch_vector_fused(const VecJob& j, uint8_t* ws, hipStream_t s);
 

@@ -121,6 +121,23 @@ hipError_t lz_decode(const StreamView& v, const NdGrid& g, int stage, void* out,
 // p (int32, the field's layout) -> out (field dtype, whole field).
 hipError_t lz_deriv_p(const int32_t* p, const StreamView& v, const NdGrid& g, int axis3, void* out, hipStream_t s);
 
+// The central-difference numerator along axis3 on D_p (Eq. (derivative_Dp)
+// before its scaling): int32 over the whole field, the D_q route's exactly.
+hipError_t lz_numerator_p(const int32_t* p, const NdGrid& g, int axis3, int32_t* out, hipStream_t s);
+
+// The Laplacian on D_p (Eq. (laplacian_Dp)) of the whole field into out
+// (field dtype); cbuf holds g.ndim int32 fields of scratch.
+hipError_t lz_laplacian_p(const int32_t* p, const NdGrid& g, double quantum, int dtype, int32_t* cbuf, void* out,
+                          hipStream_t s);
+
+// Divergence / curl on D_p of an HSZp-nd vector field (whole field): term k
+// is component tc[k] differentiated along view axis ta[k], signed ts[k],
+// added to output to[k]; p[c] the components' D_p buffers, halfq[c] their
+// Delta/2; nbuf holds nterms int32 fields of scratch.
+hipError_t lz_vector_p(const int32_t* const* p, const NdGrid& g, int nterms, const int* tc, const int* ta,
+                       const int* ts, const int* to, int nout, const double* halfq, int dtype, int32_t* nbuf,
+                       void* const* out, hipStream_t s);
+
 // Prefix sums along the 3D view's axes z..x except 'skip' (-1: none) of an
 // int32 field stored at element stride es (1 or 2 words), in place.  A
 // single row (Z = Y = 1) is scanned device-wide in tiles of 4096 words whose

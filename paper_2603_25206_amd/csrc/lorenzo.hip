@@ -554,6 +554,49 @@ unsigned grid_of(int64_t items, int per) {
   return (unsigned)(g < 1 ? 1 : (g > 65535 ? 65535 : g));
 }
 
+// The Laplacian on D_p (Eq. (laplacian_Dp), in any rank): c_a holds the
+// prefix sums of p over every axis but a, which is q's backward difference
+// along a (c_a at index 0 is q there).  The second difference along a is
+// c_a one step further minus c_a here; the end value standing in for the
+// missing neighbour drops the first term at the far end and the second at
+// index 0 (an axis of length 1 adds 0).  The integer numerator is the D_q
+// route's exactly, scaled by Delta once.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_lz_lap(const int32_t* __restrict__ cz, const int32_t* __restrict__ cy,
+                                                    const int32_t* __restrict__ cx, NdGrid g, double quantum,
+                                                    T* __restrict__ out) {
+  const int64_t n = g.Z * g.Y * g.X, sz = g.Y * g.X;
+  for (int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
+    const int64_t z = e / sz, y = (e / g.X) % g.Y, x = e % g.X;
+    int num = 0;
+    if (cz) num += (z + 1 < g.Z ? cz[e + sz] : 0) - (z > 0 ? cz[e] : 0);
+    if (cy) num += (y + 1 < g.Y ? cy[e + g.X] : 0) - (y > 0 ? cy[e] : 0);
+    num += (x + 1 < g.X ? cx[e + 1] : 0) - (x > 0 ? cx[e] : 0);
+    out[e] = (T)((double)num * quantum);
+  }
+}
+
+// Divergence / curl terms on D_p: term k is component c_k's central-
+// difference numerator along its axis (an int32 field), signed s_k, scaled
+// by that component's Delta/2 and added in binary64 to output o_k, in the
+// order of the D_q route's terms (so the results equal it bit for bit).
+struct LzVecTerms {
+  const int32_t* num[6];
+  double halfq[6];
+  int s[6], o[6];
+  int n, nout;
+  void* out[3];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_lz_vec(LzVecTerms t, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < t.n; ++k) acc[t.o[k]] += (double)(t.s[k] * t.num[k][e]) * t.halfq[k];
+    for (int o = 0; o < t.nout; ++o) ((T*)t.out[o])[e] = (T)acc[o];
+  }
+}
+
 __global__ void __launch_bounds__(kThreads) k_clear_i32(int32_t* __restrict__ p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) p[i] = 0;
 }
@@ -651,6 +694,59 @@ hipError_t lz_decode(const StreamView& v, const NdGrid& g, int stage, void* out,
   else
     hipLaunchKernelGGL(k_lz_dequant<double>, dim3(grid_of(n, kThreads)), dim3(kThreads), 0, s, out, n, es,
                        v.quantum);
+  return hipGetLastError();
+}
+
+hipError_t lz_numerator_p(const int32_t* p, const NdGrid& g, int axis3, int32_t* out, hipStream_t s) {
+  const int64_t n = g.Z * g.Y * g.X;
+  hipLaunchKernelGGL(k_lz_pair, dim3(grid_of(n, kThreads)), dim3(kThreads), 0, s, p, g, axis3, out, 1);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? lz_scan_axes(out, g.Z, g.Y, g.X, 1, axis3, nullptr, s) : e;
+}
+
+hipError_t lz_laplacian_p(const int32_t* p, const NdGrid& g, double quantum, int dtype, int32_t* cbuf, void* out,
+                          hipStream_t s) {
+  const int64_t n = g.Z * g.Y * g.X;
+  const int first = 3 - g.ndim;  // the field's slowest axis in the 3D view
+  const int32_t* c[3] = {nullptr, nullptr, nullptr};
+  for (int a = first; a < 3; ++a) {
+    int32_t* ca = cbuf + (uint64_t)(a - first) * (uint64_t)n;
+    hipError_t e = hipMemcpyAsync(ca, p, 4 * (uint64_t)n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = lz_scan_axes(ca, g.Z, g.Y, g.X, 1, a, nullptr, s);
+    if (e != hipSuccess) return e;
+    c[a] = ca;
+  }
+  if (dtype == 1)
+    hipLaunchKernelGGL(k_lz_lap<float>, dim3(grid_of(n, kThreads)), dim3(kThreads), 0, s, c[0], c[1], c[2], g, quantum,
+                       (float*)out);
+  else
+    hipLaunchKernelGGL(k_lz_lap<double>, dim3(grid_of(n, kThreads)), dim3(kThreads), 0, s, c[0], c[1], c[2], g,
+                       quantum, (double*)out);
+  return hipGetLastError();
+}
+
+hipError_t lz_vector_p(const int32_t* const* p, const NdGrid& g, int nterms, const int* tc, const int* ta,
+                       const int* ts, const int* to, int nout, const double* halfq, int dtype, int32_t* nbuf,
+                       void* const* out, hipStream_t s) {
+  if (nterms < 1 || nterms > 6 || nout < 1 || nout > 3) return hipErrorInvalidValue;
+  const int64_t n = g.Z * g.Y * g.X;
+  LzVecTerms t{};
+  t.n = nterms;
+  t.nout = nout;
+  for (int k = 0; k < nterms; ++k) {
+    int32_t* num = nbuf + (uint64_t)k * (uint64_t)n;
+    hipError_t e = lz_numerator_p(p[tc[k]], g, ta[k], num, s);
+    if (e != hipSuccess) return e;
+    t.num[k] = num;
+    t.halfq[k] = halfq[tc[k]];
+    t.s[k] = ts[k];
+    t.o[k] = to[k];
+  }
+  for (int o = 0; o < nout; ++o) t.out[o] = out[o];
+  if (dtype == 1)
+    hipLaunchKernelGGL(k_lz_vec<float>, dim3(grid_of(n, kThreads)), dim3(kThreads), 0, s, t, n);
+  else
+    hipLaunchKernelGGL(k_lz_vec<double>, dim3(grid_of(n, kThreads)), dim3(kThreads), 0, s, t, n);
   return hipGetLastError();
 }
 

@@ -399,6 +399,31 @@ hipError_t fused_s(const VecJob& j, uint8_t* ws, hipStream_t s) {
 
 }  // namespace
 
+template <int OP, int NC>
+int terms_of(int* c, int* a, int* s, int* o, int* nout) {
+  using Tm = VTerms<OP, NC>;
+  for (int k = 0; k < Tm::n; ++k) {
+    c[k] = Tm::t[k].c;
+    a[k] = Tm::t[k].a;
+    s[k] = Tm::t[k].s;
+    o[k] = Tm::t[k].o;
+  }
+  *nout = Tm::nout;
+  return Tm::n;
+}
+
+int vector_terms(int op, int nc, int* c, int* a, int* s, int* o, int* nout) {
+  if (op == kOpDivergence) {
+    if (nc == 1) return terms_of<kOpDivergence, 1>(c, a, s, o, nout);
+    if (nc == 2) return terms_of<kOpDivergence, 2>(c, a, s, o, nout);
+    if (nc == 3) return terms_of<kOpDivergence, 3>(c, a, s, o, nout);
+  } else if (op == kOpCurl) {
+    if (nc == 2) return terms_of<kOpCurl, 2>(c, a, s, o, nout);
+    if (nc == 3) return terms_of<kOpCurl, 3>(c, a, s, o, nout);
+  }
+  return 0;
+}
+
 uint64_t vector_workspace_bytes(const int64_t* nb, int nc) {
   uint64_t off = kGradIndexOff;
   for (int c = 0; c < nc; ++c) off += ((2 * (uint64_t)nb[c] + 255) / 256) * 256;

@@ -2,14 +2,15 @@
 decorrelation) and HSZp streams (deltas across the blocks of the flat
 field) against the oracle: compressed bytes, stages 2-4, the mean with its
 weights and Alg. 4 (the running sum for HSZp) on D_p, the derivative of
-Eq. (derivative_Dp) on D_p of HSZp-nd, every operation through D_q and D_f,
-and the routes these modes refuse.
+Eq. (derivative_Dp) on D_p of HSZp-nd, the Laplacian of Eq. (laplacian_Dp)
+and the divergence and curl of HSZp-nd vector fields on D_p, every
+operation through D_q and D_f, and the routes these modes refuse.
 
 Bars: bytes, stages and integer sums bit-exact; means and variances 1e-12
-relative (the mean against max(|mean|, mean |d'|)); the D_p derivative
-equals the D_q route's bit for bit (same integer numerator, same scaling)
-and the oracle's within 1e-6 (binary32) or 1e-12 (binary64) relative plus
-4 * 2^-53 * max|d'|.
+relative (the mean against max(|mean|, mean |d'|)); the D_p derivative,
+Laplacian, divergence and curl equal the D_q route's bit for bit (same
+integer numerators, same scaling) and the oracle's within 1e-6 (binary32)
+or 1e-12 (binary64) relative plus a few 2^-53 * max|d'|.
 """
 from __future__ import annotations
 
@@ -167,6 +168,24 @@ def test_derivative_on_dp(lcase):
             assert not (err > tol).any(), (ax, float(err.max()))
 
 
+def test_laplacian_on_dp(lcase):
+    """Eq. (laplacian_Dp) in the field's rank, fused and on the stage-2
+    buffer: bit for bit the D_q route's result, and the oracle's Laplacian
+    of d' = q Delta."""
+    c = lcase["c"]
+    dbuf = hsz.decompress_to_stage(c, hsz.DELTA)
+    qbuf = hsz.decompress_to_stage(c, hsz.QUANT)
+    via_q = hsz.op_on_stage(qbuf, c.header, hsz.QUANT, "laplacian").cpu().numpy()
+    want = oracle.laplacian(lcase["xh64"])
+    m = float(np.max(np.abs(lcase["xh64"])))
+    tol = (1e-6 if lcase["f32"] else 1e-12) * np.abs(want) + 16 * 2.0 ** -53 * m
+    for got in (hsz.op_fused(c, hsz.DELTA, "laplacian"), hsz.op_on_stage(dbuf, c.header, hsz.DELTA, "laplacian")):
+        g = got.cpu().numpy()
+        assert g.shape == tuple(lcase["shape"])
+        assert np.array_equal(g.view(np.uint8), via_q.view(np.uint8))
+        assert not (np.abs(g.astype(np.float64) - want) > tol).any()
+
+
 @pytest.mark.parametrize("op", ["gradmag", "laplacian"])
 def test_stencils_through_dq_and_df(lcase, op):
     """Fused via D_q / D_f (the stage rebuilt in the workspace) equals the
@@ -193,7 +212,6 @@ def test_refused_routes(lcase):
     box = (tuple(0 for _ in shape), tuple(shape[:-1]) + (shape[-1] - 1,)) if shape[-1] > 1 else None
     dbuf = hsz.decompress_to_stage(c, hsz.DELTA)
     bad = [lambda: hsz.op_fused(c, hsz.DELTA, "gradmag"),
-           lambda: hsz.op_fused(c, hsz.DELTA, "laplacian"),
            lambda: hsz.op_on_stage(dbuf, c.header, hsz.DELTA, "gradmag"),
            lambda: hsz.op_fused(c, hsz.META, "mean"),
            lambda: hsz.op_fused(c, hsz.QUANT, "var_mt"),
@@ -201,19 +219,77 @@ def test_refused_routes(lcase):
            lambda: c.build_index()]
     if box is not None:
         bad += [lambda: hsz.op_fused(c, hsz.DELTA, "mean", box=box),
-                lambda: hsz.op_on_stage(dbuf, c.header, hsz.DELTA, "deriv", axis=0, box=box)]
+                lambda: hsz.op_on_stage(dbuf, c.header, hsz.DELTA, "deriv", axis=0, box=box),
+                lambda: hsz.op_fused(c, hsz.DELTA, "laplacian", box=box)]
     for fn in bad:
         with pytest.raises(hsz.HszError) as e:
             fn()
         assert e.value.code == hsz.ERR_UNSUPPORTED
 
 
+VCASES = [
+    ((24, 30, 40), np.float32, 1e-3, 32),
+    ((37, 41, 29), np.float32, 1e-4, 64),  # ragged blocks on every axis
+    ((60, 90), np.float64, 1e-6, 32),
+    ((1, 20, 36), np.float32, 1e-3, 32),  # one plane: the z terms are 0
+    ((45, 70), np.float32, 1e-3, 64),
+]
+
+
+@pytest.mark.parametrize("case", VCASES, ids=[case_id(c) for c in VCASES])
+@pytest.mark.parametrize("op", ["divergence", "curl"])
+def test_vector_ops_on_dp(case, op):
+    """Divergence and curl of HSZp-nd vector fields on D_p (each term from
+    its component's p by Eq. (derivative_Dp)), on stage-2 buffers and fused
+    via D_p: bit for bit the D_q route's result, and the oracle's operation
+    on the components' d' = q Delta."""
+    shape, dt, rel, S = case
+    say(f"[case] lorenzo vector {op} {case_id(case)}")
+    nd = len(shape)
+    xs = [np.ascontiguousarray(synth.gaussian_mixture(shape, 5, (2.0, max(3.0, min(shape) / 3.0)),
+                                                      seed=40 + 7 * k + S).astype(dt)) for k in range(nd)]
+    comps = [hsz.compress(torch.from_numpy(x).to(DEV), rel, rel=True, block=S, lorenzo=True) for x in xs]
+    hs = [c.header for c in comps]
+    pbufs = [hsz.decompress_to_stage(c, hsz.DELTA)[0] for c in comps]
+    qbufs = [hsz.decompress_to_stage(c, hsz.QUANT) for c in comps]
+    ref = [g.cpu().numpy() for g in _as_list(hsz.vector_op_on_stage(qbufs, hs, hsz.QUANT, op))]
+    ints = [oracle.dequantize64(oracle.decompress(c.to_bytes(), oracle.QUANT), c.header.quantum) for c in comps]
+    want = (oracle.divergence if op == "divergence" else oracle.curl)(ints)
+    wants = list(want) if (op == "curl" and nd == 3) else [want]
+    m = max(float(np.abs(i).max()) for i in ints)
+    for run in (lambda: hsz.vector_op_on_stage(pbufs, hs, hsz.DELTA, op),
+                lambda: hsz.vector_op_fused(comps, op, via=hsz.DELTA)):
+        got = [g.cpu().numpy() for g in _as_list(run())]
+        assert len(got) == len(ref) == len(wants)
+        for g, r, w in zip(got, ref, wants):
+            assert np.array_equal(g.view(np.uint8), r.view(np.uint8))
+            tol = (1e-6 if dt == np.float32 else 1e-12) * np.abs(w) + 16 * 2.0 ** -53 * m
+            assert not (np.abs(g.astype(np.float64) - w) > tol).any()
+    box = (tuple(0 for _ in shape), tuple(shape[:-1]) + (shape[-1] - 1,))
+    for fn in (lambda: hsz.vector_op_on_stage(pbufs, hs, hsz.DELTA, op, box=box),
+               lambda: hsz.vector_op_fused(comps, op, via=hsz.DELTA, box=box)):
+        with pytest.raises(hsz.HszError) as e:
+            fn()
+        assert e.value.code == hsz.ERR_UNSUPPORTED
+
+
+def _as_list(r):
+    return list(r) if isinstance(r, tuple) else [r]
+
+
 def test_vector_fields_and_one_dimensional_fields_refused():
     x = np.ascontiguousarray(synth.gaussian_mixture((12, 40), 3, (2.0, 6.0), seed=1).astype(np.float32))
     comps = [hsz.compress(torch.from_numpy(x * (k + 1)).to(DEV), 1e-3, lorenzo=True) for k in range(2)]
     with pytest.raises(hsz.HszError) as e:
-        hsz.vector_op_fused(comps, "divergence")
+        hsz.vector_op_fused(comps, "divergence")  # fused windows through D_q decode delta streams
     assert e.value.code == hsz.ERR_UNSUPPORTED
+    plain = [hsz.compress(torch.from_numpy(x * (k + 1)).to(DEV), 1e-3) for k in range(2)]
+    pb = [hsz.decompress_to_stage(cc, hsz.DELTA)[0] for cc in plain]
+    for fn in (lambda: hsz.vector_op_on_stage(pb, [cc.header for cc in plain], hsz.DELTA, "divergence"),
+               lambda: hsz.vector_op_fused(plain, "divergence", via=hsz.DELTA)):
+        with pytest.raises(hsz.HszError) as e:
+            fn()  # stage 2 of delta streams keeps no multidimensional neighbours
+        assert e.value.code == hsz.ERR_UNSUPPORTED
     qb = [hsz.decompress_to_stage(cc, hsz.QUANT) for cc in comps]  # materialised stage 3 works
     got = hsz.vector_op_on_stage(qb, [cc.header for cc in comps], hsz.QUANT, "divergence").cpu().numpy()
     ints = [oracle.dequantize64(oracle.decompress(cc.to_bytes(), oracle.QUANT), cc.header.quantum) for cc in comps]
@@ -314,6 +390,7 @@ def test_inter_block_stencils_and_refusals(fcase):
     tol = (1e-6 if fcase["x"].dtype == np.float32 else 1e-12) * np.abs(want) + 4 * 2.0 ** -53 * m
     assert not (np.abs(a.astype(np.float64) - want) > tol).any()
     for fn in (lambda: hsz.op_fused(c, hsz.DELTA, "deriv", axis=nd - 1),
+               lambda: hsz.op_fused(c, hsz.DELTA, "laplacian"),
                lambda: hsz.decompress_to_stage(c, hsz.META),
                lambda: hsz.Plan([hsz.Job(c, "var", hsz.QUANT)])):
         with pytest.raises(hsz.HszError) as e:
