@@ -46,7 +46,12 @@ hsz::NdGrid grid_of(const hsz_header* h) {
 }
 
 // tile sums of the device-wide scan of HSZp's single row (stages 3 and 4)
-uint64_t flat_tmp_bytes(const hsz_header* h) { return is_flat(h) ? hsz::lz_scan_tmp_bytes(h->n) : 0; }
+// HSZp: tile sums of the flat row's scan; HSZp-nd: the z segments' totals of
+// the two-pass D_q (rows of at most 512 columns)
+uint64_t lz_tmp_bytes(const hsz_header* h) {
+  if (is_flat(h)) return hsz::lz_scan_tmp_bytes(h->n);
+  return is_nd(h) ? hsz::lz_dq_tmp_bytes(grid_of(h)) : 0;
+}
 
 // HSZp-nd streams: the fused routes and the D_p operations rebuild a stage
 // in scratch memory after the operation's own workspace (4 bytes per point,
@@ -58,7 +63,7 @@ uint64_t nd_scratch_off(const hsz_header* h) {
 uint64_t nd_scratch_bytes(const hsz_header* h) {
   return ((h->dtype == HSZ_F64 ? 8 : 4) * (uint64_t)h->n + 255) / 256 * 256;
 }
-uint64_t nd_workspace(const hsz_header* h) { return nd_scratch_off(h) + nd_scratch_bytes(h) + flat_tmp_bytes(h); }
+uint64_t nd_workspace(const hsz_header* h) { return nd_scratch_off(h) + nd_scratch_bytes(h) + lz_tmp_bytes(h); }
 // the Laplacian on D_p of an HSZp-nd stream also keeps one int32 field per
 // axis (the prefix sums of p over the other axes)
 uint64_t nd_lap_bytes(const hsz_header* h) { return ((4 * (uint64_t)h->n + 255) / 256 * 256) * (uint64_t)h->ndim; }
@@ -130,7 +135,7 @@ int nd_op(const void* d_c, const void* d_stage, const hsz_header* h, int stage, 
   if (ws_bytes < (stage == HSZ_DELTA ? nd_workspace_op(h, op) : nd_workspace(h))) return HSZ_ERR_CAPACITY;
   uint8_t* ws = (uint8_t*)d_ws;
   int32_t* scratch = (int32_t*)(ws + nd_scratch_off(h));
-  int32_t* tmp = is_flat(h) ? (int32_t*)(ws + nd_scratch_off(h) + nd_scratch_bytes(h)) : nullptr;
+  int32_t* tmp = lz_tmp_bytes(h) ? (int32_t*)(ws + nd_scratch_off(h) + nd_scratch_bytes(h)) : nullptr;
   const hsz::StreamView v = view_of(d_c, h);
   const hsz::NdGrid g = grid_of(h);
   int rc = reset_status(d_ws, s);
@@ -385,7 +390,7 @@ int hsz_decompress_workspace(const hsz_header* h, int stage, uint64_t* h_bytes) 
   int rc = check_header(h);
   if (rc) return rc;
   if (!h_bytes || stage < HSZ_META || stage > HSZ_FLOAT) return HSZ_ERR_INVALID_ARG;
-  *h_bytes = 256 + (stage >= HSZ_QUANT ? flat_tmp_bytes(h) : 0);
+  *h_bytes = 256 + (stage >= HSZ_QUANT ? lz_tmp_bytes(h) : 0);
   return HSZ_OK;
 }
 

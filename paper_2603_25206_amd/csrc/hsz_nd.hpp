@@ -84,28 +84,84 @@ inline int lz_kmax(uint32_t max_abs_q) {
   return tile_rows<S>(wmax > kMaxWidth ? kMaxWidth : wmax) - 1;
 }
 
-// Stage the payload of chunk c into the lane columns of 'tile' (row k at
-// tile + k*64, lane l <-> block 64c + l) and return the lane's block width;
-// an inconsistent chunk records a status and its blocks decode as zeros.
+// payload words per lane in flight per round trip of the chunk staging below
+constexpr int kStageBatch = 8;
+
+// a value every lane of the wave holds, moved to scalar registers
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+}
+
+// A chunk's metadata as loaded: the lane's block width (through a
+// descriptor of the chunk's blocks: a lane past the last block reads 0) and
+// the chunk's word offsets, all in one round trip.  Nothing here waits for
+// the loads, so a caller may issue them a step ahead of their use.
+struct LzMeta {
+  int w;
+  uint64_t base, next;
+};
+
+__device__ __forceinline__ LzMeta lz_meta(const StreamView& v, int64_t c) {
+  const int64_t b0 = c * kChunkBlocks;
+  const int64_t nbc = v.nb - b0 < kChunkBlocks ? v.nb - b0 : kChunkBlocks;
+  const __amdgpu_buffer_rsrc_t r_w =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(v.width + b0), (short)0, (int)(nbc > 0 ? nbc : 0), 0x00020000);
+  LzMeta m;
+  m.w = (int)__builtin_amdgcn_raw_buffer_load_b8(r_w, (uint32_t)lane_id(), 0, 0);
+  m.base = v.chunk_off[c];
+  m.next = v.chunk_off[c + 1];
+  return m;
+}
+
+// Stage the payload of chunk c (metadata m) into the lane columns of 'tile'
+// (row k at tile + k*64, lane l <-> block 64c + l) and return the lane's
+// block width; an inconsistent chunk records a status and its blocks decode
+// as zeros.
 template <int S>
-__device__ __forceinline__ int lz_stage(const StreamView& v, int64_t c, uint32_t* tile, int kmax, int* status) {
+__device__ __forceinline__ int lz_stage_meta(const StreamView& v, const LzMeta& m, uint32_t* tile, int kmax,
+                                             int* status) {
   const int l = lane_id();
-  const int64_t b = c * kChunkBlocks + l;
-  int w = b < v.nb ? (int)v.width[b] : 0;
+  // the offsets are the wave's (c is): moved to scalar registers, so the
+  // payload descriptor below is one
+  const uint64_t base = uniform_u64(m.base), next = uniform_u64(m.next);
+  int w = m.w;
   int nw = block_words<S>(w);
   const bool bad = (w > kMaxWidth) || (nw > kmax);
   const int incl = wave_incl_scan(bad ? 0 : nw);
   const int woff = incl - (bad ? 0 : nw);
-  const int total = __shfl(incl, kWave - 1);
-  const uint64_t base = v.chunk_off[c], next = v.chunk_off[c + 1];
+  const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
   if (__any(bad) || next - base != (uint64_t)total || next > v.payload_words) {
     if (l == 0) record_status(status, kErrBadStream);
     w = 0;
     nw = 0;
   }
-  const uint32_t* src = v.payload + base + woff;
-  for (int k = 0; k < nw; ++k) tile[k * kWave + l] = src[k];
+  // kStageBatch words per lane in flight per round trip (a load, its wait
+  // and the LDS write per word would make the chunk's latency its width in
+  // trips).  Loads through a descriptor of the chunk's words: past a lane's
+  // own words the offset leaves the descriptor and the load returns 0, so no
+  // lane branches; rows past the lane's width are written with those zeros,
+  // up to the tile's last row.
+  const uint32_t chunk_bytes = (uint32_t)total * 4u;
+  const __amdgpu_buffer_rsrc_t r_pay =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(v.payload + base), (short)0, (int)chunk_bytes, 0x00020000);
+  for (int k0 = 0; __any(k0 < nw); k0 += kStageBatch) {
+    uint32_t r[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u)
+      r[u] = __builtin_amdgcn_raw_buffer_load_b32(r_pay, k0 + u < nw ? 4u * (uint32_t)(woff + k0 + u) : 0x80000000u,
+                                                  0, 0);
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u)
+      if (k0 + u <= kmax) tile[(k0 + u) * kWave + l] = r[u];
+  }
   return w;
+}
+
+// The two steps above at once.
+template <int S>
+__device__ __forceinline__ int lz_stage(const StreamView& v, int64_t c, uint32_t* tile, int kmax, int* status) {
+  return lz_stage_meta<S>(v, lz_meta(v, c), tile, kmax, status);
 }
 
 // Decoding of an HSZp-nd stream to stage 2 (p, int32, the field's layout),
@@ -120,6 +176,18 @@ hipError_t lz_decode(const StreamView& v, const NdGrid& g, int stage, void* out,
 // Derivative along axis3 (of the 3D view) on D_p (Eq. (derivative_Dp)):
 // p (int32, the field's layout) -> out (field dtype, whole field).
 hipError_t lz_deriv_p(const int32_t* p, const StreamView& v, const NdGrid& g, int axis3, void* out, hipStream_t s);
+
+// D_q of an HSZp-nd stream in two passes for fields of three dimensions
+// whose rows hold at most 512 columns, a multiple of 4 (lz_dq_ok): lz_dq_front decodes and takes the prefix sums along x and,
+// within z segments, along z into t (the field's layout) and the segments'
+// totals into tot (lz_dq_tmp_bytes), then the exclusive prefix of those over
+// segments; q is then the prefix sum along y of t plus tot of the element's
+// segment (seg_planes planes each).  lz_decode takes this route for stages
+// 3 and 4 (binary32) when given tmp of lz_dq_tmp_bytes.
+bool lz_dq_ok(const NdGrid& g);
+uint64_t lz_dq_tmp_bytes(const NdGrid& g);
+hipError_t lz_dq_front(const StreamView& v, const NdGrid& g, int32_t* t, int32_t* tot, int* status, hipStream_t s,
+                       int64_t* seg_planes);
 
 // The central-difference numerator along axis3 on D_p (Eq. (derivative_Dp)
 // before its scaling): int32 over the whole field, the D_q route's exactly.

@@ -331,6 +331,221 @@ __global__ void __launch_bounds__(kThreads) k_scan_strided4(int32_t* __restrict_
   }
 }
 
+// ---- D_q in two passes (HSZp-nd, rows of at most kDqMaxX columns) -------------
+// q = prefix sums of p along x, y and z.  First pass: a workgroup owns one
+// block row (BY rows, all columns) and a segment of block layers along z.
+// Per layer its blocks are decoded into an LDS copy of the layer's BZ x BY
+// rows; wave w then prefix-sums rows w, w + 4, .. of each plane along x
+// (eight consecutive columns per lane, a wave scan of the lane totals) and
+// adds the running sum along z of each position, kept in registers from
+// plane to plane within the segment, writing t (prefix over x and over the
+// segment's planes up to z); at the segment's end the running sums, the
+// segment's totals, go to tot[segment][y][x].  Second pass: a thread per
+// (z, two columns) walks y with a running sum of t plus the totals of the
+// earlier segments (the exclusive prefix of tot over segments), which is q.
+// Two passes over the field instead of decoding and three prefix passes.
+// The lane that scans eight columns also owns their running sums along z
+// and stores them (two 16-byte words), so the scanned row never returns to
+// LDS; the next layer's chunk metadata is loaded a layer ahead.
+typedef int i4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr uint32_t kDqNoStore = 0x80000000u;  // a buffer offset past every row: the store is discarded
+constexpr int kDqMaxX = 512;   // eight columns per lane
+constexpr int kDqMaxSeg = 16;  // z segments, at most
+
+template <int S, int ND>
+__global__ void __launch_bounds__(kThreads) k_lz_dq1(StreamView v, NdGrid g, int kmax, int wave_words, int ndec,
+                                                    int pitch, int64_t seg_layers, int32_t* __restrict__ t,
+                                                    int32_t* __restrict__ tot, int* status) {
+  using Sh = NdShape<ND, S>;
+  constexpr int BZ = Sh::BZ, BY = Sh::BY, BX = Sh::BX;
+  constexpr int RPW = (BY + kWavesPerGroup - 1) / kWavesPerGroup;  // rows per wave
+  constexpr int V = kDqMaxX / kWave;
+  extern __shared__ uint32_t smem[];
+  const int wv = wave_in_group(), l = lane_id();
+  // a layer's blocks span at most ndec chunks (the host's count), one per
+  // wave: only those waves hold a staging tile
+  uint32_t* stage = smem + wv * wave_words;
+  int32_t* lay = (int32_t*)(smem + ndec * wave_words);
+  const int64_t by = blockIdx.x % g.nby, seg = blockIdx.x / g.nby;
+  const int L0 = (int)(seg * seg_layers), L1 = (int)min(L0 + seg_layers, g.nbz);
+  const int nbx = (int)g.nbx;
+  const int64_t X = g.X, YX = g.Y * g.X;
+  int carry[RPW][V];
+#pragma unroll
+  for (int k = 0; k < RPW; ++k)
+#pragma unroll
+    for (int m = 0; m < V; ++m) carry[k][m] = 0;
+  // the wave's chunk of layer bz (blocks b0..b1 of the layer are consecutive
+  // in the stream, one lane each), or -1
+  // (32-bit tests: the layer's first block sits b0 % 64 into its chunk)
+  auto chunk_of = [&](int bz, int64_t& b0) {
+    b0 = ((int64_t)bz * g.nby + by) * g.nbx;
+    const int in_chunk = (int)(b0 % kChunkBlocks);
+    return (bz < L1 && wv < ndec && wv * kChunkBlocks - in_chunk < nbx) ? b0 / kChunkBlocks + wv : (int64_t)-1;
+  };
+  // metadata of chunk c, loaded unconditionally (chunk 0 stands in for none)
+  // so the waits count the loads exactly
+  auto meta_of = [&](int64_t c) { return lz_meta(v, c >= 0 ? c : 0); };
+  auto layer = [&](int bz, int64_t c, int64_t b0, const LzMeta& m) {
+    if (c >= 0) {
+      const int w = lz_stage_meta<S>(v, m, stage, kmax, status);
+      const int64_t b = c * kChunkBlocks + l;
+      if (b >= b0 && b < b0 + nbx) {
+        int32_t* dst = lay + (b - b0) * BX;
+        decode_lane_block<S, kWave, true>(stage + l, w, 0, [&](int j, int p, int) {
+          dst[((j / BX) / BY % BZ * BY + (j / BX) % BY) * pitch + j % BX] = p;
+        });
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int sz = 0; sz < BZ; ++sz) {
+      const int64_t z = (int64_t)bz * BZ + sz;
+#pragma unroll
+      for (int k = 0; k < RPW; ++k) {
+        const int sy = wv + kWavesPerGroup * k;
+        if (BY % kWavesPerGroup != 0 && sy >= BY) continue;
+        const int64_t y = by * BY + sy;
+        const bool ok = z < g.Z && y < g.Y;
+        const int32_t* row = lay + (sz * BY + sy) * pitch;
+        // x prefix: the lane's eight consecutive columns, then the lane totals
+        const i4v lo = *(const i4v*)(row + V * l), hi = *(const i4v*)(row + V * l + 4);
+        const int in[V] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+        int vals[V], run = 0;
+#pragma unroll
+        for (int m = 0; m < V; ++m) {
+          run += V * l + m < X ? in[m] : 0;
+          vals[m] = run;
+        }
+        const int off = wave_incl_scan(run) - run;
+        // then the running sum along z (rows past the field add nothing), and
+        // the row stored as two 16-byte words per lane; every lane stores,
+        // offsets past the row (or a row past the field) are discarded, so
+        // the stores are the same on every path
+#pragma unroll
+        for (int m = 0; m < V; ++m) carry[k][m] += ok ? vals[m] + off : 0;
+        const __amdgpu_buffer_rsrc_t r_row = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(ok ? t + z * YX + y * X : t), (short)0, ok ? (int)(4 * X) : 0, 0x00020000);
+        const uint32_t o = 4u * (uint32_t)(V * l);
+        __builtin_amdgcn_raw_buffer_store_b128(i4v{carry[k][0], carry[k][1], carry[k][2], carry[k][3]}, r_row,
+                                               V * l < X ? o : kDqNoStore, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(i4v{carry[k][4], carry[k][5], carry[k][6], carry[k][7]}, r_row,
+                                               V * l + 4 < X ? o + 16u : kDqNoStore, 0, 0);
+      }
+    }
+    lds_barrier();
+  };
+  // layers in pairs with two metadata sets in turn: a layer's metadata is
+  // loaded before the previous layer is decoded and stored, so its wait
+  // includes none of that layer's stores
+  int64_t bA = 0, bB = 0;
+  int64_t cA = chunk_of(L0, bA), cB = -1;
+  LzMeta mA = meta_of(cA), mB;
+  for (int bz = L0; bz < L1; bz += 2) {
+    cB = chunk_of(bz + 1, bB);
+    mB = meta_of(cB);
+    layer(bz, cA, bA, mA);
+    if (bz + 1 >= L1) break;
+    cA = chunk_of(bz + 2, bA);
+    mA = meta_of(cA);
+    layer(bz + 1, cB, bB, mB);
+  }
+  // the segment's totals
+#pragma unroll
+  for (int k = 0; k < RPW; ++k) {
+    const int sy = wv + kWavesPerGroup * k;
+    const int64_t y = by * BY + sy;
+    if (sy >= BY || y >= g.Y) continue;
+#pragma unroll
+    for (int m = 0; m < V; ++m) {
+      const int x = V * l + m;
+      if (x < X) tot[seg * YX + y * X + x] = carry[k][m];
+    }
+  }
+}
+
+// tot[s] <- sum of tot[s'] for s' < s, per position (in place)
+__global__ void __launch_bounds__(kThreads) k_lz_seg_carry(int32_t* __restrict__ tot, int nseg, int64_t YX) {
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < YX; i += (int64_t)gridDim.x * kThreads) {
+    int run = 0;
+    for (int s = 0; s < nseg; ++s) {
+      const int v = tot[s * YX + i];
+      tot[s * YX + i] = run;
+      run += v;
+    }
+  }
+}
+
+// Second pass (X even): MODE 0 writes q, MODE 1 (float)(q Delta).  Two
+// columns per thread (twice the waves of four, for latency), kDqBatch rows
+// of t and of the carries per load batch, the next batch's loads issued
+// before this batch's stores.
+constexpr int kDqBatch = 8;
+
+template <int MODE>
+__device__ __forceinline__ void dq2_put(int32_t* p, int a, int b, double quantum) {
+  typedef int i2 __attribute__((ext_vector_type(2)));
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  if constexpr (MODE == 0) *(i2*)p = i2{a, b};
+  else *(f2*)p = f2{(float)dequant64(a, quantum), (float)dequant64(b, quantum)};
+}
+
+template <int MODE>
+__device__ __forceinline__ void dq2_load(const int32_t* p, const int32_t* cr, int64_t y, int64_t h2, int2* a) {
+  typedef int i2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int u = 0; u < kDqBatch; ++u) {
+    const i2 t = ((const i2*)p)[(y + u) * h2];
+    const i2 c = ((const i2*)cr)[(y + u) * h2];
+    a[2 * u] = make_int2(t.x, t.y);
+    a[2 * u + 1] = make_int2(c.x, c.y);
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void dq2_emit(int32_t* p, int64_t y, int64_t h2, const int2* a, int& rx, int& ry,
+                                         double quantum) {
+#pragma unroll
+  for (int u = 0; u < kDqBatch; ++u) {
+    rx += a[2 * u].x + a[2 * u + 1].x;
+    ry += a[2 * u].y + a[2 * u + 1].y;
+    dq2_put<MODE>(p + 2 * (y + u) * h2, rx, ry, quantum);
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kThreads) k_lz_dq2(int32_t* __restrict__ buf, int64_t Z, int64_t Y, int64_t X,
+                                                    const int32_t* __restrict__ carry, int64_t seg_planes,
+                                                    double quantum) {
+  const int64_t h2 = X / 2, cols = Z * h2;
+  const int64_t nfull = Y / kDqBatch;
+  for (int64_t c = blockIdx.x * (int64_t)kThreads + threadIdx.x; c < cols; c += (int64_t)gridDim.x * kThreads) {
+    const int64_t z = c / h2, k = c % h2;
+    int32_t* p = buf + z * Y * X + 2 * k;
+    const int32_t* cr = carry + (z / seg_planes) * Y * X + 2 * k;
+    int rx = 0, ry = 0;
+    // two register sets in turn: a batch's loads are issued one batch of
+    // stores ahead of their use.  The loads are unconditional (past the last
+    // batch they read it again) so the waits count them exactly.
+    int2 A[2 * kDqBatch], B[2 * kDqBatch];
+    const int64_t last = nfull > 0 ? nfull - 1 : 0;
+    if (nfull > 0) dq2_load<MODE>(p, cr, 0, h2, A);
+    for (int64_t i = 0; i < nfull; i += 2) {
+      dq2_load<MODE>(p, cr, min(i + 1, last) * kDqBatch, h2, B);
+      dq2_emit<MODE>(p, i * kDqBatch, h2, A, rx, ry, quantum);
+      if (i + 1 >= nfull) break;
+      dq2_load<MODE>(p, cr, min(i + 2, last) * kDqBatch, h2, A);
+      dq2_emit<MODE>(p, (i + 1) * kDqBatch, h2, B, rx, ry, quantum);
+    }
+    for (int64_t y = nfull * kDqBatch; y < Y; ++y) {
+      rx += p[2 * y * h2] + cr[2 * y * h2];
+      ry += p[2 * y * h2 + 1] + cr[2 * y * h2 + 1];
+      dq2_put<MODE>(p + 2 * y * h2, rx, ry, quantum);
+    }
+  }
+}
+
 // ---- the derivative on D_p with its first and last passes fused ---------------
 // For binary32 outputs (element stride 1, X a multiple of 4) and a derivative
 // along z or y (so four x neighbours share their index along the axis): the
@@ -338,9 +553,6 @@ __global__ void __launch_bounds__(kThreads) k_scan_strided4(int32_t* __restrict_
 // the last pass of the prefix sums writes (float)num * (float)(Delta/2)
 // instead of the integer.  Two passes over the field fewer than pair, scans
 // and scale one after another.
-typedef int i4v __attribute__((ext_vector_type(4)));
-typedef float f4v __attribute__((ext_vector_type(4)));
-
 __device__ __forceinline__ i4v pair4(const i4v* __restrict__ p4, int64_t e4, int64_t i, int64_t L, int64_t s4) {
   if (L < 2) return i4v{0, 0, 0, 0};
   if (i == 0) return 2 * p4[e4 + s4];
@@ -632,6 +844,81 @@ hipError_t decode_p_any(const StreamView& v, const NdGrid& g, int32_t* out, int 
                        : decode_p<64, 1>(v, g, out, es, status, s, tsums);
 }
 
+// compute units of the current device (cached per device)
+int device_cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    cached[dev] = cus;
+  }
+  return cached[dev];
+}
+
+template <int S, int ND>
+hipError_t dq_front(const StreamView& v, const NdGrid& g, int32_t* t, int32_t* tot, int* status, hipStream_t s,
+                    int64_t* seg_planes) {
+  using Sh = NdShape<ND, S>;
+  const int kmax = lz_kmax<S, ND>(v.max_abs_q);
+  const int wave_words = (kmax + 1) * kWave;
+  const int pitch = kDqMaxX + 4;
+  // chunks a layer's blocks can touch: nbx / 64 when layers start on chunk
+  // borders, else one more (nbx <= 128 here, so at most 3)
+  const int ndec = (int)(g.nbx % kChunkBlocks == 0 ? g.nbx / kChunkBlocks : g.nbx / kChunkBlocks + 2);
+  if (ndec > kWavesPerGroup) return hipErrorInvalidValue;
+  const size_t lds = ((size_t)ndec * wave_words + (size_t)Sh::BZ * Sh::BY * pitch) * sizeof(uint32_t);
+  // z segments: as many workgroups as fit on the chip at once (by LDS, at
+  // most eight per compute unit)
+  const int64_t per_cu = std::min<int64_t>(8, (int64_t)(160 * 1024) / (int64_t)lds);
+  const int64_t resident = std::max<int64_t>(1, per_cu) * device_cu_count();
+  int64_t nseg = resident / g.nby;
+  nseg = nseg < 1 ? 1 : (nseg > kDqMaxSeg ? kDqMaxSeg : nseg);
+  nseg = nseg > g.nbz ? g.nbz : nseg;
+  const int64_t seg_layers = (g.nbz + nseg - 1) / nseg;
+  nseg = (g.nbz + seg_layers - 1) / seg_layers;
+  hipLaunchKernelGGL((k_lz_dq1<S, ND>), dim3((unsigned)(g.nby * nseg)), dim3(kThreads), lds, s, v, g, kmax, wave_words,
+                     ndec, pitch, seg_layers, t, tot, status);
+  hipLaunchKernelGGL(k_lz_seg_carry, dim3(grid_of(g.Y * g.X, kThreads)), dim3(kThreads), 0, s, tot, (int)nseg,
+                     g.Y * g.X);
+  *seg_planes = seg_layers * Sh::BZ;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool lz_dq_ok(const NdGrid& g) { return g.ndim == 3 && g.X <= kDqMaxX && (g.X & 3) == 0; }
+
+uint64_t lz_dq_tmp_bytes(const NdGrid& g) {
+  return lz_dq_ok(g) ? (uint64_t)kDqMaxSeg * (uint64_t)(g.Y * g.X) * sizeof(int32_t) : 0;
+}
+
+hipError_t lz_dq_front(const StreamView& v, const NdGrid& g, int32_t* t, int32_t* tot, int* status, hipStream_t s,
+                       int64_t* seg_planes) {
+  if (!lz_dq_ok(g) || !tot) return hipErrorNotSupported;
+  if (g.ndim == 3)
+    return v.block == 32 ? dq_front<32, 3>(v, g, t, tot, status, s, seg_planes)
+                         : dq_front<64, 3>(v, g, t, tot, status, s, seg_planes);
+  return v.block == 32 ? dq_front<32, 2>(v, g, t, tot, status, s, seg_planes)
+                       : dq_front<64, 2>(v, g, t, tot, status, s, seg_planes);
+}
+
+namespace {
+// D_q (mode 0) or binary32 D_f (mode 1) of an HSZp-nd stream in two passes
+hipError_t lz_dq(const StreamView& v, const NdGrid& g, int mode, int32_t* out, int32_t* tot, int* status,
+                 hipStream_t s) {
+  int64_t seg_planes = 1;
+  hipError_t e = lz_dq_front(v, g, out, tot, status, s, &seg_planes);
+  if (e != hipSuccess) return e;
+  const unsigned grid = grid_of(g.Z * g.X / 2, kThreads);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_lz_dq2<0>, dim3(grid), dim3(kThreads), 0, s, out, g.Z, g.Y, g.X, tot, seg_planes, 0.0);
+  else
+    hipLaunchKernelGGL(k_lz_dq2<1>, dim3(grid), dim3(kThreads), 0, s, out, g.Z, g.Y, g.X, tot, seg_planes,
+                       v.quantum);
+  return hipGetLastError();
+}
 }  // namespace
 
 hipError_t lz_scan_axes(int32_t* buf, int64_t Z, int64_t Y, int64_t X, int es, int skip, int32_t* tmp,
@@ -669,6 +956,8 @@ hipError_t lz_decode(const StreamView& v, const NdGrid& g, int stage, void* out,
                      hipStream_t s) {
   if (stage < 2 || stage > 4) return hipErrorInvalidValue;
   const int es = (stage == 4 && v.dtype == 2) ? 2 : 1;
+  // rows of at most kDqMaxX columns: two passes (tmp holds the z segments' totals)
+  if (es == 1 && stage >= 3 && tmp && lz_dq_ok(g)) return lz_dq(v, g, stage == 3 ? 0 : 1, (int32_t*)out, tmp, status, s);
   // the flat field's device-wide scan takes its tile sums from the decoder
   const bool fused_sums = stage >= 3 && g.ndim == 1 && g.Z * g.Y == 1 && g.X > kFlatTile && tmp;
   hipError_t e = decode_p_any(v, g, (int32_t*)out, es, status, s, fused_sums ? tmp : nullptr);

@@ -1074,6 +1074,45 @@ __global__ void __launch_bounds__(kThreads) k_lz_scan_stats(const int32_t* __res
   store_int_partial(acc, parts);
 }
 
+// Alg. 4 on the two-pass D_q: the second pass's running sum along y (t plus
+// the earlier z segments' totals) is q; its sums of q and q^2 are taken and
+// nothing is written.
+__global__ void __launch_bounds__(kThreads) k_lz_dq2_stats(const int32_t* __restrict__ buf, int64_t Z, int64_t Y,
+                                                          int64_t X, const int32_t* __restrict__ carry,
+                                                          int64_t seg_planes, Partial* parts) {
+  typedef int i2 __attribute__((ext_vector_type(2)));
+  constexpr int kRows = 8;  // rows of t and of the carries in flight per thread
+  IntAcc acc;
+  const int64_t h2 = X / 2, cols = Z * h2;
+  for (int64_t c = blockIdx.x * (int64_t)kThreads + threadIdx.x; c < cols; c += (int64_t)gridDim.x * kThreads) {
+    const int64_t z = c / h2, k = c % h2;
+    const i2* p = (const i2*)(buf + z * Y * X) + k;
+    const i2* cr = (const i2*)(carry + (z / seg_planes) * Y * X) + k;
+    i2 run = {0, 0};
+    int64_t y = 0;
+    for (; y + kRows <= Y; y += kRows) {
+      i2 a[kRows], b[kRows];
+#pragma unroll
+      for (int u = 0; u < kRows; ++u) {
+        a[u] = p[(y + u) * h2];
+        b[u] = cr[(y + u) * h2];
+      }
+#pragma unroll
+      for (int u = 0; u < kRows; ++u) {
+        run += a[u] + b[u];
+        acc.add(run.x, true);
+        acc.add(run.y, true);
+      }
+    }
+    for (; y < Y; ++y) {
+      run += p[y * h2] + cr[y * h2];
+      acc.add(run.x, true);
+      acc.add(run.y, true);
+    }
+  }
+  store_int_partial(acc, parts);
+}
+
 template <int S, int ND>
 int launch_lz_mean_fused(const StreamView& v, const NdGrid& g, Partial* parts, int* status, hipStream_t s) {
   const int kmax = lz_kmax<S, ND>(v.max_abs_q);
@@ -1111,6 +1150,21 @@ hipError_t launch_lz_stats(const int32_t* p, const StreamView& v, const NdGrid& 
     // then also provides the scan's tile sums)
     const int last = g.ndim == 3 ? 0 : (g.ndim == 2 ? 1 : -1);
     const bool to_q = !p && g.ndim == 1;
+    if (!p && tmp && lz_dq_ok(g)) {
+      // from the stream: the two-pass D_q's first pass, then its second
+      // pass summing instead of writing
+      int64_t seg_planes = 1;
+      hipError_t e = lz_dq_front(v, g, scratch, tmp, status, s, &seg_planes);
+      if (e != hipSuccess) return e;
+      grid = grid_for(g.Z * g.X / 2, kThreads);
+      hipLaunchKernelGGL(k_lz_dq2_stats, dim3(grid), dim3(kThreads), 0, s, scratch, g.Z, g.Y, g.X, tmp, seg_planes,
+                         parts);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, parts, grid, op, 0, v.quantum,
+                         (const StatsOut*)nullptr, (StatsOut*)result);
+      return hipGetLastError();
+    }
     if (p) hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n, kThreads * 4)), dim3(kThreads), 0, s, p, n, scratch);
     else {
       hipError_t e = lz_decode(v, g, to_q ? 3 : 2, scratch, status, tmp, s);

@@ -49,6 +49,9 @@ CASES = [
     ((6, 9, 1100), np.float32, 1e-3, 32),  # rows of several residual tiles, the last partial
     ((30, 1300), np.float32, 1e-3, 64),
     ((13, 21, 45), np.float64, 1e-5, 64),
+    ((35, 8, 128), np.float32, 1e-3, 32),  # z segments of two layers, the last one partial
+    ((24, 30, 96), np.float64, 1e-6, 64),  # binary64 D_q in two passes
+    ((6, 10, 512), np.float32, 1e-3, 64),  # the widest rows the two-pass D_q takes
 ]
 
 
