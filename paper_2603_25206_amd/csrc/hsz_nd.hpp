@@ -158,6 +158,74 @@ __device__ __forceinline__ int lz_stage_meta(const StreamView& v, const LzMeta& 
   return w;
 }
 
+// The staging split in two for callers that keep a chunk's payload in
+// flight while they do other work: lz_issue takes the metadata (whose loads
+// must have landed) and issues the loads of the lane's first PF payload
+// words into registers; lz_commit writes them to the tile (which holds at
+// least PF rows: all PF are written, without branches, so the wait for them
+// counts exactly the memory operations issued since) and stages the rest
+// (widths past PF words), which then waits.  A chunk of none (ok false)
+// issues loads that all fall past their descriptor.
+template <int PF>
+struct LzPending {
+  uint32_t r[PF];
+  int w, nw, woff;
+  uint64_t base;
+  int total;
+};
+
+template <int S, int PF>
+__device__ __forceinline__ LzPending<PF> lz_issue(const StreamView& v, const LzMeta& m, bool ok, int kmax,
+                                                  int* status) {
+  LzPending<PF> P;
+  const uint64_t base = uniform_u64(m.base), next = uniform_u64(m.next);
+  int w = ok ? m.w : 0;
+  int nw = block_words<S>(w);
+  const bool bad = (w > kMaxWidth) || (nw > kmax);
+  const int incl = wave_incl_scan(bad ? 0 : nw);
+  const int woff = incl - (bad ? 0 : nw);
+  const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
+  if (ok && (__any(bad) || next - base != (uint64_t)total || next > v.payload_words)) {
+    if (lane_id() == 0) record_status(status, kErrBadStream);
+    w = 0;
+    nw = 0;
+  }
+  if (!ok) nw = 0;
+  const __amdgpu_buffer_rsrc_t r_pay =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(v.payload + base), (short)0, (int)((uint32_t)total * 4u), 0x00020000);
+#pragma unroll
+  for (int u = 0; u < PF; ++u)
+    P.r[u] = __builtin_amdgcn_raw_buffer_load_b32(r_pay, u < nw ? 4u * (uint32_t)(woff + u) : 0x80000000u, 0, 0);
+  P.w = w;
+  P.nw = nw;
+  P.woff = woff;
+  P.base = base;
+  P.total = total;
+  return P;
+}
+
+template <int PF>
+__device__ __forceinline__ int lz_commit(const StreamView& v, const LzPending<PF>& P, uint32_t* tile, int kmax) {
+  const int l = lane_id();
+#pragma unroll
+  for (int u = 0; u < PF; ++u) tile[u * kWave + l] = P.r[u];
+  if (kmax >= PF) {
+    const __amdgpu_buffer_rsrc_t r_pay = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(v.payload + P.base), (short)0, (int)((uint32_t)P.total * 4u), 0x00020000);
+    for (int k0 = PF; __any(k0 < P.nw); k0 += kStageBatch) {
+      uint32_t r[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u)
+        r[u] = __builtin_amdgcn_raw_buffer_load_b32(
+            r_pay, k0 + u < P.nw ? 4u * (uint32_t)(P.woff + k0 + u) : 0x80000000u, 0, 0);
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u)
+        if (k0 + u <= kmax) tile[(k0 + u) * kWave + l] = r[u];
+    }
+  }
+  return P.w;
+}
+
 // The two steps above at once.
 template <int S>
 __device__ __forceinline__ int lz_stage(const StreamView& v, int64_t c, uint32_t* tile, int kmax, int* status) {

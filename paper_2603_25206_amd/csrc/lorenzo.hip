@@ -350,6 +350,7 @@ __global__ void __launch_bounds__(kThreads) k_scan_strided4(int32_t* __restrict_
 typedef int i4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr uint32_t kDqNoStore = 0x80000000u;  // a buffer offset past every row: the store is discarded
+constexpr int kDqPrefetch = 16;  // payload words per lane kept in flight a layer ahead
 constexpr int kDqMaxX = 512;   // eight columns per lane
 constexpr int kDqMaxSeg = 16;  // z segments, at most
 
@@ -361,12 +362,14 @@ __global__ void __launch_bounds__(kThreads) k_lz_dq1(StreamView v, NdGrid g, int
   constexpr int BZ = Sh::BZ, BY = Sh::BY, BX = Sh::BX;
   constexpr int RPW = (BY + kWavesPerGroup - 1) / kWavesPerGroup;  // rows per wave
   constexpr int V = kDqMaxX / kWave;
+  static_assert(BX == 4, "three-dimensional blocks: rows of four words");
   extern __shared__ uint32_t smem[];
   const int wv = wave_in_group(), l = lane_id();
-  // a layer's blocks span at most ndec chunks (the host's count), one per
-  // wave: only those waves hold a staging tile
-  uint32_t* stage = smem + wv * wave_words;
+  // a layer's blocks span at most ndec chunks (the host's count); chunk k
+  // of layer bz is decoded by wave (k - bz) mod 4 in staging tile k, so the
+  // decoding turns over all four waves (and their SIMDs) layer by layer
   int32_t* lay = (int32_t*)(smem + ndec * wave_words);
+  auto slot_of = [&](int bz) { return (wv + bz) & (kWavesPerGroup - 1); };
   const int64_t by = blockIdx.x % g.nby, seg = blockIdx.x / g.nby;
   const int L0 = (int)(seg * seg_layers), L1 = (int)min(L0 + seg_layers, g.nbz);
   const int nbx = (int)g.nbx;
@@ -381,24 +384,30 @@ __global__ void __launch_bounds__(kThreads) k_lz_dq1(StreamView v, NdGrid g, int
   // (32-bit tests: the layer's first block sits b0 % 64 into its chunk)
   auto chunk_of = [&](int bz, int64_t& b0) {
     b0 = ((int64_t)bz * g.nby + by) * g.nbx;
-    const int in_chunk = (int)(b0 % kChunkBlocks);
-    return (bz < L1 && wv < ndec && wv * kChunkBlocks - in_chunk < nbx) ? b0 / kChunkBlocks + wv : (int64_t)-1;
+    const int in_chunk = (int)(b0 % kChunkBlocks), k = slot_of(bz);
+    return (bz < L1 && k < ndec && k * kChunkBlocks - in_chunk < nbx) ? b0 / kChunkBlocks + k : (int64_t)-1;
   };
   // metadata of chunk c, loaded unconditionally (chunk 0 stands in for none)
   // so the waits count the loads exactly
   auto meta_of = [&](int64_t c) { return lz_meta(v, c >= 0 ? c : 0); };
-  auto layer = [&](int bz, int64_t c, int64_t b0, const LzMeta& m) {
-    if (c >= 0) {
-      const int w = lz_stage_meta<S>(v, m, stage, kmax, status);
-      const int64_t b = c * kChunkBlocks + l;
-      if (b >= b0 && b < b0 + nbx) {
-        int32_t* dst = lay + (b - b0) * BX;
-        decode_lane_block<S, kWave, true>(stage + l, w, 0, [&](int j, int p, int) {
-          dst[((j / BX) / BY % BZ * BY + (j / BX) % BY) * pitch + j % BX] = p;
-        });
-      }
+  using Pend = LzPending<kDqPrefetch>;
+  auto decode = [&](int bz, int64_t c, int64_t b0, const Pend& P) {
+    if (c < 0) return;
+    uint32_t* stage = smem + slot_of(bz) * wave_words;
+    const int w = lz_commit<kDqPrefetch>(v, P, stage, kmax);
+    const int64_t b = c * kChunkBlocks + l;
+    if (b >= b0 && b < b0 + nbx) {
+      // a block row is BX = 4 consecutive words of the layer: written as one
+      // 16-byte word (lanes 16 bytes apart, no bank conflicts)
+      int32_t* dst = lay + (b - b0) * BX;
+      i4v row4 = {0, 0, 0, 0};
+      decode_lane_block<S, kWave, true>(stage + l, w, 0, [&](int j, int p, int) {
+        row4[j % BX] = p;
+        if (j % BX == BX - 1) *(i4v*)&dst[((j / BX) / BY % BZ * BY + (j / BX) % BY) * pitch] = row4;
+      });
     }
-    lds_barrier();
+  };
+  auto rows = [&](int bz) {
 #pragma unroll
     for (int sz = 0; sz < BZ; ++sz) {
       const int64_t z = (int64_t)bz * BZ + sz;
@@ -434,22 +443,44 @@ __global__ void __launch_bounds__(kThreads) k_lz_dq1(StreamView v, NdGrid g, int
                                                V * l + 4 < X ? o + 16u : kDqNoStore, 0, 0);
       }
     }
-    lds_barrier();
   };
-  // layers in pairs with two metadata sets in turn: a layer's metadata is
-  // loaded before the previous layer is decoded and stored, so its wait
-  // includes none of that layer's stores
+  // Software pipeline over the segment's layers, in pairs with two register
+  // sets in turn: while layer L is decoded and its rows scanned and stored,
+  // the payload of layer L + 1 is in flight (issued before layer L's
+  // stores, so its wait includes none of them) and the metadata of layer
+  // L + 2 too.
+  // The first layer is peeled off so that the loop is entered, as it is
+  // repeated, just after a layer's stores: the wait for a payload then
+  // counts the same operations on both ways in.
   int64_t bA = 0, bB = 0;
-  int64_t cA = chunk_of(L0, bA), cB = -1;
-  LzMeta mA = meta_of(cA), mB;
-  for (int bz = L0; bz < L1; bz += 2) {
-    cB = chunk_of(bz + 1, bB);
-    mB = meta_of(cB);
-    layer(bz, cA, bA, mA);
+  int64_t cA = chunk_of(L0, bA), cB = chunk_of(L0 + 1, bB);
+  LzMeta mA = meta_of(cA), mB = meta_of(cB);
+  Pend PA = lz_issue<S, kDqPrefetch>(v, mA, cA >= 0, kmax, status), PB;
+  decode(L0, cA, bA, PA);
+  cA = chunk_of(L0 + 2, bA);
+  mA = meta_of(cA);
+  PB = lz_issue<S, kDqPrefetch>(v, mB, cB >= 0, kmax, status);
+  lds_barrier();
+  rows(L0);
+  lds_barrier();
+  for (int bz = L0 + 1; bz < L1; bz += 2) {
+    decode(bz, cB, bB, PB);
+    const int64_t cB2 = chunk_of(bz + 2, bB);
+    mB = meta_of(cB2);
+    PA = lz_issue<S, kDqPrefetch>(v, mA, cA >= 0, kmax, status);
+    lds_barrier();
+    rows(bz);
+    lds_barrier();
+    cB = cB2;
     if (bz + 1 >= L1) break;
-    cA = chunk_of(bz + 2, bA);
-    mA = meta_of(cA);
-    layer(bz + 1, cB, bB, mB);
+    decode(bz + 1, cA, bA, PA);
+    const int64_t cA2 = chunk_of(bz + 3, bA);
+    mA = meta_of(cA2);
+    PB = lz_issue<S, kDqPrefetch>(v, mB, cB >= 0, kmax, status);
+    lds_barrier();
+    rows(bz + 1);
+    lds_barrier();
+    cA = cA2;
   }
   // the segment's totals
 #pragma unroll
@@ -862,7 +893,7 @@ hipError_t dq_front(const StreamView& v, const NdGrid& g, int32_t* t, int32_t* t
                     int64_t* seg_planes) {
   using Sh = NdShape<ND, S>;
   const int kmax = lz_kmax<S, ND>(v.max_abs_q);
-  const int wave_words = (kmax + 1) * kWave;
+  const int wave_words = std::max(kmax + 1, kDqPrefetch) * kWave;  // the prefetched rows are all written
   const int pitch = kDqMaxX + 4;
   // chunks a layer's blocks can touch: nbx / 64 when layers start on chunk
   // borders, else one more (nbx <= 128 here, so at most 3)
@@ -896,12 +927,9 @@ uint64_t lz_dq_tmp_bytes(const NdGrid& g) {
 
 hipError_t lz_dq_front(const StreamView& v, const NdGrid& g, int32_t* t, int32_t* tot, int* status, hipStream_t s,
                        int64_t* seg_planes) {
-  if (!lz_dq_ok(g) || !tot) return hipErrorNotSupported;
-  if (g.ndim == 3)
-    return v.block == 32 ? dq_front<32, 3>(v, g, t, tot, status, s, seg_planes)
-                         : dq_front<64, 3>(v, g, t, tot, status, s, seg_planes);
-  return v.block == 32 ? dq_front<32, 2>(v, g, t, tot, status, s, seg_planes)
-                       : dq_front<64, 2>(v, g, t, tot, status, s, seg_planes);
+  if (!lz_dq_ok(g) || !tot) return hipErrorNotSupported;  // three dimensions only
+  return v.block == 32 ? dq_front<32, 3>(v, g, t, tot, status, s, seg_planes)
+                       : dq_front<64, 3>(v, g, t, tot, status, s, seg_planes);
 }
 
 namespace {
