@@ -14,10 +14,11 @@
 // component (q_{+1} - q_{-1}, or 2 (q_1 - q_0) at an end), scaled by that
 // component's Delta/2; the terms of an output are summed in binary64 in a
 // fixed order and rounded once to the field dtype.  The fused kernel decodes
-// each component's plane from its stream into one LDS plane in turn (the
-// blockwise window of Alg. 3 with one window per component); the stage
-// kernel reads materialised q buffers and sums the same terms in the same
-// order, so the two agree bit for bit.  Float route (D_f, stage buffers):
+// a plane of every component from its stream in one pass, each into its own
+// LDS window (the blockwise window of Alg. 3, one per component, with only
+// the halo that component's terms need); the stage kernel reads
+// materialised q buffers and sums the same terms in the same order, so the
+// two agree bit for bit.  Float route (D_f, stage buffers):
 // the same differences on the decompressed values in the field's precision.
 #include <algorithm>
 
@@ -65,6 +66,14 @@ struct VTerms<kOpCurl, 3> {
   static constexpr VTerm t[6] = {{1, 2, 1, 0}, {2, 1, -1, 0}, {2, 0, 1, 1},
                                  {0, 2, -1, 1}, {0, 1, 1, 2}, {1, 0, -1, 2}};
 };
+
+// whether some term differentiates component c along view axis a
+template <class Tm>
+__host__ __device__ constexpr bool needs_axis(int c, int a) {
+  for (int k = 0; k < Tm::n; ++k)
+    if (Tm::t[k].c == c && Tm::t[k].a == a) return true;
+  return false;
+}
 
 // integer numerator along one axis at coordinate i of length L
 __device__ __forceinline__ int vnum(int vm, int v0, int vp, int64_t i, int64_t L) {
@@ -136,30 +145,65 @@ struct VRow {
     return p;
   }
   static constexpr int kPitch = pitch();
-  static constexpr int kStageOff = (kRows * kPitch + 63) / 64 * 64;
   static __host__ __device__ constexpr int at(int e) { return e + (e >> 5); }
 };
 
 template <int OP, int NC>
 constexpr int vty() { return (OP == kOpCurl && NC == 3) ? 4 : 8; }
 
+// The windows of one plane, one per component, all decoded in one pass (one
+// decode item per thread).  Component c's window holds TY rows, plus the
+// rows above and below when one of c's terms is a y difference (hy), and
+// the tile's columns, plus one either side when one of c's terms is an x
+// difference (hx): a divergence decodes each component with the one halo
+// its own axis needs.  The windows sit one after another in LDS, row by row
+// (row r of the window is tile row r - 1; windows without hy hold rows 1..TY).
+template <int S, int OP, int NC>
+struct VWin {
+  using Tm = VTerms<OP, NC>;
+  static constexpr int TY = vty<OP, NC>();
+  using R = VRow<S, TY>;
+  static constexpr int kNb0 = (kVTx + S - 2) / S + 1;  // blocks covering the tile's columns
+  static constexpr bool hy(int c) { return needs_axis<Tm>(c, 1); }
+  static constexpr bool hx(int c) { return needs_axis<Tm>(c, 2); }
+  static constexpr int rows(int c) { return TY + (hy(c) ? 2 : 0); }
+  static constexpr int nb(int c) { return hx(c) ? R::kNbr : kNb0; }
+  static constexpr int items(int c) { return rows(c) * nb(c); }
+  static constexpr int item_off(int c) {
+    int o = 0;
+    for (int k = 0; k < c; ++k) o += items(k);
+    return o;
+  }
+  static constexpr int row_off(int c) {
+    int o = 0;
+    for (int k = 0; k < c; ++k) o += rows(k);
+    return o;
+  }
+  // LDS word of window c's row r (r = 0 .. TY + 1 for hy, else 1 .. TY)
+  static constexpr int base(int c) { return (row_off(c) - (hy(c) ? 0 : 1)) * R::kPitch; }
+  static constexpr int kItems = item_off(NC);
+  static constexpr int kStageOff = (row_off(NC) * R::kPitch + 63) / 64 * 64;
+};
+
 // One workgroup: a tile of kVTx columns x TY rows over tz planes.  Per plane
-// p, for each component c: its decode items stage and decode their blocks
-// of plane p (rows y0-1 .. y0+TY) into the LDS plane; after a barrier every
-// column thread writes the one-sided ghosts of its column and takes the
-// in-plane numerators of c's terms (plane p) and the z numerators (plane
-// p-1, from q of planes p and p-2 kept in registers); a barrier frees the
-// plane for the next component.  Then plane p-1 is emitted.
+// p, every thread with a decode item stages and decodes its block of plane
+// p into its component's window; after a barrier every column thread writes
+// the one-sided ghosts of its column and takes the in-plane numerators of
+// every term (plane p) and the z numerators (plane p - 1, from q of planes
+// p and p - 2 kept in registers); a barrier frees the windows for the next
+// plane, whose payload words were loaded during the stencil.  Then plane
+// p - 1 is emitted.
 template <int S, int OP, int NC, typename T>
 __global__ void __launch_bounds__(kVThreads) k_vector_fused(VecJob j, int* status) {
   using Tm = VTerms<OP, NC>;
-  constexpr int TY = vty<OP, NC>();
-  using R = VRow<S, TY>;
-  constexpr int P = R::kPitch, NBR = R::kNbr, NT = Tm::n;
-  static_assert(R::kRows * NBR <= kVThreads, "one decode item per thread");
+  using W = VWin<S, OP, NC>;
+  constexpr int TY = W::TY;
+  using R = typename W::R;
+  constexpr int P = R::kPitch, NT = Tm::n;
+  static_assert(W::kItems <= kVThreads, "one decode item per thread");
   extern __shared__ uint32_t smem[];
   int* const pl = (int*)smem;
-  uint32_t* const stage = smem + R::kStageOff;
+  uint32_t* const stage = smem + W::kStageOff;
   const int t = threadIdx.x;
   const Dims3 d = j.d;
   const Box3 b = j.b;
@@ -179,14 +223,31 @@ __global__ void __launch_bounds__(kVThreads) k_vector_fused(VecJob j, int* statu
   const int64_t cA = max((int64_t)0, x0 - 1), cB = min(d.x, x0 + xs + 1);
   const int64_t rA = max((int64_t)0, y0 - 1), rB = min(d.y, y0 + ys + 1);
   const int64_t za = max((int64_t)0, z0 - 1), zb = min(d.z, z0 + zs + 1);
-  const int nrows = (int)(rB - rA);
   const bool aligned = (d.x & 31) == 0 && (x0 & 31) == 0;
 
-  // decode item of this thread
-  const int dr = t / NBR, dk = t % NBR;
-  const int64_t dy = rA + dr;
-  const bool decoder = dr < nrows;
-  int* const prow = pl + (int)(dy - (y0 - 1)) * P;
+  // this thread's decode item: component dc, window row dr, block dk (the
+  // same for every plane); none past the last item
+  int dc = -1, dr = 0, dk = 0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    if (t >= W::item_off(c) && t < W::item_off(c) + W::items(c)) {
+      dc = c;
+      dr = (t - W::item_off(c)) / W::nb(c);
+      dk = (t - W::item_off(c)) % W::nb(c);
+    }
+  bool dhy = false, dhx = false;
+  int dbase = 0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    if (c == dc) {
+      dhy = W::hy(c);
+      dhx = W::hx(c);
+      dbase = W::base(c);
+    }
+  const int64_t dy = (dhy ? rA : y0) + dr;
+  const bool decoder = dc >= 0 && dy < (dhy ? rB : y0 + ys);
+  const int64_t dxa = dhx ? cA : x0, dxb = dhx ? cB : x0 + xs;  // the window's columns
+  int* const drow = pl + dbase + (int)(dy - (y0 - 1)) * P;
   uint32_t* const col = stage + t;
 
   // stencil column of this thread
@@ -202,29 +263,28 @@ __global__ void __launch_bounds__(kVThreads) k_vector_fused(VecJob j, int* statu
 #pragma unroll
     for (int i = 0; i < TY; ++i) { ipc[k][i] = 0; ipp[k][i] = 0; zn[k][i] = 0; h1[k][i] = 0; h2[k][i] = 0; }
 
-  // Staging of one (component, plane): the decode item's metadata and the
-  // first PF payload words of its block, loaded into registers ahead of use.
+  // Staging of one plane's block: the item's metadata and the first PF
+  // payload words of its block, loaded into registers ahead of use.
   constexpr int PF = 16 * (S / 32);
   struct Pending {
-    int w, q0, words, e0, c;
+    int w, q0, words, e0;
     uint64_t off;
     bool valid;
     uint32_t pw[PF];
   };
-  auto issue = [&](int c, int64_t p, Pending& m) {
+  auto issue = [&](int64_t p, Pending& m) {
     m.valid = false;
-    m.c = c;
     m.w = 0;
     m.words = 0;
     if (!decoder || p >= zb) return;
-    const StreamView& v = j.v[c];
+    const StreamView& v = j.v[dc];
     const int64_t f = (p * d.y + dy) * d.x;
-    const int64_t bA = (f + cA) / S, bB = (f + cB - 1) / S, bk = bA + dk;
+    const int64_t bA = (f + dxa) / S, bB = (f + dxb - 1) / S, bk = bA + dk;
     if (bk > bB) return;
     m.valid = true;
     m.w = (int)v.width[bk];
     m.q0 = v.q0[bk];
-    m.off = v.chunk_off[bk / kChunkBlocks] + j.rel[c][bk];
+    m.off = v.chunk_off[bk / kChunkBlocks] + j.rel[dc][bk];
     m.e0 = (int)(bk * S - f);
     m.words = block_words<S>(m.w);
     if (m.w > kMaxWidth || m.words > kmax || m.off + (uint64_t)m.words > v.payload_words) {
@@ -234,32 +294,36 @@ __global__ void __launch_bounds__(kVThreads) k_vector_fused(VecJob j, int* statu
     }
     prefetch_words<PF>(v.payload, v.payload_words, m.off, m.words, m.pw);
   };
-  // staged words to this thread's column, then the block into the LDS plane
+  // staged words to this thread's column, then the block into its window
   auto commit = [&](const Pending& m) {
     if (!m.valid) return;
 #pragma unroll
     for (int k = 0; k < PF; ++k)
       if (k < m.words) col[k * kVThreads] = m.pw[k];
-    const uint32_t* src = j.v[m.c].payload + m.off;
+    const uint32_t* src = j.v[dc].payload + m.off;
     for (int k = PF; k < m.words; ++k) col[k * kVThreads] = src[k];
     const int cb = m.e0 - (int)(x0 - 1) + R::kOff;  // extended column of slot 0 (>= 0)
-    int* dst = prow + R::at(cb);
+    int* dst = drow + R::at(cb);
     // (a block of width 0 decodes as q0 everywhere: zero magnitudes)
     if (aligned) decode_block_q<S, true, kVThreads>(col, m.w, m.q0, dst, 32);
     else decode_block_q<S, false, kVThreads>(col, m.w, m.q0, dst, 32 - (cb & 31));
   };
-  // the one-sided ghosts of this thread's column (after the decode barrier)
-  auto ghosts = [&]() {
+  // the one-sided ghosts of this thread's column in window c (after the
+  // decode barrier): rows for a window with y terms, columns for x terms
+  auto ghosts = [&](int c) {
     if (!active) return;
-    if (ylo) pl[ec] = y2 ? 2 * pl[P + ec] - pl[2 * P + ec] : pl[P + ec];
-    if (yhi) {
-      int* r = pl + ys * P + ec;
-      r[P] = y2 ? 2 * r[0] - r[-P] : r[0];
+    int* const w0 = pl + W::base(c);
+    if (W::hy(c)) {
+      if (ylo) w0[ec] = y2 ? 2 * w0[P + ec] - w0[2 * P + ec] : w0[P + ec];
+      if (yhi) {
+        int* r = w0 + ys * P + ec;
+        r[P] = y2 ? 2 * r[0] - r[-P] : r[0];
+      }
     }
-    if (xlo || xhi) {
+    if (W::hx(c) && (xlo || xhi)) {
 #pragma unroll
       for (int i = 0; i < TY; ++i) {
-        int* r = pl + (i + 1) * P;
+        int* r = w0 + (i + 1) * P;
         if (xlo) r[em] = x2 ? 2 * r[ec] - r[ep] : r[ec];
         if (xhi) r[ep] = x2 ? 2 * r[ec] - r[em] : r[ec];
       }
@@ -291,46 +355,43 @@ __global__ void __launch_bounds__(kVThreads) k_vector_fused(VecJob j, int* statu
     }
   };
 
-  // (component, plane) pairs in order (p, 0), (p, 1), ..., (p + 1, 0): the
-  // next pair's metadata and words load while this pair's stencil runs
+  // planes in order; the next plane's metadata and words load while this
+  // plane's stencil runs
   Pending cur, nxt;
-  issue(0, za, cur);
+  issue(za, cur);
   for (int64_t p = za; p < zb; ++p) {
     const int64_t o = p - 1;
+    commit(cur);
+    lds_barrier();
+    issue(p + 1, nxt);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      commit(cur);
-      lds_barrier();
-      if (c + 1 < NC) issue(c + 1, p, nxt);
-      else issue(0, p + 1, nxt);
-      ghosts();
-      if (active) {
+    for (int c = 0; c < NC; ++c) ghosts(c);
+    if (active) {
 #pragma unroll
-        for (int k = 0; k < NT; ++k) {
-          const VTerm tm = Tm::t[k];
-          if (tm.c != c) continue;
+      for (int k = 0; k < NT; ++k) {
+        const VTerm tm = Tm::t[k];
+        const int* const w0 = pl + W::base(tm.c);
 #pragma unroll
-          for (int i = 0; i < TY; ++i) {
-            const int r = i + 1;
-            const int qc = pl[r * P + ec];
-            if (tm.a == 0) {
-              // z numerator of plane o = p - 1; the field's first plane uses
-              // the ghost 2 q_0 - q_1 below it
-              if (o == 0) h2[k][i] = d.z >= 2 ? 2 * h1[k][i] - qc : h1[k][i];
-              zn[k][i] = qc - h2[k][i];
-              h2[k][i] = h1[k][i];
-              h1[k][i] = qc;
-            } else if (tm.a == 1) {
-              ipc[k][i] = pl[(r + 1) * P + ec] - pl[(r - 1) * P + ec];
-            } else {
-              ipc[k][i] = pl[r * P + ep] - pl[r * P + em];
-            }
+        for (int i = 0; i < TY; ++i) {
+          const int r = i + 1;
+          const int qc = w0[r * P + ec];
+          if (tm.a == 0) {
+            // z numerator of plane o = p - 1; the field's first plane uses
+            // the ghost 2 q_0 - q_1 below it
+            if (o == 0) h2[k][i] = d.z >= 2 ? 2 * h1[k][i] - qc : h1[k][i];
+            zn[k][i] = qc - h2[k][i];
+            h2[k][i] = h1[k][i];
+            h1[k][i] = qc;
+          } else if (tm.a == 1) {
+            ipc[k][i] = w0[(r + 1) * P + ec] - w0[(r - 1) * P + ec];
+          } else {
+            ipc[k][i] = w0[r * P + ep] - w0[r * P + em];
           }
         }
       }
-      lds_barrier();
-      cur = nxt;
     }
+    lds_barrier();
+    cur = nxt;
     emit(o, false);
 #pragma unroll
     for (int k = 0; k < NT; ++k)
@@ -354,15 +415,15 @@ hipError_t vec_buf(const VecJob& j, int stage, hipStream_t s) {
 template <int S, int OP, int NC, typename T>
 hipError_t vec_fused(const VecJob& j0, uint8_t* ws, hipStream_t s) {
   VecJob j = j0;
-  constexpr int TY = vty<OP, NC>();
-  using R = VRow<S, TY>;
+  using W = VWin<S, OP, NC>;
+  constexpr int TY = W::TY;
   const Box3& b = j.b;
   const int64_t ntx = (b.x1 - b.x0 + kVTx - 1) / kVTx, nty = (b.y1 - b.y0 + TY - 1) / TY;
   const int64_t bz = b.z1 - b.z0;
   int64_t tz = bz;
   while (tz > 8 && ntx * nty * ((bz + tz - 1) / tz) < 2048) tz = (tz + 1) / 2;
   j.tz = (int)tz;
-  const size_t lds = (size_t)R::kStageOff * 4 + (size_t)(j.kmax + 1) * kVThreads * 4;
+  const size_t lds = (size_t)W::kStageOff * 4 + (size_t)(j.kmax + 1) * kVThreads * 4;
   const int64_t grid = ntx * nty * ((bz + tz - 1) / tz);
   hipLaunchKernelGGL((k_vector_fused<S, OP, NC, T>), dim3((unsigned)grid), dim3(kVThreads), lds, s, j, (int*)ws);
   return hipGetLastError();
