@@ -412,6 +412,19 @@ hipError_t vec_buf(const VecJob& j, int stage, hipStream_t s) {
   return hipGetLastError();
 }
 
+// compute units of the current device (cached per device)
+int vec_device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    cached[dev] = cus;
+  }
+  return cached[dev];
+}
+
 template <int S, int OP, int NC, typename T>
 hipError_t vec_fused(const VecJob& j0, uint8_t* ws, hipStream_t s) {
   VecJob j = j0;
@@ -420,10 +433,15 @@ hipError_t vec_fused(const VecJob& j0, uint8_t* ws, hipStream_t s) {
   const Box3& b = j.b;
   const int64_t ntx = (b.x1 - b.x0 + kVTx - 1) / kVTx, nty = (b.y1 - b.y0 + TY - 1) / TY;
   const int64_t bz = b.z1 - b.z0;
-  int64_t tz = bz;
-  while (tz > 8 && ntx * nty * ((bz + tz - 1) / tz) < 2048) tz = (tz + 1) / 2;
-  j.tz = (int)tz;
   const size_t lds = (size_t)W::kStageOff * 4 + (size_t)(j.kmax + 1) * kVThreads * 4;
+  // z chunks: about as many workgroups as the chip holds at once (by LDS,
+  // at most four of these register-heavy workgroups per compute unit), each
+  // marching one chunk; chunks of at least 8 planes (two halo planes each)
+  const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(4, (int64_t)(160 * 1024) / (int64_t)lds));
+  const int64_t resident = per_cu * vec_device_cus();
+  const int64_t nzc = std::max<int64_t>(1, std::min<int64_t>((resident + ntx * nty - 1) / (ntx * nty), (bz + 7) / 8));
+  const int64_t tz = (bz + nzc - 1) / nzc;
+  j.tz = (int)tz;
   const int64_t grid = ntx * nty * ((bz + tz - 1) / tz);
   hipLaunchKernelGGL((k_vector_fused<S, OP, NC, T>), dim3((unsigned)grid), dim3(kVThreads), lds, s, j, (int*)ws);
   return hipGetLastError();
