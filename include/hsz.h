@@ -189,8 +189,9 @@ int hsz_compress(const void *d_x, int dtype, int ndim, const int64_t *h_dims, do
  * and divergence and curl of HSZp-nd vector fields (below); stages 3 and 4
  * take every operation of a delta stream.  The fused routes rebuild what
  * they need in the workspace (hsz_op_workspace: 4 bytes per point, 8 for
- * binary64 fields, beyond the operation's own; the Laplacian on stage 2
- * keeps one more int32 field per axis).  Batches and block indexes return
+ * binary64 fields, beyond the operation's own, plus 16 planes of int32 for
+ * the two-pass D_q of 3D fields with rows of at most 512 columns; the
+ * Laplacian on stage 2 keeps one more int32 field per axis).  Batches and block indexes return
  * HSZ_ERR_UNSUPPORTED for these streams. */
 #define HSZ_FLAG_LORENZO 2u
 /* HSZ_FLAG_INTER_BLOCK selects HSZp's decorrelation (Sec. IV, prediction
@@ -240,8 +241,10 @@ int hsz_read_header(const void *h_bytes, uint64_t len, uint64_t len_stream, hsz_
 int hsz_stage_bytes(const hsz_header *h, int stage, uint64_t *h_bytes);
 
 /* Workspace hsz_decompress_to_stage needs for this stream and stage: 256
- * bytes (the status word), plus tile sums for stages 3 and 4 of
- * HSZ_FLAG_INTER_BLOCK streams. */
+ * bytes (the status word), plus for stages 3 and 4 the tile sums of
+ * HSZ_FLAG_INTER_BLOCK streams, or for HSZ_FLAG_LORENZO streams of 3D
+ * fields whose rows hold at most 512 columns (a multiple of 4) the totals
+ * of the z segments of the two-pass decode (16 planes of int32). */
 int hsz_decompress_workspace(const hsz_header *h, int stage, uint64_t *h_bytes);
 
 /* Decode the stream d_c (device) to 'stage' into d_out (capacity 'cap').
