@@ -20,6 +20,7 @@
 
 #include "abi_util.hpp"
 #include "ctx.hpp"
+#include "hsz_stats.hpp"
 
 namespace {
 
@@ -286,12 +287,47 @@ int device_cus() {
   return cus;
 }
 
+// The one gradient variant of a batch that can finish itself: every job is
+// a 512-column sixteen-bit tile with statistics summed inside (and every
+// statistic is), no block index is built per pass.  -1 if none.
+int self_finishing(const Built& B) {
+  if (B.n_index > 0 || B.stats_units[0] > 0 || B.stats_units[1] > 0 || B.n_stats[0] + B.n_stats[1] == 0) return -1;
+  int only = -1;
+  for (int g = 0; g < kVariants; ++g) {
+    if (B.n_grad[g] == 0) continue;
+    if (only >= 0) return -1;
+    only = g;
+  }
+  return only == variant_q4(32, 512, 1) ? only : -1;
+}
+
 // Enqueue the kernels of a built batch ('kmax' values fix the LDS sizes).
-int enqueue(const Built& B, uint8_t* d_ws, const hsz_tuning& tune, hipStream_t s) {
+// 'primed': the workspace's accumulators, live word and done count are zero
+// (a plan, after its first reset): a batch that can finish itself is then
+// one kernel.
+int enqueue(const Built& B, uint8_t* d_ws, const hsz_tuning& tune, hipStream_t s, bool primed = false) {
   const Layout& L = B.L;
   const int64_t* counts = (const int64_t*)(d_ws + L.counts);
   int* status = (int*)d_ws;
   const int cus = device_cus();
+  const int self = primed ? self_finishing(B) : -1;
+  if (self >= 0) {
+    hsz::BatchTail T;
+    for (int c = 0; c < 2; ++c) {
+      T.jobs[c] = (const hsz::StatsJob*)(d_ws + L.stats_jobs[c]);
+      T.counts[c] = counts + 2 * cslot_stats(c);
+      T.acc[c] = (hsz::BatchAcc*)(d_ws + L.acc[c]);
+      T.n[c] = B.n_stats[c];
+    }
+    T.status_out = status;
+    T.live = status + 1;
+    T.done = (unsigned*)(status + 2);
+    const int per_cu = std::min(2, tune.grad_groups_per_cu > 0 ? tune.grad_groups_per_cu : 2);
+    hipError_t e = hsz::launch_batch_gradmag_q8_tail((const hsz::GradJob*)(d_ws + L.grad_jobs[self]),
+                                                     (const int64_t*)(d_ws + L.grad_start[self]),
+                                                     counts + 2 * cslot_grad(self), std::max(1, cus * per_cu), T, s);
+    return e == hipSuccess ? HSZ_OK : hip_fail(e);
+  }
   const int stats_grid = std::max(1, cus * (tune.stats_waves_per_cu > 0 ? tune.stats_waves_per_cu : 8) / 4);
   const int grad_grid = std::max(1, cus * (tune.grad_groups_per_cu > 0 ? tune.grad_groups_per_cu : 4));
   hipError_t e;
@@ -449,11 +485,21 @@ int hsz_plan_create(const hsz_work* items, int n, const hsz_tuning* tune, void* 
     hsz_plan_destroy(p);
     return hip_fail(e);
   }
+  // a batch that finishes itself leaves its accumulators, live word and
+  // done count zero after every pass: zero them once here, before any pass
+  // (and wait, so a pass on another stream finds them zero)
+  if (self_finishing(p->built) >= 0 &&
+      ((e = hsz::launch_batch_reset((hsz::BatchAcc*)(p->d_ws + p->built.L.acc[0]),
+                                    p->built.n_stats[0] + p->built.n_stats[1], (int*)p->d_ws, s)) != hipSuccess ||
+       (e = hipStreamSynchronize(s)) != hipSuccess)) {
+    hsz_plan_destroy(p);
+    return hip_fail(e);
+  }
   if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
     hsz_plan_destroy(p);
     return hip_fail(e);
   }
-  int erc = enqueue(p->built, p->d_ws, p->tune, s);
+  int erc = enqueue(p->built, p->d_ws, p->tune, s, true);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(s, &g);
   if (erc != HSZ_OK || e2 != hipSuccess) {
@@ -505,7 +551,7 @@ int hsz_plan_launch(hsz_plan* p, void* stream) {
   } else {
     // the table is on the device since create/update: the pass is a handful
     // of kernel launches, which reach the GPU sooner than a graph launch
-    const int erc = enqueue(p->built, p->d_ws, p->tune, s);
+    const int erc = enqueue(p->built, p->d_ws, p->tune, s, true);
     if (erc != HSZ_OK) return erc;
   }
   if ((e = hipEventRecord(p->done, s)) != hipSuccess) return hip_fail(e);

@@ -32,6 +32,7 @@
 //    |q| < 8192), then widened.
 #include "hsz_device.hpp"
 #include "hsz_launch.hpp"
+#include "hsz_stats.hpp"
 
 namespace hsz {
 
@@ -910,6 +911,31 @@ __global__ void __launch_bounds__(kQ8Threads, 4) k_batch_gradmag_q8(const GradJo
   }
 }
 
+// The batch's statistics summed in these tiles and finished by the last
+// workgroup (errors recorded in the tail's live word)
+__global__ void __launch_bounds__(kQ8Threads, 4) k_batch_gradmag_q8_tail(const GradJob* __restrict__ jobs,
+                                                                        const int64_t* __restrict__ tile_start,
+                                                                        const int64_t* __restrict__ counts,
+                                                                        BatchTail tail) {
+  extern __shared__ uint32_t smem[];
+  const int n = (int)counts[0];
+  const int64_t total = counts[1];
+  for (int64_t base = 0; base < total; base += gridDim.x) {
+    const int64_t tile = xcd_tile(base, total);
+    if (tile >= total) break;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (tile_start[mid] <= tile) lo = mid;
+      else hi = mid - 1;
+    }
+    const GradJob job = load_job(jobs, lo);
+    gradmag_tile_q8<1>(job, tile - tile_start[lo], smem, tail.live);
+  }
+  // the flag in the workgroup-sum words past the tile (free after the tiles)
+  batch_tail(tail, (int*)(smem + kQ8LdsWords));
+}
+
 template <int S, int TXL>
 size_t q4_lds() {
   return (size_t)Q4<S, TXL>::kLdsWords * sizeof(uint32_t) + (kQ4Threads / kWave) * sizeof(BatchAcc);
@@ -984,6 +1010,13 @@ hipError_t launch_batch_gradmag_q4(int S, int txl, int acc, const GradJob* jobs,
       hipLaunchKernelGGL((k_batch_gradmag_q4<32, 256, 0>), dim3(grid), dim3(kQ4Threads), (q4_lds<32, 256>()), s, jobs,
                          tile_start, counts, status);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_gradmag_q8_tail(const GradJob* jobs, const int64_t* tile_start, const int64_t* counts,
+                                        int grid, const BatchTail& tail, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_gradmag_q8_tail, dim3(grid), dim3(kQ8Threads), q8_lds(), s, jobs, tile_start, counts,
+                     tail);
   return hipGetLastError();
 }
 

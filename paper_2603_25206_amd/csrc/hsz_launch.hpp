@@ -109,7 +109,9 @@ struct BatchAcc {
   uint64_t s2lo, s2hi;
 };
 constexpr int kAccStripes = 64;
-// Zero 'slots' accumulator slots at acc and the status word.
+// Zero 'slots' accumulator slots at acc, the status word and the two words
+// after it (the live status and the done count of a batch that finishes
+// itself).
 hipError_t launch_batch_reset(BatchAcc* acc, int slots, int* status, hipStream_t s);
 hipError_t launch_batch_stats(int S, const StatsJob* jobs, const int64_t* unit_start, const int64_t* counts,
                               int kmax, BatchAcc* acc, int* status, int grid, hipStream_t s);
@@ -170,6 +172,14 @@ int q4_kmax(int S);
 hipError_t launch_gradmag_q4(const GradJob& job, int* status, hipStream_t s);
 hipError_t launch_batch_gradmag_q4(int S, int txl, int acc, const GradJob* jobs, const int64_t* tile_start,
                                    const int64_t* counts, int grid, int* status, hipStream_t s);
+// The 512-column tile with every statistic of the batch summed in its tiles,
+// finishing the batch itself (BatchTail, hsz_stats.hpp): its last workgroup
+// writes the statistics records, zeroes the accumulators and publishes the
+// status word, so no reset or finalize kernel runs around it once the
+// accumulators, the live word and the count are zero.
+struct BatchTail;
+hipError_t launch_batch_gradmag_q8_tail(const GradJob* jobs, const int64_t* tile_start, const int64_t* counts,
+                                        int grid, const BatchTail& tail, hipStream_t s);
 size_t batch_gradmag_q4_lds(int S, int txl);
 
 // Derivative (op = 3, axis in the 3D view) or gradient magnitude (op = 4).

@@ -14,6 +14,7 @@
 #include "hsz_device.hpp"
 #include "hsz_launch.hpp"
 #include "hsz_nd.hpp"
+#include "hsz_stats.hpp"
 
 namespace hsz {
 
@@ -449,40 +450,7 @@ __global__ void __launch_bounds__(kThreads) k_stats_fused(StreamView v, Segs<S> 
   else store_int_partial(acc, parts);
 }
 
-// ---- finalize: partials -> hsz_stats ------------------------------------------------
-struct StatsOut {
-  int64_t n, s1;
-  uint64_t s2lo;
-  int64_t s2hi;
-  double mean, var;
-};
-
-__device__ double u128_to_f64(unsigned __int128 v) {
-  return (double)(uint64_t)(v >> 64) * 18446744073709551616.0 + (double)(uint64_t)v;
-}
-
-// mean = s1 Delta / n; var = (n s2 - s1^2) / (n (n - 1)) Delta^2 with the
-// numerator exact in 128 bits (n < 2^34, |q| < 2^29), one rounding each
-__device__ StatsOut stats_from_sums(int64_t n, int64_t s1, uint64_t s2lo, uint64_t s2hi, int op, double quantum) {
-  StatsOut r{};
-  r.n = n;
-  r.s1 = s1;
-  r.mean = (double)s1 * quantum / (double)n;
-  if (op == 2) {
-    const unsigned __int128 S2 = ((unsigned __int128)s2hi << 64) | s2lo;
-    r.s2lo = s2lo;
-    r.s2hi = (int64_t)s2hi;
-    const unsigned __int128 a = (unsigned __int128)(uint64_t)n * S2;
-    const uint64_t m = (uint64_t)(s1 < 0 ? -s1 : s1);
-    const unsigned __int128 b = (unsigned __int128)m * m;
-    const double num = u128_to_f64(a - b);
-    r.var = n > 1 ? num / ((double)n * (double)(n - 1)) * (quantum * quantum) : __builtin_nan("");
-  } else {
-    r.var = __builtin_nan("");
-  }
-  return r;
-}
-
+// ---- finalize: partials -> hsz_stats (StatsOut, stats_from_sums) ---------------------
 __global__ void k_copy_status_word(const int* status, int* out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *out = *status;
 }
@@ -687,10 +655,16 @@ __global__ void __launch_bounds__(kThreads) k_batch_stats(const StatsJob* __rest
   flush(J.acc);
 }
 
+// status[0] is the status word; status[1] and status[2] are the live word
+// and the done count of a batch that finishes itself (BatchTail)
 __global__ void k_batch_reset(BatchAcc* acc, int slots, int* status) {
   const int n = slots * kAccStripes;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) acc[i] = BatchAcc{0, 0, 0, 0};
-  if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    status[0] = 0;
+    status[1] = 0;
+    status[2] = 0;
+  }
 }
 
 struct FinalizeArgs {
@@ -700,32 +674,14 @@ struct FinalizeArgs {
   int n0;
 };
 
-// One wave per job of either class: lane k loads stripe k of the job's slot,
-// the wave adds them exactly (sum q^2 = hi * 2^32 + lo in 128 bits), lane 0
-// finishes the job.
+// One wave per job of either class (finish_stats_job).
 __global__ void __launch_bounds__(256) k_batch_finalize(FinalizeArgs fa) {
   const int w = blockIdx.x * (blockDim.x / kWave) + wave_in_group();
   const int c = w < fa.n0 ? 0 : 1;
   const int i = c ? w - fa.n0 : w;
   if (i >= (int)fa.counts[c][0]) return;
   const StatsJob J = load_job(fa.jobs[c], i);
-  const BatchAcc a = fa.acc[c][(int64_t)J.acc * kAccStripes + lane_id()];
-  const int64_t s1 = wave_sum64(a.s1), cnt = wave_sum64(a.cnt);
-  U128 lo = {a.s2lo, 0}, hi = {a.s2hi, 0};
-  for (int m = 32; m >= 1; m >>= 1) {
-    U128 o;
-    o.lo = __shfl_xor(lo.lo, m);
-    o.hi = __shfl_xor(lo.hi, m);
-    add_u128(lo, o);
-    o.lo = __shfl_xor(hi.lo, m);
-    o.hi = __shfl_xor(hi.hi, m);
-    add_u128(hi, o);
-  }
-  if (lane_id() == 0) {
-    const unsigned __int128 s2 = ((((unsigned __int128)hi.hi << 64) | hi.lo) << 32) +
-                                 (((unsigned __int128)lo.hi << 64) | lo.lo);
-    *(StatsOut*)J.out = stats_from_sums(cnt, s1, (uint64_t)s2, (uint64_t)(s2 >> 64), J.op, J.v.quantum);
-  }
+  finish_stats_job<false>(J, fa.acc[c] + (int64_t)J.acc * kAccStripes);
 }
 
 int grid_for(int64_t work_items, int per_group) {

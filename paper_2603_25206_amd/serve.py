@@ -208,7 +208,10 @@ class Server:
         return finished
 
     def release(self, q: Query):
-        """Return a completed query's result memory to the budget."""
+        """Return a completed query's result memory to the budget.  The
+        consumer may have work reading the result still queued on its current
+        stream (a copy, say): the executor reuses the memory only after that
+        stream's work up to this call has run."""
         if q.held:
             self.ex.free(q)
             self.mem_used -= q.mem
@@ -381,6 +384,11 @@ class GpuExecutor(Executor):
         self.dstat = [torch.zeros(self.stat_bytes, dtype=torch.uint8, device=dev) for _ in range(n_slots)]
         self.hstat = [torch.zeros(self.stat_bytes, dtype=torch.uint8, pin_memory=True) for _ in range(n_slots)]
         self.events = [torch.cuda.Event() for _ in range(n_slots)]
+        # released result ranges wait for the consumer's stream: an event
+        # recorded at release (from a pool made here), the range placed again
+        # once it has passed
+        self.release_pool = [torch.cuda.Event() for _ in range(2 * self.max_batch * n_slots)]
+        self.deferred = []  # (event, offset, length)
         torch.cuda.synchronize()
 
     def result_bytes(self, q: Query) -> int:
@@ -389,10 +397,26 @@ class GpuExecutor(Executor):
         esz = 4 if self.snaps[q.snap].header.dtype == 1 else 8
         return (esz * q.volume() + 255) // 256 * 256
 
+    def _settle(self, wait: bool = False):
+        """Place again the released ranges whose consumer work has run (all of
+        them, waiting, with wait)."""
+        keep = []
+        for ev, off, n in self.deferred:
+            if wait:
+                ev.synchronize()
+            if wait or ev.query():
+                self.placer.free(off, n)
+                self.release_pool.append(ev)
+            else:
+                keep.append((ev, off, n))
+        self.deferred = keep
+
     def alloc(self, q: Query) -> bool:
         n = self.result_bytes(q)
         if n == 0:
             return True
+        if self.deferred:
+            self._settle()
         got = self.placer.alloc(n)
         if got is None:
             return False
@@ -401,7 +425,14 @@ class GpuExecutor(Executor):
 
     def free(self, q: Query):
         if q.slot_mem is not None:
-            self.placer.free(*q.slot_mem)
+            cur = self.torch.cuda.current_stream()
+            if self.release_pool:
+                ev = self.release_pool.pop()
+                ev.record(cur)
+                self.deferred.append((ev, *q.slot_mem))
+            else:  # every pooled event in use: wait for the consumer instead
+                cur.synchronize()
+                self.placer.free(*q.slot_mem)
             q.slot_mem = None
 
     def launch(self, slot: int, queries: list):
@@ -449,5 +480,6 @@ class GpuExecutor(Executor):
         return out
 
     def close(self):
+        self._settle(wait=True)
         for c in self.ctx:
             c.close()

@@ -153,3 +153,49 @@ def test_tile_shape_axis(fld, tile_x):
     assert (var["n"], var["s1"], var["s2"]) == (rvar["n"], rvar["s1"], rvar["s2"])
     assert torch.equal(mag, rmag)
     _check(mag, oracle.gradmag(fld["xh"]), f"tile {tile_x}")
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_plan_passes_finish_themselves(fld, graph):
+    """A plan whose statistics are all summed in 512-column tiles runs each
+    pass as one kernel that finishes the batch itself: every pass (eager
+    launches or graph replays, with other work and synchronisations between
+    them) gives the same exact sums and magnitude; a pass over a stream with
+    a corrupt width reports the error, and the next pass over the good
+    stream reports none (the error word is re-armed)."""
+    c = fld["c"]
+    c.build_index()
+    jobs = [hsz.Job(c, "mean", hsz.DELTA), hsz.Job(c, "var", hsz.QUANT), hsz.Job(c, "gradmag", hsz.QUANT)]
+    plan = hsz.Plan(jobs, tune={"graph_replay": graph})
+    n, s1, s2 = oracle.int_sums(fld["q"])
+    want = oracle.gradmag(fld["xh"])
+    first = None
+    for r in range(4):
+        plan.launch()
+        mean, var, mag = plan.results()
+        assert (mean["n"], mean["s1"]) == (n, s1), r
+        assert (var["n"], var["s1"], var["s2"]) == (n, s1, s2), r
+        if first is None:
+            first = mag.clone()
+            _check(mag, want, "plan")
+        assert torch.equal(mag, first), r
+        torch.zeros(1 << 20, device=DEV).add_(1.0)  # other work on the default stream
+        torch.cuda.synchronize()
+    if fld["shape"][-1] > 256 and fld["shape"][-1] % 8 == 0:
+        h = oracle.read_header(fld["ref"])
+        bad = fld["ref"].copy()
+        bad[h.off_width + 1] = 29  # wider than any block of these tiles
+        cb = hsz.from_bytes(bad, DEV)
+        cb.build_index()
+        plan.update([hsz.Job(cb, "mean", hsz.DELTA), hsz.Job(cb, "var", hsz.QUANT),
+                     hsz.Job(cb, "gradmag", hsz.QUANT)])
+        plan.launch()
+        with pytest.raises(hsz.HszError) as e:
+            plan.results()
+        assert e.value.code == hsz.ERR_BAD_STREAM
+        plan.update(jobs)
+        plan.launch()
+        mean, var, mag = plan.results()
+        assert (var["n"], var["s1"], var["s2"]) == (n, s1, s2)
+        assert torch.equal(mag, first)
+    plan.close()
