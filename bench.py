@@ -150,7 +150,8 @@ def grad_kernel_label(h, block, tune):
     tile_x = int((tune or {}).get("grad_tile_x", 0))
     acc = 1 if h.max_abs_q < 65536 else 2
     if block == 32 and h.max_abs_q < 8192 and tile_x >= 0:
-        return "k_batch_gradmag_q8<1>" if tile_x != 256 else "k_batch_gradmag_q4<32,256,1>"
+        # the 512-column tile with the statistics inside finishes the plan's pass itself
+        return "k_batch_gradmag_q8_tail" if tile_x != 256 else "k_batch_gradmag_q4<32,256,1>"
     return f"k_batch_grad<{block},3,4,float,{acc}>"
 
 
