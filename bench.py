@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workloads")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--no-vector", action="store_true", help="skip the vector-field (divergence, curl) workload")
+    ap.add_argument("--no-small", action="store_true", help="skip the 64^3 latency workload")
     ap.add_argument("--no-hszx", action="store_true", help="skip the block-mean (HSZx) workload")
     ap.add_argument("--no-lorenzo", action="store_true", help="skip the HSZp-nd (Lorenzo) workload")
     ap.add_argument("--no-ooc", action="store_true", help="skip the out-of-core (host-resident slabs) workload")
@@ -447,6 +448,8 @@ def main():
         out["large_field_configs"] = rows
     del xg
     torch.cuda.empty_cache()
+    if not a.no_small:
+        out["small_field"] = bench_small(a, log)
     if not a.no_vector:
         out["vector_field"] = bench_vector(a, log)
         torch.cuda.empty_cache()
@@ -556,6 +559,62 @@ def bench_vector(a, log):
                    "speedup_vs_full_decompress": round(ms_b / ms_f, 3)}
     log(f"[bench] vector field: {res}")
     del comps, sets, outs, qbufs, fbufs
+    return res
+
+
+def bench_small(a, log):
+    """The 64^3 binary32 field (8 bumps, sigma 4-16 cells, N(0, 1e-3) noise;
+    rel eb 1e-3, S=32), where every launch is latency: compression, the step
+    (one plan launch: mean via D_p, variance via D_q, gradient magnitude via
+    D_q), the three operations launched one by one and full decompression +
+    the operations, each the median of many HIP-event-timed calls; the
+    step's results are checked equal to the operations run one by one (the
+    oracle comparison of this field is a parity test)."""
+    import torch
+
+    from paper_2603_25206_amd import hsz, synth
+
+    spec = synth.small_field_spec(seed=0)
+    x = synth.make_field(spec)
+    xt = torch.from_numpy(x).cuda()
+    eb = 1e-3
+    c = hsz.compress(xt, eb, rel=True, block=32)
+    c.build_index()
+    torch.cuda.synchronize()
+    cur = torch.cuda.current_stream()
+    jobs = [hsz.Job(c, "mean", hsz.DELTA), hsz.Job(c, "var", hsz.QUANT), hsz.Job(c, "gradmag", hsz.QUANT)]
+    res = {"shape": list(spec.shape), "rel_eb": eb, "block": 32, "ratio": round(c.ratio, 3)}
+    res["compress_us"] = round(1e3 * _events_ms(lambda: hsz.compress(xt, eb, rel=True, block=32), 50, cur), 1)
+    ps = torch.cuda.Stream()  # a plan is captured, so it runs on a stream of its own
+    for graph in (False, True):
+        plan = hsz.Plan(jobs, tune={"graph_replay": graph}, stream=ps)
+        res["step_graph_us" if graph else "step_us"] = round(1e3 * _events_ms(plan.launch, 100, ps), 1)
+        plan.launch()
+        mean, var, mag = plan.results()
+        plan.close()
+    s48 = torch.empty(64, dtype=torch.uint8, device="cuda")
+    gout = torch.empty(4 * x.size, dtype=torch.uint8, device="cuda")
+    ws = hsz.workspace(hsz.op_workspace_bytes(c.header, hsz.GRADMAG), "cuda", key="bench-small")
+    def ops():
+        hsz.op_fused(c, hsz.DELTA, hsz.MEAN, out=s48, ws=ws, check=False, raw=True)
+        hsz.op_fused(c, hsz.QUANT, hsz.VAR, out=s48, ws=ws, check=False, raw=True)
+        hsz.op_fused(c, hsz.QUANT, hsz.GRADMAG, out=gout, ws=ws, check=False, raw=True)
+    res["separate_ops_us"] = round(1e3 * _events_ms(ops, 100, cur), 1)
+    fbuf = torch.empty(4 * x.size + 64, dtype=torch.uint8, device="cuda")
+    def full():
+        f = hsz.decompress_to_stage(c, hsz.FLOAT, out=fbuf)
+        hsz.op_on_stage(f, c.header, hsz.FLOAT, hsz.MEAN)
+        hsz.op_on_stage(f, c.header, hsz.FLOAT, hsz.VAR)
+        hsz.op_on_stage(f, c.header, hsz.FLOAT, hsz.GRADMAG)
+    res["full_decompress_then_ops_us"] = round(1e3 * _events_ms(full, 50, cur), 1)
+    m1 = hsz.op_fused(c, hsz.DELTA, hsz.MEAN)
+    v1 = hsz.op_fused(c, hsz.QUANT, hsz.VAR)
+    g1 = hsz.op_fused(c, hsz.QUANT, hsz.GRADMAG)
+    ok = ((mean["n"], mean["s1"]) == (m1["n"], m1["s1"]) and (var["s1"], var["s2"]) == (v1["s1"], v1["s2"])
+          and torch.equal(mag, g1))
+    if not ok:
+        raise RuntimeError("64^3 step differs from the operations run one by one")
+    log(f"[bench] 64^3 field: {res}")
     return res
 
 

@@ -328,10 +328,13 @@ int hsz_op_fused_noalloc(const void *d_c, const hsz_header *h, int via, int op, 
  * h_slabs[k] (HOST memory; pinned memory lets the copies overlap) holds the
  * stream of slab k, hdrs[k] its header: consecutive ranges of the field's
  * slowest axis in order, compressed by hsz_compress_range with the whole
- * field's extremes (same dtype, rank, block, quantum and other dims; delta
- * or block-mean streams).  The slabs pass through the device a few at a
- * time: at most three compressed slabs, and for stencils two windows of
- * D_q and two result slabs.
+ * field's extremes (same dtype, rank, block, decorrelation, quantum and
+ * other dims; delta, block-mean, HSZp-nd or HSZp streams: the last two are
+ * reduced or decoded slab by slab through hsz_op_fused /
+ * hsz_decompress_to_stage, whose workspace hsz_ooc_workspace includes).
+ * The slabs pass through the device a few at a time: at most three
+ * compressed slabs, and for stencils two windows of D_q and two result
+ * slabs.
  *   op = HSZ_MEAN / HSZ_VAR, via HSZ_DELTA or HSZ_QUANT: h_result = one
  *        hsz_stats of the whole field, from exact per-slab integer sums.
  *   op = HSZ_DERIV (axis) / HSZ_GRADMAG / HSZ_LAPLACIAN, via HSZ_QUANT:

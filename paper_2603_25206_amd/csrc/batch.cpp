@@ -130,6 +130,21 @@ int tz_for(const hsz::Box3& b, int want) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(tz, bz));
 }
 
+// Planes per tile of a gradient job in variant g: the tuning's value, else
+// 32, halved (down to 4) while the job has fewer than 256 tiles, so a
+// small field's planes are not marched by a few workgroups one after
+// another (each tile walks its planes in order).
+int tz_pick(const hsz::Box3& b, int want, int g) {
+  if (want > 0) return tz_for(b, want);
+  auto tiles = [&](int tz) -> int64_t {
+    if (!is_q4(g)) return hsz::grad_tiles(b, tz);
+    return hsz::q4_tiles(b, tz, ((g - kVariantsGeneral) & 2) ? 512 : 256);
+  };
+  int tz = tz_for(b, 32);
+  while (tz > 4 && tiles(tz) < 256) tz = (tz + 1) / 2;
+  return tz;
+}
+
 // Lay out and fill the table for 'items' in the workspace at d_ws.
 int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws, Built* B) {
   Layout& L = B->L;
@@ -151,7 +166,7 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
     }
   }
   std::vector<int> order_stats[2], order_grad[kVariants];
-  std::vector<int> grads;
+  std::vector<int> grads, var_of(items.size(), -1);
   for (int i = 0; i < (int)items.size(); ++i) {
     const Item& it = items[i];
     if (it.kind == 0) order_stats[it.S == 64].push_back(i);
@@ -159,8 +174,8 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
       const bool q4 =
           tune.grad_tile_x >= 0 && acc_mode[i] != 2 && hsz::q4_eligible(it.v, it.via, it.op, it.t.d, it.t.box);
       const int txl = tune.grad_tile_x == 256 ? 256 : hsz::q4_txl(it.t.box);
-      order_grad[q4 ? variant_q4(it.S, txl, acc_mode[i])
-                    : variant_of(it.S, it.via, it.op, it.dtype, acc_mode[i])].push_back(i);
+      var_of[i] = q4 ? variant_q4(it.S, txl, acc_mode[i]) : variant_of(it.S, it.via, it.op, it.dtype, acc_mode[i]);
+      order_grad[var_of[i]].push_back(i);
       if (!it.index) grads.push_back(i);  // jobs that need an index built here
     }
   }
@@ -240,7 +255,7 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
     J.d = it.t.d;
     J.b = it.t.box;
     J.axis = it.axis3;
-    J.tz = tz_for(it.t.box, tune.grad_tz);
+    J.tz = tz_pick(it.t.box, tune.grad_tz, var_of[i]);
     J.kmax = hsz::grad_kmax(it.v);
     J.halfq = 0.5 * it.v.quantum;
     J.out = it.out;

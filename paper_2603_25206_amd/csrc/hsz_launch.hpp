@@ -119,6 +119,8 @@ hipError_t launch_batch_stats(int S, const StatsJob* jobs, const int64_t* unit_s
 // wave per job summing its slot's stripes).
 // *out = *status (device ints), ordered on 's'
 hipError_t launch_copy_status(const int* status, int* out, hipStream_t s);
+// *dst takes *src's error code if *dst has none
+hipError_t launch_merge_status(const int* src, int* dst, hipStream_t s);
 // K per-slab statistics records (48 bytes each, the hsz_stats layout) of one
 // field combined exactly into one record at 'out' (device)
 hipError_t launch_stats_combine(const void* records, int K, int op, double quantum, void* out, hipStream_t s);

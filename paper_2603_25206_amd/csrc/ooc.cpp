@@ -19,6 +19,7 @@
 //     -> host from one of two output buffers while the next slab computes.
 // At most three compressed slabs, two windows and two output slabs are in
 // device memory at any time.
+#include <algorithm>
 #include <vector>
 
 #include "abi_util.hpp"
@@ -43,6 +44,8 @@ struct SlabSet {
   int64_t max_planes = 0;
   uint64_t max_bytes = 0;
   uint32_t max_abs_q = 0;
+  bool lz = false;         // HSZp-nd or HSZp slabs: decoded and reduced by the single-stream calls
+  uint64_t lz_ws = 0;      // the workspace those calls need for the largest slab
 };
 
 bool is_stencil_op(int op) { return op == HSZ_DERIV || op == HSZ_GRADMAG || op == HSZ_LAPLACIAN; }
@@ -57,8 +60,8 @@ int describe(const hsz_header* const* h, int K, SlabSet* S) {
     if (rc) return rc;
   }
   const hsz_header* h0 = h[0];
-  if (h0->flags > HSZ_FLAG_BLOCK_MEAN) return HSZ_ERR_UNSUPPORTED;
   S->K = K;
+  S->lz = (h0->flags & (HSZ_FLAG_LORENZO | HSZ_FLAG_INTER_BLOCK)) != 0;
   S->ndim = h0->ndim;
   S->dtype = h0->dtype;
   S->plane = 1;
@@ -83,10 +86,26 @@ int describe(const hsz_header* const* h, int K, SlabSet* S) {
   return HSZ_OK;
 }
 
+// HSZp-nd / HSZp slabs: workspace of the single-stream calls per slab (the
+// statistics operation, or decoding to D_q for stencils), the largest
+uint64_t lz_workspace(const hsz_header* const* h, int K, int op) {
+  uint64_t need = 0;
+  for (int k = 0; k < K; ++k) {
+    uint64_t b = 0;
+    const int rc = (op == HSZ_MEAN || op == HSZ_VAR) ? hsz_op_workspace(h[k], op, &b)
+                                                     : hsz_decompress_workspace(h[k], HSZ_QUANT, &b);
+    if (rc) return 0;
+    need = std::max(need, b);
+  }
+  return need;
+}
+
 // Workspace: op workspace (status word first) | 3 compressed slabs | 2
-// windows + 2 output slabs (stencils) or K statistics records.
+// windows + 2 output slabs (stencils) or K statistics records | for
+// HSZp-nd / HSZp slabs, the single-stream calls' workspace (its own status
+// word, merged into the first after each call).
 struct WsLayout {
-  uint64_t cbuf[3], win[2], out[2], stats, final, total;
+  uint64_t cbuf[3], win[2], out[2], stats, final, lzws, total;
 };
 
 WsLayout ws_layout(const SlabSet& S, int op) {
@@ -98,9 +117,11 @@ WsLayout ws_layout(const SlabSet& S, int op) {
   }
   if (is_stencil_op(op)) {
     const uint64_t esz = S.dtype == HSZ_F32 ? 4 : 8;
+    // a window: [pad | halo plane | slab planes | halo plane], the pad
+    // placing the slab's first plane on a 256-byte boundary
     for (int i = 0; i < 2; ++i) {
       L.win[i] = off;
-      off += a256(4 * (uint64_t)(S.max_planes + 2) * (uint64_t)S.plane);
+      off += a256(a256(4 * (uint64_t)S.plane) + 4 * (uint64_t)(S.max_planes + 1) * (uint64_t)S.plane);
     }
     for (int i = 0; i < 2; ++i) {
       L.out[i] = off;
@@ -112,6 +133,8 @@ WsLayout ws_layout(const SlabSet& S, int op) {
     L.final = off;  // the combined record (asynchronous calls)
     off += 256;
   }
+  L.lzws = off;
+  off += a256(S.lz_ws);
   L.total = off;
   return L;
 }
@@ -188,6 +211,7 @@ int ooc_check(const void* const* h_slabs, const hsz_header* const* hdrs, int nsl
               const void* h_result, uint64_t result_bytes, SlabSet* S) {
   int rc = describe(hdrs, nslabs, S);
   if (rc) return rc;
+  if (S->lz && !(S->lz_ws = lz_workspace(hdrs, nslabs, op))) return HSZ_ERR_UNSUPPORTED;
   if (!h_slabs || !h_result) return HSZ_ERR_INVALID_ARG;
   for (int k = 0; k < nslabs; ++k)
     if (!h_slabs[k]) return HSZ_ERR_INVALID_ARG;
@@ -245,11 +269,20 @@ hipError_t ooc_enqueue(const void* const* h_slabs, const hsz_header* const* hdrs
     if (K > 1) chk(issue(1));
     for (int k = 0; k < K && e == hipSuccess; ++k) {
       if (!chk(hipStreamWaitEvent(s, ev.h2d(k % 3), 0))) break;
-      hsz::OpTarget t;
-      t.d = view_dims(S, S.planes[k]);
-      t.box = hsz::Box3{0, t.d.z, 0, t.d.y, 0, t.d.x};
-      chk(hsz::launch_stats_fused(view_of(ws + L.cbuf[k % 3], hdrs[k]), via, op, t, ws + L.stats + 48 * (uint64_t)k,
-                                  ws, s));
+      if (S.lz) {
+        // the slab's own statistics through the single-stream call, then its
+        // status word merged into the pass's
+        const int rc = hsz_op_fused(ws + L.cbuf[k % 3], hdrs[k], via, op, 0, nullptr, ws + L.stats + 48 * (uint64_t)k,
+                                    48, ws + L.lzws, S.lz_ws, s);
+        if (rc && e == hipSuccess) e = hipErrorInvalidValue;
+        chk(hsz::launch_merge_status((const int*)(ws + L.lzws), status, s));
+      } else {
+        hsz::OpTarget t;
+        t.d = view_dims(S, S.planes[k]);
+        t.box = hsz::Box3{0, t.d.z, 0, t.d.y, 0, t.d.x};
+        chk(hsz::launch_stats_fused(view_of(ws + L.cbuf[k % 3], hdrs[k]), via, op, t,
+                                    ws + L.stats + 48 * (uint64_t)k, ws, s));
+      }
       chk(mark_used(k));
       if (k + 2 < K) chk(issue(k + 2));
     }
@@ -264,13 +297,23 @@ hipError_t ooc_enqueue(const void* const* h_slabs, const hsz_header* const* hdrs
   // stencils: windows of D_q with one-plane halos, results streamed out
   const int axis3 = op == HSZ_DERIV ? axis + 3 - S.ndim : 0;
   const int a_s = 3 - S.ndim;  // the slowest axis in the 3D view
-  uint8_t* win[2] = {ws + L.win[0], ws + L.win[1]};
-  uint8_t* out[2] = {ws + L.out[0], ws + L.out[1]};
   const uint64_t pb = 4 * (uint64_t)P;  // bytes of one plane of q
+  // each window starts at its halo plane, so its slab planes (win + pb)
+  // start on a 256-byte boundary
+  uint8_t* win[2] = {ws + L.win[0] + (a256(pb) - pb), ws + L.win[1] + (a256(pb) - pb)};
+  uint8_t* out[2] = {ws + L.out[0], ws + L.out[1]};
   hsz::StreamView vq = view_of(nullptr, hdrs[0]);
   auto decode = [&](int k, uint8_t* dst) -> bool {
     if (!chk(hipStreamWaitEvent(s, ev.h2d(k % 3), 0))) return false;
-    if (!chk(hsz::launch_decode(view_of(ws + L.cbuf[k % 3], hdrs[k]), HSZ_QUANT, dst, status, s))) return false;
+    if (S.lz) {
+      // HSZp-nd / HSZp: the single-stream decode to D_q, its status merged
+      const int rc = hsz_decompress_to_stage(ws + L.cbuf[k % 3], hdrs[k], HSZ_QUANT, dst,
+                                             4 * (uint64_t)S.planes[k] * (uint64_t)P, ws + L.lzws, S.lz_ws, s);
+      if (rc && e == hipSuccess) e = hipErrorInvalidValue;
+      if (!chk(hsz::launch_merge_status((const int*)(ws + L.lzws), status, s))) return false;
+    } else if (!chk(hsz::launch_decode(view_of(ws + L.cbuf[k % 3], hdrs[k]), HSZ_QUANT, dst, status, s))) {
+      return false;
+    }
     return chk(mark_used(k));
   };
   chk(issue(0));
@@ -339,6 +382,7 @@ int hsz_ooc_workspace(const hsz_header* const* h_slabs, int nslabs, int op, uint
   SlabSet S;
   int rc = describe(h_slabs, nslabs, &S);
   if (rc) return rc;
+  if (S.lz && !(S.lz_ws = lz_workspace(h_slabs, nslabs, op))) return HSZ_ERR_UNSUPPORTED;
   *h_bytes = ws_layout(S, op).total;
   return HSZ_OK;
 }

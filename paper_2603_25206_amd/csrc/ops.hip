@@ -455,6 +455,11 @@ __global__ void k_copy_status_word(const int* status, int* out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *out = *status;
 }
 
+// an error in *src becomes *dst's unless *dst holds one already
+__global__ void k_merge_status_word(const int* src, int* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && *src != 0) atomicCAS(dst, 0, *src);
+}
+
 // Records of the same field's slabs (each its own exact sums) combined into
 // one: the sums add exactly (int64, 128 bits) and are finished once.
 __global__ void k_stats_combine(const StatsOut* rec, int K, int op, double quantum, StatsOut* out) {
@@ -757,6 +762,11 @@ hipError_t fused_by_via(const StreamView& v, int via, const Rows& rows, bool who
 
 hipError_t launch_copy_status(const int* status, int* out, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_status_word, dim3(1), dim3(64), 0, s, status, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_status(const int* src, int* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_merge_status_word, dim3(1), dim3(64), 0, s, src, dst);
   return hipGetLastError();
 }
 

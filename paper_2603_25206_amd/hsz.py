@@ -716,10 +716,15 @@ def extremes(x: torch.Tensor, stream=None):
 
 
 def compress_range(x: torch.Tensor, eb: float, vmin: float, vmax: float, rel: bool = True, block: int = 32,
-                   stream=None, mean_dec: bool = False) -> Compressed:
+                   stream=None, mean_dec: bool = False, lorenzo: bool = False,
+                   inter_block: bool = False) -> Compressed:
     """Compress one slab of a larger field with the whole field's quantizer:
-    eps and the quantum come from the field's extremes [vmin, vmax]."""
+    eps and the quantum come from the field's extremes [vmin, vmax]; the
+    decorrelation as in compress()."""
     lib = load()
+    if int(bool(mean_dec)) + int(bool(lorenzo)) + int(bool(inter_block)) > 1:
+        raise ValueError("at most one of mean_dec, lorenzo, inter_block")
+    flags = FLAG_BLOCK_MEAN if mean_dec else (FLAG_LORENZO if lorenzo else (FLAG_INTER_BLOCK if inter_block else 0))
     if not x.is_cuda or not x.is_contiguous():
         raise ValueError("x must be a contiguous GPU tensor")
     dt = F32 if x.dtype == torch.float32 else F64
@@ -727,11 +732,10 @@ def compress_range(x: torch.Tensor, eb: float, vmin: float, vmax: float, rel: bo
     dims = _dims(shape)
     out = _empty_bytes(compress_bound(shape, dt, block), x.device)
     wsb = ctypes.c_uint64()
-    _check(lib.hsz_compress_workspace_mode(len(shape), dims, block, FLAG_BLOCK_MEAN if mean_dec else 0,
-                                           ctypes.byref(wsb)), "compress_workspace")
+    _check(lib.hsz_compress_workspace_mode(len(shape), dims, block, flags, ctypes.byref(wsb)), "compress_workspace")
     ws = workspace(wsb.value, x.device, key="compress")
     _check(lib.hsz_compress_range(ctypes.c_void_p(x.data_ptr()), dt, len(shape), dims, float(eb), int(rel),
-                                  float(vmin), float(vmax), block, FLAG_BLOCK_MEAN if mean_dec else 0,
+                                  float(vmin), float(vmax), block, flags,
                                   ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.c_void_p(ws.data_ptr()),
                                   ws.numel(), ctypes.c_void_p(_stream(stream))), "compress_range")
     st = read_status(ws, stream)
@@ -741,7 +745,7 @@ def compress_range(x: torch.Tensor, eb: float, vmin: float, vmax: float, rel: bo
 
 
 def compress_slabs(x: torch.Tensor, eb: float, planes: int, rel: bool = True, block: int = 32,
-                   mean_dec: bool = False, device="cuda"):
+                   mean_dec: bool = False, device="cuda", lorenzo: bool = False, inter_block: bool = False):
     """Compress a host-resident field slab by slab (ranges of 'planes' indices
     of its slowest axis) with the whole field's quantizer, keeping only one
     slab on the device at a time: a first pass reduces the extremes, a
@@ -758,7 +762,7 @@ def compress_slabs(x: torch.Tensor, eb: float, planes: int, rel: bool = True, bl
     out = []
     for a in range(0, n0, planes):
         c = compress_range(x[a:a + planes].contiguous().to(device), eb, lo, hi, rel=rel, block=block,
-                           mean_dec=mean_dec)
+                           mean_dec=mean_dec, lorenzo=lorenzo, inter_block=inter_block)
         nbytes = int(c.header.total_bytes)
         host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
         host.copy_(c.data[:nbytes])

@@ -239,7 +239,7 @@ def test_slab_and_out_of_core_validation_before_any_launch(lib):
                                        None) == hsz.ERR_CAPACITY
     assert lib.hsz_decompress_to_stage(fake, ctypes.byref(hi), 1, fake, 4 * x.size, fake, 1 << 20,
                                        None) == hsz.ERR_UNSUPPORTED
-    # out of core: slabs of one field only (same quantum and other dims), delta / block-mean streams
+    # out of core: slabs of one field only (same quantum, decorrelation and other dims)
     f = np.random.default_rng(1).normal(size=(12, 9, 10)).astype(np.float32)
     a = hsz.read_header(oracle.compress(f[:6], 1e-3))
     b = hsz.read_header(oracle.compress(f[6:] * 4, 1e-3))  # another quantum
@@ -252,7 +252,10 @@ def test_slab_and_out_of_core_validation_before_any_launch(lib):
     assert ws_of([a]) == 0
     assert ws_of([a, b]) == hsz.ERR_INVALID_ARG
     assert ws_of([a, c]) == hsz.ERR_INVALID_ARG
-    assert ws_of([nd]) == hsz.ERR_UNSUPPORTED
+    assert ws_of([a, nd]) == hsz.ERR_INVALID_ARG  # decorrelations differ
+    assert ws_of([a]) == 0
+    plain = w.value
+    assert ws_of([nd]) == 0 and w.value > plain  # HSZp-nd: the single-stream calls' workspace as well
     assert ws_of([]) == hsz.ERR_INVALID_ARG
     arr = (ctypes.POINTER(hsz.Header) * 1)(ctypes.pointer(a))
     ptrs = (ctypes.c_void_p * 1)(0x20000)

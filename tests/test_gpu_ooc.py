@@ -1,5 +1,6 @@
 """GPU parity for fields held as compressed slabs in host memory and the
-out-of-core operations over them (the sliding window of Alg. 3).
+out-of-core operations over them (the sliding window of Alg. 3), for
+delta, block-mean, HSZp-nd and HSZp slabs.
 
 Bars: each slab's stream equals the oracle's encoding of that slab with
 the whole field's quantizer, byte for byte apart from the recorded
@@ -42,24 +43,36 @@ CASES = [
     ((100003,), np.float32, 1e-3, 32, 30000, False),  # 1D: slabs of the only axis
     ((20, 33, 30), np.float32, 1e-3, 32, 6, True),    # block-mean streams
     ((12, 10, 8), np.float32, 1e-3, 32, 64, False),   # a single slab
+    ((23, 30, 64), np.float32, 1e-3, 32, 6, "lorenzo"),  # HSZp-nd slabs (two-pass D_q), the last shorter
+    ((19, 21, 45), np.float64, 1e-5, 64, 5, "lorenzo"),  # HSZp-nd binary64, ragged blocks
+    ((90, 300), np.float32, 1e-3, 32, 25, "lorenzo"),    # HSZp-nd 2D
+    ((16, 20, 70), np.float32, 1e-3, 32, 5, "inter"),    # HSZp slabs (deltas across blocks)
 ]
 
 
 def case_id(c):
-    shape, dt, rel, S, planes, mean = c
-    return f"{'x'.join(map(str, shape))}-{np.dtype(dt).name}-S{S}-p{planes}" + ("-mean" if mean else "")
+    shape, dt, rel, S, planes, mode = c
+    tag = {True: "-mean", "lorenzo": "-nd", "inter": "-flat"}.get(mode, "")
+    return f"{'x'.join(map(str, shape))}-{np.dtype(dt).name}-S{S}-p{planes}" + tag
+
+
+def mode_kw(mode):
+    """compress() keywords of a case's decorrelation (mode True: block mean)."""
+    return {"mean_dec": mode is True, "lorenzo": mode == "lorenzo", "inter_block": mode == "inter"}
 
 
 @pytest.fixture(scope="module", params=CASES, ids=[case_id(c) for c in CASES])
 def ocase(request):
-    shape, dt, rel, S, planes, mean = request.param
+    shape, dt, rel, S, planes, mode = request.param
     say(f"[case] ooc {case_id(request.param)}")
     f = synth.gaussian_mixture(shape, 5, (2.0, max(3.0, min(shape) / 3.0)), seed=sum(shape) + planes)
     x = np.ascontiguousarray(f.astype(dt))
-    slabs = hsz.compress_slabs(torch.from_numpy(x), rel, planes, rel=True, block=S, mean_dec=mean, device=DEV)
-    whole = hsz.compress(torch.from_numpy(x).to(DEV), rel, rel=True, block=S, mean_dec=mean)
+    kw = mode_kw(mode)
+    slabs = hsz.compress_slabs(torch.from_numpy(x), rel, planes, rel=True, block=S, device=DEV, **kw)
+    whole = hsz.compress(torch.from_numpy(x).to(DEV), rel, rel=True, block=S, **kw)
     torch.cuda.synchronize()
-    return dict(x=x, rel=rel, S=S, planes=planes, mean=mean, slabs=slabs, whole=whole, shape=shape)
+    return dict(x=x, rel=rel, S=S, planes=planes, mean=mode is True, mode=mode, slabs=slabs, whole=whole,
+                shape=shape)
 
 
 def test_slab_streams_match_the_oracle(ocase):
@@ -73,7 +86,7 @@ def test_slab_streams_match_the_oracle(ocase):
         xs = x[a:a + ocase["planes"]]
         assert h.quantum == quantum and h.eb_abs == eps
         q = oracle.quantize(xs, quantum).reshape(xs.shape)
-        ref = oracle.encode_q(q, xs.shape, quantum, S, dtype=dt, eb_abs=eps, mean_dec=ocase["mean"])
+        ref = oracle.encode_q(q, xs.shape, quantum, S, dtype=dt, eb_abs=eps, **mode_kw(ocase["mode"]))
         got = host.numpy()
         assert got.size == ref.size
         keep = np.ones(ref.size, dtype=bool)

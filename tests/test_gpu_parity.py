@@ -349,3 +349,28 @@ def test_corrupt_width_reported_not_faulting():
     with pytest.raises(hsz.HszError) as e:
         hsz.op_fused(c, hsz.QUANT, "var")
     assert e.value.code == hsz.ERR_BAD_STREAM
+
+
+def test_small_field_step_against_the_oracle():
+    """The 64^3 field of the latency row (synth.small_field_spec, seed 0; rel
+    eb 1e-3, S = 32): bytes identical to the oracle's, and the step's plan
+    (mean via D_p, variance via D_q, gradient magnitude via D_q) gives the
+    exact integer sums and the magnitude within 1e-6 on every element."""
+    say("[case] 64^3 small field step")
+    x = synth.make_field(synth.small_field_spec(seed=0))
+    ref = oracle.compress(x, 1e-3, rel=True, block=32)
+    c = hsz.compress(torch.from_numpy(x).to(DEV), 1e-3, rel=True, block=32)
+    c.build_index()
+    assert np.array_equal(c.to_bytes(), ref)
+    q = oracle.decompress(ref, oracle.QUANT)
+    n, s1, s2 = oracle.int_sums(q)
+    want = oracle.gradmag(oracle.dequantize64(q, oracle.read_header(ref).quantum))
+    plan = hsz.Plan([hsz.Job(c, "mean", hsz.DELTA), hsz.Job(c, "var", hsz.QUANT), hsz.Job(c, "gradmag", hsz.QUANT)])
+    plan.launch()
+    mean, var, mag = plan.results()
+    plan.close()
+    assert (mean["n"], mean["s1"]) == (n, s1)
+    assert (var["n"], var["s1"], var["s2"]) == (n, s1, s2)
+    got = mag.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - want) <= 1e-6 * np.abs(want))
+    assert np.all(got[want == 0] == 0)
