@@ -169,8 +169,9 @@ int hsz_compress(const void *d_x, int dtype, int ndim, const int64_t *h_dims, do
  * field only): mean = (sum_b M_b S_b / n) * Delta, exact integer sum in s1,
  * within eps of the mean of the decompressed field.  Streams of this mode
  * support every statistic and the materialised stages 3 and 4 of the
- * stencil and vector-field operations; fused stencils, fused vector fields
- * and batches return HSZ_ERR_UNSUPPORTED for them. */
+ * stencil and vector-field operations; fused stencils and fused vector
+ * fields return HSZ_ERR_UNSUPPORTED for them (in a batch they run as
+ * operations of their own). */
 #define HSZ_FLAG_BLOCK_MEAN 1u
 /* HSZ_FLAG_LORENZO selects HSZp-nd (Sec. IV) for 2D and 3D fields: the
  * Lorenzo residual over the whole field, p = sum over the corners c of
@@ -191,8 +192,9 @@ int hsz_compress(const void *d_x, int dtype, int ndim, const int64_t *h_dims, do
  * they need in the workspace (hsz_op_workspace: 4 bytes per point, 8 for
  * binary64 fields, beyond the operation's own, plus 16 planes of int32 for
  * the two-pass D_q of 3D fields with rows of at most 512 columns; the
- * Laplacian on stage 2 keeps one more int32 field per axis).  Batches and block indexes return
- * HSZ_ERR_UNSUPPORTED for these streams. */
+ * Laplacian on stage 2 keeps one more int32 field per axis).  Block
+ * indexes return HSZ_ERR_UNSUPPORTED for these streams; in a batch they run
+ * as operations of their own. */
 #define HSZ_FLAG_LORENZO 2u
 /* HSZ_FLAG_INTER_BLOCK selects HSZp's decorrelation (Sec. IV, prediction
  * across block borders) for fields of any rank: p_i = q_i - q_{i-1} over the
@@ -276,8 +278,8 @@ int hsz_decompress_to_stage(const void *d_c, const hsz_header *h, int stage, voi
  *      2 q) is exact and scaled once by Delta (Eq. (laplacian_Dq)); this
  *      needs max|q| < 2^27 (else HSZ_ERR_UNSUPPORTED; stage 4 has no limit).
  *      Stage 2: HSZp-nd streams only (whole field, see HSZ_FLAG_LORENZO);
- *      delta and block-mean streams and batches: HSZ_ERR_UNSUPPORTED (a 1D
- *      partition keeps no multidimensional neighbours, Sec. V-B).
+ *      delta and block-mean streams: HSZ_ERR_UNSUPPORTED (a 1D partition
+ *      keeps no multidimensional neighbours, Sec. V-B).
  * Derivatives follow Eq. (derivatives): central differences (q_{+1} -
  * q_{-1}) * Delta/2 inside the field and one-sided (q_1 - q_0) * Delta at
  * its ends, unit spacing, neighbours taken from the whole field even when
@@ -403,13 +405,18 @@ int hsz_vector_op_fused(const void *const *d_c, const hsz_header *const *h, int 
  * groups of 64 block segments (boxes); gradient units are tiles.  Statistics
  * are accumulated as exact integers with 64-bit atomics, so every job's
  * result is bit-identical to hsz_op_fused on the same stream, box and stage,
- * whatever else is in the batch.  Supported: HSZ_MEAN / HSZ_VAR via
- * HSZ_DELTA or HSZ_QUANT; HSZ_DERIV / HSZ_GRADMAG via HSZ_QUANT or
- * HSZ_FLOAT.  Other combinations return HSZ_ERR_UNSUPPORTED. */
+ * whatever else is in the batch.  The kernels take delta streams with
+ * HSZ_MEAN / HSZ_VAR via HSZ_DELTA or HSZ_QUANT and HSZ_DERIV / HSZ_GRADMAG
+ * via HSZ_QUANT or HSZ_FLOAT.  Every other item hsz_op_fused accepts
+ * (HSZp-nd, HSZp and block-mean streams, HSZ_LAPLACIAN, HSZ_VAR_MT,
+ * statistics via HSZ_FLOAT) runs in the pass as an operation of its own,
+ * with its workspace inside the batch's and its status word merged into the
+ * batch's; its refusals (hsz_op_fused's codes) are the batch's.  Vector
+ * operations are HSZ_ERR_INVALID_ARG. */
 typedef struct hsz_work {
   const void *d_c;      /* compressed stream (device, 16-byte aligned)          */
   const hsz_header *h;  /* its parsed header (host)                             */
-  int32_t op;           /* HSZ_MEAN, HSZ_VAR, HSZ_DERIV, HSZ_GRADMAG            */
+  int32_t op;           /* an operation of one stream (HSZ_MEAN .. HSZ_VAR_MT)   */
   int32_t via;          /* the stage held on chip (see above)                   */
   int32_t axis;         /* HSZ_DERIV: axis in the field's own order             */
   int32_t use_box;      /* 0: the whole field; 1: 'box'                         */
@@ -466,8 +473,9 @@ int hsz_batch_run(const hsz_work *h_items, int n, const hsz_tuning *h_tune, void
  * same structure (same jobs per kernel variant, the same classes with
  * separately summed statistics, no larger index or staging needs) -- new
  * streams, boxes, axes and result buffers; it first waits for the previous
- * replay to finish.  The workspace belongs to the plan until
- * hsz_plan_destroy. */
+ * replay to finish (a plan holding operations of their own captures its
+ * graph again with the new items).  The workspace belongs to the plan
+ * until hsz_plan_destroy. */
 typedef struct hsz_plan hsz_plan;
 int hsz_plan_create(const hsz_work *h_items, int n, const hsz_tuning *h_tune, void *d_workspace,
                     uint64_t workspace_bytes, void *stream, hsz_plan **out);

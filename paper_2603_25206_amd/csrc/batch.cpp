@@ -53,12 +53,24 @@ struct Layout {
 };
 
 struct Item {
-  int kind;  // 0 stats, 1 gradient
+  int kind;  // 0 stats, 1 gradient, 2 an operation of its own (hsz_op_fused)
   int S, via, op, dtype, axis3;
   hsz::StreamView v;
   hsz::OpTarget t;
   void* out;
   const uint16_t* index;  // caller's block index, or null
+  hsz_work w;             // kind 2: the work item (w.h unused) and its header
+  hsz_header hdr;
+  uint64_t ws_bytes;      // kind 2: hsz_op_workspace
+};
+
+// A kind-2 job of a built batch: enqueued as its own fused operation on the
+// pass's stream, with its workspace in the batch's (its status word merged
+// into the pass's afterwards).
+struct Single {
+  hsz_work w;
+  hsz_header hdr;
+  uint64_t ws_off, ws_bytes;
 };
 
 // counts slots
@@ -85,16 +97,32 @@ int classify(const hsz_work& w, Item* it) {
   it->out = w.d_result;
   it->index = (const uint16_t*)w.d_index;
   if (w.d_index && ((uintptr_t)w.d_index & 1u)) return HSZ_ERR_INVALID_ARG;
-  if (h->flags) return HSZ_ERR_UNSUPPORTED;  // batch kernels decode delta streams
-  if (w.op == HSZ_MEAN || w.op == HSZ_VAR) {
-    if (w.via != HSZ_DELTA && w.via != HSZ_QUANT) return HSZ_ERR_UNSUPPORTED;  // exact integer routes only
+  // The batch kernels decode delta streams through the exact integer
+  // statistics and the derivative / magnitude stencils; every other item
+  // (HSZp-nd, HSZp and block-mean streams, the Laplacian, the spread about
+  // the metadata mean, statistics through D_f) runs as an operation of its
+  // own inside the pass.
+  const bool stats = w.op == HSZ_MEAN || w.op == HSZ_VAR;
+  const bool grad = w.op == HSZ_DERIV || w.op == HSZ_GRADMAG;
+  if (h->flags || (!stats && !grad) || (stats && w.via != HSZ_DELTA && w.via != HSZ_QUANT)) {
+    if ((w.op < HSZ_MEAN || w.op > HSZ_LAPLACIAN) && w.op != HSZ_VAR_MT) return HSZ_ERR_INVALID_ARG;
+    uint64_t b = 0;
+    if ((rc = hsz_op_workspace(h, w.op, &b))) return rc;
+    it->kind = 2;
+    it->w = w;
+    it->w.h = nullptr;
+    it->hdr = *h;
+    it->ws_bytes = b;
+    it->axis3 = 0;
+    return HSZ_OK;
+  }
+  if (stats) {
     if (w.result_bytes < sizeof(hsz_stats)) return HSZ_ERR_CAPACITY;
     it->kind = 0;
     it->axis3 = 0;
     return HSZ_OK;
   }
-  if (w.op == HSZ_LAPLACIAN || w.op == HSZ_VAR_MT) return HSZ_ERR_UNSUPPORTED;  // single operations only
-  if (w.op == HSZ_DERIV || w.op == HSZ_GRADMAG) {
+  if (grad) {
     if (w.via != HSZ_QUANT && w.via != HSZ_FLOAT) return HSZ_ERR_UNSUPPORTED;
     if (w.op == HSZ_DERIV && (w.axis < 0 || w.axis >= h->ndim)) return HSZ_ERR_INVALID_ARG;
     if ((uintptr_t)w.d_result & 15u) return HSZ_ERR_INVALID_ARG;
@@ -109,6 +137,7 @@ int classify(const hsz_work& w, Item* it) {
 
 struct Built {
   Layout L;
+  std::vector<Single> singles;
   std::vector<uint8_t> table;  // bytes [L.counts, L.table_end)
   int stats_kmax[2] = {0, 0};
   int grad_kmax[kVariants] = {};
@@ -169,6 +198,7 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
   std::vector<int> grads, var_of(items.size(), -1);
   for (int i = 0; i < (int)items.size(); ++i) {
     const Item& it = items[i];
+    if (it.kind == 2) continue;  // an operation of its own (below)
     if (it.kind == 0) order_stats[it.S == 64].push_back(i);
     else {
       const bool q4 =
@@ -207,6 +237,12 @@ int build(const std::vector<Item>& items, const hsz_tuning& tune, uint8_t* d_ws,
   for (int i : grads) {
     L.rel[i] = off;
     off = up(off + 2 * (uint64_t)items[i].v.nb);
+  }
+  B->singles.clear();
+  for (const Item& it : items) {
+    if (it.kind != 2) continue;
+    B->singles.push_back(Single{it.w, it.hdr, off, it.ws_bytes});
+    off = up(off + it.ws_bytes);
   }
   L.total = off;
 
@@ -306,7 +342,9 @@ int device_cus() {
 // a 512-column sixteen-bit tile with statistics summed inside (and every
 // statistic is), no block index is built per pass.  -1 if none.
 int self_finishing(const Built& B) {
-  if (B.n_index > 0 || B.stats_units[0] > 0 || B.stats_units[1] > 0 || B.n_stats[0] + B.n_stats[1] == 0) return -1;
+  if (B.n_index > 0 || B.stats_units[0] > 0 || B.stats_units[1] > 0 || B.n_stats[0] + B.n_stats[1] == 0 ||
+      !B.singles.empty())
+    return -1;
   int only = -1;
   for (int g = 0; g < kVariants; ++g) {
     if (B.n_grad[g] == 0) continue;
@@ -384,6 +422,15 @@ int enqueue(const Built& B, uint8_t* d_ws, const hsz_tuning& tune, hipStream_t s
                                     (const int64_t*)(d_ws + L.grad_start[g]), counts + 2 * cslot_grad(g),
                                     B.grad_kmax[g], grad_grid, status, s)) != hipSuccess)
       return hip_fail(e);
+  }
+  // the operations of their own, each followed by its status word's merge
+  for (const Single& one : B.singles) {
+    hsz_header hdr = one.hdr;
+    const hsz_work& w = one.w;
+    const int rc = hsz_op_fused(w.d_c, &hdr, w.via, w.op, w.axis, w.use_box ? &w.box : nullptr, w.d_result,
+                                w.result_bytes, d_ws + one.ws_off, one.ws_bytes, s);
+    if (rc) return rc;
+    if ((e = hsz::launch_merge_status((const int*)(d_ws + one.ws_off), status, s)) != hipSuccess) return hip_fail(e);
   }
   const hsz::StatsJob* fj[2] = {(const hsz::StatsJob*)(d_ws + L.stats_jobs[0]),
                                 (const hsz::StatsJob*)(d_ws + L.stats_jobs[1])};
@@ -547,6 +594,9 @@ int hsz_plan_update(hsz_plan* p, const hsz_work* items, int n) {
            (B.stats_units[si] > 0) == (A.stats_units[si] > 0);
   for (int g = 0; g < kVariants && same; ++g) same = B.n_grad[g] == A.n_grad[g] && B.grad_kmax[g] <= A.grad_kmax[g];
   for (size_t i = 0; i < B.L.rel.size() && same; ++i) same = B.L.rel[i] == A.L.rel[i];
+  same = same && B.singles.size() == A.singles.size();
+  for (size_t k = 0; k < B.singles.size() && same; ++k)
+    same = B.singles[k].ws_off == A.singles[k].ws_off && B.singles[k].ws_bytes <= A.singles[k].ws_bytes;
   if (!same) return HSZ_ERR_UNSUPPORTED;
   if (p->launched) {
     hipError_t e = hipEventSynchronize(p->done);  // the last replay has read the table
@@ -554,6 +604,34 @@ int hsz_plan_update(hsz_plan* p, const hsz_work* items, int n) {
   }
   hipError_t e = hipMemcpy(p->d_ws + B.L.counts, B.table.data(), B.table.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e);
+  if (!B.singles.empty()) {
+    // the operations of their own take their streams and results as launch
+    // arguments: direct launches read the new ones from here, and the graph
+    // is captured again with them
+    for (size_t k = 0; k < B.singles.size(); ++k) {
+      p->built.singles[k].w = B.singles[k].w;
+      p->built.singles[k].hdr = B.singles[k].hdr;
+    }
+    hipStream_t cs = nullptr;
+    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e);
+    hipGraph_t g = nullptr;
+    int erc = HSZ_OK;
+    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) == hipSuccess) {
+      erc = enqueue(p->built, p->d_ws, p->tune, cs, true);
+      e = hipStreamEndCapture(cs, &g);
+    }
+    hipGraphExec_t x = nullptr;
+    if (e == hipSuccess && erc == HSZ_OK) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess || erc != HSZ_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return erc != HSZ_OK ? erc : hip_fail(e);
+    }
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph = g;
+    p->exec = x;
+  }
   return HSZ_OK;
 }
 

@@ -346,3 +346,33 @@ def test_ctx_validation_before_any_launch(lib):
     assert lib.hsz_ctx_batch_run(None, items, 1, None, None, None) == hsz.ERR_INVALID_ARG
     assert lib.hsz_ooc_op_async(None, None, None, 1, hsz.QUANT, hsz.MEAN, 0, None, 0, None, None) == \
         hsz.ERR_INVALID_ARG
+
+
+def test_batch_workspace_of_every_stream_mode(lib):
+    """A batch sizes operations of their own (HSZp-nd, HSZp and block-mean
+    streams, the Laplacian, the spread about the metadata mean, statistics
+    through D_f) beside its kernel jobs, on the host: each adds its
+    single-operation workspace; an operation no stream has is refused."""
+    f = np.random.default_rng(4).normal(size=(12, 10, 16)).astype(np.float32)
+    hd = hsz.read_header(oracle.compress(f, 1e-3))
+    hn = hsz.read_header(oracle.compress(f, 1e-3, lorenzo=True))
+    hf = hsz.read_header(oracle.compress(f, 1e-3, inter_block=True))
+    hm = hsz.read_header(oracle.compress(f, 1e-3, mean_dec=True))
+    fake = 0x10000
+
+    def ws_of(jobs):
+        items = (hsz.Work * len(jobs))()
+        for it, (h, op, via) in zip(items, jobs):
+            it.d_c, it.h, it.op, it.via = fake, ctypes.pointer(h), op, via
+            it.d_result, it.result_bytes = fake, 4 * f.size
+        w = ctypes.c_uint64()
+        rc = lib.hsz_batch_workspace(items, len(jobs), ctypes.byref(w))
+        return rc, w.value
+
+    rc, base = ws_of([(hd, hsz.GRADMAG, hsz.QUANT), (hd, hsz.VAR, hsz.QUANT)])
+    assert rc == 0
+    for extra in [(hn, hsz.VAR, hsz.DELTA), (hn, hsz.LAPLACIAN, hsz.DELTA), (hf, hsz.GRADMAG, hsz.QUANT),
+                  (hm, hsz.VAR_MT, hsz.DELTA), (hd, hsz.MEAN, hsz.FLOAT), (hd, hsz.LAPLACIAN, hsz.QUANT)]:
+        rc, w = ws_of([(hd, hsz.GRADMAG, hsz.QUANT), (hd, hsz.VAR, hsz.QUANT), extra])
+        assert rc == 0 and w > base, extra
+    assert ws_of([(hd, hsz.DIVERGENCE, hsz.QUANT)])[0] == hsz.ERR_INVALID_ARG

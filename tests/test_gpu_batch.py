@@ -185,10 +185,53 @@ def test_shared_decode_statistics(streams):
     plan.close()
 
 
-def test_batch_rejects_float_route_statistics(streams):
-    with pytest.raises(hsz.HszError) as e:
-        hsz.batch_run([hsz.Job(streams[0][1], "mean", hsz.FLOAT)])
-    assert e.value.code == hsz.ERR_UNSUPPORTED
+def test_batch_of_every_stream_mode_and_operation(streams):
+    """Items the batch kernels do not take (HSZp-nd, HSZp and block-mean
+    streams, the Laplacian, the spread about the metadata mean, statistics
+    through D_f) run inside the batch as operations of their own, mixed with
+    kernel jobs: every result equals the operation run alone, bit for bit,
+    in one-shot batches, plans launched directly and replayed as graphs, and
+    after a plan update to other streams (the graph captured again)."""
+    say("[case] batch of every mode")
+    x0, c0 = streams[0]
+    shape = (24, 20, 40)
+    xs = [np.ascontiguousarray(synth.gaussian_mixture(shape, 4, (2.0, 6.0), seed=90 + k).astype(np.float32))
+          for k in range(2)]
+
+    def modes(x):
+        xt = torch.from_numpy(x).to(DEV)
+        return (hsz.compress(xt, 1e-3, rel=True, block=32, lorenzo=True),
+                hsz.compress(xt, 1e-3, rel=True, block=32, inter_block=True),
+                hsz.compress(xt, 1e-3, rel=True, block=32, mean_dec=True))
+
+    def jobs_of(nd, flat, bm):
+        box = ((2, 3, 5), (20, 17, 33))
+        return [hsz.Job(c0, "gradmag", hsz.QUANT), hsz.Job(c0, "var", hsz.QUANT),
+                hsz.Job(c0, "mean", hsz.FLOAT), hsz.Job(c0, "laplacian", hsz.QUANT),
+                hsz.Job(nd, "mean", hsz.DELTA), hsz.Job(nd, "var", hsz.DELTA), hsz.Job(nd, "var", hsz.QUANT, box=box),
+                hsz.Job(nd, "deriv", hsz.DELTA, axis=1), hsz.Job(nd, "laplacian", hsz.DELTA),
+                hsz.Job(nd, "gradmag", hsz.QUANT, box=box),
+                hsz.Job(flat, "var", hsz.DELTA), hsz.Job(flat, "gradmag", hsz.QUANT),
+                hsz.Job(bm, "var_mt", hsz.DELTA), hsz.Job(bm, "mean", hsz.META), hsz.Job(bm, "var", hsz.QUANT)]
+
+    jobs = jobs_of(*modes(xs[0]))
+    want = [alone(j) for j in jobs]
+    for k, (j, g) in enumerate(zip(jobs, hsz.batch_run(jobs))):
+        assert same(g, want[k]), (k, j.op, j.via)
+    jobs2 = jobs_of(*modes(xs[1]))
+    want2 = [alone(j) for j in jobs2]
+    for graph in (False, True):
+        plan = hsz.Plan(jobs, tune={"graph_replay": graph})
+        for rep in range(2):
+            plan.launch()
+            for k, g in enumerate(plan.results()):
+                assert same(g, want[k]), (graph, rep, k)
+            torch.cuda.synchronize()
+        plan.update(jobs2)
+        plan.launch()
+        for k, g in enumerate(plan.results()):
+            assert same(g, want2[k]), (graph, "updated", k)
+        plan.close()
 
 
 def test_batch_with_prebuilt_block_indexes(streams):

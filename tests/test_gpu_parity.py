@@ -288,9 +288,10 @@ def test_laplacian_all_routes(case):
 
 def test_laplacian_large_integers_and_batches():
     """max|q| >= 2^27: the integer Laplacian is refused (its 32-bit numerator
-    could overflow) while the float route still matches the oracle; batches
-    do not take the Laplacian."""
-    say("[case] laplacian: max|q| >= 2^27, batch refusal")
+    could overflow) while the float route still matches the oracle; in a
+    batch the Laplacian runs as an operation of its own, with the same
+    result and the same refusal."""
+    say("[case] laplacian: max|q| >= 2^27, in a batch")
     x = field((6, 9, 40), np.float64, seed=77)
     c = hsz.compress(torch.from_numpy(x).to(DEV), 1e-9, rel=True, block=32)
     assert c.header.max_abs_q >= 2 ** 27
@@ -302,8 +303,14 @@ def test_laplacian_large_integers_and_batches():
     want = oracle.laplacian(xs)
     got = hsz.op_fused(c, hsz.FLOAT, "laplacian").cpu().numpy()
     assert np.all(np.abs(got - want) <= 1e-12 * np.abs(want) + 16 * 2.0 ** -53 * float(np.max(np.abs(xs))))
+    plan = hsz.Plan([hsz.Job(c, "laplacian", hsz.FLOAT), hsz.Job(c, "var", hsz.QUANT)])
+    plan.launch()
+    lap, var = plan.results()
+    plan.close()
+    assert torch.equal(lap.cpu(), torch.from_numpy(got))
+    assert var == hsz.op_fused(c, hsz.QUANT, "var")
     with pytest.raises(hsz.HszError) as e:
-        hsz.Plan([hsz.Job(c, "laplacian", hsz.FLOAT)])
+        hsz.Plan([hsz.Job(c, "laplacian", hsz.QUANT)])
     assert e.value.code == hsz.ERR_UNSUPPORTED
 
 
