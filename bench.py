@@ -425,8 +425,10 @@ def main():
         "dtype": "int32+f64",
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(map(str, shape))} f32 gaussian-mixture x lognormal texture, "
-                               f"rel eb {a.eb:g}, S={a.block}; step = mean(D_p) + var(D_q) + gradmag(D_q) "
-                               f"from the compressed bytes, one batched pass (one plan launch)",
+                               f"rel eb {a.eb:g}, S={a.block}; step = mean + var + gradmag(D_q) from the "
+                               f"compressed bytes, one batched pass (one plan launch): the mean (asked via D_p) "
+                               f"and the variance (via D_q) are the exact integer sums of q taken in the "
+                               f"gradient's decode (sum of the D_p weighted deltas = sum q)",
                    "global_batch": 1, "field_bytes": orig_bytes, "compressed_bytes": main_row["compressed_bytes"],
                    "ratio": main_row["ratio"], "parallelism": "single-gpu"},
         "separate_ops": main_row["separate_ops"],
