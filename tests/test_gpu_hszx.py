@@ -179,10 +179,18 @@ def test_gradient_on_materialised_stage_and_refusals(mcase):
                 lambda: hsz.op_fused(c, hsz.QUANT, "laplacian"),
                 lambda: hsz.op_on_stage(hsz.decompress_to_stage(c, hsz.DELTA), c.header, hsz.DELTA, "deriv",
                                         axis=nd - 1),
-                lambda: hsz.Plan([hsz.Job(c, "mean", hsz.QUANT)])):
+                lambda: hsz.Plan([hsz.Job(c, "gradmag", hsz.QUANT)])):
         with pytest.raises(hsz.HszError) as e:
             bad()
         assert e.value.code == hsz.ERR_UNSUPPORTED
+    # in a batch, block-mean streams run as operations of their own
+    plan = hsz.Plan([hsz.Job(c, "mean", hsz.QUANT), hsz.Job(c, "var_mt", hsz.DELTA)])
+    plan.launch()
+    mean, spread = plan.results()
+    plan.close()
+    m1, v1 = hsz.op_fused(c, hsz.QUANT, "mean"), hsz.op_fused(c, hsz.DELTA, "var_mt")
+    assert (mean["n"], mean["s1"], mean["mean"]) == (m1["n"], m1["s1"], m1["mean"])
+    assert (spread["n"], spread["s1"], spread["s2"], spread["var"]) == (v1["n"], v1["s1"], v1["s2"], v1["var"])
 
 
 def test_metadata_stage_refused_for_delta_streams():

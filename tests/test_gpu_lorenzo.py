@@ -218,7 +218,7 @@ def test_refused_routes(lcase):
            lambda: hsz.op_on_stage(dbuf, c.header, hsz.DELTA, "gradmag"),
            lambda: hsz.op_fused(c, hsz.META, "mean"),
            lambda: hsz.op_fused(c, hsz.QUANT, "var_mt"),
-           lambda: hsz.Plan([hsz.Job(c, "mean", hsz.QUANT)]),
+           lambda: hsz.Plan([hsz.Job(c, "gradmag", hsz.DELTA)]),  # in a batch: the operation's own refusal
            lambda: c.build_index()]
     if box is not None:
         bad += [lambda: hsz.op_fused(c, hsz.DELTA, "mean", box=box),
@@ -228,6 +228,15 @@ def test_refused_routes(lcase):
         with pytest.raises(hsz.HszError) as e:
             fn()
         assert e.value.code == hsz.ERR_UNSUPPORTED
+    # in a batch HSZp-nd streams run as operations of their own
+    plan = hsz.Plan([hsz.Job(c, "mean", hsz.QUANT), hsz.Job(c, "var", hsz.DELTA)])
+    plan.launch()
+    mean, var = plan.results()
+    plan.close()
+    m1, v1 = hsz.op_fused(c, hsz.QUANT, "mean"), hsz.op_fused(c, hsz.DELTA, "var")
+    assert (mean["n"], mean["s1"], mean["mean"]) == (m1["n"], m1["s1"], m1["mean"])
+    assert (var["n"], var["s1"], var["s2"], var["mean"], var["var"]) == \
+        (v1["n"], v1["s1"], v1["s2"], v1["mean"], v1["var"])
 
 
 VCASES = [
@@ -395,7 +404,7 @@ def test_inter_block_stencils_and_refusals(fcase):
     for fn in (lambda: hsz.op_fused(c, hsz.DELTA, "deriv", axis=nd - 1),
                lambda: hsz.op_fused(c, hsz.DELTA, "laplacian"),
                lambda: hsz.decompress_to_stage(c, hsz.META),
-               lambda: hsz.Plan([hsz.Job(c, "var", hsz.QUANT)])):
+               lambda: hsz.Plan([hsz.Job(c, "deriv", hsz.DELTA, axis=nd - 1)])):
         with pytest.raises(hsz.HszError) as e:
             fn()
         assert e.value.code == hsz.ERR_UNSUPPORTED
