@@ -232,9 +232,11 @@ int ooc_check(const void* const* h_slabs, const hsz_header* const* hdrs, int nsl
 // are combined on the device (ws + L.final) and copied into h_result on 's',
 // and the stencil results' last copies on 'cs' are joined into 's'; else the
 // caller drains both streams and combines the records on the host.
+// A single-stream call that refuses (HSZp-nd / HSZp slabs) leaves its code
+// in *call_rc and stops the pass.
 hipError_t ooc_enqueue(const void* const* h_slabs, const hsz_header* const* hdrs, const SlabSet& S, int via, int op,
                        int axis, void* h_result, uint8_t* ws, const WsLayout& L, hipStream_t s, hipStream_t cs,
-                       Events& ev, bool async) {
+                       Events& ev, bool async, int* call_rc) {
   int* status = (int*)ws;
   const int K = S.K;
   const int64_t P = S.plane;
@@ -274,7 +276,10 @@ hipError_t ooc_enqueue(const void* const* h_slabs, const hsz_header* const* hdrs
         // status word merged into the pass's
         const int rc = hsz_op_fused(ws + L.cbuf[k % 3], hdrs[k], via, op, 0, nullptr, ws + L.stats + 48 * (uint64_t)k,
                                     48, ws + L.lzws, S.lz_ws, s);
-        if (rc && e == hipSuccess) e = hipErrorInvalidValue;
+        if (rc) {
+          *call_rc = rc;
+          if (e == hipSuccess) e = hipErrorInvalidValue;
+        }
         chk(hsz::launch_merge_status((const int*)(ws + L.lzws), status, s));
       } else {
         hsz::OpTarget t;
@@ -309,7 +314,11 @@ hipError_t ooc_enqueue(const void* const* h_slabs, const hsz_header* const* hdrs
       // HSZp-nd / HSZp: the single-stream decode to D_q, its status merged
       const int rc = hsz_decompress_to_stage(ws + L.cbuf[k % 3], hdrs[k], HSZ_QUANT, dst,
                                              4 * (uint64_t)S.planes[k] * (uint64_t)P, ws + L.lzws, S.lz_ws, s);
-      if (rc && e == hipSuccess) e = hipErrorInvalidValue;
+      if (rc) {
+        *call_rc = rc;
+        if (e == hipSuccess) e = hipErrorInvalidValue;
+        return false;
+      }
       if (!chk(hsz::launch_merge_status((const int*)(ws + L.lzws), status, s))) return false;
     } else if (!chk(hsz::launch_decode(view_of(ws + L.cbuf[k % 3], hdrs[k]), HSZ_QUANT, dst, status, s))) {
       return false;
@@ -403,7 +412,8 @@ int hsz_ooc_op(const void* const* h_slabs, const hsz_header* const* hdrs, int ns
   Events ev;
   e = ev.create();
   std::vector<uint8_t> records;
-  if (e == hipSuccess) e = ooc_enqueue(h_slabs, hdrs, S, via, op, axis, h_result, ws, L, s, cs, ev, false);
+  int call_rc = HSZ_OK;
+  if (e == hipSuccess) e = ooc_enqueue(h_slabs, hdrs, S, via, op, axis, h_result, ws, L, s, cs, ev, false, &call_rc);
   // drain both streams whatever happened, so no copy is in flight on return
   hipError_t e1 = hipStreamSynchronize(cs);
   hipError_t e2 = hipStreamSynchronize(s);
@@ -415,6 +425,7 @@ int hsz_ooc_op(const void* const* h_slabs, const hsz_header* const* hdrs, int ns
     e = hipMemcpy(records.data(), ws + L.stats, records.size(), hipMemcpyDeviceToHost);
   }
   (void)hipStreamDestroy(cs);
+  if (call_rc != HSZ_OK) return call_rc;
   if (e != hipSuccess) return hip_fail(e);
   if (st != 0) return st;
   if (!is_stencil_op(op)) combine(records, nslabs, op, hdrs[0]->quantum, (hsz_stats*)h_result);
@@ -439,7 +450,9 @@ int hsz_ooc_op_async(hsz_ctx* ctx, const void* const* h_slabs, const hsz_header*
   // windows and the status word are reused)
   hipError_t e = hsz_ctx_util::order_after_last(ctx, s);
   if (e == hipSuccess) e = hsz_ctx_util::order_after_last(ctx, cs);
-  if (e == hipSuccess) e = ooc_enqueue(h_slabs, hdrs, S, via, op, axis, h_result, ctx->d_scratch, L, s, cs, ev, true);
+  int call_rc = HSZ_OK;
+  if (e == hipSuccess)
+    e = ooc_enqueue(h_slabs, hdrs, S, via, op, axis, h_result, ctx->d_scratch, L, s, cs, ev, true, &call_rc);
   if (e == hipSuccess && d_status) {
     e = hsz::launch_copy_status((const int*)ctx->d_scratch, d_status, s);
   }
@@ -447,6 +460,7 @@ int hsz_ooc_op_async(hsz_ctx* ctx, const void* const* h_slabs, const hsz_header*
   // on either stream is joined into 's'
   hipError_t e2 = hsz_ctx_util::mark_last(ctx, s);
   if (e == hipSuccess) e = e2;
+  if (call_rc != HSZ_OK) return call_rc;
   return e == hipSuccess ? HSZ_OK : hip_fail(e);
 }
 
