@@ -253,6 +253,12 @@ hipError_t lz_deriv_p(const int32_t* p, const StreamView& v, const NdGrid& g, in
 // segment (seg_planes planes each).  lz_decode takes this route for stages
 // 3 and 4 (binary32) when given tmp of lz_dq_tmp_bytes.
 bool lz_dq_ok(const NdGrid& g);
+// HSZp (one row of more than kFlatTile words) from the stream: p into 'p'
+// with the sum of each kFlatTile tile in 'tsums', then the exclusive prefix
+// of the sums (tile t's carry); q is p prefix-summed within its tile plus
+// the carry.
+hipError_t lz_flat_front(const StreamView& v, const NdGrid& g, int32_t* p, int32_t* tsums, int* status,
+                         hipStream_t s);
 uint64_t lz_dq_tmp_bytes(const NdGrid& g);
 hipError_t lz_dq_front(const StreamView& v, const NdGrid& g, int32_t* t, int32_t* tot, int* status, hipStream_t s,
                        int64_t* seg_planes);

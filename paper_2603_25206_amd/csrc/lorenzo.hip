@@ -925,6 +925,16 @@ uint64_t lz_dq_tmp_bytes(const NdGrid& g) {
   return lz_dq_ok(g) ? (uint64_t)kDqMaxSeg * (uint64_t)(g.Y * g.X) * sizeof(int32_t) : 0;
 }
 
+hipError_t lz_flat_front(const StreamView& v, const NdGrid& g, int32_t* p, int32_t* tsums, int* status,
+                         hipStream_t s) {
+  if (g.ndim != 1 || g.Z * g.Y != 1 || g.X <= kFlatTile || !tsums) return hipErrorNotSupported;
+  hipError_t e = decode_p_any(v, g, p, 1, status, s, tsums);
+  if (e != hipSuccess) return e;
+  const int64_t ntiles = (g.X + kFlatTile - 1) / kFlatTile;
+  hipLaunchKernelGGL(k_flat_scan_sums, dim3(1), dim3(kThreads), 0, s, tsums, ntiles);
+  return hipGetLastError();
+}
+
 hipError_t lz_dq_front(const StreamView& v, const NdGrid& g, int32_t* t, int32_t* tot, int* status, hipStream_t s,
                        int64_t* seg_planes) {
   if (!lz_dq_ok(g) || !tot) return hipErrorNotSupported;  // three dimensions only

@@ -1079,6 +1079,48 @@ __global__ void __launch_bounds__(kThreads) k_lz_dq2_stats(const int32_t* __rest
   store_int_partial(acc, parts);
 }
 
+// Alg. 4 on HSZp's flat row from lz_flat_front's p and tile carries: each
+// tile's q (the in-tile prefix sum of p plus the carry, as the device-wide
+// scan's last pass forms it) is summed, q and q^2, and not written.
+constexpr int kFlatStatsPer = (int)(kFlatTile / kThreads);
+__global__ void __launch_bounds__(kThreads) k_flat_stats(const int32_t* __restrict__ p, int64_t n,
+                                                        const int32_t* __restrict__ carry, Partial* parts) {
+  __shared__ int wt[kFlatStatsPer * kWavesPerGroup];
+  IntAcc acc;
+  const int64_t ntiles = (n + kFlatTile - 1) / kFlatTile;
+  const int wv = wave_in_group();
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t i0 = t * kFlatTile + threadIdx.x;
+    int v[kFlatStatsPer];
+#pragma unroll
+    for (int k = 0; k < kFlatStatsPer; ++k) {
+      const int64_t i = i0 + (int64_t)k * kThreads;
+      v[k] = i < n ? p[i] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kFlatStatsPer; ++k) {
+      v[k] = wave_incl_scan(v[k]);
+      if (lane_id() == kWave - 1) wt[k * kWavesPerGroup + wv] = v[k];
+    }
+    lds_barrier();
+    int run = carry[t];
+#pragma unroll
+    for (int k = 0; k < kFlatStatsPer; ++k) {
+      int before = 0, row = 0;
+#pragma unroll
+      for (int w = 0; w < kWavesPerGroup; ++w) {
+        const int x = wt[k * kWavesPerGroup + w];
+        before += w < wv ? x : 0;
+        row += x;
+      }
+      if (i0 + (int64_t)k * kThreads < n) acc.add(run + before + v[k], true);
+      run += row;
+    }
+    lds_barrier();  // wt is rewritten by the next tile
+  }
+  store_int_partial(acc, parts);
+}
+
 template <int S, int ND>
 int launch_lz_mean_fused(const StreamView& v, const NdGrid& g, Partial* parts, int* status, hipStream_t s) {
   const int kmax = lz_kmax<S, ND>(v.max_abs_q);
@@ -1116,6 +1158,20 @@ hipError_t launch_lz_stats(const int32_t* p, const StreamView& v, const NdGrid& 
     // then also provides the scan's tile sums)
     const int last = g.ndim == 3 ? 0 : (g.ndim == 2 ? 1 : -1);
     const bool to_q = !p && g.ndim == 1;
+    if (!p && tmp && g.ndim == 1 && g.Z * g.Y == 1 && g.X > kFlatTile) {
+      // HSZp from the stream: decode to p with the tile sums, their prefix,
+      // then one pass summing q as the scan's last pass would form it
+      hipError_t e = lz_flat_front(v, g, scratch, tmp, status, s);
+      if (e != hipSuccess) return e;
+      const int64_t ntiles = (g.X + kFlatTile - 1) / kFlatTile;
+      grid = (int)(ntiles < kOpWorkgroups ? ntiles : kOpWorkgroups);
+      hipLaunchKernelGGL(k_flat_stats, dim3(grid), dim3(kThreads), 0, s, scratch, g.X, tmp, parts);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, parts, grid, op, 0, v.quantum,
+                         (const StatsOut*)nullptr, (StatsOut*)result);
+      return hipGetLastError();
+    }
     if (!p && tmp && lz_dq_ok(g)) {
       // from the stream: the two-pass D_q's first pass, then its second
       // pass summing instead of writing
