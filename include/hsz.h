@@ -438,7 +438,8 @@ int hsz_block_index(const void *d_c, const hsz_header *h, void *d_index, uint64_
 typedef struct hsz_tuning {
   int32_t stats_waves_per_cu;  /* statistics launch: waves per compute unit (8)   */
   int32_t grad_groups_per_cu;  /* gradient launch: workgroups per compute unit (4) */
-  int32_t grad_tz;             /* planes per gradient tile (32)                    */
+  int32_t grad_tz;             /* planes per gradient tile; 0: 32, halved (to 4 at
+                                  least) while a job has fewer than 256 tiles        */
   int32_t separate_stats;      /* 1: statistics never share a gradient job's decode
                                   (by default a mean/variance job over the same stream
                                   and box as a gradient job through D_q is summed
