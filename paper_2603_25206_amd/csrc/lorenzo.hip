@@ -346,7 +346,8 @@ __global__ void __launch_bounds__(kThreads) k_scan_strided4(int32_t* __restrict_
 // Two passes over the field instead of decoding and three prefix passes.
 // The lane that scans eight columns also owns their running sums along z
 // and stores them (two 16-byte words), so the scanned row never returns to
-// LDS; the next layer's chunk metadata is loaded a layer ahead.
+// LDS; a layer's chunk metadata is loaded two layers ahead and its first
+// payload words one layer ahead (the pipeline at the end of k_lz_dq1).
 typedef int i4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr uint32_t kDqNoStore = 0x80000000u;  // a buffer offset past every row: the store is discarded
