@@ -122,13 +122,15 @@ def test_context_capacity_and_tuning():
         ctx.close()
 
 
+@pytest.mark.parametrize("mode", ["delta", "nd"])
 @pytest.mark.parametrize("op", ["mean", "var", "gradmag"])
-def test_out_of_core_async_equals_sync(op):
-    shape = (37, 41, 29)
-    say(f"[case] ctx ooc {op}")
+def test_out_of_core_async_equals_sync(op, mode):
+    shape = (37, 41, 32)
+    say(f"[case] ctx ooc {op} {mode}")
     f = synth.gaussian_mixture(shape, 5, (2.0, 12.0), seed=11)
     x = np.ascontiguousarray(f.astype(np.float32))
-    slabs = hsz.compress_slabs(torch.from_numpy(x), 1e-3, 8, rel=True, block=32, device=DEV)
+    slabs = hsz.compress_slabs(torch.from_numpy(x), 1e-3, 8, rel=True, block=32, device=DEV,
+                               lorenzo=mode == "nd")
     want = hsz.ooc_op(slabs, op)
     ctx = hsz.Context(scratch_bytes=0, host_bytes=1 << 16)
     try:
