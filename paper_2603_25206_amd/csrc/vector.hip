@@ -130,6 +130,7 @@ __global__ void __launch_bounds__(256) k_vector_buf(VecJob j) {
 
 // ---- fused from the compressed streams (D_q) ------------------------------------
 constexpr int kVTx = 256, kVThreads = 256;
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
 
 template <int S, int TY>
 struct VRow {
@@ -185,6 +186,60 @@ struct VWin {
   static constexpr int kStageOff = (row_off(NC) * R::kPitch + 63) / 64 * 64;
 };
 
+// A staged block decoded two slots per funnel shift: with every width at most
+// 16 bits (the stream's max|q| below 2^15, which bounds every delta's width),
+// slots j and j + 1 lie in one 32-bit window of the magnitude words, so a
+// pair costs one pair of LDS reads and one shift where the slot-by-slot
+// decode of the general case costs two each.  Same slots, same values.
+constexpr int kVPairW = 16;
+template <int S, bool ALIGNED>
+__device__ __forceinline__ void decode_block_pairs(const uint32_t* col, int w, int q0, int* dst, int jx) {
+  const uint32_t sg0 = col[0];
+  const uint32_t sg1 = S == 64 ? col[kVThreads] : 0u;
+  const uint32_t* mag = col + (S / 32) * kVThreads;
+  int* dst1 = dst + 1;
+  int q = q0;
+  const uint32_t uw = (uint32_t)w, w2 = 2u * uw;
+  uint32_t pos = 0;
+#pragma unroll
+  for (int g = 0; g < S; g += 8) {
+    // bit positions of the four pairs by additions (the empty asm keeps the
+    // compiler from computing all of them up front)
+    asm volatile("" : "+v"(pos));
+    uint32_t lo[4], hi[4], pp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      pp[u] = pos;
+      pos += w2;
+      uint32_t k = pp[u] >> 5;
+      asm("" : "+v"(k));  // one shift-add per address
+      const uint32_t* a = mag + k * kVThreads;
+      lo[u] = a[0];
+      hi[u] = a[kVThreads];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = g + 2 * u;
+      const uint32_t win = __builtin_amdgcn_alignbit(hi[u], lo[u], pp[u]);
+      const uint32_t sgw = j < 32 ? sg0 : sg1;
+      const int s0 = __builtin_amdgcn_sbfe((int)sgw, (uint32_t)(j & 31), 1u);
+      const int s1 = __builtin_amdgcn_sbfe((int)sgw, (uint32_t)((j + 1) & 31), 1u);
+      const uint32_t m0 = __builtin_amdgcn_ubfe(win, 0u, uw), m1 = __builtin_amdgcn_ubfe(win, uw, uw);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int jj = j + h, sg = h ? s1 : s0;
+        q = (int)(((h ? m1 : m0) ^ (uint32_t)sg) + (uint32_t)q) - sg;  // q += (m ^ s) - s
+        if constexpr (ALIGNED) {
+          dst[jj + (jj >> 5)] = q;
+        } else {
+          int* d = ((jj & 31) >= jx) ? dst1 : dst;
+          d[jj + (jj >> 5)] = q;
+        }
+      }
+    }
+  }
+}
+
 // One workgroup: a tile of kVTx columns x TY rows over tz planes.  Per plane
 // p, every thread with a decode item stages and decodes its block of plane
 // p into its component's window; after a barrier every column thread writes
@@ -193,7 +248,7 @@ struct VWin {
 // p and p - 2 kept in registers); a barrier frees the windows for the next
 // plane, whose payload words were loaded during the stencil.  Then plane
 // p - 1 is emitted.
-template <int S, int OP, int NC, typename T>
+template <int S, int OP, int NC, typename T, bool PAIRS>
 __global__ void __launch_bounds__(kVThreads) k_vector_fused(VecJob j, int* status) {
   using Tm = VTerms<OP, NC>;
   using W = VWin<S, OP, NC>;
@@ -247,6 +302,25 @@ __global__ void __launch_bounds__(kVThreads) k_vector_fused(VecJob j, int* statu
   const int64_t dy = (dhy ? rA : y0) + dr;
   const bool decoder = dc >= 0 && dy < (dhy ? rB : y0 + ys);
   const int64_t dxa = dhx ? cA : x0, dxb = dhx ? cB : x0 + xs;  // the window's columns
+  // the item's stream, picked from the kernel arguments once (selects of
+  // uniform values, not loads: the planes' metadata loads then depend on
+  // nothing but the plane)
+  const uint8_t* s_width = j.v[0].width;
+  const int32_t* s_q0 = j.v[0].q0;
+  const uint64_t* s_chunk = j.v[0].chunk_off;
+  const uint32_t* s_pay = j.v[0].payload;
+  uint64_t s_words = j.v[0].payload_words;
+  const uint16_t* s_rel = j.rel[0];
+#pragma unroll
+  for (int c = 1; c < NC; ++c)
+    if (c == dc) {
+      s_width = j.v[c].width;
+      s_q0 = j.v[c].q0;
+      s_chunk = j.v[c].chunk_off;
+      s_pay = j.v[c].payload;
+      s_words = j.v[c].payload_words;
+      s_rel = j.rel[c];
+    }
   int* const drow = pl + dbase + (int)(dy - (y0 - 1)) * P;
   uint32_t* const col = stage + t;
 
@@ -277,22 +351,21 @@ __global__ void __launch_bounds__(kVThreads) k_vector_fused(VecJob j, int* statu
     m.w = 0;
     m.words = 0;
     if (!decoder || p >= zb) return;
-    const StreamView& v = j.v[dc];
     const int64_t f = (p * d.y + dy) * d.x;
     const int64_t bA = (f + dxa) / S, bB = (f + dxb - 1) / S, bk = bA + dk;
     if (bk > bB) return;
     m.valid = true;
-    m.w = (int)v.width[bk];
-    m.q0 = v.q0[bk];
-    m.off = v.chunk_off[bk / kChunkBlocks] + j.rel[dc][bk];
+    m.w = (int)s_width[bk];
+    m.q0 = s_q0[bk];
+    m.off = s_chunk[bk / kChunkBlocks] + s_rel[bk];
     m.e0 = (int)(bk * S - f);
     m.words = block_words<S>(m.w);
-    if (m.w > kMaxWidth || m.words > kmax || m.off + (uint64_t)m.words > v.payload_words) {
+    if (m.w > kMaxWidth || m.words > kmax || m.off + (uint64_t)m.words > s_words) {
       record_status(status, kErrBadStream);
       m.w = 0;
       m.words = 0;
     }
-    prefetch_words<PF>(v.payload, v.payload_words, m.off, m.words, m.pw);
+    prefetch_words<PF>(s_pay, s_words, m.off, m.words, m.pw);
   };
   // staged words to this thread's column, then the block into its window
   auto commit = [&](const Pending& m) {
@@ -300,13 +373,18 @@ __global__ void __launch_bounds__(kVThreads) k_vector_fused(VecJob j, int* statu
 #pragma unroll
     for (int k = 0; k < PF; ++k)
       if (k < m.words) col[k * kVThreads] = m.pw[k];
-    const uint32_t* src = j.v[dc].payload + m.off;
+    const uint32_t* src = s_pay + m.off;
     for (int k = PF; k < m.words; ++k) col[k * kVThreads] = src[k];
     const int cb = m.e0 - (int)(x0 - 1) + R::kOff;  // extended column of slot 0 (>= 0)
     int* dst = drow + R::at(cb);
     // (a block of width 0 decodes as q0 everywhere: zero magnitudes)
-    if (aligned) decode_block_q<S, true, kVThreads>(col, m.w, m.q0, dst, 32);
-    else decode_block_q<S, false, kVThreads>(col, m.w, m.q0, dst, 32 - (cb & 31));
+    if constexpr (PAIRS) {
+      if (aligned) decode_block_pairs<S, true>(col, m.w, m.q0, dst, 32);
+      else decode_block_pairs<S, false>(col, m.w, m.q0, dst, 32 - (cb & 31));
+    } else {
+      if (aligned) decode_block_q<S, true, kVThreads>(col, m.w, m.q0, dst, 32);
+      else decode_block_q<S, false, kVThreads>(col, m.w, m.q0, dst, 32 - (cb & 31));
+    }
   };
   // the one-sided ghosts of this thread's column in window c (after the
   // decode barrier): rows for a window with y terms, columns for x terms
@@ -330,37 +408,60 @@ __global__ void __launch_bounds__(kVThreads) k_vector_fused(VecJob j, int* statu
     }
   };
 
-  // one output value of plane o from the numerators of its terms
+  // One output value of plane o per row from the numerators of its terms.
+  // Every wave issues the same TY x nout buffer stores whatever the plane,
+  // row or lane (a row outside the box gets a descriptor of 0 bytes, a lane
+  // past the tile's columns an offset past its xs values: the hardware
+  // discards both), so the wait for the next plane's payload loads, issued
+  // before these stores, need not drain them.
   auto emit = [&](int64_t o, bool last) {
-    if (!active || o < z0 || o >= z0 + zs) return;
+    const bool plane_ok = o >= z0 && o < z0 + zs;
 #pragma unroll
     for (int i = 0; i < TY; ++i) {
-      if (i < ys) {
-        const int64_t e = ((o - b.z0) * by + (y0 + i - b.y0)) * bx + (x - b.x0);
+      const bool row_ok = plane_ok && i < ys;
+      const int64_t r0 = ((o - b.z0) * by + (y0 + i - b.y0)) * bx + (x0 - b.x0);
 #pragma unroll
-        for (int oo = 0; oo < Tm::nout; ++oo) {
-          double acc = 0.0;
+      for (int oo = 0; oo < Tm::nout; ++oo) {
+        double acc = 0.0;
 #pragma unroll
-          for (int k = 0; k < NT; ++k) {
-            const VTerm tm = Tm::t[k];
-            if (tm.o != oo) continue;
-            int n;
-            if (tm.a == 0) n = last ? ((d.z >= 2) ? 2 * (h1[k][i] - h2[k][i]) : 0) : zn[k][i];
-            else n = ipp[k][i];
-            acc += (double)(tm.s * n) * j.halfq[tm.c];
-          }
-          ((T*)j.out[oo])[e] = (T)acc;
+        for (int k = 0; k < NT; ++k) {
+          const VTerm tm = Tm::t[k];
+          if (tm.o != oo) continue;
+          int n;
+          if (tm.a == 0) n = last ? ((d.z >= 2) ? 2 * (h1[k][i] - h2[k][i]) : 0) : zn[k][i];
+          else n = ipp[k][i];
+          acc += (double)(tm.s * n) * j.halfq[tm.c];
         }
+        T* const row = (T*)j.out[oo] + (row_ok ? r0 : 0);
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)row, (short)0, row_ok ? xs * (int)sizeof(T) : 0, 0x00020000);
+        const int off = t * (int)sizeof(T);
+        if constexpr (sizeof(T) == 4)
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, (float)acc), r, off, 0, 0);
+        else
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, acc), r, off, 0, 0);
       }
     }
   };
 
   // planes in order; the next plane's metadata and words load while this
-  // plane's stencil runs
+  // plane's stencil runs.  Each plane's payload loads are followed by
+  // exactly kStores stores (the emit of the plane before; ahead of the
+  // first plane, an emit whose stores are all discarded), so one wait for
+  // all but the kStores newest memory operations, at the top of every
+  // iteration whatever the thread's item, retires them without draining
+  // the stores.
+  constexpr int kStores = TY * Tm::nout;
+  static_assert(kStores < 64, "vmcnt holds 6 bits");
+  // s_waitcnt immediate: vmcnt = kStores (bits 3:0 and 15:14), expcnt and
+  // lgkmcnt at their maxima (no wait)
+  constexpr int kWaitImm = (kStores & 15) | (7 << 4) | (15 << 8) | ((kStores >> 4) << 14);
   Pending cur, nxt;
   issue(za, cur);
+  emit(za - 1, false);
   for (int64_t p = za; p < zb; ++p) {
     const int64_t o = p - 1;
+    __builtin_amdgcn_s_waitcnt(kWaitImm);
     commit(cur);
     lds_barrier();
     issue(p + 1, nxt);
@@ -443,7 +544,11 @@ hipError_t vec_fused(const VecJob& j0, uint8_t* ws, hipStream_t s) {
   const int64_t tz = (bz + nzc - 1) / nzc;
   j.tz = (int)tz;
   const int64_t grid = ntx * nty * ((bz + tz - 1) / tz);
-  hipLaunchKernelGGL((k_vector_fused<S, OP, NC, T>), dim3((unsigned)grid), dim3(kVThreads), lds, s, j, (int*)ws);
+  // every block at most kVPairW bits wide (wider ones are refused as corrupt)
+  if (j.kmax <= (S / 32) * (1 + kVPairW))
+    hipLaunchKernelGGL((k_vector_fused<S, OP, NC, T, true>), dim3((unsigned)grid), dim3(kVThreads), lds, s, j, (int*)ws);
+  else
+    hipLaunchKernelGGL((k_vector_fused<S, OP, NC, T, false>), dim3((unsigned)grid), dim3(kVThreads), lds, s, j, (int*)ws);
   return hipGetLastError();
 }
 

@@ -8,7 +8,9 @@ d' = q*Delta within 1e-6 relative for binary32 (1e-12 for binary64) plus the
 oracle's own rounding (16 * 2^-53 * max|d'|); the two integer paths agree
 bit for bit.  The float route (stage-4 buffers) differences the stored
 values in the field's precision: 1e-6 (1e-12) relative plus 16 units of
-that precision times max|d'|.
+that precision times max|d'|.  The binary32 cases (blocks at most 16 bits
+wide) take the fused kernel's pair decode, blocks of 32 and of 64; the
+binary64 ones (wider blocks) its slot-by-slot decode.
 """
 from __future__ import annotations
 
@@ -43,6 +45,8 @@ CASES = [
     ((20, 37, 264), np.float32, (1e-3, 1e-4, 1e-2), 32),  # whole and partial tiles, ragged blocks
     ((9, 33, 70), np.float64, (1e-6, 1e-6, 1e-7), 32),
     ((1, 17, 40), np.float32, (1e-3, 1e-3, 1e-3), 32),   # length-1 axis 0
+    ((30, 200), np.float32, (1e-3, 1e-2), 64),            # blocks of 64 decoded in pairs
+    ((11, 20, 130), np.float32, (1e-3, 1e-2, 1e-3), 64),
 ]
 
 
