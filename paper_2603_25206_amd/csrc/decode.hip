@@ -98,18 +98,45 @@ __global__ void __launch_bounds__(kThreads) k_decode(StreamView v, int kmax, int
 
 // Per-block payload offsets relative to the block's chunk (16 bits: a chunk
 // holds at most 64 * 62 words), so that any block's words can be located
-// with two independent loads: chunk_off[b / 64] + rel[b].  One wave per chunk.
+// with two independent loads: chunk_off[b / 64] + rel[b].  A wave takes four
+// chunks at a time: lane l the blocks 4l .. 4l + 3 of them (one 16-lane row
+// per chunk), their word counts summed in the lane and scanned over the row;
+// one 8-byte store writes the lane's four offsets.
+constexpr int kIndexChunks = kWave * 4 / kChunkBlocks;  // chunks per wave and step
+static_assert(kChunkBlocks % 4 == 0 && kChunkBlocks / 4 == 16, "one 16-lane row per chunk");
 template <int S>
 __global__ void __launch_bounds__(kThreads) k_block_index(StreamView v, uint16_t* __restrict__ rel) {
   const int wv = wave_in_group();
   const int l = lane_id();
   const int64_t waves = (int64_t)gridDim.x * kWavesPerGroup;
-  for (int64_t c = blockIdx.x * (int64_t)kWavesPerGroup + wv; c < v.nchunks; c += waves) {
-    const int64_t b = c * kChunkBlocks + l;
-    const int w = b < v.nb ? (int)v.width[b] : 0;
-    const int nw = block_words<S>(w < kMaxWidth ? w : kMaxWidth);
-    const int incl = wave_incl_scan(nw);
-    if (b < v.nb) rel[b] = (uint16_t)(incl - nw);
+  const int64_t steps = (v.nchunks + kIndexChunks - 1) / kIndexChunks;
+  for (int64_t c = blockIdx.x * (int64_t)kWavesPerGroup + wv; c < steps; c += waves) {
+    const int64_t b0 = c * (kIndexChunks * kChunkBlocks) + 4 * l;
+    int nw[4], pre[4], tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int w = b0 + k < v.nb ? (int)v.width[b0 + k] : 0;
+      nw[k] = block_words<S>(w < kMaxWidth ? w : kMaxWidth);
+      pre[k] = tot;
+      tot += nw[k];
+    }
+    // exclusive scan of the lane totals within the lane's 16-lane row
+    int incl = tot;
+    incl += dpp<0x111>(incl);
+    incl += dpp<0x112>(incl);
+    incl += dpp<0x114>(incl);
+    incl += dpp<0x118>(incl);
+    const int ex = incl - tot;
+    if (b0 + 3 < v.nb) {
+      typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+      const u2v pk = {(uint32_t)(ex + pre[0]) | ((uint32_t)(ex + pre[1]) << 16),
+                      (uint32_t)(ex + pre[2]) | ((uint32_t)(ex + pre[3]) << 16)};
+      *(u2v*)(rel + b0) = pk;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (b0 + k < v.nb) rel[b0 + k] = (uint16_t)(ex + pre[k]);
+    }
   }
 }
 
@@ -178,7 +205,8 @@ hipError_t dispatch(const StreamView& v, int stage, void* out, int* status, hipS
 }  // namespace
 
 hipError_t launch_block_index(const StreamView& v, uint16_t* rel, hipStream_t s) {
-  const int64_t groups = (v.nchunks + kWavesPerGroup - 1) / kWavesPerGroup;
+  const int64_t steps = (v.nchunks + kIndexChunks - 1) / kIndexChunks;
+  const int64_t groups = (steps + kWavesPerGroup - 1) / kWavesPerGroup;
   const unsigned grid = (unsigned)(groups < 8192 ? groups : 8192);
   if (v.block == 32) hipLaunchKernelGGL(k_block_index<32>, dim3(grid), dim3(kThreads), 0, s, v, rel);
   else hipLaunchKernelGGL(k_block_index<64>, dim3(grid), dim3(kThreads), 0, s, v, rel);
