@@ -1081,42 +1081,62 @@ __global__ void __launch_bounds__(kThreads) k_lz_dq2_stats(const int32_t* __rest
 
 // Alg. 4 on HSZp's flat row from lz_flat_front's p and tile carries: each
 // tile's q (the in-tile prefix sum of p plus the carry, as the device-wide
-// scan's last pass forms it) is summed, q and q^2, and not written.
+// scan's last pass forms it) is summed, q and q^2, and not written.  Thread
+// t of a tile owns its kFlatStatsPer consecutive words (16-byte loads),
+// scans them in registers, and one workgroup scan of the thread totals
+// places them: q = the tile's carry + the threads before + the thread's own
+// prefix.  The prefix sums are taken modulo 2^32: every q fits 32 bits, so
+// the wrapped sums are exact.
 constexpr int kFlatStatsPer = (int)(kFlatTile / kThreads);
+static_assert(kFlatStatsPer % 4 == 0, "16-byte loads");
 __global__ void __launch_bounds__(kThreads) k_flat_stats(const int32_t* __restrict__ p, int64_t n,
                                                         const int32_t* __restrict__ carry, Partial* parts) {
-  __shared__ int wt[kFlatStatsPer * kWavesPerGroup];
+  typedef int i4 __attribute__((ext_vector_type(4)));
+  __shared__ uint32_t wt[kWavesPerGroup];
   IntAcc acc;
   const int64_t ntiles = (n + kFlatTile - 1) / kFlatTile;
   const int wv = wave_in_group();
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t i0 = t * kFlatTile + threadIdx.x;
-    int v[kFlatStatsPer];
+    const int64_t i0 = t * kFlatTile + (int64_t)threadIdx.x * kFlatStatsPer;
+    uint32_t v[kFlatStatsPer];
+    if (i0 + kFlatStatsPer <= n) {
 #pragma unroll
-    for (int k = 0; k < kFlatStatsPer; ++k) {
-      const int64_t i = i0 + (int64_t)k * kThreads;
-      v[k] = i < n ? p[i] : 0;
-    }
-#pragma unroll
-    for (int k = 0; k < kFlatStatsPer; ++k) {
-      v[k] = wave_incl_scan(v[k]);
-      if (lane_id() == kWave - 1) wt[k * kWavesPerGroup + wv] = v[k];
-    }
-    lds_barrier();
-    int run = carry[t];
-#pragma unroll
-    for (int k = 0; k < kFlatStatsPer; ++k) {
-      int before = 0, row = 0;
-#pragma unroll
-      for (int w = 0; w < kWavesPerGroup; ++w) {
-        const int x = wt[k * kWavesPerGroup + w];
-        before += w < wv ? x : 0;
-        row += x;
+      for (int k = 0; k < kFlatStatsPer; k += 4) {
+        const i4 w = *(const i4*)(p + i0 + k);
+        v[k] = (uint32_t)w.x;
+        v[k + 1] = (uint32_t)w.y;
+        v[k + 2] = (uint32_t)w.z;
+        v[k + 3] = (uint32_t)w.w;
       }
-      if (i0 + (int64_t)k * kThreads < n) acc.add(run + before + v[k], true);
-      run += row;
+    } else {
+#pragma unroll
+      for (int k = 0; k < kFlatStatsPer; ++k) v[k] = i0 + k < n ? (uint32_t)p[i0 + k] : 0u;
     }
+    uint32_t tot = 0;
+#pragma unroll
+    for (int k = 0; k < kFlatStatsPer; ++k) {
+      tot += v[k];
+      v[k] = tot;
+    }
+    // the threads before this one: a wave scan, then the waves before
+    const uint32_t incl = (uint32_t)wave_incl_scan((int)tot);
+    if (lane_id() == kWave - 1) wt[wv] = incl;
+    lds_barrier();
+    uint32_t before = incl - tot;
+#pragma unroll
+    for (int w = 0; w < kWavesPerGroup; ++w) before += w < wv ? wt[w] : 0u;
     lds_barrier();  // wt is rewritten by the next tile
+    const uint32_t base = (uint32_t)carry[t] + before;
+    const int valid = (int)min((int64_t)kFlatStatsPer, max((int64_t)0, n - i0));
+    int64_t s1 = 0;
+#pragma unroll
+    for (int k = 0; k < kFlatStatsPer; ++k) {
+      const int q = k < valid ? (int)(base + v[k]) : 0;
+      s1 += q;
+      add_u64(acc.s2, (uint64_t)((int64_t)q * (int64_t)q));
+    }
+    acc.s1 += s1;
+    acc.cnt += valid;
   }
   store_int_partial(acc, parts);
 }
